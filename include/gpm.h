@@ -1,0 +1,211 @@
+/*
+ * gpm.h -- C ABI of the MI355X (gfx950) graph pattern mining library
+ * (libgpmhip.so).
+ *
+ * What it computes.  Given an undirected graph G and a pattern P (Section 2,
+ * problem definition; Section 3.1, high-level API: induced-ness flag,
+ * listing-or-counting flag, explicit pattern edge list, runtime size k), the
+ * library counts or lists the embeddings of P in G:
+ *   - triangle counting and k-clique counting/listing (problems 1-2),
+ *     vertex-induced, on the degree-ordered DAG (Appendix B.2);
+ *   - subgraph listing of the diamond and the 4-cycle, edge-induced
+ *     (problem 3; matching order and partial orders of Appendices B.1, B.3);
+ *   - k-motif counting for k = 3, 4, vertex-induced, connected patterns only
+ *     (problem 4), by local counting (Section 5, the wedge equation; the
+ *     3-motif and 4-motif local-counting listings of Appendix A);
+ *   - the same motif counts for a batch of small graphs in one launch.
+ *
+ * Conventions shared by every entry point.
+ *   - No entry point throws, aborts or exits on bad input; each returns a
+ *     gpm_status.  gpm_last_error() (thread-local) describes the last
+ *     failure on the calling thread.
+ *   - Device memory is owned by the caller: every device buffer (inputs,
+ *     outputs, graph storage, workspace) is allocated and freed by the
+ *     caller.  The library performs no device allocation in any entry point.
+ *     Required sizes come from the *_bytes query functions.  Every device
+ *     pointer must be 256-byte aligned.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued asynchronously on it; outputs are valid once the stream has
+ *     been synchronised.  Exceptions are stated per function (gpm_graph_build
+ *     synchronises the stream once, to learn the graph's sizes).
+ *   - Argument errors are detected on the host before anything is enqueued.
+ *     HIP errors are returned as GPM_DEVICE_ERROR.
+ *   - Vertex ids are int32 in [0, n).  The symmetric adjacency must have
+ *     fewer than 2^31 entries.  Counts are exact uint64.
+ *   - Calls that share a workspace buffer must not overlap in time (same
+ *     stream, or the caller orders them).  Graph storage is read-only after
+ *     gpm_graph_build and may be shared by concurrent calls.
+ */
+#ifndef GPM_H
+#define GPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status --- */
+
+typedef int32_t gpm_status;
+#define GPM_OK                0
+#define GPM_INVALID_ARGUMENT  1  /* bad pointer, size, id or flag combination */
+#define GPM_OUT_OF_MEMORY     2  /* a caller buffer is smaller than required */
+#define GPM_DEVICE_ERROR      3  /* a HIP call failed; see gpm_last_error() */
+#define GPM_TRUNCATED         4  /* (reported in listing results, see gpm_list) */
+#define GPM_UNSUPPORTED       5  /* pattern or size outside what is implemented */
+#define GPM_NOT_CANONICAL     6  /* input ids out of range */
+#define GPM_INCONSISTENT      7  /* an exact-division check of a formula failed */
+
+/* Static string naming a status code. */
+const char *gpm_status_string(gpm_status s);
+/* Description of the last failure on the calling thread ("" if none). */
+const char *gpm_last_error(void);
+/* Library version string, e.g. "gpmhip 0.1 gfx950". */
+const char *gpm_version(void);
+
+/* ----------------------------------------------------------- pattern --- */
+
+/* Pattern flags (Section 3.1: the two required per-problem flags). */
+#define GPM_VERTEX_INDUCED 0x1u
+#define GPM_EDGE_INDUCED   0x2u
+#define GPM_LIST           0x4u   /* listing; absent means counting */
+
+#define GPM_MAX_PATTERN_VERTICES 8
+#define GPM_MAX_PATTERN_EDGES    28
+
+/* A pattern is an edge list on vertices 0..k-1 (Section 3.1: patterns are
+ * given as edge lists, e.g. the triangle {(0,1),(0,2),(1,2)}). */
+typedef struct gpm_pattern {
+    int32_t k;                                   /* number of vertices */
+    int32_t n_edges;                             /* number of edges */
+    int32_t edges[GPM_MAX_PATTERN_EDGES][2];     /* pairs (a, b), a != b */
+    uint32_t flags;                              /* exactly one of *_INDUCED, optional GPM_LIST */
+} gpm_pattern;
+
+/* Builds the pattern from an edge list (uv holds n_edges pairs, host
+ * memory).  Rejects loops, repeated edges, ids outside [0, k), disconnected
+ * patterns and k outside [2, 8] with GPM_INVALID_ARGUMENT. */
+gpm_status gpm_pattern_from_edges(int32_t k, int32_t n_edges, const int32_t *uv,
+                                  uint32_t flags, gpm_pattern *out);
+/* The k-clique (helper named in Section 3.1); flags as above. */
+gpm_status gpm_pattern_clique(int32_t k, uint32_t flags, gpm_pattern *out);
+
+/* Plan chosen for a pattern (Section 4.3 enablement rules: orientation
+ * iff the pattern is a clique, |E| = |V|(|V|-1)/2 (Appendix B.2); a
+ * matching order with partial orders for other single explicit patterns). */
+#define GPM_PLAN_CLIQUE_DAG     1   /* triangles and k-cliques, k <= 5 */
+#define GPM_PLAN_SL_DIAMOND     2   /* edge-induced diamond listing/counting */
+#define GPM_PLAN_SL_4CYCLE      3   /* edge-induced 4-cycle listing/counting */
+/* Returns the plan for (graph-independent) pattern p, or GPM_UNSUPPORTED. */
+gpm_status gpm_pattern_plan(const gpm_pattern *p, int32_t *plan);
+
+/* ------------------------------------------------------------- graph --- */
+
+/* Opaque host handle.  It records device pointers into caller-owned graph
+ * storage and the graph's sizes; it owns no device memory. */
+typedef struct gpm_graph gpm_graph;
+
+/* Sizes of the caller buffers gpm_graph_build needs for a graph on n
+ * vertices given by n_input_edges raw edge-stream entries.  graph_bytes is
+ * kept for the graph's lifetime; scratch_bytes only during the build.
+ * n must be in [1, 2^31 - 2]; 2 * n_input_edges must be < 2^31. */
+gpm_status gpm_graph_build_bytes(int32_t n, int64_t n_input_edges,
+                                 uint64_t *graph_bytes, uint64_t *scratch_bytes);
+
+/* Builds the canonical graph on the device from a raw undirected edge stream
+ * (d_u[i], d_v[i]), i < n_input_edges (device int32 arrays): self-loops are
+ * dropped, repeated and reversed pairs are merged, rows are sorted -- the
+ * input form the method assumes (Section 6, input-graph table caption).  It
+ * then orients the graph by degree: each edge points to the endpoint of
+ * larger degree, ties to the larger id (Appendix B.2).  Stored in
+ * d_graph_mem (graph_bytes, from gpm_graph_build_bytes):
+ *   symmetric CSR  off int32[n+1], adj int32[2m], rows ascending;
+ *   oriented CSR   dag_off int32[n+1], dag_adj int32[m], rows ascending;
+ *                  arc index e in [0, m) is the undirected edge id;
+ *   arc sources    dag_src int32[m].
+ * d_scratch (scratch_bytes) may be reused once the call returns.  The call
+ * synchronises `stream` once.  Ids outside [0, n) give GPM_NOT_CANONICAL
+ * (and *out is not set).  On success *out must later be released with
+ * gpm_graph_release. */
+gpm_status gpm_graph_build(int32_t n, const int32_t *d_u, const int32_t *d_v,
+                           int64_t n_input_edges, void *d_graph_mem, uint64_t graph_bytes,
+                           void *d_scratch, uint64_t scratch_bytes, void *stream,
+                           gpm_graph **out);
+
+typedef struct gpm_graph_info {
+    int32_t n;              /* vertices */
+    int32_t max_degree;     /* largest undirected degree */
+    int64_t m;              /* undirected edges after canonicalisation */
+    int32_t max_out_degree; /* largest out-degree of the oriented graph */
+    int32_t reserved;
+    const int32_t *off, *adj, *dag_off, *dag_adj, *dag_src;   /* device */
+} gpm_graph_info;
+
+gpm_status gpm_graph_get_info(const gpm_graph *g, gpm_graph_info *info);
+/* Frees the host handle (not the caller's device memory).  NULL is a no-op. */
+void gpm_graph_release(gpm_graph *g);
+
+/* ------------------------------------------------- counting, listing --- */
+
+/* Workspace needed by gpm_count / gpm_list for pattern p on graph g. */
+gpm_status gpm_workspace_bytes(const gpm_graph *g, const gpm_pattern *p, uint64_t *bytes);
+
+/* Counts the embeddings of p in g (Section 2: unique subgraphs, each
+ * automorphism class once): triangles and k-cliques (k <= 5) for
+ * vertex-induced cliques; edge-induced diamonds and 4-cycles.  Writes one
+ * uint64 to d_count (device).  p must not carry GPM_LIST. */
+gpm_status gpm_count(const gpm_graph *g, const gpm_pattern *p, void *d_ws, uint64_t ws_bytes,
+                     uint64_t *d_count, void *stream);
+
+/* Lists the embeddings of p in g.  Embedding number i (in an unspecified
+ * order) is written to d_buf[i*k .. i*k+k-1] as the data vertices matched
+ * to pattern vertices 0..k-1, for i < cap.  d_result (device uint64[3])
+ * receives {total, written, checksum}: total counts every embedding even
+ * past cap, written = min(total, cap), and checksum is the sum modulo 2^64,
+ * over all embeddings, of a per-embedding hash of its canonical key:
+ *     h = L; for each key element c in ascending order:
+ *         h = fmix64((h XOR c) + 0x9E3779B97F4A7C15)
+ * (fmix64 = the splitmix64 finaliser), with key = the ascending vertex
+ * tuple (vertex-induced) or the ascending edge codes (min << 32 | max)
+ * (edge-induced), L its length.  written < total means the listing was
+ * truncated (GPM_TRUNCATED is not returned, since the call is
+ * asynchronous).  p must carry GPM_LIST. */
+gpm_status gpm_list(const gpm_graph *g, const gpm_pattern *p, void *d_ws, uint64_t ws_bytes,
+                    int32_t *d_buf, uint64_t cap, uint64_t *d_result, void *stream);
+
+/* ----------------------------------------------------------- motifs --- */
+
+/* Workspace needed by gpm_motif_count(g, k). */
+gpm_status gpm_motif_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes);
+
+/* Induced k-motif counts, k = 3 or 4 (problem 4, connected patterns only),
+ * written to d_counts (device uint64) in this fixed order:
+ *   k = 3: {wedge, triangle}, then a status word;
+ *   k = 4: {3-star, 4-path, 4-cycle, tailed-triangle, diamond, 4-clique},
+ *          then a status word.
+ * The status word is 0 when every exact division of the combining formulas
+ * held and every count fit in 64 bits, nonzero otherwise. */
+gpm_status gpm_motif_count(const gpm_graph *g, int32_t k, void *d_ws, uint64_t ws_bytes,
+                           uint64_t *d_counts, void *stream);
+
+/* ------------------------------------------------------------ batch --- */
+
+/* Batched motif counting over G small graphs held as ONE graph g (their
+ * disjoint union, built with gpm_graph_build from the concatenated edge
+ * streams with vertex ids shifted per graph): graph i owns vertices
+ * d_voff[i] .. d_voff[i+1]-1 (device int32[G+1], ascending, d_voff[0] = 0,
+ * d_voff[G] = n).  No edge may join two graphs.  Writes d_counts (device
+ * uint64[G][k == 3 ? 3 : 7]) row i = gpm_motif_count's output for graph i.
+ * Every graph must have at most GPM_BATCH_MAX_VERTICES vertices. */
+#define GPM_BATCH_MAX_VERTICES 1024
+gpm_status gpm_batch_workspace_bytes(int32_t G, int32_t k, uint64_t *bytes);
+gpm_status gpm_batch_motif_count(const gpm_graph *g, const int32_t *d_voff, int32_t G,
+                                 int32_t k, void *d_ws, uint64_t ws_bytes,
+                                 uint64_t *d_counts, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPM_H */

@@ -1,0 +1,31 @@
+"""MI355X (gfx950) graph pattern mining: Python binding of libgpmhip.so.
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch provides device memory (caller-owned buffers) and the stream.  The
+binding raises if the built library is missing; there is no fallback.
+
+    import paper_2011_03135_amd as gpm
+    g = gpm.Graph.build(n, u, v)            # u, v: int32 CUDA tensors
+    gpm.count(g, gpm.clique(4))             # exact int
+    gpm.motif_count(g, 4)                   # 6 induced 4-motif counts
+"""
+from .binding import (  # noqa: F401
+    GpmError,
+    Graph,
+    Pattern,
+    batch_motif_count,
+    clique,
+    count,
+    diamond,
+    cycle4,
+    library_path,
+    list_embeddings,
+    load,
+    motif_count,
+    pattern,
+    MOTIF3_NAMES,
+    MOTIF4_NAMES,
+    VERTEX_INDUCED,
+    EDGE_INDUCED,
+    LIST,
+)

@@ -1,0 +1,270 @@
+"""ctypes binding of include/gpm.h (same names, argument marshalling only)."""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libgpmhip.so")
+
+VERTEX_INDUCED = 0x1
+EDGE_INDUCED = 0x2
+LIST = 0x4
+
+MOTIF3_NAMES = ("wedge", "triangle")
+MOTIF4_NAMES = ("3-star", "4-path", "4-cycle", "tailed-triangle", "diamond", "4-clique")
+
+_STATUS = {0: "GPM_OK", 1: "GPM_INVALID_ARGUMENT", 2: "GPM_OUT_OF_MEMORY",
+           3: "GPM_DEVICE_ERROR", 4: "GPM_TRUNCATED", 5: "GPM_UNSUPPORTED",
+           6: "GPM_NOT_CANONICAL", 7: "GPM_INCONSISTENT"}
+
+
+class GpmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Pattern(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("n_edges", ctypes.c_int32),
+                ("edges", (ctypes.c_int32 * 2) * 28), ("flags", ctypes.c_uint32)]
+
+
+class _GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("max_degree", ctypes.c_int32),
+                ("m", ctypes.c_int64), ("max_out_degree", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("off", ctypes.c_void_p), ("adj", ctypes.c_void_p),
+                ("dag_off", ctypes.c_void_p), ("dag_adj", ctypes.c_void_p),
+                ("dag_src", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def load():
+    """Loads libgpmhip.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                          "python -m paper_2011_03135_amd.build")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                             ctypes.c_uint32, ctypes.c_uint64)
+    sigs = {
+        "gpm_status_string": ([i32], ctypes.c_char_p),
+        "gpm_last_error": ([], ctypes.c_char_p),
+        "gpm_version": ([], ctypes.c_char_p),
+        "gpm_pattern_from_edges": ([i32, i32, P, u32, P], i32),
+        "gpm_pattern_clique": ([i32, u32, P], i32),
+        "gpm_pattern_plan": ([P, P], i32),
+        "gpm_graph_build_bytes": ([i32, i64, P, P], i32),
+        "gpm_graph_build": ([i32, P, P, i64, P, u64, P, u64, P, P], i32),
+        "gpm_graph_get_info": ([P, P], i32),
+        "gpm_graph_release": ([P], None),
+        "gpm_workspace_bytes": ([P, P, P], i32),
+        "gpm_count": ([P, P, P, u64, P, P], i32),
+        "gpm_list": ([P, P, P, u64, P, u64, P, P], i32),
+        "gpm_motif_workspace_bytes": ([P, i32, P], i32),
+        "gpm_motif_count": ([P, i32, P, u64, P, P], i32),
+        "gpm_batch_workspace_bytes": ([i32, i32, P], i32),
+        "gpm_batch_motif_count": ([P, P, i32, i32, P, u64, P, P], i32),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        msg = load().gpm_last_error().decode(errors="replace")
+        raise GpmError(rc, msg)
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _buffer(nbytes, device):
+    t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    if t.data_ptr() % 256:
+        raise GpmError(1, "allocator returned a buffer that is not 256-byte aligned")
+    return t
+
+
+def _u64(x):
+    x = int(x)
+    return x + (1 << 64) if x < 0 else x
+
+
+def pattern(k, edges, flags):
+    """gpm_pattern_from_edges: edges is a list of (a, b) pairs on 0..k-1."""
+    lib = load()
+    flat = (ctypes.c_int32 * (2 * max(len(edges), 1)))(*[x for e in edges for x in e])
+    p = Pattern()
+    _check(lib.gpm_pattern_from_edges(int(k), len(edges), flat, int(flags), ctypes.byref(p)))
+    return p
+
+
+def clique(k, flags=VERTEX_INDUCED):
+    p = Pattern()
+    _check(load().gpm_pattern_clique(int(k), int(flags), ctypes.byref(p)))
+    return p
+
+
+def diamond(flags=EDGE_INDUCED):
+    """Diamond with diagonal (0, 1) and tips 2, 3."""
+    return pattern(4, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3)], flags)
+
+
+def cycle4(flags=EDGE_INDUCED):
+    """4-cycle 0-1-2-3-0."""
+    return pattern(4, [(0, 1), (1, 2), (2, 3), (3, 0)], flags)
+
+
+class Graph:
+    """A canonical, degree-oriented graph in caller-owned (torch) device memory."""
+
+    def __init__(self, handle, storage, device):
+        self._h = handle
+        self._storage = storage
+        self.device = device
+        info = _GraphInfo()
+        _check(load().gpm_graph_get_info(self._h, ctypes.byref(info)))
+        self.n = info.n
+        self.m = info.m
+        self.max_degree = info.max_degree
+        self.max_out_degree = info.max_out_degree
+        self._info = info
+
+    @staticmethod
+    def build_bytes(n, n_input_edges):
+        gb, sb = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load().gpm_graph_build_bytes(int(n), int(n_input_edges), ctypes.byref(gb),
+                                            ctypes.byref(sb)))
+        return gb.value, sb.value
+
+    @classmethod
+    def build(cls, n, u, v, stream=None, scratch=None):
+        """gpm_graph_build from int32 CUDA tensors u, v (a raw edge stream)."""
+        if u.dtype != torch.int32 or v.dtype != torch.int32 or not u.is_cuda or not v.is_cuda:
+            raise TypeError("u and v must be int32 CUDA tensors")
+        if u.shape != v.shape or u.dim() != 1:
+            raise ValueError("u and v must be 1-D of equal length")
+        u = u.contiguous()
+        v = v.contiguous()
+        gb, sb = cls.build_bytes(n, u.shape[0])
+        storage = _buffer(gb, u.device)
+        if scratch is None or scratch.numel() < sb:
+            scratch = _buffer(sb, u.device)
+        h = ctypes.c_void_p()
+        _check(load().gpm_graph_build(int(n), _ptr(u), _ptr(v), int(u.shape[0]), _ptr(storage),
+                                      gb, _ptr(scratch), sb, _stream(stream), ctypes.byref(h)))
+        return cls(h, storage, u.device)
+
+    def csr(self):
+        """(off, adj) views (int32 device tensors) of the symmetric CSR."""
+        return self._view(self._info.off, self.n + 1), self._view(self._info.adj, 2 * self.m)
+
+    def dag(self):
+        """(dag_off, dag_adj, dag_src) views of the oriented CSR."""
+        return (self._view(self._info.dag_off, self.n + 1),
+                self._view(self._info.dag_adj, self.m), self._view(self._info.dag_src, self.m))
+
+    def _view(self, addr, count):
+        base = self._storage.data_ptr()
+        start = (addr - base) // 4
+        return self._storage.view(torch.int32)[start:start + int(count)]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        try:
+            if self._h:
+                load().gpm_graph_release(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def workspace_bytes(g, p):
+    b = ctypes.c_uint64()
+    _check(load().gpm_workspace_bytes(g.handle, ctypes.byref(p), ctypes.byref(b)))
+    return b.value
+
+
+def count(g, p, stream=None, ws=None, out=None):
+    """gpm_count -> exact int (synchronises the stream when out is None)."""
+    nb = workspace_bytes(g, p)
+    if ws is None or ws.numel() < nb:
+        ws = _buffer(nb, g.device)
+    res = out if out is not None else torch.zeros(1, dtype=torch.int64, device=g.device)
+    _check(load().gpm_count(g.handle, ctypes.byref(p), _ptr(ws), ws.numel(), _ptr(res),
+                            _stream(stream)))
+    if out is not None:
+        return out
+    return _u64(res.item())
+
+
+def list_embeddings(g, p, cap, stream=None, ws=None):
+    """gpm_list -> (total, written, checksum, rows[written, k] int32 tensor)."""
+    nb = workspace_bytes(g, p)
+    if ws is None or ws.numel() < nb:
+        ws = _buffer(nb, g.device)
+    k = p.k
+    buf = torch.empty((max(int(cap), 1), k), dtype=torch.int32, device=g.device)
+    res = torch.zeros(3, dtype=torch.int64, device=g.device)
+    _check(load().gpm_list(g.handle, ctypes.byref(p), _ptr(ws), ws.numel(), _ptr(buf), int(cap),
+                           _ptr(res), _stream(stream)))
+    total, written, chk = (_u64(x) for x in res.tolist())
+    return total, written, chk, buf[:written]
+
+
+def motif_count(g, k, stream=None, ws=None, out=None):
+    """gpm_motif_count -> list of exact ints (3-motifs: 2, 4-motifs: 6)."""
+    b = ctypes.c_uint64()
+    _check(load().gpm_motif_workspace_bytes(g.handle, int(k), ctypes.byref(b)))
+    if ws is None or ws.numel() < b.value:
+        ws = _buffer(b.value, g.device)
+    nout = 3 if k == 3 else 7
+    res = out if out is not None else torch.zeros(nout, dtype=torch.int64, device=g.device)
+    _check(load().gpm_motif_count(g.handle, int(k), _ptr(ws), ws.numel(), _ptr(res),
+                                  _stream(stream)))
+    if out is not None:
+        return out
+    vals = [_u64(x) for x in res.tolist()]
+    if vals[-1] != 0:
+        raise GpmError(7, f"motif combination check failed (status word {vals[-1]})")
+    return vals[:-1]
+
+
+def batch_motif_count(g, voff, k, stream=None, ws=None, out=None):
+    """gpm_batch_motif_count -> int64 tensor [G, 3 or 7] (uint64 bits)."""
+    G = int(voff.shape[0] - 1)
+    if voff.dtype != torch.int32 or not voff.is_cuda:
+        raise TypeError("voff must be an int32 CUDA tensor")
+    b = ctypes.c_uint64()
+    _check(load().gpm_batch_workspace_bytes(G, int(k), ctypes.byref(b)))
+    if ws is None or ws.numel() < b.value:
+        ws = _buffer(b.value, g.device)
+    width = 3 if k == 3 else 7
+    res = out if out is not None else torch.zeros((G, width), dtype=torch.int64, device=g.device)
+    _check(load().gpm_batch_motif_count(g.handle, _ptr(voff.contiguous()), G, int(k), _ptr(ws),
+                                        ws.numel(), _ptr(res), _stream(stream)))
+    return res

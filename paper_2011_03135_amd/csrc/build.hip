@@ -1,0 +1,427 @@
+// Canonical CSR build and degree-ordered orientation, entirely on the device.
+//
+// Input: a raw undirected edge stream (u[i], v[i]).  Output (graph storage):
+//   off/adj        symmetric, loop-free, duplicate-free, rows ascending
+//                  (the input form assumed in Section 6, input-graph table);
+//   dag_off/adj    arcs u -> v with (deg u, u) < (deg v, v), rows ascending
+//                  (degree-based orientation, Appendix B.2);
+//   dag_src        the source vertex of every arc.
+//
+// Pipeline (one stream, no host round trip until the final size read-back):
+//   count arcs per vertex -> scan -> scatter arcs into rows (atomic cursors)
+//   -> per-row sort + unique (wave bitonic in registers for <= 64 entries,
+//      wave bitonic in LDS for <= 2048, workgroup bitmap for longer rows)
+//   -> scan unique counts -> compact rows -> count out-arcs -> scan -> fill.
+#include "gpm_internal.h"
+
+#include <algorithm>
+#include <climits>
+#include <new>
+
+namespace gpm {
+
+namespace {
+
+enum Flag : int {
+    F_ERR = 0,        // nonzero: an input id was out of range
+    F_BIG_COUNT = 1,  // rows routed to the bitmap sorter
+    F_MAX_DEG = 2,
+    F_MAX_OUT = 3,
+    F_WORDS = 16,
+};
+
+constexpr int kBlock = 256;                 // 4 waves
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kSortLds = 2048;              // per-wave LDS sort capacity (entries)
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ void __launch_bounds__(kBlock) k_count_raw(const int32_t *__restrict__ u,
+                                                      const int32_t *__restrict__ v, int64_t E,
+                                                      int32_t n, int32_t *cnt, uint32_t *flags) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (; i < E; i += stride) {
+        int32_t a = u[i], b = v[i];
+        if ((uint32_t)a >= (uint32_t)n || (uint32_t)b >= (uint32_t)n) {
+            atomicOr(&flags[F_ERR], 1u);
+            continue;
+        }
+        if (a == b) continue;
+        atomicAdd(&cnt[a], 1);
+        atomicAdd(&cnt[b], 1);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_scatter_raw(const int32_t *__restrict__ u,
+                                                        const int32_t *__restrict__ v, int64_t E,
+                                                        int32_t n, const int32_t *raw_off,
+                                                        int32_t *cursor, int32_t *raw_adj) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (; i < E; i += stride) {
+        int32_t a = u[i], b = v[i];
+        if ((uint32_t)a >= (uint32_t)n || (uint32_t)b >= (uint32_t)n || a == b) continue;
+        int32_t pa = atomicAdd(&cursor[a], 1);
+        raw_adj[raw_off[a] + pa] = b;
+        int32_t pb = atomicAdd(&cursor[b], 1);
+        raw_adj[raw_off[b] + pb] = a;
+    }
+}
+
+// Sorts row entries held one per lane (lanes >= L hold INT_MAX) ascending.
+__device__ __forceinline__ int32_t wave_bitonic_sort(int32_t x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            int32_t y = __shfl_xor(x, j, 64);
+            bool ascending = (lane & k) == 0;
+            bool lower = (lane & j) == 0;
+            int32_t lo = x < y ? x : y, hi = x < y ? y : x;
+            x = (lower == ascending) ? lo : hi;
+        }
+    }
+    return x;
+}
+
+// One wave per row: sort + unique in place; long rows are deferred.
+__global__ void __launch_bounds__(kBlock) k_sort_rows(const int32_t *__restrict__ raw_off,
+                                                      int32_t *raw_adj, int32_t n, int32_t *ucnt,
+                                                      int32_t *big_list, uint32_t *flags) {
+    __shared__ int32_t lds[kWavesPerBlock][kSortLds];
+    const int lane = lane_id();
+    const int wib = threadIdx.x / kWave;
+    int32_t *buf = lds[wib];
+    const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + wib;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t row = wave0; row < n; row += nwaves) {
+        const int32_t s = raw_off[row];
+        const int32_t L = raw_off[row + 1] - s;
+        int32_t *r = raw_adj + s;
+        if (L <= 64) {
+            int32_t x = lane < L ? r[lane] : INT_MAX;
+            x = wave_bitonic_sort(x);
+            int32_t prev = __shfl_up(x, 1, 64);
+            bool keep = lane < L && (lane == 0 || x != prev);
+            uint64_t mask = __ballot(keep);
+            if (keep) r[lanes_below(mask)] = x;
+            if (lane == 0) ucnt[row] = __popcll(mask);
+        } else if (L <= kSortLds) {
+            int P = 128;
+            while (P < L) P <<= 1;
+            for (int i = lane; i < P; i += kWave) buf[i] = i < L ? r[i] : INT_MAX;
+            wave_sync();
+            for (int k = 2; k <= P; k <<= 1) {
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int t = lane; t < P / 2; t += kWave) {
+                        int i = (t / j) * 2 * j + (t % j);
+                        int p = i + j;
+                        int32_t a = buf[i], b = buf[p];
+                        bool ascending = (i & k) == 0;
+                        if ((a > b) == ascending) {
+                            buf[i] = b;
+                            buf[p] = a;
+                        }
+                    }
+                    wave_sync();
+                }
+            }
+            int32_t count = 0;
+            for (int base = 0; base < L; base += kWave) {
+                int i = base + lane;
+                int32_t x = i < L ? buf[i] : INT_MAX;
+                bool keep = i < L && (i == 0 || x != buf[i - 1]);
+                uint64_t mask = __ballot(keep);
+                if (keep) r[count + lanes_below(mask)] = x;
+                count += __popcll(mask);
+            }
+            if (lane == 0) ucnt[row] = count;
+            wave_sync();
+        } else {
+            if (lane == 0) {
+                uint32_t slot = atomicAdd(&flags[F_BIG_COUNT], 1u);
+                big_list[slot] = (int32_t)row;
+            }
+        }
+    }
+}
+
+// One workgroup per long row: set one bit per entry in a bitmap over the
+// id range, then read the set bits back in ascending order.
+__global__ void __launch_bounds__(kBlock) k_sort_big_rows(const int32_t *__restrict__ raw_off,
+                                                          int32_t *raw_adj, int32_t *ucnt,
+                                                          const int32_t *big_list,
+                                                          const uint32_t *flags,
+                                                          uint32_t *bitmaps, int64_t words) {
+    __shared__ int64_t sh[kWavesPerBlock + 1];
+    uint32_t *bm = bitmaps + (int64_t)blockIdx.x * words;
+    const uint32_t nbig = flags[F_BIG_COUNT];
+    for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
+        const int32_t row = big_list[b];
+        const int32_t s = raw_off[row];
+        const int32_t L = raw_off[row + 1] - s;
+        int32_t *r = raw_adj + s;
+        for (int64_t w = threadIdx.x; w < words; w += kBlock) bm[w] = 0u;
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < L; i += kBlock) {
+            uint32_t x = (uint32_t)r[i];
+            atomicOr(&bm[x >> 5], 1u << (x & 31));
+        }
+        __syncthreads();
+        int64_t running = 0;
+        for (int64_t w0 = 0; w0 < words; w0 += kBlock) {
+            int64_t w = w0 + threadIdx.x;
+            uint32_t word = w < words ? bm[w] : 0u;
+            int64_t c = __popc(word);
+            // block exclusive scan of c
+            const int lanew = threadIdx.x & 63, wid = threadIdx.x >> 6;
+            int64_t inc = wave_incl_scan(c);
+            if (lanew == 63) sh[wid] = inc;
+            __syncthreads();
+            int64_t before = 0, total = 0;
+            for (int q = 0; q < kWavesPerBlock; q++) {
+                if (q < wid) before += sh[q];
+                total += sh[q];
+            }
+            int64_t pos = running + before + inc - c;
+            while (word) {
+                int bit = __builtin_ctz(word);
+                word &= word - 1;
+                r[pos++] = (int32_t)(w * 32 + bit);
+            }
+            running += total;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) ucnt[row] = (int32_t)running;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_compact_rows(const int32_t *__restrict__ raw_off,
+                                                         const int32_t *__restrict__ raw_adj,
+                                                         const int32_t *__restrict__ off,
+                                                         int32_t *adj, int32_t n,
+                                                         uint32_t *flags) {
+    const int lane = lane_id();
+    const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    int32_t maxd = 0;
+    for (int64_t row = wave0; row < n; row += nwaves) {
+        const int32_t src = raw_off[row], dst = off[row], L = off[row + 1] - dst;
+        for (int32_t i = lane; i < L; i += kWave) adj[dst + i] = raw_adj[src + i];
+        maxd = L > maxd ? L : maxd;
+    }
+    if (lane == 0 && maxd > 0) atomicMax(&flags[F_MAX_DEG], (uint32_t)maxd);
+}
+
+__global__ void __launch_bounds__(kBlock) k_orient_count(const int32_t *__restrict__ off,
+                                                         const int32_t *__restrict__ adj,
+                                                         int32_t n, int32_t *outcnt) {
+    const int lane = lane_id();
+    const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t row = wave0; row < n; row += nwaves) {
+        const int32_t u = (int32_t)row;
+        const int32_t s = off[u], du = off[u + 1] - s;
+        int32_t c = 0;
+        for (int32_t i = lane; i < du; i += kWave) {
+            int32_t v = adj[s + i];
+            int32_t dv = off[v + 1] - off[v];
+            c += rank_less(du, u, dv, v) ? 1 : 0;
+        }
+        c = wave_sum(c);
+        if (lane == 0) outcnt[u] = c;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_orient_fill(const int32_t *__restrict__ off,
+                                                        const int32_t *__restrict__ adj,
+                                                        const int32_t *__restrict__ dag_off,
+                                                        int32_t n, int32_t *dag_adj,
+                                                        int32_t *dag_src, uint32_t *flags) {
+    const int lane = lane_id();
+    const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    int32_t maxo = 0;
+    for (int64_t row = wave0; row < n; row += nwaves) {
+        const int32_t u = (int32_t)row;
+        const int32_t s = off[u], du = off[u + 1] - s;
+        int32_t base = dag_off[u];
+        for (int32_t i0 = 0; i0 < du; i0 += kWave) {
+            int32_t i = i0 + lane;
+            int32_t v = i < du ? adj[s + i] : 0;
+            bool keep = false;
+            if (i < du) {
+                int32_t dv = off[v + 1] - off[v];
+                keep = rank_less(du, u, dv, v);
+            }
+            uint64_t mask = __ballot(keep);
+            if (keep) {
+                int32_t p = base + lanes_below(mask);
+                dag_adj[p] = v;
+                dag_src[p] = u;
+            }
+            base += __popcll(mask);
+        }
+        int32_t d = base - dag_off[u];
+        maxo = d > maxo ? d : maxo;
+    }
+    if (lane == 0 && maxo > 0) atomicMax(&flags[F_MAX_OUT], (uint32_t)maxo);
+}
+
+__global__ void k_meta(const int32_t *off, const int32_t *dag_off, int32_t n,
+                       const uint32_t *flags, int64_t *meta) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        meta[0] = off[n];
+        meta[1] = dag_off[n];
+        meta[2] = flags[F_MAX_DEG];
+        meta[3] = flags[F_MAX_OUT];
+        meta[4] = flags[F_ERR];
+        meta[5] = flags[F_BIG_COUNT];
+    }
+}
+
+struct BuildLayout {
+    // graph storage
+    int32_t *off, *adj, *dag_off, *dag_adj, *dag_src;
+    int64_t *meta;
+    // scratch
+    int32_t *cnt, *raw_off, *raw_adj, *ucnt, *outcnt, *big_list;
+    int64_t *scan_tmp;
+    uint32_t *flags, *bitmaps;
+    int64_t words;
+    int nbig_blocks;
+    uint64_t graph_bytes, scratch_bytes;
+};
+
+BuildLayout layout(int32_t n, int64_t E, void *gmem, void *smem) {
+    BuildLayout L{};
+    Carve g(gmem, ~0ull);
+    L.off = g.take<int32_t>((uint64_t)n + 1);
+    L.adj = g.take<int32_t>((uint64_t)(2 * E));
+    L.dag_off = g.take<int32_t>((uint64_t)n + 1);
+    L.dag_adj = g.take<int32_t>((uint64_t)E);
+    L.dag_src = g.take<int32_t>((uint64_t)E);
+    L.meta = g.take<int64_t>(8);
+    L.graph_bytes = g.used;
+    Carve s(smem, ~0ull);
+    L.cnt = s.take<int32_t>((uint64_t)n + 1);
+    L.raw_off = s.take<int32_t>((uint64_t)n + 1);
+    L.raw_adj = s.take<int32_t>((uint64_t)(2 * E));
+    L.ucnt = s.take<int32_t>((uint64_t)n + 1);
+    L.outcnt = s.take<int32_t>((uint64_t)n + 1);
+    L.big_list = s.take<int32_t>((uint64_t)n + 1);
+    L.scan_tmp = s.take<int64_t>(scan_tmp_words((uint64_t)n + 1));
+    L.flags = s.take<uint32_t>(F_WORDS);
+    L.words = ((int64_t)n + 31) / 32;
+    // bitmap sorters: as many concurrent workgroups as fit in 64 MiB, 1..256
+    int64_t per = L.words * 4;
+    int64_t nb = (64ll << 20) / (per > 0 ? per : 1);
+    L.nbig_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, nb));
+    L.bitmaps = s.take<uint32_t>((uint64_t)L.words * L.nbig_blocks);
+    L.scratch_bytes = s.used;
+    return L;
+}
+
+unsigned wave_grid(int64_t rows) {
+    int64_t blocks = (rows + kWavesPerBlock - 1) / kWavesPerBlock;
+    int64_t cap = (int64_t)cu_count() * 16;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, cap));
+}
+
+unsigned flat_grid(int64_t items) {
+    int64_t blocks = (items + kBlock - 1) / kBlock;
+    int64_t cap = (int64_t)cu_count() * 32;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, cap));
+}
+
+}  // namespace
+
+gpm_status graph_build_bytes(int32_t n, int64_t E, uint64_t *gb, uint64_t *sb) {
+    if (n < 1 || n > INT32_MAX - 1) return fail(GPM_INVALID_ARGUMENT, "n must be in [1, 2^31-2]");
+    if (E < 0 || 2 * E >= (int64_t)INT32_MAX)
+        return fail(GPM_UNSUPPORTED, "2 * n_input_edges must be below 2^31");
+    BuildLayout L = layout(n, E, nullptr, nullptr);
+    *gb = L.graph_bytes;
+    *sb = L.scratch_bytes;
+    return GPM_OK;
+}
+
+gpm_status graph_build(int32_t n, const int32_t *d_u, const int32_t *d_v, int64_t E, void *gmem,
+                       uint64_t gbytes, void *smem, uint64_t sbytes, hipStream_t st,
+                       gpm_graph **out) {
+    uint64_t need_g, need_s;
+    gpm_status rc = graph_build_bytes(n, E, &need_g, &need_s);
+    if (rc != GPM_OK) return rc;
+    if (!out) return fail(GPM_INVALID_ARGUMENT, "out is NULL");
+    if (E > 0 && (!d_u || !d_v)) return fail(GPM_INVALID_ARGUMENT, "edge arrays are NULL");
+    if (!gmem || !smem) return fail(GPM_INVALID_ARGUMENT, "graph or scratch memory is NULL");
+    if (((uintptr_t)gmem & 255) || ((uintptr_t)smem & 255))
+        return fail(GPM_INVALID_ARGUMENT, "device buffers must be 256-byte aligned");
+    if (gbytes < need_g || sbytes < need_s)
+        return fail(GPM_OUT_OF_MEMORY, "graph or scratch buffer smaller than gpm_graph_build_bytes");
+    BuildLayout L = layout(n, E, gmem, smem);
+
+    GPM_HIP(fill_u32(L.cnt, 0, (uint64_t)n + 1, st));
+    GPM_HIP(fill_u32(L.flags, 0, F_WORDS, st));
+    if (E > 0) {
+        hipLaunchKernelGGL(k_count_raw, dim3(flat_grid(E)), dim3(kBlock), 0, st, d_u, d_v, E, n,
+                           L.cnt, L.flags);
+        GPM_LAUNCH_CHECK("k_count_raw");
+    }
+    GPM_HIP(exclusive_scan_i32(L.cnt, L.raw_off, (uint64_t)n, L.scan_tmp, st));
+    GPM_HIP(fill_u32(L.cnt, 0, (uint64_t)n + 1, st));
+    if (E > 0) {
+        hipLaunchKernelGGL(k_scatter_raw, dim3(flat_grid(E)), dim3(kBlock), 0, st, d_u, d_v, E,
+                           n, L.raw_off, L.cnt, L.raw_adj);
+        GPM_LAUNCH_CHECK("k_scatter_raw");
+    }
+    hipLaunchKernelGGL(k_sort_rows, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.raw_off,
+                       L.raw_adj, n, L.ucnt, L.big_list, L.flags);
+    GPM_LAUNCH_CHECK("k_sort_rows");
+    hipLaunchKernelGGL(k_sort_big_rows, dim3(L.nbig_blocks), dim3(kBlock), 0, st, L.raw_off,
+                       L.raw_adj, L.ucnt, L.big_list, L.flags, L.bitmaps, L.words);
+    GPM_LAUNCH_CHECK("k_sort_big_rows");
+    GPM_HIP(exclusive_scan_i32(L.ucnt, L.off, (uint64_t)n, L.scan_tmp, st));
+    hipLaunchKernelGGL(k_compact_rows, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.raw_off,
+                       L.raw_adj, L.off, L.adj, n, L.flags);
+    GPM_LAUNCH_CHECK("k_compact_rows");
+    hipLaunchKernelGGL(k_orient_count, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.off, L.adj, n,
+                       L.outcnt);
+    GPM_LAUNCH_CHECK("k_orient_count");
+    GPM_HIP(exclusive_scan_i32(L.outcnt, L.dag_off, (uint64_t)n, L.scan_tmp, st));
+    hipLaunchKernelGGL(k_orient_fill, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.off, L.adj,
+                       L.dag_off, n, L.dag_adj, L.dag_src, L.flags);
+    GPM_LAUNCH_CHECK("k_orient_fill");
+    hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, st, L.off, L.dag_off, n, L.flags, L.meta);
+    GPM_LAUNCH_CHECK("k_meta");
+
+    int64_t meta[8] = {0};
+    GPM_HIP(hipMemcpyAsync(meta, L.meta, sizeof(int64_t) * 6, hipMemcpyDeviceToHost, st));
+    GPM_HIP(hipStreamSynchronize(st));
+    if (meta[4] != 0) return fail(GPM_NOT_CANONICAL, "an input vertex id is outside [0, n)");
+    if (meta[0] % 2 != 0 || meta[1] * 2 != meta[0])
+        return fail(GPM_DEVICE_ERROR, "graph build produced inconsistent sizes");
+
+    gpm_graph *g = new (std::nothrow) gpm_graph;
+    if (!g) return fail(GPM_OUT_OF_MEMORY, "host allocation of the graph handle failed");
+    g->n = n;
+    g->m = meta[1];
+    g->max_degree = (int32_t)meta[2];
+    g->max_out_degree = (int32_t)meta[3];
+    g->off = L.off;
+    g->adj = L.adj;
+    g->dag_off = L.dag_off;
+    g->dag_adj = L.dag_adj;
+    g->dag_src = L.dag_src;
+    *out = g;
+    return GPM_OK;
+}
+
+}  // namespace gpm

@@ -1,0 +1,766 @@
+// Triangle and k-clique counting/listing on the degree-ordered DAG.
+//
+// Every k-clique {x_0 < x_1 < ... < x_{k-1}} (in degree order) is found
+// exactly once, from x_0, as a path of the DAG: C_1 = N+(x_0), and
+// C_{i+1} = C_i ∩ N+(x_i) are the candidates for x_{i+1} (Appendix B.2
+// orientation; Appendix B.4 clique pruning; Section 5 local graph).
+// Vertices with fewer than k-1 out-neighbours are skipped (degree
+// filtering, Section 4.3).
+//
+// Kernels:
+//   k_tc_flat       triangles.  The work of root u is the list of pairs
+//                   (v, w), v in N+(u), w in N+(v); all pairs of all roots
+//                   form one flattened index space cut into fixed-size
+//                   chunks that waves pop from an atomic cursor, so a hub's
+//                   pairs are shared among many waves.  N+(u) and the pair
+//                   prefix of its out-neighbours sit in LDS; each pair is a
+//                   membership test of w in N+(u).  Optionally adds 1 to the
+//                   triangle count of each of the triangle's three arcs.
+//   k_clique_wave   k = 4, 5, roots with out-degree <= 64: one wave builds
+//                   the local graph on N+(u) as 64-bit adjacency rows in LDS
+//                   and counts cliques with AND + popcount.
+//   k_clique_block  k = 4, 5, roots with out-degree 65..1024: one workgroup,
+//                   rows of ceil(d/32) words in LDS (d <= 512) or in a
+//                   per-workgroup global slot.
+//   k_clique_generic  any k in [3, 8], any degree, counting or listing: one
+//                   wave per root, depth-first with candidate sets in a
+//                   per-wave global scratch, wave-cooperative intersections.
+#include "gpm_internal.h"
+
+#include <algorithm>
+#include <climits>
+
+namespace gpm {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWPB = kBlock / kWave;   // waves per block
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// First index i in [0, n) with a[i] >= x (n if none).
+__device__ __forceinline__ int lower_bound_i32(const int32_t *a, int n, int32_t x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Largest j in [0, n) with a[j] <= x, for ascending a with a[0] <= x.
+__device__ __forceinline__ int last_le_i32(const int32_t *a, int n, int32_t x) {
+    int lo = 0, hi = n;  // invariant: a[lo] <= x
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t last_le_i64(const int64_t *a, int64_t n, int64_t x) {
+    int64_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------ task build --
+
+// Classes of roots by out-degree.
+enum RootClass : int { RC_NONE = 0, RC_SMALL = 1, RC_MID = 2, RC_BIG = 3 };
+
+// Per root: class and pair work W_u = sum over v in N+(u) of d+(v).
+__global__ void __launch_bounds__(kBlock) k_root_work(const int32_t *__restrict__ dag_off,
+                                                      const int32_t *__restrict__ dag_adj,
+                                                      int32_t n, int32_t min_out, int32_t small_max,
+                                                      int32_t mid_max, int32_t big_max,
+                                                      int32_t *work, int32_t *cls) {
+    const int lane = lane_id();
+    const int64_t wave0 = (int64_t)blockIdx.x * kWPB + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWPB;
+    for (int64_t r = wave0; r < n; r += nwaves) {
+        const int32_t s = dag_off[r], d = dag_off[r + 1] - s;
+        int c = RC_NONE;
+        if (d >= min_out && d <= big_max) c = d <= small_max ? RC_SMALL : (d <= mid_max ? RC_MID : RC_BIG);
+        int64_t w = 0;
+        if (c != RC_NONE)
+            for (int32_t i = lane; i < d; i += kWave) {
+                int32_t v = dag_adj[s + i];
+                w += dag_off[v + 1] - dag_off[v];
+            }
+        w = wave_sum(w);
+        if (lane == 0) {
+            cls[r] = (c != RC_NONE && w > 0) ? c : RC_NONE;
+            work[r] = (int32_t)w;
+        }
+    }
+}
+
+// flag[r] = (cls[r] == want)
+__global__ void k_class_flag(const int32_t *cls, int32_t n, int32_t want, int32_t *flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) flag[i] = cls[i] == want ? 1 : 0;
+}
+
+// Compacts the flagged roots: list[pos[r]] = r, lwork[pos[r]] = work[r].
+__global__ void k_compact_roots(const int32_t *cls, const int32_t *pos, const int32_t *work,
+                                int32_t n, int32_t want, int32_t *list, int32_t *lwork) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        if (cls[i] == want) {
+            list[pos[i]] = (int32_t)i;
+            if (lwork) lwork[pos[i]] = work[i];
+        }
+}
+
+// Chunk map of a flattened pair space: chunk c starts inside active root a
+// iff wpre[a] <= c*tau < wpre[a+1]; first[c] = a.
+__global__ void k_chunk_map(const int64_t *wpre, const int32_t *pos_total, int64_t tau,
+                            int32_t *first, uint32_t *ctl) {
+    const int32_t nact = *pos_total;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (i == 0) {
+        ctl[0] = (uint32_t)nact;
+        ctl[1] = (uint32_t)((wpre[nact] + tau - 1) / tau);
+    }
+    for (; i < nact; i += stride) {
+        int64_t c0 = (wpre[i] + tau - 1) / tau, c1 = (wpre[i + 1] + tau - 1) / tau;
+        for (int64_t c = c0; c < c1; c++) first[c] = (int32_t)i;
+    }
+}
+
+// ---------------------------------------------------------- triangles ---
+
+template <int CAP, bool TE>
+__global__ void __launch_bounds__(kBlock) k_tc_flat(const int32_t *__restrict__ dag_off,
+                                                    const int32_t *__restrict__ dag_adj,
+                                                    const int32_t *__restrict__ act,
+                                                    const int64_t *__restrict__ wpre,
+                                                    const int32_t *__restrict__ first,
+                                                    const uint32_t *__restrict__ ctl,
+                                                    uint32_t *cursor, int64_t tau,
+                                                    unsigned long long *result, uint32_t *te) {
+    __shared__ int32_t s_list[kWPB][CAP];
+    __shared__ int32_t s_pre[kWPB][CAP + 1];
+    __shared__ int32_t s_base[kWPB][CAP];
+    const int lane = lane_id();
+    const int wib = threadIdx.x / kWave;
+    int32_t *list = s_list[wib], *pre = s_pre[wib], *base = s_base[wib];
+    const int32_t nact = (int32_t)ctl[0];
+    const uint32_t nchunks = ctl[1];
+    const int64_t total = wpre[nact];
+    uint64_t acc = 0;
+    for (;;) {
+        uint32_t c = 0;
+        if (lane == 0) c = atomicAdd(cursor, 1u);
+        c = __shfl(c, 0, 64);
+        if (c >= nchunks) break;
+        int64_t p = (int64_t)c * tau;
+        const int64_t p1 = min(p + tau, total);
+        int32_t a = first[c];
+        while (p < p1) {
+            const int64_t w0 = wpre[a], w1 = wpre[a + 1];
+            const int32_t u = act[a];
+            const int32_t s = dag_off[u], d = dag_off[u + 1] - s;
+            int32_t carry = 0;
+            for (int32_t i0 = 0; i0 < d; i0 += kWave) {
+                int32_t i = i0 + lane, dv = 0;
+                if (i < d) {
+                    int32_t v = dag_adj[s + i];
+                    int32_t st = dag_off[v];
+                    dv = dag_off[v + 1] - st;
+                    list[i] = v;
+                    base[i] = st;
+                }
+                int32_t inc = wave_incl_scan(dv);
+                if (i < d) pre[i + 1] = carry + inc;
+                carry += __shfl(inc, 63, 64);
+            }
+            if (lane == 0) pre[0] = 0;
+            wave_sync();
+            const int32_t q0 = (int32_t)(p - w0);
+            const int32_t q1 = (int32_t)(min(p1, w1) - w0);
+            for (int32_t qb = q0; qb < q1; qb += kWave) {
+                const int32_t q = qb + lane;
+                if (q < q1) {
+                    const int32_t j = last_le_i32(pre, d + 1, q);
+                    const int32_t e_vw = base[j] + (q - pre[j]);
+                    const int32_t w = dag_adj[e_vw];
+                    const int32_t idx = lower_bound_i32(list, d, w);
+                    if (idx < d && list[idx] == w) {
+                        acc++;
+                        if (TE) {
+                            atomicAdd(&te[s + j], 1u);
+                            atomicAdd(&te[e_vw], 1u);
+                            atomicAdd(&te[s + idx], 1u);
+                        }
+                    }
+                }
+            }
+            wave_sync();
+            p = min(p1, w1);
+            a++;
+        }
+    }
+    acc = wave_sum(acc);
+    if (lane == 0 && acc) atomicAdd(result, (unsigned long long)acc);
+}
+
+// ------------------------------------------- local-graph k-cliques ---
+
+// Counts (K-1)-vertex cliques of the local DAG whose rows are 64-bit masks
+// (local graph on <= 64 vertices), starting at local vertex with row r.
+template <int K>
+__device__ __forceinline__ uint64_t local_count64(uint64_t r, const uint64_t *rows) {
+    uint64_t c = 0;
+    uint64_t m = r;
+    while (m) {
+        int j = __builtin_ctzll(m);
+        m &= m - 1;
+        uint64_t x = r & rows[j];
+        if (K == 4) {
+            c += __popcll(x);
+        } else {
+            uint64_t mm = x;
+            while (mm) {
+                int l = __builtin_ctzll(mm);
+                mm &= mm - 1;
+                c += __popcll(x & rows[l]);
+            }
+        }
+    }
+    return c;
+}
+
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_clique_wave(const int32_t *__restrict__ dag_off,
+                                                        const int32_t *__restrict__ dag_adj,
+                                                        const int32_t *__restrict__ roots,
+                                                        const int32_t *__restrict__ nroots_p,
+                                                        unsigned long long *result) {
+    __shared__ uint64_t s_rows[kWPB][64];
+    __shared__ int32_t s_list[kWPB][64];
+    __shared__ int32_t s_pre[kWPB][65];
+    __shared__ int32_t s_base[kWPB][64];
+    const int lane = lane_id();
+    const int wib = threadIdx.x / kWave;
+    uint64_t *rows = s_rows[wib];
+    int32_t *list = s_list[wib], *pre = s_pre[wib], *base = s_base[wib];
+    const int32_t nroots = *nroots_p;
+    const int64_t wave0 = (int64_t)blockIdx.x * kWPB + wib;
+    const int64_t nwaves = (int64_t)gridDim.x * kWPB;
+    uint64_t acc = 0;
+    for (int64_t r = wave0; r < nroots; r += nwaves) {
+        const int32_t u = roots[r];
+        const int32_t s = dag_off[u], d = dag_off[u + 1] - s;
+        int32_t dv = 0;
+        if (lane < d) {
+            int32_t v = dag_adj[s + lane];
+            int32_t st = dag_off[v];
+            dv = dag_off[v + 1] - st;
+            list[lane] = v;
+            base[lane] = st;
+        }
+        int32_t inc = wave_incl_scan(dv);
+        if (lane < d) pre[lane + 1] = inc;
+        if (lane == 0) pre[0] = 0;
+        rows[lane] = 0;
+        const int32_t W = __shfl(inc, 63, 64);
+        wave_sync();
+        for (int32_t qb = 0; qb < W; qb += kWave) {
+            const int32_t q = qb + lane;
+            if (q < W) {
+                const int32_t j = last_le_i32(pre, d + 1, q);
+                const int32_t w = dag_adj[base[j] + (q - pre[j])];
+                const int32_t idx = lower_bound_i32(list, d, w);
+                if (idx < d && list[idx] == w)
+                    atomicOr((unsigned long long *)&rows[j], 1ull << idx);
+            }
+        }
+        wave_sync();
+        if (lane < d) acc += local_count64<K>(rows[lane], rows);
+        wave_sync();
+    }
+    acc = wave_sum(acc);
+    if (lane == 0 && acc) atomicAdd(result, (unsigned long long)acc);
+}
+
+constexpr int kBlockMaxD = 1024;
+constexpr int kLdsRowsMaxD = 512;
+constexpr int kMaxW32 = kBlockMaxD / 32;
+
+template <int K, bool ROWS_LDS>
+__global__ void __launch_bounds__(kBlock) k_clique_block(const int32_t *__restrict__ dag_off,
+                                                         const int32_t *__restrict__ dag_adj,
+                                                         const int32_t *__restrict__ roots,
+                                                         const int32_t *__restrict__ nroots_p,
+                                                         uint32_t *cursor, uint32_t *grows,
+                                                         unsigned long long *result) {
+    constexpr int kRowsWords = ROWS_LDS ? kLdsRowsMaxD * (kLdsRowsMaxD / 32) : 1;
+    __shared__ uint32_t s_rows[kRowsWords];
+    __shared__ int32_t list[kBlockMaxD];
+    __shared__ int32_t pre[kBlockMaxD + 1];
+    __shared__ int32_t base[kBlockMaxD];
+    __shared__ int32_t s_sum[kWPB];
+    __shared__ uint32_t s_task;
+    uint32_t *rows = ROWS_LDS ? s_rows : grows + (int64_t)blockIdx.x * kBlockMaxD * kMaxW32;
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    const uint32_t nroots = (uint32_t)*nroots_p;
+    uint64_t acc = 0;
+    for (;;) {
+        if (tid == 0) s_task = atomicAdd(cursor, 1u);
+        __syncthreads();
+        const uint32_t r = s_task;
+        __syncthreads();
+        if (r >= nroots) break;
+        const int32_t u = roots[r];
+        const int32_t s = dag_off[u], d = dag_off[u + 1] - s;
+        const int32_t W32 = (d + 31) >> 5;
+        // list, base and the pair prefix; each thread owns 4 consecutive entries
+        int32_t dv[4];
+        int32_t mysum = 0;
+        for (int t = 0; t < 4; t++) {
+            int32_t i = tid * 4 + t;
+            dv[t] = 0;
+            if (i < d) {
+                int32_t v = dag_adj[s + i];
+                int32_t st = dag_off[v];
+                dv[t] = dag_off[v + 1] - st;
+                list[i] = v;
+                base[i] = st;
+            }
+            mysum += dv[t];
+        }
+        int32_t inc = wave_incl_scan(mysum);
+        if (lane == 63) s_sum[wid] = inc;
+        for (int32_t i = tid; i < d * W32; i += kBlock) rows[i] = 0u;
+        __syncthreads();
+        int32_t before = 0;
+        for (int q = 0; q < wid; q++) before += s_sum[q];
+        int32_t run = before + inc - mysum;
+        for (int t = 0; t < 4; t++) {
+            int32_t i = tid * 4 + t;
+            run += dv[t];
+            if (i < d) pre[i + 1] = run;
+        }
+        if (tid == 0) pre[0] = 0;
+        __syncthreads();
+        const int32_t W = pre[d];
+        for (int32_t q = tid; q < W; q += kBlock) {
+            const int32_t j = last_le_i32(pre, d + 1, q);
+            const int32_t w = dag_adj[base[j] + (q - pre[j])];
+            const int32_t idx = lower_bound_i32(list, d, w);
+            if (idx < d && list[idx] == w) atomicOr(&rows[j * W32 + (idx >> 5)], 1u << (idx & 31));
+        }
+        __syncthreads();
+        for (int32_t i = tid; i < d; i += kBlock) {
+            const uint32_t *ri = rows + i * W32;
+            for (int32_t wj = 0; wj < W32; wj++) {
+                uint32_t mj = ri[wj];
+                while (mj) {
+                    const int32_t j = wj * 32 + __builtin_ctz(mj);
+                    mj &= mj - 1;
+                    const uint32_t *rj = rows + j * W32;
+                    if (K == 4) {
+                        for (int32_t w = 0; w < W32; w++) acc += __popc(ri[w] & rj[w]);
+                    } else {
+                        uint32_t x[kMaxW32];
+#pragma unroll
+                        for (int w = 0; w < kMaxW32; w++) x[w] = w < W32 ? (ri[w] & rj[w]) : 0u;
+#pragma unroll
+                        for (int wl = 0; wl < kMaxW32; wl++) {
+                            uint32_t ml = x[wl];
+                            while (ml) {
+                                const int32_t l = wl * 32 + __builtin_ctz(ml);
+                                ml &= ml - 1;
+                                const uint32_t *rl = rows + l * W32;
+                                for (int32_t w = 0; w < W32; w++) acc += __popc(x[w] & rl[w]);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    acc = wave_sum(acc);
+    if (lane == 0 && acc) atomicAdd(result, (unsigned long long)acc);
+}
+
+// ------------------------------------------------- generic DFS (k <= 8) ---
+
+constexpr int kGenMaxK = 8;
+
+struct ListOut {
+    int32_t *buf;
+    uint64_t cap;
+};
+
+// Wave-cooperative |A ∩ B| or A ∩ B (ascending, into out) for ascending
+// global arrays; lanes walk the shorter list and binary-search the longer.
+template <bool WRITE>
+__device__ int32_t wave_intersect(const int32_t *a, int32_t na, const int32_t *b, int32_t nb,
+                                  int32_t *out) {
+    const int lane = lane_id();
+    if (na > nb) {
+        const int32_t *t = a; a = b; b = t;
+        int32_t tn = na; na = nb; nb = tn;
+    }
+    int32_t cnt = 0;
+    for (int32_t i0 = 0; i0 < na; i0 += kWave) {
+        const int32_t i = i0 + lane;
+        bool hit = false;
+        int32_t x = 0;
+        if (i < na) {
+            x = a[i];
+            int32_t p = lower_bound_i32(b, nb, x);
+            hit = p < nb && b[p] == x;
+        }
+        const uint64_t mask = __ballot(hit);
+        if (WRITE && hit) out[cnt + lanes_below(mask)] = x;
+        cnt += __popcll(mask);
+    }
+    return cnt;
+}
+
+__device__ __forceinline__ void sort_small(uint64_t *k, int len) {
+    for (int i = 1; i < len; i++) {
+        uint64_t x = k[i];
+        int j = i - 1;
+        while (j >= 0 && k[j] > x) { k[j + 1] = k[j]; j--; }
+        k[j + 1] = x;
+    }
+}
+
+template <bool LIST>
+__global__ void __launch_bounds__(kBlock) k_clique_generic(const int32_t *__restrict__ dag_off,
+                                                           const int32_t *__restrict__ dag_adj,
+                                                           int32_t n, int32_t k, int32_t maxout,
+                                                           int32_t *scratch,
+                                                           unsigned long long *result,
+                                                           ListOut lo) {
+    const int lane = lane_id();
+    const int64_t wave_gid = (int64_t)blockIdx.x * kWPB + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWPB;
+    int32_t *mine = scratch + wave_gid * (int64_t)(kGenMaxK - 2) * maxout;
+    uint64_t acc = 0, hsum = 0;
+    const int last = k - 2;   // level whose intersection is counted/listed
+    for (int64_t ur = wave_gid; ur < n; ur += nwaves) {
+        const int32_t u = (int32_t)ur;
+        const int32_t s = dag_off[u], d = dag_off[u + 1] - s;
+        if (d < k - 1) continue;
+        const int32_t *cand[kGenMaxK];
+        int32_t csz[kGenMaxK], it[kGenMaxK], pv[kGenMaxK];
+        cand[1] = dag_adj + s;
+        csz[1] = d;
+        it[1] = 0;
+        pv[0] = u;
+        int l = 1;
+        while (l >= 1) {
+            if (it[l] >= csz[l]) {
+                l--;
+                if (l >= 1) it[l]++;
+                continue;
+            }
+            const int32_t v = cand[l][it[l]];
+            pv[l] = v;
+            const int32_t vs = dag_off[v], vd = dag_off[v + 1] - vs;
+            if (l == last) {
+                if (!LIST) {
+                    acc += wave_intersect<false>(cand[l], csz[l], dag_adj + vs, vd, nullptr);
+                } else {
+                    // enumerate C_l ∩ N+(v): each element closes a k-clique
+                    const int32_t *a = cand[l], *b = dag_adj + vs;
+                    int32_t na = csz[l], nb = vd;
+                    for (int32_t i0 = 0; i0 < na; i0 += kWave) {
+                        const int32_t i = i0 + lane;
+                        bool hit = false;
+                        int32_t x = 0;
+                        if (i < na) {
+                            x = a[i];
+                            int32_t p = lower_bound_i32(b, nb, x);
+                            hit = p < nb && b[p] == x;
+                        }
+                        const uint64_t mask = __ballot(hit);
+                        if (!mask) continue;
+                        unsigned long long basei = 0;
+                        if (lane == 0) basei = atomicAdd(&result[0], (unsigned long long)__popcll(mask));
+                        basei = __shfl(basei, 0, 64);
+                        if (hit) {
+                            uint64_t key[kGenMaxK];
+                            for (int t = 0; t <= last; t++) key[t] = (uint64_t)(uint32_t)pv[t];
+                            key[last + 1] = (uint64_t)(uint32_t)x;
+                            const uint64_t slot = basei + lanes_below(mask);
+                            if (slot < lo.cap) {
+                                int32_t *o = lo.buf + slot * (uint64_t)k;
+                                for (int t = 0; t <= last; t++) o[t] = pv[t];
+                                o[last + 1] = x;
+                            }
+                            sort_small(key, k);
+                            uint64_t h = (uint64_t)k;
+                            for (int t = 0; t < k; t++) h = fmix64((h ^ key[t]) + 0x9E3779B97F4A7C15ull);
+                            hsum += h;
+                        }
+                    }
+                }
+                it[l]++;
+            } else {
+                int32_t *out = mine + (int64_t)(l - 1) * maxout;
+                const int32_t c = wave_intersect<true>(cand[l], csz[l], dag_adj + vs, vd, out);
+                wave_sync();
+                if (c >= k - 1 - l) {
+                    l++;
+                    cand[l] = out;
+                    csz[l] = c;
+                    it[l] = 0;
+                } else {
+                    it[l]++;
+                }
+            }
+        }
+    }
+    if (!LIST) {
+        acc = wave_sum(acc);
+        if (lane == 0 && acc) atomicAdd(&result[0], (unsigned long long)acc);
+    } else {
+        hsum = wave_sum(hsum);
+        if (lane == 0) atomicAdd(&result[2], (unsigned long long)hsum);
+    }
+}
+
+__global__ void k_finish_listing(unsigned long long *result, uint64_t cap) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) result[1] = result[0] < cap ? result[0] : cap;
+}
+
+// ------------------------------------------------------------ host side --
+
+constexpr int64_t kTcTau = 4096;
+constexpr int32_t kSmallMax = 256;   // k_tc_flat<256> class
+constexpr int32_t kTcMax = 1024;     // k_tc_flat<1024> class
+
+struct CliqueWs {
+    unsigned long long *result;   // [4]
+    uint32_t *ctl;                // [16]: cursors and per-class {nact, nchunks}
+    int32_t *work, *cls, *flag, *pos;
+    int32_t *list_s, *list_m, *list_b;
+    int32_t *lwork;               // compacted work of one class (reused)
+    int64_t *wpre_s, *wpre_m;
+    int32_t *first_s, *first_m;
+    int64_t *scan_tmp;
+    uint32_t *grows;              // per-workgroup local-graph rows (global)
+    int32_t *gen_scratch;
+    int gen_waves, grows_blocks;
+    uint64_t bytes;
+};
+
+int64_t chunk_bound(const gpm_graph *g) {
+    // total pair work = sum_v d-(v) d+(v) <= m * max_out; chunks = ceil(total / tau)
+    int64_t w = g->m * (int64_t)std::max(g->max_out_degree, 1);
+    return w / kTcTau + 2;
+}
+
+CliqueWs clique_layout(const gpm_graph *g, int32_t k, bool list, void *base) {
+    CliqueWs W{};
+    Carve c(base, ~0ull);
+    const uint64_t n1 = (uint64_t)g->n + 1;
+    W.result = c.take<unsigned long long>(4);
+    W.ctl = c.take<uint32_t>(16);
+    W.work = c.take<int32_t>(n1);
+    W.cls = c.take<int32_t>(n1);
+    W.flag = c.take<int32_t>(n1);
+    W.pos = c.take<int32_t>(n1);
+    W.list_s = c.take<int32_t>(n1);
+    W.list_m = c.take<int32_t>(n1);
+    W.list_b = c.take<int32_t>(n1);
+    W.lwork = c.take<int32_t>(n1);
+    W.wpre_s = c.take<int64_t>(n1);
+    W.wpre_m = c.take<int64_t>(n1);
+    W.scan_tmp = c.take<int64_t>(scan_tmp_words(n1));
+    bool generic = list || k > 5 || g->max_out_degree > kTcMax;
+    if (!generic && k == 3) {
+        W.first_s = c.take<int32_t>((uint64_t)chunk_bound(g));
+        W.first_m = c.take<int32_t>((uint64_t)chunk_bound(g));
+    }
+    if (!generic && k >= 4) {
+        W.grows_blocks = persistent_blocks(kWPB, 2);
+        W.grows = c.take<uint32_t>((uint64_t)W.grows_blocks * kBlockMaxD * kMaxW32);
+    }
+    if (generic) {
+        W.gen_waves = persistent_blocks(kWPB, 8) * kWPB;
+        W.gen_scratch = c.take<int32_t>((uint64_t)W.gen_waves * (kGenMaxK - 2) *
+                                        (uint64_t)std::max(1, g->max_out_degree));
+    }
+    W.bytes = c.used;
+    return W;
+}
+
+unsigned grid_for(int64_t items, int per_block, int cap_per_cu) {
+    int64_t b = (items + per_block - 1) / per_block;
+    int64_t cap = (int64_t)cu_count() * cap_per_cu;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+// Builds the compacted root list of one class; returns its count in *count_dev
+// (device int32 = pos[n]) and, when wpre is given, the int64 work prefix.
+hipError_t build_class(const gpm_graph *g, CliqueWs &W, int32_t want, int32_t *list,
+                       int64_t *wpre, hipStream_t st) {
+    const int32_t n = g->n;
+    if (wpre) {
+        hipError_t z = fill_u32(W.lwork, 0, (uint64_t)n + 1, st);
+        if (z != hipSuccess) return z;
+    }
+    hipLaunchKernelGGL(k_class_flag, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.cls, n, want,
+                       W.flag);
+    hipError_t e = exclusive_scan_i32(W.flag, W.pos, (uint64_t)n, W.scan_tmp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_compact_roots, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.cls, W.pos,
+                       W.work, n, want, list, wpre ? W.lwork : (int32_t *)nullptr);
+    e = hipGetLastError();
+    if (e != hipSuccess || !wpre) return e;
+    // work prefix over the class's roots; the count is pos[n] (device)
+    return exclusive_scan_i64(W.lwork, wpre, (uint64_t)n, W.scan_tmp, st);
+}
+
+}  // namespace
+
+gpm_status clique_workspace_bytes(const gpm_graph *g, int32_t k, bool list, uint64_t *bytes) {
+    if (k < 3 || k > kGenMaxK) return fail(GPM_UNSUPPORTED, "clique size must be in [3, 8]");
+    *bytes = clique_layout(g, k, list, nullptr).bytes;
+    return GPM_OK;
+}
+
+// Triangle scatter used by motif counting: adds 1 to the triangle count of
+// each of the three arcs of every triangle (te, m words, must be zero on
+// entry) and the number of triangles to *tri (zero on entry).  Uses the
+// triangle workspace (clique_workspace_bytes(g, 3, false)).
+gpm_status triangle_arc_counts(const gpm_graph *g, void *ws, uint64_t ws_bytes, uint32_t *te,
+                               unsigned long long *tri, hipStream_t st) {
+    if (g->max_out_degree > kTcMax)
+        return fail(GPM_UNSUPPORTED, "motif counting needs every out-degree <= 1024");
+    CliqueWs W = clique_layout(g, 3, false, ws);
+    if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
+    const int32_t n = g->n;
+    GPM_HIP(fill_u32(W.ctl, 0, 16, st));
+    hipLaunchKernelGGL(k_root_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st, g->dag_off,
+                       g->dag_adj, n, 2, kSmallMax, kTcMax, kTcMax, W.work, W.cls);
+    GPM_LAUNCH_CHECK("k_root_work");
+    GPM_HIP(build_class(g, W, RC_SMALL, W.list_s, W.wpre_s, st));
+    hipLaunchKernelGGL(k_chunk_map, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.wpre_s,
+                       W.pos + n, kTcTau, W.first_s, W.ctl + 2);
+    GPM_LAUNCH_CHECK("k_chunk_map");
+    GPM_HIP(build_class(g, W, RC_MID, W.list_m, W.wpre_m, st));
+    hipLaunchKernelGGL(k_chunk_map, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.wpre_m,
+                       W.pos + n, kTcTau, W.first_m, W.ctl + 4);
+    GPM_LAUNCH_CHECK("k_chunk_map");
+    hipLaunchKernelGGL((k_tc_flat<kTcMax, true>), dim3((unsigned)persistent_blocks(kWPB, 3)),
+                       dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_m, W.wpre_m, W.first_m,
+                       W.ctl + 4, W.ctl + 1, kTcTau, tri, te);
+    GPM_LAUNCH_CHECK("k_tc_flat<1024, te>");
+    hipLaunchKernelGGL((k_tc_flat<kSmallMax, true>), dim3((unsigned)persistent_blocks(kWPB, 8)),
+                       dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_s, W.wpre_s, W.first_s,
+                       W.ctl + 2, W.ctl + 0, kTcTau, tri, te);
+    GPM_LAUNCH_CHECK("k_tc_flat<256, te>");
+    return GPM_OK;
+}
+
+gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64_t ws_bytes,
+                      unsigned long long *d_count, int32_t *d_buf, uint64_t cap,
+                      unsigned long long *d_result, hipStream_t st) {
+    CliqueWs W = clique_layout(g, k, list, ws);
+    if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
+    const int32_t n = g->n;
+    unsigned long long *res = list ? d_result : W.result;
+    GPM_HIP(fill_u32(res, 0, list ? 6 : 8, st));
+    GPM_HIP(fill_u32(W.ctl, 0, 16, st));
+    const bool generic = list || k > 5 || g->max_out_degree > kTcMax;
+    if (generic) {
+        ListOut lo{d_buf, list ? cap : 0};
+        int blocks = W.gen_waves / kWPB;
+        if (list)
+            hipLaunchKernelGGL(k_clique_generic<true>, dim3(blocks), dim3(kBlock), 0, st,
+                               g->dag_off, g->dag_adj, n, k, std::max(1, g->max_out_degree),
+                               W.gen_scratch, res, lo);
+        else
+            hipLaunchKernelGGL(k_clique_generic<false>, dim3(blocks), dim3(kBlock), 0, st,
+                               g->dag_off, g->dag_adj, n, k, std::max(1, g->max_out_degree),
+                               W.gen_scratch, res, lo);
+        GPM_LAUNCH_CHECK("k_clique_generic");
+        if (list) {
+            hipLaunchKernelGGL(k_finish_listing, dim3(1), dim3(64), 0, st, res, cap);
+            GPM_LAUNCH_CHECK("k_finish_listing");
+        }
+    } else {
+        const int32_t small_max = k == 3 ? kSmallMax : 64;
+        const int32_t mid_max = k == 3 ? kTcMax : kLdsRowsMaxD;
+        hipLaunchKernelGGL(k_root_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st,
+                           g->dag_off, g->dag_adj, n, k - 1, small_max, mid_max, kTcMax, W.work,
+                           W.cls);
+        GPM_LAUNCH_CHECK("k_root_work");
+        if (k == 3) {
+            GPM_HIP(build_class(g, W, RC_SMALL, W.list_s, W.wpre_s, st));
+            hipLaunchKernelGGL(k_chunk_map, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.wpre_s,
+                               W.pos + n, kTcTau, W.first_s, W.ctl + 2);
+            GPM_LAUNCH_CHECK("k_chunk_map");
+            GPM_HIP(build_class(g, W, RC_MID, W.list_m, W.wpre_m, st));
+            hipLaunchKernelGGL(k_chunk_map, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.wpre_m,
+                               W.pos + n, kTcTau, W.first_m, W.ctl + 4);
+            GPM_LAUNCH_CHECK("k_chunk_map");
+            unsigned blocks = (unsigned)persistent_blocks(kWPB, 8);
+            hipLaunchKernelGGL((k_tc_flat<kTcMax, false>), dim3((unsigned)persistent_blocks(kWPB, 3)),
+                               dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_m, W.wpre_m,
+                               W.first_m, W.ctl + 4, W.ctl + 1, kTcTau, res, (uint32_t *)nullptr);
+            GPM_LAUNCH_CHECK("k_tc_flat<1024>");
+            hipLaunchKernelGGL((k_tc_flat<kSmallMax, false>), dim3(blocks), dim3(kBlock), 0, st,
+                               g->dag_off, g->dag_adj, W.list_s, W.wpre_s, W.first_s, W.ctl + 2,
+                               W.ctl + 0, kTcTau, res, (uint32_t *)nullptr);
+            GPM_LAUNCH_CHECK("k_tc_flat<256>");
+        } else {
+            // three classes; each count lives in its own pos snapshot
+            int32_t *cnt_s = (int32_t *)(W.ctl + 8), *cnt_m = (int32_t *)(W.ctl + 9),
+                    *cnt_b = (int32_t *)(W.ctl + 10);
+            GPM_HIP(build_class(g, W, RC_BIG, W.list_b, nullptr, st));
+            GPM_HIP(hipMemcpyAsync(cnt_b, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
+            GPM_HIP(build_class(g, W, RC_MID, W.list_m, nullptr, st));
+            GPM_HIP(hipMemcpyAsync(cnt_m, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
+            GPM_HIP(build_class(g, W, RC_SMALL, W.list_s, nullptr, st));
+            GPM_HIP(hipMemcpyAsync(cnt_s, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
+            if (k == 4) {
+                hipLaunchKernelGGL((k_clique_block<4, false>), dim3(W.grows_blocks), dim3(kBlock), 0,
+                                   st, g->dag_off, g->dag_adj, W.list_b, cnt_b, W.ctl + 0, W.grows,
+                                   res);
+                hipLaunchKernelGGL((k_clique_block<4, true>), dim3((unsigned)persistent_blocks(kWPB, 3)),
+                                   dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_m, cnt_m,
+                                   W.ctl + 1, (uint32_t *)nullptr, res);
+                hipLaunchKernelGGL(k_clique_wave<4>, dim3((unsigned)persistent_blocks(kWPB, 8)),
+                                   dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_s, cnt_s,
+                                   res);
+            } else {
+                hipLaunchKernelGGL((k_clique_block<5, false>), dim3(W.grows_blocks), dim3(kBlock), 0,
+                                   st, g->dag_off, g->dag_adj, W.list_b, cnt_b, W.ctl + 0, W.grows,
+                                   res);
+                hipLaunchKernelGGL((k_clique_block<5, true>), dim3((unsigned)persistent_blocks(kWPB, 3)),
+                                   dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_m, cnt_m,
+                                   W.ctl + 1, (uint32_t *)nullptr, res);
+                hipLaunchKernelGGL(k_clique_wave<5>, dim3((unsigned)persistent_blocks(kWPB, 8)),
+                                   dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_s, cnt_s,
+                                   res);
+            }
+            GPM_LAUNCH_CHECK("k_clique_*");
+        }
+    }
+    if (!list) GPM_HIP(hipMemcpyAsync(d_count, res, 8, hipMemcpyDeviceToDevice, st));
+    return GPM_OK;
+}
+
+}  // namespace gpm

@@ -1,0 +1,166 @@
+"""Device graph build and clique counting/listing against the CPU oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+from oracle import canonical_csr
+from gpu_util import build, degree_rank_dag
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "rmat_counts.json")
+
+
+@pytest.fixture(scope="module")
+def gpm():
+    import paper_2011_03135_amd as m
+    m.load()
+    return m
+
+
+def noisy_stream(n, pairs, seed):
+    """A raw stream holding every pair in both directions, repeats and loops."""
+    rng = np.random.default_rng(seed)
+    a = np.array([p[0] for p in pairs], np.int64)
+    b = np.array([p[1] for p in pairs], np.int64)
+    rep = rng.integers(1, 4, size=a.shape[0])
+    a2, b2 = np.repeat(a, rep), np.repeat(b, rep)
+    flip = rng.integers(0, 2, size=a2.shape[0]).astype(bool)
+    u = np.where(flip, b2, a2)
+    v = np.where(flip, a2, b2)
+    loops = rng.integers(0, n, size=max(1, n // 10))
+    u = np.concatenate([u, loops])
+    v = np.concatenate([v, loops])
+    perm = rng.permutation(u.shape[0])
+    return graphgen.EdgeList(n, u[perm].astype(np.int32), v[perm].astype(np.int32), "noisy")
+
+
+def build_cases():
+    star = graphgen.star_graph(5000)                      # one 5000-entry row: bitmap sorter
+    star_pairs = list(zip(star.u.tolist(), star.v.tolist()))
+    mid = graphgen.star_graph(700)                        # a 700-entry row: LDS sorter
+    return [
+        graphgen.erdos_renyi(300, 0.05, 3),
+        graphgen.rmat(12, seed=7),
+        noisy_stream(5001, star_pairs, 1),
+        noisy_stream(701, list(zip(mid.u.tolist(), mid.v.tolist())), 2),
+        graphgen.complete_graph(40),
+        graphgen.EdgeList(5, np.zeros(0, np.int32), np.zeros(0, np.int32), "empty"),
+    ]
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_build_matches_oracle(gpm, case):
+    e = build_cases()[case]
+    print(f"build case {case} {e.name} n={e.n} E={e.num_input_edges}", flush=True)
+    g = build(gpm, e)
+    off_ref, adj_ref = canonical_csr(e.n, e.u, e.v)
+    off, adj = (t.cpu().numpy() for t in g.csr())
+    assert g.n == e.n and g.m == adj_ref.shape[0] // 2
+    assert np.array_equal(off, off_ref.astype(np.int32))
+    assert np.array_equal(adj, adj_ref)
+    dag_off, dag_adj, dag_src = (t.cpu().numpy() for t in g.dag())
+    src, dst = degree_rank_dag(off_ref, adj_ref)
+    assert np.array_equal(dag_adj, dst.astype(np.int32))
+    assert np.array_equal(dag_src, src.astype(np.int32))
+    assert np.array_equal(np.diff(dag_off), np.bincount(src, minlength=e.n))
+    assert g.max_degree == (int(np.diff(off_ref).max()) if e.n else 0)
+    assert g.max_out_degree == int(np.diff(dag_off).max())
+
+
+def test_build_rejects_out_of_range(gpm):
+    e = graphgen.EdgeList(4, np.array([0, 1], np.int32), np.array([1, 4], np.int32))
+    with pytest.raises(gpm.GpmError) as ei:
+        build(gpm, e)
+    assert ei.value.status == 6
+
+
+def clique_cases():
+    return [
+        graphgen.complete_graph(12),
+        graphgen.complete_graph(70),                        # out-degree 69: workgroup class
+        graphgen.complete_multipartite([3, 5, 2, 7, 4, 6]),
+        graphgen.erdos_renyi(200, 0.15, 11),
+        graphgen.rmat(12, seed=5),
+        graphgen.rmat(14, seed=14),
+        graphgen.star_graph(100),
+        graphgen.EdgeList(5, np.zeros(0, np.int32), np.zeros(0, np.int32), "empty"),
+    ]
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_clique_counts(gpm, case):
+    e = clique_cases()[case]
+    g = build(gpm, e)
+    off, adj = canonical_csr(e.n, e.u, e.v)
+    for k in (3, 4, 5, 6):
+        print(f"clique case {case} {e.name} k={k}", flush=True)
+        assert gpm.count(g, gpm.clique(k)) == oracle.clique_count(off, adj, k), (e.name, k)
+
+
+def test_er_workload_triangles(gpm):
+    """Erdos-Renyi G(4096, 0.004), seed 1."""
+    e = graphgen.erdos_renyi(4096, 0.004, 1)
+    g = build(gpm, e)
+    off, adj = canonical_csr(e.n, e.u, e.v)
+    assert gpm.count(g, gpm.clique(3)) == oracle.triangle_count(off, adj)
+
+
+def test_generic_path_high_out_degree(gpm):
+    """Out-degrees above 1024 take the depth-first kernel."""
+    e = graphgen.complete_multipartite([2] * 520)
+    g = build(gpm, e)
+    assert g.max_out_degree > 1024
+    off, adj = canonical_csr(e.n, e.u, e.v)
+    assert gpm.count(g, gpm.clique(3)) == oracle.clique_count(off, adj, 3)
+
+
+def test_relabel_invariance(gpm):
+    e = graphgen.rmat(13, seed=3)
+    a = build(gpm, e)
+    b = build(gpm, graphgen.relabel(e, 77))
+    for k in (3, 4, 5):
+        assert gpm.count(a, gpm.clique(k)) == gpm.count(b, gpm.clique(k))
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_clique_listing(gpm, k):
+    e = graphgen.erdos_renyi(60, 0.35, 4)
+    g = build(gpm, e)
+    off, adj = canonical_csr(e.n, e.u, e.v)
+    total, chk, rows = oracle.clique_list(off, adj, k, cap=10 ** 6)
+    t, w, c, got = gpm.list_embeddings(g, gpm.clique(k, gpm.VERTEX_INDUCED | gpm.LIST), 10 ** 6)
+    assert (t, w, c) == (total, total, chk)
+    assert {tuple(sorted(r)) for r in got.cpu().tolist()} == {tuple(r) for r in rows.tolist()}
+    # truncated: totals and checksum still exact, every written row a clique
+    cap = max(1, total // 3)
+    t, w, c, got = gpm.list_embeddings(g, gpm.clique(k, gpm.VERTEX_INDUCED | gpm.LIST), cap)
+    assert (t, w, c) == (total, min(cap, total), chk)
+    A = set(map(tuple, np.stack([np.repeat(np.arange(e.n), np.diff(off)), adj], 1).tolist()))
+    for r in got.cpu().tolist():
+        assert len(set(r)) == k
+        assert all((a, b) in A for i, a in enumerate(r) for b in r[i + 1:])
+
+
+def _golden():
+    if not os.path.exists(GOLDEN):
+        pytest.skip("golden counts not generated")
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("scale", [18, 20])
+def test_rmat_clique_counts_golden(gpm, scale):
+    gold = _golden().get(f"rmat{scale}")
+    if gold is None or "clique5" not in gold:
+        pytest.skip("golden counts for this scale not generated")
+    e = graphgen.rmat(scale, seed=scale)
+    g = build(gpm, e)
+    assert g.m == gold["m"]
+    for k in (3, 4, 5):
+        print(f"rmat{scale} k={k}", flush=True)
+        assert gpm.count(g, gpm.clique(k)) == gold[f"clique{k}"], k
