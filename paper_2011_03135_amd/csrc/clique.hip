@@ -478,7 +478,8 @@ __global__ void __launch_bounds__(kBlock) k_clique_generic(const int32_t *__rest
             const int32_t vs = dag_off[v], vd = dag_off[v + 1] - vs;
             if (l == last) {
                 if (!LIST) {
-                    acc += wave_intersect<false>(cand[l], csz[l], dag_adj + vs, vd, nullptr);
+                    const int32_t c = wave_intersect<false>(cand[l], csz[l], dag_adj + vs, vd, nullptr);
+                    if (lane == 0) acc += (uint64_t)c;   // c is wave-uniform
                 } else {
                     // enumerate C_l ∩ N+(v): each element closes a k-clique
                     const int32_t *a = cand[l], *b = dag_adj + vs;

@@ -1,0 +1,491 @@
+// Induced 3- and 4-motif counting by local counting (Section 5: the wedge
+// equation and the diamond count from per-edge triangle counts; Appendix A:
+// the 3-motif and 4-motif local-counting listings, whose elided final step is
+// completed here with per-edge identities).
+//
+// 3-motifs: wedges (open) = sum_v C(d_v, 2) - 3T, triangles = T.
+//
+// 4-motifs.  For every undirected edge e = (u, v) with T_e triangles,
+// S_u = d_u - T_e - 1 and S_v = d_v - T_e - 1 (the local wedge terms of the
+// wedge equation), these sums over edges, each edge visited once, equal
+// induced counts (I_*):
+//   sum C(T_e, 2)                  = I_diamond + 6 I_K4
+//   sum T_e (S_u + S_v)            = 2 I_paw + 4 I_diamond
+//   sum S_u S_v                    = I_P4 + 4 I_C4
+//   sum C(S_u, 2) + C(S_v, 2)      = 3 I_claw + I_paw
+// With I_K4 from 4-clique counting and the number of 4-cycles N_C4 (not
+// necessarily induced; N_C4 = I_C4 + I_diamond + 3 I_K4) the system solves
+// exactly; every division is checked.
+//
+// N_C4 is counted from each cycle's highest-ranked vertex x (degree order):
+// for wedges x - y - z with y, z ranked below x, c(x, z) = #middles y and the
+// cycles with apex x and opposite vertex z number C(c(x, z), 2).  The sum is
+// formed incrementally: each new wedge to z adds the number of earlier ones.
+//   light apexes (wedge work <= kLightW): one wave, LDS hash table on z;
+//   heavy apexes: tasks (x, part p) with dense LDS counters for z in part p;
+//   each in-neighbour list N(y) is entered at part p by binary search.
+#include "gpm_internal.h"
+
+#include <algorithm>
+#include <climits>
+
+namespace gpm {
+
+gpm_status clique_workspace_bytes(const gpm_graph *g, int32_t k, bool list, uint64_t *bytes);
+gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64_t ws_bytes,
+                      unsigned long long *d_count, int32_t *d_buf, uint64_t cap,
+                      unsigned long long *d_result, hipStream_t st);
+gpm_status triangle_arc_counts(const gpm_graph *g, void *ws, uint64_t ws_bytes, uint32_t *te,
+                               unsigned long long *tri, hipStream_t st);
+
+namespace {
+
+typedef unsigned __int128 u128;
+
+constexpr int kBlock = 256;
+constexpr int kWPB = kBlock / kWave;
+constexpr int kLightW = 512;         // wedge work of a light apex
+constexpr int kHashSlots = 1024;     // per-wave LDS hash (load <= 1/2)
+constexpr int kPartZ = 8192;         // z-range per heavy task (LDS counters)
+constexpr int kYChunk = kBlock;      // in-neighbours staged per round
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ u128 wave_sum_u128(u128 x) {
+    uint64_t lo = (uint64_t)x, hi = (uint64_t)(x >> 64);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint64_t lo2 = __shfl_xor(lo, o, 64), hi2 = __shfl_xor(hi, o, 64);
+        uint64_t s = lo + lo2;
+        hi = hi + hi2 + (s < lo ? 1 : 0);
+        lo = s;
+    }
+    return ((u128)hi << 64) | lo;
+}
+
+__device__ __forceinline__ int lower_bound_i32(const int32_t *a, int n, int32_t x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int last_le_i32(const int32_t *a, int n, int32_t x) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_degrees(const int32_t *off, int32_t n, int32_t *deg) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) deg[i] = off[i + 1] - off[i];
+}
+
+// sum_v C(d_v, 2) as 128 bits.
+__global__ void __launch_bounds__(kBlock) k_wedge_sum(const int32_t *deg, int32_t n,
+                                                      unsigned long long *out) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * kBlock;
+    u128 s = 0;
+    for (; i < n; i += stride) {
+        uint64_t d = (uint64_t)deg[i];
+        s += (u128)(d * (d - (d > 0)) / 2);
+    }
+    s = wave_sum_u128(s);
+    if (lane_id() == 0 && s) atomic_add_u128(out, s);
+}
+
+// The four per-edge local-count sums, each 128 bits: out[0..7].
+__global__ void __launch_bounds__(kBlock) k_lc_sums(const int32_t *__restrict__ dag_src,
+                                                    const int32_t *__restrict__ dag_adj,
+                                                    const uint32_t *__restrict__ te,
+                                                    const int32_t *__restrict__ deg, int64_t m,
+                                                    unsigned long long *out) {
+    int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * kBlock;
+    u128 s1 = 0, s2 = 0, s3 = 0, s4 = 0;
+    for (; e < m; e += stride) {
+        const uint64_t t = te[e];
+        const uint64_t du = (uint64_t)deg[dag_src[e]], dv = (uint64_t)deg[dag_adj[e]];
+        const uint64_t su = du - t - 1, sv = dv - t - 1;
+        s1 += (u128)(t * (t - (t > 0)) / 2);
+        s2 += (u128)t * (su + sv);
+        s3 += (u128)su * sv;
+        s4 += (u128)(su * (su - (su > 0)) / 2) + (u128)(sv * (sv - (sv > 0)) / 2);
+    }
+    s1 = wave_sum_u128(s1);
+    s2 = wave_sum_u128(s2);
+    s3 = wave_sum_u128(s3);
+    s4 = wave_sum_u128(s4);
+    if (lane_id() == 0) {
+        if (s1) atomic_add_u128(out + 0, s1);
+        if (s2) atomic_add_u128(out + 2, s2);
+        if (s3) atomic_add_u128(out + 4, s3);
+        if (s4) atomic_add_u128(out + 6, s4);
+    }
+}
+
+// ------------------------------------------------------------ 4-cycles ---
+
+enum C4Class : int { C4_NONE = 0, C4_LIGHT = 1, C4_HEAVY = 2 };
+
+// Wedge work of apex x: sum of d(y) over in-neighbours y (ranked below x).
+__global__ void __launch_bounds__(kBlock) k_c4_work(const int32_t *__restrict__ off,
+                                                    const int32_t *__restrict__ adj,
+                                                    const int32_t *__restrict__ deg, int32_t n,
+                                                    int32_t *cls) {
+    const int lane = lane_id();
+    const int64_t wave0 = (int64_t)blockIdx.x * kWPB + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWPB;
+    for (int64_t r = wave0; r < n; r += nwaves) {
+        const int32_t x = (int32_t)r, s = off[x], dx = off[x + 1] - s;
+        int64_t w = 0;
+        int32_t ny = 0;
+        for (int32_t i = lane; i < dx; i += kWave) {
+            const int32_t y = adj[s + i], dy = deg[y];
+            if (rank_less(dy, y, dx, x)) {
+                w += dy;
+                ny++;
+            }
+        }
+        w = wave_sum(w);
+        ny = wave_sum(ny);
+        if (lane == 0) cls[x] = (ny < 2) ? C4_NONE : (w <= kLightW ? C4_LIGHT : C4_HEAVY);
+    }
+}
+
+__global__ void k_flag_eq(const int32_t *cls, int32_t n, int32_t want, int32_t *flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) flag[i] = cls[i] == want ? 1 : 0;
+}
+
+__global__ void k_compact_eq(const int32_t *cls, const int32_t *pos, int32_t n, int32_t want,
+                             int32_t *list) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        if (cls[i] == want) list[pos[i]] = (int32_t)i;
+}
+
+__device__ __forceinline__ uint32_t hash_slot(int32_t z) {
+    return ((uint32_t)z * 0x9E3779B1u) >> 22;   // 10 bits -> kHashSlots
+}
+
+// Light apexes: one wave each, LDS hash z -> count, wedge by wedge.
+__global__ void __launch_bounds__(kBlock) k_c4_light(const int32_t *__restrict__ off,
+                                                     const int32_t *__restrict__ adj,
+                                                     const int32_t *__restrict__ deg,
+                                                     const int32_t *__restrict__ list,
+                                                     const int32_t *__restrict__ count_p,
+                                                     unsigned long long *out) {
+    __shared__ int32_t s_key[kWPB][kHashSlots];
+    __shared__ uint32_t s_cnt[kWPB][kHashSlots];
+    __shared__ int32_t s_pre[kWPB][kLightW + 1];
+    __shared__ int32_t s_base[kWPB][kLightW];
+    const int lane = lane_id(), wib = threadIdx.x / kWave;
+    int32_t *key = s_key[wib], *pre = s_pre[wib], *base = s_base[wib];
+    uint32_t *cnt = s_cnt[wib];
+    const int32_t count = *count_p;
+    const int64_t wave0 = (int64_t)blockIdx.x * kWPB + wib;
+    const int64_t nwaves = (int64_t)gridDim.x * kWPB;
+    for (int i = lane; i < kHashSlots; i += kWave) { key[i] = -1; cnt[i] = 0; }
+    uint64_t acc = 0;
+    for (int64_t r = wave0; r < count; r += nwaves) {
+        const int32_t x = list[r], s = off[x], dx = off[x + 1] - s;
+        // stage in-neighbours: their list starts and a prefix of their degrees
+        int32_t ny = 0, carry = 0;
+        for (int32_t i0 = 0; i0 < dx; i0 += kWave) {
+            const int32_t i = i0 + lane;
+            int32_t y = 0, dy = 0;
+            bool in = false;
+            if (i < dx) {
+                y = adj[s + i];
+                dy = deg[y];
+                in = rank_less(dy, y, dx, x);
+            }
+            const uint64_t mask = __ballot(in);
+            const int32_t p = ny + lanes_below(mask);
+            const int32_t inc = wave_incl_scan(in ? dy : 0);
+            if (in) {
+                base[p] = off[y];
+                pre[p + 1] = carry + inc;
+            }
+            carry += __shfl(inc, 63, 64);
+            ny += __popcll(mask);
+        }
+        if (lane == 0) pre[0] = 0;
+        wave_sync();
+        const int32_t W = carry;
+        for (int32_t qb = 0; qb < W; qb += kWave) {
+            const int32_t q = qb + lane;
+            if (q < W) {
+                const int32_t j = last_le_i32(pre, ny + 1, q);
+                const int32_t z = adj[base[j] + (q - pre[j])];
+                if (rank_less(deg[z], z, dx, x)) {
+                    uint32_t h = hash_slot(z);
+                    for (;;) {
+                        int32_t k = key[h];
+                        if (k == -1) {
+                            k = atomicCAS(&key[h], -1, z);
+                            if (k == -1) k = z;
+                        }
+                        if (k == z) {
+                            acc += atomicAdd(&cnt[h], 1u);
+                            break;
+                        }
+                        h = (h + 1) & (kHashSlots - 1);
+                    }
+                }
+            }
+        }
+        wave_sync();
+        // clear the slots this apex used
+        for (int i = lane; i < kHashSlots; i += kWave)
+            if (key[i] != -1) { key[i] = -1; cnt[i] = 0; }
+        wave_sync();
+    }
+    acc = wave_sum(acc);
+    if (lane == 0 && acc) atomic_add_u128(out, (u128)acc);
+}
+
+// Heavy apexes: block per (apex, z-part) task with dense LDS counters.
+__global__ void __launch_bounds__(kBlock) k_c4_heavy(const int32_t *__restrict__ off,
+                                                     const int32_t *__restrict__ adj,
+                                                     const int32_t *__restrict__ deg,
+                                                     const int32_t *__restrict__ list,
+                                                     const int32_t *__restrict__ count_p,
+                                                     int32_t nparts, uint32_t *cursor,
+                                                     unsigned long long *out) {
+    __shared__ uint32_t cnt[kPartZ];
+    __shared__ int32_t s_pre[kYChunk + 1];
+    __shared__ int32_t s_start[kYChunk];
+    __shared__ int32_t s_sum[kWPB];
+    __shared__ uint32_t s_task;
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    const uint64_t ntasks = (uint64_t)(*count_p) * (uint64_t)nparts;
+    uint64_t acc = 0;
+    for (int i = tid; i < kPartZ; i += kBlock) cnt[i] = 0;
+    for (;;) {
+        if (tid == 0) s_task = atomicAdd(cursor, 1u);
+        __syncthreads();
+        const uint64_t t = s_task;
+        __syncthreads();
+        if (t >= ntasks) break;
+        const int32_t x = list[t / nparts];
+        const int32_t part = (int32_t)(t % nparts);
+        const int32_t z0 = part * kPartZ, z1 = z0 + kPartZ;
+        const int32_t s = off[x], dx = off[x + 1] - s;
+        for (int32_t c0 = 0; c0 < dx; c0 += kYChunk) {
+            const int32_t i = c0 + tid;
+            int32_t len = 0, start = 0;
+            if (i < dx) {
+                const int32_t y = adj[s + i], dy = deg[y];
+                if (rank_less(dy, y, dx, x)) {
+                    const int32_t *ny = adj + off[y];
+                    const int32_t lo = lower_bound_i32(ny, dy, z0);
+                    const int32_t hi = lo + lower_bound_i32(ny + lo, dy - lo, z1);
+                    start = off[y] + lo;
+                    len = hi - lo;
+                }
+            }
+            const int32_t inc = wave_incl_scan(len);
+            if (lane == 63) s_sum[wid] = inc;
+            __syncthreads();
+            int32_t before = 0, total = 0;
+            for (int q = 0; q < kWPB; q++) {
+                if (q < wid) before += s_sum[q];
+                total += s_sum[q];
+            }
+            s_pre[tid + 1] = before + inc;
+            s_start[tid] = start;
+            if (tid == 0) s_pre[0] = 0;
+            __syncthreads();
+            for (int32_t q = tid; q < total; q += kBlock) {
+                const int32_t j = last_le_i32(s_pre, kYChunk + 1, q);
+                const int32_t z = adj[s_start[j] + (q - s_pre[j])];
+                if (rank_less(deg[z], z, dx, x)) acc += atomicAdd(&cnt[z - z0], 1u);
+            }
+            __syncthreads();
+        }
+        for (int i = tid; i < kPartZ; i += kBlock) cnt[i] = 0;
+        __syncthreads();
+    }
+    acc = wave_sum(acc);
+    if (lane == 0 && acc) atomic_add_u128(out, (u128)acc);
+}
+
+// ------------------------------------------------------------- combine ---
+
+struct Sums {
+    unsigned long long tri;        // T (triangles)
+    unsigned long long k4;         // 4-cliques
+    unsigned long long lc[8];      // four 128-bit local-count sums
+    unsigned long long wedge[2];   // sum_v C(d_v, 2)
+    unsigned long long c4[2];      // N_C4
+};
+
+__device__ __forceinline__ u128 get128(const unsigned long long *p) {
+    return ((u128)p[1] << 64) | p[0];
+}
+
+__global__ void k_combine(const Sums *S, int32_t k, unsigned long long *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const u128 lim = (u128)1 << 64;
+    unsigned long long bad = 0;
+    if (k == 3) {
+        const u128 w = get128(S->wedge), t3 = (u128)3 * S->tri;
+        if (w < t3) bad |= 1;
+        const u128 wo = w - t3;
+        if (wo >= lim) bad |= 2;
+        out[0] = (unsigned long long)wo;
+        out[1] = S->tri;
+        out[2] = bad;
+        return;
+    }
+    const u128 k4 = S->k4;
+    const u128 s1 = get128(S->lc + 0), s2 = get128(S->lc + 2), s3 = get128(S->lc + 4),
+               s4 = get128(S->lc + 6), nc4 = get128(S->c4);
+    u128 dia = 0, paw = 0, c4 = 0, p4 = 0, claw = 0;
+    if (s1 < 6 * k4) bad |= 1; else dia = s1 - 6 * k4;
+    if (s2 < 4 * dia || ((s2 - 4 * dia) & 1)) bad |= 2; else paw = (s2 - 4 * dia) / 2;
+    if (nc4 < dia + 3 * k4) bad |= 4; else c4 = nc4 - dia - 3 * k4;
+    if (s3 < 4 * c4) bad |= 8; else p4 = s3 - 4 * c4;
+    if (s4 < paw || (s4 - paw) % 3) bad |= 16; else claw = (s4 - paw) / 3;
+    const u128 r[6] = {claw, p4, c4, paw, dia, k4};
+    for (int i = 0; i < 6; i++) {
+        if (r[i] >= lim) bad |= 32;
+        out[i] = (unsigned long long)r[i];
+    }
+    out[6] = bad;
+}
+
+struct MotifWs {
+    Sums *sums;
+    uint32_t *te;
+    int32_t *deg, *cls, *flag, *pos, *light, *heavy;
+    int64_t *scan_tmp;
+    uint32_t *ctl;     // [0] heavy cursor, [1] light count, [2] heavy count
+    void *shared;      // clique workspace (k = 3 or 4), reused in sequence
+    uint64_t shared_bytes, bytes;
+};
+
+MotifWs motif_layout(const gpm_graph *g, int32_t k, void *base) {
+    MotifWs W{};
+    Carve c(base, ~0ull);
+    const uint64_t n1 = (uint64_t)g->n + 1;
+    W.sums = c.take<Sums>(1);
+    W.ctl = c.take<uint32_t>(16);
+    W.deg = c.take<int32_t>(n1);
+    if (k == 4) {
+        W.te = c.take<uint32_t>((uint64_t)std::max<int64_t>(g->m, 1));
+        W.cls = c.take<int32_t>(n1);
+        W.flag = c.take<int32_t>(n1);
+        W.pos = c.take<int32_t>(n1);
+        W.light = c.take<int32_t>(n1);
+        W.heavy = c.take<int32_t>(n1);
+        W.scan_tmp = c.take<int64_t>(scan_tmp_words(n1));
+    }
+    uint64_t b3 = 0, b4 = 0;
+    clique_workspace_bytes(g, 3, false, &b3);
+    if (k == 4) clique_workspace_bytes(g, 4, false, &b4);
+    W.shared_bytes = std::max(b3, b4);
+    W.shared = c.take<char>(W.shared_bytes);
+    W.bytes = c.used;
+    return W;
+}
+
+unsigned grid_for(int64_t items, int per_block, int cap_per_cu) {
+    int64_t b = (items + per_block - 1) / per_block;
+    int64_t cap = (int64_t)cu_count() * cap_per_cu;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+}  // namespace
+
+gpm_status motif_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes) {
+    if (k == 4 && g->max_out_degree > 1024)
+        return fail(GPM_UNSUPPORTED, "4-motif counting needs every out-degree <= 1024");
+    *bytes = motif_layout(g, k, nullptr).bytes;
+    return GPM_OK;
+}
+
+// Counts N_C4 into S->c4 (zeroed by the caller).
+static gpm_status c4_count(const gpm_graph *g, MotifWs &W, hipStream_t st) {
+    const int32_t n = g->n;
+    hipLaunchKernelGGL(k_c4_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st, g->off,
+                       g->adj, W.deg, n, W.cls);
+    GPM_LAUNCH_CHECK("k_c4_work");
+    int32_t *cnt_light = (int32_t *)(W.ctl + 1), *cnt_heavy = (int32_t *)(W.ctl + 2);
+    for (int cls = C4_LIGHT; cls <= C4_HEAVY; cls++) {
+        int32_t *list = cls == C4_LIGHT ? W.light : W.heavy;
+        hipLaunchKernelGGL(k_flag_eq, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.cls, n, cls,
+                           W.flag);
+        GPM_HIP(exclusive_scan_i32(W.flag, W.pos, (uint64_t)n, W.scan_tmp, st));
+        hipLaunchKernelGGL(k_compact_eq, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.cls,
+                           W.pos, n, cls, list);
+        GPM_HIP(hipMemcpyAsync(cls == C4_LIGHT ? cnt_light : cnt_heavy, W.pos + n, 4,
+                               hipMemcpyDeviceToDevice, st));
+    }
+    GPM_LAUNCH_CHECK("c4 classes");
+    const int32_t nparts = (n + kPartZ - 1) / kPartZ;
+    hipLaunchKernelGGL(k_c4_heavy, dim3((unsigned)persistent_blocks(kWPB, 4)), dim3(kBlock), 0, st,
+                       g->off, g->adj, W.deg, W.heavy, cnt_heavy, nparts, W.ctl + 0,
+                       W.sums->c4);
+    GPM_LAUNCH_CHECK("k_c4_heavy");
+    hipLaunchKernelGGL(k_c4_light, dim3((unsigned)persistent_blocks(kWPB, 4)), dim3(kBlock), 0, st,
+                       g->off, g->adj, W.deg, W.light, cnt_light, W.sums->c4);
+    GPM_LAUNCH_CHECK("k_c4_light");
+    return GPM_OK;
+}
+
+gpm_status motif_run(const gpm_graph *g, int32_t k, void *ws, uint64_t ws_bytes,
+                     unsigned long long *d_counts, hipStream_t st) {
+    if (k == 4 && g->max_out_degree > 1024)
+        return fail(GPM_UNSUPPORTED, "4-motif counting needs every out-degree <= 1024");
+    MotifWs W = motif_layout(g, k, ws);
+    if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
+    const int32_t n = g->n;
+    GPM_HIP(fill_u32(W.sums, 0, sizeof(Sums) / 4, st));
+    GPM_HIP(fill_u32(W.ctl, 0, 16, st));
+    hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, g->off, n, W.deg);
+    GPM_LAUNCH_CHECK("k_degrees");
+    hipLaunchKernelGGL(k_wedge_sum, dim3(grid_for(n, kBlock, 8)), dim3(kBlock), 0, st, W.deg, n,
+                       W.sums->wedge);
+    GPM_LAUNCH_CHECK("k_wedge_sum");
+    gpm_status rc;
+    if (k == 3) {
+        rc = clique_run(g, 3, false, W.shared, W.shared_bytes, &W.sums->tri, nullptr, 0, nullptr,
+                        st);
+        if (rc) return rc;
+    } else {
+        if (g->m > 0) GPM_HIP(fill_u32(W.te, 0, (uint64_t)g->m, st));
+        rc = triangle_arc_counts(g, W.shared, W.shared_bytes, W.te, &W.sums->tri, st);
+        if (rc) return rc;
+        if (g->m > 0) {
+            hipLaunchKernelGGL(k_lc_sums, dim3(grid_for(g->m, kBlock, 8)), dim3(kBlock), 0, st,
+                               g->dag_src, g->dag_adj, W.te, W.deg, g->m, W.sums->lc);
+            GPM_LAUNCH_CHECK("k_lc_sums");
+        }
+        rc = clique_run(g, 4, false, W.shared, W.shared_bytes, &W.sums->k4, nullptr, 0, nullptr,
+                        st);
+        if (rc) return rc;
+        rc = c4_count(g, W, st);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_combine, dim3(1), dim3(64), 0, st, W.sums, k, d_counts);
+    GPM_LAUNCH_CHECK("k_combine");
+    return GPM_OK;
+}
+
+}  // namespace gpm

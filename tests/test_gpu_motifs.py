@@ -1,0 +1,71 @@
+"""Induced 3- and 4-motif counts (local counting) against the CPU oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from oracle import canonical_csr
+from gpu_util import build
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "rmat_counts.json")
+
+
+@pytest.fixture(scope="module")
+def gpm():
+    import paper_2011_03135_amd as m
+    m.load()
+    return m
+
+
+def cases():
+    return [
+        graphgen.star_graph(30),
+        graphgen.cycle_graph(4),
+        graphgen.cycle_graph(9),
+        graphgen.complete_bipartite(5, 8),
+        graphgen.complete_graph(9),
+        graphgen.path_graph(6),
+        graphgen.erdos_renyi(120, 0.08, 21),
+        graphgen.erdos_renyi(400, 0.03, 22),
+        graphgen.rmat(11, seed=31),
+        graphgen.rmat(14, seed=14),
+        graphgen.star_graph(2000),                      # one heavy apex
+        graphgen.complete_bipartite(40, 300),            # heavy apexes, many 4-cycles
+        graphgen.EdgeList(3, np.zeros(0, np.int32), np.zeros(0, np.int32), "empty"),
+    ]
+
+
+@pytest.mark.parametrize("case", range(13))
+def test_motif_counts(gpm, case):
+    e = cases()[case]
+    print(f"motif case {case} {e.name}", flush=True)
+    g = build(gpm, e)
+    off, adj = canonical_csr(e.n, e.u, e.v)
+    assert gpm.motif_count(g, 3) == oracle.motif3(off, adj), e.name
+    assert gpm.motif_count(g, 4) == oracle.motif4(off, adj), e.name
+
+
+def test_motif_disjoint_union_additive(gpm):
+    a = graphgen.erdos_renyi(90, 0.1, 3)
+    b = graphgen.rmat(10, seed=4)
+    ga, gb = build(gpm, a), build(gpm, b)
+    gu = build(gpm, graphgen.disjoint_union([a, b]))
+    for k in (3, 4):
+        x, y, z = gpm.motif_count(ga, k), gpm.motif_count(gb, k), gpm.motif_count(gu, k)
+        assert z == [p + q for p, q in zip(x, y)]
+
+
+def test_rmat18_motifs_golden(gpm):
+    if not os.path.exists(GOLDEN):
+        pytest.skip("golden counts not generated")
+    with open(GOLDEN) as f:
+        gold = json.load(f).get("rmat18", {})
+    if "motif4" not in gold:
+        pytest.skip("rmat18 motif golden counts not generated")
+    g = build(gpm, graphgen.rmat(18, seed=18))
+    assert gpm.motif_count(g, 3) == gold["motif3"]
+    assert gpm.motif_count(g, 4) == gold["motif4"]
