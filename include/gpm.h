@@ -204,6 +204,17 @@ gpm_status gpm_batch_motif_count(const gpm_graph *g, const int32_t *d_voff, int3
                                  int32_t k, void *d_ws, uint64_t ws_bytes,
                                  uint64_t *d_counts, void *stream);
 
+/* ----------------------------------------------------------- timing --- */
+
+/* Kernel timing for measurement (off by default).  While on, the library
+ * brackets each of its main kernels with HIP events recorded on the launch
+ * stream.  Switch it off for production and for graph capture. */
+gpm_status gpm_timing_enable(int32_t on);
+/* Waits for the recorded events, writes up to cap (name, milliseconds)
+ * pairs in launch order (names stay valid until the next call), clears the
+ * record, and returns the number of spans recorded (may exceed cap). */
+int32_t gpm_timing_read(const char **names, float *ms, int32_t cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -53,6 +53,8 @@ def _load():
         lib.orc_list_diamonds.argtypes = [i32, p, p, i32, p, u64, p, p, p]
         lib.orc_list_c4.argtypes = [i32, p, p, i32, p, u64, p, p, p]
         lib.orc_wedges.argtypes = [i32, p, p]
+        lib.orc_clique_count_sampled.argtypes = [i32, p, p, i32, i32, i32, p]
+        lib.orc_clique_count_sampled.restype = ctypes.c_int
         for f in (lib.orc_clique_count, lib.orc_clique_list, lib.orc_edge_triangles,
                   lib.orc_motif4_noninduced, lib.orc_list_diamonds, lib.orc_list_c4,
                   lib.orc_wedges):
@@ -86,6 +88,16 @@ def clique_count(off, adj, k, threads=0):
     out = np.zeros(2, dtype=np.uint64)
     _check(_load().orc_clique_count(n, _ptr(off), _ptr(adj), int(k), int(threads), _ptr(out)),
            "clique_count")
+    return _u128(out[0], out[1])
+
+
+def clique_count_sampled(off, adj, k, stride, threads=0):
+    """k-cliques whose first vertex (core order) has position % stride == 0;
+    a bounded share of clique_count's work, used only for CPU timing."""
+    off, adj, n = _prep(off, adj)
+    out = np.zeros(2, dtype=np.uint64)
+    _check(_load().orc_clique_count_sampled(n, _ptr(off), _ptr(adj), int(k), int(threads),
+                                            int(stride), _ptr(out)), "clique_count_sampled")
     return _u128(out[0], out[1])
 
 

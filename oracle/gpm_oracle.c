@@ -224,6 +224,41 @@ int orc_clique_count(int32_t n, const int64_t *off, const int32_t *adj, int32_t 
     return ORC_OK;
 }
 
+/* Timing sample of orc_clique_count: only the cliques whose first vertex in
+ * the core order has a position divisible by `stride` (a bounded, seeded
+ * share of the roots).  Used to time the oracle on part of a workload. */
+int orc_clique_count_sampled(int32_t n, const int64_t *off, const int32_t *adj, int32_t k,
+                             int32_t threads, int32_t stride, uint64_t *out)
+{
+    if (n < 0 || k < 3 || stride < 1 || !out) return ORC_BAD_ARG;
+    int32_t *pos = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!pos) return ORC_NO_MEMORY;
+    int rc = core_positions(n, off, adj, pos);
+    if (rc) { free(pos); return rc; }
+    int64_t *o; int32_t *a; int32_t mo;
+    rc = core_dag(n, off, adj, &o, &a, &mo);
+    if (rc) { free(pos); return rc; }
+    u128 total = 0;
+    int failed = 0;
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel reduction(+ : total) reduction(| : failed)
+    {
+        int32_t *scratch = malloc(sizeof(int32_t) * ((size_t)mo * (size_t)k + 1));
+        if (!scratch) failed = 1;
+#pragma omp for schedule(dynamic, 64)
+        for (int32_t v = 0; v < n; v++) {
+            if (!scratch || pos[v] % stride != 0) continue;
+            int64_t d = o[v + 1] - o[v];
+            if (d >= k - 1) total += clique_extend(o, a, a + o[v], d, k - 1, scratch);
+        }
+        free(scratch);
+    }
+    free(o); free(a); free(pos);
+    if (failed) return ORC_NO_MEMORY;
+    put128(out, total);
+    return ORC_OK;
+}
+
 /* Lists every k-clique (k >= 3) as its ascending vertex tuple.  The first
  * `cap` found are written to buf (k ints each, in an unspecified order);
  * total and the checksum cover all of them. */

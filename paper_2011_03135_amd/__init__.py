@@ -23,6 +23,9 @@ from .binding import (  # noqa: F401
     load,
     motif_count,
     pattern,
+    timing_enable,
+    timing_read,
+    workspace_bytes,
     MOTIF3_NAMES,
     MOTIF4_NAMES,
     VERTEX_INDUCED,

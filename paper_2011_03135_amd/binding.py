@@ -75,6 +75,8 @@ def load():
         "gpm_motif_count": ([P, i32, P, u64, P, P], i32),
         "gpm_batch_workspace_bytes": ([i32, i32, P], i32),
         "gpm_batch_motif_count": ([P, P, i32, i32, P, u64, P, P], i32),
+        "gpm_timing_enable": ([i32], i32),
+        "gpm_timing_read": ([P, P, i32], i32),
     }
     for name, (args, res) in sigs.items():
         f = getattr(lib, name)
@@ -159,8 +161,9 @@ class Graph:
         return gb.value, sb.value
 
     @classmethod
-    def build(cls, n, u, v, stream=None, scratch=None):
-        """gpm_graph_build from int32 CUDA tensors u, v (a raw edge stream)."""
+    def build(cls, n, u, v, stream=None, scratch=None, storage=None):
+        """gpm_graph_build from int32 CUDA tensors u, v (a raw edge stream).
+        storage / scratch: optional preallocated uint8 device buffers."""
         if u.dtype != torch.int32 or v.dtype != torch.int32 or not u.is_cuda or not v.is_cuda:
             raise TypeError("u and v must be int32 CUDA tensors")
         if u.shape != v.shape or u.dim() != 1:
@@ -168,7 +171,8 @@ class Graph:
         u = u.contiguous()
         v = v.contiguous()
         gb, sb = cls.build_bytes(n, u.shape[0])
-        storage = _buffer(gb, u.device)
+        if storage is None or storage.numel() < gb:
+            storage = _buffer(gb, u.device)
         if scratch is None or scratch.numel() < sb:
             scratch = _buffer(sb, u.device)
         h = ctypes.c_void_p()
@@ -201,6 +205,19 @@ class Graph:
                 self._h = None
         except Exception:
             pass
+
+
+def timing_enable(on=True):
+    """gpm_timing_enable: bracket the library's main kernels with HIP events."""
+    _check(load().gpm_timing_enable(1 if on else 0))
+
+
+def timing_read(cap=4096):
+    """gpm_timing_read -> list of (kernel name, milliseconds) in launch order."""
+    names = (ctypes.c_char_p * cap)()
+    ms = (ctypes.c_float * cap)()
+    k = load().gpm_timing_read(names, ms, cap)
+    return [(names[i].decode(), float(ms[i])) for i in range(min(k, cap))]
 
 
 def workspace_bytes(g, p):

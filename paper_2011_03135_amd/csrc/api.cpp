@@ -83,6 +83,15 @@ const char *gpm_last_error(void) { return gpm::last_error().c_str(); }
 
 const char *gpm_version(void) { return "gpmhip 0.1 gfx950"; }
 
+gpm_status gpm_timing_enable(int32_t on) {
+    gpm::timing_set(on != 0);
+    return GPM_OK;
+}
+
+int32_t gpm_timing_read(const char **names, float *ms, int32_t cap) {
+    return gpm::timing_read(names, ms, cap < 0 ? 0 : cap);
+}
+
 gpm_status gpm_pattern_from_edges(int32_t k, int32_t n_edges, const int32_t *uv, uint32_t flags,
                                   gpm_pattern *out) {
     if (!out) return fail(GPM_INVALID_ARGUMENT, "out is NULL");

@@ -343,6 +343,9 @@ unsigned flat_grid(int64_t items) {
 
 }  // namespace
 
+static gpm_status enqueue_build(int32_t n, const int32_t *d_u, const int32_t *d_v, int64_t E,
+                                const BuildLayout &L, hipStream_t st);
+
 gpm_status graph_build_bytes(int32_t n, int64_t E, uint64_t *gb, uint64_t *sb) {
     if (n < 1 || n > INT32_MAX - 1) return fail(GPM_INVALID_ARGUMENT, "n must be in [1, 2^31-2]");
     if (E < 0 || 2 * E >= (int64_t)INT32_MAX)
@@ -367,7 +370,35 @@ gpm_status graph_build(int32_t n, const int32_t *d_u, const int32_t *d_v, int64_
     if (gbytes < need_g || sbytes < need_s)
         return fail(GPM_OUT_OF_MEMORY, "graph or scratch buffer smaller than gpm_graph_build_bytes");
     BuildLayout L = layout(n, E, gmem, smem);
+    gpm_status rc2 = enqueue_build(n, d_u, d_v, E, L, st);
+    if (rc2 != GPM_OK) return rc2;
 
+    int64_t meta[8] = {0};
+    GPM_HIP(hipMemcpyAsync(meta, L.meta, sizeof(int64_t) * 6, hipMemcpyDeviceToHost, st));
+    GPM_HIP(hipStreamSynchronize(st));
+    if (meta[4] != 0) return fail(GPM_NOT_CANONICAL, "an input vertex id is outside [0, n)");
+    if (meta[0] % 2 != 0 || meta[1] * 2 != meta[0])
+        return fail(GPM_DEVICE_ERROR, "graph build produced inconsistent sizes");
+
+    gpm_graph *g = new (std::nothrow) gpm_graph;
+    if (!g) return fail(GPM_OUT_OF_MEMORY, "host allocation of the graph handle failed");
+    g->n = n;
+    g->m = meta[1];
+    g->max_degree = (int32_t)meta[2];
+    g->max_out_degree = (int32_t)meta[3];
+    g->off = L.off;
+    g->adj = L.adj;
+    g->dag_off = L.dag_off;
+    g->dag_adj = L.dag_adj;
+    g->dag_src = L.dag_src;
+    *out = g;
+    return GPM_OK;
+}
+
+// All build kernels, in stream order (a1 then a2).
+static gpm_status enqueue_build(int32_t n, const int32_t *d_u, const int32_t *d_v, int64_t E,
+                         const BuildLayout &L, hipStream_t st) {
+    Span whole("graph_build", st);
     GPM_HIP(fill_u32(L.cnt, 0, (uint64_t)n + 1, st));
     GPM_HIP(fill_u32(L.flags, 0, F_WORDS, st));
     if (E > 0) {
@@ -401,26 +432,6 @@ gpm_status graph_build(int32_t n, const int32_t *d_u, const int32_t *d_v, int64_
     GPM_LAUNCH_CHECK("k_orient_fill");
     hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, st, L.off, L.dag_off, n, L.flags, L.meta);
     GPM_LAUNCH_CHECK("k_meta");
-
-    int64_t meta[8] = {0};
-    GPM_HIP(hipMemcpyAsync(meta, L.meta, sizeof(int64_t) * 6, hipMemcpyDeviceToHost, st));
-    GPM_HIP(hipStreamSynchronize(st));
-    if (meta[4] != 0) return fail(GPM_NOT_CANONICAL, "an input vertex id is outside [0, n)");
-    if (meta[0] % 2 != 0 || meta[1] * 2 != meta[0])
-        return fail(GPM_DEVICE_ERROR, "graph build produced inconsistent sizes");
-
-    gpm_graph *g = new (std::nothrow) gpm_graph;
-    if (!g) return fail(GPM_OUT_OF_MEMORY, "host allocation of the graph handle failed");
-    g->n = n;
-    g->m = meta[1];
-    g->max_degree = (int32_t)meta[2];
-    g->max_out_degree = (int32_t)meta[3];
-    g->off = L.off;
-    g->adj = L.adj;
-    g->dag_off = L.dag_off;
-    g->dag_adj = L.dag_adj;
-    g->dag_src = L.dag_src;
-    *out = g;
     return GPM_OK;
 }
 

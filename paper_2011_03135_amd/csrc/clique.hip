@@ -19,9 +19,8 @@
 //   k_clique_wave   k = 4, 5, roots with out-degree <= 64: one wave builds
 //                   the local graph on N+(u) as 64-bit adjacency rows in LDS
 //                   and counts cliques with AND + popcount.
-//   k_clique_block  k = 4, 5, roots with out-degree 65..1024: one workgroup,
-//                   rows of ceil(d/32) words in LDS (d <= 512) or in a
-//                   per-workgroup global slot.
+//   (local_graph.hip) k = 4, 5, roots with out-degree 65..1024: workgroup
+//                   local graphs in LDS.
 //   k_clique_generic  any k in [3, 8], any degree, counting or listing: one
 //                   wave per root, depth-first with candidate sets in a
 //                   per-wave global scratch, wave-cooperative intersections.
@@ -31,6 +30,11 @@
 #include <climits>
 
 namespace gpm {
+
+gpm_status lg_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes);
+gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, const int32_t *cnt_m,
+                      const int32_t *list_b, const int32_t *cnt_b, const int32_t *work, void *ws,
+                      uint64_t ws_bytes, unsigned long long *res, hipStream_t st);
 
 namespace {
 
@@ -297,105 +301,21 @@ __global__ void __launch_bounds__(kBlock) k_clique_wave(const int32_t *__restric
 }
 
 constexpr int kBlockMaxD = 1024;
-constexpr int kLdsRowsMaxD = 512;
-constexpr int kMaxW32 = kBlockMaxD / 32;
+constexpr int kMidMaxD = 256;
 
-template <int K, bool ROWS_LDS>
-__global__ void __launch_bounds__(kBlock) k_clique_block(const int32_t *__restrict__ dag_off,
-                                                         const int32_t *__restrict__ dag_adj,
-                                                         const int32_t *__restrict__ roots,
-                                                         const int32_t *__restrict__ nroots_p,
-                                                         uint32_t *cursor, uint32_t *grows,
-                                                         unsigned long long *result) {
-    constexpr int kRowsWords = ROWS_LDS ? kLdsRowsMaxD * (kLdsRowsMaxD / 32) : 1;
-    __shared__ uint32_t s_rows[kRowsWords];
-    __shared__ int32_t list[kBlockMaxD];
-    __shared__ int32_t pre[kBlockMaxD + 1];
-    __shared__ int32_t base[kBlockMaxD];
-    __shared__ int32_t s_sum[kWPB];
-    __shared__ uint32_t s_task;
-    uint32_t *rows = ROWS_LDS ? s_rows : grows + (int64_t)blockIdx.x * kBlockMaxD * kMaxW32;
-    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
-    const uint32_t nroots = (uint32_t)*nroots_p;
-    uint64_t acc = 0;
-    for (;;) {
-        if (tid == 0) s_task = atomicAdd(cursor, 1u);
-        __syncthreads();
-        const uint32_t r = s_task;
-        __syncthreads();
-        if (r >= nroots) break;
-        const int32_t u = roots[r];
-        const int32_t s = dag_off[u], d = dag_off[u + 1] - s;
-        const int32_t W32 = (d + 31) >> 5;
-        // list, base and the pair prefix; each thread owns 4 consecutive entries
-        int32_t dv[4];
-        int32_t mysum = 0;
-        for (int t = 0; t < 4; t++) {
-            int32_t i = tid * 4 + t;
-            dv[t] = 0;
-            if (i < d) {
-                int32_t v = dag_adj[s + i];
-                int32_t st = dag_off[v];
-                dv[t] = dag_off[v + 1] - st;
-                list[i] = v;
-                base[i] = st;
-            }
-            mysum += dv[t];
-        }
-        int32_t inc = wave_incl_scan(mysum);
-        if (lane == 63) s_sum[wid] = inc;
-        for (int32_t i = tid; i < d * W32; i += kBlock) rows[i] = 0u;
-        __syncthreads();
-        int32_t before = 0;
-        for (int q = 0; q < wid; q++) before += s_sum[q];
-        int32_t run = before + inc - mysum;
-        for (int t = 0; t < 4; t++) {
-            int32_t i = tid * 4 + t;
-            run += dv[t];
-            if (i < d) pre[i + 1] = run;
-        }
-        if (tid == 0) pre[0] = 0;
-        __syncthreads();
-        const int32_t W = pre[d];
-        for (int32_t q = tid; q < W; q += kBlock) {
-            const int32_t j = last_le_i32(pre, d + 1, q);
-            const int32_t w = dag_adj[base[j] + (q - pre[j])];
-            const int32_t idx = lower_bound_i32(list, d, w);
-            if (idx < d && list[idx] == w) atomicOr(&rows[j * W32 + (idx >> 5)], 1u << (idx & 31));
-        }
-        __syncthreads();
-        for (int32_t i = tid; i < d; i += kBlock) {
-            const uint32_t *ri = rows + i * W32;
-            for (int32_t wj = 0; wj < W32; wj++) {
-                uint32_t mj = ri[wj];
-                while (mj) {
-                    const int32_t j = wj * 32 + __builtin_ctz(mj);
-                    mj &= mj - 1;
-                    const uint32_t *rj = rows + j * W32;
-                    if (K == 4) {
-                        for (int32_t w = 0; w < W32; w++) acc += __popc(ri[w] & rj[w]);
-                    } else {
-                        uint32_t x[kMaxW32];
+// Position of the r-th set bit (0-based) of x; x must have more than r bits.
+__device__ __forceinline__ int select_bit64(uint64_t x, int r) {
+    int pos = 0;
 #pragma unroll
-                        for (int w = 0; w < kMaxW32; w++) x[w] = w < W32 ? (ri[w] & rj[w]) : 0u;
-#pragma unroll
-                        for (int wl = 0; wl < kMaxW32; wl++) {
-                            uint32_t ml = x[wl];
-                            while (ml) {
-                                const int32_t l = wl * 32 + __builtin_ctz(ml);
-                                ml &= ml - 1;
-                                const uint32_t *rl = rows + l * W32;
-                                for (int32_t w = 0; w < W32; w++) acc += __popc(x[w] & rl[w]);
-                            }
-                        }
-                    }
-                }
-            }
+    for (int s = 32; s > 0; s >>= 1) {
+        const int low = __popcll(x & ((1ull << s) - 1));
+        if (r >= low) {
+            r -= low;
+            x >>= s;
+            pos += s;
         }
-        __syncthreads();
     }
-    acc = wave_sum(acc);
-    if (lane == 0 && acc) atomicAdd(result, (unsigned long long)acc);
+    return pos;
 }
 
 // ------------------------------------------------- generic DFS (k <= 8) ---
@@ -559,9 +479,10 @@ struct CliqueWs {
     int64_t *wpre_s, *wpre_m;
     int32_t *first_s, *first_m;
     int64_t *scan_tmp;
-    uint32_t *grows;              // per-workgroup local-graph rows (global)
+    void *lg;                     // local-graph workspace (k = 4, 5)
+    uint64_t lg_bytes;
     int32_t *gen_scratch;
-    int gen_waves, grows_blocks;
+    int gen_waves;
     uint64_t bytes;
 };
 
@@ -594,8 +515,8 @@ CliqueWs clique_layout(const gpm_graph *g, int32_t k, bool list, void *base) {
         W.first_m = c.take<int32_t>((uint64_t)chunk_bound(g));
     }
     if (!generic && k >= 4) {
-        W.grows_blocks = persistent_blocks(kWPB, 2);
-        W.grows = c.take<uint32_t>((uint64_t)W.grows_blocks * kBlockMaxD * kMaxW32);
+        lg_workspace_bytes(g, k, &W.lg_bytes);
+        W.lg = c.take<char>(W.lg_bytes);
     }
     if (generic) {
         W.gen_waves = persistent_blocks(kWPB, 8) * kWPB;
@@ -631,6 +552,22 @@ hipError_t build_class(const gpm_graph *g, CliqueWs &W, int32_t want, int32_t *l
     if (e != hipSuccess || !wpre) return e;
     // work prefix over the class's roots; the count is pos[n] (device)
     return exclusive_scan_i64(W.lwork, wpre, (uint64_t)n, W.scan_tmp, st);
+}
+
+template <int K>
+gpm_status launch_local(const gpm_graph *g, CliqueWs &W, const int32_t *cnt_s,
+                        const int32_t *cnt_m, const int32_t *cnt_b, unsigned long long *res,
+                        hipStream_t st) {
+    gpm_status rc = lg_cliques(g, K, W.list_m, cnt_m, W.list_b, cnt_b, W.work, W.lg, W.lg_bytes,
+                               res, st);
+    if (rc) return rc;
+    {
+        Span sp(K == 4 ? "k_clique_wave<4>" : "k_clique_wave<5>", st);
+        hipLaunchKernelGGL(k_clique_wave<K>, dim3((unsigned)persistent_blocks(kWPB, 8)),
+                           dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_s, cnt_s, res);
+    }
+    GPM_LAUNCH_CHECK("k_clique_wave");
+    return GPM_OK;
 }
 
 }  // namespace
@@ -703,7 +640,7 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
         }
     } else {
         const int32_t small_max = k == 3 ? kSmallMax : 64;
-        const int32_t mid_max = k == 3 ? kTcMax : kLdsRowsMaxD;
+        const int32_t mid_max = k == 3 ? kTcMax : kMidMaxD;
         hipLaunchKernelGGL(k_root_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st,
                            g->dag_off, g->dag_adj, n, k - 1, small_max, mid_max, kTcMax, W.work,
                            W.cls);
@@ -718,13 +655,20 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
                                W.pos + n, kTcTau, W.first_m, W.ctl + 4);
             GPM_LAUNCH_CHECK("k_chunk_map");
             unsigned blocks = (unsigned)persistent_blocks(kWPB, 8);
-            hipLaunchKernelGGL((k_tc_flat<kTcMax, false>), dim3((unsigned)persistent_blocks(kWPB, 3)),
-                               dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_m, W.wpre_m,
-                               W.first_m, W.ctl + 4, W.ctl + 1, kTcTau, res, (uint32_t *)nullptr);
+            {
+                Span sp("k_tc_flat<1024>", st);
+                hipLaunchKernelGGL((k_tc_flat<kTcMax, false>),
+                                   dim3((unsigned)persistent_blocks(kWPB, 3)), dim3(kBlock), 0, st,
+                                   g->dag_off, g->dag_adj, W.list_m, W.wpre_m, W.first_m,
+                                   W.ctl + 4, W.ctl + 1, kTcTau, res, (uint32_t *)nullptr);
+            }
             GPM_LAUNCH_CHECK("k_tc_flat<1024>");
-            hipLaunchKernelGGL((k_tc_flat<kSmallMax, false>), dim3(blocks), dim3(kBlock), 0, st,
-                               g->dag_off, g->dag_adj, W.list_s, W.wpre_s, W.first_s, W.ctl + 2,
-                               W.ctl + 0, kTcTau, res, (uint32_t *)nullptr);
+            {
+                Span sp("k_tc_flat<256>", st);
+                hipLaunchKernelGGL((k_tc_flat<kSmallMax, false>), dim3(blocks), dim3(kBlock), 0, st,
+                                   g->dag_off, g->dag_adj, W.list_s, W.wpre_s, W.first_s,
+                                   W.ctl + 2, W.ctl + 0, kTcTau, res, (uint32_t *)nullptr);
+            }
             GPM_LAUNCH_CHECK("k_tc_flat<256>");
         } else {
             // three classes; each count lives in its own pos snapshot
@@ -736,28 +680,9 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
             GPM_HIP(hipMemcpyAsync(cnt_m, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
             GPM_HIP(build_class(g, W, RC_SMALL, W.list_s, nullptr, st));
             GPM_HIP(hipMemcpyAsync(cnt_s, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
-            if (k == 4) {
-                hipLaunchKernelGGL((k_clique_block<4, false>), dim3(W.grows_blocks), dim3(kBlock), 0,
-                                   st, g->dag_off, g->dag_adj, W.list_b, cnt_b, W.ctl + 0, W.grows,
-                                   res);
-                hipLaunchKernelGGL((k_clique_block<4, true>), dim3((unsigned)persistent_blocks(kWPB, 3)),
-                                   dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_m, cnt_m,
-                                   W.ctl + 1, (uint32_t *)nullptr, res);
-                hipLaunchKernelGGL(k_clique_wave<4>, dim3((unsigned)persistent_blocks(kWPB, 8)),
-                                   dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_s, cnt_s,
-                                   res);
-            } else {
-                hipLaunchKernelGGL((k_clique_block<5, false>), dim3(W.grows_blocks), dim3(kBlock), 0,
-                                   st, g->dag_off, g->dag_adj, W.list_b, cnt_b, W.ctl + 0, W.grows,
-                                   res);
-                hipLaunchKernelGGL((k_clique_block<5, true>), dim3((unsigned)persistent_blocks(kWPB, 3)),
-                                   dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_m, cnt_m,
-                                   W.ctl + 1, (uint32_t *)nullptr, res);
-                hipLaunchKernelGGL(k_clique_wave<5>, dim3((unsigned)persistent_blocks(kWPB, 8)),
-                                   dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_s, cnt_s,
-                                   res);
-            }
-            GPM_LAUNCH_CHECK("k_clique_*");
+            gpm_status rc = k == 4 ? launch_local<4>(g, W, cnt_s, cnt_m, cnt_b, res, st)
+                                   : launch_local<5>(g, W, cnt_s, cnt_m, cnt_b, res, st);
+            if (rc) return rc;
         }
     }
     if (!list) GPM_HIP(hipMemcpyAsync(d_count, res, 8, hipMemcpyDeviceToDevice, st));

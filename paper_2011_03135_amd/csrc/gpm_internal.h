@@ -72,6 +72,24 @@ hipError_t exclusive_scan_i32(const int32_t *in, int32_t *out, uint64_t n, int64
 hipError_t exclusive_scan_i64(const int32_t *in, int64_t *out, uint64_t n, int64_t *tmp,
                               hipStream_t s);
 
+// Optional kernel timing (off by default): when on, span_begin/span_end
+// bracket a launch with HIP events recorded on its stream.
+bool timing_on();
+void timing_set(bool on);
+int timing_read(const char **names, float *ms, int cap);
+void span_begin(const char *name, hipStream_t s);
+void span_end(hipStream_t s);
+struct Span {
+    hipStream_t s;
+    bool on;
+    Span(const char *name, hipStream_t st) : s(st), on(timing_on()) {
+        if (on) span_begin(name, s);
+    }
+    ~Span() {
+        if (on) span_end(s);
+    }
+};
+
 // Number of workgroups a persistent kernel launches: enough resident waves
 // to cover every CU several times.
 int persistent_blocks(int waves_per_block, int blocks_per_cu);

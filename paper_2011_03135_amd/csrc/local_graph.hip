@@ -1,0 +1,449 @@
+// Local-graph 4- and 5-clique counting for roots of out-degree 65..1024.
+//
+// For a root u of the degree-ordered DAG the local graph is the subgraph
+// induced on N+(u), itself oriented (Section 5, search on a local graph; the
+// local graph here is built once per root and kept as bit rows instead of
+// being shrunk in place).  Row i holds, as a bit set over local indices, the
+// out-neighbours of the i-th out-neighbour v_i that lie in N+(u).  Then
+//   4-cliques rooted at u = sum over local edges (i, j) of |row_i & row_j|,
+//   5-cliques rooted at u = sum over local edges (i, j), l in row_i & row_j
+//                           of |row_i & row_j & row_l|.
+// Rows are 64-bit words in LDS (at most 1024 x 16 words = 128 KiB of the
+// 160 KiB a gfx950 workgroup may use).
+//
+// 4-cliques: one workgroup per root builds the rows and counts (counting
+// costs about as much as building).
+// 5-cliques: counting can cost far more than building on hub roots, so one
+// kernel builds every root's rows once and stores them in HBM, and a second
+// kernel splits each root into slices of its local edges (e = s mod S, S
+// proportional to the root's local edge count times its row width); a slice
+// copies the rows back into LDS and runs a per-lane work loop (fetch an
+// edge, then step through its candidates one at a time) so skewed candidate
+// sets do not stall a wave.
+#include "gpm_internal.h"
+
+#include <algorithm>
+
+namespace gpm {
+
+namespace {
+
+constexpr int kMidMaxD = 256;
+constexpr int kBigMaxD = 1024;
+constexpr int kMidThreads = 256;
+constexpr int kBigThreads = 1024;
+constexpr uint64_t kSlice5 = 1 << 20;  // word-steps of counting work per slice
+constexpr int32_t kMaxSlices = 1024;
+
+__device__ __forceinline__ int lower_bound_i32(const int32_t *a, int n, int32_t x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int last_le_i32(const int32_t *a, int n, int32_t x) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Position of the r-th set bit (0-based) of x; x must have more than r bits.
+__device__ __forceinline__ int select_bit64(uint64_t x, int r) {
+    int pos = 0;
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) {
+        const int low = __popcll(x & ((1ull << s) - 1));
+        if (r >= low) {
+            r -= low;
+            x >>= s;
+            pos += s;
+        }
+    }
+    return pos;
+}
+
+template <int NT>
+struct Lds {
+    int32_t s_sum[NT / kWave];
+    uint32_t s_task, s_next;
+    uint64_t s_tri;
+};
+
+// Block-wide exclusive scan of PER values per thread (thread t owns entries
+// t*PER .. t*PER+PER-1); writes pre[i+1] for i < d and pre[0] = 0.
+template <int NT, int PER>
+__device__ void block_prefix(const int32_t (&val)[PER], int32_t d, int32_t *pre, int32_t *s_sum) {
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    int32_t mysum = 0;
+#pragma unroll
+    for (int q = 0; q < PER; q++) mysum += val[q];
+    const int32_t inc = wave_incl_scan(mysum);
+    if (lane == 63) s_sum[wid] = inc;
+    __syncthreads();
+    int32_t run = inc - mysum;
+    for (int q = 0; q < wid; q++) run += s_sum[q];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int32_t i = tid * PER + q;
+        run += val[q];
+        if (i < d) pre[i + 1] = run;
+    }
+    if (tid == 0) pre[0] = 0;
+    __syncthreads();
+}
+
+// Builds the local graph of root u (d out-neighbours, W words per row) in
+// LDS.  Uses list/base/pre as scratch; ends with a barrier.
+template <int DMAX, int NT>
+__device__ void build_rows(const int32_t *__restrict__ dag_off, const int32_t *__restrict__ dag_adj,
+                           int32_t u, int32_t d, int32_t W, uint64_t *rows, int32_t *list,
+                           int32_t *base, int32_t *pre, int32_t *s_sum) {
+    constexpr int PER = (DMAX + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    const int32_t s = dag_off[u];
+    int32_t dv[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int32_t i = tid * PER + q;
+        dv[q] = 0;
+        if (i < d) {
+            const int32_t v = dag_adj[s + i];
+            const int32_t st = dag_off[v];
+            dv[q] = dag_off[v + 1] - st;
+            list[i] = v;
+            base[i] = st;
+        }
+    }
+    for (int32_t i = tid; i < d * W; i += NT) rows[i] = 0ull;
+    block_prefix<NT, PER>(dv, d, pre, s_sum);
+    const int32_t npairs = pre[d];
+    for (int32_t q = tid; q < npairs; q += NT) {
+        const int32_t j = last_le_i32(pre, d + 1, q);
+        const int32_t w = dag_adj[base[j] + (q - pre[j])];
+        const int32_t idx = lower_bound_i32(list, d, w);
+        if (idx < d && list[idx] == w)
+            atomicOr((unsigned long long *)&rows[j * W + (idx >> 6)], 1ull << (idx & 63));
+    }
+    __syncthreads();
+}
+
+// pre[i] = number of local edges in rows 0..i-1; returns the total.
+template <int DMAX, int NT>
+__device__ int32_t row_prefix(const uint64_t *rows, int32_t d, int32_t W, int32_t *pre,
+                              int32_t *s_sum) {
+    constexpr int PER = (DMAX + NT - 1) / NT;
+    int32_t pc[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int32_t i = threadIdx.x * PER + q;
+        pc[q] = 0;
+        if (i < d)
+            for (int32_t w = 0; w < W; w++) pc[q] += __popcll(rows[i * W + w]);
+    }
+    block_prefix<NT, PER>(pc, d, pre, s_sum);
+    return pre[d];
+}
+
+// Local edge number e -> (row i, column j).
+__device__ __forceinline__ void edge_at(const uint64_t *rows, const int32_t *pre, int32_t d,
+                                        int32_t W, int32_t e, int32_t &i, int32_t &j) {
+    i = last_le_i32(pre, d + 1, e);
+    int32_t rr = e - pre[i];
+    const uint64_t *ri = rows + i * W;
+    int32_t wj = 0;
+    for (;; wj++) {
+        const int pc = __popcll(ri[wj]);
+        if (rr < pc) break;
+        rr -= pc;
+    }
+    j = wj * 64 + select_bit64(ri[wj], rr);
+}
+
+// 4-cliques: workgroup per root (atomic cursor over the class list).
+template <int DMAX, int NT>
+__global__ void __launch_bounds__(NT) k_lg4(const int32_t *__restrict__ dag_off,
+                                            const int32_t *__restrict__ dag_adj,
+                                            const int32_t *__restrict__ roots,
+                                            const int32_t *__restrict__ nroots_p,
+                                            uint32_t *cursor, unsigned long long *result) {
+    __shared__ uint64_t rows[DMAX * (DMAX / 64)];
+    __shared__ int32_t list[DMAX], base[DMAX], pre[DMAX + 1];
+    __shared__ Lds<NT> sh;
+    const int tid = threadIdx.x;
+    const int32_t nroots = *nroots_p;
+    uint64_t acc = 0;
+    for (;;) {
+        if (tid == 0) sh.s_task = atomicAdd(cursor, 1u);
+        __syncthreads();
+        const int32_t r = (int32_t)sh.s_task;
+        __syncthreads();
+        if (r >= nroots) break;
+        const int32_t u = roots[r];
+        const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
+        build_rows<DMAX, NT>(dag_off, dag_adj, u, d, W, rows, list, base, pre, sh.s_sum);
+        const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
+        for (int32_t e = tid; e < ne; e += NT) {
+            int32_t i, j;
+            edge_at(rows, pre, d, W, e, i, j);
+            const uint64_t *ri = rows + i * W, *rj = rows + j * W;
+            for (int32_t w = 0; w < W; w++) acc += __popcll(ri[w] & rj[w]);
+        }
+        __syncthreads();
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0 && acc) atomicAdd(result, (unsigned long long)acc);
+}
+
+// 5-cliques, step 1: rows of every root to HBM, and local edge counts.
+template <int DMAX, int NT>
+__global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ dag_off,
+                                                 const int32_t *__restrict__ dag_adj,
+                                                 const int32_t *__restrict__ roots,
+                                                 const int32_t *__restrict__ nroots_p,
+                                                 uint32_t *cursor, const int64_t *__restrict__ rowoff,
+                                                 uint64_t *grows, int32_t *slices) {
+    __shared__ uint64_t rows[DMAX * (DMAX / 64)];
+    __shared__ int32_t list[DMAX], base[DMAX], pre[DMAX + 1];
+    __shared__ Lds<NT> sh;
+    const int tid = threadIdx.x;
+    const int32_t nroots = *nroots_p;
+    if (tid == 0) sh.s_tri = 0;
+    for (;;) {
+        if (tid == 0) sh.s_task = atomicAdd(cursor, 1u);
+        __syncthreads();
+        const int32_t r = (int32_t)sh.s_task;
+        __syncthreads();
+        if (r >= nroots) break;
+        const int32_t u = roots[r];
+        const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
+        build_rows<DMAX, NT>(dag_off, dag_adj, u, d, W, rows, list, base, pre, sh.s_sum);
+        uint64_t *dst = grows + rowoff[r];
+        for (int32_t i = tid; i < d * W; i += NT) dst[i] = rows[i];
+        const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
+        // local triangles = candidates summed over local edges: the 5-clique work
+        uint64_t tri = 0;
+        for (int32_t e = tid; e < ne; e += NT) {
+            int32_t i, j;
+            edge_at(rows, pre, d, W, e, i, j);
+            const uint64_t *ri = rows + i * W, *rj = rows + j * W;
+            for (int32_t w = 0; w < W; w++) tri += __popcll(ri[w] & rj[w]);
+        }
+        tri = wave_sum(tri);
+        if (lane_id() == 0 && tri) atomicAdd((unsigned long long *)&sh.s_tri, (unsigned long long)tri);
+        __syncthreads();
+        if (tid == 0) {
+            const uint64_t work = sh.s_tri * (uint64_t)W;
+            slices[r] = (int32_t)std::min<uint64_t>(kMaxSlices, 1 + work / kSlice5);
+            sh.s_tri = 0;
+        }
+        __syncthreads();
+    }
+}
+
+// Row words (d * W) of every class root, for the row storage prefix.
+__global__ void k_lg_words(const int32_t *dag_off, const int32_t *roots, const int32_t *nroots_p,
+                           int32_t *words) {
+    const int32_t nroots = *nroots_p;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < nroots; i += stride) {
+        const int32_t u = roots[i], d = dag_off[u + 1] - dag_off[u];
+        words[i] = d * ((d + 63) >> 6);
+    }
+}
+
+// 5-cliques, step 2: task (root, slice); rows come back from HBM into LDS.
+template <int DMAX, int NT>
+__global__ void __launch_bounds__(NT) k_lg5(const int32_t *__restrict__ dag_off,
+                                            const int32_t *__restrict__ roots,
+                                            const int32_t *__restrict__ toff,
+                                            const int32_t *__restrict__ nroots_p,
+                                            const int64_t *__restrict__ rowoff,
+                                            const uint64_t *__restrict__ grows,
+                                            uint32_t *cursor, unsigned long long *result) {
+    __shared__ uint64_t rows[DMAX * (DMAX / 64)];
+    __shared__ int32_t pre[DMAX + 1];
+    __shared__ Lds<NT> sh;
+    const int tid = threadIdx.x;
+    const int32_t nroots = *nroots_p;
+    const int32_t ntasks = toff[nroots];
+    uint64_t acc = 0;
+    for (;;) {
+        if (tid == 0) sh.s_task = atomicAdd(cursor, 1u);
+        __syncthreads();
+        const int32_t t = (int32_t)sh.s_task;
+        __syncthreads();
+        if (t >= ntasks) break;
+        const int32_t r = last_le_i32(toff, nroots + 1, t);
+        const int32_t slice = t - toff[r], S = toff[r + 1] - toff[r];
+        const int32_t u = roots[r];
+        const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
+        const uint64_t *src = grows + rowoff[r];
+        for (int32_t i = tid; i < d * W; i += NT) rows[i] = src[i];
+        if (tid == 0) sh.s_next = 0;
+        __syncthreads();
+        const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
+        const int32_t nmine = ne > slice ? (ne - slice + S - 1) / S : 0;
+        constexpr int WMAX = DMAX / 64;
+        uint64_t cand[WMAX];   // row_i & row_j, statically indexed (stays in VGPRs)
+        const uint64_t *ri = rows, *rj = rows;
+        int32_t w = 0;
+        uint64_t cw = 0;
+        bool have = false, done = false;
+        for (;;) {
+            if (!have && !done) {
+                const int32_t c = (int32_t)atomicAdd(&sh.s_next, 1u);
+                if (c >= nmine) {
+                    done = true;
+                } else {
+                    int32_t i, j;
+                    edge_at(rows, pre, d, W, slice + S * c, i, j);
+                    ri = rows + i * W;
+                    rj = rows + j * W;
+#pragma unroll
+                    for (int x = 0; x < WMAX; x++) cand[x] = x < W ? (ri[x] & rj[x]) : 0ull;
+                    w = 0;
+                    cw = cand[0];
+                    have = true;
+                }
+            }
+            if (__ballot(!done) == 0) break;
+            if (have) {
+                if (cw == 0) {
+                    if (++w >= W) have = false;
+                    else cw = ri[w] & rj[w];
+                } else {
+                    const int32_t l = w * 64 + __builtin_ctzll(cw);
+                    cw &= cw - 1;
+                    const uint64_t *rl = rows + l * W;
+#pragma unroll
+                    for (int x = 0; x < WMAX; x++)
+                        if (x < W) acc += __popcll(cand[x] & rl[x]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0 && acc) atomicAdd(result, (unsigned long long)acc);
+}
+
+struct LgWs {
+    uint32_t *ctl;                 // cursors
+    int32_t *words, *eloc_m, *eloc_b, *slices, *toff_m, *toff_b;
+    int64_t *rowoff_m, *rowoff_b, *scan_tmp;
+    uint64_t *rows_m, *rows_b;
+    uint64_t bytes;
+};
+
+LgWs lg_layout(const gpm_graph *g, int32_t k, void *base) {
+    LgWs L{};
+    Carve c(base, ~0ull);
+    const uint64_t n1 = (uint64_t)g->n + 1;
+    L.ctl = c.take<uint32_t>(16);
+    if (k == 5) {
+        L.words = c.take<int32_t>(n1);
+        L.eloc_m = c.take<int32_t>(n1);
+        L.eloc_b = c.take<int32_t>(n1);
+        L.slices = c.take<int32_t>(n1);
+        L.toff_m = c.take<int32_t>(n1);
+        L.toff_b = c.take<int32_t>(n1);
+        L.rowoff_m = c.take<int64_t>(n1);
+        L.rowoff_b = c.take<int64_t>(n1);
+        L.scan_tmp = c.take<int64_t>(scan_tmp_words(n1));
+        // rows of all roots with out-degree in (64, 1024]: sum of d * ceil(d / 64)
+        // <= m * ceil(max_out / 64) words
+        const uint64_t wmax = (uint64_t)(std::max(g->max_out_degree, 1) + 63) / 64;
+        const uint64_t words = (uint64_t)std::max<int64_t>(g->m, 1) * wmax;
+        L.rows_m = c.take<uint64_t>(words);
+        L.rows_b = c.take<uint64_t>(words);
+    }
+    L.bytes = c.used;
+    return L;
+}
+
+unsigned grid_for(int64_t items, int per_block, int cap_per_cu) {
+    int64_t b = (items + per_block - 1) / per_block;
+    int64_t cap = (int64_t)cu_count() * cap_per_cu;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+template <int DMAX, int NT>
+gpm_status lg5_class(const gpm_graph *g, LgWs &L, const int32_t *list, const int32_t *cnt,
+                     int64_t *rowoff, uint64_t *rows, int32_t *eloc, int32_t *toff,
+                     uint32_t *cursors, unsigned long long *res, hipStream_t st, const char *nb,
+                     const char *nc) {
+    const int32_t n = g->n;
+    GPM_HIP(fill_u32(L.words, 0, (uint64_t)n + 1, st));
+    hipLaunchKernelGGL(k_lg_words, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, g->dag_off, list,
+                       cnt, L.words);
+    GPM_LAUNCH_CHECK("k_lg_words");
+    GPM_HIP(exclusive_scan_i64(L.words, rowoff, (uint64_t)n, L.scan_tmp, st));
+    GPM_HIP(fill_u32(L.slices, 0, (uint64_t)n + 1, st));
+    {
+        Span sp(nb, st);
+        hipLaunchKernelGGL((k_lg_build<DMAX, NT>), dim3((unsigned)cu_count() * (NT <= 256 ? 8 : 1)),
+                           dim3(NT), 0, st, g->dag_off, g->dag_adj, list, cnt, cursors + 0,
+                           rowoff, rows, L.slices);
+    }
+    GPM_LAUNCH_CHECK("k_lg_build");
+    GPM_HIP(exclusive_scan_i32(L.slices, toff, (uint64_t)n, L.scan_tmp, st));
+    {
+        Span sp(nc, st);
+        hipLaunchKernelGGL((k_lg5<DMAX, NT>), dim3((unsigned)cu_count() * (NT <= 256 ? 8 : 1)),
+                           dim3(NT), 0, st, g->dag_off, list, toff, cnt, rowoff,
+                           (const uint64_t *)rows, cursors + 1, res);
+    }
+    GPM_LAUNCH_CHECK("k_lg5");
+    return GPM_OK;
+}
+
+}  // namespace
+
+gpm_status lg_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes) {
+    *bytes = lg_layout(g, k, nullptr).bytes;
+    return GPM_OK;
+}
+
+// Counts k-cliques (k = 4, 5) rooted at the two workgroup classes: list_m
+// (out-degree 65..256) and list_b (257..1024), device counts cnt_m, cnt_b.
+gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, const int32_t *cnt_m,
+                      const int32_t *list_b, const int32_t *cnt_b, const int32_t *work, void *ws,
+                      uint64_t ws_bytes, unsigned long long *res, hipStream_t st) {
+    (void)work;
+    LgWs L = lg_layout(g, k, ws);
+    if (L.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "local-graph workspace too small");
+    GPM_HIP(fill_u32(L.ctl, 0, 16, st));
+    if (k == 4) {
+        {
+            Span sp("k_lg4<1024>", st);
+            hipLaunchKernelGGL((k_lg4<kBigMaxD, kBigThreads>), dim3((unsigned)cu_count()),
+                               dim3(kBigThreads), 0, st, g->dag_off, g->dag_adj, list_b, cnt_b,
+                               L.ctl + 0, res);
+        }
+        GPM_LAUNCH_CHECK("k_lg4<1024>");
+        {
+            Span sp("k_lg4<256>", st);
+            hipLaunchKernelGGL((k_lg4<kMidMaxD, kMidThreads>), dim3((unsigned)cu_count() * 8),
+                               dim3(kMidThreads), 0, st, g->dag_off, g->dag_adj, list_m, cnt_m,
+                               L.ctl + 1, res);
+        }
+        GPM_LAUNCH_CHECK("k_lg4<256>");
+        return GPM_OK;
+    }
+    gpm_status rc = lg5_class<kBigMaxD, kBigThreads>(g, L, list_b, cnt_b, L.rowoff_b, L.rows_b,
+                                                     L.eloc_b, L.toff_b, L.ctl + 2, res, st,
+                                                     "k_lg_build<1024>", "k_lg5<1024>");
+    if (rc) return rc;
+    return lg5_class<kMidMaxD, kMidThreads>(g, L, list_m, cnt_m, L.rowoff_m, L.rows_m, L.eloc_m,
+                                            L.toff_m, L.ctl + 4, res, st, "k_lg_build<256>",
+                                            "k_lg5<256>");
+}
+
+}  // namespace gpm

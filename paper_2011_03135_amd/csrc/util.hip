@@ -2,6 +2,7 @@
 #include "gpm_internal.h"
 
 #include <mutex>
+#include <vector>
 
 namespace gpm {
 
@@ -147,6 +148,65 @@ hipError_t exclusive_scan_i32(const int32_t *in, int32_t *out, uint64_t n, int64
 hipError_t exclusive_scan_i64(const int32_t *in, int64_t *out, uint64_t n, int64_t *tmp,
                               hipStream_t s) {
     return scan_impl<int64_t>(in, out, n, tmp, s);
+}
+
+// ---------------------------------------------------------------- timing --
+namespace {
+struct Rec {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<Rec> g_recs;
+std::vector<size_t> g_open;
+}  // namespace
+
+bool timing_on() { return g_timing; }
+
+void span_begin(const char *name, hipStream_t s) {
+    std::lock_guard<std::mutex> lock(g_tmu);
+    Rec r{name, nullptr, nullptr};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+    hipEventRecord(r.a, s);
+    g_open.push_back(g_recs.size());
+    g_recs.push_back(r);
+}
+
+void span_end(hipStream_t s) {
+    std::lock_guard<std::mutex> lock(g_tmu);
+    if (g_open.empty()) return;
+    size_t i = g_open.back();
+    g_open.pop_back();
+    hipEventRecord(g_recs[i].b, s);
+}
+
+void timing_set(bool on) {
+    std::lock_guard<std::mutex> lock(g_tmu);
+    g_timing = on;
+}
+
+int timing_read(const char **names, float *ms, int cap) {
+    std::lock_guard<std::mutex> lock(g_tmu);
+    static std::vector<std::string> keep;
+    keep.clear();
+    int k = 0;
+    for (auto &r : g_recs) {
+        float t = -1.f;
+        if (hipEventSynchronize(r.b) == hipSuccess) hipEventElapsedTime(&t, r.a, r.b);
+        if (k < cap) {
+            keep.push_back(r.name);
+            if (ms) ms[k] = t;
+        }
+        k++;
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    if (names)
+        for (int i = 0; i < (int)keep.size(); i++) names[i] = keep[i].c_str();
+    g_recs.clear();
+    g_open.clear();
+    return k;
 }
 
 // ---------------------------------------------------------- launch sizing --
