@@ -146,7 +146,14 @@ __global__ void k_chunk_map(const int64_t *wpre, const int32_t *pos_total, int64
 
 // ---------------------------------------------------------- triangles ---
 
-template <int CAP, bool TE>
+// What k_tc_flat does with each triangle (u, v, w), u -> v -> w, u -> w.
+enum TcMode : int {
+    TC_COUNT = 0,   // count only
+    TC_ARCS = 1,    // also +1 on the triangle count of each of its three arcs
+    TC_LISTS = 2,   // also append the third vertex to each arc's list
+};
+
+template <int CAP, int MODE>
 __global__ void __launch_bounds__(kBlock) k_tc_flat(const int32_t *__restrict__ dag_off,
                                                     const int32_t *__restrict__ dag_adj,
                                                     const int32_t *__restrict__ act,
@@ -154,7 +161,9 @@ __global__ void __launch_bounds__(kBlock) k_tc_flat(const int32_t *__restrict__ 
                                                     const int32_t *__restrict__ first,
                                                     const uint32_t *__restrict__ ctl,
                                                     uint32_t *cursor, int64_t tau,
-                                                    unsigned long long *result, uint32_t *te) {
+                                                    unsigned long long *result, uint32_t *te,
+                                                    const int64_t *__restrict__ toff,
+                                                    int32_t *tl) {
     __shared__ int32_t s_list[kWPB][CAP];
     __shared__ int32_t s_pre[kWPB][CAP + 1];
     __shared__ int32_t s_base[kWPB][CAP];
@@ -204,10 +213,16 @@ __global__ void __launch_bounds__(kBlock) k_tc_flat(const int32_t *__restrict__ 
                     const int32_t idx = lower_bound_i32(list, d, w);
                     if (idx < d && list[idx] == w) {
                         acc++;
-                        if (TE) {
+                        if (MODE == TC_ARCS) {
                             atomicAdd(&te[s + j], 1u);
                             atomicAdd(&te[e_vw], 1u);
                             atomicAdd(&te[s + idx], 1u);
+                        } else if (MODE == TC_LISTS) {
+                            // te holds per-arc cursors here
+                            const int32_t v = list[j];
+                            tl[toff[s + j] + atomicAdd(&te[s + j], 1u)] = w;
+                            tl[toff[e_vw] + atomicAdd(&te[e_vw], 1u)] = u;
+                            tl[toff[s + idx] + atomicAdd(&te[s + idx], 1u)] = v;
                         }
                     }
                 }
@@ -582,12 +597,9 @@ gpm_status clique_workspace_bytes(const gpm_graph *g, int32_t k, bool list, uint
 // each of the three arcs of every triangle (te, m words, must be zero on
 // entry) and the number of triangles to *tri (zero on entry).  Uses the
 // triangle workspace (clique_workspace_bytes(g, 3, false)).
-gpm_status triangle_arc_counts(const gpm_graph *g, void *ws, uint64_t ws_bytes, uint32_t *te,
-                               unsigned long long *tri, hipStream_t st) {
-    if (g->max_out_degree > kTcMax)
-        return fail(GPM_UNSUPPORTED, "motif counting needs every out-degree <= 1024");
-    CliqueWs W = clique_layout(g, 3, false, ws);
-    if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
+template <int MODE>
+static gpm_status tc_launch(const gpm_graph *g, CliqueWs &W, unsigned long long *res,
+                            uint32_t *te, const int64_t *toff, int32_t *tl, hipStream_t st) {
     const int32_t n = g->n;
     GPM_HIP(fill_u32(W.ctl, 0, 16, st));
     hipLaunchKernelGGL(k_root_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st, g->dag_off,
@@ -601,15 +613,44 @@ gpm_status triangle_arc_counts(const gpm_graph *g, void *ws, uint64_t ws_bytes, 
     hipLaunchKernelGGL(k_chunk_map, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.wpre_m,
                        W.pos + n, kTcTau, W.first_m, W.ctl + 4);
     GPM_LAUNCH_CHECK("k_chunk_map");
-    hipLaunchKernelGGL((k_tc_flat<kTcMax, true>), dim3((unsigned)persistent_blocks(kWPB, 3)),
-                       dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_m, W.wpre_m, W.first_m,
-                       W.ctl + 4, W.ctl + 1, kTcTau, tri, te);
-    GPM_LAUNCH_CHECK("k_tc_flat<1024, te>");
-    hipLaunchKernelGGL((k_tc_flat<kSmallMax, true>), dim3((unsigned)persistent_blocks(kWPB, 8)),
-                       dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_s, W.wpre_s, W.first_s,
-                       W.ctl + 2, W.ctl + 0, kTcTau, tri, te);
-    GPM_LAUNCH_CHECK("k_tc_flat<256, te>");
+    {
+        Span sp(MODE == TC_COUNT ? "k_tc_flat<1024>" : "k_tc_flat<1024,arcs>", st);
+        hipLaunchKernelGGL((k_tc_flat<kTcMax, MODE>), dim3((unsigned)persistent_blocks(kWPB, 3)),
+                           dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_m, W.wpre_m,
+                           W.first_m, W.ctl + 4, W.ctl + 1, kTcTau, res, te, toff, tl);
+    }
+    GPM_LAUNCH_CHECK("k_tc_flat<1024>");
+    {
+        Span sp(MODE == TC_COUNT ? "k_tc_flat<256>" : "k_tc_flat<256,arcs>", st);
+        hipLaunchKernelGGL((k_tc_flat<kSmallMax, MODE>), dim3((unsigned)persistent_blocks(kWPB, 8)),
+                           dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_s, W.wpre_s,
+                           W.first_s, W.ctl + 2, W.ctl + 0, kTcTau, res, te, toff, tl);
+    }
+    GPM_LAUNCH_CHECK("k_tc_flat<256>");
     return GPM_OK;
+}
+
+gpm_status triangle_arc_counts(const gpm_graph *g, void *ws, uint64_t ws_bytes, uint32_t *te,
+                               unsigned long long *tri, hipStream_t st) {
+    if (g->max_out_degree > kTcMax)
+        return fail(GPM_UNSUPPORTED, "per-edge triangle counts need every out-degree <= 1024");
+    CliqueWs W = clique_layout(g, 3, false, ws);
+    if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
+    return tc_launch<TC_ARCS>(g, W, tri, te, nullptr, nullptr, st);
+}
+
+// Second triangle pass for listings: appends the third vertex of every
+// triangle to the list of each of its three arcs; arc e's list starts at
+// toff[e] (exclusive prefix of the per-arc triangle counts) and cur (m
+// words, zero on entry) serves as per-arc cursors.
+gpm_status triangle_third_lists(const gpm_graph *g, void *ws, uint64_t ws_bytes,
+                                const int64_t *toff, uint32_t *cur, int32_t *tl,
+                                unsigned long long *tri, hipStream_t st) {
+    if (g->max_out_degree > kTcMax)
+        return fail(GPM_UNSUPPORTED, "per-edge triangle lists need every out-degree <= 1024");
+    CliqueWs W = clique_layout(g, 3, false, ws);
+    if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
+    return tc_launch<TC_LISTS>(g, W, tri, cur, toff, tl, st);
 }
 
 gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64_t ws_bytes,
@@ -638,39 +679,14 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
             hipLaunchKernelGGL(k_finish_listing, dim3(1), dim3(64), 0, st, res, cap);
             GPM_LAUNCH_CHECK("k_finish_listing");
         }
+    } else if (k == 3) {
+        gpm_status rc = tc_launch<TC_COUNT>(g, W, res, nullptr, nullptr, nullptr, st);
+        if (rc) return rc;
     } else {
-        const int32_t small_max = k == 3 ? kSmallMax : 64;
-        const int32_t mid_max = k == 3 ? kTcMax : kMidMaxD;
         hipLaunchKernelGGL(k_root_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st,
-                           g->dag_off, g->dag_adj, n, k - 1, small_max, mid_max, kTcMax, W.work,
-                           W.cls);
+                           g->dag_off, g->dag_adj, n, k - 1, 64, kMidMaxD, kTcMax, W.work, W.cls);
         GPM_LAUNCH_CHECK("k_root_work");
-        if (k == 3) {
-            GPM_HIP(build_class(g, W, RC_SMALL, W.list_s, W.wpre_s, st));
-            hipLaunchKernelGGL(k_chunk_map, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.wpre_s,
-                               W.pos + n, kTcTau, W.first_s, W.ctl + 2);
-            GPM_LAUNCH_CHECK("k_chunk_map");
-            GPM_HIP(build_class(g, W, RC_MID, W.list_m, W.wpre_m, st));
-            hipLaunchKernelGGL(k_chunk_map, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.wpre_m,
-                               W.pos + n, kTcTau, W.first_m, W.ctl + 4);
-            GPM_LAUNCH_CHECK("k_chunk_map");
-            unsigned blocks = (unsigned)persistent_blocks(kWPB, 8);
-            {
-                Span sp("k_tc_flat<1024>", st);
-                hipLaunchKernelGGL((k_tc_flat<kTcMax, false>),
-                                   dim3((unsigned)persistent_blocks(kWPB, 3)), dim3(kBlock), 0, st,
-                                   g->dag_off, g->dag_adj, W.list_m, W.wpre_m, W.first_m,
-                                   W.ctl + 4, W.ctl + 1, kTcTau, res, (uint32_t *)nullptr);
-            }
-            GPM_LAUNCH_CHECK("k_tc_flat<1024>");
-            {
-                Span sp("k_tc_flat<256>", st);
-                hipLaunchKernelGGL((k_tc_flat<kSmallMax, false>), dim3(blocks), dim3(kBlock), 0, st,
-                                   g->dag_off, g->dag_adj, W.list_s, W.wpre_s, W.first_s,
-                                   W.ctl + 2, W.ctl + 0, kTcTau, res, (uint32_t *)nullptr);
-            }
-            GPM_LAUNCH_CHECK("k_tc_flat<256>");
-        } else {
+        {
             // three classes; each count lives in its own pos snapshot
             int32_t *cnt_s = (int32_t *)(W.ctl + 8), *cnt_m = (int32_t *)(W.ctl + 9),
                     *cnt_b = (int32_t *)(W.ctl + 10);

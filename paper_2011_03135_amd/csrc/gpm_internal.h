@@ -71,6 +71,9 @@ hipError_t exclusive_scan_i32(const int32_t *in, int32_t *out, uint64_t n, int64
 // Same with 64-bit output offsets.
 hipError_t exclusive_scan_i64(const int32_t *in, int64_t *out, uint64_t n, int64_t *tmp,
                               hipStream_t s);
+// 64-bit counts in, 64-bit offsets out.
+hipError_t exclusive_scan_64(const int64_t *in, int64_t *out, uint64_t n, int64_t *tmp,
+                             hipStream_t s);
 
 // Optional kernel timing (off by default): when on, span_begin/span_end
 // bracket a launch with HIP events recorded on its stream.

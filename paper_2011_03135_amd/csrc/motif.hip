@@ -17,13 +17,7 @@
 // necessarily induced; N_C4 = I_C4 + I_diamond + 3 I_K4) the system solves
 // exactly; every division is checked.
 //
-// N_C4 is counted from each cycle's highest-ranked vertex x (degree order):
-// for wedges x - y - z with y, z ranked below x, c(x, z) = #middles y and the
-// cycles with apex x and opposite vertex z number C(c(x, z), 2).  The sum is
-// formed incrementally: each new wedge to z adds the number of earlier ones.
-//   light apexes (wedge work <= kLightW): one wave, LDS hash table on z;
-//   heavy apexes: tasks (x, part p) with dense LDS counters for z in part p;
-//   each in-neighbour list N(y) is entered at part p by binary search.
+// N_C4 comes from the 4-cycle counter (c4.hip).
 #include "gpm_internal.h"
 
 #include <algorithm>
@@ -37,6 +31,10 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
                       unsigned long long *d_result, hipStream_t st);
 gpm_status triangle_arc_counts(const gpm_graph *g, void *ws, uint64_t ws_bytes, uint32_t *te,
                                unsigned long long *tri, hipStream_t st);
+gpm_status c4_workspace_bytes(const gpm_graph *g, bool list, uint64_t *bytes);
+gpm_status c4_run(const gpm_graph *g, bool list, void *ws, uint64_t ws_bytes,
+                  unsigned long long *out128, int32_t *d_buf, uint64_t cap,
+                  unsigned long long *d_result, hipStream_t st);
 
 namespace {
 
@@ -44,16 +42,6 @@ typedef unsigned __int128 u128;
 
 constexpr int kBlock = 256;
 constexpr int kWPB = kBlock / kWave;
-constexpr int kLightW = 512;         // wedge work of a light apex
-constexpr int kHashSlots = 1024;     // per-wave LDS hash (load <= 1/2)
-constexpr int kPartZ = 8192;         // z-range per heavy task (LDS counters)
-constexpr int kYChunk = kBlock;      // in-neighbours staged per round
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ __forceinline__ u128 wave_sum_u128(u128 x) {
     uint64_t lo = (uint64_t)x, hi = (uint64_t)(x >> 64);
@@ -65,24 +53,6 @@ __device__ __forceinline__ u128 wave_sum_u128(u128 x) {
         lo = s;
     }
     return ((u128)hi << 64) | lo;
-}
-
-__device__ __forceinline__ int lower_bound_i32(const int32_t *a, int n, int32_t x) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (a[mid] < x) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ int last_le_i32(const int32_t *a, int n, int32_t x) {
-    int lo = 0, hi = n;
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (a[mid] <= x) lo = mid; else hi = mid;
-    }
-    return lo;
 }
 
 __global__ void k_degrees(const int32_t *off, int32_t n, int32_t *deg) {
@@ -135,196 +105,6 @@ __global__ void __launch_bounds__(kBlock) k_lc_sums(const int32_t *__restrict__ 
     }
 }
 
-// ------------------------------------------------------------ 4-cycles ---
-
-enum C4Class : int { C4_NONE = 0, C4_LIGHT = 1, C4_HEAVY = 2 };
-
-// Wedge work of apex x: sum of d(y) over in-neighbours y (ranked below x).
-__global__ void __launch_bounds__(kBlock) k_c4_work(const int32_t *__restrict__ off,
-                                                    const int32_t *__restrict__ adj,
-                                                    const int32_t *__restrict__ deg, int32_t n,
-                                                    int32_t *cls) {
-    const int lane = lane_id();
-    const int64_t wave0 = (int64_t)blockIdx.x * kWPB + threadIdx.x / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * kWPB;
-    for (int64_t r = wave0; r < n; r += nwaves) {
-        const int32_t x = (int32_t)r, s = off[x], dx = off[x + 1] - s;
-        int64_t w = 0;
-        int32_t ny = 0;
-        for (int32_t i = lane; i < dx; i += kWave) {
-            const int32_t y = adj[s + i], dy = deg[y];
-            if (rank_less(dy, y, dx, x)) {
-                w += dy;
-                ny++;
-            }
-        }
-        w = wave_sum(w);
-        ny = wave_sum(ny);
-        if (lane == 0) cls[x] = (ny < 2) ? C4_NONE : (w <= kLightW ? C4_LIGHT : C4_HEAVY);
-    }
-}
-
-__global__ void k_flag_eq(const int32_t *cls, int32_t n, int32_t want, int32_t *flag) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) flag[i] = cls[i] == want ? 1 : 0;
-}
-
-__global__ void k_compact_eq(const int32_t *cls, const int32_t *pos, int32_t n, int32_t want,
-                             int32_t *list) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride)
-        if (cls[i] == want) list[pos[i]] = (int32_t)i;
-}
-
-__device__ __forceinline__ uint32_t hash_slot(int32_t z) {
-    return ((uint32_t)z * 0x9E3779B1u) >> 22;   // 10 bits -> kHashSlots
-}
-
-// Light apexes: one wave each, LDS hash z -> count, wedge by wedge.
-__global__ void __launch_bounds__(kBlock) k_c4_light(const int32_t *__restrict__ off,
-                                                     const int32_t *__restrict__ adj,
-                                                     const int32_t *__restrict__ deg,
-                                                     const int32_t *__restrict__ list,
-                                                     const int32_t *__restrict__ count_p,
-                                                     unsigned long long *out) {
-    __shared__ int32_t s_key[kWPB][kHashSlots];
-    __shared__ uint32_t s_cnt[kWPB][kHashSlots];
-    __shared__ int32_t s_pre[kWPB][kLightW + 1];
-    __shared__ int32_t s_base[kWPB][kLightW];
-    const int lane = lane_id(), wib = threadIdx.x / kWave;
-    int32_t *key = s_key[wib], *pre = s_pre[wib], *base = s_base[wib];
-    uint32_t *cnt = s_cnt[wib];
-    const int32_t count = *count_p;
-    const int64_t wave0 = (int64_t)blockIdx.x * kWPB + wib;
-    const int64_t nwaves = (int64_t)gridDim.x * kWPB;
-    for (int i = lane; i < kHashSlots; i += kWave) { key[i] = -1; cnt[i] = 0; }
-    uint64_t acc = 0;
-    for (int64_t r = wave0; r < count; r += nwaves) {
-        const int32_t x = list[r], s = off[x], dx = off[x + 1] - s;
-        // stage in-neighbours: their list starts and a prefix of their degrees
-        int32_t ny = 0, carry = 0;
-        for (int32_t i0 = 0; i0 < dx; i0 += kWave) {
-            const int32_t i = i0 + lane;
-            int32_t y = 0, dy = 0;
-            bool in = false;
-            if (i < dx) {
-                y = adj[s + i];
-                dy = deg[y];
-                in = rank_less(dy, y, dx, x);
-            }
-            const uint64_t mask = __ballot(in);
-            const int32_t p = ny + lanes_below(mask);
-            const int32_t inc = wave_incl_scan(in ? dy : 0);
-            if (in) {
-                base[p] = off[y];
-                pre[p + 1] = carry + inc;
-            }
-            carry += __shfl(inc, 63, 64);
-            ny += __popcll(mask);
-        }
-        if (lane == 0) pre[0] = 0;
-        wave_sync();
-        const int32_t W = carry;
-        for (int32_t qb = 0; qb < W; qb += kWave) {
-            const int32_t q = qb + lane;
-            if (q < W) {
-                const int32_t j = last_le_i32(pre, ny + 1, q);
-                const int32_t z = adj[base[j] + (q - pre[j])];
-                if (rank_less(deg[z], z, dx, x)) {
-                    uint32_t h = hash_slot(z);
-                    for (;;) {
-                        int32_t k = key[h];
-                        if (k == -1) {
-                            k = atomicCAS(&key[h], -1, z);
-                            if (k == -1) k = z;
-                        }
-                        if (k == z) {
-                            acc += atomicAdd(&cnt[h], 1u);
-                            break;
-                        }
-                        h = (h + 1) & (kHashSlots - 1);
-                    }
-                }
-            }
-        }
-        wave_sync();
-        // clear the slots this apex used
-        for (int i = lane; i < kHashSlots; i += kWave)
-            if (key[i] != -1) { key[i] = -1; cnt[i] = 0; }
-        wave_sync();
-    }
-    acc = wave_sum(acc);
-    if (lane == 0 && acc) atomic_add_u128(out, (u128)acc);
-}
-
-// Heavy apexes: block per (apex, z-part) task with dense LDS counters.
-__global__ void __launch_bounds__(kBlock) k_c4_heavy(const int32_t *__restrict__ off,
-                                                     const int32_t *__restrict__ adj,
-                                                     const int32_t *__restrict__ deg,
-                                                     const int32_t *__restrict__ list,
-                                                     const int32_t *__restrict__ count_p,
-                                                     int32_t nparts, uint32_t *cursor,
-                                                     unsigned long long *out) {
-    __shared__ uint32_t cnt[kPartZ];
-    __shared__ int32_t s_pre[kYChunk + 1];
-    __shared__ int32_t s_start[kYChunk];
-    __shared__ int32_t s_sum[kWPB];
-    __shared__ uint32_t s_task;
-    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
-    const uint64_t ntasks = (uint64_t)(*count_p) * (uint64_t)nparts;
-    uint64_t acc = 0;
-    for (int i = tid; i < kPartZ; i += kBlock) cnt[i] = 0;
-    for (;;) {
-        if (tid == 0) s_task = atomicAdd(cursor, 1u);
-        __syncthreads();
-        const uint64_t t = s_task;
-        __syncthreads();
-        if (t >= ntasks) break;
-        const int32_t x = list[t / nparts];
-        const int32_t part = (int32_t)(t % nparts);
-        const int32_t z0 = part * kPartZ, z1 = z0 + kPartZ;
-        const int32_t s = off[x], dx = off[x + 1] - s;
-        for (int32_t c0 = 0; c0 < dx; c0 += kYChunk) {
-            const int32_t i = c0 + tid;
-            int32_t len = 0, start = 0;
-            if (i < dx) {
-                const int32_t y = adj[s + i], dy = deg[y];
-                if (rank_less(dy, y, dx, x)) {
-                    const int32_t *ny = adj + off[y];
-                    const int32_t lo = lower_bound_i32(ny, dy, z0);
-                    const int32_t hi = lo + lower_bound_i32(ny + lo, dy - lo, z1);
-                    start = off[y] + lo;
-                    len = hi - lo;
-                }
-            }
-            const int32_t inc = wave_incl_scan(len);
-            if (lane == 63) s_sum[wid] = inc;
-            __syncthreads();
-            int32_t before = 0, total = 0;
-            for (int q = 0; q < kWPB; q++) {
-                if (q < wid) before += s_sum[q];
-                total += s_sum[q];
-            }
-            s_pre[tid + 1] = before + inc;
-            s_start[tid] = start;
-            if (tid == 0) s_pre[0] = 0;
-            __syncthreads();
-            for (int32_t q = tid; q < total; q += kBlock) {
-                const int32_t j = last_le_i32(s_pre, kYChunk + 1, q);
-                const int32_t z = adj[s_start[j] + (q - s_pre[j])];
-                if (rank_less(deg[z], z, dx, x)) acc += atomicAdd(&cnt[z - z0], 1u);
-            }
-            __syncthreads();
-        }
-        for (int i = tid; i < kPartZ; i += kBlock) cnt[i] = 0;
-        __syncthreads();
-    }
-    acc = wave_sum(acc);
-    if (lane == 0 && acc) atomic_add_u128(out, (u128)acc);
-}
-
 // ------------------------------------------------------------- combine ---
 
 struct Sums {
@@ -373,11 +153,11 @@ __global__ void k_combine(const Sums *S, int32_t k, unsigned long long *out) {
 struct MotifWs {
     Sums *sums;
     uint32_t *te;
-    int32_t *deg, *cls, *flag, *pos, *light, *heavy;
-    int64_t *scan_tmp;
-    uint32_t *ctl;     // [0] heavy cursor, [1] light count, [2] heavy count
+    int32_t *deg;
+    uint32_t *ctl;
     void *shared;      // clique workspace (k = 3 or 4), reused in sequence
-    uint64_t shared_bytes, bytes;
+    void *c4ws;        // 4-cycle counting workspace
+    uint64_t shared_bytes, c4_bytes, bytes;
 };
 
 MotifWs motif_layout(const gpm_graph *g, int32_t k, void *base) {
@@ -389,12 +169,8 @@ MotifWs motif_layout(const gpm_graph *g, int32_t k, void *base) {
     W.deg = c.take<int32_t>(n1);
     if (k == 4) {
         W.te = c.take<uint32_t>((uint64_t)std::max<int64_t>(g->m, 1));
-        W.cls = c.take<int32_t>(n1);
-        W.flag = c.take<int32_t>(n1);
-        W.pos = c.take<int32_t>(n1);
-        W.light = c.take<int32_t>(n1);
-        W.heavy = c.take<int32_t>(n1);
-        W.scan_tmp = c.take<int64_t>(scan_tmp_words(n1));
+        c4_workspace_bytes(g, false, &W.c4_bytes);
+        W.c4ws = c.take<char>(W.c4_bytes);
     }
     uint64_t b3 = 0, b4 = 0;
     clique_workspace_bytes(g, 3, false, &b3);
@@ -417,35 +193,6 @@ gpm_status motif_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes)
     if (k == 4 && g->max_out_degree > 1024)
         return fail(GPM_UNSUPPORTED, "4-motif counting needs every out-degree <= 1024");
     *bytes = motif_layout(g, k, nullptr).bytes;
-    return GPM_OK;
-}
-
-// Counts N_C4 into S->c4 (zeroed by the caller).
-static gpm_status c4_count(const gpm_graph *g, MotifWs &W, hipStream_t st) {
-    const int32_t n = g->n;
-    hipLaunchKernelGGL(k_c4_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st, g->off,
-                       g->adj, W.deg, n, W.cls);
-    GPM_LAUNCH_CHECK("k_c4_work");
-    int32_t *cnt_light = (int32_t *)(W.ctl + 1), *cnt_heavy = (int32_t *)(W.ctl + 2);
-    for (int cls = C4_LIGHT; cls <= C4_HEAVY; cls++) {
-        int32_t *list = cls == C4_LIGHT ? W.light : W.heavy;
-        hipLaunchKernelGGL(k_flag_eq, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.cls, n, cls,
-                           W.flag);
-        GPM_HIP(exclusive_scan_i32(W.flag, W.pos, (uint64_t)n, W.scan_tmp, st));
-        hipLaunchKernelGGL(k_compact_eq, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.cls,
-                           W.pos, n, cls, list);
-        GPM_HIP(hipMemcpyAsync(cls == C4_LIGHT ? cnt_light : cnt_heavy, W.pos + n, 4,
-                               hipMemcpyDeviceToDevice, st));
-    }
-    GPM_LAUNCH_CHECK("c4 classes");
-    const int32_t nparts = (n + kPartZ - 1) / kPartZ;
-    hipLaunchKernelGGL(k_c4_heavy, dim3((unsigned)persistent_blocks(kWPB, 4)), dim3(kBlock), 0, st,
-                       g->off, g->adj, W.deg, W.heavy, cnt_heavy, nparts, W.ctl + 0,
-                       W.sums->c4);
-    GPM_LAUNCH_CHECK("k_c4_heavy");
-    hipLaunchKernelGGL(k_c4_light, dim3((unsigned)persistent_blocks(kWPB, 4)), dim3(kBlock), 0, st,
-                       g->off, g->adj, W.deg, W.light, cnt_light, W.sums->c4);
-    GPM_LAUNCH_CHECK("k_c4_light");
     return GPM_OK;
 }
 
@@ -480,7 +227,7 @@ gpm_status motif_run(const gpm_graph *g, int32_t k, void *ws, uint64_t ws_bytes,
         rc = clique_run(g, 4, false, W.shared, W.shared_bytes, &W.sums->k4, nullptr, 0, nullptr,
                         st);
         if (rc) return rc;
-        rc = c4_count(g, W, st);
+        rc = c4_run(g, false, W.c4ws, W.c4_bytes, W.sums->c4, nullptr, 0, nullptr, st);
         if (rc) return rc;
     }
     hipLaunchKernelGGL(k_combine, dim3(1), dim3(64), 0, st, W.sums, k, d_counts);

@@ -65,7 +65,8 @@ __device__ int64_t block_excl_scan(int64_t x, int64_t *sh /*[kScanThreads/64]*/,
     return base + inc - x;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const int32_t *in, uint64_t n,
+template <class InT>
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const InT *in, uint64_t n,
                                                              int64_t *tile_sums) {
     __shared__ int64_t sh[kScanThreads / 64];
     uint64_t base = (uint64_t)blockIdx.x * kTile;
@@ -94,11 +95,11 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(int64_t *tile_sums,
     if (threadIdx.x == 0) tile_sums[ntiles] = carry;
 }
 
-template <class OutT>
-__global__ void __launch_bounds__(kScanThreads) k_scan_down(const int32_t *in, OutT *out,
+template <class InT, class OutT>
+__global__ void __launch_bounds__(kScanThreads) k_scan_down(const InT *in, OutT *out,
                                                            uint64_t n, const int64_t *tile_sums,
                                                            uint64_t ntiles) {
-    __shared__ int32_t tile[kTile];
+    __shared__ InT tile[kTile];
     __shared__ int64_t sh[kScanThreads / 64];
     uint64_t base = (uint64_t)blockIdx.x * kTile;
     for (int i = 0; i < kScanItems; i++) {
@@ -106,7 +107,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(const int32_t *in, O
         tile[j] = (base + j < n) ? in[base + j] : 0;
     }
     __syncthreads();
-    int32_t v[kScanItems];
+    InT v[kScanItems];
     int64_t s = 0;
     for (int i = 0; i < kScanItems; i++) {
         v[i] = tile[threadIdx.x * kScanItems + i];
@@ -122,32 +123,37 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(const int32_t *in, O
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = (OutT)tile_sums[ntiles];
 }
 
-template <class OutT>
-static hipError_t scan_impl(const int32_t *in, OutT *out, uint64_t n, int64_t *tmp,
-                            hipStream_t s) {
+template <class InT, class OutT>
+static hipError_t scan_impl(const InT *in, OutT *out, uint64_t n, int64_t *tmp, hipStream_t s) {
     uint64_t ntiles = (n + kTile - 1) / kTile;
     if (ntiles == 0) {
         // n == 0: out[0] = 0
         hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, tmp, (uint64_t)0);
-        hipLaunchKernelGGL((k_scan_down<OutT>), dim3(1), dim3(kScanThreads), 0, s, in, out,
+        hipLaunchKernelGGL((k_scan_down<InT, OutT>), dim3(1), dim3(kScanThreads), 0, s, in, out,
                            (uint64_t)0, (const int64_t *)tmp, (uint64_t)0);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, in, n, tmp);
+    hipLaunchKernelGGL((k_scan_reduce<InT>), dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, in,
+                       n, tmp);
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, tmp, ntiles);
-    hipLaunchKernelGGL((k_scan_down<OutT>), dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, in,
-                       out, n, (const int64_t *)tmp, ntiles);
+    hipLaunchKernelGGL((k_scan_down<InT, OutT>), dim3((unsigned)ntiles), dim3(kScanThreads), 0, s,
+                       in, out, n, (const int64_t *)tmp, ntiles);
     return hipGetLastError();
 }
 
 hipError_t exclusive_scan_i32(const int32_t *in, int32_t *out, uint64_t n, int64_t *tmp,
                               hipStream_t s) {
-    return scan_impl<int32_t>(in, out, n, tmp, s);
+    return scan_impl<int32_t, int32_t>(in, out, n, tmp, s);
 }
 
 hipError_t exclusive_scan_i64(const int32_t *in, int64_t *out, uint64_t n, int64_t *tmp,
                               hipStream_t s) {
-    return scan_impl<int64_t>(in, out, n, tmp, s);
+    return scan_impl<int32_t, int64_t>(in, out, n, tmp, s);
+}
+
+hipError_t exclusive_scan_64(const int64_t *in, int64_t *out, uint64_t n, int64_t *tmp,
+                             hipStream_t s) {
+    return scan_impl<int64_t, int64_t>(in, out, n, tmp, s);
 }
 
 // ---------------------------------------------------------------- timing --
