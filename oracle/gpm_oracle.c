@@ -270,7 +270,11 @@ struct list_sink {
 
 static void sink_emit(struct list_sink *s, const int32_t *tuple, int k)
 {
-    uint64_t slot;
+    uint64_t slot, seen;
+    /* once the buffer is full, stop touching the shared counter */
+#pragma omp atomic read
+    seen = s->written;
+    if (seen >= s->cap) return;
 #pragma omp atomic capture
     slot = s->written++;
     if (slot < s->cap) memcpy(s->buf + slot * (uint64_t)k, tuple, sizeof(int32_t) * (size_t)k);

@@ -38,6 +38,8 @@ def main():
         rec.update({"scale": s, "seed": s, "edge_factor": 16, "n": g.n,
                     "input_edges": g.num_input_edges, "m": int(adj.shape[0] // 2)})
         for k in (3, 4, 5):
+            if f"clique{k}" in rec:
+                continue
             t = time.time()
             rec[f"clique{k}"] = oracle.clique_count(off, adj, k, args.threads)
             print(f"{key} clique{k} = {rec[f'clique{k}']} ({time.time() - t:.1f} s)", flush=True)
@@ -45,9 +47,12 @@ def main():
             with open(OUT, "w") as f:
                 json.dump(data, f, indent=1, sort_keys=True)
         if s <= 18:
-            rec["motif3"] = oracle.motif3(off, adj, args.threads)
-            rec["motif4"] = oracle.motif4(off, adj, args.threads)
+            if "motif4" not in rec:
+                rec["motif3"] = oracle.motif3(off, adj, args.threads)
+                rec["motif4"] = oracle.motif4(off, adj, args.threads)
             for name, fn in (("diamond", oracle.list_diamonds), ("4-cycle", oracle.list_c4)):
+                if f"sl_{name}" in rec:
+                    continue
                 t = time.time()
                 total, chk, _ = fn(off, adj, 0, args.threads)
                 rec[f"sl_{name}"] = {"total": total, "checksum": chk}
