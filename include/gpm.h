@@ -204,6 +204,60 @@ gpm_status gpm_batch_motif_count(const gpm_graph *g, const int32_t *d_voff, int3
                                  int32_t k, void *d_ws, uint64_t ws_bytes,
                                  uint64_t *d_counts, void *stream);
 
+/* ---------------------------------------------------------- serving --- */
+
+/* A request-serving runtime (not part of the paper's method; it serves the
+ * counting entry points above): requests arrive at any time; a scheduler
+ * thread admits them, first come first served, whenever a slot (one HIP
+ * stream each) is free and the request's workspace fits in the free part of
+ * a caller-owned device memory pool; admitted requests run concurrently on
+ * their slots' streams; completions are collected without blocking.  Every
+ * request recomputes its answer from the resident graph. */
+typedef struct gpm_server gpm_server;
+
+typedef struct gpm_server_config {
+    int32_t max_slots;      /* concurrent requests on the device, 1..64 */
+    int32_t reserved;
+    void *d_pool;           /* device memory for request workspaces (caller-owned) */
+    uint64_t pool_bytes;
+} gpm_server_config;
+
+#define GPM_QUERY_CLIQUE 1  /* k-clique count, k = 3..8 (triangles: k = 3) */
+#define GPM_QUERY_MOTIF  2  /* induced k-motif counts, k = 3 or 4 */
+
+typedef struct gpm_request {
+    int32_t kind;           /* GPM_QUERY_* */
+    int32_t k;
+    const gpm_graph *graph; /* resident graph; must outlive the request */
+    uint64_t tag;           /* caller's label, returned with the response */
+} gpm_request;
+
+typedef struct gpm_response {
+    uint64_t id;            /* from gpm_server_submit */
+    uint64_t tag;
+    int32_t status;         /* GPM_OK or the failing status */
+    int32_t n_values;       /* 1 (clique) or 2 / 6 (motif) */
+    uint64_t values[7];     /* counts (motif: plus the status word) */
+    double t_submit, t_admit, t_done;   /* seconds on gpm_server_now()'s clock */
+} gpm_response;
+
+/* Creates the server and its scheduler thread.  Streams (default priority)
+ * and a small pinned host buffer are created here; request workspaces come
+ * only from the pool. */
+gpm_status gpm_server_create(const gpm_server_config *cfg, gpm_server **out);
+/* Queues a request (thread-safe, non-blocking); *id identifies it.  A
+ * request whose workspace can never fit in the pool fails at once. */
+gpm_status gpm_server_submit(gpm_server *s, const gpm_request *r, uint64_t *id);
+/* Moves up to max finished responses to out; *n gets their number. */
+gpm_status gpm_server_poll(gpm_server *s, gpm_response *out, int32_t max, int32_t *n);
+/* Number of requests queued or running. */
+int64_t gpm_server_pending(gpm_server *s);
+/* Monotonic clock (seconds) used for the response timestamps. */
+double gpm_server_now(void);
+/* Waits for every submitted request, stops the thread, frees host state.
+ * Unpolled responses are discarded. */
+void gpm_server_destroy(gpm_server *s);
+
 /* ----------------------------------------------------------- timing --- */
 
 /* Kernel timing for measurement (off by default).  While on, the library

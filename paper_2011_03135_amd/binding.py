@@ -77,6 +77,12 @@ def load():
         "gpm_batch_motif_count": ([P, P, i32, i32, P, u64, P, P], i32),
         "gpm_timing_enable": ([i32], i32),
         "gpm_timing_read": ([P, P, i32], i32),
+        "gpm_server_create": ([P, P], i32),
+        "gpm_server_submit": ([P, P, P], i32),
+        "gpm_server_poll": ([P, P, i32, P], i32),
+        "gpm_server_pending": ([P], i64),
+        "gpm_server_now": ([], ctypes.c_double),
+        "gpm_server_destroy": ([P], None),
     }
     for name, (args, res) in sigs.items():
         f = getattr(lib, name)
@@ -285,3 +291,75 @@ def batch_motif_count(g, voff, k, stream=None, ws=None, out=None):
     _check(load().gpm_batch_motif_count(g.handle, _ptr(voff.contiguous()), G, int(k), _ptr(ws),
                                         ws.numel(), _ptr(res), _stream(stream)))
     return res
+
+
+# ------------------------------------------------------------- serving ---
+
+QUERY_CLIQUE = 1
+QUERY_MOTIF = 2
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("d_pool", ctypes.c_void_p), ("pool_bytes", ctypes.c_uint64)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("graph", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+
+
+class Response(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("tag", ctypes.c_uint64),
+                ("status", ctypes.c_int32), ("n_values", ctypes.c_int32),
+                ("values", ctypes.c_uint64 * 7),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+    def counts(self):
+        return [int(self.values[i]) for i in range(self.n_values)]
+
+
+class Server:
+    """gpm_server_*: concurrent request execution over resident graphs."""
+
+    def __init__(self, max_slots=4, pool_bytes=8 << 30, device="cuda"):
+        self._pool = _buffer(pool_bytes, torch.device(device))
+        cfg = _ServerConfig(int(max_slots), 0, self._pool.data_ptr(), int(self._pool.numel()))
+        self._h = ctypes.c_void_p()
+        _check(load().gpm_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self._graphs = {}
+
+    def submit(self, graph, kind, k, tag=0):
+        req = _Request(int(kind), int(k), graph.handle, int(tag))
+        rid = ctypes.c_uint64()
+        _check(load().gpm_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
+        self._graphs[rid.value] = graph     # keep the graph alive while in flight
+        return rid.value
+
+    def poll(self, max_n=1024):
+        buf = (Response * max_n)()
+        n = ctypes.c_int32()
+        _check(load().gpm_server_poll(self._h, buf, max_n, ctypes.byref(n)))
+        out = [buf[i] for i in range(n.value)]
+        for r in out:
+            self._graphs.pop(r.id, None)
+        return out
+
+    def pending(self):
+        return int(load().gpm_server_pending(self._h))
+
+    @staticmethod
+    def now():
+        return float(load().gpm_server_now())
+
+    def close(self):
+        if self._h:
+            load().gpm_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,73 @@
+"""Serving runtime: results in a concurrent mix equal isolated results."""
+import pytest
+
+import graphgen
+from gpu_util import build
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpm():
+    import paper_2011_03135_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def graphs(gpm):
+    return [build(gpm, graphgen.rmat(s, seed=1000 + s)) for s in (9, 10, 11, 12)]
+
+
+def isolated(gpm, g, name):
+    if name == "TC":
+        return [gpm.count(g, gpm.clique(3))]
+    if name == "4-clique":
+        return [gpm.count(g, gpm.clique(4))]
+    return gpm.motif_count(g, 3 if name == "3-motif" else 4)
+
+
+def test_mix_equals_isolated(gpm, graphs):
+    from paper_2011_03135_amd.serve import QUERIES, run_load
+    want = {(gi, qi): isolated(gpm, graphs[gi], QUERIES[qi][0])
+            for gi in range(len(graphs)) for qi in range(len(QUERIES))}
+    stats, per = run_load(graphs, rate=2000.0, n_requests=400, n_warmup=40, seed=5,
+                          max_slots=4, pool_bytes=1 << 30)
+    assert stats["failed"] == 0
+    for gi, qi, r in per:
+        assert r.status == 0
+        got = r.counts()
+        assert got == want[(gi, qi)], (gi, qi, got)
+        assert r.t_submit <= r.t_admit <= r.t_done
+
+
+def test_small_pool_defers(gpm, graphs):
+    """A pool that holds one request at a time still serves every request."""
+    from paper_2011_03135_amd.binding import QUERY_CLIQUE, Server
+    g = graphs[-1]
+    ws = gpm.workspace_bytes(g, gpm.clique(4))
+    srv = Server(max_slots=4, pool_bytes=ws + 4 * 256 + 4096)   # room for one workspace
+    ids = [srv.submit(g, QUERY_CLIQUE, 4, tag=i) for i in range(12)]
+    got = {}
+    while len(got) < len(ids):
+        for r in srv.poll():
+            got[r.tag] = r
+    srv.close()
+    want = [gpm.count(g, gpm.clique(4))]
+    for i in range(12):
+        assert got[i].status == 0
+        assert got[i].counts() == want
+    # admissions never overlapped: each started after the previous finished
+    spans = sorted((r.t_admit, r.t_done) for r in got.values())
+    for (a0, d0), (a1, d1) in zip(spans, spans[1:]):
+        assert a1 >= d0 - 1e-4
+
+
+def test_rejects_oversized_and_invalid(gpm, graphs):
+    from paper_2011_03135_amd.binding import QUERY_CLIQUE, QUERY_MOTIF, Server
+    srv = Server(max_slots=2, pool_bytes=1 << 16)
+    with pytest.raises(gpm.GpmError):
+        srv.submit(graphs[-1], QUERY_MOTIF, 4)      # workspace larger than the pool
+    with pytest.raises(gpm.GpmError):
+        srv.submit(graphs[0], QUERY_CLIQUE, 9)      # unsupported clique size
+    srv.close()
