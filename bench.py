@@ -1,20 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of the pattern-mining hot path on one MI355X.
 
-Workload (one "step"): an RMAT graph, scale 20 (2^20 vertices, 16 * 2^20
-distinct undirected edges, a, b, c, d = 0.57, 0.19, 0.19, 0.05, seed 20, ids
-permuted), given as its raw edge stream resident in HBM.  A step builds the
-canonical CSR and the degree-ordered DAG on the device, then counts
-triangles, 4-cliques and 5-cliques.  The input stream is synthetic (seeded).
+Workload of one step: an RMAT graph of scale 20 (2^20 vertices, exactly
+16 * 2^20 distinct undirected edges, a, b, c, d = 0.57, 0.19, 0.19, 0.05,
+seed 20, ids permuted) given as its raw edge stream (17,978,493 entries with
+repeats and self-loops) resident in HBM.  A step builds the canonical CSR and
+the degree-ordered DAG on the device and counts triangles, 4-cliques and
+5-cliques.  Inputs are synthetic and seeded.
 
-Prints ONE JSON line:
-  value      = undirected edges per second of the whole step (m / t_step)
-  matches/s  = (triangles + 4-cliques + 5-cliques) / t_step
-  phases     = per-kernel milliseconds (HIP events on the launch stream)
-  roofline   = the dominant kernel's algorithmic bytes per launch / its
-               average duration, against MI355X's 8 TB/s HBM peak
-  cpu_baseline = the CPU oracle timed on a bounded sample of the same
-               workload (every F-th root, seeded), scaled to edges/s
+One JSON line:
+  value             undirected edges per second of the whole step
+  matches_per_sec   (triangles + 4-cliques + 5-cliques) per second
+  phases_ms         per-kernel milliseconds per step, HIP events recorded on
+                    the launch stream by the library's timing spans
+  roofline          the dominant kernel against its bound
+  batched_vs_plain  20,000 random geometric graphs (n in [10, 200]), induced
+                    4-motif counts: one fused launch replayed from a HIP
+                    graph vs one library call per graph on prebuilt graphs
+  cpu_baseline      the CPU oracle on a bounded sample of the same workload
 """
 import argparse
 import json
@@ -28,13 +31,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: one 32-bit integer VALU op per lane
+# per clock (a wave64 instruction occupies a 16-lane SIMD for 4 clocks)
+INT32_VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# algorithmic int32 ops per local triangle of the 5-clique kernel: the AND and
+# the population count of one 64-bit candidate word (2 + 2 32-bit ops)
+OPS_PER_LOCAL_TRIANGLE = 4
 
 
-def algorithmic_bytes(off, adj, min_out):
-    """Bytes the local-graph / triangle kernels must read from the DAG for
-    every root u with out-degree >= min_out: u's out-list (4 B per arc), the
-    two offsets of each out-neighbour v (8 B) and v's out-list (4 B per
-    entry).  Returns (bytes, pairs)."""
+def dag_class_bytes(off, adj, dmin, dmax, kmin):
+    """Algorithmic bytes of one triangle/local-graph-build launch over the
+    roots u with dmin < d+(u) <= dmax and d+(u) >= kmin: per root, its
+    out-list (4 B per arc); per out-neighbour v, v's two offsets (8 B) and
+    v's out-list (4 B per entry, the (v, w) pairs)."""
     n = off.shape[0] - 1
     deg = np.diff(off).astype(np.int64)
     rows = np.repeat(np.arange(n, dtype=np.int64), deg)
@@ -42,11 +51,34 @@ def algorithmic_bytes(off, adj, min_out):
     fwd = (deg[rows] < deg[cols]) | ((deg[rows] == deg[cols]) & (rows < cols))
     src, dst = rows[fwd], cols[fwd]
     dout = np.bincount(src, minlength=n)
-    pairs_per_root = np.bincount(src, weights=dout[dst], minlength=n).astype(np.int64)
-    roots = dout >= min_out
-    arcs = int(dout[roots].sum())
-    pairs = int(pairs_per_root[roots].sum())
-    return 4 * arcs + 8 * arcs + 4 * pairs, pairs
+    pairs_root = np.bincount(src, weights=dout[dst], minlength=n).astype(np.int64)
+    sel = (dout > dmin) & (dout <= dmax) & (dout >= kmin) & (pairs_root > 0)
+    arcs = int(dout[sel].sum())
+    pairs = int(pairs_root[sel].sum())
+    return 12 * arcs + 4 * pairs, arcs, pairs
+
+
+def roofline(dom, ms, units, off, adj):
+    if dom.startswith("k_lg5"):
+        ops = OPS_PER_LOCAL_TRIANGLE * units
+        ach = ops / (ms * 1e-3) / 1e12
+        return {"kernel": dom, "bound": "alu", "achieved": ach, "peak": INT32_VALU_PEAK_TOPS,
+                "unit": "TOP/s (int32)", "frac": ach / INT32_VALU_PEAK_TOPS, "traffic": None,
+                "units_per_launch": units, "unit_name": "local triangles",
+                "ops_per_unit": OPS_PER_LOCAL_TRIANGLE, "avg_launch_ms": ms}
+    if dom.startswith("k_tc_flat"):
+        dmin, dmax, kmin = (0, 256, 2) if "<256" in dom else (256, 1024, 2)
+    elif dom.startswith("k_clique_wave"):
+        dmin, dmax, kmin = 0, 64, int(dom.split("<")[1][0]) - 1
+    elif "<256>" in dom or "<256," in dom:
+        dmin, dmax, kmin = 64, 256, 3
+    else:
+        dmin, dmax, kmin = 256, 1024, 3
+    b, arcs, pairs = dag_class_bytes(off, adj, dmin, dmax, kmin)
+    ach = b / (ms * 1e-3) / 1e9
+    return {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "alg_bytes_per_launch": b,
+            "pairs_per_launch": pairs, "device_units": units, "avg_launch_ms": ms}
 
 
 def cpu_baseline(e, fraction_inv, ks, threads):
@@ -62,9 +94,67 @@ def cpu_baseline(e, fraction_inv, ks, threads):
         "unit": "edges/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"roots with (core-order position mod {fraction_inv}) == 0 of the same "
-                  f"rmat{int(np.log2(e.n))} graph, cliques k={list(ks)}; "
-                  f"{dt:.1f} s; rate = (m / {fraction_inv}) / time",
+        "sample": f"cliques k={list(ks)} rooted at every {fraction_inv}-th vertex of the core "
+                  f"order of the same rmat graph ({dt:.1f} s); rate = (m / {fraction_inv}) / time",
+    }
+
+
+def batch_leg(gpm, torch, G, plain_graphs, replays):
+    import graphgen
+    dev = torch.device("cuda:0")
+    batch = graphgen.rgg_batch(G, seed=2020)
+    u = torch.from_numpy(batch.u).to(dev)
+    v = torch.from_numpy(batch.v).to(dev)
+    g = gpm.Graph.build(batch.n, u, v)
+    voff = torch.from_numpy(batch.voff.astype(np.int32)).to(dev)
+    ws = torch.empty(1 << 16, dtype=torch.uint8, device=dev)
+    out = torch.zeros((G, 7), dtype=torch.int64, device=dev)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        gpm.batch_motif_count(g, voff, 4, ws=ws, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gpm.batch_motif_count(g, voff, 4, ws=ws, out=out)
+    graph.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(replays):
+        graph.replay()
+    b.record()
+    torch.cuda.synchronize()
+    batched_ms = a.elapsed_time(b) / replays
+    batched = out.cpu().numpy()
+    # plain: one motif call per graph on graphs built beforehand
+    P = min(plain_graphs, G)
+    graphs = []
+    for i in range(P):
+        e = batch.graph(i)
+        graphs.append(gpm.Graph.build(e.n, torch.from_numpy(e.u).to(dev),
+                                      torch.from_numpy(e.v).to(dev)))
+    wsb = max(gpm.binding.motif_workspace_bytes(gi, 4) for gi in graphs)
+    pws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    pout = torch.zeros((P, 7), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    a.record()
+    for i, gi in enumerate(graphs):
+        gpm.motif_count(gi, 4, ws=pws, out=pout[i])
+    b.record()
+    torch.cuda.synchronize()
+    plain_ms = a.elapsed_time(b)
+    same = bool(np.array_equal(pout.cpu().numpy()[:, :6], batched[:P, :6]))
+    plain_equiv = plain_ms * G / P
+    return {
+        "workload": f"rgg batch G={G} (n uniform in [10, 200], seed 2020), induced 4-motifs",
+        "batched_ms": batched_ms,
+        "graphs_per_sec_batched": G / (batched_ms * 1e-3),
+        "plain_ms_measured": plain_ms, "plain_graphs_measured": P,
+        "plain_ms_for_all": plain_equiv,
+        "speedup": plain_equiv / batched_ms,
+        "plain_equals_batched": same,
+        "batched_status_ok": bool((batched[:, 6] == 0).all()),
     }
 
 
@@ -75,9 +165,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--kmax", type=int, default=5, help="largest clique size counted")
-    ap.add_argument("--cpu-fraction", type=int, default=64,
-                    help="CPU baseline times every F-th root")
+    ap.add_argument("--cpu-fraction", type=int, default=48,
+                    help="the CPU baseline times every F-th root")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=20000)
+    ap.add_argument("--plain-graphs", type=int, default=20000)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -101,10 +194,12 @@ def main():
     ks = list(range(3, args.kmax + 1))
     pats = [gpm.clique(k) for k in ks]
     g0 = gpm.Graph.build(e.n, u, v, storage=storage, scratch=scratch)
+    m = g0.m
+    off_h = g0.csr()[0].cpu().numpy().astype(np.int64)
+    adj_h = g0.csr()[1].cpu().numpy()
     wsb = max(gpm.workspace_bytes(g0, p) for p in pats)
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     out = torch.zeros(len(ks), dtype=torch.int64, device=dev)
-    m = g0.m
     stream = torch.cuda.current_stream()
 
     def step():
@@ -119,7 +214,6 @@ def main():
     gpm.timing_enable(True)
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t_start.record(stream)
     for _ in range(args.steps):
         step()
@@ -127,40 +221,15 @@ def main():
     torch.cuda.synchronize()
     gpm.timing_enable(False)
     spans = gpm.timing_read()
-    ms_total = t_start.elapsed_time(t_end)
-    ms_step = ms_total / args.steps
+    ms_step = t_start.elapsed_time(t_end) / args.steps
     counts = [int(x) for x in out.tolist()]
 
-    phases = {}
-    for name, ms in spans:
+    phases, units = {}, {}
+    for name, ms, un in spans:
         phases[name] = phases.get(name, 0.0) + ms / args.steps
+        units[name] = units.get(name, 0) + un / args.steps
     dom = max((k for k in phases if k != "graph_build"), key=lambda k: phases[k])
-    off_h = g0.csr()[0].cpu().numpy().astype(np.int64)
-    adj_h = g0.csr()[1].cpu().numpy()
-    # algorithmic bytes of the dominant kernel's launch
-    if dom.startswith("k_tc_flat"):
-        dmax = 256 if "256" in dom else 1024
-        dmin = 0 if "256" in dom else 256
-    elif dom.startswith("k_clique_wave"):
-        dmin, dmax = 0, 64
-    elif "lds" in dom:
-        dmin, dmax = 64, 512
-    else:
-        dmin, dmax = 512, 1024
-    kdom = 3 if dom.startswith("k_tc") else int(dom.split("<")[1][0])
-    n = off_h.shape[0] - 1
-    deg = np.diff(off_h)
-    rows = np.repeat(np.arange(n), deg)
-    fwd = (deg[rows] < deg[adj_h]) | ((deg[rows] == deg[adj_h]) & (rows < adj_h))
-    dout = np.bincount(rows[fwd], minlength=n)
-    src, dst = rows[fwd], adj_h[fwd].astype(np.int64)
-    sel = (dout >= max(kdom - 1, 2 if kdom == 3 else kdom - 1)) & (dout > dmin) & (dout <= dmax)
-    pairs_root = np.bincount(src, weights=dout[dst], minlength=n)
-    arcs = int(dout[sel].sum())
-    pairs = int(pairs_root[sel].sum())
-    alg_bytes = 4 * arcs + 8 * arcs + 4 * pairs
-    dom_ms = phases[dom]
-    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+    roof = roofline(dom, phases[dom], int(units[dom]), off_h, adj_h)
 
     res = {
         "metric": "edges/sec & matches/sec for TC and 4-clique on RMAT-20; batched vs plain speedup",
@@ -176,22 +245,19 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {
-            "workload": f"rmat{args.scale}: device CSR build + degree DAG + "
+            "workload": f"rmat{args.scale}: device CSR build + degree-ordered DAG + "
                         + " + ".join(f"{k}-clique count" for k in ks),
-            "n": e.n, "m": m, "input_edges": int(e.u.shape[0]),
-            "seed": args.scale, "rmat": [0.57, 0.19, 0.19, 0.05],
+            "n": e.n, "m": m, "input_edges": int(e.u.shape[0]), "seed": args.scale,
+            "rmat_abcd": [0.57, 0.19, 0.19, 0.05],
         },
         "counts": {f"clique{k}": c for k, c in zip(ks, counts)},
         "matches_per_sec": sum(counts) / (ms_step * 1e-3),
         "count_phase_edges_per_sec": m / ((ms_step - phases.get("graph_build", 0.0)) * 1e-3),
-        "phases_ms": {k: round(v, 4) for k, v in phases.items()},
-        "roofline": {
-            "kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "alg_bytes_per_launch": alg_bytes, "pairs_per_launch": pairs,
-            "avg_launch_ms": dom_ms,
-        },
+        "phases_ms": {k: round(x, 4) for k, x in phases.items()},
+        "roofline": roof,
     }
+    if not args.no_batch:
+        res["batched_vs_plain"] = batch_leg(gpm, torch, args.batch_graphs, args.plain_graphs, 20)
     if not args.no_cpu_baseline:
         threads = len(os.sched_getaffinity(0))
         res["cpu_baseline"] = cpu_baseline(e, args.cpu_fraction, ks, threads)

@@ -264,10 +264,13 @@ void gpm_server_destroy(gpm_server *s);
  * brackets each of its main kernels with HIP events recorded on the launch
  * stream.  Switch it off for production and for graph capture. */
 gpm_status gpm_timing_enable(int32_t on);
-/* Waits for the recorded events, writes up to cap (name, milliseconds)
- * pairs in launch order (names stay valid until the next call), clears the
- * record, and returns the number of spans recorded (may exceed cap). */
-int32_t gpm_timing_read(const char **names, float *ms, int32_t cap);
+/* Waits for the recorded events, writes up to cap (name, milliseconds, work
+ * units) triples in launch order (names stay valid until the next call;
+ * units is 0 for kernels that report none, and any pointer may be NULL),
+ * clears the record, and returns the number of spans recorded (may exceed
+ * cap).  Work units, where reported, are counted on the device:
+ * k_tc_flat* = (v, w) pairs tested, k_lg5* = local triangles expanded. */
+int32_t gpm_timing_read(const char **names, float *ms, uint64_t *units, int32_t cap);
 
 #ifdef __cplusplus
 }

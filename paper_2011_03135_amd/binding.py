@@ -76,7 +76,7 @@ def load():
         "gpm_batch_workspace_bytes": ([i32, i32, P], i32),
         "gpm_batch_motif_count": ([P, P, i32, i32, P, u64, P, P], i32),
         "gpm_timing_enable": ([i32], i32),
-        "gpm_timing_read": ([P, P, i32], i32),
+        "gpm_timing_read": ([P, P, P, i32], i32),
         "gpm_server_create": ([P, P], i32),
         "gpm_server_submit": ([P, P, P], i32),
         "gpm_server_poll": ([P, P, i32, P], i32),
@@ -219,11 +219,12 @@ def timing_enable(on=True):
 
 
 def timing_read(cap=4096):
-    """gpm_timing_read -> list of (kernel name, milliseconds) in launch order."""
+    """gpm_timing_read -> list of (kernel name, milliseconds, work units)."""
     names = (ctypes.c_char_p * cap)()
     ms = (ctypes.c_float * cap)()
-    k = load().gpm_timing_read(names, ms, cap)
-    return [(names[i].decode(), float(ms[i])) for i in range(min(k, cap))]
+    units = (ctypes.c_uint64 * cap)()
+    k = load().gpm_timing_read(names, ms, units, cap)
+    return [(names[i].decode(), float(ms[i]), int(units[i])) for i in range(min(k, cap))]
 
 
 def workspace_bytes(g, p):
@@ -257,6 +258,12 @@ def list_embeddings(g, p, cap, stream=None, ws=None):
                            _ptr(res), _stream(stream)))
     total, written, chk = (_u64(x) for x in res.tolist())
     return total, written, chk, buf[:written]
+
+
+def motif_workspace_bytes(g, k):
+    b = ctypes.c_uint64()
+    _check(load().gpm_motif_workspace_bytes(g.handle, int(k), ctypes.byref(b)))
+    return b.value
 
 
 def motif_count(g, k, stream=None, ws=None, out=None):

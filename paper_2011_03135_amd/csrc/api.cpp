@@ -88,8 +88,8 @@ gpm_status gpm_timing_enable(int32_t on) {
     return GPM_OK;
 }
 
-int32_t gpm_timing_read(const char **names, float *ms, int32_t cap) {
-    return gpm::timing_read(names, ms, cap < 0 ? 0 : cap);
+int32_t gpm_timing_read(const char **names, float *ms, uint64_t *units, int32_t cap) {
+    return gpm::timing_read(names, ms, units, cap < 0 ? 0 : cap);
 }
 
 gpm_status gpm_pattern_from_edges(int32_t k, int32_t n_edges, const int32_t *uv, uint32_t flags,

@@ -130,13 +130,14 @@ __global__ void k_compact_roots(const int32_t *cls, const int32_t *pos, const in
 // Chunk map of a flattened pair space: chunk c starts inside active root a
 // iff wpre[a] <= c*tau < wpre[a+1]; first[c] = a.
 __global__ void k_chunk_map(const int64_t *wpre, const int32_t *pos_total, int64_t tau,
-                            int32_t *first, uint32_t *ctl) {
+                            int32_t *first, uint32_t *ctl, unsigned long long *total_pairs) {
     const int32_t nact = *pos_total;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if (i == 0) {
         ctl[0] = (uint32_t)nact;
         ctl[1] = (uint32_t)((wpre[nact] + tau - 1) / tau);
+        *total_pairs = (unsigned long long)wpre[nact];
     }
     for (; i < nact; i += stride) {
         int64_t c0 = (wpre[i] + tau - 1) / tau, c1 = (wpre[i + 1] + tau - 1) / tau;
@@ -606,18 +607,20 @@ static gpm_status tc_launch(const gpm_graph *g, CliqueWs &W, unsigned long long 
                        g->dag_adj, n, 2, kSmallMax, kTcMax, kTcMax, W.work, W.cls);
     GPM_LAUNCH_CHECK("k_root_work");
     GPM_HIP(build_class(g, W, RC_SMALL, W.list_s, W.wpre_s, st));
+    // W.result[2], [3]: pairs of each class (work units of the timing spans)
     hipLaunchKernelGGL(k_chunk_map, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.wpre_s,
-                       W.pos + n, kTcTau, W.first_s, W.ctl + 2);
+                       W.pos + n, kTcTau, W.first_s, W.ctl + 2, W.result + 2);
     GPM_LAUNCH_CHECK("k_chunk_map");
     GPM_HIP(build_class(g, W, RC_MID, W.list_m, W.wpre_m, st));
     hipLaunchKernelGGL(k_chunk_map, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.wpre_m,
-                       W.pos + n, kTcTau, W.first_m, W.ctl + 4);
+                       W.pos + n, kTcTau, W.first_m, W.ctl + 4, W.result + 3);
     GPM_LAUNCH_CHECK("k_chunk_map");
     {
         Span sp(MODE == TC_COUNT ? "k_tc_flat<1024>" : "k_tc_flat<1024,arcs>", st);
         hipLaunchKernelGGL((k_tc_flat<kTcMax, MODE>), dim3((unsigned)persistent_blocks(kWPB, 3)),
                            dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_m, W.wpre_m,
                            W.first_m, W.ctl + 4, W.ctl + 1, kTcTau, res, te, toff, tl);
+        span_units(W.result + 3, st);
     }
     GPM_LAUNCH_CHECK("k_tc_flat<1024>");
     {
@@ -625,6 +628,7 @@ static gpm_status tc_launch(const gpm_graph *g, CliqueWs &W, unsigned long long 
         hipLaunchKernelGGL((k_tc_flat<kSmallMax, MODE>), dim3((unsigned)persistent_blocks(kWPB, 8)),
                            dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_s, W.wpre_s,
                            W.first_s, W.ctl + 2, W.ctl + 0, kTcTau, res, te, toff, tl);
+        span_units(W.result + 2, st);
     }
     GPM_LAUNCH_CHECK("k_tc_flat<256>");
     return GPM_OK;

@@ -79,7 +79,10 @@ hipError_t exclusive_scan_64(const int64_t *in, int64_t *out, uint64_t n, int64_
 // bracket a launch with HIP events recorded on its stream.
 bool timing_on();
 void timing_set(bool on);
-int timing_read(const char **names, float *ms, int cap);
+int timing_read(const char **names, float *ms, uint64_t *units, int cap);
+// Attaches work units (a device uint64, copied when this is called, in
+// stream order) to the innermost open span; no-op when timing is off.
+void span_units(const unsigned long long *d_units, hipStream_t s);
 void span_begin(const char *name, hipStream_t s);
 void span_end(hipStream_t s);
 struct Span {

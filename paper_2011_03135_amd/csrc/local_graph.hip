@@ -32,8 +32,14 @@ constexpr int kMidMaxD = 256;
 constexpr int kBigMaxD = 1024;
 constexpr int kMidThreads = 256;
 constexpr int kBigThreads = 1024;
-constexpr uint64_t kSlice5 = 1 << 20;  // word-steps of counting work per slice
+constexpr uint64_t kSlice5 = 1 << 20;  // local triangles per 5-clique slice
 constexpr int32_t kMaxSlices = 1024;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ __forceinline__ int lower_bound_i32(const int32_t *a, int n, int32_t x) {
     int lo = 0, hi = n;
@@ -207,7 +213,8 @@ __global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ dag
                                                  const int32_t *__restrict__ roots,
                                                  const int32_t *__restrict__ nroots_p,
                                                  uint32_t *cursor, const int64_t *__restrict__ rowoff,
-                                                 uint64_t *grows, int32_t *slices) {
+                                                 uint64_t *grows, int32_t *slices,
+                                                 unsigned long long *units) {
     __shared__ uint64_t rows[DMAX * (DMAX / 64)];
     __shared__ int32_t list[DMAX], base[DMAX], pre[DMAX + 1];
     __shared__ Lds<NT> sh;
@@ -238,8 +245,12 @@ __global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ dag
         if (lane_id() == 0 && tri) atomicAdd((unsigned long long *)&sh.s_tri, (unsigned long long)tri);
         __syncthreads();
         if (tid == 0) {
-            const uint64_t work = sh.s_tri * (uint64_t)W;
-            slices[r] = (int32_t)std::min<uint64_t>(kMaxSlices, 1 + work / kSlice5);
+            // slices over local vertices: about kSlice5 local triangles each,
+            // at least 8 local vertices each
+            const uint64_t s_work = 1 + sh.s_tri / kSlice5;
+            const uint64_t s_cap = (uint64_t)(d / 8 + 1);
+            slices[r] = (int32_t)std::min<uint64_t>(kMaxSlices, std::min(s_work, s_cap));
+            if (sh.s_tri) atomicAdd(units, (unsigned long long)sh.s_tri);
             sh.s_tri = 0;
         }
         __syncthreads();
@@ -259,18 +270,27 @@ __global__ void k_lg_words(const int32_t *dag_off, const int32_t *roots, const i
 }
 
 // 5-cliques, step 2: task (root, slice); rows come back from HBM into LDS.
-template <int DMAX, int NT>
-__global__ void __launch_bounds__(NT) k_lg5(const int32_t *__restrict__ dag_off,
-                                            const int32_t *__restrict__ roots,
-                                            const int32_t *__restrict__ toff,
-                                            const int32_t *__restrict__ nroots_p,
-                                            const int64_t *__restrict__ rowoff,
-                                            const uint64_t *__restrict__ grows,
-                                            uint32_t *cursor, unsigned long long *result) {
-    __shared__ uint64_t rows[DMAX * (DMAX / 64)];
-    __shared__ int32_t pre[DMAX + 1];
-    __shared__ Lds<NT> sh;
-    const int tid = threadIdx.x;
+// LDS is dynamic: rows (dmax x ceil(dmax/64) words for the class's largest
+// out-degree), then per wave a re-encoding area of kCands x kCW words.
+constexpr int kCands = 256;    // candidate sets up to this size are re-encoded
+constexpr int kCW = kCands / 64;
+
+template <int DMAX>
+__global__ void __launch_bounds__(1024) k_lg5(const int32_t *__restrict__ dag_off,
+                                              const int32_t *__restrict__ roots,
+                                              const int32_t *__restrict__ toff,
+                                              const int32_t *__restrict__ nroots_p,
+                                              const int64_t *__restrict__ rowoff,
+                                              const uint64_t *__restrict__ grows,
+                                              int32_t rows_words, uint32_t *cursor,
+                                              unsigned long long *result) {
+    constexpr int WMAX = DMAX / 64;
+    extern __shared__ uint64_t dyn[];
+    uint64_t *rows = dyn;
+    __shared__ Lds<1024> sh;
+    const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
+    const int NT = blockDim.x;
+    uint64_t *crow = dyn + rows_words + (int64_t)wib * kCands * kCW;
     const int32_t nroots = *nroots_p;
     const int32_t ntasks = toff[nroots];
     uint64_t acc = 0;
@@ -288,55 +308,111 @@ __global__ void __launch_bounds__(NT) k_lg5(const int32_t *__restrict__ dag_off,
         for (int32_t i = tid; i < d * W; i += NT) rows[i] = src[i];
         if (tid == 0) sh.s_next = 0;
         __syncthreads();
-        const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
-        const int32_t nmine = ne > slice ? (ne - slice + S - 1) / S : 0;
-        constexpr int WMAX = DMAX / 64;
-        uint64_t cand[WMAX];   // row_i & row_j, statically indexed (stays in VGPRs)
-        const uint64_t *ri = rows, *rj = rows;
-        int32_t w = 0;
-        uint64_t cw = 0;
-        bool have = false, done = false;
+        // waves take the slice's local vertices i = slice + S * c; R = row_i
         for (;;) {
-            if (!have && !done) {
-                const int32_t c = (int32_t)atomicAdd(&sh.s_next, 1u);
-                if (c >= nmine) {
-                    done = true;
-                } else {
-                    int32_t i, j;
-                    edge_at(rows, pre, d, W, slice + S * c, i, j);
-                    ri = rows + i * W;
-                    rj = rows + j * W;
+            uint32_t c = 0;
+            if (lane == 0) c = atomicAdd(&sh.s_next, 1u);
+            c = __shfl(c, 0, 64);
+            const int32_t i = slice + S * (int32_t)c;
+            if (i >= d) break;
+            const uint64_t *ri = rows + i * W;
+            int32_t cnt = 0;
+            for (int32_t w = 0; w < W; w++) cnt += __popcll(ri[w]);
+            if (cnt < 3) continue;
+            if (cnt <= kCands) {
+                // member a of R (a-th set bit) gets row_a' = row_j & R re-encoded
+                // over R's members: CW words per row
+                const int32_t CW = (cnt + 63) >> 6;
+                for (int32_t a = lane; a < cnt; a += kWave) {
+                    int32_t w0 = 0, before = 0;
+                    for (;; w0++) {
+                        const int pc = __popcll(ri[w0]);
+                        if (a - before < pc) break;
+                        before += pc;
+                    }
+                    const int32_t j = w0 * 64 + select_bit64(ri[w0], a - before);
+                    const uint64_t *rj = rows + j * W;
+                    uint64_t cr[kCW] = {0, 0, 0, 0};
+                    int32_t base = 0;
+                    for (int32_t w = 0; w < W; w++) {
+                        const uint64_t rw = ri[w];
+                        uint64_t mm = rj[w] & rw;
+                        while (mm) {
+                            const int p = __builtin_ctzll(mm);
+                            mm &= mm - 1;
+                            const int32_t b = base + __popcll(rw & ((1ull << p) - 1));
+#pragma unroll
+                            for (int q = 0; q < kCW; q++)
+                                if ((b >> 6) == q) cr[q] |= 1ull << (b & 63);
+                        }
+                        base += __popcll(rw);
+                    }
+#pragma unroll
+                    for (int q = 0; q < kCW; q++) crow[a * kCW + q] = cr[q];
+                }
+                wave_sync();
+                // triangles of the re-encoded local DAG on R
+                for (int32_t a = lane; a < cnt; a += kWave) {
+                    uint64_t cr[kCW];
+#pragma unroll
+                    for (int q = 0; q < kCW; q++) cr[q] = crow[a * kCW + q];
+#pragma unroll
+                    for (int q = 0; q < kCW; q++) {
+                        if (q >= CW) break;
+                        uint64_t m2 = cr[q];
+                        while (m2) {
+                            const int32_t b = q * 64 + __builtin_ctzll(m2);
+                            m2 &= m2 - 1;
+                            const uint64_t *cb = crow + b * kCW;
+#pragma unroll
+                            for (int x = 0; x < kCW; x++)
+                                if (x < CW) acc += __popcll(cr[x] & cb[x]);
+                        }
+                    }
+                }
+                wave_sync();
+            } else {
+                // wider candidate sets: lane per member j, candidates in VGPRs
+                for (int32_t a0 = 0; a0 < cnt; a0 += kWave) {
+                    const int32_t a = a0 + lane;
+                    if (a >= cnt) continue;
+                    int32_t w0 = 0, before = 0;
+                    for (;; w0++) {
+                        const int pc = __popcll(ri[w0]);
+                        if (a - before < pc) break;
+                        before += pc;
+                    }
+                    const int32_t j = w0 * 64 + select_bit64(ri[w0], a - before);
+                    const uint64_t *rj = rows + j * W;
+                    uint64_t cand[WMAX];
 #pragma unroll
                     for (int x = 0; x < WMAX; x++) cand[x] = x < W ? (ri[x] & rj[x]) : 0ull;
-                    w = 0;
-                    cw = cand[0];
-                    have = true;
-                }
-            }
-            if (__ballot(!done) == 0) break;
-            if (have) {
-                if (cw == 0) {
-                    if (++w >= W) have = false;
-                    else cw = ri[w] & rj[w];
-                } else {
-                    const int32_t l = w * 64 + __builtin_ctzll(cw);
-                    cw &= cw - 1;
-                    const uint64_t *rl = rows + l * W;
 #pragma unroll
-                    for (int x = 0; x < WMAX; x++)
-                        if (x < W) acc += __popcll(cand[x] & rl[x]);
+                    for (int x = 0; x < WMAX; x++) {
+                        if (x >= W) break;
+                        uint64_t cw = cand[x];
+                        while (cw) {
+                            const int32_t l = x * 64 + __builtin_ctzll(cw);
+                            cw &= cw - 1;
+                            const uint64_t *rl = rows + l * W;
+#pragma unroll
+                            for (int y = 0; y < WMAX; y++)
+                                if (y < W) acc += __popcll(cand[y] & rl[y]);
+                        }
+                    }
                 }
             }
         }
         __syncthreads();
     }
     acc = wave_sum(acc);
-    if (lane_id() == 0 && acc) atomicAdd(result, (unsigned long long)acc);
+    if (lane == 0 && acc) atomicAdd(result, (unsigned long long)acc);
 }
 
 struct LgWs {
     uint32_t *ctl;                 // cursors
-    int32_t *words, *eloc_m, *eloc_b, *slices, *toff_m, *toff_b;
+    unsigned long long *units;     // per class: local triangles (5-cliques' work)
+    int32_t *words, *slices, *toff_m, *toff_b;
     int64_t *rowoff_m, *rowoff_b, *scan_tmp;
     uint64_t *rows_m, *rows_b;
     uint64_t bytes;
@@ -347,10 +423,9 @@ LgWs lg_layout(const gpm_graph *g, int32_t k, void *base) {
     Carve c(base, ~0ull);
     const uint64_t n1 = (uint64_t)g->n + 1;
     L.ctl = c.take<uint32_t>(16);
+    L.units = c.take<unsigned long long>(4);
     if (k == 5) {
         L.words = c.take<int32_t>(n1);
-        L.eloc_m = c.take<int32_t>(n1);
-        L.eloc_b = c.take<int32_t>(n1);
         L.slices = c.take<int32_t>(n1);
         L.toff_m = c.take<int32_t>(n1);
         L.toff_b = c.take<int32_t>(n1);
@@ -376,7 +451,7 @@ unsigned grid_for(int64_t items, int per_block, int cap_per_cu) {
 
 template <int DMAX, int NT>
 gpm_status lg5_class(const gpm_graph *g, LgWs &L, const int32_t *list, const int32_t *cnt,
-                     int64_t *rowoff, uint64_t *rows, int32_t *eloc, int32_t *toff,
+                     int64_t *rowoff, uint64_t *rows, unsigned long long *units, int32_t *toff,
                      uint32_t *cursors, unsigned long long *res, hipStream_t st, const char *nb,
                      const char *nc) {
     const int32_t n = g->n;
@@ -390,15 +465,26 @@ gpm_status lg5_class(const gpm_graph *g, LgWs &L, const int32_t *list, const int
         Span sp(nb, st);
         hipLaunchKernelGGL((k_lg_build<DMAX, NT>), dim3((unsigned)cu_count() * (NT <= 256 ? 8 : 1)),
                            dim3(NT), 0, st, g->dag_off, g->dag_adj, list, cnt, cursors + 0,
-                           rowoff, rows, L.slices);
+                           rowoff, rows, L.slices, units);
     }
     GPM_LAUNCH_CHECK("k_lg_build");
     GPM_HIP(exclusive_scan_i32(L.slices, toff, (uint64_t)n, L.scan_tmp, st));
     {
+        // LDS: rows of the class's largest local graph, then per-wave
+        // re-encoding areas; as many waves as fit in 160 KiB (at most 16)
+        const int32_t dmax = std::min<int32_t>(DMAX, std::max(g->max_out_degree, 1));
+        const int32_t rows_words = dmax * ((dmax + 63) / 64);
+        const int64_t lds_cap = 160 * 1024 - 1024;
+        const int64_t per_wave = (int64_t)kCands * kCW * 8;
+        int waves = (int)std::min<int64_t>(DMAX <= 256 ? 4 : 16,
+                                           (lds_cap - (int64_t)rows_words * 8) / per_wave);
+        if (waves < 1) return fail(GPM_DEVICE_ERROR, "local graph does not fit in LDS");
+        const size_t shmem = (size_t)rows_words * 8 + (size_t)waves * per_wave;
         Span sp(nc, st);
-        hipLaunchKernelGGL((k_lg5<DMAX, NT>), dim3((unsigned)cu_count() * (NT <= 256 ? 8 : 1)),
-                           dim3(NT), 0, st, g->dag_off, list, toff, cnt, rowoff,
-                           (const uint64_t *)rows, cursors + 1, res);
+        hipLaunchKernelGGL((k_lg5<DMAX>), dim3((unsigned)cu_count() * (DMAX <= 256 ? 4 : 1)),
+                           dim3(waves * kWave), shmem, st, g->dag_off, list, toff, cnt, rowoff,
+                           (const uint64_t *)rows, rows_words, cursors + 1, res);
+        span_units(units, st);
     }
     GPM_LAUNCH_CHECK("k_lg5");
     return GPM_OK;
@@ -420,6 +506,7 @@ gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, cons
     LgWs L = lg_layout(g, k, ws);
     if (L.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "local-graph workspace too small");
     GPM_HIP(fill_u32(L.ctl, 0, 16, st));
+    GPM_HIP(fill_u32(L.units, 0, 8, st));
     if (k == 4) {
         {
             Span sp("k_lg4<1024>", st);
@@ -438,12 +525,12 @@ gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, cons
         return GPM_OK;
     }
     gpm_status rc = lg5_class<kBigMaxD, kBigThreads>(g, L, list_b, cnt_b, L.rowoff_b, L.rows_b,
-                                                     L.eloc_b, L.toff_b, L.ctl + 2, res, st,
+                                                     L.units + 0, L.toff_b, L.ctl + 2, res, st,
                                                      "k_lg_build<1024>", "k_lg5<1024>");
     if (rc) return rc;
-    return lg5_class<kMidMaxD, kMidThreads>(g, L, list_m, cnt_m, L.rowoff_m, L.rows_m, L.eloc_m,
-                                            L.toff_m, L.ctl + 4, res, st, "k_lg_build<256>",
-                                            "k_lg5<256>");
+    return lg5_class<kMidMaxD, kMidThreads>(g, L, list_m, cnt_m, L.rowoff_m, L.rows_m,
+                                            L.units + 1, L.toff_m, L.ctl + 4, res, st,
+                                            "k_lg_build<256>", "k_lg5<256>");
 }
 
 }  // namespace gpm

@@ -161,18 +161,39 @@ namespace {
 struct Rec {
     std::string name;
     hipEvent_t a, b;
+    int unit_slot;   // pinned slot holding the span's work units, or -1
 };
 std::mutex g_tmu;
 bool g_timing = false;
 std::vector<Rec> g_recs;
 std::vector<size_t> g_open;
+constexpr int kUnitSlots = 4096;
+unsigned long long *g_units = nullptr;   // pinned host slots
+int g_units_used = 0;
 }  // namespace
+
+void span_units(const unsigned long long *d_units, hipStream_t s) {
+    std::lock_guard<std::mutex> lock(g_tmu);
+    if (!g_timing || g_open.empty()) return;
+    if (!g_units) {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, sizeof(unsigned long long) * kUnitSlots, hipHostMallocDefault) !=
+            hipSuccess)
+            return;
+        g_units = static_cast<unsigned long long *>(p);
+    }
+    if (g_units_used >= kUnitSlots) return;
+    const int slot = g_units_used++;
+    g_recs[g_open.back()].unit_slot = slot;
+    (void)hipMemcpyAsync(g_units + slot, d_units, sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, s);
+}
 
 bool timing_on() { return g_timing; }
 
 void span_begin(const char *name, hipStream_t s) {
     std::lock_guard<std::mutex> lock(g_tmu);
-    Rec r{name, nullptr, nullptr};
+    Rec r{name, nullptr, nullptr, -1};
     if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
     hipEventRecord(r.a, s);
     g_open.push_back(g_recs.size());
@@ -192,26 +213,28 @@ void timing_set(bool on) {
     g_timing = on;
 }
 
-int timing_read(const char **names, float *ms, int cap) {
+int timing_read(const char **names, float *ms, uint64_t *units, int cap) {
     std::lock_guard<std::mutex> lock(g_tmu);
     static std::vector<std::string> keep;
     keep.clear();
     int k = 0;
     for (auto &r : g_recs) {
         float t = -1.f;
-        if (hipEventSynchronize(r.b) == hipSuccess) hipEventElapsedTime(&t, r.a, r.b);
+        if (hipEventSynchronize(r.b) == hipSuccess) (void)hipEventElapsedTime(&t, r.a, r.b);
         if (k < cap) {
             keep.push_back(r.name);
             if (ms) ms[k] = t;
+            if (units) units[k] = r.unit_slot >= 0 ? g_units[r.unit_slot] : 0;
         }
         k++;
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
     }
     if (names)
         for (int i = 0; i < (int)keep.size(); i++) names[i] = keep[i].c_str();
     g_recs.clear();
     g_open.clear();
+    g_units_used = 0;
     return k;
 }
 

@@ -1,0 +1,85 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/gpm.h declares, and validates arguments on the host."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gpm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(gpm_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2011_03135_amd as gpm
+    return gpm.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 25
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    assert lib.gpm_status_string(0) == b"GPM_OK"
+    assert lib.gpm_status_string(6) == b"GPM_NOT_CANONICAL"
+    assert lib.gpm_version().startswith(b"gpmhip")
+
+
+def test_patterns_and_plans():
+    import paper_2011_03135_amd as gpm
+    from paper_2011_03135_amd.binding import GpmError, Pattern, load
+    plan = ctypes.c_int32()
+    p = gpm.clique(4)
+    assert load().gpm_pattern_plan(ctypes.byref(p), ctypes.byref(plan)) == 0 and plan.value == 1
+    p = gpm.diamond()
+    assert load().gpm_pattern_plan(ctypes.byref(p), ctypes.byref(plan)) == 0 and plan.value == 2
+    p = gpm.cycle4()
+    assert load().gpm_pattern_plan(ctypes.byref(p), ctypes.byref(plan)) == 0 and plan.value == 3
+    # the triangle given as an edge list is a clique (orientation applies)
+    p = gpm.pattern(3, [(0, 1), (0, 2), (1, 2)], gpm.VERTEX_INDUCED)
+    assert load().gpm_pattern_plan(ctypes.byref(p), ctypes.byref(plan)) == 0 and plan.value == 1
+    # a vertex-induced diamond, a 4-path: not planned
+    for pat in (gpm.diamond(gpm.VERTEX_INDUCED), gpm.pattern(4, [(0, 1), (1, 2), (2, 3)],
+                                                              gpm.EDGE_INDUCED)):
+        assert load().gpm_pattern_plan(ctypes.byref(pat), ctypes.byref(plan)) == 5
+    with pytest.raises(GpmError):
+        gpm.pattern(4, [(0, 1), (2, 3)], gpm.EDGE_INDUCED)            # disconnected
+    with pytest.raises(GpmError):
+        gpm.pattern(3, [(0, 1), (0, 1), (1, 2)], gpm.EDGE_INDUCED)    # repeated edge
+    with pytest.raises(GpmError):
+        gpm.pattern(3, [(0, 0), (1, 2)], gpm.EDGE_INDUCED)            # loop
+    with pytest.raises(GpmError):
+        gpm.clique(3, gpm.VERTEX_INDUCED | gpm.EDGE_INDUCED)          # both flags
+    with pytest.raises(GpmError):
+        gpm.clique(9)                                                 # too large
+    assert isinstance(Pattern(), ctypes.Structure)
+
+
+def test_build_sizes_and_limits():
+    import paper_2011_03135_amd as gpm
+    from paper_2011_03135_amd.binding import GpmError
+    gb, sb = gpm.Graph.build_bytes(1000, 5000)
+    assert gb >= 4 * (2 * 1001 + 4 * 5000) and sb > 0
+    with pytest.raises(GpmError):
+        gpm.Graph.build_bytes(0, 10)
+    with pytest.raises(GpmError) as ei:
+        gpm.Graph.build_bytes(10, 1 << 31)
+    assert ei.value.status == 5
+
+
+def test_null_arguments_rejected(lib):
+    assert lib.gpm_count(None, None, None, 0, None, None) == 1
+    assert lib.gpm_motif_count(None, 4, None, 0, None, None) == 1
+    assert lib.gpm_graph_get_info(None, None) == 1
+    assert b"NULL" in lib.gpm_last_error() or lib.gpm_last_error() != b""
