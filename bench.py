@@ -30,6 +30,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: one 32-bit integer VALU op per lane
 # per clock (a wave64 instruction occupies a 16-lane SIMD for 4 clocks)
@@ -107,16 +111,18 @@ def batch_leg(gpm, torch, G, plain_graphs, replays):
     v = torch.from_numpy(batch.v).to(dev)
     g = gpm.Graph.build(batch.n, u, v)
     voff = torch.from_numpy(batch.voff.astype(np.int32)).to(dev)
-    ws = torch.empty(1 << 16, dtype=torch.uint8, device=dev)
+    ws = torch.empty(gpm.binding.batch_workspace_bytes(G, 4), dtype=torch.uint8, device=dev)
     out = torch.zeros((G, 7), dtype=torch.int64, device=dev)
+    # the autotuner picks team width, tiers and teams per CU on this batch
+    cfg, tuned_ms, _ = gpm.batch_autotune(g, voff, 4, reps=3, ws=ws, out=out)
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
-        gpm.batch_motif_count(g, voff, 4, ws=ws, out=out)
+        gpm.batch_motif_count(g, voff, 4, ws=ws, out=out, config=cfg)
     torch.cuda.current_stream().wait_stream(s)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        gpm.batch_motif_count(g, voff, 4, ws=ws, out=out)
+        gpm.batch_motif_count(g, voff, 4, ws=ws, out=out, config=cfg)
     graph.replay()
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -149,6 +155,7 @@ def batch_leg(gpm, torch, G, plain_graphs, replays):
     return {
         "workload": f"rgg batch G={G} (n uniform in [10, 200], seed 2020), induced 4-motifs",
         "batched_ms": batched_ms,
+        "autotuned_config": cfg.as_dict(), "autotune_ms": tuned_ms,
         "graphs_per_sec_batched": G / (batched_ms * 1e-3),
         "plain_ms_measured": plain_ms, "plain_graphs_measured": P,
         "plain_ms_for_all": plain_equiv,
@@ -156,6 +163,31 @@ def batch_leg(gpm, torch, G, plain_graphs, replays):
         "plain_equals_batched": same,
         "batched_status_ok": bool((batched[:, 6] == 0).all()),
     }
+
+
+def serve_leg(gpm, torch, g20, scale, requests, warmup):
+    """Open-loop serving load: Poisson arrivals at 500 requests/s, each a
+    query drawn uniformly from {TC, 4-clique, 3-motif, 4-motif} on one of 8
+    resident graphs drawn uniformly (RMAT scales 12..18 and the step's
+    scale-20 graph).  Every request recomputes its answer."""
+    import graphgen
+    from paper_2011_03135_amd.serve import run_load
+    dev = torch.device("cuda:0")
+    graphs, names = [], []
+    for s in (12, 13, 14, 15, 16, 17, 18):
+        e = graphgen.rmat(s, seed=s if s == 18 else 1000 + s)
+        graphs.append(gpm.Graph.build(e.n, torch.from_numpy(e.u).to(dev),
+                                      torch.from_numpy(e.v).to(dev)))
+        names.append(f"rmat{s}")
+    graphs.append(g20)
+    names.append(f"rmat{scale}")
+    torch.cuda.synchronize()
+    stats, per = run_load(graphs, rate=500.0, n_requests=requests, n_warmup=warmup, seed=500,
+                          max_slots=4, pool_bytes=48 << 30,
+                          progress=lambda d, t: log(f"serving: {d}/{t} requests done"))
+    stats["graphs"] = names
+    stats["latency"] = "arrival to result visible on the host"
+    return stats
 
 
 def main():
@@ -171,6 +203,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=20000)
     ap.add_argument("--plain-graphs", type=int, default=20000)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=5000)
+    ap.add_argument("--serve-warmup", type=int, default=500)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -256,9 +291,16 @@ def main():
         "phases_ms": {k: round(x, 4) for k, x in phases.items()},
         "roofline": roof,
     }
+    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step")
     if not args.no_batch:
         res["batched_vs_plain"] = batch_leg(gpm, torch, args.batch_graphs, args.plain_graphs, 20)
+    if not args.no_serve:
+        log("serving load")
+        g_res = gpm.Graph.build(e.n, u, v)
+        res["serving"] = serve_leg(gpm, torch, g_res, args.scale, args.serve_requests,
+                                   args.serve_warmup)
     if not args.no_cpu_baseline:
+        log("cpu baseline")
         threads = len(os.sched_getaffinity(0))
         res["cpu_baseline"] = cpu_baseline(e, args.cpu_fraction, ks, threads)
     print(json.dumps(res))

@@ -196,13 +196,58 @@ gpm_status gpm_motif_count(const gpm_graph *g, int32_t k, void *d_ws, uint64_t w
  * streams with vertex ids shifted per graph): graph i owns vertices
  * d_voff[i] .. d_voff[i+1]-1 (device int32[G+1], ascending, d_voff[0] = 0,
  * d_voff[G] = n).  No edge may join two graphs.  Writes d_counts (device
- * uint64[G][k == 3 ? 3 : 7]) row i = gpm_motif_count's output for graph i.
- * Every graph must have at most GPM_BATCH_MAX_VERTICES vertices. */
+ * uint64[G][k == 3 ? 3 : 7]) row i = gpm_motif_count's output for graph i:
+ * the k = 3 or k = 4 induced motif counts (Section 2, motif counting; the
+ * local-count identities of Section 5), then a status word: 0, or an OR of
+ * 1 (an exact division of the identities failed), 64 (the graph has more
+ * than GPM_BATCH_MAX_VERTICES vertices; counts 0), 128 (d_voff[i..i+1] not
+ * an ascending range within [0, n]; counts 0), 256 (an edge leaves the
+ * graph's range).  The workspace (gpm_batch_workspace_bytes, 256-byte
+ * aligned) holds the order in which graphs are mined.  Nothing is
+ * allocated and the host never waits, so the call can be captured in a HIP
+ * graph. */
 #define GPM_BATCH_MAX_VERTICES 1024
 gpm_status gpm_batch_workspace_bytes(int32_t G, int32_t k, uint64_t *bytes);
 gpm_status gpm_batch_motif_count(const gpm_graph *g, const int32_t *d_voff, int32_t G,
                                  int32_t k, void *d_ws, uint64_t ws_bytes,
                                  uint64_t *d_counts, void *stream);
+
+/* How a batch is mined.  Graphs are mined largest first by teams of
+ * threads, one graph per team at a time, each graph's adjacency held as bit
+ * rows in LDS.  Graphs of 257..1024 vertices always go to 256-thread teams;
+ * for graphs of at most 256 vertices:
+ *   team_threads   64, 128 or 256 threads per team;
+ *   tiers          1: one launch sized for 256 vertices; 2: graphs of at
+ *                  most 128 vertices get their own launch with 4x smaller
+ *                  LDS rows; 3: also graphs of at most 64 vertices;
+ *   blocks_per_cu  1..32 resident teams per compute unit requested. */
+typedef struct {
+    int32_t team_threads;
+    int32_t tiers;
+    int32_t blocks_per_cu;
+    int32_t reserved;          /* 0 */
+} gpm_batch_config;
+
+/* The configuration gpm_batch_motif_count uses. */
+gpm_status gpm_batch_default_config(gpm_batch_config *out);
+
+/* gpm_batch_motif_count with an explicit configuration (INVALID_ARGUMENT
+ * if a field is out of range). */
+gpm_status gpm_batch_motif_count_config(const gpm_graph *g, const int32_t *d_voff, int32_t G,
+                                        int32_t k, const gpm_batch_config *cfg, void *d_ws,
+                                        uint64_t ws_bytes, uint64_t *d_counts, void *stream);
+
+/* Autotuner: mines the batch once per candidate configuration (every
+ * combination of team_threads {64, 128, 256}, tiers {1, 2, 3} and
+ * blocks_per_cu {4, 8, 16, 32}) and then `reps` more times timed with HIP
+ * events on `stream`, keeps the fastest, and leaves d_counts as that
+ * configuration computed them (every configuration computes the same
+ * counts).  Blocks the calling thread (it waits for the stream); not for use
+ * under graph capture.  *best_ms (may be NULL) = mean milliseconds per call
+ * of the chosen configuration. */
+gpm_status gpm_batch_autotune(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,
+                              void *d_ws, uint64_t ws_bytes, uint64_t *d_counts, void *stream,
+                              int32_t reps, gpm_batch_config *best, float *best_ms);
 
 /* ---------------------------------------------------------- serving --- */
 

@@ -13,6 +13,9 @@ from .binding import (  # noqa: F401
     GpmError,
     Graph,
     Pattern,
+    BatchConfig,
+    batch_autotune,
+    batch_default_config,
     batch_motif_count,
     clique,
     count,

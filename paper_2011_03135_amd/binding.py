@@ -75,6 +75,9 @@ def load():
         "gpm_motif_count": ([P, i32, P, u64, P, P], i32),
         "gpm_batch_workspace_bytes": ([i32, i32, P], i32),
         "gpm_batch_motif_count": ([P, P, i32, i32, P, u64, P, P], i32),
+        "gpm_batch_default_config": ([P], i32),
+        "gpm_batch_motif_count_config": ([P, P, i32, i32, P, P, u64, P, P], i32),
+        "gpm_batch_autotune": ([P, P, i32, i32, P, u64, P, P, i32, P, P], i32),
         "gpm_timing_enable": ([i32], i32),
         "gpm_timing_read": ([P, P, P, i32], i32),
         "gpm_server_create": ([P, P], i32),
@@ -284,20 +287,65 @@ def motif_count(g, k, stream=None, ws=None, out=None):
     return vals[:-1]
 
 
-def batch_motif_count(g, voff, k, stream=None, ws=None, out=None):
-    """gpm_batch_motif_count -> int64 tensor [G, 3 or 7] (uint64 bits)."""
+class BatchConfig(ctypes.Structure):
+    """gpm_batch_config: team_threads, tiers, blocks_per_cu."""
+    _fields_ = [("team_threads", ctypes.c_int32), ("tiers", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"team_threads": self.team_threads, "tiers": self.tiers,
+                "blocks_per_cu": self.blocks_per_cu}
+
+
+def batch_default_config():
+    c = BatchConfig()
+    _check(load().gpm_batch_default_config(ctypes.byref(c)))
+    return c
+
+
+def batch_workspace_bytes(G, k):
+    b = ctypes.c_uint64()
+    _check(load().gpm_batch_workspace_bytes(int(G), int(k), ctypes.byref(b)))
+    return b.value
+
+
+def _batch_args(g, voff, k, ws, out):
     G = int(voff.shape[0] - 1)
     if voff.dtype != torch.int32 or not voff.is_cuda:
         raise TypeError("voff must be an int32 CUDA tensor")
-    b = ctypes.c_uint64()
-    _check(load().gpm_batch_workspace_bytes(G, int(k), ctypes.byref(b)))
-    if ws is None or ws.numel() < b.value:
-        ws = _buffer(b.value, g.device)
+    need = batch_workspace_bytes(G, k)
+    if ws is None:
+        ws = _buffer(need, g.device)
+    elif ws.numel() < need:
+        raise GpmError(2, f"batch workspace of {ws.numel()} bytes, {need} needed")
     width = 3 if k == 3 else 7
     res = out if out is not None else torch.zeros((G, width), dtype=torch.int64, device=g.device)
-    _check(load().gpm_batch_motif_count(g.handle, _ptr(voff.contiguous()), G, int(k), _ptr(ws),
-                                        ws.numel(), _ptr(res), _stream(stream)))
+    return G, ws, res
+
+
+def batch_motif_count(g, voff, k, stream=None, ws=None, out=None, config=None):
+    """gpm_batch_motif_count (or _config when `config` is given) -> int64
+    tensor [G, 3 or 7] (uint64 bits)."""
+    G, ws, res = _batch_args(g, voff, k, ws, out)
+    if config is None:
+        _check(load().gpm_batch_motif_count(g.handle, _ptr(voff.contiguous()), G, int(k),
+                                            _ptr(ws), ws.numel(), _ptr(res), _stream(stream)))
+    else:
+        _check(load().gpm_batch_motif_count_config(g.handle, _ptr(voff.contiguous()), G, int(k),
+                                                   ctypes.byref(config), _ptr(ws), ws.numel(),
+                                                   _ptr(res), _stream(stream)))
     return res
+
+
+def batch_autotune(g, voff, k, reps=3, stream=None, ws=None, out=None):
+    """gpm_batch_autotune -> (BatchConfig, mean ms per call, counts tensor)."""
+    G, ws, res = _batch_args(g, voff, k, ws, out)
+    best = BatchConfig()
+    ms = ctypes.c_float()
+    _check(load().gpm_batch_autotune(g.handle, _ptr(voff.contiguous()), G, int(k), _ptr(ws),
+                                     ws.numel(), _ptr(res), _stream(stream), int(reps),
+                                     ctypes.byref(best), ctypes.byref(ms)))
+    return best, ms.value, res
 
 
 # ------------------------------------------------------------- serving ---

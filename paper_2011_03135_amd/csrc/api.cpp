@@ -25,8 +25,13 @@ gpm_status sl_run(const gpm_graph *g, int32_t plan, bool list, void *ws, uint64_
                   unsigned long long *d_count, int32_t *d_buf, uint64_t cap,
                   unsigned long long *d_result, hipStream_t st);
 gpm_status batch_workspace_bytes(int32_t G, int32_t k, uint64_t *bytes);
-gpm_status batch_run(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k, void *ws,
-                     uint64_t ws_bytes, unsigned long long *d_counts, hipStream_t st);
+gpm_status batch_default_config(gpm_batch_config *c);
+gpm_status batch_run(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,
+                     const gpm_batch_config *cfg, void *ws, uint64_t ws_bytes,
+                     unsigned long long *d_counts, hipStream_t st);
+gpm_status batch_autotune(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,
+                          void *ws, uint64_t ws_bytes, unsigned long long *d_counts,
+                          hipStream_t st, int32_t reps, gpm_batch_config *best, float *best_ms);
 }  // namespace gpm
 
 using gpm::fail;
@@ -271,18 +276,51 @@ gpm_status gpm_batch_workspace_bytes(int32_t G, int32_t k, uint64_t *bytes) {
     return gpm::batch_workspace_bytes(G, k, bytes);
 }
 
-gpm_status gpm_batch_motif_count(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,
-                                 void *d_ws, uint64_t ws_bytes, uint64_t *d_counts,
-                                 void *stream) {
+static gpm_status check_batch(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,
+                              void *d_ws, uint64_t *d_counts) {
     gpm_status rc = check_graph(g);
     if (rc) return rc;
     if (!d_voff || !d_counts) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
     if (G < 1) return fail(GPM_INVALID_ARGUMENT, "G must be >= 1");
     if (k != 3 && k != 4) return fail(GPM_UNSUPPORTED, "motif size must be 3 or 4");
     if (!d_ws || !aligned256(d_ws)) return fail(GPM_INVALID_ARGUMENT, "workspace NULL or unaligned");
-    return gpm::batch_run(g, d_voff, G, k, d_ws, ws_bytes,
+    return GPM_OK;
+}
+
+gpm_status gpm_batch_default_config(gpm_batch_config *out) {
+    if (!out) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    return gpm::batch_default_config(out);
+}
+
+gpm_status gpm_batch_motif_count_config(const gpm_graph *g, const int32_t *d_voff, int32_t G,
+                                        int32_t k, const gpm_batch_config *cfg, void *d_ws,
+                                        uint64_t ws_bytes, uint64_t *d_counts, void *stream) {
+    gpm_status rc = check_batch(g, d_voff, G, k, d_ws, d_counts);
+    if (rc) return rc;
+    if (!cfg) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    return gpm::batch_run(g, d_voff, G, k, cfg, d_ws, ws_bytes,
                           reinterpret_cast<unsigned long long *>(d_counts),
                           static_cast<hipStream_t>(stream));
+}
+
+gpm_status gpm_batch_motif_count(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,
+                                 void *d_ws, uint64_t ws_bytes, uint64_t *d_counts,
+                                 void *stream) {
+    gpm_batch_config cfg;
+    gpm::batch_default_config(&cfg);
+    return gpm_batch_motif_count_config(g, d_voff, G, k, &cfg, d_ws, ws_bytes, d_counts, stream);
+}
+
+gpm_status gpm_batch_autotune(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,
+                              void *d_ws, uint64_t ws_bytes, uint64_t *d_counts, void *stream,
+                              int32_t reps, gpm_batch_config *best, float *best_ms) {
+    gpm_status rc = check_batch(g, d_voff, G, k, d_ws, d_counts);
+    if (rc) return rc;
+    if (!best) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    if (reps < 1) return fail(GPM_INVALID_ARGUMENT, "reps must be >= 1");
+    return gpm::batch_autotune(g, d_voff, G, k, d_ws, ws_bytes,
+                               reinterpret_cast<unsigned long long *>(d_counts),
+                               static_cast<hipStream_t>(stream), reps, best, best_ms);
 }
 
 }  // extern "C"

@@ -1,10 +1,11 @@
-// Batched 3- and 4-motif counting of many small graphs in one launch.
+// Batched 3- and 4-motif counting of many small graphs in one pass.
 //
 // The G graphs are one union graph g whose graph i owns vertices
-// voff[i] .. voff[i+1]-1.  A persistent grid of teams (one workgroup per
-// graph at a time, graphs popped from an atomic cursor) computes every step
-// of the motif path for its graph entirely on chip: the graph's adjacency
-// becomes bit rows in LDS (row v = neighbours of v, ceil(n/64) words), and
+// voff[i] .. voff[i+1]-1.  Teams of threads (one workgroup per graph at a
+// time, graphs popped from an atomic cursor) compute every step of the motif
+// path for their graph entirely on chip: the graph's offsets are staged in
+// LDS, its adjacency becomes bit rows in LDS (row v = neighbours of v,
+// ceil(n/64) words), and
 //   degrees             d_v = |A_v|
 //   per-edge triangles  T_uv = |A_u & A_v|               (Section 5)
 //   local-count sums    the four per-edge sums of the motif path
@@ -14,9 +15,19 @@
 //                       opposite vertex z; the middles lie below x)
 // are combined into the induced counts with the same exact identities as the
 // single-graph path, and written to the graph's row of the output.
+//
+// Scheduling.  A counting sort orders the graphs by vertex count, largest
+// first (longest job first, so the last teams to finish hold the smallest
+// graphs).  The sorted order is cut into tiers by row width (graphs of at
+// most 64, 128, 256 and 1024 vertices); each tier is one persistent launch
+// whose LDS is sized for its widest graph, so narrow graphs are not held to
+// the occupancy of wide ones.  Team width, the tiers used below 256 vertices
+// and the teams per compute unit are run-time choices (gpm_batch_config);
+// gpm_batch_autotune times the candidates on the caller's batch.
 #include "gpm_internal.h"
 
 #include <algorithm>
+#include <vector>
 
 namespace gpm {
 
@@ -24,10 +35,9 @@ namespace {
 
 typedef unsigned __int128 u128;
 
-constexpr int kSmallN = 256;    // one wave per graph
-constexpr int kSmallNT = 64;
-constexpr int kLargeN = GPM_BATCH_MAX_VERTICES;   // one 256-thread workgroup per graph
+constexpr int kMaxN = GPM_BATCH_MAX_VERTICES;
 constexpr int kLargeNT = 256;
+constexpr int kHist = kMaxN + 1;   // vertex counts 0 .. kMaxN
 
 enum BatchFlags : unsigned long long {
     B_DIVISION = 1,       // an exact division of the combining identities failed
@@ -36,32 +46,35 @@ enum BatchFlags : unsigned long long {
     B_CROSS_EDGE = 256,   // an edge leaves the graph's vertex range
 };
 
+// Workspace (int32 words): hist[kHist], gt[kHist + 1] (gt[b] = number of
+// sortable graphs with more than b vertices, b <= kMaxN; gt[kHist] = number
+// of sortable graphs), cur[kHist] (scatter cursors), tier cursors[8],
+// order[G] (sortable graphs by vertex count, descending).
+struct BatchWs {
+    int32_t *hist, *gt, *cur;
+    uint32_t *tcur;
+    int32_t *order;
+};
+
+constexpr int64_t kWsHead = 3 * (int64_t)kHist + 1 + 8;
+
+BatchWs batch_ws(void *ws) {
+    int32_t *w = static_cast<int32_t *>(ws);
+    BatchWs b;
+    b.hist = w;
+    b.gt = w + kHist;
+    b.cur = w + 2 * kHist + 1;
+    b.tcur = reinterpret_cast<uint32_t *>(w + 3 * kHist + 1);
+    b.order = w + kWsHead;
+    return b;
+}
+
 __device__ __forceinline__ uint64_t below_mask(int32_t x, int32_t w) {
     // bits < x within word w
     const int32_t lo = w * 64;
     if (x <= lo) return 0ull;
     if (x >= lo + 64) return ~0ull;
     return (1ull << (x - lo)) - 1ull;
-}
-
-template <int NMAX, int NT>
-struct BatchLds {
-    static constexpr int W = NMAX / 64;
-    uint64_t rows[NMAX * W];
-    int32_t deg[NMAX];
-    unsigned long long part[NT / kWave][8];
-    unsigned long long flags;
-    uint32_t task;
-};
-
-template <int NMAX, int NT>
-__device__ unsigned long long block_sum(BatchLds<NMAX, NT> &sh, unsigned long long x, int slot) {
-    x = wave_sum(x);
-    if (lane_id() == 0) sh.part[threadIdx.x / kWave][slot] = x;
-    __syncthreads();
-    unsigned long long s = 0;
-    for (int q = 0; q < NT / kWave; q++) s += sh.part[q][slot];
-    return s;
 }
 
 // Exact combination (one thread); flags |= B_DIVISION on a failed check.
@@ -91,63 +104,140 @@ __device__ void combine(int32_t k, u128 wedge, u128 tri, u128 k4, u128 s1, u128 
     out[6] = bad;
 }
 
-template <int NMAX, int NT, bool STATIC>
+// ------------------------------------------------------------ ordering ---
+
+// Per graph: flags graphs no tier can take (their rows are written here) and
+// histograms the vertex counts of the others.
+__global__ void k_batch_hist(const int32_t *__restrict__ voff, int32_t G, int32_t n, int32_t k,
+                             int32_t *hist, unsigned long long *counts) {
+    const int width = k == 3 ? 3 : 7;
+    for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < G;
+         gi += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v0 = voff[gi], v1 = voff[gi + 1];
+        unsigned long long bad = 0;
+        if (v0 < 0 || v1 < v0 || v1 > n) bad = B_BAD_RANGE;
+        else if (v1 - v0 > kMaxN) bad = B_TOO_LARGE;
+        if (bad) {
+            unsigned long long *out = counts + gi * width;
+            for (int q = 0; q < width - 1; q++) out[q] = 0;
+            out[width - 1] = bad;
+        } else {
+            atomicAdd(&hist[v1 - v0], 1);
+        }
+    }
+}
+
+// One wave: gt[b] = sum of hist[b'] over b' > b; cur = gt (scatter cursors);
+// gt[kHist] = total.  Lane l owns the reversed indices r = l*kPer ..
+// (l+1)*kPer - 1 (b = kMaxN - r).
+__global__ void __launch_bounds__(kWave) k_batch_scan(const int32_t *hist, int32_t *gt,
+                                                      int32_t *cur) {
+    constexpr int kPer = (kHist + kWave - 1) / kWave;
+    const int l = lane_id();
+    int32_t loc[kPer];
+    int32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; i++) {
+        const int r = l * kPer + i;
+        loc[i] = r < kHist ? hist[kMaxN - r] : 0;
+        s += loc[i];
+    }
+    int32_t before = wave_incl_scan(s) - s;
+#pragma unroll
+    for (int i = 0; i < kPer; i++) {
+        const int r = l * kPer + i;
+        if (r < kHist) {
+            gt[kMaxN - r] = before;   // graphs with more than b vertices
+            cur[kMaxN - r] = before;
+        }
+        before += loc[i];
+    }
+    if (l == kWave - 1) gt[kHist] = before;
+}
+
+__global__ void k_batch_scatter(const int32_t *__restrict__ voff, int32_t G, int32_t n,
+                                int32_t *cur, int32_t *order) {
+    for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < G;
+         gi += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v0 = voff[gi], v1 = voff[gi + 1];
+        if (v0 < 0 || v1 < v0 || v1 > n || v1 - v0 > kMaxN) continue;
+        order[atomicAdd(&cur[v1 - v0], 1)] = (int32_t)gi;
+    }
+}
+
+// ------------------------------------------------------------- mining ---
+
+template <int NMAX, int NT>
+struct BatchLds {
+    static constexpr int W = NMAX / 64;
+    uint64_t rows[NMAX * W];
+    int32_t deg[NMAX];
+    int32_t off[NMAX + 1];   // arc offsets relative to the graph's first arc
+    unsigned long long part[NT / kWave][8];
+    unsigned long long flags;
+    uint32_t task;
+};
+
+template <int NMAX, int NT>
+__device__ unsigned long long block_sum(BatchLds<NMAX, NT> &sh, unsigned long long x, int slot) {
+    x = wave_sum(x);
+    if (lane_id() == 0) sh.part[threadIdx.x / kWave][slot] = x;
+    __syncthreads();
+    unsigned long long s = 0;
+    for (int q = 0; q < NT / kWave; q++) s += sh.part[q][slot];
+    return s;
+}
+
+// Vertex owning relative arc r: the last i in [0, ng) with off[i] <= r.
+__device__ __forceinline__ int32_t arc_owner(const int32_t *off, int32_t ng, int32_t r) {
+    int32_t lo = 0, hi = ng;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= r) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Mines the graphs at sorted positions gt[hi_b] .. gt[lo_b]-1, i.e. those
+// with lo_b < n_g <= hi_b (lo_b = -1: through the end of the order).
+template <int NMAX, int NT>
 __global__ void __launch_bounds__(NT) k_batch(const int32_t *__restrict__ off,
                                               const int32_t *__restrict__ adj,
-                                              const int32_t *__restrict__ voff, int32_t G,
-                                              int32_t n, int32_t k, int32_t nmin,
-                                              uint32_t *cursor, unsigned long long *counts) {
+                                              const int32_t *__restrict__ voff,
+                                              const int32_t *__restrict__ order,
+                                              const int32_t *__restrict__ gt, int32_t lo_b,
+                                              int32_t k, uint32_t *cursor,
+                                              unsigned long long *counts) {
     constexpr int W = NMAX / 64;
     __shared__ BatchLds<NMAX, NT> sh;
     const int tid = threadIdx.x;
     const int width = k == 3 ? 3 : 7;
-    uint32_t gi = STATIC ? blockIdx.x : 0;
+    const int32_t p_begin = gt[NMAX];
+    const int32_t p_end = gt[lo_b < 0 ? kHist : lo_b];
     for (;;) {
-        if (!STATIC) {
-            if (tid == 0) sh.task = atomicAdd(cursor, 1u);
-            __syncthreads();
-            gi = sh.task;
-            __syncthreads();
-        }
-        if ((int32_t)gi >= G) break;
-        const int32_t v0 = voff[gi], v1 = voff[gi + 1];
+        if (tid == 0) sh.task = atomicAdd(cursor, 1u);
+        __syncthreads();
+        const int32_t p = p_begin + (int32_t)sh.task;
+        __syncthreads();
+        if (p >= p_end) break;
+        const int32_t gi = order[p];
+        const int32_t v0 = voff[gi], ng = voff[gi + 1] - v0;
         unsigned long long *out = counts + (int64_t)gi * width;
-        const bool bad_range = v0 < 0 || v1 < v0 || v1 > n;
-        const int32_t ng = bad_range ? 0 : v1 - v0;
-        const bool mine = !bad_range && ng > nmin && ng <= NMAX;
-        if (!mine) {
-            // the atomic-cursor kernel (every graph passes through it) reports
-            // graphs that no kernel can take
-            if (!bad_range && ng > kLargeN && tid == 0 && !STATIC) {
-                for (int q = 0; q < width; q++) out[q] = 0;
-                out[width - 1] = B_TOO_LARGE;
-            }
-            if (bad_range && tid == 0 && !STATIC) {
-                for (int q = 0; q < width; q++) out[q] = 0;
-                out[width - 1] = B_BAD_RANGE;
-            }
-            gi += STATIC ? gridDim.x : 0;
-            continue;
-        }
         const int32_t Wg = (ng + 63) >> 6;
+        const int32_t a0 = off[v0];
         for (int32_t i = tid; i < ng * W; i += NT) sh.rows[i] = 0ull;
+        for (int32_t i = tid; i <= ng; i += NT) sh.off[i] = off[v0 + i] - a0;
         if (tid == 0) sh.flags = 0;
         __syncthreads();
-        const int32_t a0 = off[v0], a1 = off[v1];
-        for (int32_t e = a0 + tid; e < a1; e += NT) {
-            // row owner of arc e: binary search over the graph's offsets
-            int32_t lo = v0, hi = v1;
-            while (hi - lo > 1) {
-                const int32_t mid = (lo + hi) >> 1;
-                if (off[mid] <= e) lo = mid; else hi = mid;
-            }
-            const int32_t w = adj[e];
-            if (w < v0 || w >= v1) {
+        const int32_t na = sh.off[ng];
+        for (int32_t r = tid; r < na; r += NT) {
+            const int32_t w = adj[a0 + r] - v0;
+            if (w < 0 || w >= ng) {
                 atomicOr(&sh.flags, (unsigned long long)B_CROSS_EDGE);
                 continue;
             }
-            const int32_t u = lo - v0, x = w - v0;
-            atomicOr((unsigned long long *)&sh.rows[u * W + (x >> 6)], 1ull << (x & 63));
+            const int32_t u = arc_owner(sh.off, ng, r);
+            atomicOr((unsigned long long *)&sh.rows[u * W + (w >> 6)], 1ull << (w & 63));
         }
         __syncthreads();
         unsigned long long wedge = 0;
@@ -159,16 +249,11 @@ __global__ void __launch_bounds__(NT) k_batch(const int32_t *__restrict__ off,
         }
         __syncthreads();
         unsigned long long tri3 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, k4 = 0, c4 = 0;
-        // edges u < v, one per thread
-        for (int32_t e = a0 + tid; e < a1; e += NT) {
-            int32_t lo = v0, hi = v1;
-            while (hi - lo > 1) {
-                const int32_t mid = (lo + hi) >> 1;
-                if (off[mid] <= e) lo = mid; else hi = mid;
-            }
-            const int32_t w = adj[e];
-            if (w < v0 || w >= v1) continue;
-            const int32_t u = lo - v0, v = w - v0;
+        // edges u < v, one arc per thread
+        for (int32_t r = tid; r < na; r += NT) {
+            const int32_t v = adj[a0 + r] - v0;
+            if (v < 0 || v >= ng) continue;
+            const int32_t u = arc_owner(sh.off, ng, r);
             if (!(u < v)) continue;
             const uint64_t *ru = sh.rows + u * W, *rv = sh.rows + v * W;
             uint64_t t = 0;
@@ -187,24 +272,24 @@ __global__ void __launch_bounds__(NT) k_batch(const int32_t *__restrict__ off,
                         const int32_t x = q * 64 + __builtin_ctzll(c);
                         c &= c - 1;
                         const uint64_t *rx = sh.rows + x * W;
-                        for (int32_t r = x >> 6; r < Wg; r++)
-                            k4 += __popcll(ru[r] & rv[r] & rx[r] & ~below_mask(x + 1, r));
+                        for (int32_t r2 = x >> 6; r2 < Wg; r2++)
+                            k4 += __popcll(ru[r2] & rv[r2] & rx[r2] & ~below_mask(x + 1, r2));
                     }
                 }
             }
         }
         if (k == 4) {
-            // 4-cycles from their largest vertex x and opposite vertex z < x
-            const int64_t npairs = (int64_t)ng * (ng - 1) / 2;
-            for (int64_t p = tid; p < npairs; p += NT) {
-                int64_t x = (int64_t)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
-                while (x * (x - 1) / 2 > p) x--;
-                while ((x + 1) * x / 2 <= p) x++;
-                const int32_t z = (int32_t)(p - x * (x - 1) / 2);
+            // 4-cycles from their largest vertex x and opposite vertex z < x;
+            // pair p = x(x-1)/2 + z, p < 2^19, so the float root is within 1
+            const int32_t npairs = ng * (ng - 1) / 2;
+            for (int32_t p2 = tid; p2 < npairs; p2 += NT) {
+                int32_t x = (int32_t)((1.0f + sqrtf(1.0f + 8.0f * (float)p2)) * 0.5f);
+                while (x * (x - 1) / 2 > p2) x--;
+                while ((x + 1) * x / 2 <= p2) x++;
+                const int32_t z = p2 - x * (x - 1) / 2;
                 const uint64_t *rx = sh.rows + x * W, *rz = sh.rows + z * W;
                 uint64_t c = 0;
-                for (int32_t q = 0; q < Wg; q++)
-                    c += __popcll(rx[q] & rz[q] & below_mask((int32_t)x, q));
+                for (int32_t q = 0; q < Wg; q++) c += __popcll(rx[q] & rz[q] & below_mask(x, q));
                 c4 += c * (c - (c > 0)) / 2;
             }
         }
@@ -219,41 +304,145 @@ __global__ void __launch_bounds__(NT) k_batch(const int32_t *__restrict__ off,
             combine(k, W_, T3 / 3, K4, S1, S2, S3, S4, C4, fl, out);
         }
         __syncthreads();
-        gi += STATIC ? gridDim.x : 0;
     }
+}
+
+template <int NMAX, int NT>
+void launch_tier(const gpm_graph *g, const int32_t *voff, const BatchWs &b, int32_t lo_b,
+                 int32_t k, uint32_t *cursor, int blocks, unsigned long long *counts,
+                 hipStream_t st) {
+    hipLaunchKernelGGL((k_batch<NMAX, NT>), dim3((unsigned)blocks), dim3(NT), 0, st, g->off,
+                       g->adj, voff, b.order, b.gt, lo_b, k, cursor, counts);
+}
+
+template <int NMAX>
+void launch_small(int nt, const gpm_graph *g, const int32_t *voff, const BatchWs &b,
+                  int32_t lo_b, int32_t k, uint32_t *cursor, int blocks,
+                  unsigned long long *counts, hipStream_t st) {
+    if (nt == 64) launch_tier<NMAX, 64>(g, voff, b, lo_b, k, cursor, blocks, counts, st);
+    else if (nt == 128) launch_tier<NMAX, 128>(g, voff, b, lo_b, k, cursor, blocks, counts, st);
+    else launch_tier<NMAX, 256>(g, voff, b, lo_b, k, cursor, blocks, counts, st);
 }
 
 }  // namespace
 
-gpm_status batch_workspace_bytes(int32_t G, int32_t k, uint64_t *bytes) {
-    (void)G;
-    (void)k;
-    *bytes = 256;   // one cursor word
+gpm_status batch_default_config(gpm_batch_config *c) {
+    c->team_threads = 64;
+    c->tiers = 3;
+    c->blocks_per_cu = 16;
+    c->reserved = 0;
     return GPM_OK;
 }
 
-gpm_status batch_run(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k, void *ws,
-                     uint64_t ws_bytes, unsigned long long *d_counts, hipStream_t st) {
-    if (ws_bytes < 256) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
-    uint32_t *cursor = static_cast<uint32_t *>(ws);
-    GPM_HIP(fill_u32(cursor, 0, 1, st));
+gpm_status batch_check_config(const gpm_batch_config *c) {
+    if (c->team_threads != 64 && c->team_threads != 128 && c->team_threads != 256)
+        return fail(GPM_INVALID_ARGUMENT, "team_threads must be 64, 128 or 256");
+    if (c->tiers < 1 || c->tiers > 3) return fail(GPM_INVALID_ARGUMENT, "tiers must be 1, 2 or 3");
+    if (c->blocks_per_cu < 1 || c->blocks_per_cu > 32)
+        return fail(GPM_INVALID_ARGUMENT, "blocks_per_cu must be in [1, 32]");
+    return GPM_OK;
+}
+
+gpm_status batch_workspace_bytes(int32_t G, int32_t k, uint64_t *bytes) {
+    (void)k;
+    *bytes = ((uint64_t)(kWsHead + G) * 4 + 255) / 256 * 256;
+    return GPM_OK;
+}
+
+gpm_status batch_run(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,
+                     const gpm_batch_config *cfg, void *ws, uint64_t ws_bytes,
+                     unsigned long long *d_counts, hipStream_t st) {
+    uint64_t need = 0;
+    batch_workspace_bytes(G, k, &need);
+    if (ws_bytes < need) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
+    gpm_status rc = batch_check_config(cfg);
+    if (rc) return rc;
+    const BatchWs b = batch_ws(ws);
+    const int cus = cu_count();
+    const int eblocks = (int)std::min<int64_t>(((int64_t)G + 255) / 256, (int64_t)cus * 8);
     {
-        Span sp("k_batch<256>", st);
-        hipLaunchKernelGGL((k_batch<kSmallN, kSmallNT, false>),
-                           dim3((unsigned)std::min<int64_t>(G, (int64_t)cu_count() * 16)),
-                           dim3(kSmallNT), 0, st, g->off, g->adj, d_voff, G, g->n, k, -1, cursor,
-                           d_counts);
+        Span sp("batch_order", st);
+        GPM_HIP(fill_u32(b.hist, 0, kHist, st));
+        GPM_HIP(fill_u32(b.tcur, 0, 8, st));
+        hipLaunchKernelGGL(k_batch_hist, dim3((unsigned)eblocks), dim3(256), 0, st, d_voff, G,
+                           g->n, k, b.hist, d_counts);
+        hipLaunchKernelGGL(k_batch_scan, dim3(1), dim3(kWave), 0, st, b.hist, b.gt, b.cur);
+        hipLaunchKernelGGL(k_batch_scatter, dim3((unsigned)eblocks), dim3(256), 0, st, d_voff,
+                           G, g->n, b.cur, b.order);
     }
-    GPM_LAUNCH_CHECK("k_batch<256>");
+    GPM_LAUNCH_CHECK("batch_order");
+    // tiers by row width, widest first; each takes (next narrower bound, own bound]
+    const int nt = cfg->team_threads;
+    const int small = (int)std::min<int64_t>(G, (int64_t)cus * cfg->blocks_per_cu);
     {
         Span sp("k_batch<1024>", st);
-        hipLaunchKernelGGL((k_batch<kLargeN, kLargeNT, true>),
-                           dim3((unsigned)std::min<int64_t>(G, (int64_t)cu_count())),
-                           dim3(kLargeNT), 0, st, g->off, g->adj, d_voff, G, g->n, k, kSmallN,
-                           cursor, d_counts);
+        launch_tier<kMaxN, kLargeNT>(g, d_voff, b, 256, k, b.tcur + 0,
+                                     (int)std::min<int64_t>(G, (int64_t)cus), d_counts, st);
     }
     GPM_LAUNCH_CHECK("k_batch<1024>");
+    const int lo256 = cfg->tiers >= 2 ? 128 : -1;
+    {
+        Span sp("k_batch<256>", st);
+        launch_small<256>(nt, g, d_voff, b, lo256, k, b.tcur + 1, small, d_counts, st);
+    }
+    GPM_LAUNCH_CHECK("k_batch<256>");
+    if (cfg->tiers >= 2) {
+        const int lo128 = cfg->tiers >= 3 ? 64 : -1;
+        {
+            Span sp("k_batch<128>", st);
+            launch_small<128>(nt, g, d_voff, b, lo128, k, b.tcur + 2, small, d_counts, st);
+        }
+        GPM_LAUNCH_CHECK("k_batch<128>");
+    }
+    if (cfg->tiers >= 3) {
+        {
+            Span sp("k_batch<64>", st);
+            launch_small<64>(nt, g, d_voff, b, -1, k, b.tcur + 3, small, d_counts, st);
+        }
+        GPM_LAUNCH_CHECK("k_batch<64>");
+    }
     return GPM_OK;
+}
+
+gpm_status batch_autotune(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,
+                          void *ws, uint64_t ws_bytes, unsigned long long *d_counts,
+                          hipStream_t st, int32_t reps, gpm_batch_config *best,
+                          float *best_ms) {
+    std::vector<gpm_batch_config> cands;
+    for (int nt : {64, 128, 256})
+        for (int tiers : {1, 2, 3})
+            for (int bpc : {4, 8, 16, 32}) cands.push_back({nt, tiers, bpc, 0});
+    hipEvent_t e0, e1;
+    GPM_HIP(hipEventCreate(&e0));
+    GPM_HIP(hipEventCreate(&e1));
+    float best_t = -1.0f;
+    gpm_status rc = GPM_OK;
+    for (const gpm_batch_config &c : cands) {
+        rc = batch_run(g, d_voff, G, k, &c, ws, ws_bytes, d_counts, st);   // warm-up
+        if (rc) break;
+        hipEventRecord(e0, st);
+        for (int r = 0; r < reps && !rc; r++)
+            rc = batch_run(g, d_voff, G, k, &c, ws, ws_bytes, d_counts, st);
+        hipEventRecord(e1, st);
+        if (rc) break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = hip_fail(hipGetLastError(), "autotune timing");
+            break;
+        }
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)reps;
+        if (best_t < 0.0f || ms < best_t) {
+            best_t = ms;
+            *best = c;
+        }
+    }
+    if (!rc) rc = batch_run(g, d_voff, G, k, best, ws, ws_bytes, d_counts, st);
+    if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = hip_fail(hipGetLastError(), "autotune");
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (best_ms) *best_ms = best_t;
+    return rc;
 }
 
 }  // namespace gpm

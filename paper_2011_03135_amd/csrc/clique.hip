@@ -316,23 +316,7 @@ __global__ void __launch_bounds__(kBlock) k_clique_wave(const int32_t *__restric
     if (lane == 0 && acc) atomicAdd(result, (unsigned long long)acc);
 }
 
-constexpr int kBlockMaxD = 1024;
 constexpr int kMidMaxD = 256;
-
-// Position of the r-th set bit (0-based) of x; x must have more than r bits.
-__device__ __forceinline__ int select_bit64(uint64_t x, int r) {
-    int pos = 0;
-#pragma unroll
-    for (int s = 32; s > 0; s >>= 1) {
-        const int low = __popcll(x & ((1ull << s) - 1));
-        if (r >= low) {
-            r -= low;
-            x >>= s;
-            pos += s;
-        }
-    }
-    return pos;
-}
 
 // ------------------------------------------------- generic DFS (k <= 8) ---
 

@@ -41,7 +41,6 @@ namespace {
 typedef unsigned __int128 u128;
 
 constexpr int kBlock = 256;
-constexpr int kWPB = kBlock / kWave;
 
 __device__ __forceinline__ u128 wave_sum_u128(u128 x) {
     uint64_t lo = (uint64_t)x, hi = (uint64_t)(x >> 64);

@@ -27,8 +27,9 @@ def percentile(xs, q):
 
 
 def run_load(graphs, rate=500.0, n_requests=5000, n_warmup=500, seed=500, max_slots=4,
-             pool_bytes=16 << 30, queries=QUERIES, server=None):
-    """Returns (stats dict, list of (graph index, query index, response))."""
+             pool_bytes=16 << 30, queries=QUERIES, server=None, progress=None):
+    """Returns (stats dict, list of (graph index, query index, response)).
+    `progress(done, total)` is called after every 500 completions."""
     rng = np.random.default_rng(seed)
     total = n_warmup + n_requests
     gaps = rng.exponential(1.0 / rate, size=total)
@@ -50,6 +51,8 @@ def run_load(graphs, rate=500.0, n_requests=5000, n_warmup=500, seed=500, max_sl
             i += 1
         for r in srv.poll():
             done[r.tag] = r
+            if progress is not None and len(done) % 500 == 0:
+                progress(len(done), total)
         if i < total:
             wait = arrivals[i] - Server.now()
             if wait > 0.0005:
@@ -68,11 +71,13 @@ def run_load(graphs, rate=500.0, n_requests=5000, n_warmup=500, seed=500, max_sl
         "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
         "mean_queue_ms": 1e3 * float(np.mean(qwait)),
         "failed": sum(1 for r in measured if r.status != 0),
-        "max_slots": srv_slots(max_slots, server),
+        "max_slots": max_slots if own else None,
     }
+    by_query = {}
+    for j in range(n_warmup, total):
+        by_query.setdefault(queries[qidx[j]][0], []).append(done[j].t_done - arrivals[j])
+    stats["per_query"] = {name: {"requests": len(xs), "p50_ms": 1e3 * percentile(xs, 50),
+                                 "p99_ms": 1e3 * percentile(xs, 99)}
+                          for name, xs in by_query.items()}
     per = [(int(gidx[j]), int(qidx[j]), done[j]) for j in range(total)]
     return stats, per
-
-
-def srv_slots(max_slots, server):
-    return max_slots if server is None else None

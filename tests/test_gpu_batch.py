@@ -76,7 +76,8 @@ def test_batch_graph_capture_replays(gpm):
     g, voff = union_graph(gpm, batch)
     eager = gpm.batch_motif_count(g, voff, 4).clone()
     out = torch.zeros_like(eager)
-    ws = torch.empty(1 << 16, dtype=torch.uint8, device="cuda")
+    wsb = gpm.binding.batch_workspace_bytes(batch.num_graphs, 4)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -102,3 +103,73 @@ def test_batch_full_workload(gpm):
     want = oracle.batch_motifs(batch, 4)
     assert all(r[-1] == 0 for r in got)
     assert [r[:6] for r in got] == want
+
+
+def tier_parts():
+    """Graphs on both sides of every tier bound (64, 128, 256, 1024 vertices)."""
+    sizes = [1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 700, 1024]
+    parts = []
+    for i, n in enumerate(sizes):
+        p = min(1.0, 8.0 / max(n - 1, 1))
+        parts.append(graphgen.erdos_renyi(n, p, 100 + i))
+    parts.insert(5, graphgen.complete_graph(40))
+    parts.insert(9, graphgen.complete_bipartite(60, 60))
+    return parts
+
+
+def all_configs(gpm):
+    out = []
+    for nt in (64, 128, 256):
+        for tiers in (1, 2, 3):
+            for bpc in (4, 8, 16, 32):
+                out.append(gpm.BatchConfig(nt, tiers, bpc, 0))
+    return out
+
+
+@pytest.fixture(scope="module")
+def tier_batch(gpm):
+    parts = tier_parts()
+    u = graphgen.disjoint_union(parts)
+    voff = np.cumsum([0] + [p.n for p in parts]).astype(np.int32)
+    want = []
+    for p in parts:
+        off, adj = oracle.canonical_csr(p.n, p.u, p.v)
+        want.append(oracle.motif4(off, adj, 8))
+    return build(gpm, u), torch.from_numpy(voff).cuda(), want
+
+
+def test_batch_every_config_matches_oracle(gpm, tier_batch):
+    g, voff, want = tier_batch
+    for cfg in all_configs(gpm):
+        got = unpack(gpm.batch_motif_count(g, voff, 4, config=cfg))
+        assert [r[-1] for r in got] == [0] * len(want), cfg.as_dict()
+        assert [r[:6] for r in got] == want, cfg.as_dict()
+
+
+def test_batch_autotune(gpm, tier_batch):
+    g, voff, want = tier_batch
+    best, ms, out = gpm.batch_autotune(g, voff, 4, reps=2)
+    assert ms > 0
+    assert best.as_dict() in [c.as_dict() for c in all_configs(gpm)]
+    assert [r[:6] for r in unpack(out)] == want
+    # the default configuration is one of the candidates
+    assert gpm.batch_default_config().as_dict() in [c.as_dict() for c in all_configs(gpm)]
+
+
+def test_batch_bad_config_rejected(gpm, tier_batch):
+    g, voff, _ = tier_batch
+    for bad in (gpm.BatchConfig(96, 1, 8, 0), gpm.BatchConfig(64, 4, 8, 0),
+                gpm.BatchConfig(64, 1, 0, 0), gpm.BatchConfig(64, 1, 33, 0)):
+        with pytest.raises(gpm.GpmError):
+            gpm.batch_motif_count(g, voff, 4, config=bad)
+
+
+def test_batch_empty_graphs(gpm):
+    """Graphs with no vertices get zero counts and status 0."""
+    parts = [graphgen.complete_graph(5), graphgen.cycle_graph(7)]
+    u = graphgen.disjoint_union(parts)
+    voff = np.array([0, 0, 5, 5, 5, 12, 12], dtype=np.int32)
+    g = build(gpm, u)
+    got = unpack(gpm.batch_motif_count(g, torch.from_numpy(voff).cuda(), 3))
+    assert got == [[0, 0, 0], [0, 10, 0], [0, 0, 0], [0, 0, 0], [7, 0, 0], [0, 0, 0]]
+
