@@ -8,14 +8,15 @@
 // filtering, Section 4.3).
 //
 // Kernels:
-//   k_tc_flat       triangles.  The work of root u is the list of pairs
-//                   (v, w), v in N+(u), w in N+(v); all pairs of all roots
-//                   form one flattened index space cut into fixed-size
-//                   chunks that waves pop from an atomic cursor, so a hub's
-//                   pairs are shared among many waves.  N+(u) and the pair
-//                   prefix of its out-neighbours sit in LDS; each pair is a
-//                   membership test of w in N+(u).  Optionally adds 1 to the
-//                   triangle count of each of the triangle's three arcs.
+//   k_tc_block      triangles.  The work of root u is the list of pairs
+//                   (v, w), v in N+(u), w in N+(v); all pairs of the roots of
+//                   one out-degree class form one flattened index space cut
+//                   into fixed-size chunks that blocks pop from an atomic
+//                   cursor, so a hub's pairs are shared among many blocks.
+//                   N+(u) sits in LDS as a hash table next to the pair
+//                   prefix of its out-neighbours; each pair is a membership
+//                   test of w in N+(u).  Optionally adds 1 to the triangle
+//                   count of each of the triangle's three arcs.
 //   k_clique_wave   k = 4, 5, roots with out-degree <= 64: one wave builds
 //                   the local graph on N+(u) as 64-bit adjacency rows in LDS
 //                   and counts cliques with AND + popcount.
@@ -147,38 +148,56 @@ __global__ void k_chunk_map(const int64_t *wpre, const int32_t *pos_total, int64
 
 // ---------------------------------------------------------- triangles ---
 
-// What k_tc_flat does with each triangle (u, v, w), u -> v -> w, u -> w.
+// What k_tc_block does with each triangle (u, v, w), u -> v -> w, u -> w.
 enum TcMode : int {
     TC_COUNT = 0,   // count only
     TC_ARCS = 1,    // also +1 on the triangle count of each of its three arcs
-    TC_LISTS = 2,   // also append the third vertex to each arc's list
 };
 
-template <int CAP, int MODE>
-__global__ void __launch_bounds__(kBlock) k_tc_flat(const int32_t *__restrict__ dag_off,
-                                                    const int32_t *__restrict__ dag_adj,
-                                                    const int32_t *__restrict__ act,
-                                                    const int64_t *__restrict__ wpre,
-                                                    const int32_t *__restrict__ first,
-                                                    const uint32_t *__restrict__ ctl,
-                                                    uint32_t *cursor, int64_t tau,
-                                                    unsigned long long *result, uint32_t *te,
-                                                    const int64_t *__restrict__ toff,
-                                                    int32_t *tl) {
-    __shared__ int32_t s_list[kWPB][CAP];
-    __shared__ int32_t s_pre[kWPB][CAP + 1];
-    __shared__ int32_t s_base[kWPB][CAP];
-    const int lane = lane_id();
-    const int wib = threadIdx.x / kWave;
-    int32_t *list = s_list[wib], *pre = s_pre[wib], *base = s_base[wib];
+// Triangles of the roots of one out-degree class (d+(u) <= DMAX), NT
+// threads per block.  A block pops a chunk of tau pairs of the class's
+// flattened pair space; for each root u the chunk touches it stages, in LDS,
+//   pre[j]   the pair prefix over N+(u) (pairs of v_j start at pre[j]),
+//   offj[j]  dag_off[v_j] - pre[j], so pair q of segment j is arc offj[j] + q,
+//   a hash table of N+(u) (key v_j, value j; load factor <= 1/4);
+// then every wave takes a contiguous run of the chunk's pairs of u.  Lane q
+// finds its segment by walking forward from the segment of the previous
+// tile's last pair (segments are long on power-law graphs, so a tile
+// crosses few boundaries) and tests w in N+(u) with the hash.  In TC_ARCS
+// mode the two arcs out of u are counted in LDS and flushed once per root
+// and chunk; the arc v -> w takes a global atomic.
+template <int DMAX, int NT, int MODE, int U>
+__global__ void __launch_bounds__(NT) k_tc_block(const int32_t *__restrict__ dag_off,
+                                                 const int32_t *__restrict__ dag_adj,
+                                                 const int32_t *__restrict__ act,
+                                                 const int64_t *__restrict__ wpre,
+                                                 const int32_t *__restrict__ first,
+                                                 const uint32_t *__restrict__ ctl,
+                                                 uint32_t *cursor, int64_t tau,
+                                                 unsigned long long *result, uint32_t *te) {
+    constexpr int NW = NT / kWave;
+    constexpr int H = 4 * DMAX;
+    constexpr int PER = (DMAX + NT - 1) / NT;
+    static_assert(DMAX <= 32767, "local indices are kept as int16");
+    __shared__ int32_t keys[H];
+    __shared__ int16_t vals[MODE == TC_ARCS ? H : 1];
+    __shared__ int32_t pre[DMAX + 1];
+    __shared__ int32_t offj[DMAX];
+    __shared__ uint32_t cnt[MODE == TC_ARCS ? DMAX : 1];
+    __shared__ int32_t s_sum[NW];
+    __shared__ uint32_t s_chunk;
+    __shared__ unsigned long long s_acc[NW];
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     const int32_t nact = (int32_t)ctl[0];
     const uint32_t nchunks = ctl[1];
     const int64_t total = wpre[nact];
+    if (MODE == TC_ARCS)
+        for (int i = tid; i < DMAX; i += NT) cnt[i] = 0;
     uint64_t acc = 0;
     for (;;) {
-        uint32_t c = 0;
-        if (lane == 0) c = atomicAdd(cursor, 1u);
-        c = __shfl(c, 0, 64);
+        if (tid == 0) s_chunk = atomicAdd(cursor, 1u);
+        __syncthreads();
+        const uint32_t c = s_chunk;
         if (c >= nchunks) break;
         int64_t p = (int64_t)c * tau;
         const int64_t p1 = min(p + tau, total);
@@ -187,54 +206,51 @@ __global__ void __launch_bounds__(kBlock) k_tc_flat(const int32_t *__restrict__ 
             const int64_t w0 = wpre[a], w1 = wpre[a + 1];
             const int32_t u = act[a];
             const int32_t s = dag_off[u], d = dag_off[u + 1] - s;
-            int32_t carry = 0;
-            for (int32_t i0 = 0; i0 < d; i0 += kWave) {
-                int32_t i = i0 + lane, dv = 0;
-                if (i < d) {
-                    int32_t v = dag_adj[s + i];
-                    int32_t st = dag_off[v];
-                    dv = dag_off[v + 1] - st;
-                    list[i] = v;
-                    base[i] = st;
-                }
-                int32_t inc = wave_incl_scan(dv);
-                if (i < d) pre[i + 1] = carry + inc;
-                carry += __shfl(inc, 63, 64);
-            }
-            if (lane == 0) pre[0] = 0;
-            wave_sync();
+            const int32_t hb = lds_hash_bits(d);
+            for (int i = tid; i < (1 << hb); i += NT) keys[i] = -1;
+            stage_root<NT, PER>(dag_off, dag_adj, s, d, keys, MODE == TC_ARCS ? vals : nullptr,
+                                hb, pre, offj, s_sum);
             const int32_t q0 = (int32_t)(p - w0);
             const int32_t q1 = (int32_t)(min(p1, w1) - w0);
-            for (int32_t qb = q0; qb < q1; qb += kWave) {
-                const int32_t q = qb + lane;
-                if (q < q1) {
-                    const int32_t j = last_le_i32(pre, d + 1, q);
-                    const int32_t e_vw = base[j] + (q - pre[j]);
-                    const int32_t w = dag_adj[e_vw];
-                    const int32_t idx = lower_bound_i32(list, d, w);
-                    if (idx < d && list[idx] == w) {
-                        acc++;
-                        if (MODE == TC_ARCS) {
-                            atomicAdd(&te[s + j], 1u);
-                            atomicAdd(&te[e_vw], 1u);
-                            atomicAdd(&te[s + idx], 1u);
-                        } else if (MODE == TC_LISTS) {
-                            // te holds per-arc cursors here
-                            const int32_t v = list[j];
-                            tl[toff[s + j] + atomicAdd(&te[s + j], 1u)] = w;
-                            tl[toff[e_vw] + atomicAdd(&te[e_vw], 1u)] = u;
-                            tl[toff[s + idx] + atomicAdd(&te[s + idx], 1u)] = v;
-                        }
+            // wave wid takes pairs [qa, qz), whole steps except the last
+            const int32_t per_wave =
+                ((q1 - q0 + NW - 1) / NW + U * kWave - 1) / (U * kWave) * (U * kWave);
+            const int32_t qa = min(q1, q0 + wid * per_wave);
+            const int32_t qz = min(q1, qa + per_wave);
+            walk_pairs<U>(pre, offj, dag_adj, d, qa, qz, [&](int32_t jj, int32_t e_vw, int32_t w) {
+                const int32_t slot = lds_hash_find(keys, hb, w);
+                if (slot >= 0) {
+                    acc++;
+                    if (MODE == TC_ARCS) {
+                        atomicAdd(&cnt[jj], 1u);
+                        atomicAdd(&cnt[vals[slot]], 1u);
+                        atomicAdd(&te[e_vw], 1u);
                     }
                 }
+            });
+            __syncthreads();
+            if (MODE == TC_ARCS) {
+                for (int32_t i = tid; i < d; i += NT) {
+                    const uint32_t x = cnt[i];
+                    if (x) {
+                        atomicAdd(&te[s + i], x);
+                        cnt[i] = 0;
+                    }
+                }
+                __syncthreads();
             }
-            wave_sync();
             p = min(p1, w1);
             a++;
         }
     }
     acc = wave_sum(acc);
-    if (lane == 0 && acc) atomicAdd(result, (unsigned long long)acc);
+    if (lane == 0) s_acc[wid] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long t = 0;
+        for (int q = 0; q < NW; q++) t += s_acc[q];
+        if (t) atomicAdd(result, t);
+    }
 }
 
 // ------------------------------------------- local-graph k-cliques ---
@@ -263,54 +279,35 @@ __device__ __forceinline__ uint64_t local_count64(uint64_t r, const uint64_t *ro
     return c;
 }
 
+// One 64-thread block (one wave) per root at a time: stages N+(u), sets the
+// local rows through the pair walk and the membership hash, then counts.
 template <int K>
-__global__ void __launch_bounds__(kBlock) k_clique_wave(const int32_t *__restrict__ dag_off,
-                                                        const int32_t *__restrict__ dag_adj,
-                                                        const int32_t *__restrict__ roots,
-                                                        const int32_t *__restrict__ nroots_p,
-                                                        unsigned long long *result) {
-    __shared__ uint64_t s_rows[kWPB][64];
-    __shared__ int32_t s_list[kWPB][64];
-    __shared__ int32_t s_pre[kWPB][65];
-    __shared__ int32_t s_base[kWPB][64];
+__global__ void __launch_bounds__(kWave) k_clique_wave(const int32_t *__restrict__ dag_off,
+                                                       const int32_t *__restrict__ dag_adj,
+                                                       const int32_t *__restrict__ roots,
+                                                       const int32_t *__restrict__ nroots_p,
+                                                       unsigned long long *result) {
+    __shared__ uint64_t rows[kWave];
+    __shared__ int32_t keys[4 * kWave];
+    __shared__ int16_t vals[4 * kWave];
+    __shared__ int32_t pre[kWave + 1], offj[kWave];
     const int lane = lane_id();
-    const int wib = threadIdx.x / kWave;
-    uint64_t *rows = s_rows[wib];
-    int32_t *list = s_list[wib], *pre = s_pre[wib], *base = s_base[wib];
     const int32_t nroots = *nroots_p;
-    const int64_t wave0 = (int64_t)blockIdx.x * kWPB + wib;
-    const int64_t nwaves = (int64_t)gridDim.x * kWPB;
     uint64_t acc = 0;
-    for (int64_t r = wave0; r < nroots; r += nwaves) {
+    for (int64_t r = blockIdx.x; r < nroots; r += gridDim.x) {
         const int32_t u = roots[r];
         const int32_t s = dag_off[u], d = dag_off[u + 1] - s;
-        int32_t dv = 0;
-        if (lane < d) {
-            int32_t v = dag_adj[s + lane];
-            int32_t st = dag_off[v];
-            dv = dag_off[v + 1] - st;
-            list[lane] = v;
-            base[lane] = st;
-        }
-        int32_t inc = wave_incl_scan(dv);
-        if (lane < d) pre[lane + 1] = inc;
-        if (lane == 0) pre[0] = 0;
+        const int32_t hb = lds_hash_bits(d);
+        for (int i = lane; i < (1 << hb); i += kWave) keys[i] = -1;
         rows[lane] = 0;
-        const int32_t W = __shfl(inc, 63, 64);
-        wave_sync();
-        for (int32_t qb = 0; qb < W; qb += kWave) {
-            const int32_t q = qb + lane;
-            if (q < W) {
-                const int32_t j = last_le_i32(pre, d + 1, q);
-                const int32_t w = dag_adj[base[j] + (q - pre[j])];
-                const int32_t idx = lower_bound_i32(list, d, w);
-                if (idx < d && list[idx] == w)
-                    atomicOr((unsigned long long *)&rows[j], 1ull << idx);
-            }
-        }
-        wave_sync();
+        stage_root<kWave, 1>(dag_off, dag_adj, s, d, keys, vals, hb, pre, offj, nullptr);
+        walk_pairs<2>(pre, offj, dag_adj, d, 0, pre[d], [&](int32_t j, int32_t, int32_t w) {
+            const int32_t slot = lds_hash_find(keys, hb, w);
+            if (slot >= 0) atomicOr((unsigned long long *)&rows[j], 1ull << vals[slot]);
+        });
+        __syncthreads();
         if (lane < d) acc += local_count64<K>(rows[lane], rows);
-        wave_sync();
+        __syncthreads();
     }
     acc = wave_sum(acc);
     if (lane == 0 && acc) atomicAdd(result, (unsigned long long)acc);
@@ -466,18 +463,22 @@ __global__ void k_finish_listing(unsigned long long *result, uint64_t cap) {
 
 // ------------------------------------------------------------ host side --
 
-constexpr int64_t kTcTau = 4096;
-constexpr int32_t kSmallMax = 256;   // k_tc_flat<256> class
-constexpr int32_t kTcMax = 1024;     // k_tc_flat<1024> class
+// Triangle classes by out-degree: (1, 64] one wave per block, (64, 256] and
+// (256, 1024] larger blocks sharing one staged root.  Chunk sizes in pairs:
+// every chunk costs one atomic on the class's cursor, and a few hundred
+// thousand atomics on one address cost milliseconds, so chunks stay large.
+constexpr int32_t kTcSmall = 64, kTcMid = 256, kTcMax = 1024;
+constexpr int64_t kTauSmall = 8192, kTauMid = 16384, kTauBig = 65536;
+constexpr int64_t kTauMin = kTauSmall;
 
 struct CliqueWs {
-    unsigned long long *result;   // [4]
-    uint32_t *ctl;                // [16]: cursors and per-class {nact, nchunks}
+    unsigned long long *result;   // [8]: count, -, pairs of each triangle class
+    uint32_t *ctl;                // [32]: cursors, per-class {nact, nchunks}, class counts
     int32_t *work, *cls, *flag, *pos;
     int32_t *list_s, *list_m, *list_b;
     int32_t *lwork;               // compacted work of one class (reused)
-    int64_t *wpre_s, *wpre_m;
-    int32_t *first_s, *first_m;
+    int64_t *wpre_s, *wpre_m, *wpre_b;
+    int32_t *first_s, *first_m, *first_b;
     int64_t *scan_tmp;
     void *lg;                     // local-graph workspace (k = 4, 5)
     uint64_t lg_bytes;
@@ -489,15 +490,15 @@ struct CliqueWs {
 int64_t chunk_bound(const gpm_graph *g) {
     // total pair work = sum_v d-(v) d+(v) <= m * max_out; chunks = ceil(total / tau)
     int64_t w = g->m * (int64_t)std::max(g->max_out_degree, 1);
-    return w / kTcTau + 2;
+    return w / kTauMin + 2;
 }
 
 CliqueWs clique_layout(const gpm_graph *g, int32_t k, bool list, void *base) {
     CliqueWs W{};
     Carve c(base, ~0ull);
     const uint64_t n1 = (uint64_t)g->n + 1;
-    W.result = c.take<unsigned long long>(4);
-    W.ctl = c.take<uint32_t>(16);
+    W.result = c.take<unsigned long long>(8);
+    W.ctl = c.take<uint32_t>(32);
     W.work = c.take<int32_t>(n1);
     W.cls = c.take<int32_t>(n1);
     W.flag = c.take<int32_t>(n1);
@@ -508,11 +509,13 @@ CliqueWs clique_layout(const gpm_graph *g, int32_t k, bool list, void *base) {
     W.lwork = c.take<int32_t>(n1);
     W.wpre_s = c.take<int64_t>(n1);
     W.wpre_m = c.take<int64_t>(n1);
+    W.wpre_b = c.take<int64_t>(n1);
     W.scan_tmp = c.take<int64_t>(scan_tmp_words(n1));
     bool generic = list || k > 5 || g->max_out_degree > kTcMax;
     if (!generic && k == 3) {
         W.first_s = c.take<int32_t>((uint64_t)chunk_bound(g));
         W.first_m = c.take<int32_t>((uint64_t)chunk_bound(g));
+        W.first_b = c.take<int32_t>((uint64_t)chunk_bound(g));
     }
     if (!generic && k >= 4) {
         lg_workspace_bytes(g, k, &W.lg_bytes);
@@ -563,8 +566,8 @@ gpm_status launch_local(const gpm_graph *g, CliqueWs &W, const int32_t *cnt_s,
     if (rc) return rc;
     {
         Span sp(K == 4 ? "k_clique_wave<4>" : "k_clique_wave<5>", st);
-        hipLaunchKernelGGL(k_clique_wave<K>, dim3((unsigned)persistent_blocks(kWPB, 8)),
-                           dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_s, cnt_s, res);
+        hipLaunchKernelGGL(k_clique_wave<K>, dim3((unsigned)(cu_count() * 32)), dim3(kWave), 0,
+                           st, g->dag_off, g->dag_adj, W.list_s, cnt_s, res);
     }
     GPM_LAUNCH_CHECK("k_clique_wave");
     return GPM_OK;
@@ -578,44 +581,54 @@ gpm_status clique_workspace_bytes(const gpm_graph *g, int32_t k, bool list, uint
     return GPM_OK;
 }
 
-// Triangle scatter used by motif counting: adds 1 to the triangle count of
-// each of the three arcs of every triangle (te, m words, must be zero on
-// entry) and the number of triangles to *tri (zero on entry).  Uses the
-// triangle workspace (clique_workspace_bytes(g, 3, false)).
+template <int DMAX, int NT, int MODE>
+static gpm_status tc_class(const gpm_graph *g, CliqueWs &W, int32_t want, int32_t *list,
+                           int64_t *wpre, int32_t *first, int cls_idx, int64_t tau,
+                           int blocks_per_cu, const char *name, unsigned long long *res,
+                           uint32_t *te, hipStream_t st) {
+    const int32_t n = g->n;
+    uint32_t *info = W.ctl + 4 + 2 * cls_idx;   // {nact, nchunks}
+    GPM_HIP(build_class(g, W, want, list, wpre, st));
+    hipLaunchKernelGGL(k_chunk_map, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, wpre, W.pos + n,
+                       tau, first, info, W.result + 2 + cls_idx);
+    GPM_LAUNCH_CHECK("k_chunk_map");
+    {
+        Span sp(name, st);
+        hipLaunchKernelGGL((k_tc_block<DMAX, NT, MODE, 2>),
+                           dim3((unsigned)(cu_count() * blocks_per_cu)), dim3(NT), 0, st,
+                           g->dag_off, g->dag_adj, list, wpre, first, info, W.ctl + cls_idx,
+                           tau, res, te);
+        span_units(W.result + 2 + cls_idx, st);
+    }
+    GPM_LAUNCH_CHECK(name);
+    return GPM_OK;
+}
+
+// Triangle count into *res (zero on entry); with MODE == TC_ARCS also adds 1
+// to the triangle count of each of the three arcs of every triangle (te, m
+// words, zero on entry).  Uses the triangle workspace
+// (clique_workspace_bytes(g, 3, false)).
 template <int MODE>
 static gpm_status tc_launch(const gpm_graph *g, CliqueWs &W, unsigned long long *res,
-                            uint32_t *te, const int64_t *toff, int32_t *tl, hipStream_t st) {
+                            uint32_t *te, hipStream_t st) {
     const int32_t n = g->n;
-    GPM_HIP(fill_u32(W.ctl, 0, 16, st));
+    GPM_HIP(fill_u32(W.ctl, 0, 32, st));
     hipLaunchKernelGGL(k_root_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st, g->dag_off,
-                       g->dag_adj, n, 2, kSmallMax, kTcMax, kTcMax, W.work, W.cls);
+                       g->dag_adj, n, 2, kTcSmall, kTcMid, kTcMax, W.work, W.cls);
     GPM_LAUNCH_CHECK("k_root_work");
-    GPM_HIP(build_class(g, W, RC_SMALL, W.list_s, W.wpre_s, st));
-    // W.result[2], [3]: pairs of each class (work units of the timing spans)
-    hipLaunchKernelGGL(k_chunk_map, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.wpre_s,
-                       W.pos + n, kTcTau, W.first_s, W.ctl + 2, W.result + 2);
-    GPM_LAUNCH_CHECK("k_chunk_map");
-    GPM_HIP(build_class(g, W, RC_MID, W.list_m, W.wpre_m, st));
-    hipLaunchKernelGGL(k_chunk_map, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.wpre_m,
-                       W.pos + n, kTcTau, W.first_m, W.ctl + 4, W.result + 3);
-    GPM_LAUNCH_CHECK("k_chunk_map");
-    {
-        Span sp(MODE == TC_COUNT ? "k_tc_flat<1024>" : "k_tc_flat<1024,arcs>", st);
-        hipLaunchKernelGGL((k_tc_flat<kTcMax, MODE>), dim3((unsigned)persistent_blocks(kWPB, 3)),
-                           dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_m, W.wpre_m,
-                           W.first_m, W.ctl + 4, W.ctl + 1, kTcTau, res, te, toff, tl);
-        span_units(W.result + 3, st);
-    }
-    GPM_LAUNCH_CHECK("k_tc_flat<1024>");
-    {
-        Span sp(MODE == TC_COUNT ? "k_tc_flat<256>" : "k_tc_flat<256,arcs>", st);
-        hipLaunchKernelGGL((k_tc_flat<kSmallMax, MODE>), dim3((unsigned)persistent_blocks(kWPB, 8)),
-                           dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_s, W.wpre_s,
-                           W.first_s, W.ctl + 2, W.ctl + 0, kTcTau, res, te, toff, tl);
-        span_units(W.result + 2, st);
-    }
-    GPM_LAUNCH_CHECK("k_tc_flat<256>");
-    return GPM_OK;
+    const bool arcs = MODE == TC_ARCS;
+    gpm_status rc = tc_class<kTcMax, 512, MODE>(
+        g, W, RC_BIG, W.list_b, W.wpre_b, W.first_b, 2, kTauBig, 4,
+        arcs ? "k_tc_block<1024,arcs>" : "k_tc_block<1024>", res, te, st);
+    if (rc) return rc;
+    rc = tc_class<kTcMid, 256, MODE>(g, W, RC_MID, W.list_m, W.wpre_m, W.first_m, 1, kTauMid, 8,
+                                     arcs ? "k_tc_block<256,arcs>" : "k_tc_block<256>", res, te,
+                                     st);
+    if (rc) return rc;
+    return tc_class<kTcSmall, 64, MODE>(g, W, RC_SMALL, W.list_s, W.wpre_s, W.first_s, 0,
+                                        kTauSmall, 32,
+                                        arcs ? "k_tc_block<64,arcs>" : "k_tc_block<64>", res, te,
+                                        st);
 }
 
 gpm_status triangle_arc_counts(const gpm_graph *g, void *ws, uint64_t ws_bytes, uint32_t *te,
@@ -624,21 +637,7 @@ gpm_status triangle_arc_counts(const gpm_graph *g, void *ws, uint64_t ws_bytes, 
         return fail(GPM_UNSUPPORTED, "per-edge triangle counts need every out-degree <= 1024");
     CliqueWs W = clique_layout(g, 3, false, ws);
     if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
-    return tc_launch<TC_ARCS>(g, W, tri, te, nullptr, nullptr, st);
-}
-
-// Second triangle pass for listings: appends the third vertex of every
-// triangle to the list of each of its three arcs; arc e's list starts at
-// toff[e] (exclusive prefix of the per-arc triangle counts) and cur (m
-// words, zero on entry) serves as per-arc cursors.
-gpm_status triangle_third_lists(const gpm_graph *g, void *ws, uint64_t ws_bytes,
-                                const int64_t *toff, uint32_t *cur, int32_t *tl,
-                                unsigned long long *tri, hipStream_t st) {
-    if (g->max_out_degree > kTcMax)
-        return fail(GPM_UNSUPPORTED, "per-edge triangle lists need every out-degree <= 1024");
-    CliqueWs W = clique_layout(g, 3, false, ws);
-    if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
-    return tc_launch<TC_LISTS>(g, W, tri, cur, toff, tl, st);
+    return tc_launch<TC_ARCS>(g, W, tri, te, st);
 }
 
 gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64_t ws_bytes,
@@ -648,8 +647,8 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
     if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
     const int32_t n = g->n;
     unsigned long long *res = list ? d_result : W.result;
-    GPM_HIP(fill_u32(res, 0, list ? 6 : 8, st));
-    GPM_HIP(fill_u32(W.ctl, 0, 16, st));
+    GPM_HIP(fill_u32(res, 0, list ? 6 : 16, st));
+    GPM_HIP(fill_u32(W.ctl, 0, 32, st));
     const bool generic = list || k > 5 || g->max_out_degree > kTcMax;
     if (generic) {
         ListOut lo{d_buf, list ? cap : 0};
@@ -668,7 +667,7 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
             GPM_LAUNCH_CHECK("k_finish_listing");
         }
     } else if (k == 3) {
-        gpm_status rc = tc_launch<TC_COUNT>(g, W, res, nullptr, nullptr, nullptr, st);
+        gpm_status rc = tc_launch<TC_COUNT>(g, W, res, nullptr, st);
         if (rc) return rc;
     } else {
         hipLaunchKernelGGL(k_root_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st,
@@ -676,8 +675,8 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
         GPM_LAUNCH_CHECK("k_root_work");
         {
             // three classes; each count lives in its own pos snapshot
-            int32_t *cnt_s = (int32_t *)(W.ctl + 8), *cnt_m = (int32_t *)(W.ctl + 9),
-                    *cnt_b = (int32_t *)(W.ctl + 10);
+            int32_t *cnt_s = (int32_t *)(W.ctl + 12), *cnt_m = (int32_t *)(W.ctl + 13),
+                    *cnt_b = (int32_t *)(W.ctl + 14);
             GPM_HIP(build_class(g, W, RC_BIG, W.list_b, nullptr, st));
             GPM_HIP(hipMemcpyAsync(cnt_b, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
             GPM_HIP(build_class(g, W, RC_MID, W.list_m, nullptr, st));

@@ -152,6 +152,156 @@ __device__ __forceinline__ void atomic_add_u128(unsigned long long *p, unsigned 
     if (hi) atomicAdd(p + 1, hi);
 }
 
+// ------------------------------------------------- LDS membership hash ---
+// Open addressing with linear probing over a power-of-two table of int32
+// keys (-1 = empty) in LDS, multiplicative hashing.  Used to test whether a
+// vertex is one of a root's out-neighbours (and to find its local index)
+// with one or two LDS reads instead of a binary search.
+
+__device__ __forceinline__ uint32_t lds_hash_slot(int32_t key, int32_t bits) {
+    return ((uint32_t)key * 0x9E3779B1u) >> (32 - bits);
+}
+
+// Smallest table size exponent with 2^bits >= 4 * d (load factor <= 1/4),
+// at least 6 (64 slots).
+__device__ __forceinline__ int32_t lds_hash_bits(int32_t d) {
+    int32_t b = 6;
+    while ((1 << b) < 4 * d) b++;
+    return b;
+}
+
+// Inserts distinct key with value val (vals may be null).
+__device__ __forceinline__ void lds_hash_insert(int32_t *keys, int16_t *vals, int32_t bits,
+                                                int32_t key, int32_t val) {
+    const uint32_t mask = (1u << bits) - 1u;
+    uint32_t h = lds_hash_slot(key, bits);
+    for (;;) {
+        if (atomicCAS(&keys[h], -1, key) == -1) {
+            if (vals) vals[h] = (int16_t)val;
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// Slot holding key, or -1 when absent.
+__device__ __forceinline__ int32_t lds_hash_find(const int32_t *keys, int32_t bits, int32_t key) {
+    const uint32_t mask = (1u << bits) - 1u;
+    uint32_t h = lds_hash_slot(key, bits);
+    for (;;) {
+        const int32_t k = keys[h];
+        if (k == key) return (int32_t)h;
+        if (k < 0) return -1;
+        h = (h + 1) & mask;
+    }
+}
+
+// Block-wide exclusive scan of PER values per thread (thread t owns entries
+// t*PER .. t*PER+PER-1): pre[i+1] = sum of entries 0..i for i < d, pre[0] =
+// 0.  s_sum holds NT/64 words of LDS.  Ends with a barrier.
+template <int NT, int PER>
+__device__ void block_prefix(const int32_t (&val)[PER], int32_t d, int32_t *pre, int32_t *s_sum) {
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / 64;
+    int32_t mysum = 0;
+#pragma unroll
+    for (int q = 0; q < PER; q++) mysum += val[q];
+    const int32_t inc = wave_incl_scan(mysum);
+    if (NT > 64) {
+        if (lane == 63) s_sum[wid] = inc;
+        __syncthreads();
+    }
+    int32_t run = inc - mysum;
+    if (NT > 64)
+        for (int q = 0; q < wid; q++) run += s_sum[q];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int32_t i = tid * PER + q;
+        run += val[q];
+        if (i < d) pre[i + 1] = run;
+    }
+    if (tid == 0) pre[0] = 0;
+    __syncthreads();
+}
+
+// --------------------------------------------- staged roots and pairs ---
+// The pairs of a root u of the degree-ordered DAG are (v_j, w) with v_j the
+// j-th out-neighbour of u and w in N+(v_j), numbered q = 0 .. W_u - 1 in
+// (j, position of w) order.  A staged root holds in LDS
+//   pre[j]   first pair number of segment j (pre[d] = W_u),
+//   offj[j]  dag_off[v_j] - pre[j], so pair q of segment j is arc offj[j] + q,
+//   keys/vals  the membership hash of N+(u) (key v_j, value j).
+
+// Stages root u (d out-neighbours starting at arc s) with NT threads, PER
+// out-neighbours per thread (NT * PER >= d).  keys must hold 2^hb slots and
+// be cleared to -1 before the call; vals may be null.  Ends with a barrier.
+template <int NT, int PER>
+__device__ void stage_root(const int32_t *__restrict__ dag_off, const int32_t *__restrict__ dag_adj,
+                           int32_t s, int32_t d, int32_t *keys, int16_t *vals, int32_t hb,
+                           int32_t *pre, int32_t *offj, int32_t *s_sum) {
+    int32_t dv[PER], vv[PER], st[PER];
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+        const int32_t i = threadIdx.x * PER + k;
+        dv[k] = 0;
+        vv[k] = 0;
+        st[k] = 0;
+        if (i < d) {
+            vv[k] = dag_adj[s + i];
+            st[k] = dag_off[vv[k]];
+            dv[k] = dag_off[vv[k] + 1] - st[k];
+        }
+    }
+    block_prefix<NT, PER>(dv, d, pre, s_sum);
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+        const int32_t i = threadIdx.x * PER + k;
+        if (i < d) {
+            offj[i] = st[k] - pre[i];
+            lds_hash_insert(keys, vals, hb, vv[k], i);
+        }
+    }
+    __syncthreads();
+}
+
+// Calls f(j, e_vw, w) for every pair q in [qa, qz) of a staged root with d
+// out-neighbours, one pair per lane, U tiles of 64 pairs per step with their
+// loads of w issued together.  A lane finds the segment of its pair by
+// walking forward from the segment of the previous step's last pair (one
+// binary search per call), so a tile costs one LDS read per segment
+// boundary it crosses.  Wave-uniform qa and qz.
+template <int U, class F>
+__device__ __forceinline__ void walk_pairs(const int32_t *pre, const int32_t *offj,
+                                           const int32_t *__restrict__ dag_adj, int32_t d,
+                                           int32_t qa, int32_t qz, F &&f) {
+    if (qa >= qz) return;
+    const int lane = lane_id();
+    int32_t lo = 0, hi = d;   // last j with pre[j] <= qa
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= qa) lo = mid; else hi = mid;
+    }
+    int32_t j = lo;
+    for (int32_t qb = qa; qb < qz; qb += U * 64) {
+        int32_t jj[U], e[U], w[U];
+        int32_t jc = j;
+#pragma unroll
+        for (int t = 0; t < U; t++) {
+            const int32_t q = qb + t * 64 + lane;
+            if (q < qz)
+                while (pre[jc + 1] <= q) jc++;
+            jj[t] = jc;
+            e[t] = offj[jc] + q;
+        }
+#pragma unroll
+        for (int t = 0; t < U; t++)
+            w[t] = qb + t * 64 + lane < qz ? dag_adj[e[t]] : -1;
+#pragma unroll
+        for (int t = 0; t < U; t++)
+            if (qb + t * 64 + lane < qz) f(jj[t], e[t], w[t]);
+        j = __shfl(jc, 63, 64);
+    }
+}
+
 // splitmix64 finaliser, for the listing checksum.
 __device__ __forceinline__ uint64_t fmix64(uint64_t z) {
     z ^= z >> 30; z *= 0xBF58476D1CE4E5B9ull;

@@ -41,15 +41,6 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ int lower_bound_i32(const int32_t *a, int n, int32_t x) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (a[mid] < x) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ int last_le_i32(const int32_t *a, int n, int32_t x) {
     int lo = 0, hi = n;
     while (hi - lo > 1) {
@@ -81,61 +72,41 @@ struct Lds {
     uint64_t s_tri;
 };
 
-// Block-wide exclusive scan of PER values per thread (thread t owns entries
-// t*PER .. t*PER+PER-1); writes pre[i+1] for i < d and pre[0] = 0.
-template <int NT, int PER>
-__device__ void block_prefix(const int32_t (&val)[PER], int32_t d, int32_t *pre, int32_t *s_sum) {
-    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
-    int32_t mysum = 0;
-#pragma unroll
-    for (int q = 0; q < PER; q++) mysum += val[q];
-    const int32_t inc = wave_incl_scan(mysum);
-    if (lane == 63) s_sum[wid] = inc;
-    __syncthreads();
-    int32_t run = inc - mysum;
-    for (int q = 0; q < wid; q++) run += s_sum[q];
-#pragma unroll
-    for (int q = 0; q < PER; q++) {
-        const int32_t i = tid * PER + q;
-        run += val[q];
-        if (i < d) pre[i + 1] = run;
-    }
-    if (tid == 0) pre[0] = 0;
-    __syncthreads();
-}
+// Hash table of a local-graph block: 2 slots per out-neighbour at the class
+// bound (load factor <= 1/4 up to half the bound, <= 1/2 at the bound), so
+// the 1024-bound rows (128 KiB) and the table fit the 160 KiB of LDS.
+template <int DMAX> struct LgHash {
+    static constexpr int kSlots = 2 * DMAX;
+    static constexpr int kBits = DMAX == 1024 ? 11 : (DMAX == 256 ? 9 : 7);
+    static_assert((1 << kBits) == kSlots, "slots must be a power of two");
+};
 
 // Builds the local graph of root u (d out-neighbours, W words per row) in
-// LDS.  Uses list/base/pre as scratch; ends with a barrier.
+// LDS: row j gets bit i for every pair (v_j, w) with w = v_i in N+(u).
+// keys/vals/pre/offj are the root's staging area; ends with a barrier.
 template <int DMAX, int NT>
 __device__ void build_rows(const int32_t *__restrict__ dag_off, const int32_t *__restrict__ dag_adj,
-                           int32_t u, int32_t d, int32_t W, uint64_t *rows, int32_t *list,
-                           int32_t *base, int32_t *pre, int32_t *s_sum) {
+                           int32_t u, int32_t d, int32_t W, uint64_t *rows, int32_t *keys,
+                           int16_t *vals, int32_t *pre, int32_t *offj, int32_t *s_sum) {
     constexpr int PER = (DMAX + NT - 1) / NT;
-    const int tid = threadIdx.x;
+    constexpr int NW = NT / kWave;
+    constexpr int U = 2;
     const int32_t s = dag_off[u];
-    int32_t dv[PER];
-#pragma unroll
-    for (int q = 0; q < PER; q++) {
-        const int32_t i = tid * PER + q;
-        dv[q] = 0;
-        if (i < d) {
-            const int32_t v = dag_adj[s + i];
-            const int32_t st = dag_off[v];
-            dv[q] = dag_off[v + 1] - st;
-            list[i] = v;
-            base[i] = st;
-        }
-    }
-    for (int32_t i = tid; i < d * W; i += NT) rows[i] = 0ull;
-    block_prefix<NT, PER>(dv, d, pre, s_sum);
+    const int32_t hb = min(lds_hash_bits(d), LgHash<DMAX>::kBits);
+    for (int32_t i = threadIdx.x; i < (1 << hb); i += NT) keys[i] = -1;
+    for (int32_t i = threadIdx.x; i < d * W; i += NT) rows[i] = 0ull;
+    stage_root<NT, PER>(dag_off, dag_adj, s, d, keys, vals, hb, pre, offj, s_sum);
     const int32_t npairs = pre[d];
-    for (int32_t q = tid; q < npairs; q += NT) {
-        const int32_t j = last_le_i32(pre, d + 1, q);
-        const int32_t w = dag_adj[base[j] + (q - pre[j])];
-        const int32_t idx = lower_bound_i32(list, d, w);
-        if (idx < d && list[idx] == w)
+    const int32_t per_wave = ((npairs + NW - 1) / NW + U * kWave - 1) / (U * kWave) * (U * kWave);
+    const int32_t qa = min(npairs, (int32_t)(threadIdx.x / kWave) * per_wave);
+    const int32_t qz = min(npairs, qa + per_wave);
+    walk_pairs<U>(pre, offj, dag_adj, d, qa, qz, [&](int32_t j, int32_t, int32_t w) {
+        const int32_t slot = lds_hash_find(keys, hb, w);
+        if (slot >= 0) {
+            const int32_t idx = vals[slot];
             atomicOr((unsigned long long *)&rows[j * W + (idx >> 6)], 1ull << (idx & 63));
-    }
+        }
+    });
     __syncthreads();
 }
 
@@ -179,7 +150,9 @@ __global__ void __launch_bounds__(NT) k_lg4(const int32_t *__restrict__ dag_off,
                                             const int32_t *__restrict__ nroots_p,
                                             uint32_t *cursor, unsigned long long *result) {
     __shared__ uint64_t rows[DMAX * (DMAX / 64)];
-    __shared__ int32_t list[DMAX], base[DMAX], pre[DMAX + 1];
+    __shared__ int32_t keys[LgHash<DMAX>::kSlots];
+    __shared__ int16_t vals[LgHash<DMAX>::kSlots];
+    __shared__ int32_t offj[DMAX], pre[DMAX + 1];
     __shared__ Lds<NT> sh;
     const int tid = threadIdx.x;
     const int32_t nroots = *nroots_p;
@@ -192,7 +165,7 @@ __global__ void __launch_bounds__(NT) k_lg4(const int32_t *__restrict__ dag_off,
         if (r >= nroots) break;
         const int32_t u = roots[r];
         const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
-        build_rows<DMAX, NT>(dag_off, dag_adj, u, d, W, rows, list, base, pre, sh.s_sum);
+        build_rows<DMAX, NT>(dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj, sh.s_sum);
         const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
         for (int32_t e = tid; e < ne; e += NT) {
             int32_t i, j;
@@ -216,7 +189,9 @@ __global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ dag
                                                  uint64_t *grows, int32_t *slices,
                                                  unsigned long long *units) {
     __shared__ uint64_t rows[DMAX * (DMAX / 64)];
-    __shared__ int32_t list[DMAX], base[DMAX], pre[DMAX + 1];
+    __shared__ int32_t keys[LgHash<DMAX>::kSlots];
+    __shared__ int16_t vals[LgHash<DMAX>::kSlots];
+    __shared__ int32_t offj[DMAX], pre[DMAX + 1];
     __shared__ Lds<NT> sh;
     const int tid = threadIdx.x;
     const int32_t nroots = *nroots_p;
@@ -229,7 +204,7 @@ __global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ dag
         if (r >= nroots) break;
         const int32_t u = roots[r];
         const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
-        build_rows<DMAX, NT>(dag_off, dag_adj, u, d, W, rows, list, base, pre, sh.s_sum);
+        build_rows<DMAX, NT>(dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj, sh.s_sum);
         uint64_t *dst = grows + rowoff[r];
         for (int32_t i = tid; i < d * W; i += NT) dst[i] = rows[i];
         const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
