@@ -233,11 +233,13 @@ __device__ void block_prefix(const int32_t (&val)[PER], int32_t d, int32_t *pre,
 
 // Stages root u (d out-neighbours starting at arc s) with NT threads, PER
 // out-neighbours per thread (NT * PER >= d).  keys must hold 2^hb slots and
-// be cleared to -1 before the call; vals may be null.  Ends with a barrier.
+// be cleared to -1 before the call; vals may be null.  The hash value of v_j
+// is j, or lidx[j] when lidx is given.  Ends with a barrier.
 template <int NT, int PER>
 __device__ void stage_root(const int32_t *__restrict__ dag_off, const int32_t *__restrict__ dag_adj,
                            int32_t s, int32_t d, int32_t *keys, int16_t *vals, int32_t hb,
-                           int32_t *pre, int32_t *offj, int32_t *s_sum) {
+                           int32_t *pre, int32_t *offj, int32_t *s_sum,
+                           const int16_t *lidx = nullptr) {
     int32_t dv[PER], vv[PER], st[PER];
 #pragma unroll
     for (int k = 0; k < PER; k++) {
@@ -257,7 +259,7 @@ __device__ void stage_root(const int32_t *__restrict__ dag_off, const int32_t *_
         const int32_t i = threadIdx.x * PER + k;
         if (i < d) {
             offj[i] = st[k] - pre[i];
-            lds_hash_insert(keys, vals, hb, vv[k], i);
+            lds_hash_insert(keys, vals, hb, vv[k], lidx ? (int32_t)lidx[i] : i);
         }
     }
     __syncthreads();

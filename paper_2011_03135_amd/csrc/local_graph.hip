@@ -82,20 +82,43 @@ template <int DMAX> struct LgHash {
 };
 
 // Builds the local graph of root u (d out-neighbours, W words per row) in
-// LDS: row j gets bit i for every pair (v_j, w) with w = v_i in N+(u).
+// LDS: row a gets bit b for every pair (v, w) of the root with v, w the
+// out-neighbours of local indices a and b.  Local indices are positions in
+// the out-list, or with RANK positions in the degree order (off = the
+// symmetric CSR offsets give the degrees; lidx, d entries, receives them),
+// which makes every row hold only bits above its own index.
 // keys/vals/pre/offj are the root's staging area; ends with a barrier.
-template <int DMAX, int NT>
-__device__ void build_rows(const int32_t *__restrict__ dag_off, const int32_t *__restrict__ dag_adj,
-                           int32_t u, int32_t d, int32_t W, uint64_t *rows, int32_t *keys,
-                           int16_t *vals, int32_t *pre, int32_t *offj, int32_t *s_sum) {
+template <int DMAX, int NT, bool RANK>
+__device__ void build_rows(const int32_t *__restrict__ off, const int32_t *__restrict__ dag_off,
+                           const int32_t *__restrict__ dag_adj, int32_t u, int32_t d, int32_t W,
+                           uint64_t *rows, int32_t *keys, int16_t *vals, int32_t *pre,
+                           int32_t *offj, int16_t *lidx, int32_t *s_sum) {
     constexpr int PER = (DMAX + NT - 1) / NT;
     constexpr int NW = NT / kWave;
     constexpr int U = 2;
     const int32_t s = dag_off[u];
+    if (RANK) {
+        // rank of each out-neighbour among the others, by (degree, id); the
+        // row area is scratch for the keys until it is cleared below
+        uint64_t *key = rows;
+        for (int32_t i = threadIdx.x; i < d; i += NT) {
+            const int32_t v = dag_adj[s + i];
+            key[i] = ((uint64_t)(uint32_t)(off[v + 1] - off[v]) << 32) | (uint32_t)v;
+        }
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < d; i += NT) {
+            const uint64_t k = key[i];
+            int32_t c = 0;
+            for (int32_t j = 0; j < d; j++) c += key[j] < k;
+            lidx[i] = (int16_t)c;
+        }
+        __syncthreads();
+    }
     const int32_t hb = min(lds_hash_bits(d), LgHash<DMAX>::kBits);
     for (int32_t i = threadIdx.x; i < (1 << hb); i += NT) keys[i] = -1;
     for (int32_t i = threadIdx.x; i < d * W; i += NT) rows[i] = 0ull;
-    stage_root<NT, PER>(dag_off, dag_adj, s, d, keys, vals, hb, pre, offj, s_sum);
+    stage_root<NT, PER>(dag_off, dag_adj, s, d, keys, vals, hb, pre, offj, s_sum,
+                        RANK ? lidx : nullptr);
     const int32_t npairs = pre[d];
     const int32_t per_wave = ((npairs + NW - 1) / NW + U * kWave - 1) / (U * kWave) * (U * kWave);
     const int32_t qa = min(npairs, (int32_t)(threadIdx.x / kWave) * per_wave);
@@ -103,8 +126,9 @@ __device__ void build_rows(const int32_t *__restrict__ dag_off, const int32_t *_
     walk_pairs<U>(pre, offj, dag_adj, d, qa, qz, [&](int32_t j, int32_t, int32_t w) {
         const int32_t slot = lds_hash_find(keys, hb, w);
         if (slot >= 0) {
-            const int32_t idx = vals[slot];
-            atomicOr((unsigned long long *)&rows[j * W + (idx >> 6)], 1ull << (idx & 63));
+            const int32_t a = RANK ? (int32_t)lidx[j] : j;
+            const int32_t b = vals[slot];
+            atomicOr((unsigned long long *)&rows[a * W + (b >> 6)], 1ull << (b & 63));
         }
     });
     __syncthreads();
@@ -165,7 +189,8 @@ __global__ void __launch_bounds__(NT) k_lg4(const int32_t *__restrict__ dag_off,
         if (r >= nroots) break;
         const int32_t u = roots[r];
         const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
-        build_rows<DMAX, NT>(dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj, sh.s_sum);
+        build_rows<DMAX, NT, false>(nullptr, dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj,
+                                     nullptr, sh.s_sum);
         const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
         for (int32_t e = tid; e < ne; e += NT) {
             int32_t i, j;
@@ -179,9 +204,11 @@ __global__ void __launch_bounds__(NT) k_lg4(const int32_t *__restrict__ dag_off,
     if (lane_id() == 0 && acc) atomicAdd(result, (unsigned long long)acc);
 }
 
-// 5-cliques, step 1: rows of every root to HBM, and local edge counts.
+// 5-cliques, step 1: rows of every root (local indices in degree order) to
+// HBM, and local triangle counts for slicing.
 template <int DMAX, int NT>
-__global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ dag_off,
+__global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ off,
+                                                 const int32_t *__restrict__ dag_off,
                                                  const int32_t *__restrict__ dag_adj,
                                                  const int32_t *__restrict__ roots,
                                                  const int32_t *__restrict__ nroots_p,
@@ -191,6 +218,7 @@ __global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ dag
     __shared__ uint64_t rows[DMAX * (DMAX / 64)];
     __shared__ int32_t keys[LgHash<DMAX>::kSlots];
     __shared__ int16_t vals[LgHash<DMAX>::kSlots];
+    __shared__ int16_t lidx[DMAX];
     __shared__ int32_t offj[DMAX], pre[DMAX + 1];
     __shared__ Lds<NT> sh;
     const int tid = threadIdx.x;
@@ -204,7 +232,8 @@ __global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ dag
         if (r >= nroots) break;
         const int32_t u = roots[r];
         const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
-        build_rows<DMAX, NT>(dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj, sh.s_sum);
+        build_rows<DMAX, NT, true>(off, dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj,
+                                   lidx, sh.s_sum);
         uint64_t *dst = grows + rowoff[r];
         for (int32_t i = tid; i < d * W; i += NT) dst[i] = rows[i];
         const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
@@ -245,10 +274,83 @@ __global__ void k_lg_words(const int32_t *dag_off, const int32_t *roots, const i
 }
 
 // 5-cliques, step 2: task (root, slice); rows come back from HBM into LDS.
+// For local vertex i with out-row R (members p_0 < ... < p_{c-1}), the
+// 5-cliques {u, v_i, ...} are the triangles a < b < x of the local DAG
+// inside R: the sum over members a < b of [a -> b] * |row_a & R & row_b|.
+// Lanes own a (64 members at a time, row_a & R in registers); b runs over
+// R's members in a wave-uniform loop, so row_b is a broadcast LDS read, and
+// the AND + population count runs over the words from b's word up (a row
+// only holds bits above its own vertex).  Local graphs of hub roots are
+// dense, so testing every pair costs little more than following edges and
+// keeps all 64 lanes busy.
 // LDS is dynamic: rows (dmax x ceil(dmax/64) words for the class's largest
-// out-degree), then per wave a re-encoding area of kCands x kCW words.
-constexpr int kCands = 256;    // candidate sets up to this size are re-encoded
-constexpr int kCW = kCands / 64;
+// out-degree), then per wave a member list of DMAX int16.
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int W>
+__device__ uint64_t lg5_vertex(const uint64_t *rows, const uint64_t *ri, int32_t c, int16_t *mem) {
+    const int lane = lane_id();
+    uint64_t R[W];
+#pragma unroll
+    for (int q = 0; q < W; q++) R[q] = uniform64(ri[q]);
+    int32_t base = 0;
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+        if ((R[q] >> lane) & 1ull) mem[base + lanes_below(R[q])] = (int16_t)(q * 64 + lane);
+        base += __popcll(R[q]);
+    }
+    wave_sync();
+    uint64_t acc = 0;
+    for (int32_t a0 = 0; a0 < c; a0 += kWave) {
+        const int32_t a = a0 + lane;
+        uint64_t X[W];
+        if (a < c) {
+            const uint64_t *ra = rows + (int32_t)mem[a] * W;
+#pragma unroll
+            for (int q = 0; q < W; q++) X[q] = ra[q] & R[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < W; q++) X[q] = 0ull;
+        }
+        const int32_t p0 = __builtin_amdgcn_readfirstlane((int32_t)mem[a0]);
+        const int32_t q0 = p0 >> 6;
+        uint32_t part = 0;
+#pragma unroll
+        for (int q = 0; q < W; q++) {
+            if (q < q0) continue;
+            uint64_t m = R[q];
+            if (q == q0) m &= ~((2ull << (p0 & 63)) - 1ull);   // members above p0
+            while (m) {
+                const int bp = __builtin_ctzll(m);
+                m &= m - 1ull;
+                const uint64_t *yb = rows + (q * 64 + bp) * W;
+                uint32_t sc = 0;
+#pragma unroll
+                for (int w = q; w < W; w++) sc += (uint32_t)__popcll(X[w] & yb[w]);
+                part += (uint32_t)((X[q] >> bp) & 1ull) * sc;
+            }
+        }
+        acc += part;
+    }
+    wave_sync();
+    return acc;
+}
+
+template <int WLO, int WHI>
+__device__ __forceinline__ uint64_t lg5_dispatch(int32_t W, const uint64_t *rows, const uint64_t *ri,
+                                                 int32_t c, int16_t *mem) {
+    if constexpr (WLO > WHI) {
+        return 0;
+    } else {
+        if (W == WLO) return lg5_vertex<WLO>(rows, ri, c, mem);
+        return lg5_dispatch<WLO + 1, WHI>(W, rows, ri, c, mem);
+    }
+}
 
 template <int DMAX>
 __global__ void __launch_bounds__(1024) k_lg5(const int32_t *__restrict__ dag_off,
@@ -259,13 +361,14 @@ __global__ void __launch_bounds__(1024) k_lg5(const int32_t *__restrict__ dag_of
                                               const uint64_t *__restrict__ grows,
                                               int32_t rows_words, uint32_t *cursor,
                                               unsigned long long *result) {
-    constexpr int WMAX = DMAX / 64;
+    // row widths of the class: out-degrees (DMAX/4, DMAX]
+    constexpr int WLO = DMAX / 256 + 1, WHI = DMAX / 64;
     extern __shared__ uint64_t dyn[];
     uint64_t *rows = dyn;
     __shared__ Lds<1024> sh;
     const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
     const int NT = blockDim.x;
-    uint64_t *crow = dyn + rows_words + (int64_t)wib * kCands * kCW;
+    int16_t *mem = reinterpret_cast<int16_t *>(dyn + rows_words) + wib * DMAX;
     const int32_t nroots = *nroots_p;
     const int32_t ntasks = toff[nroots];
     uint64_t acc = 0;
@@ -283,7 +386,7 @@ __global__ void __launch_bounds__(1024) k_lg5(const int32_t *__restrict__ dag_of
         for (int32_t i = tid; i < d * W; i += NT) rows[i] = src[i];
         if (tid == 0) sh.s_next = 0;
         __syncthreads();
-        // waves take the slice's local vertices i = slice + S * c; R = row_i
+        // waves take the slice's local vertices i = slice + S * c
         for (;;) {
             uint32_t c = 0;
             if (lane == 0) c = atomicAdd(&sh.s_next, 1u);
@@ -294,89 +397,7 @@ __global__ void __launch_bounds__(1024) k_lg5(const int32_t *__restrict__ dag_of
             int32_t cnt = 0;
             for (int32_t w = 0; w < W; w++) cnt += __popcll(ri[w]);
             if (cnt < 3) continue;
-            if (cnt <= kCands) {
-                // member a of R (a-th set bit) gets row_a' = row_j & R re-encoded
-                // over R's members: CW words per row
-                const int32_t CW = (cnt + 63) >> 6;
-                for (int32_t a = lane; a < cnt; a += kWave) {
-                    int32_t w0 = 0, before = 0;
-                    for (;; w0++) {
-                        const int pc = __popcll(ri[w0]);
-                        if (a - before < pc) break;
-                        before += pc;
-                    }
-                    const int32_t j = w0 * 64 + select_bit64(ri[w0], a - before);
-                    const uint64_t *rj = rows + j * W;
-                    uint64_t cr[kCW] = {0, 0, 0, 0};
-                    int32_t base = 0;
-                    for (int32_t w = 0; w < W; w++) {
-                        const uint64_t rw = ri[w];
-                        uint64_t mm = rj[w] & rw;
-                        while (mm) {
-                            const int p = __builtin_ctzll(mm);
-                            mm &= mm - 1;
-                            const int32_t b = base + __popcll(rw & ((1ull << p) - 1));
-#pragma unroll
-                            for (int q = 0; q < kCW; q++)
-                                if ((b >> 6) == q) cr[q] |= 1ull << (b & 63);
-                        }
-                        base += __popcll(rw);
-                    }
-#pragma unroll
-                    for (int q = 0; q < kCW; q++) crow[a * kCW + q] = cr[q];
-                }
-                wave_sync();
-                // triangles of the re-encoded local DAG on R
-                for (int32_t a = lane; a < cnt; a += kWave) {
-                    uint64_t cr[kCW];
-#pragma unroll
-                    for (int q = 0; q < kCW; q++) cr[q] = crow[a * kCW + q];
-#pragma unroll
-                    for (int q = 0; q < kCW; q++) {
-                        if (q >= CW) break;
-                        uint64_t m2 = cr[q];
-                        while (m2) {
-                            const int32_t b = q * 64 + __builtin_ctzll(m2);
-                            m2 &= m2 - 1;
-                            const uint64_t *cb = crow + b * kCW;
-#pragma unroll
-                            for (int x = 0; x < kCW; x++)
-                                if (x < CW) acc += __popcll(cr[x] & cb[x]);
-                        }
-                    }
-                }
-                wave_sync();
-            } else {
-                // wider candidate sets: lane per member j, candidates in VGPRs
-                for (int32_t a0 = 0; a0 < cnt; a0 += kWave) {
-                    const int32_t a = a0 + lane;
-                    if (a >= cnt) continue;
-                    int32_t w0 = 0, before = 0;
-                    for (;; w0++) {
-                        const int pc = __popcll(ri[w0]);
-                        if (a - before < pc) break;
-                        before += pc;
-                    }
-                    const int32_t j = w0 * 64 + select_bit64(ri[w0], a - before);
-                    const uint64_t *rj = rows + j * W;
-                    uint64_t cand[WMAX];
-#pragma unroll
-                    for (int x = 0; x < WMAX; x++) cand[x] = x < W ? (ri[x] & rj[x]) : 0ull;
-#pragma unroll
-                    for (int x = 0; x < WMAX; x++) {
-                        if (x >= W) break;
-                        uint64_t cw = cand[x];
-                        while (cw) {
-                            const int32_t l = x * 64 + __builtin_ctzll(cw);
-                            cw &= cw - 1;
-                            const uint64_t *rl = rows + l * W;
-#pragma unroll
-                            for (int y = 0; y < WMAX; y++)
-                                if (y < W) acc += __popcll(cand[y] & rl[y]);
-                        }
-                    }
-                }
-            }
+            acc += lg5_dispatch<WLO, WHI>(W, rows, ri, cnt, mem);
         }
         __syncthreads();
     }
@@ -439,18 +460,18 @@ gpm_status lg5_class(const gpm_graph *g, LgWs &L, const int32_t *list, const int
     {
         Span sp(nb, st);
         hipLaunchKernelGGL((k_lg_build<DMAX, NT>), dim3((unsigned)cu_count() * (NT <= 256 ? 8 : 1)),
-                           dim3(NT), 0, st, g->dag_off, g->dag_adj, list, cnt, cursors + 0,
+                           dim3(NT), 0, st, g->off, g->dag_off, g->dag_adj, list, cnt, cursors + 0,
                            rowoff, rows, L.slices, units);
     }
     GPM_LAUNCH_CHECK("k_lg_build");
     GPM_HIP(exclusive_scan_i32(L.slices, toff, (uint64_t)n, L.scan_tmp, st));
     {
-        // LDS: rows of the class's largest local graph, then per-wave
-        // re-encoding areas; as many waves as fit in 160 KiB (at most 16)
+        // LDS: rows of the class's largest local graph, then per-wave member
+        // lists; as many waves as fit in 160 KiB (at most 16)
         const int32_t dmax = std::min<int32_t>(DMAX, std::max(g->max_out_degree, 1));
         const int32_t rows_words = dmax * ((dmax + 63) / 64);
         const int64_t lds_cap = 160 * 1024 - 1024;
-        const int64_t per_wave = (int64_t)kCands * kCW * 8;
+        const int64_t per_wave = (int64_t)DMAX * 2;
         int waves = (int)std::min<int64_t>(DMAX <= 256 ? 4 : 16,
                                            (lds_cap - (int64_t)rows_words * 8) / per_wave);
         if (waves < 1) return fail(GPM_DEVICE_ERROR, "local graph does not fit in LDS");

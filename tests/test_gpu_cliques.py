@@ -2,6 +2,8 @@
 import json
 import os
 
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -100,6 +102,34 @@ def test_clique_counts(gpm, case):
     for k in (3, 4, 5, 6):
         print(f"clique case {case} {e.name} k={k}", flush=True)
         assert gpm.count(g, gpm.clique(k)) == oracle.clique_count(off, adj, k), (e.name, k)
+
+
+@pytest.mark.parametrize("n", [130, 200, 257, 300, 520, 700])
+def test_dense_local_graphs(gpm, n):
+    """Complete graphs put every root's local graph at full density; the
+    roots' out-degrees cover local rows of 3 to 11 words."""
+    g = build(gpm, graphgen.complete_graph(n))
+    for k in (4, 5):
+        print(f"complete graph n={n} k={k}", flush=True)
+        assert gpm.count(g, gpm.clique(k)) == math.comb(n, k)
+
+
+def elementary_symmetric(parts, k):
+    e = [1] + [0] * k
+    for x in parts:
+        for j in range(k, 0, -1):
+            e[j] += e[j - 1] * x
+    return e[k]
+
+
+@pytest.mark.parametrize("parts", [[20] * 20, [7, 13, 25, 40, 3, 60, 90, 30, 50, 22, 18, 35, 11, 70]])
+def test_dense_multipartite_local_graphs(gpm, parts):
+    """Complete multipartite graphs: k-cliques = e_k(part sizes); local graphs
+    are dense but not complete, with out-degrees up to about 470."""
+    g = build(gpm, graphgen.complete_multipartite(parts))
+    for k in (3, 4, 5):
+        print(f"multipartite {len(parts)} parts k={k} max_out={g.max_out_degree}", flush=True)
+        assert gpm.count(g, gpm.clique(k)) == elementary_symmetric(parts, k)
 
 
 def test_er_workload_triangles(gpm):
