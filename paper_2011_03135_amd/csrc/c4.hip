@@ -15,8 +15,9 @@
 // every pair of middles.
 //   light apex (wedge work <= kLightW): one wave, wedges in LDS;
 //   heavy apex: tasks (x, part p) for z in the part's id range, dense LDS
-//   counters over the range; each N(y) is entered at the part by binary
-//   search.
+//   counters over the range; each N(y) is entered at the part through a
+//   part-major table of per-vertex segments, or by binary search when the
+//   table would be too large.
 #include "gpm_internal.h"
 
 #include <algorithm>
@@ -64,6 +65,14 @@ __global__ void k_degrees(const int32_t *off, int32_t n, int32_t *deg) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) deg[i] = off[i + 1] - off[i];
+}
+
+// adeg[e] = degree of the end of arc e, so the rank test of a wedge's end
+// is a coalesced read next to the arc instead of a gather.
+__global__ void k_arc_deg(const int32_t *adj, const int32_t *deg, int64_t arcs, int32_t *adeg) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < arcs; i += stride) adeg[i] = deg[adj[i]];
 }
 
 enum C4Class : int { C4_NONE = 0, C4_LIGHT = 1, C4_HEAVY = 2 };
@@ -228,6 +237,7 @@ __device__ __forceinline__ int32_t stage_in(const int32_t *__restrict__ off,
 __global__ void __launch_bounds__(kBlock) k_c4_light(const int32_t *__restrict__ off,
                                                      const int32_t *__restrict__ adj,
                                                      const int32_t *__restrict__ deg,
+                                                     const int32_t *__restrict__ adeg,
                                                      const int32_t *__restrict__ list,
                                                      const int32_t *__restrict__ count_p,
                                                      unsigned long long *out) {
@@ -251,8 +261,9 @@ __global__ void __launch_bounds__(kBlock) k_c4_light(const int32_t *__restrict__
             const int32_t q = qb + lane;
             if (q < W) {
                 const int32_t j = last_le_i32(pre, ny + 1, q);
-                const int32_t z = adj[base[j] + (q - pre[j])];
-                if (rank_less(deg[z], z, dx, x)) {
+                const int32_t e = base[j] + (q - pre[j]);
+                const int32_t z = adj[e];
+                if (rank_less(adeg[e], z, dx, x)) {
                     uint32_t h = hash_slot(z);
                     for (;;) {
                         int32_t k = key[h];
@@ -278,66 +289,127 @@ __global__ void __launch_bounds__(kBlock) k_c4_light(const int32_t *__restrict__
     if (lane == 0 && acc) atomic_add_u128(out, (u128)acc);
 }
 
-// Heavy apexes, counting: workgroup per (apex, z-part) task.
-__global__ void __launch_bounds__(kBlock) k_c4_heavy(const int32_t *__restrict__ off,
-                                                     const int32_t *__restrict__ adj,
-                                                     const int32_t *__restrict__ deg,
-                                                     const int32_t *__restrict__ list,
-                                                     const int32_t *__restrict__ count_p,
-                                                     int32_t nparts, uint32_t *cursor,
-                                                     unsigned long long *out) {
-    __shared__ uint32_t cnt[kPartZ];
-    __shared__ int32_t s_pre[kYChunk + 1];
-    __shared__ int32_t s_start[kYChunk];
-    __shared__ int32_t s_sum[kWPB];
+// Heavy apexes, counting.  Task (z-part p, apex x), part-major so that the
+// tasks running together share one part's table row and degree slice.  The
+// block keeps a dense LDS counter per z of the part; for each in-neighbour
+// y of x it takes the segment of N(y) inside the part (from the part table,
+// else by binary search in N(y)), and the block walks the concatenated
+// segments, one wedge per lane: each wedge to a z ranked below x adds the
+// count of earlier wedges to that z (the C(c, 2) sum).
+constexpr int kCountPartZ = 32768;   // z-range of a counting task (128 KiB of counters)
+constexpr int kHeavyNT = 1024;
+constexpr int kSegMaxParts = 256;    // part table only for graphs of at most 256 parts
+constexpr uint64_t kSegMaxBytes = 2ull << 30;
+
+// Part table: seg[p * n + y] = {first arc of N(y) with end >= p * kCountPartZ,
+// number of arcs of N(y) with end in part p}.
+__global__ void __launch_bounds__(kBlock) k_c4_seg(const int32_t *__restrict__ off,
+                                                   const int32_t *__restrict__ adj, int32_t n,
+                                                   int32_t nparts, int2 *seg) {
+    __shared__ int32_t s_bnd[kWPB][kSegMaxParts + 1];
+    const int lane = lane_id();
+    int32_t *bnd = s_bnd[threadIdx.x / kWave];
+    const int64_t wave0 = (int64_t)blockIdx.x * kWPB + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWPB;
+    for (int64_t y = wave0; y < n; y += nwaves) {
+        const int32_t s = off[y], d = off[y + 1] - s;
+        for (int32_t i = lane; i < d; i += kWave) {
+            const int32_t pc = adj[s + i] / kCountPartZ;
+            const int32_t pp = i == 0 ? -1 : adj[s + i - 1] / kCountPartZ;
+            for (int32_t q = pp + 1; q <= pc; q++) bnd[q] = i;
+        }
+        const int32_t plast = d > 0 ? adj[s + d - 1] / kCountPartZ : -1;
+        for (int32_t q = plast + 1 + lane; q <= nparts; q += kWave) bnd[q] = d;
+        wave_sync();
+        for (int32_t q = lane; q < nparts; q += kWave)
+            seg[(int64_t)q * n + y] = make_int2(s + bnd[q], bnd[q + 1] - bnd[q]);
+        wave_sync();
+    }
+}
+
+// Last j in [lo, hi) with pre[j] <= q, given pre[lo] <= q.
+__device__ __forceinline__ int32_t seg_of(const int32_t *pre, int32_t lo, int32_t hi, int32_t q) {
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= q) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kHeavyNT) k_c4_heavy(const int32_t *__restrict__ off,
+                                                       const int32_t *__restrict__ adj,
+                                                       const int32_t *__restrict__ adeg,
+                                                       const int32_t *__restrict__ list,
+                                                       const int32_t *__restrict__ count_p,
+                                                       int32_t n, int32_t nparts,
+                                                       const int2 *__restrict__ seg,
+                                                       uint32_t *cursor, unsigned long long *out) {
+    constexpr int NW = kHeavyNT / kWave;
+    __shared__ uint32_t cnt[kCountPartZ];
+    __shared__ int32_t s_pre[kHeavyNT + 1];
+    __shared__ int32_t s_off[kHeavyNT];    // segment start arc minus its pair prefix
+    __shared__ int32_t s_sum[NW];
     __shared__ uint32_t s_task;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
-    const uint64_t ntasks = (uint64_t)(*count_p) * (uint64_t)nparts;
+    const int32_t nheavy = *count_p;
+    const uint64_t ntasks = (uint64_t)nheavy * (uint64_t)nparts;
     uint64_t acc = 0;
-    for (int i = tid; i < kPartZ; i += kBlock) cnt[i] = 0;
+    for (int i = tid; i < kCountPartZ; i += kHeavyNT) cnt[i] = 0;
     for (;;) {
         if (tid == 0) s_task = atomicAdd(cursor, 1u);
         __syncthreads();
         const uint64_t t = s_task;
         __syncthreads();
         if (t >= ntasks) break;
-        const int32_t x = list[t / nparts];
-        const int32_t part = (int32_t)(t % nparts);
-        const int32_t z0 = part * kPartZ, z1 = z0 + kPartZ;
+        const int32_t part = (int32_t)(t / (uint64_t)nheavy);
+        const int32_t x = list[t % (uint64_t)nheavy];
+        const int32_t z0 = part * kCountPartZ, z1 = z0 + kCountPartZ;
         const int32_t s = off[x], dx = off[x + 1] - s;
-        for (int32_t c0 = 0; c0 < dx; c0 += kYChunk) {
+        for (int32_t c0 = 0; c0 < dx; c0 += kHeavyNT) {
             const int32_t i = c0 + tid;
-            int32_t len = 0, start = 0;
+            int32_t len[1] = {0}, start = 0;
             if (i < dx) {
-                const int32_t y = adj[s + i], dy = deg[y];
+                const int32_t y = adj[s + i], dy = adeg[s + i];
                 if (rank_less(dy, y, dx, x)) {
-                    const int32_t *ny = adj + off[y];
-                    const int32_t lo = lower_bound_i32(ny, dy, z0);
-                    const int32_t hi = lo + lower_bound_i32(ny + lo, dy - lo, z1);
-                    start = off[y] + lo;
-                    len = hi - lo;
+                    if (seg) {
+                        const int2 sg = seg[(int64_t)part * n + y];
+                        start = sg.x;
+                        len[0] = sg.y;
+                    } else {
+                        const int32_t oy = off[y];
+                        const int32_t lo = lower_bound_i32(adj + oy, dy, z0);
+                        const int32_t hi = lo + lower_bound_i32(adj + oy + lo, dy - lo, z1);
+                        start = oy + lo;
+                        len[0] = hi - lo;
+                    }
                 }
             }
-            const int32_t inc = wave_incl_scan(len);
-            if (lane == 63) s_sum[wid] = inc;
+            block_prefix<kHeavyNT, 1>(len, kHeavyNT, s_pre, s_sum);   // ends with a barrier
+            s_off[tid] = start - s_pre[tid];
             __syncthreads();
-            int32_t before = 0, total = 0;
-            for (int q = 0; q < kWPB; q++) {
-                if (q < wid) before += s_sum[q];
-                total += s_sum[q];
-            }
-            s_pre[tid + 1] = before + inc;
-            s_start[tid] = start;
-            if (tid == 0) s_pre[0] = 0;
-            __syncthreads();
-            for (int32_t q = tid; q < total; q += kBlock) {
-                const int32_t j = last_le_i32(s_pre, kYChunk + 1, q);
-                const int32_t z = adj[s_start[j] + (q - s_pre[j])];
-                if (rank_less(deg[z], z, dx, x)) acc += atomicAdd(&cnt[z - z0], 1u);
+            const int32_t total = s_pre[kHeavyNT];
+            // segments are short (a part of one list): each lane finds its
+            // segment by binary search in the 64 segments after the previous
+            // tile's last one, or beyond them
+            const int32_t per_wave = ((total + NW - 1) / NW + kWave - 1) / kWave * kWave;
+            const int32_t qa = min(total, wid * per_wave);
+            const int32_t qz = min(total, qa + per_wave);
+            int32_t j0 = qa < qz ? seg_of(s_pre, 0, kHeavyNT, qa) : 0;
+            for (int32_t qb = qa; qb < qz; qb += kWave) {
+                const int32_t q = qb + lane;
+                int32_t j = j0;
+                if (q < qz) {
+                    const int32_t w = min(j0 + kWave, kHeavyNT);
+                    j = s_pre[w] <= q ? seg_of(s_pre, w, kHeavyNT, q) : seg_of(s_pre, j0, w, q);
+                    const int32_t e = s_off[j] + q;
+                    const int32_t z = adj[e];
+                    if (rank_less(adeg[e], z, dx, x)) acc += atomicAdd(&cnt[z - z0], 1u);
+                }
+                j0 = __shfl(j, kWave - 1, kWave);
             }
             __syncthreads();
         }
-        for (int i = tid; i < kPartZ; i += kBlock) cnt[i] = 0;
+        for (int i = tid; i < kCountPartZ; i += kHeavyNT) cnt[i] = 0;
         __syncthreads();
     }
     acc = wave_sum(acc);
@@ -606,8 +678,17 @@ struct C4Ws {
     int32_t *deg, *cls, *flag, *pos, *light, *heavy;
     int64_t *scan_tmp;
     int32_t *wedges;               // listing: per-workgroup wedge buffers
+    int2 *seg;                     // counting: part table (null when too large)
+    int32_t *adeg;                 // counting: degree of each arc's end
     uint64_t bytes;
 };
+
+int32_t count_parts(const gpm_graph *g) { return (g->n + kCountPartZ - 1) / kCountPartZ; }
+
+bool seg_table(const gpm_graph *g) {
+    const int32_t np = count_parts(g);
+    return np <= kSegMaxParts && (uint64_t)np * (uint64_t)g->n * sizeof(int2) <= kSegMaxBytes;
+}
 
 C4Ws c4_layout(const gpm_graph *g, bool list, void *base) {
     C4Ws W{};
@@ -624,6 +705,10 @@ C4Ws c4_layout(const gpm_graph *g, bool list, void *base) {
     W.heavy = c.take<int32_t>(n1);
     W.scan_tmp = c.take<int64_t>(scan_tmp_words(n1));
     if (list) W.wedges = c.take<int32_t>((uint64_t)kListBlocks * kWedgeCap);
+    if (!list) {
+        W.adeg = c.take<int32_t>((uint64_t)std::max<int64_t>(2 * g->m, 1));
+        if (seg_table(g)) W.seg = c.take<int2>((uint64_t)count_parts(g) * (uint64_t)g->n);
+    }
     W.bytes = c.used;
     return W;
 }
@@ -675,17 +760,24 @@ gpm_status c4_run(const gpm_graph *g, bool list, void *ws, uint64_t ws_bytes,
     GPM_LAUNCH_CHECK("c4 classes");
     const int32_t nparts = (n + kPartZ - 1) / kPartZ;
     if (!list) {
+        const int32_t cparts = count_parts(g);
+        hipLaunchKernelGGL(k_arc_deg, dim3(grid_for(2 * g->m, 256, 16)), dim3(256), 0, st, g->adj,
+                           W.deg, 2 * g->m, W.adeg);
+        if (W.seg)
+            hipLaunchKernelGGL(k_c4_seg, dim3(grid_for(n, kWPB, 8)), dim3(kBlock), 0, st, g->off,
+                               g->adj, n, cparts, W.seg);
+        GPM_LAUNCH_CHECK("k_c4_seg");
         {
             Span sp("k_c4_heavy", st);
-            hipLaunchKernelGGL(k_c4_heavy, dim3((unsigned)persistent_blocks(kWPB, 4)), dim3(kBlock),
-                               0, st, g->off, g->adj, W.deg, W.heavy, cnt_heavy, nparts,
+            hipLaunchKernelGGL(k_c4_heavy, dim3((unsigned)cu_count()), dim3(kHeavyNT), 0, st,
+                               g->off, g->adj, W.adeg, W.heavy, cnt_heavy, n, cparts, W.seg,
                                W.ctl + 0, out128);
         }
         GPM_LAUNCH_CHECK("k_c4_heavy");
         {
             Span sp("k_c4_light", st);
             hipLaunchKernelGGL(k_c4_light, dim3((unsigned)persistent_blocks(kWPB, 4)), dim3(kBlock),
-                               0, st, g->off, g->adj, W.deg, W.light, cnt_light, out128);
+                               0, st, g->off, g->adj, W.deg, W.adeg, W.light, cnt_light, out128);
         }
         GPM_LAUNCH_CHECK("k_c4_light");
         return GPM_OK;
