@@ -11,12 +11,19 @@ the degree-ordered DAG on the device and counts triangles, 4-cliques and
 One JSON line:
   value             undirected edges per second of the whole step
   matches_per_sec   (triangles + 4-cliques + 5-cliques) per second
+  per_problem       each counting call timed alone (HIP events around it on
+                    the launch stream): ms, edges/s and matches/s
   phases_ms         per-kernel milliseconds per step, HIP events recorded on
                     the launch stream by the library's timing spans
-  roofline          the dominant kernel against its bound (see DESIGN.md)
+  roofline          the dominant kernel against its bound
+  phase_rooflines   the triangle and 4-clique calls against the HBM roofline
+                    on the algorithmic bytes of their pair scans
   batched_vs_plain  20,000 random geometric graphs (n in [10, 200]), induced
                     4-motif counts: one fused launch replayed from a HIP
-                    graph vs one library call per graph on prebuilt graphs
+                    graph (configuration picked by the autotuner) vs one
+                    library call per graph on prebuilt graphs
+  serving           Poisson load of mixed queries on 8 resident graphs:
+                    throughput and p50/p99 latency
   cpu_baseline      the CPU oracle on a bounded sample of the same workload
 """
 import argparse
@@ -43,6 +50,30 @@ INT32_VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 OPS_PER_LOCAL_TRIANGLE = 4
 
 
+# HBM bytes per launch of the dominant kernel from two rocprofv3 counter runs
+# (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a 1 GiB copy
+# (profiles/rmat20_cliques_hbm_traffic.md); valid only while the kernel's
+# source is the one measured.
+MEASURED_TRAFFIC = {
+    "kernel": "k_lg5<1024>",
+    "source": "paper_2011_03135_amd/csrc/local_graph.hip",
+    "source_sha256_prefix": "663bc6bb1b524cb7",
+    "bytes_read": 267540 * 1024 * 2,
+    "bytes_written": 959 * 1024,
+}
+
+
+def measured_traffic(kernel):
+    import hashlib
+    t = MEASURED_TRAFFIC
+    if kernel != t["kernel"]:
+        return None
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != t["source_sha256_prefix"]:
+            return None
+    return t["bytes_read"] + t["bytes_written"]
+
+
 def dag_class_bytes(off, adj, dmin, dmax, kmin):
     """Algorithmic bytes of one triangle/local-graph-build launch over the
     roots u with dmin < d+(u) <= dmax and d+(u) >= kmin: per root, its
@@ -67,7 +98,8 @@ def roofline(dom, ms, units, off, adj):
         ops = OPS_PER_LOCAL_TRIANGLE * units
         ach = ops / (ms * 1e-3) / 1e12
         return {"kernel": dom, "bound": "alu", "achieved": ach, "peak": INT32_VALU_PEAK_TOPS,
-                "unit": "TOP/s (int32)", "frac": ach / INT32_VALU_PEAK_TOPS, "traffic": None,
+                "unit": "TOP/s (int32)", "frac": ach / INT32_VALU_PEAK_TOPS,
+                "traffic": measured_traffic(dom), "traffic_unit": "bytes per launch",
                 "units_per_launch": units, "unit_name": "local triangles",
                 "ops_per_unit": OPS_PER_LOCAL_TRIANGLE, "avg_launch_ms": ms}
     if dom.startswith("k_tc_flat"):
@@ -83,6 +115,18 @@ def roofline(dom, ms, units, off, adj):
     return {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": None, "alg_bytes_per_launch": b,
             "pairs_per_launch": pairs, "device_units": units, "avg_launch_ms": ms}
+
+
+def phase_roofline(name, ms, off, adj, kmin):
+    """HBM roofline of a whole counting call (all its kernels) on the
+    algorithmic bytes of its pair scan: every root with d+ >= kmin reads its
+    out-list and its out-neighbours' offsets (12 B per arc) and each
+    out-neighbour's out-list once (4 B per pair); everything after that runs
+    on chip (LDS hash, LDS bit rows)."""
+    b, arcs, pairs = dag_class_bytes(off, adj, 0, 1 << 30, kmin)
+    ach = b / (ms * 1e-3) / 1e9
+    return {"phase": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "alg_bytes": b, "arcs": arcs, "pairs": pairs, "ms": ms}
 
 
 def cpu_baseline(e, fraction_inv, ks, threads):
@@ -187,7 +231,27 @@ def serve_leg(gpm, torch, g20, scale, requests, warmup):
                           progress=lambda d, t: log(f"serving: {d}/{t} requests done"))
     stats["graphs"] = names
     stats["latency"] = "arrival to result visible on the host"
+    # the same mix offered below the measured capacity, for latency without
+    # queue growth
+    low_rate = max(10.0, 0.6 * stats["throughput_rps"])
+    low, _ = run_load(graphs, rate=low_rate, n_requests=max(200, requests // 5),
+                      n_warmup=max(20, warmup // 5), seed=501, max_slots=4, pool_bytes=48 << 30,
+                      progress=lambda d, t: log(f"serving (below capacity): {d}/{t} requests done"))
+    stats["below_capacity"] = {k: low[k] for k in ("offered_rate", "requests", "throughput_rps",
+                                                   "p50_ms", "p99_ms", "mean_queue_ms", "failed",
+                                                   "per_query")}
     return stats
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 30
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}))
 
 
 def main():
@@ -206,7 +270,13 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--serve-warmup", type=int, default=500)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device to device three times (reference kernel "
+                         "for scaling hardware byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -237,10 +307,19 @@ def main():
     out = torch.zeros(len(ks), dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
 
-    def step():
+    phase_names = ["graph_build"] + [f"clique{k}" for k in ks]
+    phase_ms = [0.0] * len(phase_names)
+
+    def step(events=None):
+        if events is not None:
+            events[0].record(stream)
         g = gpm.Graph.build(e.n, u, v, storage=storage, scratch=scratch)
+        if events is not None:
+            events[1].record(stream)
         for i, p in enumerate(pats):
             gpm.count(g, p, ws=ws, out=out[i:i + 1])
+            if events is not None:
+                events[i + 2].record(stream)
         return g
 
     for _ in range(args.warmup):
@@ -249,14 +328,19 @@ def main():
     gpm.timing_enable(True)
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(phase_names) + 1)]
+          for _ in range(args.steps)]
     t_start.record(stream)
-    for _ in range(args.steps):
-        step()
+    for i in range(args.steps):
+        step(ev[i])
     t_end.record(stream)
     torch.cuda.synchronize()
     gpm.timing_enable(False)
     spans = gpm.timing_read()
     ms_step = t_start.elapsed_time(t_end) / args.steps
+    for evs in ev:
+        for i in range(len(phase_names)):
+            phase_ms[i] += evs[i].elapsed_time(evs[i + 1]) / args.steps
     counts = [int(x) for x in out.tolist()]
 
     phases, units = {}, {}
@@ -265,6 +349,16 @@ def main():
         units[name] = units.get(name, 0) + un / args.steps
     dom = max((k for k in phases if k != "graph_build"), key=lambda k: phases[k])
     roof = roofline(dom, phases[dom], int(units[dom]), off_h, adj_h)
+    per_problem = {"graph_build": {"ms": phase_ms[0]}}
+    for k, c, ms in zip(ks, counts, phase_ms[1:]):
+        per_problem[f"{k}-clique" if k > 3 else "TC"] = {
+            "ms": ms, "edges_per_sec": m / (ms * 1e-3), "matches_per_sec": c / (ms * 1e-3)}
+    phase_roof = {}
+    if 3 in ks:
+        phase_roof["TC"] = phase_roofline("TC", phase_ms[1 + ks.index(3)], off_h, adj_h, 2)
+    if 4 in ks:
+        phase_roof["4-clique"] = phase_roofline("4-clique", phase_ms[1 + ks.index(4)], off_h,
+                                                adj_h, 3)
 
     res = {
         "metric": "edges/sec & matches/sec for TC and 4-clique on RMAT-20; batched vs plain speedup",
@@ -287,9 +381,11 @@ def main():
         },
         "counts": {f"clique{k}": c for k, c in zip(ks, counts)},
         "matches_per_sec": sum(counts) / (ms_step * 1e-3),
-        "count_phase_edges_per_sec": m / ((ms_step - phases.get("graph_build", 0.0)) * 1e-3),
+        "count_phase_edges_per_sec": m / (sum(phase_ms[1:]) * 1e-3),
+        "per_problem": per_problem,
         "phases_ms": {k: round(x, 4) for k, x in phases.items()},
         "roofline": roof,
+        "phase_rooflines": phase_roof,
     }
     log(f"timed {args.steps} steps: {ms_step:.2f} ms/step")
     if not args.no_batch:
