@@ -54,7 +54,8 @@ typedef int32_t gpm_status;
 #define GPM_DEVICE_ERROR      3  /* a HIP call failed; see gpm_last_error() */
 #define GPM_TRUNCATED         4  /* (reported in listing results, see gpm_list) */
 #define GPM_UNSUPPORTED       5  /* pattern or size outside what is implemented */
-#define GPM_NOT_CANONICAL     6  /* input ids out of range */
+#define GPM_NOT_CANONICAL     6  /* input not in the required form (ids out of range, a
+                                    failed CSR check) */
 #define GPM_INCONSISTENT      7  /* an exact-division check of a formula failed */
 
 /* Static string naming a status code. */
@@ -132,6 +133,26 @@ gpm_status gpm_graph_build(int32_t n, const int32_t *d_u, const int32_t *d_v,
                            int64_t n_input_edges, void *d_graph_mem, uint64_t graph_bytes,
                            void *d_scratch, uint64_t scratch_bytes, void *stream,
                            gpm_graph **out);
+
+/* Sizes for gpm_graph_from_csr: a graph on n vertices whose symmetric CSR has
+ * nnz = 2m entries.  nnz must be even and below 2^31. */
+gpm_status gpm_graph_from_csr_bytes(int32_t n, int64_t nnz, uint64_t *graph_bytes,
+                                    uint64_t *scratch_bytes);
+
+/* Graph from a caller's symmetric CSR already in the method's input form
+ * (Section 6, input-graph table caption): d_offsets int32[n+1] with
+ * d_offsets[0] = 0 and d_offsets[n] = nnz, d_adj int32[nnz] (device).  Both
+ * are copied into d_graph_mem (same layout as gpm_graph_build) and the graph
+ * is oriented by degree (Appendix B.2).  Always checked on the device:
+ * offsets ascending and consistent with nnz, ids in [0, n).  With
+ * validate != 0 also: rows strictly ascending, no self-loops, every arc
+ * present in both directions.  A failed check gives GPM_NOT_CANONICAL (*out
+ * not set); with validate == 0 a graph outside the form gives undefined
+ * counts.  Synchronises `stream` once. */
+gpm_status gpm_graph_from_csr(int32_t n, const int32_t *d_offsets, const int32_t *d_adj,
+                              int64_t nnz, int32_t validate, void *d_graph_mem,
+                              uint64_t graph_bytes, void *d_scratch, uint64_t scratch_bytes,
+                              void *stream, gpm_graph **out);
 
 typedef struct gpm_graph_info {
     int32_t n;              /* vertices */

@@ -66,6 +66,8 @@ def load():
         "gpm_pattern_plan": ([P, P], i32),
         "gpm_graph_build_bytes": ([i32, i64, P, P], i32),
         "gpm_graph_build": ([i32, P, P, i64, P, u64, P, u64, P, P], i32),
+        "gpm_graph_from_csr_bytes": ([i32, i64, P, P], i32),
+        "gpm_graph_from_csr": ([i32, P, P, i64, i32, P, u64, P, u64, P, P], i32),
         "gpm_graph_get_info": ([P, P], i32),
         "gpm_graph_release": ([P], None),
         "gpm_workspace_bytes": ([P, P, P], i32),
@@ -188,6 +190,35 @@ class Graph:
         _check(load().gpm_graph_build(int(n), _ptr(u), _ptr(v), int(u.shape[0]), _ptr(storage),
                                       gb, _ptr(scratch), sb, _stream(stream), ctypes.byref(h)))
         return cls(h, storage, u.device)
+
+    @staticmethod
+    def from_csr_bytes(n, nnz):
+        gb, sb = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load().gpm_graph_from_csr_bytes(int(n), int(nnz), ctypes.byref(gb),
+                                               ctypes.byref(sb)))
+        return gb.value, sb.value
+
+    @classmethod
+    def from_csr(cls, n, off, adj, validate=True, stream=None, scratch=None, storage=None):
+        """gpm_graph_from_csr from int32 CUDA tensors off [n+1] and adj [nnz]
+        holding a symmetric CSR in canonical form (checked when validate)."""
+        for t in (off, adj):
+            if t.dtype != torch.int32 or not t.is_cuda or t.dim() != 1:
+                raise TypeError("off and adj must be 1-D int32 CUDA tensors")
+        if off.shape[0] != int(n) + 1:
+            raise ValueError("off must have n + 1 entries")
+        off = off.contiguous()
+        adj = adj.contiguous()
+        gb, sb = cls.from_csr_bytes(n, adj.shape[0])
+        if storage is None or storage.numel() < gb:
+            storage = _buffer(gb, off.device)
+        if scratch is None or scratch.numel() < sb:
+            scratch = _buffer(sb, off.device)
+        h = ctypes.c_void_p()
+        _check(load().gpm_graph_from_csr(int(n), _ptr(off), _ptr(adj), int(adj.shape[0]),
+                                         1 if validate else 0, _ptr(storage), gb, _ptr(scratch),
+                                         sb, _stream(stream), ctypes.byref(h)))
+        return cls(h, storage, off.device)
 
     def csr(self):
         """(off, adj) views (int32 device tensors) of the symmetric CSR."""

@@ -10,6 +10,10 @@
 
 namespace gpm {
 gpm_status graph_build_bytes(int32_t n, int64_t E, uint64_t *gb, uint64_t *sb);
+gpm_status graph_from_csr_bytes(int32_t n, int64_t nnz, uint64_t *gb, uint64_t *sb);
+gpm_status graph_from_csr(int32_t n, const int32_t *d_off, const int32_t *d_adj, int64_t nnz,
+                          int32_t validate, void *gmem, uint64_t gbytes, void *smem,
+                          uint64_t sbytes, hipStream_t st, gpm_graph **out);
 gpm_status graph_build(int32_t n, const int32_t *d_u, const int32_t *d_v, int64_t E, void *gmem,
                        uint64_t gbytes, void *smem, uint64_t sbytes, hipStream_t st,
                        gpm_graph **out);
@@ -184,6 +188,20 @@ gpm_status gpm_graph_build(int32_t n, const int32_t *d_u, const int32_t *d_v,
                            gpm_graph **out) {
     return gpm::graph_build(n, d_u, d_v, n_input_edges, d_graph_mem, graph_bytes, d_scratch,
                             scratch_bytes, static_cast<hipStream_t>(stream), out);
+}
+
+gpm_status gpm_graph_from_csr_bytes(int32_t n, int64_t nnz, uint64_t *graph_bytes,
+                                    uint64_t *scratch_bytes) {
+    if (!graph_bytes || !scratch_bytes) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    return gpm::graph_from_csr_bytes(n, nnz, graph_bytes, scratch_bytes);
+}
+
+gpm_status gpm_graph_from_csr(int32_t n, const int32_t *d_offsets, const int32_t *d_adj,
+                              int64_t nnz, int32_t validate, void *d_graph_mem,
+                              uint64_t graph_bytes, void *d_scratch, uint64_t scratch_bytes,
+                              void *stream, gpm_graph **out) {
+    return gpm::graph_from_csr(n, d_offsets, d_adj, nnz, validate, d_graph_mem, graph_bytes,
+                               d_scratch, scratch_bytes, static_cast<hipStream_t>(stream), out);
 }
 
 gpm_status gpm_graph_get_info(const gpm_graph *g, gpm_graph_info *info) {

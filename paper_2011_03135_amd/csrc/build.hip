@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(kBlock) k_orient_count(const int32_t *__restri
 __global__ void __launch_bounds__(kBlock) k_orient_fill(const int32_t *__restrict__ off,
                                                         const int32_t *__restrict__ adj,
                                                         const int32_t *__restrict__ dag_off,
-                                                        int32_t n, int32_t *dag_adj,
+                                                        int32_t n, int64_t cap, int32_t *dag_adj,
                                                         int32_t *dag_src, uint32_t *flags) {
     const int lane = lane_id();
     const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
@@ -264,8 +264,12 @@ __global__ void __launch_bounds__(kBlock) k_orient_fill(const int32_t *__restric
             uint64_t mask = __ballot(keep);
             if (keep) {
                 int32_t p = base + lanes_below(mask);
-                dag_adj[p] = v;
-                dag_src[p] = u;
+                if (p < cap) {
+                    dag_adj[p] = v;
+                    dag_src[p] = u;
+                } else {
+                    atomicOr(&flags[F_ERR], 4u);   // more arcs than the storage holds
+                }
             }
             base += __popcll(mask);
         }
@@ -285,6 +289,58 @@ __global__ void k_meta(const int32_t *off, const int32_t *dag_off, int32_t n,
         meta[4] = flags[F_ERR];
         meta[5] = flags[F_BIG_COUNT];
     }
+}
+
+// Checks of a caller's CSR (one wave per row).  Always: offsets ascending
+// and within [0, nnz], ids in [0, n); with FULL also strictly ascending rows,
+// no self-loop, and every arc (u, w) matched by (w, u).  Any failure sets
+// F_ERR; the largest degree goes to F_MAX_DEG.
+template <bool FULL>
+__global__ void __launch_bounds__(kBlock) k_check_csr(const int32_t *__restrict__ off,
+                                                      const int32_t *__restrict__ adj, int32_t n,
+                                                      int64_t nnz, uint32_t *flags) {
+    const int lane = lane_id();
+    const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (off[0] != 0 || (int64_t)off[n] != nnz))
+        atomicOr(&flags[F_ERR], 2u);
+    int32_t maxd = 0;
+    for (int64_t row = wave0; row < n; row += nwaves) {
+        const int32_t u = (int32_t)row;
+        const int32_t s = off[u], e = off[u + 1];
+        if (s < 0 || e < s || (int64_t)e > nnz) {
+            if (lane == 0) atomicOr(&flags[F_ERR], 2u);
+            continue;
+        }
+        maxd = max(maxd, e - s);
+        bool bad = false;
+        for (int32_t i = s + lane; i < e; i += kWave) {
+            const int32_t w = adj[i];
+            if (w < 0 || w >= n) {
+                bad = true;
+                continue;
+            }
+            if (FULL) {
+                if (w == u || (i > s && adj[i - 1] >= w)) bad = true;
+                // (w, u) present: binary search u in N(w), whose bounds are
+                // checked first
+                const int32_t ws = off[w], we = off[w + 1];
+                if (ws < 0 || we < ws || (int64_t)we > nnz) {
+                    bad = true;
+                    continue;
+                }
+                int32_t lo = ws, hi = we;
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi) >> 1;
+                    if (adj[mid] < u) lo = mid + 1; else hi = mid;
+                }
+                if (lo >= we || adj[lo] != u) bad = true;
+            }
+        }
+        if (__any(bad) && lane == 0) atomicOr(&flags[F_ERR], 2u);
+    }
+    maxd = wave_max(maxd);
+    if (lane == 0 && maxd > 0) atomicMax(&flags[F_MAX_DEG], (uint32_t)maxd);
 }
 
 struct BuildLayout {
@@ -395,6 +451,89 @@ gpm_status graph_build(int32_t n, const int32_t *d_u, const int32_t *d_v, int64_
     return GPM_OK;
 }
 
+gpm_status graph_from_csr_bytes(int32_t n, int64_t nnz, uint64_t *gb, uint64_t *sb) {
+    if (n < 1 || n > INT32_MAX - 1) return fail(GPM_INVALID_ARGUMENT, "n must be in [1, 2^31-2]");
+    if (nnz < 0 || (nnz & 1) || nnz >= (int64_t)INT32_MAX)
+        return fail(GPM_UNSUPPORTED, "nnz must be even and below 2^31");
+    BuildLayout L = layout(n, nnz / 2, nullptr, nullptr);
+    *gb = L.graph_bytes;
+    Carve s(nullptr, ~0ull);
+    s.take<int32_t>((uint64_t)n + 1);                              // out-degrees
+    s.take<int64_t>(scan_tmp_words((uint64_t)n + 1));
+    s.take<uint32_t>(F_WORDS);
+    *sb = s.used;
+    return GPM_OK;
+}
+
+gpm_status graph_from_csr(int32_t n, const int32_t *d_off, const int32_t *d_adj, int64_t nnz,
+                          int32_t validate, void *gmem, uint64_t gbytes, void *smem,
+                          uint64_t sbytes, hipStream_t st, gpm_graph **out) {
+    uint64_t need_g, need_s;
+    gpm_status rc = graph_from_csr_bytes(n, nnz, &need_g, &need_s);
+    if (rc != GPM_OK) return rc;
+    if (!out) return fail(GPM_INVALID_ARGUMENT, "out is NULL");
+    if (!d_off || (nnz > 0 && !d_adj)) return fail(GPM_INVALID_ARGUMENT, "CSR arrays are NULL");
+    if (!gmem || !smem) return fail(GPM_INVALID_ARGUMENT, "graph or scratch memory is NULL");
+    if (((uintptr_t)gmem & 255) || ((uintptr_t)smem & 255))
+        return fail(GPM_INVALID_ARGUMENT, "device buffers must be 256-byte aligned");
+    if (gbytes < need_g || sbytes < need_s)
+        return fail(GPM_OUT_OF_MEMORY, "graph or scratch buffer smaller than required");
+    BuildLayout L = layout(n, nnz / 2, gmem, nullptr);
+    Carve sc(smem, ~0ull);
+    int32_t *outcnt = sc.take<int32_t>((uint64_t)n + 1);
+    int64_t *scan_tmp = sc.take<int64_t>(scan_tmp_words((uint64_t)n + 1));
+    uint32_t *flags = sc.take<uint32_t>(F_WORDS);
+    {
+        Span whole("graph_from_csr", st);
+        GPM_HIP(fill_u32(flags, 0, F_WORDS, st));
+        GPM_HIP(hipMemcpyAsync(L.off, d_off, sizeof(int32_t) * ((size_t)n + 1),
+                               hipMemcpyDeviceToDevice, st));
+        if (nnz > 0)
+            GPM_HIP(hipMemcpyAsync(L.adj, d_adj, sizeof(int32_t) * (size_t)nnz,
+                                   hipMemcpyDeviceToDevice, st));
+        if (validate)
+            hipLaunchKernelGGL(k_check_csr<true>, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.off,
+                               L.adj, n, nnz, flags);
+        else
+            hipLaunchKernelGGL(k_check_csr<false>, dim3(wave_grid(n)), dim3(kBlock), 0, st,
+                               L.off, L.adj, n, nnz, flags);
+        GPM_LAUNCH_CHECK("k_check_csr");
+        // orientation needs a valid CSR: read the check result first
+        int64_t meta[8] = {0};
+        hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, st, L.off, L.off, n, flags, L.meta);
+        GPM_HIP(hipMemcpyAsync(meta, L.meta, sizeof(int64_t) * 6, hipMemcpyDeviceToHost, st));
+        GPM_HIP(hipStreamSynchronize(st));
+        if (meta[4] != 0) return fail(GPM_NOT_CANONICAL, "the CSR is not in canonical form");
+        hipLaunchKernelGGL(k_orient_count, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.off, L.adj,
+                           n, outcnt);
+        GPM_LAUNCH_CHECK("k_orient_count");
+        GPM_HIP(exclusive_scan_i32(outcnt, L.dag_off, (uint64_t)n, scan_tmp, st));
+        hipLaunchKernelGGL(k_orient_fill, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.off, L.adj,
+                           L.dag_off, n, nnz / 2, L.dag_adj, L.dag_src, flags);
+        GPM_LAUNCH_CHECK("k_orient_fill");
+        hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, st, L.off, L.dag_off, n, flags, L.meta);
+        GPM_LAUNCH_CHECK("k_meta");
+    }
+    int64_t meta[8] = {0};
+    GPM_HIP(hipMemcpyAsync(meta, L.meta, sizeof(int64_t) * 6, hipMemcpyDeviceToHost, st));
+    GPM_HIP(hipStreamSynchronize(st));
+    if (meta[4] != 0 || meta[0] != nnz || meta[1] * 2 != meta[0])
+        return fail(GPM_NOT_CANONICAL, "the CSR is not symmetric");
+    gpm_graph *g = new (std::nothrow) gpm_graph;
+    if (!g) return fail(GPM_OUT_OF_MEMORY, "host allocation of the graph handle failed");
+    g->n = n;
+    g->m = meta[1];
+    g->max_degree = (int32_t)meta[2];
+    g->max_out_degree = (int32_t)meta[3];
+    g->off = L.off;
+    g->adj = L.adj;
+    g->dag_off = L.dag_off;
+    g->dag_adj = L.dag_adj;
+    g->dag_src = L.dag_src;
+    *out = g;
+    return GPM_OK;
+}
+
 // All build kernels, in stream order (a1 then a2).
 static gpm_status enqueue_build(int32_t n, const int32_t *d_u, const int32_t *d_v, int64_t E,
                          const BuildLayout &L, hipStream_t st) {
@@ -428,7 +567,7 @@ static gpm_status enqueue_build(int32_t n, const int32_t *d_u, const int32_t *d_
     GPM_LAUNCH_CHECK("k_orient_count");
     GPM_HIP(exclusive_scan_i32(L.outcnt, L.dag_off, (uint64_t)n, L.scan_tmp, st));
     hipLaunchKernelGGL(k_orient_fill, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.off, L.adj,
-                       L.dag_off, n, L.dag_adj, L.dag_src, L.flags);
+                       L.dag_off, n, E, L.dag_adj, L.dag_src, L.flags);
     GPM_LAUNCH_CHECK("k_orient_fill");
     hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, st, L.off, L.dag_off, n, L.flags, L.meta);
     GPM_LAUNCH_CHECK("k_meta");

@@ -74,6 +74,56 @@ def test_build_matches_oracle(gpm, case):
     assert g.max_out_degree == int(np.diff(dag_off).max())
 
 
+@pytest.mark.parametrize("case", range(4))
+def test_from_csr_equals_build(gpm, case):
+    """A graph made from a canonical CSR equals the one built from the edge
+    stream: same CSR, DAG and counts."""
+    e = [graphgen.rmat(12, seed=5), graphgen.erdos_renyi(500, 0.05, 3),
+         graphgen.complete_graph(40), graphgen.star_graph(50)][case]
+    g = build(gpm, e)
+    off, adj = g.csr()
+    h = gpm.Graph.from_csr(e.n, off.clone(), adj.clone(), validate=True)
+    assert (h.n, h.m, h.max_degree, h.max_out_degree) == (g.n, g.m, g.max_degree,
+                                                            g.max_out_degree)
+    for a, b in zip(g.dag(), h.dag()):
+        assert torch.equal(a, b)
+    for k in (3, 4, 5):
+        assert gpm.count(h, gpm.clique(k)) == gpm.count(g, gpm.clique(k))
+    assert gpm.motif_count(h, 4) == gpm.motif_count(g, 4)
+
+
+def test_from_csr_rejects_non_canonical(gpm):
+    e = graphgen.erdos_renyi(200, 0.05, 4)
+    g = build(gpm, e)
+    off, adj = (t.clone() for t in g.csr())
+    bad_cases = []
+    a = adj.clone()
+    a[0], a[1] = adj[1], adj[0]                     # row 0 out of order
+    bad_cases.append((off, a, True))
+    a = adj.clone()
+    a[5] = 10 ** 6                                  # id out of range
+    bad_cases.append((off, a, False))
+    o = off.clone()
+    o[-1] = o[-1] - 2                               # offsets inconsistent with nnz
+    bad_cases.append((o, adj, False))
+    # one direction of an edge missing: move the last arc of a row to the
+    # next id, which is not yet a neighbour (rows stay sorted, nnz even)
+    oh, ah = off.cpu().numpy(), adj.cpu().numpy()
+    r = next(r for r in range(e.n) if oh[r + 1] > oh[r]
+             and ah[oh[r + 1] - 1] + 1 < e.n and ah[oh[r + 1] - 1] + 1 != r)
+    a = adj.clone()
+    last = int(oh[r + 1]) - 1
+    a[last] = a[last] + 1
+    bad_cases.append((off, a, True))
+    for o_, a_, validate in bad_cases:
+        with pytest.raises(gpm.GpmError) as ei:
+            gpm.Graph.from_csr(e.n, o_, a_, validate=validate)
+        assert ei.value.status == 6
+    with pytest.raises(gpm.GpmError) as ei:          # odd nnz
+        gpm.Graph.from_csr(e.n, off, adj[:-1].clone())
+    assert ei.value.status == 5
+
+
 def test_build_rejects_out_of_range(gpm):
     e = graphgen.EdgeList(4, np.array([0, 1], np.int32), np.array([1, 4], np.int32))
     with pytest.raises(gpm.GpmError) as ei:
