@@ -195,6 +195,18 @@ gpm_status gpm_count(const gpm_graph *g, const gpm_pattern *p, void *d_ws, uint6
 gpm_status gpm_list(const gpm_graph *g, const gpm_pattern *p, void *d_ws, uint64_t ws_bytes,
                     int32_t *d_buf, uint64_t cap, uint64_t *d_result, void *stream);
 
+/* Triangles, 4-cliques and (kmax = 5) 5-cliques of g in one pass: the
+ * local graph on N+(u) (Section 5, search on a local graph) holds the
+ * triangles at root u as its edges, the 4-cliques at u as its triangles and
+ * the 5-cliques at u as its 4-cliques, so one build per root serves every
+ * size (the per-size calls of gpm_count build it once per size).  Writes
+ * d_counts (device uint64[kmax - 2]) = {3-cliques, 4-cliques[, 5-cliques]},
+ * the same values as gpm_count per size.  kmax must be 4 or 5; graphs with
+ * an out-degree above 1024 give GPM_UNSUPPORTED (count per size instead). */
+gpm_status gpm_clique_counts_workspace_bytes(const gpm_graph *g, int32_t kmax, uint64_t *bytes);
+gpm_status gpm_clique_counts(const gpm_graph *g, int32_t kmax, void *d_ws, uint64_t ws_bytes,
+                             uint64_t *d_counts, void *stream);
+
 /* ----------------------------------------------------------- motifs --- */
 
 /* Workspace needed by gpm_motif_count(g, k). */

@@ -18,6 +18,7 @@ from .binding import (  # noqa: F401
     batch_default_config,
     batch_motif_count,
     clique,
+    clique_counts,
     count,
     diamond,
     cycle4,

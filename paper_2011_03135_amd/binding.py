@@ -73,6 +73,8 @@ def load():
         "gpm_workspace_bytes": ([P, P, P], i32),
         "gpm_count": ([P, P, P, u64, P, P], i32),
         "gpm_list": ([P, P, P, u64, P, u64, P, P], i32),
+        "gpm_clique_counts_workspace_bytes": ([P, i32, P], i32),
+        "gpm_clique_counts": ([P, i32, P, u64, P, P], i32),
         "gpm_motif_workspace_bytes": ([P, i32, P], i32),
         "gpm_motif_count": ([P, i32, P, u64, P, P], i32),
         "gpm_batch_workspace_bytes": ([i32, i32, P], i32),
@@ -292,6 +294,30 @@ def list_embeddings(g, p, cap, stream=None, ws=None):
                            _ptr(res), _stream(stream)))
     total, written, chk = (_u64(x) for x in res.tolist())
     return total, written, chk, buf[:written]
+
+
+def clique_counts_workspace_bytes(g, kmax):
+    b = ctypes.c_uint64()
+    _check(load().gpm_clique_counts_workspace_bytes(g.handle, int(kmax), ctypes.byref(b)))
+    return b.value
+
+
+def clique_counts(g, kmax, stream=None, ws=None, out=None):
+    """gpm_clique_counts: [3-cliques, ..., kmax-cliques] from one pass.  With
+    `out` (int64 device tensor of kmax - 2 entries) the call only enqueues
+    and returns `out`; otherwise it waits and returns Python ints."""
+    need = clique_counts_workspace_bytes(g, kmax)
+    if ws is None:
+        ws = _buffer(need, g.device)
+    elif ws.numel() < need:
+        raise GpmError(2, f"workspace of {ws.numel()} bytes, {need} needed")
+    res = out if out is not None else torch.zeros(int(kmax) - 2, dtype=torch.int64,
+                                                  device=g.device)
+    _check(load().gpm_clique_counts(g.handle, int(kmax), _ptr(ws), ws.numel(), _ptr(res),
+                                    _stream(stream)))
+    if out is not None:
+        return out
+    return [_u64(x) for x in res.tolist()]
 
 
 def motif_workspace_bytes(g, k):

@@ -10,6 +10,9 @@
 
 namespace gpm {
 gpm_status graph_build_bytes(int32_t n, int64_t E, uint64_t *gb, uint64_t *sb);
+gpm_status clique_multi_workspace_bytes(const gpm_graph *g, int32_t kmax, uint64_t *bytes);
+gpm_status clique_multi_run(const gpm_graph *g, int32_t kmax, void *ws, uint64_t ws_bytes,
+                            unsigned long long *d_counts, hipStream_t st);
 gpm_status graph_from_csr_bytes(int32_t n, int64_t nnz, uint64_t *gb, uint64_t *sb);
 gpm_status graph_from_csr(int32_t n, const int32_t *d_off, const int32_t *d_adj, int64_t nnz,
                           int32_t validate, void *gmem, uint64_t gbytes, void *smem,
@@ -266,6 +269,26 @@ gpm_status gpm_list(const gpm_graph *g, const gpm_pattern *p, void *d_ws, uint64
     if (plan == GPM_PLAN_CLIQUE_DAG)
         return gpm::clique_run(g, p->k, true, d_ws, ws_bytes, nullptr, d_buf, cap, res, st);
     return gpm::sl_run(g, plan, true, d_ws, ws_bytes, nullptr, d_buf, cap, res, st);
+}
+
+gpm_status gpm_clique_counts_workspace_bytes(const gpm_graph *g, int32_t kmax, uint64_t *bytes) {
+    gpm_status rc = check_graph(g);
+    if (rc) return rc;
+    if (!bytes) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    if (kmax != 4 && kmax != 5) return fail(GPM_UNSUPPORTED, "kmax must be 4 or 5");
+    return gpm::clique_multi_workspace_bytes(g, kmax, bytes);
+}
+
+gpm_status gpm_clique_counts(const gpm_graph *g, int32_t kmax, void *d_ws, uint64_t ws_bytes,
+                             uint64_t *d_counts, void *stream) {
+    gpm_status rc = check_graph(g);
+    if (rc) return rc;
+    if (!d_counts) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    if (kmax != 4 && kmax != 5) return fail(GPM_UNSUPPORTED, "kmax must be 4 or 5");
+    if (!d_ws || !aligned256(d_ws)) return fail(GPM_INVALID_ARGUMENT, "workspace NULL or unaligned");
+    return gpm::clique_multi_run(g, kmax, d_ws, ws_bytes,
+                                 reinterpret_cast<unsigned long long *>(d_counts),
+                                 static_cast<hipStream_t>(stream));
 }
 
 gpm_status gpm_motif_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes) {

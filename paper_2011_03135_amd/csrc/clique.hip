@@ -34,8 +34,9 @@ namespace gpm {
 
 gpm_status lg_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes);
 gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, const int32_t *cnt_m,
-                      const int32_t *list_b, const int32_t *cnt_b, const int32_t *work, void *ws,
-                      uint64_t ws_bytes, unsigned long long *res, hipStream_t st);
+                      const int32_t *list_b, const int32_t *cnt_b, void *ws, uint64_t ws_bytes,
+                      unsigned long long *res, unsigned long long *res3,
+                      unsigned long long *res4, hipStream_t st);
 
 namespace {
 
@@ -286,14 +287,16 @@ __global__ void __launch_bounds__(kWave) k_clique_wave(const int32_t *__restrict
                                                        const int32_t *__restrict__ dag_adj,
                                                        const int32_t *__restrict__ roots,
                                                        const int32_t *__restrict__ nroots_p,
-                                                       unsigned long long *result) {
+                                                       unsigned long long *result,
+                                                       unsigned long long *res3,
+                                                       unsigned long long *res4) {
     __shared__ uint64_t rows[kWave];
     __shared__ int32_t keys[4 * kWave];
     __shared__ int16_t vals[4 * kWave];
     __shared__ int32_t pre[kWave + 1], offj[kWave];
     const int lane = lane_id();
     const int32_t nroots = *nroots_p;
-    uint64_t acc = 0;
+    uint64_t acc = 0, acc3 = 0, acc4 = 0;
     for (int64_t r = blockIdx.x; r < nroots; r += gridDim.x) {
         const int32_t u = roots[r];
         const int32_t s = dag_off[u], d = dag_off[u + 1] - s;
@@ -306,11 +309,23 @@ __global__ void __launch_bounds__(kWave) k_clique_wave(const int32_t *__restrict
             if (slot >= 0) atomicOr((unsigned long long *)&rows[j], 1ull << vals[slot]);
         });
         __syncthreads();
-        if (lane < d) acc += local_count64<K>(rows[lane], rows);
+        if (lane < d) {
+            acc += local_count64<K>(rows[lane], rows);
+            if (res3) acc3 += __popcll(rows[lane]);                     // triangles at u
+            if (K == 5 && res4) acc4 += local_count64<4>(rows[lane], rows);
+        }
         __syncthreads();
     }
     acc = wave_sum(acc);
     if (lane == 0 && acc) atomicAdd(result, (unsigned long long)acc);
+    if (res3) {
+        acc3 = wave_sum(acc3);
+        if (lane == 0 && acc3) atomicAdd(res3, (unsigned long long)acc3);
+    }
+    if (K == 5 && res4) {
+        acc4 = wave_sum(acc4);
+        if (lane == 0 && acc4) atomicAdd(res4, (unsigned long long)acc4);
+    }
 }
 
 constexpr int kMidMaxD = 256;
@@ -560,14 +575,14 @@ hipError_t build_class(const gpm_graph *g, CliqueWs &W, int32_t want, int32_t *l
 template <int K>
 gpm_status launch_local(const gpm_graph *g, CliqueWs &W, const int32_t *cnt_s,
                         const int32_t *cnt_m, const int32_t *cnt_b, unsigned long long *res,
-                        hipStream_t st) {
-    gpm_status rc = lg_cliques(g, K, W.list_m, cnt_m, W.list_b, cnt_b, W.work, W.lg, W.lg_bytes,
-                               res, st);
+                        unsigned long long *res3, unsigned long long *res4, hipStream_t st) {
+    gpm_status rc = lg_cliques(g, K, W.list_m, cnt_m, W.list_b, cnt_b, W.lg, W.lg_bytes, res,
+                               res3, res4, st);
     if (rc) return rc;
     {
         Span sp(K == 4 ? "k_clique_wave<4>" : "k_clique_wave<5>", st);
         hipLaunchKernelGGL(k_clique_wave<K>, dim3((unsigned)(cu_count() * 32)), dim3(kWave), 0,
-                           st, g->dag_off, g->dag_adj, W.list_s, cnt_s, res);
+                           st, g->dag_off, g->dag_adj, W.list_s, cnt_s, res, res3, res4);
     }
     GPM_LAUNCH_CHECK("k_clique_wave");
     return GPM_OK;
@@ -683,12 +698,58 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
             GPM_HIP(hipMemcpyAsync(cnt_m, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
             GPM_HIP(build_class(g, W, RC_SMALL, W.list_s, nullptr, st));
             GPM_HIP(hipMemcpyAsync(cnt_s, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
-            gpm_status rc = k == 4 ? launch_local<4>(g, W, cnt_s, cnt_m, cnt_b, res, st)
-                                   : launch_local<5>(g, W, cnt_s, cnt_m, cnt_b, res, st);
+            gpm_status rc =
+                k == 4 ? launch_local<4>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st)
+                       : launch_local<5>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st);
             if (rc) return rc;
         }
     }
     if (!list) GPM_HIP(hipMemcpyAsync(d_count, res, 8, hipMemcpyDeviceToDevice, st));
+    return GPM_OK;
+}
+
+// Cliques of every size 3..kmax (kmax = 4 or 5) from one local-graph pass:
+// the local graph of root u holds the triangles at u (its edges), the
+// 4-cliques at u (its triangles) and the 5-cliques at u (its 4-cliques), so
+// one build per root serves all sizes.  Roots need out-degree >= 2.
+gpm_status clique_multi_workspace_bytes(const gpm_graph *g, int32_t kmax, uint64_t *bytes) {
+    return clique_workspace_bytes(g, kmax, false, bytes);
+}
+
+gpm_status clique_multi_run(const gpm_graph *g, int32_t kmax, void *ws, uint64_t ws_bytes,
+                            unsigned long long *d_counts, hipStream_t st) {
+    if (kmax < 4 || kmax > 5) return fail(GPM_UNSUPPORTED, "kmax must be 4 or 5");
+    if (g->max_out_degree > kTcMax)
+        return fail(GPM_UNSUPPORTED, "fused clique counts need every out-degree <= 1024");
+    CliqueWs W = clique_layout(g, kmax, false, ws);
+    if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
+    const int32_t n = g->n;
+    unsigned long long *res = W.result;   // [0] k = kmax, [1] triangles, [2] 4-cliques (kmax 5)
+    GPM_HIP(fill_u32(res, 0, 16, st));
+    GPM_HIP(fill_u32(W.ctl, 0, 32, st));
+    hipLaunchKernelGGL(k_root_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st, g->dag_off,
+                       g->dag_adj, n, 2, 64, kMidMaxD, kTcMax, W.work, W.cls);
+    GPM_LAUNCH_CHECK("k_root_work");
+    int32_t *cnt_s = (int32_t *)(W.ctl + 12), *cnt_m = (int32_t *)(W.ctl + 13),
+            *cnt_b = (int32_t *)(W.ctl + 14);
+    GPM_HIP(build_class(g, W, RC_BIG, W.list_b, nullptr, st));
+    GPM_HIP(hipMemcpyAsync(cnt_b, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
+    GPM_HIP(build_class(g, W, RC_MID, W.list_m, nullptr, st));
+    GPM_HIP(hipMemcpyAsync(cnt_m, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
+    GPM_HIP(build_class(g, W, RC_SMALL, W.list_s, nullptr, st));
+    GPM_HIP(hipMemcpyAsync(cnt_s, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
+    gpm_status rc = kmax == 4
+                        ? launch_local<4>(g, W, cnt_s, cnt_m, cnt_b, res, res + 1, nullptr, st)
+                        : launch_local<5>(g, W, cnt_s, cnt_m, cnt_b, res, res + 1, res + 2, st);
+    if (rc) return rc;
+    // d_counts = {triangles, 4-cliques[, 5-cliques]}
+    GPM_HIP(hipMemcpyAsync(d_counts, res + 1, 8, hipMemcpyDeviceToDevice, st));
+    if (kmax == 4) {
+        GPM_HIP(hipMemcpyAsync(d_counts + 1, res, 8, hipMemcpyDeviceToDevice, st));
+    } else {
+        GPM_HIP(hipMemcpyAsync(d_counts + 1, res + 2, 8, hipMemcpyDeviceToDevice, st));
+        GPM_HIP(hipMemcpyAsync(d_counts + 2, res, 8, hipMemcpyDeviceToDevice, st));
+    }
     return GPM_OK;
 }
 

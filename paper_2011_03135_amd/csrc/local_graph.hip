@@ -172,7 +172,8 @@ __global__ void __launch_bounds__(NT) k_lg4(const int32_t *__restrict__ dag_off,
                                             const int32_t *__restrict__ dag_adj,
                                             const int32_t *__restrict__ roots,
                                             const int32_t *__restrict__ nroots_p,
-                                            uint32_t *cursor, unsigned long long *result) {
+                                            uint32_t *cursor, unsigned long long *result,
+                                            unsigned long long *res3) {
     __shared__ uint64_t rows[DMAX * (DMAX / 64)];
     __shared__ int32_t keys[LgHash<DMAX>::kSlots];
     __shared__ int16_t vals[LgHash<DMAX>::kSlots];
@@ -192,6 +193,7 @@ __global__ void __launch_bounds__(NT) k_lg4(const int32_t *__restrict__ dag_off,
         build_rows<DMAX, NT, false>(nullptr, dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj,
                                      nullptr, sh.s_sum);
         const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
+        if (res3 && tid == 0 && ne) atomicAdd(res3, (unsigned long long)ne);   // triangles at u
         for (int32_t e = tid; e < ne; e += NT) {
             int32_t i, j;
             edge_at(rows, pre, d, W, e, i, j);
@@ -214,7 +216,9 @@ __global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ off
                                                  const int32_t *__restrict__ nroots_p,
                                                  uint32_t *cursor, const int64_t *__restrict__ rowoff,
                                                  uint64_t *grows, int32_t *slices,
-                                                 unsigned long long *units) {
+                                                 unsigned long long *units,
+                                                 unsigned long long *res3,
+                                                 unsigned long long *res4) {
     __shared__ uint64_t rows[DMAX * (DMAX / 64)];
     __shared__ int32_t keys[LgHash<DMAX>::kSlots];
     __shared__ int16_t vals[LgHash<DMAX>::kSlots];
@@ -237,7 +241,9 @@ __global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ off
         uint64_t *dst = grows + rowoff[r];
         for (int32_t i = tid; i < d * W; i += NT) dst[i] = rows[i];
         const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
-        // local triangles = candidates summed over local edges: the 5-clique work
+        if (res3 && tid == 0 && ne) atomicAdd(res3, (unsigned long long)ne);   // triangles at u
+        // local triangles (the 4-cliques at u) = candidates summed over local
+        // edges: the 5-clique work
         uint64_t tri = 0;
         for (int32_t e = tid; e < ne; e += NT) {
             int32_t i, j;
@@ -255,6 +261,7 @@ __global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ off
             const uint64_t s_cap = (uint64_t)(d / 8 + 1);
             slices[r] = (int32_t)std::min<uint64_t>(kMaxSlices, std::min(s_work, s_cap));
             if (sh.s_tri) atomicAdd(units, (unsigned long long)sh.s_tri);
+            if (sh.s_tri && res4) atomicAdd(res4, (unsigned long long)sh.s_tri);
             sh.s_tri = 0;
         }
         __syncthreads();
@@ -448,8 +455,8 @@ unsigned grid_for(int64_t items, int per_block, int cap_per_cu) {
 template <int DMAX, int NT>
 gpm_status lg5_class(const gpm_graph *g, LgWs &L, const int32_t *list, const int32_t *cnt,
                      int64_t *rowoff, uint64_t *rows, unsigned long long *units, int32_t *toff,
-                     uint32_t *cursors, unsigned long long *res, hipStream_t st, const char *nb,
-                     const char *nc) {
+                     uint32_t *cursors, unsigned long long *res, unsigned long long *res3,
+                     unsigned long long *res4, hipStream_t st, const char *nb, const char *nc) {
     const int32_t n = g->n;
     GPM_HIP(fill_u32(L.words, 0, (uint64_t)n + 1, st));
     hipLaunchKernelGGL(k_lg_words, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, g->dag_off, list,
@@ -461,7 +468,7 @@ gpm_status lg5_class(const gpm_graph *g, LgWs &L, const int32_t *list, const int
         Span sp(nb, st);
         hipLaunchKernelGGL((k_lg_build<DMAX, NT>), dim3((unsigned)cu_count() * (NT <= 256 ? 8 : 1)),
                            dim3(NT), 0, st, g->off, g->dag_off, g->dag_adj, list, cnt, cursors + 0,
-                           rowoff, rows, L.slices, units);
+                           rowoff, rows, L.slices, units, res3, res4);
     }
     GPM_LAUNCH_CHECK("k_lg_build");
     GPM_HIP(exclusive_scan_i32(L.slices, toff, (uint64_t)n, L.scan_tmp, st));
@@ -494,11 +501,13 @@ gpm_status lg_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes) {
 }
 
 // Counts k-cliques (k = 4, 5) rooted at the two workgroup classes: list_m
-// (out-degree 65..256) and list_b (257..1024), device counts cnt_m, cnt_b.
+// (out-degree 65..256) and list_b (257..1024), device counts cnt_m, cnt_b,
+// into *res.  res3 / res4 (may be null) also receive the triangles and (for
+// k = 5) the 4-cliques rooted at the same roots.
 gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, const int32_t *cnt_m,
-                      const int32_t *list_b, const int32_t *cnt_b, const int32_t *work, void *ws,
-                      uint64_t ws_bytes, unsigned long long *res, hipStream_t st) {
-    (void)work;
+                      const int32_t *list_b, const int32_t *cnt_b, void *ws, uint64_t ws_bytes,
+                      unsigned long long *res, unsigned long long *res3,
+                      unsigned long long *res4, hipStream_t st) {
     LgWs L = lg_layout(g, k, ws);
     if (L.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "local-graph workspace too small");
     GPM_HIP(fill_u32(L.ctl, 0, 16, st));
@@ -508,25 +517,25 @@ gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, cons
             Span sp("k_lg4<1024>", st);
             hipLaunchKernelGGL((k_lg4<kBigMaxD, kBigThreads>), dim3((unsigned)cu_count()),
                                dim3(kBigThreads), 0, st, g->dag_off, g->dag_adj, list_b, cnt_b,
-                               L.ctl + 0, res);
+                               L.ctl + 0, res, res3);
         }
         GPM_LAUNCH_CHECK("k_lg4<1024>");
         {
             Span sp("k_lg4<256>", st);
             hipLaunchKernelGGL((k_lg4<kMidMaxD, kMidThreads>), dim3((unsigned)cu_count() * 8),
                                dim3(kMidThreads), 0, st, g->dag_off, g->dag_adj, list_m, cnt_m,
-                               L.ctl + 1, res);
+                               L.ctl + 1, res, res3);
         }
         GPM_LAUNCH_CHECK("k_lg4<256>");
         return GPM_OK;
     }
     gpm_status rc = lg5_class<kBigMaxD, kBigThreads>(g, L, list_b, cnt_b, L.rowoff_b, L.rows_b,
-                                                     L.units + 0, L.toff_b, L.ctl + 2, res, st,
-                                                     "k_lg_build<1024>", "k_lg5<1024>");
+                                                     L.units + 0, L.toff_b, L.ctl + 2, res, res3,
+                                                     res4, st, "k_lg_build<1024>", "k_lg5<1024>");
     if (rc) return rc;
     return lg5_class<kMidMaxD, kMidThreads>(g, L, list_m, cnt_m, L.rowoff_m, L.rows_m,
-                                            L.units + 1, L.toff_m, L.ctl + 4, res, st,
-                                            "k_lg_build<256>", "k_lg5<256>");
+                                            L.units + 1, L.toff_m, L.ctl + 4, res, res3, res4,
+                                            st, "k_lg_build<256>", "k_lg5<256>");
 }
 
 }  // namespace gpm

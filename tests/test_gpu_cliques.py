@@ -182,6 +182,33 @@ def test_dense_multipartite_local_graphs(gpm, parts):
         assert gpm.count(g, gpm.clique(k)) == elementary_symmetric(parts, k)
 
 
+@pytest.mark.parametrize("case", range(8))
+def test_fused_clique_counts(gpm, case):
+    """One local-graph pass gives the same triangle, 4- and 5-clique counts
+    as the per-size calls and the oracle."""
+    e = clique_cases()[case]
+    g = build(gpm, e)
+    off, adj = canonical_csr(e.n, e.u, e.v)
+    want = [oracle.clique_count(off, adj, k) for k in (3, 4, 5)]
+    print(f"fused case {case} {e.name}", flush=True)
+    assert gpm.clique_counts(g, 5) == want
+    assert gpm.clique_counts(g, 4) == want[:2]
+
+
+@pytest.mark.parametrize("n", [70, 300, 700])
+def test_fused_clique_counts_dense(gpm, n):
+    g = build(gpm, graphgen.complete_graph(n))
+    assert gpm.clique_counts(g, 5) == [math.comb(n, k) for k in (3, 4, 5)]
+
+
+def test_fused_clique_counts_rmat_golden(gpm):
+    gold = _golden().get("rmat18")
+    if not gold or "clique5" not in gold:
+        pytest.skip("golden counts for rmat18 not generated")
+    g = build(gpm, graphgen.rmat(18, seed=18))
+    assert gpm.clique_counts(g, 5) == [gold["clique3"], gold["clique4"], gold["clique5"]]
+
+
 def test_er_workload_triangles(gpm):
     """Erdos-Renyi G(4096, 0.004), seed 1."""
     e = graphgen.erdos_renyi(4096, 0.004, 1)
