@@ -83,3 +83,27 @@ def test_null_arguments_rejected(lib):
     assert lib.gpm_motif_count(None, 4, None, 0, None, None) == 1
     assert lib.gpm_graph_get_info(None, None) == 1
     assert b"NULL" in lib.gpm_last_error() or lib.gpm_last_error() != b""
+
+
+def test_new_entry_points_validate_on_host(lib):
+    import paper_2011_03135_amd as gpm
+    from paper_2011_03135_amd.binding import GpmError
+    # graph from CSR: sizes and limits
+    gb, sb = gpm.Graph.from_csr_bytes(100, 400)
+    assert gb > 0 and sb > 0
+    with pytest.raises(GpmError) as ei:
+        gpm.Graph.from_csr_bytes(100, 401)             # odd nnz
+    assert ei.value.status == 5
+    with pytest.raises(GpmError):
+        gpm.Graph.from_csr_bytes(0, 0)
+    out = ctypes.c_void_p()
+    assert lib.gpm_graph_from_csr(10, None, None, 0, 1, None, 0, None, 0, None,
+                                  ctypes.byref(out)) == 1
+    # fused clique counts and batch configuration
+    assert lib.gpm_clique_counts(None, 5, None, 0, None, None) == 1
+    assert lib.gpm_clique_counts_workspace_bytes(None, 5, None) == 1
+    cfg = gpm.batch_default_config()
+    assert (cfg.team_threads, cfg.tiers) in [(64, 3), (128, 3), (256, 3), (64, 1), (256, 1)]
+    assert lib.gpm_batch_default_config(None) == 1
+    assert lib.gpm_batch_motif_count_config(None, None, 1, 4, None, None, 0, None, None) == 1
+    assert lib.gpm_batch_autotune(None, None, 1, 4, None, 0, None, None, 1, None, None) == 1
