@@ -17,14 +17,15 @@
 //                   prefix of its out-neighbours; each pair is a membership
 //                   test of w in N+(u).  Optionally adds 1 to the triangle
 //                   count of each of the triangle's three arcs.
-//   k_clique_wave   k = 4, 5, roots with out-degree <= 64: one wave builds
+//   k_clique_wave   k = 4..8, roots with out-degree <= 64: one wave builds
 //                   the local graph on N+(u) as 64-bit adjacency rows in LDS
 //                   and counts cliques with AND + popcount.
-//   (local_graph.hip) k = 4, 5, roots with out-degree 65..1024: workgroup
+//   (local_graph.hip) k = 4..8, roots with out-degree 65..1024: workgroup
 //                   local graphs in LDS.
-//   k_clique_generic  any k in [3, 8], any degree, counting or listing: one
-//                   wave per root, depth-first with candidate sets in a
-//                   per-wave global scratch, wave-cooperative intersections.
+//   k_clique_generic  any k in [3, 8] when an out-degree exceeds 1024, and
+//                   listing: one wave per root, depth-first with candidate
+//                   sets in a per-wave global scratch, wave-cooperative
+//                   intersections.
 #include "gpm_internal.h"
 
 #include <algorithm>
@@ -256,28 +257,36 @@ __global__ void __launch_bounds__(NT) k_tc_block(const int32_t *__restrict__ dag
 
 // ------------------------------------------- local-graph k-cliques ---
 
-// Counts (K-1)-vertex cliques of the local DAG whose rows are 64-bit masks
-// (local graph on <= 64 vertices), starting at local vertex with row r.
+// Number of D-vertex cliques of the local DAG (rows: 64-bit masks, local
+// graph on <= 64 vertices) whose vertices all lie in mask.
+template <int D>
+__device__ __forceinline__ uint64_t cliques_in64(uint64_t mask, const uint64_t *rows) {
+    if constexpr (D == 1) {
+        return (uint64_t)__popcll(mask);
+    } else if constexpr (D == 2) {
+        uint64_t c = 0, m = mask;
+        while (m) {
+            const int j = __builtin_ctzll(m);
+            m &= m - 1;
+            c += __popcll(mask & rows[j]);
+        }
+        return c;
+    } else {
+        uint64_t c = 0, m = mask;
+        while (m) {
+            const int j = __builtin_ctzll(m);
+            m &= m - 1;
+            c += cliques_in64<D - 1>(mask & rows[j], rows);
+        }
+        return c;
+    }
+}
+
+// K-cliques of the root through local vertex with row r: (K-2)-cliques of
+// the local DAG inside r.
 template <int K>
 __device__ __forceinline__ uint64_t local_count64(uint64_t r, const uint64_t *rows) {
-    uint64_t c = 0;
-    uint64_t m = r;
-    while (m) {
-        int j = __builtin_ctzll(m);
-        m &= m - 1;
-        uint64_t x = r & rows[j];
-        if (K == 4) {
-            c += __popcll(x);
-        } else {
-            uint64_t mm = x;
-            while (mm) {
-                int l = __builtin_ctzll(mm);
-                mm &= mm - 1;
-                c += __popcll(x & rows[l]);
-            }
-        }
-    }
-    return c;
+    return cliques_in64<K - 2>(r, rows);
 }
 
 // One 64-thread block (one wave) per root at a time: stages N+(u), sets the
@@ -526,7 +535,7 @@ CliqueWs clique_layout(const gpm_graph *g, int32_t k, bool list, void *base) {
     W.wpre_m = c.take<int64_t>(n1);
     W.wpre_b = c.take<int64_t>(n1);
     W.scan_tmp = c.take<int64_t>(scan_tmp_words(n1));
-    bool generic = list || k > 5 || g->max_out_degree > kTcMax;
+    bool generic = list || g->max_out_degree > kTcMax;
     if (!generic && k == 3) {
         W.first_s = c.take<int32_t>((uint64_t)chunk_bound(g));
         W.first_m = c.take<int32_t>((uint64_t)chunk_bound(g));
@@ -580,7 +589,10 @@ gpm_status launch_local(const gpm_graph *g, CliqueWs &W, const int32_t *cnt_s,
                                res3, res4, st);
     if (rc) return rc;
     {
-        Span sp(K == 4 ? "k_clique_wave<4>" : "k_clique_wave<5>", st);
+        static const char *const kNames[] = {"k_clique_wave<4>", "k_clique_wave<5>",
+                                             "k_clique_wave<6>", "k_clique_wave<7>",
+                                             "k_clique_wave<8>"};
+        Span sp(kNames[K - 4], st);
         hipLaunchKernelGGL(k_clique_wave<K>, dim3((unsigned)(cu_count() * 32)), dim3(kWave), 0,
                            st, g->dag_off, g->dag_adj, W.list_s, cnt_s, res, res3, res4);
     }
@@ -664,7 +676,7 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
     unsigned long long *res = list ? d_result : W.result;
     GPM_HIP(fill_u32(res, 0, list ? 6 : 16, st));
     GPM_HIP(fill_u32(W.ctl, 0, 32, st));
-    const bool generic = list || k > 5 || g->max_out_degree > kTcMax;
+    const bool generic = list || g->max_out_degree > kTcMax;
     if (generic) {
         ListOut lo{d_buf, list ? cap : 0};
         int blocks = W.gen_waves / kWPB;
@@ -698,9 +710,14 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
             GPM_HIP(hipMemcpyAsync(cnt_m, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
             GPM_HIP(build_class(g, W, RC_SMALL, W.list_s, nullptr, st));
             GPM_HIP(hipMemcpyAsync(cnt_s, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
-            gpm_status rc =
-                k == 4 ? launch_local<4>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st)
-                       : launch_local<5>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st);
+            gpm_status rc;
+            switch (k) {
+            case 4: rc = launch_local<4>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st); break;
+            case 5: rc = launch_local<5>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st); break;
+            case 6: rc = launch_local<6>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st); break;
+            case 7: rc = launch_local<7>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st); break;
+            default: rc = launch_local<8>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st); break;
+            }
             if (rc) return rc;
         }
     }

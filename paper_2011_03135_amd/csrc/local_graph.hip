@@ -348,14 +348,71 @@ __device__ uint64_t lg5_vertex(const uint64_t *rows, const uint64_t *ri, int32_t
     return acc;
 }
 
+// (e + 3)-cliques of the local DAG inside the set S (W words, c >= 3
+// members): for e = 0 the triangles inside S; for e > 0 the sum over members
+// v of S of the (e + 2)-cliques inside S & row_v (rows hold only bits above
+// their own index, so each clique is found once, from its lowest member).
+// The descent is wave-uniform and iterative: level l keeps its set and the
+// members still to visit in the wave's stack area (2 W words per level,
+// e + 1 levels), the deepest child set in the last slot.
+template <int W>
+__device__ uint64_t lgk_set(const uint64_t *rows, const uint64_t *S, int32_t c, int32_t e,
+                            int16_t *mem, uint64_t *stack) {
+    if (e == 0) return lg5_vertex<W>(rows, S, c, mem);
+    uint64_t acc = 0;
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+        const uint64_t x = uniform64(S[q]);
+        stack[q] = x;
+        stack[W + q] = x;
+    }
+    wave_sync();
+    int32_t lvl = 0;
+    while (lvl >= 0) {
+        uint64_t *set = stack + lvl * 2 * W, *rem = set + W;
+        int32_t v = -1;
+#pragma unroll
+        for (int q = 0; q < W; q++) {
+            const uint64_t r = uniform64(rem[q]);
+            if (v < 0 && r) {
+                v = q * 64 + __builtin_ctzll(r);
+                rem[q] = r & (r - 1ull);
+            }
+        }
+        wave_sync();
+        if (v < 0) {
+            lvl--;
+            continue;
+        }
+        const uint64_t *rv = rows + v * W;
+        uint64_t *child = stack + (lvl + 1) * 2 * W;
+        int32_t cnt = 0;
+#pragma unroll
+        for (int q = 0; q < W; q++) {
+            const uint64_t x = uniform64(set[q]) & uniform64(rv[q]);
+            child[q] = x;
+            child[W + q] = x;
+            cnt += __popcll(x);
+        }
+        wave_sync();
+        if (lvl + 1 == e) {
+            if (cnt >= 3) acc += lg5_vertex<W>(rows, child, cnt, mem);
+        } else if (cnt >= e - lvl + 2) {
+            lvl++;
+        }
+    }
+    return acc;
+}
+
 template <int WLO, int WHI>
 __device__ __forceinline__ uint64_t lg5_dispatch(int32_t W, const uint64_t *rows, const uint64_t *ri,
-                                                 int32_t c, int16_t *mem) {
+                                                 int32_t c, int32_t e, int16_t *mem,
+                                                 uint64_t *stack) {
     if constexpr (WLO > WHI) {
         return 0;
     } else {
-        if (W == WLO) return lg5_vertex<WLO>(rows, ri, c, mem);
-        return lg5_dispatch<WLO + 1, WHI>(W, rows, ri, c, mem);
+        if (W == WLO) return lgk_set<WLO>(rows, ri, c, e, mem, stack);
+        return lg5_dispatch<WLO + 1, WHI>(W, rows, ri, c, e, mem, stack);
     }
 }
 
@@ -366,8 +423,8 @@ __global__ void __launch_bounds__(1024) k_lg5(const int32_t *__restrict__ dag_of
                                               const int32_t *__restrict__ nroots_p,
                                               const int64_t *__restrict__ rowoff,
                                               const uint64_t *__restrict__ grows,
-                                              int32_t rows_words, uint32_t *cursor,
-                                              unsigned long long *result) {
+                                              int32_t rows_words, int32_t extra,
+                                              uint32_t *cursor, unsigned long long *result) {
     // row widths of the class: out-degrees (DMAX/4, DMAX]
     constexpr int WLO = DMAX / 256 + 1, WHI = DMAX / 64;
     extern __shared__ uint64_t dyn[];
@@ -375,7 +432,11 @@ __global__ void __launch_bounds__(1024) k_lg5(const int32_t *__restrict__ dag_of
     __shared__ Lds<1024> sh;
     const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
     const int NT = blockDim.x;
-    int16_t *mem = reinterpret_cast<int16_t *>(dyn + rows_words) + wib * DMAX;
+    // per wave: member list (DMAX int16), then the descent stack
+    uint8_t *wave_area = reinterpret_cast<uint8_t *>(dyn + rows_words) +
+                         (size_t)wib * (DMAX * 2 + (size_t)(extra + 1) * 2 * (DMAX / 64) * 8);
+    int16_t *mem = reinterpret_cast<int16_t *>(wave_area);
+    uint64_t *stack = reinterpret_cast<uint64_t *>(wave_area + DMAX * 2);
     const int32_t nroots = *nroots_p;
     const int32_t ntasks = toff[nroots];
     uint64_t acc = 0;
@@ -403,8 +464,8 @@ __global__ void __launch_bounds__(1024) k_lg5(const int32_t *__restrict__ dag_of
             const uint64_t *ri = rows + i * W;
             int32_t cnt = 0;
             for (int32_t w = 0; w < W; w++) cnt += __popcll(ri[w]);
-            if (cnt < 3) continue;
-            acc += lg5_dispatch<WLO, WHI>(W, rows, ri, cnt, mem);
+            if (cnt < 3 + extra) continue;
+            acc += lg5_dispatch<WLO, WHI>(W, rows, ri, cnt, extra, mem, stack);
         }
         __syncthreads();
     }
@@ -427,7 +488,7 @@ LgWs lg_layout(const gpm_graph *g, int32_t k, void *base) {
     const uint64_t n1 = (uint64_t)g->n + 1;
     L.ctl = c.take<uint32_t>(16);
     L.units = c.take<unsigned long long>(4);
-    if (k == 5) {
+    if (k >= 5) {
         L.words = c.take<int32_t>(n1);
         L.slices = c.take<int32_t>(n1);
         L.toff_m = c.take<int32_t>(n1);
@@ -453,7 +514,8 @@ unsigned grid_for(int64_t items, int per_block, int cap_per_cu) {
 }
 
 template <int DMAX, int NT>
-gpm_status lg5_class(const gpm_graph *g, LgWs &L, const int32_t *list, const int32_t *cnt,
+gpm_status lg5_class(const gpm_graph *g, int32_t k, LgWs &L, const int32_t *list,
+                     const int32_t *cnt,
                      int64_t *rowoff, uint64_t *rows, unsigned long long *units, int32_t *toff,
                      uint32_t *cursors, unsigned long long *res, unsigned long long *res3,
                      unsigned long long *res4, hipStream_t st, const char *nb, const char *nc) {
@@ -478,7 +540,8 @@ gpm_status lg5_class(const gpm_graph *g, LgWs &L, const int32_t *list, const int
         const int32_t dmax = std::min<int32_t>(DMAX, std::max(g->max_out_degree, 1));
         const int32_t rows_words = dmax * ((dmax + 63) / 64);
         const int64_t lds_cap = 160 * 1024 - 1024;
-        const int64_t per_wave = (int64_t)DMAX * 2;
+        const int32_t extra = k - 5;
+        const int64_t per_wave = (int64_t)DMAX * 2 + (int64_t)(extra + 1) * 2 * (DMAX / 64) * 8;
         int waves = (int)std::min<int64_t>(DMAX <= 256 ? 4 : 16,
                                            (lds_cap - (int64_t)rows_words * 8) / per_wave);
         if (waves < 1) return fail(GPM_DEVICE_ERROR, "local graph does not fit in LDS");
@@ -486,7 +549,7 @@ gpm_status lg5_class(const gpm_graph *g, LgWs &L, const int32_t *list, const int
         Span sp(nc, st);
         hipLaunchKernelGGL((k_lg5<DMAX>), dim3((unsigned)cu_count() * (DMAX <= 256 ? 4 : 1)),
                            dim3(waves * kWave), shmem, st, g->dag_off, list, toff, cnt, rowoff,
-                           (const uint64_t *)rows, rows_words, cursors + 1, res);
+                           (const uint64_t *)rows, rows_words, extra, cursors + 1, res);
         span_units(units, st);
     }
     GPM_LAUNCH_CHECK("k_lg5");
@@ -500,7 +563,7 @@ gpm_status lg_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes) {
     return GPM_OK;
 }
 
-// Counts k-cliques (k = 4, 5) rooted at the two workgroup classes: list_m
+// Counts k-cliques (k = 4..8) rooted at the two workgroup classes: list_m
 // (out-degree 65..256) and list_b (257..1024), device counts cnt_m, cnt_b,
 // into *res.  res3 / res4 (may be null) also receive the triangles and (for
 // k = 5) the 4-cliques rooted at the same roots.
@@ -529,13 +592,15 @@ gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, cons
         GPM_LAUNCH_CHECK("k_lg4<256>");
         return GPM_OK;
     }
-    gpm_status rc = lg5_class<kBigMaxD, kBigThreads>(g, L, list_b, cnt_b, L.rowoff_b, L.rows_b,
+    gpm_status rc = lg5_class<kBigMaxD, kBigThreads>(g, k, L, list_b, cnt_b, L.rowoff_b, L.rows_b,
                                                      L.units + 0, L.toff_b, L.ctl + 2, res, res3,
-                                                     res4, st, "k_lg_build<1024>", "k_lg5<1024>");
+                                                     res4, st, "k_lg_build<1024>",
+                                                     k == 5 ? "k_lg5<1024>" : "k_lgk<1024>");
     if (rc) return rc;
-    return lg5_class<kMidMaxD, kMidThreads>(g, L, list_m, cnt_m, L.rowoff_m, L.rows_m,
+    return lg5_class<kMidMaxD, kMidThreads>(g, k, L, list_m, cnt_m, L.rowoff_m, L.rows_m,
                                             L.units + 1, L.toff_m, L.ctl + 4, res, res3, res4,
-                                            st, "k_lg_build<256>", "k_lg5<256>");
+                                            st, "k_lg_build<256>",
+                                            k == 5 ? "k_lg5<256>" : "k_lgk<256>");
 }
 
 }  // namespace gpm

@@ -149,9 +149,32 @@ def test_clique_counts(gpm, case):
     e = clique_cases()[case]
     g = build(gpm, e)
     off, adj = canonical_csr(e.n, e.u, e.v)
-    for k in (3, 4, 5, 6):
+    # 7- and 8-cliques where the oracle finishes quickly (not the RMAT cases)
+    ks = (3, 4, 5, 6) if e.name.startswith("rmat") else (3, 4, 5, 6, 7, 8)
+    complete = e.name[1:].isdigit()     # K_n: the closed form C(n, k)
+    for k in ks:
         print(f"clique case {case} {e.name} k={k}", flush=True)
-        assert gpm.count(g, gpm.clique(k)) == oracle.clique_count(off, adj, k), (e.name, k)
+        want = math.comb(e.n, k) if complete else oracle.clique_count(off, adj, k)
+        assert gpm.count(g, gpm.clique(k)) == want, (e.name, k)
+
+
+@pytest.mark.parametrize("n", [66, 100])
+def test_dense_local_graphs_large_k(gpm, n):
+    """k = 6..8 on complete graphs (local rows of 2 words, level-1 sets of up
+    to n - 2 members)."""
+    g = build(gpm, graphgen.complete_graph(n))
+    for k in (6, 7, 8):
+        print(f"complete graph n={n} k={k}", flush=True)
+        assert gpm.count(g, gpm.clique(k)) == math.comb(n, k)
+
+
+def test_large_k_multipartite(gpm):
+    """Complete multipartite graph with out-degrees above 256 (5- to 8-word
+    local rows): 6-cliques = e_6(part sizes)."""
+    parts = [40, 35, 30, 25, 20, 45, 50, 15, 10, 60]
+    g = build(gpm, graphgen.complete_multipartite(parts))
+    print(f"multipartite max_out={g.max_out_degree}", flush=True)
+    assert gpm.count(g, gpm.clique(6)) == elementary_symmetric(parts, 6)
 
 
 @pytest.mark.parametrize("n", [130, 200, 257, 300, 520, 700])
