@@ -37,7 +37,7 @@ gpm_status lg_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes);
 gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, const int32_t *cnt_m,
                       const int32_t *list_b, const int32_t *cnt_b, void *ws, uint64_t ws_bytes,
                       unsigned long long *res, unsigned long long *res3,
-                      unsigned long long *res4, hipStream_t st);
+                      unsigned long long *res4, const RowEmitter *em, hipStream_t st);
 
 namespace {
 
@@ -154,6 +154,7 @@ __global__ void k_chunk_map(const int64_t *wpre, const int32_t *pos_total, int64
 enum TcMode : int {
     TC_COUNT = 0,   // count only
     TC_ARCS = 1,    // also +1 on the triangle count of each of its three arcs
+    TC_LIST = 2,    // list: emit (u, v, w)
 };
 
 // Triangles of the roots of one out-degree class (d+(u) <= DMAX), NT
@@ -176,7 +177,8 @@ __global__ void __launch_bounds__(NT) k_tc_block(const int32_t *__restrict__ dag
                                                  const int32_t *__restrict__ first,
                                                  const uint32_t *__restrict__ ctl,
                                                  uint32_t *cursor, int64_t tau,
-                                                 unsigned long long *result, uint32_t *te) {
+                                                 unsigned long long *result, uint32_t *te,
+                                                 RowEmitter em) {
     constexpr int NW = NT / kWave;
     constexpr int H = 4 * DMAX;
     constexpr int PER = (DMAX + NT - 1) / NT;
@@ -186,6 +188,7 @@ __global__ void __launch_bounds__(NT) k_tc_block(const int32_t *__restrict__ dag
     __shared__ int32_t pre[DMAX + 1];
     __shared__ int32_t offj[DMAX];
     __shared__ uint32_t cnt[MODE == TC_ARCS ? DMAX : 1];
+    __shared__ int32_t verts[MODE == TC_LIST ? DMAX : 1];
     __shared__ int32_t s_sum[NW];
     __shared__ uint32_t s_chunk;
     __shared__ unsigned long long s_acc[NW];
@@ -211,7 +214,8 @@ __global__ void __launch_bounds__(NT) k_tc_block(const int32_t *__restrict__ dag
             const int32_t hb = lds_hash_bits(d);
             for (int i = tid; i < (1 << hb); i += NT) keys[i] = -1;
             stage_root<NT, PER>(dag_off, dag_adj, s, d, keys, MODE == TC_ARCS ? vals : nullptr,
-                                hb, pre, offj, s_sum);
+                                hb, pre, offj, s_sum, nullptr,
+                                MODE == TC_LIST ? verts : nullptr);
             const int32_t q0 = (int32_t)(p - w0);
             const int32_t q1 = (int32_t)(min(p1, w1) - w0);
             // wave wid takes pairs [qa, qz), whole steps except the last
@@ -227,6 +231,10 @@ __global__ void __launch_bounds__(NT) k_tc_block(const int32_t *__restrict__ dag
                         atomicAdd(&cnt[jj], 1u);
                         atomicAdd(&cnt[vals[slot]], 1u);
                         atomicAdd(&te[e_vw], 1u);
+                    }
+                    if (MODE == TC_LIST) {
+                        const int32_t tri[3] = {u, verts[jj], w};
+                        emit_vertices<3>(em, tri);
                     }
                 }
             });
@@ -244,6 +252,10 @@ __global__ void __launch_bounds__(NT) k_tc_block(const int32_t *__restrict__ dag
             p = min(p1, w1);
             a++;
         }
+    }
+    if (MODE == TC_LIST) {
+        row_emitter_flush(em, result);
+        return;
     }
     acc = wave_sum(acc);
     if (lane == 0) s_acc[wid] = acc;
@@ -282,6 +294,25 @@ __device__ __forceinline__ uint64_t cliques_in64(uint64_t mask, const uint64_t *
     }
 }
 
+// Emits every (K)-clique {u, v_i, ...} through local vertex i (row r): the
+// (K-2)-cliques of the local DAG inside r, by nested bit loops.  v holds the
+// clique's vertices chosen so far (u, v_i, ...), depth = how many.
+template <int K, int DEPTH>
+__device__ void list_in64(uint64_t mask, const uint64_t *rows, const int32_t *verts,
+                          int32_t (&v)[K], RowEmitter &em) {
+    uint64_t m = mask;
+    while (m) {
+        const int j = __builtin_ctzll(m);
+        m &= m - 1;
+        v[DEPTH] = verts[j];
+        if constexpr (DEPTH + 1 == K) {
+            emit_vertices<K>(em, v);
+        } else {
+            list_in64<K, DEPTH + 1>(mask & rows[j], rows, verts, v, em);
+        }
+    }
+}
+
 // K-cliques of the root through local vertex with row r: (K-2)-cliques of
 // the local DAG inside r.
 template <int K>
@@ -291,18 +322,19 @@ __device__ __forceinline__ uint64_t local_count64(uint64_t r, const uint64_t *ro
 
 // One 64-thread block (one wave) per root at a time: stages N+(u), sets the
 // local rows through the pair walk and the membership hash, then counts.
-template <int K>
+template <int K, bool LIST>
 __global__ void __launch_bounds__(kWave) k_clique_wave(const int32_t *__restrict__ dag_off,
                                                        const int32_t *__restrict__ dag_adj,
                                                        const int32_t *__restrict__ roots,
                                                        const int32_t *__restrict__ nroots_p,
                                                        unsigned long long *result,
                                                        unsigned long long *res3,
-                                                       unsigned long long *res4) {
+                                                       unsigned long long *res4, RowEmitter em) {
     __shared__ uint64_t rows[kWave];
     __shared__ int32_t keys[4 * kWave];
     __shared__ int16_t vals[4 * kWave];
     __shared__ int32_t pre[kWave + 1], offj[kWave];
+    __shared__ int32_t verts[LIST ? kWave : 1];
     const int lane = lane_id();
     const int32_t nroots = *nroots_p;
     uint64_t acc = 0, acc3 = 0, acc4 = 0;
@@ -312,18 +344,30 @@ __global__ void __launch_bounds__(kWave) k_clique_wave(const int32_t *__restrict
         const int32_t hb = lds_hash_bits(d);
         for (int i = lane; i < (1 << hb); i += kWave) keys[i] = -1;
         rows[lane] = 0;
-        stage_root<kWave, 1>(dag_off, dag_adj, s, d, keys, vals, hb, pre, offj, nullptr);
+        stage_root<kWave, 1>(dag_off, dag_adj, s, d, keys, vals, hb, pre, offj, nullptr, nullptr,
+                             LIST ? verts : nullptr);
         walk_pairs<2>(pre, offj, dag_adj, d, 0, pre[d], [&](int32_t j, int32_t, int32_t w) {
             const int32_t slot = lds_hash_find(keys, hb, w);
             if (slot >= 0) atomicOr((unsigned long long *)&rows[j], 1ull << vals[slot]);
         });
         __syncthreads();
         if (lane < d) {
-            acc += local_count64<K>(rows[lane], rows);
-            if (res3) acc3 += __popcll(rows[lane]);                     // triangles at u
-            if (K == 5 && res4) acc4 += local_count64<4>(rows[lane], rows);
+            if constexpr (LIST) {
+                int32_t v[K];
+                v[0] = u;
+                v[1] = verts[lane];
+                list_in64<K, 2>(rows[lane], rows, verts, v, em);
+            } else {
+                acc += local_count64<K>(rows[lane], rows);
+                if (res3) acc3 += __popcll(rows[lane]);                 // triangles at u
+                if (K == 5 && res4) acc4 += local_count64<4>(rows[lane], rows);
+            }
         }
         __syncthreads();
+    }
+    if (LIST) {
+        row_emitter_flush(em, result);
+        return;
     }
     acc = wave_sum(acc);
     if (lane == 0 && acc) atomicAdd(result, (unsigned long long)acc);
@@ -481,6 +525,12 @@ __global__ void __launch_bounds__(kBlock) k_clique_generic(const int32_t *__rest
     }
 }
 
+// written = min(slots handed out, cap)
+__global__ void k_finish_rows(unsigned long long *result, const unsigned long long *slot_ctr,
+                              uint64_t cap) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) result[1] = *slot_ctr < cap ? *slot_ctr : cap;
+}
+
 __global__ void k_finish_listing(unsigned long long *result, uint64_t cap) {
     if (threadIdx.x == 0 && blockIdx.x == 0) result[1] = result[0] < cap ? result[0] : cap;
 }
@@ -517,6 +567,12 @@ int64_t chunk_bound(const gpm_graph *g) {
     return w / kTauMin + 2;
 }
 
+// The generic DFS serves out-degrees above 1024 and listings of k >= 6;
+// everything else runs on the triangle and local-graph kernels.
+bool uses_generic(const gpm_graph *g, int32_t k, bool list) {
+    return g->max_out_degree > kTcMax || (list && k > 5);
+}
+
 CliqueWs clique_layout(const gpm_graph *g, int32_t k, bool list, void *base) {
     CliqueWs W{};
     Carve c(base, ~0ull);
@@ -535,7 +591,7 @@ CliqueWs clique_layout(const gpm_graph *g, int32_t k, bool list, void *base) {
     W.wpre_m = c.take<int64_t>(n1);
     W.wpre_b = c.take<int64_t>(n1);
     W.scan_tmp = c.take<int64_t>(scan_tmp_words(n1));
-    bool generic = list || g->max_out_degree > kTcMax;
+    bool generic = uses_generic(g, k, list);
     if (!generic && k == 3) {
         W.first_s = c.take<int32_t>((uint64_t)chunk_bound(g));
         W.first_m = c.take<int32_t>((uint64_t)chunk_bound(g));
@@ -584,17 +640,24 @@ hipError_t build_class(const gpm_graph *g, CliqueWs &W, int32_t want, int32_t *l
 template <int K>
 gpm_status launch_local(const gpm_graph *g, CliqueWs &W, const int32_t *cnt_s,
                         const int32_t *cnt_m, const int32_t *cnt_b, unsigned long long *res,
-                        unsigned long long *res3, unsigned long long *res4, hipStream_t st) {
+                        unsigned long long *res3, unsigned long long *res4, hipStream_t st,
+                        const RowEmitter *em = nullptr) {
     gpm_status rc = lg_cliques(g, K, W.list_m, cnt_m, W.list_b, cnt_b, W.lg, W.lg_bytes, res,
-                               res3, res4, st);
+                               res3, res4, em, st);
     if (rc) return rc;
     {
         static const char *const kNames[] = {"k_clique_wave<4>", "k_clique_wave<5>",
                                              "k_clique_wave<6>", "k_clique_wave<7>",
                                              "k_clique_wave<8>"};
         Span sp(kNames[K - 4], st);
-        hipLaunchKernelGGL(k_clique_wave<K>, dim3((unsigned)(cu_count() * 32)), dim3(kWave), 0,
-                           st, g->dag_off, g->dag_adj, W.list_s, cnt_s, res, res3, res4);
+        if (em)
+            hipLaunchKernelGGL((k_clique_wave<K, true>), dim3((unsigned)(cu_count() * 32)),
+                               dim3(kWave), 0, st, g->dag_off, g->dag_adj, W.list_s, cnt_s, res,
+                               res3, res4, *em);
+        else
+            hipLaunchKernelGGL((k_clique_wave<K, false>), dim3((unsigned)(cu_count() * 32)),
+                               dim3(kWave), 0, st, g->dag_off, g->dag_adj, W.list_s, cnt_s, res,
+                               res3, res4, RowEmitter{});
     }
     GPM_LAUNCH_CHECK("k_clique_wave");
     return GPM_OK;
@@ -612,7 +675,7 @@ template <int DMAX, int NT, int MODE>
 static gpm_status tc_class(const gpm_graph *g, CliqueWs &W, int32_t want, int32_t *list,
                            int64_t *wpre, int32_t *first, int cls_idx, int64_t tau,
                            int blocks_per_cu, const char *name, unsigned long long *res,
-                           uint32_t *te, hipStream_t st) {
+                           uint32_t *te, const RowEmitter &em, hipStream_t st) {
     const int32_t n = g->n;
     uint32_t *info = W.ctl + 4 + 2 * cls_idx;   // {nact, nchunks}
     GPM_HIP(build_class(g, W, want, list, wpre, st));
@@ -624,7 +687,7 @@ static gpm_status tc_class(const gpm_graph *g, CliqueWs &W, int32_t want, int32_
         hipLaunchKernelGGL((k_tc_block<DMAX, NT, MODE, 2>),
                            dim3((unsigned)(cu_count() * blocks_per_cu)), dim3(NT), 0, st,
                            g->dag_off, g->dag_adj, list, wpre, first, info, W.ctl + cls_idx,
-                           tau, res, te);
+                           tau, res, te, em);
         span_units(W.result + 2 + cls_idx, st);
     }
     GPM_LAUNCH_CHECK(name);
@@ -637,7 +700,7 @@ static gpm_status tc_class(const gpm_graph *g, CliqueWs &W, int32_t want, int32_
 // (clique_workspace_bytes(g, 3, false)).
 template <int MODE>
 static gpm_status tc_launch(const gpm_graph *g, CliqueWs &W, unsigned long long *res,
-                            uint32_t *te, hipStream_t st) {
+                            uint32_t *te, hipStream_t st, const RowEmitter &em = RowEmitter{}) {
     const int32_t n = g->n;
     GPM_HIP(fill_u32(W.ctl, 0, 32, st));
     hipLaunchKernelGGL(k_root_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st, g->dag_off,
@@ -646,16 +709,19 @@ static gpm_status tc_launch(const gpm_graph *g, CliqueWs &W, unsigned long long 
     const bool arcs = MODE == TC_ARCS;
     gpm_status rc = tc_class<kTcMax, 512, MODE>(
         g, W, RC_BIG, W.list_b, W.wpre_b, W.first_b, 2, kTauBig, 4,
-        arcs ? "k_tc_block<1024,arcs>" : "k_tc_block<1024>", res, te, st);
+        MODE == TC_LIST ? "k_tc_block<1024,list>" : (arcs ? "k_tc_block<1024,arcs>" : "k_tc_block<1024>"),
+        res, te, em, st);
     if (rc) return rc;
     rc = tc_class<kTcMid, 256, MODE>(g, W, RC_MID, W.list_m, W.wpre_m, W.first_m, 1, kTauMid, 8,
-                                     arcs ? "k_tc_block<256,arcs>" : "k_tc_block<256>", res, te,
-                                     st);
+                                     MODE == TC_LIST ? "k_tc_block<256,list>"
+                                                     : (arcs ? "k_tc_block<256,arcs>" : "k_tc_block<256>"),
+                                     res, te, em, st);
     if (rc) return rc;
     return tc_class<kTcSmall, 64, MODE>(g, W, RC_SMALL, W.list_s, W.wpre_s, W.first_s, 0,
                                         kTauSmall, 32,
-                                        arcs ? "k_tc_block<64,arcs>" : "k_tc_block<64>", res, te,
-                                        st);
+                                        MODE == TC_LIST ? "k_tc_block<64,list>"
+                                                        : (arcs ? "k_tc_block<64,arcs>" : "k_tc_block<64>"),
+                                        res, te, em, st);
 }
 
 gpm_status triangle_arc_counts(const gpm_graph *g, void *ws, uint64_t ws_bytes, uint32_t *te,
@@ -676,7 +742,11 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
     unsigned long long *res = list ? d_result : W.result;
     GPM_HIP(fill_u32(res, 0, list ? 6 : 16, st));
     GPM_HIP(fill_u32(W.ctl, 0, 32, st));
-    const bool generic = list || g->max_out_degree > kTcMax;
+    const bool generic = uses_generic(g, k, list);
+    // listing through the triangle / local-graph kernels: slot counter in the
+    // workspace, totals and checksum into d_result
+    GPM_HIP(fill_u32(W.result, 0, 16, st));
+    RowEmitter em{W.result + 6, d_buf, list ? cap : 0, 0, 0, 0};
     if (generic) {
         ListOut lo{d_buf, list ? cap : 0};
         int blocks = W.gen_waves / kWPB;
@@ -694,7 +764,8 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
             GPM_LAUNCH_CHECK("k_finish_listing");
         }
     } else if (k == 3) {
-        gpm_status rc = tc_launch<TC_COUNT>(g, W, res, nullptr, st);
+        gpm_status rc = list ? tc_launch<TC_LIST>(g, W, res, nullptr, st, em)
+                             : tc_launch<TC_COUNT>(g, W, res, nullptr, st);
         if (rc) return rc;
     } else {
         hipLaunchKernelGGL(k_root_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st,
@@ -711,9 +782,10 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
             GPM_HIP(build_class(g, W, RC_SMALL, W.list_s, nullptr, st));
             GPM_HIP(hipMemcpyAsync(cnt_s, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
             gpm_status rc;
+            const RowEmitter *pem = list ? &em : nullptr;
             switch (k) {
-            case 4: rc = launch_local<4>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st); break;
-            case 5: rc = launch_local<5>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st); break;
+            case 4: rc = launch_local<4>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st, pem); break;
+            case 5: rc = launch_local<5>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st, pem); break;
             case 6: rc = launch_local<6>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st); break;
             case 7: rc = launch_local<7>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st); break;
             default: rc = launch_local<8>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st); break;
@@ -722,6 +794,10 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
         }
     }
     if (!list) GPM_HIP(hipMemcpyAsync(d_count, res, 8, hipMemcpyDeviceToDevice, st));
+    if (list && !generic) {
+        hipLaunchKernelGGL(k_finish_rows, dim3(1), dim3(64), 0, st, res, W.result + 6, cap);
+        GPM_LAUNCH_CHECK("k_finish_rows");
+    }
     return GPM_OK;
 }
 

@@ -234,12 +234,13 @@ __device__ void block_prefix(const int32_t (&val)[PER], int32_t d, int32_t *pre,
 // Stages root u (d out-neighbours starting at arc s) with NT threads, PER
 // out-neighbours per thread (NT * PER >= d).  keys must hold 2^hb slots and
 // be cleared to -1 before the call; vals may be null.  The hash value of v_j
-// is j, or lidx[j] when lidx is given.  Ends with a barrier.
+// is j, or lidx[j] when lidx is given.  verts (may be null) receives v_j at
+// its local index.  Ends with a barrier.
 template <int NT, int PER>
 __device__ void stage_root(const int32_t *__restrict__ dag_off, const int32_t *__restrict__ dag_adj,
                            int32_t s, int32_t d, int32_t *keys, int16_t *vals, int32_t hb,
                            int32_t *pre, int32_t *offj, int32_t *s_sum,
-                           const int16_t *lidx = nullptr) {
+                           const int16_t *lidx = nullptr, int32_t *verts = nullptr) {
     int32_t dv[PER], vv[PER], st[PER];
 #pragma unroll
     for (int k = 0; k < PER; k++) {
@@ -259,7 +260,9 @@ __device__ void stage_root(const int32_t *__restrict__ dag_off, const int32_t *_
         const int32_t i = threadIdx.x * PER + k;
         if (i < d) {
             offj[i] = st[k] - pre[i];
-            lds_hash_insert(keys, vals, hb, vv[k], lidx ? (int32_t)lidx[i] : i);
+            const int32_t li = lidx ? (int32_t)lidx[i] : i;
+            lds_hash_insert(keys, vals, hb, vv[k], li);
+            if (verts) verts[li] = vv[k];
         }
     }
     __syncthreads();
@@ -310,6 +313,75 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t z) {
     z ^= z >> 27; z *= 0x94D049BB133111EBull;
     z ^= z >> 31;
     return z;
+}
+
+// ---------------------------------------------------------- listing ---
+// Listing output: a slot counter hands out rows of the caller's buffer while
+// it has room (once a wave has seen the counter pass the capacity it stops
+// asking); the total and the checksum are kept per lane and added once per
+// wave at the end (row_emitter_flush), the written count by the host-side
+// finish (min(counter, cap)).
+struct RowEmitter {
+    unsigned long long *slot_ctr;
+    int32_t *buf;
+    uint64_t cap;
+    uint64_t cached;   // last counter value this lane's wave saw
+    uint64_t count;    // per lane
+    uint64_t hsum;     // per lane
+};
+
+// Checksum term of an embedding: its key sorted ascending, then
+// h = L, h = fmix64((h XOR key_i) + 0x9E3779B97F4A7C15) over the key.
+template <int L>
+__device__ __forceinline__ uint64_t sorted_key_hash(uint64_t (&k)[L]) {
+#pragma unroll
+    for (int i = 1; i < L; i++)
+#pragma unroll
+        for (int j = L - 1; j >= i; j--) {
+            const uint64_t a = k[j - 1], b = k[j];
+            k[j - 1] = a < b ? a : b;
+            k[j] = a < b ? b : a;
+        }
+    uint64_t h = (uint64_t)L;
+#pragma unroll
+    for (int i = 0; i < L; i++) h = fmix64((h ^ k[i]) + 0x9E3779B97F4A7C15ull);
+    return h;
+}
+
+// Emits the vertex-induced embedding v (L vertex ids, written in this order)
+// for every calling lane; may be called from divergent code (the lowest
+// active lane takes the slots for the others).
+template <int L>
+__device__ __forceinline__ void emit_vertices(RowEmitter &em, const int32_t (&v)[L]) {
+    uint64_t key[L];
+#pragma unroll
+    for (int i = 0; i < L; i++) key[i] = (uint64_t)(uint32_t)v[i];
+    em.hsum += sorted_key_hash<L>(key);
+    em.count++;
+    const uint64_t mask = __ballot(1);
+    const int leader = __builtin_ctzll(mask);
+    const bool ask = __shfl(em.cached, leader, 64) < em.cap;
+    if (!ask) return;
+    unsigned long long base = 0;
+    if (lane_id() == leader) base = atomicAdd(em.slot_ctr, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    em.cached = base + (uint64_t)__popcll(mask);
+    const uint64_t slot = base + (uint64_t)lanes_below(mask);
+    if (slot < em.cap) {
+        int32_t *o = em.buf + slot * (uint64_t)L;
+#pragma unroll
+        for (int i = 0; i < L; i++) o[i] = v[i];
+    }
+}
+
+// Adds the wave's totals to result[0] (embeddings) and result[2] (checksum);
+// the whole wave must call it.
+__device__ __forceinline__ void row_emitter_flush(const RowEmitter &em, unsigned long long *result) {
+    const uint64_t c = wave_sum(em.count), h = wave_sum(em.hsum);
+    if (lane_id() == 0) {
+        if (c) atomicAdd(&result[0], (unsigned long long)c);
+        if (h) atomicAdd(&result[2], (unsigned long long)h);
+    }
 }
 #endif
 

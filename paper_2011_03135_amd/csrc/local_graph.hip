@@ -92,7 +92,8 @@ template <int DMAX, int NT, bool RANK>
 __device__ void build_rows(const int32_t *__restrict__ off, const int32_t *__restrict__ dag_off,
                            const int32_t *__restrict__ dag_adj, int32_t u, int32_t d, int32_t W,
                            uint64_t *rows, int32_t *keys, int16_t *vals, int32_t *pre,
-                           int32_t *offj, int16_t *lidx, int32_t *s_sum) {
+                           int32_t *offj, int16_t *lidx, int32_t *s_sum,
+                           int32_t *verts = nullptr) {
     constexpr int PER = (DMAX + NT - 1) / NT;
     constexpr int NW = NT / kWave;
     constexpr int U = 2;
@@ -118,7 +119,7 @@ __device__ void build_rows(const int32_t *__restrict__ off, const int32_t *__res
     for (int32_t i = threadIdx.x; i < (1 << hb); i += NT) keys[i] = -1;
     for (int32_t i = threadIdx.x; i < d * W; i += NT) rows[i] = 0ull;
     stage_root<NT, PER>(dag_off, dag_adj, s, d, keys, vals, hb, pre, offj, s_sum,
-                        RANK ? lidx : nullptr);
+                        RANK ? lidx : nullptr, verts);
     const int32_t npairs = pre[d];
     const int32_t per_wave = ((npairs + NW - 1) / NW + U * kWave - 1) / (U * kWave) * (U * kWave);
     const int32_t qa = min(npairs, (int32_t)(threadIdx.x / kWave) * per_wave);
@@ -166,18 +167,20 @@ __device__ __forceinline__ void edge_at(const uint64_t *rows, const int32_t *pre
     j = wj * 64 + select_bit64(ri[wj], rr);
 }
 
-// 4-cliques: workgroup per root (atomic cursor over the class list).
-template <int DMAX, int NT>
+// 4-cliques: workgroup per root (atomic cursor over the class list).  With
+// LIST every 4-clique (u, v_i, v_j, v_x) is emitted instead of counted.
+template <int DMAX, int NT, bool LIST>
 __global__ void __launch_bounds__(NT) k_lg4(const int32_t *__restrict__ dag_off,
                                             const int32_t *__restrict__ dag_adj,
                                             const int32_t *__restrict__ roots,
                                             const int32_t *__restrict__ nroots_p,
                                             uint32_t *cursor, unsigned long long *result,
-                                            unsigned long long *res3) {
+                                            unsigned long long *res3, RowEmitter em) {
     __shared__ uint64_t rows[DMAX * (DMAX / 64)];
     __shared__ int32_t keys[LgHash<DMAX>::kSlots];
     __shared__ int16_t vals[LgHash<DMAX>::kSlots];
     __shared__ int32_t offj[DMAX], pre[DMAX + 1];
+    __shared__ int32_t verts[LIST ? DMAX : 1];
     __shared__ Lds<NT> sh;
     const int tid = threadIdx.x;
     const int32_t nroots = *nroots_p;
@@ -191,16 +194,32 @@ __global__ void __launch_bounds__(NT) k_lg4(const int32_t *__restrict__ dag_off,
         const int32_t u = roots[r];
         const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
         build_rows<DMAX, NT, false>(nullptr, dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj,
-                                     nullptr, sh.s_sum);
+                                     nullptr, sh.s_sum, LIST ? verts : nullptr);
         const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
         if (res3 && tid == 0 && ne) atomicAdd(res3, (unsigned long long)ne);   // triangles at u
         for (int32_t e = tid; e < ne; e += NT) {
             int32_t i, j;
             edge_at(rows, pre, d, W, e, i, j);
             const uint64_t *ri = rows + i * W, *rj = rows + j * W;
-            for (int32_t w = 0; w < W; w++) acc += __popcll(ri[w] & rj[w]);
+            if constexpr (LIST) {
+                for (int32_t w = 0; w < W; w++) {
+                    uint64_t m = ri[w] & rj[w];
+                    while (m) {
+                        const int32_t x = w * 64 + __builtin_ctzll(m);
+                        m &= m - 1ull;
+                        const int32_t q[4] = {u, verts[i], verts[j], verts[x]};
+                        emit_vertices<4>(em, q);
+                    }
+                }
+            } else {
+                for (int32_t w = 0; w < W; w++) acc += __popcll(ri[w] & rj[w]);
+            }
         }
         __syncthreads();
+    }
+    if (LIST) {
+        row_emitter_flush(em, result);
+        return;
     }
     acc = wave_sum(acc);
     if (lane_id() == 0 && acc) atomicAdd(result, (unsigned long long)acc);
@@ -224,6 +243,7 @@ __global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ off
     __shared__ int16_t vals[LgHash<DMAX>::kSlots];
     __shared__ int16_t lidx[DMAX];
     __shared__ int32_t offj[DMAX], pre[DMAX + 1];
+    __shared__ int32_t verts[DMAX];
     __shared__ Lds<NT> sh;
     const int tid = threadIdx.x;
     const int32_t nroots = *nroots_p;
@@ -237,9 +257,12 @@ __global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ off
         const int32_t u = roots[r];
         const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
         build_rows<DMAX, NT, true>(off, dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj,
-                                   lidx, sh.s_sum);
+                                   lidx, sh.s_sum, verts);
         uint64_t *dst = grows + rowoff[r];
         for (int32_t i = tid; i < d * W; i += NT) dst[i] = rows[i];
+        // then the out-neighbours in local (degree) order, for listings
+        int32_t *dverts = reinterpret_cast<int32_t *>(dst + d * W);
+        for (int32_t i = tid; i < d; i += NT) dverts[i] = verts[i];
         const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
         if (res3 && tid == 0 && ne) atomicAdd(res3, (unsigned long long)ne);   // triangles at u
         // local triangles (the 4-cliques at u) = candidates summed over local
@@ -268,7 +291,8 @@ __global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ off
     }
 }
 
-// Row words (d * W) of every class root, for the row storage prefix.
+// Storage words of every class root (d * W row words and d vertex ids), for
+// the row storage prefix.
 __global__ void k_lg_words(const int32_t *dag_off, const int32_t *roots, const int32_t *nroots_p,
                            int32_t *words) {
     const int32_t nroots = *nroots_p;
@@ -276,7 +300,7 @@ __global__ void k_lg_words(const int32_t *dag_off, const int32_t *roots, const i
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < nroots; i += stride) {
         const int32_t u = roots[i], d = dag_off[u + 1] - dag_off[u];
-        words[i] = d * ((d + 63) >> 6);
+        words[i] = d * ((d + 63) >> 6) + (d + 1) / 2;   // rows, then d int32 vertex ids
     }
 }
 
@@ -348,6 +372,77 @@ __device__ uint64_t lg5_vertex(const uint64_t *rows, const uint64_t *ri, int32_t
     return acc;
 }
 
+// Listing form of lg5_vertex: emits every 5-clique {u, v_i, a, b, x} with
+// a < b < x a triangle inside R (vertex ids from verts, the out-neighbours
+// in local order).
+template <int W>
+__device__ void lg5_list(const uint64_t *rows, const uint64_t *ri, int32_t c, int16_t *mem,
+                         const int32_t *verts, int32_t u, int32_t vi, RowEmitter &em) {
+    const int lane = lane_id();
+    uint64_t R[W];
+#pragma unroll
+    for (int q = 0; q < W; q++) R[q] = uniform64(ri[q]);
+    int32_t base = 0;
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+        if ((R[q] >> lane) & 1ull) mem[base + lanes_below(R[q])] = (int16_t)(q * 64 + lane);
+        base += __popcll(R[q]);
+    }
+    wave_sync();
+    for (int32_t a0 = 0; a0 < c; a0 += kWave) {
+        const int32_t a = a0 + lane;
+        uint64_t X[W];
+        int32_t pa = 0;
+        if (a < c) {
+            pa = mem[a];
+            const uint64_t *ra = rows + pa * W;
+#pragma unroll
+            for (int q = 0; q < W; q++) X[q] = ra[q] & R[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < W; q++) X[q] = 0ull;
+        }
+        const int32_t p0 = __builtin_amdgcn_readfirstlane((int32_t)mem[a0]);
+        const int32_t q0 = p0 >> 6;
+#pragma unroll
+        for (int q = 0; q < W; q++) {
+            if (q < q0) continue;
+            uint64_t m = R[q];
+            if (q == q0) m &= ~((2ull << (p0 & 63)) - 1ull);
+            while (m) {
+                const int bp = __builtin_ctzll(m);
+                m &= m - 1ull;
+                const int32_t pb = q * 64 + bp;
+                if ((X[q] >> bp) & 1ull) {
+                    const uint64_t *yb = rows + pb * W;
+#pragma unroll
+                    for (int w = q; w < W; w++) {
+                        uint64_t mm = X[w] & yb[w];
+                        while (mm) {
+                            const int32_t x = w * 64 + __builtin_ctzll(mm);
+                            mm &= mm - 1ull;
+                            const int32_t clq[5] = {u, vi, verts[pa], verts[pb], verts[x]};
+                            emit_vertices<5>(em, clq);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    wave_sync();
+}
+
+template <int WLO, int WHI>
+__device__ __forceinline__ void lg5_list_dispatch(int32_t W, const uint64_t *rows,
+                                                  const uint64_t *ri, int32_t c, int16_t *mem,
+                                                  const int32_t *verts, int32_t u, int32_t vi,
+                                                  RowEmitter &em) {
+    if constexpr (WLO <= WHI) {
+        if (W == WLO) lg5_list<WLO>(rows, ri, c, mem, verts, u, vi, em);
+        else lg5_list_dispatch<WLO + 1, WHI>(W, rows, ri, c, mem, verts, u, vi, em);
+    }
+}
+
 // (e + 3)-cliques of the local DAG inside the set S (W words, c >= 3
 // members): for e = 0 the triangles inside S; for e > 0 the sum over members
 // v of S of the (e + 2)-cliques inside S & row_v (rows hold only bits above
@@ -416,7 +511,7 @@ __device__ __forceinline__ uint64_t lg5_dispatch(int32_t W, const uint64_t *rows
     }
 }
 
-template <int DMAX>
+template <int DMAX, bool LIST>
 __global__ void __launch_bounds__(1024) k_lg5(const int32_t *__restrict__ dag_off,
                                               const int32_t *__restrict__ roots,
                                               const int32_t *__restrict__ toff,
@@ -424,7 +519,8 @@ __global__ void __launch_bounds__(1024) k_lg5(const int32_t *__restrict__ dag_of
                                               const int64_t *__restrict__ rowoff,
                                               const uint64_t *__restrict__ grows,
                                               int32_t rows_words, int32_t extra,
-                                              uint32_t *cursor, unsigned long long *result) {
+                                              uint32_t *cursor, unsigned long long *result,
+                                              RowEmitter em) {
     // row widths of the class: out-degrees (DMAX/4, DMAX]
     constexpr int WLO = DMAX / 256 + 1, WHI = DMAX / 64;
     extern __shared__ uint64_t dyn[];
@@ -432,8 +528,10 @@ __global__ void __launch_bounds__(1024) k_lg5(const int32_t *__restrict__ dag_of
     __shared__ Lds<1024> sh;
     const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
     const int NT = blockDim.x;
-    // per wave: member list (DMAX int16), then the descent stack
-    uint8_t *wave_area = reinterpret_cast<uint8_t *>(dyn + rows_words) +
+    // then the out-neighbours in local order (listing), then per wave: member
+    // list (DMAX int16) and the descent stack
+    int32_t *verts = reinterpret_cast<int32_t *>(dyn + rows_words);
+    uint8_t *wave_area = reinterpret_cast<uint8_t *>(verts + DMAX) +
                          (size_t)wib * (DMAX * 2 + (size_t)(extra + 1) * 2 * (DMAX / 64) * 8);
     int16_t *mem = reinterpret_cast<int16_t *>(wave_area);
     uint64_t *stack = reinterpret_cast<uint64_t *>(wave_area + DMAX * 2);
@@ -452,6 +550,10 @@ __global__ void __launch_bounds__(1024) k_lg5(const int32_t *__restrict__ dag_of
         const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
         const uint64_t *src = grows + rowoff[r];
         for (int32_t i = tid; i < d * W; i += NT) rows[i] = src[i];
+        if (LIST) {
+            const int32_t *sv = reinterpret_cast<const int32_t *>(src + d * W);
+            for (int32_t i = tid; i < d; i += NT) verts[i] = sv[i];
+        }
         if (tid == 0) sh.s_next = 0;
         __syncthreads();
         // waves take the slice's local vertices i = slice + S * c
@@ -465,9 +567,16 @@ __global__ void __launch_bounds__(1024) k_lg5(const int32_t *__restrict__ dag_of
             int32_t cnt = 0;
             for (int32_t w = 0; w < W; w++) cnt += __popcll(ri[w]);
             if (cnt < 3 + extra) continue;
-            acc += lg5_dispatch<WLO, WHI>(W, rows, ri, cnt, extra, mem, stack);
+            if constexpr (LIST)
+                lg5_list_dispatch<WLO, WHI>(W, rows, ri, cnt, mem, verts, u, verts[i], em);
+            else
+                acc += lg5_dispatch<WLO, WHI>(W, rows, ri, cnt, extra, mem, stack);
         }
         __syncthreads();
+    }
+    if (LIST) {
+        row_emitter_flush(em, result);
+        return;
     }
     acc = wave_sum(acc);
     if (lane == 0 && acc) atomicAdd(result, (unsigned long long)acc);
@@ -496,10 +605,10 @@ LgWs lg_layout(const gpm_graph *g, int32_t k, void *base) {
         L.rowoff_m = c.take<int64_t>(n1);
         L.rowoff_b = c.take<int64_t>(n1);
         L.scan_tmp = c.take<int64_t>(scan_tmp_words(n1));
-        // rows of all roots with out-degree in (64, 1024]: sum of d * ceil(d / 64)
-        // <= m * ceil(max_out / 64) words
-        const uint64_t wmax = (uint64_t)(std::max(g->max_out_degree, 1) + 63) / 64;
-        const uint64_t words = (uint64_t)std::max<int64_t>(g->m, 1) * wmax;
+        // rows and vertex ids of all roots with out-degree in (64, 1024]: sum of
+        // d * ceil(d / 64) + ceil(d / 2) <= m * (ceil(max_out / 64) + 1) words
+        const uint64_t wmax = (uint64_t)(std::max(g->max_out_degree, 1) + 63) / 64 + 1;
+        const uint64_t words = (uint64_t)std::max<int64_t>(g->m, 1) * wmax + (uint64_t)g->n;
         L.rows_m = c.take<uint64_t>(words);
         L.rows_b = c.take<uint64_t>(words);
     }
@@ -518,7 +627,8 @@ gpm_status lg5_class(const gpm_graph *g, int32_t k, LgWs &L, const int32_t *list
                      const int32_t *cnt,
                      int64_t *rowoff, uint64_t *rows, unsigned long long *units, int32_t *toff,
                      uint32_t *cursors, unsigned long long *res, unsigned long long *res3,
-                     unsigned long long *res4, hipStream_t st, const char *nb, const char *nc) {
+                     unsigned long long *res4, const RowEmitter *em, hipStream_t st,
+                     const char *nb, const char *nc) {
     const int32_t n = g->n;
     GPM_HIP(fill_u32(L.words, 0, (uint64_t)n + 1, st));
     hipLaunchKernelGGL(k_lg_words, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, g->dag_off, list,
@@ -542,14 +652,21 @@ gpm_status lg5_class(const gpm_graph *g, int32_t k, LgWs &L, const int32_t *list
         const int64_t lds_cap = 160 * 1024 - 1024;
         const int32_t extra = k - 5;
         const int64_t per_wave = (int64_t)DMAX * 2 + (int64_t)(extra + 1) * 2 * (DMAX / 64) * 8;
-        int waves = (int)std::min<int64_t>(DMAX <= 256 ? 4 : 16,
-                                           (lds_cap - (int64_t)rows_words * 8) / per_wave);
+        // rows, the local vertex ids, then the per-wave areas
+        const int64_t fixed = (int64_t)rows_words * 8 + (int64_t)DMAX * 4;
+        int waves = (int)std::min<int64_t>(DMAX <= 256 ? 4 : 16, (lds_cap - fixed) / per_wave);
         if (waves < 1) return fail(GPM_DEVICE_ERROR, "local graph does not fit in LDS");
-        const size_t shmem = (size_t)rows_words * 8 + (size_t)waves * per_wave;
+        const size_t shmem = (size_t)fixed + (size_t)waves * per_wave;
         Span sp(nc, st);
-        hipLaunchKernelGGL((k_lg5<DMAX>), dim3((unsigned)cu_count() * (DMAX <= 256 ? 4 : 1)),
-                           dim3(waves * kWave), shmem, st, g->dag_off, list, toff, cnt, rowoff,
-                           (const uint64_t *)rows, rows_words, extra, cursors + 1, res);
+        const dim3 grid((unsigned)cu_count() * (DMAX <= 256 ? 4 : 1));
+        if (em)
+            hipLaunchKernelGGL((k_lg5<DMAX, true>), grid, dim3(waves * kWave), shmem, st,
+                               g->dag_off, list, toff, cnt, rowoff, (const uint64_t *)rows,
+                               rows_words, extra, cursors + 1, res, *em);
+        else
+            hipLaunchKernelGGL((k_lg5<DMAX, false>), grid, dim3(waves * kWave), shmem, st,
+                               g->dag_off, list, toff, cnt, rowoff, (const uint64_t *)rows,
+                               rows_words, extra, cursors + 1, res, RowEmitter{});
         span_units(units, st);
     }
     GPM_LAUNCH_CHECK("k_lg5");
@@ -570,7 +687,7 @@ gpm_status lg_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes) {
 gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, const int32_t *cnt_m,
                       const int32_t *list_b, const int32_t *cnt_b, void *ws, uint64_t ws_bytes,
                       unsigned long long *res, unsigned long long *res3,
-                      unsigned long long *res4, hipStream_t st) {
+                      unsigned long long *res4, const RowEmitter *em, hipStream_t st) {
     LgWs L = lg_layout(g, k, ws);
     if (L.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "local-graph workspace too small");
     GPM_HIP(fill_u32(L.ctl, 0, 16, st));
@@ -578,28 +695,39 @@ gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, cons
     if (k == 4) {
         {
             Span sp("k_lg4<1024>", st);
-            hipLaunchKernelGGL((k_lg4<kBigMaxD, kBigThreads>), dim3((unsigned)cu_count()),
-                               dim3(kBigThreads), 0, st, g->dag_off, g->dag_adj, list_b, cnt_b,
-                               L.ctl + 0, res, res3);
+            if (em)
+                hipLaunchKernelGGL((k_lg4<kBigMaxD, kBigThreads, true>), dim3((unsigned)cu_count()),
+                                   dim3(kBigThreads), 0, st, g->dag_off, g->dag_adj, list_b, cnt_b,
+                                   L.ctl + 0, res, res3, *em);
+            else
+                hipLaunchKernelGGL((k_lg4<kBigMaxD, kBigThreads, false>),
+                                   dim3((unsigned)cu_count()), dim3(kBigThreads), 0, st, g->dag_off,
+                                   g->dag_adj, list_b, cnt_b, L.ctl + 0, res, res3, RowEmitter{});
         }
         GPM_LAUNCH_CHECK("k_lg4<1024>");
         {
             Span sp("k_lg4<256>", st);
-            hipLaunchKernelGGL((k_lg4<kMidMaxD, kMidThreads>), dim3((unsigned)cu_count() * 8),
-                               dim3(kMidThreads), 0, st, g->dag_off, g->dag_adj, list_m, cnt_m,
-                               L.ctl + 1, res, res3);
+            if (em)
+                hipLaunchKernelGGL((k_lg4<kMidMaxD, kMidThreads, true>),
+                                   dim3((unsigned)cu_count() * 8), dim3(kMidThreads), 0, st,
+                                   g->dag_off, g->dag_adj, list_m, cnt_m, L.ctl + 1, res, res3, *em);
+            else
+                hipLaunchKernelGGL((k_lg4<kMidMaxD, kMidThreads, false>),
+                                   dim3((unsigned)cu_count() * 8), dim3(kMidThreads), 0, st,
+                                   g->dag_off, g->dag_adj, list_m, cnt_m, L.ctl + 1, res, res3,
+                                   RowEmitter{});
         }
         GPM_LAUNCH_CHECK("k_lg4<256>");
         return GPM_OK;
     }
     gpm_status rc = lg5_class<kBigMaxD, kBigThreads>(g, k, L, list_b, cnt_b, L.rowoff_b, L.rows_b,
                                                      L.units + 0, L.toff_b, L.ctl + 2, res, res3,
-                                                     res4, st, "k_lg_build<1024>",
+                                                     res4, em, st, "k_lg_build<1024>",
                                                      k == 5 ? "k_lg5<1024>" : "k_lgk<1024>");
     if (rc) return rc;
     return lg5_class<kMidMaxD, kMidThreads>(g, k, L, list_m, cnt_m, L.rowoff_m, L.rows_m,
                                             L.units + 1, L.toff_m, L.ctl + 4, res, res3, res4,
-                                            st, "k_lg_build<256>",
+                                            em, st, "k_lg_build<256>",
                                             k == 5 ? "k_lg5<256>" : "k_lgk<256>");
 }
 

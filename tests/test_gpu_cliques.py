@@ -276,6 +276,54 @@ def test_clique_listing(gpm, k):
         assert all((a, b) in A for i, a in enumerate(r) for b in r[i + 1:])
 
 
+def hub_graph(seed=3):
+    """Roots in every out-degree class: 300 hubs (350 leaf edges each, random
+    hub-hub edges p = 0.15), root A adjacent to all hubs (out-degree 300,
+    above 256), root B to 150 of them (out-degree 150), 3000 leaves."""
+    rng = np.random.default_rng(seed)
+    H, L = 300, 3000
+    hubs = np.arange(H)
+    a_root, b_root = H, H + 1
+    leaf0 = H + 2
+    us, vs = [], []
+    for h in hubs:
+        lv = leaf0 + rng.choice(L, 350, replace=False)
+        us.append(np.full(350, h)); vs.append(lv)
+    iu, ju = np.triu_indices(H, 1)
+    keep = rng.random(iu.shape[0]) < 0.15
+    us.append(iu[keep]); vs.append(ju[keep])
+    us.append(np.full(H, a_root)); vs.append(hubs)
+    bsel = rng.choice(H, 150, replace=False)
+    us.append(np.full(150, b_root)); vs.append(bsel)
+    u = np.concatenate(us).astype(np.int32)
+    v = np.concatenate(vs).astype(np.int32)
+    return graphgen.EdgeList(leaf0 + L, u, v, "hubs")
+
+
+@pytest.mark.parametrize("gname", ["rmat14", "hubs"])
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_clique_listing_classes(gpm, k, gname):
+    """Listing through every out-degree class (<= 64, 65..256, 257..1024):
+    exact total and checksum, truncated rows that are cliques."""
+    e = graphgen.rmat(14, seed=14) if gname == "rmat14" else hub_graph()
+    g = build(gpm, e)
+    off, adj = canonical_csr(e.n, e.u, e.v)
+    print(f"{gname} k={k} max_out={g.max_out_degree}", flush=True)
+    if gname == "hubs":
+        assert g.max_out_degree > 256
+    total, chk, _ = oracle.clique_list(off, adj, k, cap=0)
+    cap = 1 << 16
+    t, w, c, got = gpm.list_embeddings(g, gpm.clique(k, gpm.VERTEX_INDUCED | gpm.LIST), cap)
+    assert (t, w, c) == (total, min(cap, total), chk)
+    rows = got.cpu().numpy().astype(np.int64)
+    assert rows.shape == (min(cap, total), k)
+    assert (np.sort(rows, axis=1)[:, 1:] > np.sort(rows, axis=1)[:, :-1]).all()
+    A = set((np.repeat(np.arange(e.n), np.diff(off)) * e.n + adj).tolist())
+    for i in range(k):
+        for j in range(i + 1, k):
+            assert all(int(x) in A for x in rows[:, i] * e.n + rows[:, j])
+
+
 def _golden():
     if not os.path.exists(GOLDEN):
         pytest.skip("golden counts not generated")
