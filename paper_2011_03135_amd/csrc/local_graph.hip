@@ -582,12 +582,93 @@ __global__ void __launch_bounds__(1024) k_lg5(const int32_t *__restrict__ dag_of
     if (lane == 0 && acc) atomicAdd(result, (unsigned long long)acc);
 }
 
+// k >= 5 for roots of out-degree 65..256, build and count in one kernel: a
+// workgroup builds the root's local graph in LDS (degree order), adds its
+// local edges (triangles at u) to res3 and its local triangles (4-cliques at
+// u) to res4 when asked, then its waves take the level-1 vertices and count
+// (or list) as k_lg5 does.  The local graphs are small, so no slicing and no
+// trip through HBM.
+template <int DMAX, int NT, bool LIST>
+__global__ void __launch_bounds__(NT) k_lg5_mid(const int32_t *__restrict__ off,
+                                                const int32_t *__restrict__ dag_off,
+                                                const int32_t *__restrict__ dag_adj,
+                                                const int32_t *__restrict__ roots,
+                                                const int32_t *__restrict__ nroots_p,
+                                                int32_t extra, uint32_t *cursor,
+                                                unsigned long long *result,
+                                                unsigned long long *res3,
+                                                unsigned long long *res4, RowEmitter em) {
+    constexpr int NW = NT / kWave;
+    constexpr int WMAX = DMAX / 64;
+    constexpr int WLO = 2, WHI = WMAX;   // out-degrees 65..DMAX
+    constexpr int kMaxExtra = 3;         // k <= 8
+    __shared__ uint64_t rows[DMAX * WMAX];
+    __shared__ int32_t keys[LgHash<DMAX>::kSlots];
+    __shared__ int16_t vals[LgHash<DMAX>::kSlots];
+    __shared__ int16_t lidx[DMAX];
+    __shared__ int32_t offj[DMAX], pre[DMAX + 1];
+    __shared__ int32_t verts[DMAX];
+    __shared__ int16_t s_mem[NW][DMAX];
+    __shared__ uint64_t s_stack[NW][(kMaxExtra + 1) * 2 * WMAX];
+    __shared__ Lds<NT> sh;
+    const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
+    const int32_t nroots = *nroots_p;
+    uint64_t acc = 0, acc3 = 0, acc4 = 0;
+    for (;;) {
+        if (tid == 0) sh.s_task = atomicAdd(cursor, 1u);
+        __syncthreads();
+        const int32_t r = (int32_t)sh.s_task;
+        __syncthreads();
+        if (r >= nroots) break;
+        const int32_t u = roots[r];
+        const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
+        build_rows<DMAX, NT, true>(off, dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj,
+                                   lidx, sh.s_sum, verts);
+        if (res3 || res4) {
+            const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
+            if (tid == 0) acc3 += ne;
+            if (res4)
+                for (int32_t e = tid; e < ne; e += NT) {
+                    int32_t i, j;
+                    edge_at(rows, pre, d, W, e, i, j);
+                    const uint64_t *ri = rows + i * W, *rj = rows + j * W;
+                    for (int32_t w = 0; w < W; w++) acc4 += __popcll(ri[w] & rj[w]);
+                }
+        }
+        for (int32_t i = wib; i < d; i += NW) {
+            const uint64_t *ri = rows + i * W;
+            int32_t cnt = 0;
+            for (int32_t w = 0; w < W; w++) cnt += __popcll(ri[w]);
+            if (cnt < 3 + extra) continue;
+            if constexpr (LIST)
+                lg5_list_dispatch<WLO, WHI>(W, rows, ri, cnt, s_mem[wib], verts, u, verts[i], em);
+            else
+                acc += lg5_dispatch<WLO, WHI>(W, rows, ri, cnt, extra, s_mem[wib], s_stack[wib]);
+        }
+        __syncthreads();
+    }
+    if (LIST) {
+        row_emitter_flush(em, result);
+        return;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0 && acc) atomicAdd(result, (unsigned long long)acc);
+    if (res3) {
+        acc3 = wave_sum(acc3);
+        if (lane == 0 && acc3) atomicAdd(res3, (unsigned long long)acc3);
+    }
+    if (res4) {
+        acc4 = wave_sum(acc4);
+        if (lane == 0 && acc4) atomicAdd(res4, (unsigned long long)acc4);
+    }
+}
+
 struct LgWs {
     uint32_t *ctl;                 // cursors
     unsigned long long *units;     // per class: local triangles (5-cliques' work)
-    int32_t *words, *slices, *toff_m, *toff_b;
-    int64_t *rowoff_m, *rowoff_b, *scan_tmp;
-    uint64_t *rows_m, *rows_b;
+    int32_t *words, *slices, *toff_b;
+    int64_t *rowoff_b, *scan_tmp;
+    uint64_t *rows_b;
     uint64_t bytes;
 };
 
@@ -600,16 +681,13 @@ LgWs lg_layout(const gpm_graph *g, int32_t k, void *base) {
     if (k >= 5) {
         L.words = c.take<int32_t>(n1);
         L.slices = c.take<int32_t>(n1);
-        L.toff_m = c.take<int32_t>(n1);
         L.toff_b = c.take<int32_t>(n1);
-        L.rowoff_m = c.take<int64_t>(n1);
         L.rowoff_b = c.take<int64_t>(n1);
         L.scan_tmp = c.take<int64_t>(scan_tmp_words(n1));
-        // rows and vertex ids of all roots with out-degree in (64, 1024]: sum of
+        // rows and vertex ids of all roots with out-degree in (256, 1024]: sum of
         // d * ceil(d / 64) + ceil(d / 2) <= m * (ceil(max_out / 64) + 1) words
         const uint64_t wmax = (uint64_t)(std::max(g->max_out_degree, 1) + 63) / 64 + 1;
         const uint64_t words = (uint64_t)std::max<int64_t>(g->m, 1) * wmax + (uint64_t)g->n;
-        L.rows_m = c.take<uint64_t>(words);
         L.rows_b = c.take<uint64_t>(words);
     }
     L.bytes = c.used;
@@ -725,10 +803,20 @@ gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, cons
                                                      res4, em, st, "k_lg_build<1024>",
                                                      k == 5 ? "k_lg5<1024>" : "k_lgk<1024>");
     if (rc) return rc;
-    return lg5_class<kMidMaxD, kMidThreads>(g, k, L, list_m, cnt_m, L.rowoff_m, L.rows_m,
-                                            L.units + 1, L.toff_m, L.ctl + 4, res, res3, res4,
-                                            em, st, "k_lg_build<256>",
-                                            k == 5 ? "k_lg5<256>" : "k_lgk<256>");
+    {
+        Span sp(k == 5 ? "k_lg5_mid<256>" : "k_lgk_mid<256>", st);
+        const dim3 grid((unsigned)cu_count() * 8);
+        if (em)
+            hipLaunchKernelGGL((k_lg5_mid<kMidMaxD, kMidThreads, true>), grid, dim3(kMidThreads), 0,
+                               st, g->off, g->dag_off, g->dag_adj, list_m, cnt_m, k - 5,
+                               L.ctl + 4, res, res3, res4, *em);
+        else
+            hipLaunchKernelGGL((k_lg5_mid<kMidMaxD, kMidThreads, false>), grid, dim3(kMidThreads),
+                               0, st, g->off, g->dag_off, g->dag_adj, list_m, cnt_m, k - 5,
+                               L.ctl + 4, res, res3, res4, RowEmitter{});
+    }
+    GPM_LAUNCH_CHECK("k_lg5_mid");
+    return GPM_OK;
 }
 
 }  // namespace gpm
