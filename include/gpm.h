@@ -295,7 +295,9 @@ typedef struct gpm_server gpm_server;
 
 typedef struct gpm_server_config {
     int32_t max_slots;      /* concurrent requests on the device, 1..64 */
-    int32_t reserved;
+    int32_t cu_percent;     /* share of the compute units one request's persistent
+                               kernels are sized for, 1..100 (0: 50), so that
+                               concurrent requests run side by side */
     void *d_pool;           /* device memory for request workspaces (caller-owned) */
     uint64_t pool_bytes;
 } gpm_server_config;

@@ -412,7 +412,7 @@ QUERY_MOTIF = 2
 
 
 class _ServerConfig(ctypes.Structure):
-    _fields_ = [("max_slots", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("max_slots", ctypes.c_int32), ("cu_percent", ctypes.c_int32),
                 ("d_pool", ctypes.c_void_p), ("pool_bytes", ctypes.c_uint64)]
 
 
@@ -435,9 +435,10 @@ class Response(ctypes.Structure):
 class Server:
     """gpm_server_*: concurrent request execution over resident graphs."""
 
-    def __init__(self, max_slots=4, pool_bytes=8 << 30, device="cuda"):
+    def __init__(self, max_slots=4, pool_bytes=8 << 30, device="cuda", cu_percent=0):
         self._pool = _buffer(pool_bytes, torch.device(device))
-        cfg = _ServerConfig(int(max_slots), 0, self._pool.data_ptr(), int(self._pool.numel()))
+        cfg = _ServerConfig(int(max_slots), int(cu_percent), self._pool.data_ptr(),
+                            int(self._pool.numel()))
         self._h = ctypes.c_void_p()
         _check(load().gpm_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
         self._graphs = {}

@@ -100,6 +100,8 @@ struct Span {
 // to cover every CU several times.
 int persistent_blocks(int waves_per_block, int blocks_per_cu);
 int cu_count();
+// Caps cu_count() for the calling thread (0 = no cap).
+void set_cu_limit(int limit);
 
 // ---------------------------------------------------------- device side --
 #ifdef __HIPCC__

@@ -97,6 +97,7 @@ struct gpm_server {
     bool stop = false;
     std::thread worker;
     int dev = 0;
+    int cu_limit = 0;              // compute units one request's grids are sized for
 };
 
 namespace {
@@ -119,10 +120,13 @@ gpm_status launch(gpm_server *s, int i, Job *j) {
     void *ws = pool + s->result_bytes + j->ws_off;
     hipStream_t st = s->streams[i];
     gpm_status rc;
+    // size this request's persistent grids for its share of the device
+    gpm::set_cu_limit(s->cu_limit);
     if (j->req.kind == GPM_QUERY_CLIQUE)
         rc = gpm_count(j->req.graph, &j->pat, ws, j->ws_bytes, d_res, st);
     else
         rc = gpm_motif_count(j->req.graph, j->req.k, ws, j->ws_bytes, d_res, st);
+    gpm::set_cu_limit(0);
     if (rc) return rc;
     GPM_HIP(hipMemcpyAsync(s->pinned + 8 * i, d_res, 64, hipMemcpyDeviceToHost, st));
     GPM_HIP(hipEventRecord(s->events[i], st));
@@ -201,6 +205,8 @@ gpm_status gpm_server_create(const gpm_server_config *cfg, gpm_server **out) {
     if (!cfg || !out) return gpm::fail(GPM_INVALID_ARGUMENT, "NULL argument");
     if (cfg->max_slots < 1 || cfg->max_slots > 64)
         return gpm::fail(GPM_INVALID_ARGUMENT, "max_slots must be in [1, 64]");
+    if (cfg->cu_percent < 0 || cfg->cu_percent > 100)
+        return gpm::fail(GPM_INVALID_ARGUMENT, "cu_percent must be in [0, 100]");
     if (!cfg->d_pool || ((uintptr_t)cfg->d_pool & 255))
         return gpm::fail(GPM_INVALID_ARGUMENT, "pool NULL or not 256-byte aligned");
     const uint64_t result_bytes = (uint64_t)cfg->max_slots * 256;
@@ -212,6 +218,10 @@ gpm_status gpm_server_create(const gpm_server_config *cfg, gpm_server **out) {
     s->result_bytes = result_bytes;
     s->pool = new Pool(cfg->pool_bytes - result_bytes);
     hipGetDevice(&s->dev);
+    {
+        const int pct = cfg->cu_percent > 0 ? cfg->cu_percent : 50;
+        s->cu_limit = std::max(1, gpm::cu_count() * pct / 100);
+    }
     for (int i = 0; i < cfg->max_slots; i++) {
         hipStream_t st;
         hipEvent_t ev;

@@ -239,20 +239,32 @@ int timing_read(const char **names, float *ms, uint64_t *units, int cap) {
 }
 
 // ---------------------------------------------------------- launch sizing --
+// Persistent grids are sized from the compute-unit count; a thread may cap
+// the count it sees (the serving scheduler does, so that one request's
+// persistent kernels leave room for others').
+static thread_local int tls_cu_limit = 0;
+
+void set_cu_limit(int limit) { tls_cu_limit = limit > 0 ? limit : 0; }
+
 int cu_count() {
     static int cached = 0;
     static std::mutex mu;
-    std::lock_guard<std::mutex> lock(mu);
-    if (cached == 0) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            cus > 0)
-            cached = cus;
-        else
-            cached = 256;
+    int c;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        if (cached == 0) {
+            int dev = 0, cus = 0;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) ==
+                    hipSuccess &&
+                cus > 0)
+                cached = cus;
+            else
+                cached = 256;
+        }
+        c = cached;
     }
-    return cached;
+    return tls_cu_limit > 0 && tls_cu_limit < c ? tls_cu_limit : c;
 }
 
 int persistent_blocks(int waves_per_block, int blocks_per_cu) {

@@ -27,7 +27,7 @@ def percentile(xs, q):
 
 
 def run_load(graphs, rate=500.0, n_requests=5000, n_warmup=500, seed=500, max_slots=4,
-             pool_bytes=16 << 30, queries=QUERIES, server=None, progress=None):
+             pool_bytes=16 << 30, queries=QUERIES, server=None, progress=None, cu_percent=0):
     """Returns (stats dict, list of (graph index, query index, response)).
     `progress(done, total)` is called after every 500 completions."""
     rng = np.random.default_rng(seed)
@@ -36,7 +36,7 @@ def run_load(graphs, rate=500.0, n_requests=5000, n_warmup=500, seed=500, max_sl
     gidx = rng.integers(0, len(graphs), size=total)
     qidx = rng.integers(0, len(queries), size=total)
     own = server is None
-    srv = server or Server(max_slots=max_slots, pool_bytes=pool_bytes)
+    srv = server or Server(max_slots=max_slots, pool_bytes=pool_bytes, cu_percent=cu_percent)
     done = {}
     t0 = Server.now() + 0.05
     arrivals = t0 + np.cumsum(gaps)
