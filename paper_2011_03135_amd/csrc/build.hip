@@ -8,7 +8,8 @@
 //   dag_src        the source vertex of every arc.
 //
 // Pipeline (one stream, no host round trip until the final size read-back):
-//   count arcs per vertex -> scan -> scatter arcs into rows (atomic cursors)
+//   arcs into buckets of consecutive source ids (LDS histograms per tile)
+//   -> per bucket: row offsets and arcs into rows (LDS counters)
 //   -> per-row sort + unique (wave bitonic in registers for <= 64 entries,
 //      wave bitonic in LDS for <= 2048, workgroup bitmap for longer rows)
 //   -> scan unique counts -> compact rows -> count out-arcs -> scan -> fill.
@@ -71,6 +72,122 @@ __global__ void __launch_bounds__(kBlock) k_scatter_raw(const int32_t *__restric
         int32_t pb = atomicAdd(&cursor[b], 1);
         raw_adj[raw_off[b] + pb] = a;
     }
+}
+
+// ------------------------------------------- bucketed arc distribution --
+// Arcs (both directions of every raw edge, loops dropped) go to rows in
+// three passes without global atomics on hot vertices: arcs are first
+// counted and moved into buckets of 2^S consecutive source ids (one LDS
+// histogram per tile of edges, one global atomic per tile and bucket), then
+// each bucket's block counts its sources in LDS, writes the row offsets and
+// places the arcs inside the bucket's own range of the row array.
+constexpr int kTileEdges = 8192;     // raw edges per tile
+constexpr int kMaxBuckets = 4096;    // LDS histogram of a tile
+constexpr int kMaxBucketIds = 16384; // LDS counters of a bucket (2^S <= this)
+constexpr int kBucketNT = 1024;
+
+__global__ void __launch_bounds__(kBlock) k_bucket_count(const int32_t *__restrict__ u,
+                                                         const int32_t *__restrict__ v,
+                                                         int64_t E, int32_t n, int32_t S,
+                                                         int32_t nb, int32_t *bucket_cnt,
+                                                         uint32_t *flags) {
+    __shared__ int32_t hist[kMaxBuckets];
+    const int64_t ntiles = (E + kTileEdges - 1) / kTileEdges;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        for (int b = threadIdx.x; b < nb; b += kBlock) hist[b] = 0;
+        __syncthreads();
+        const int64_t e1 = min(E, (t + 1) * (int64_t)kTileEdges);
+        for (int64_t i = t * (int64_t)kTileEdges + threadIdx.x; i < e1; i += kBlock) {
+            const int32_t a = u[i], b = v[i];
+            if ((uint32_t)a >= (uint32_t)n || (uint32_t)b >= (uint32_t)n) {
+                atomicOr(&flags[F_ERR], 1u);
+                continue;
+            }
+            if (a == b) continue;
+            atomicAdd(&hist[a >> S], 1);
+            atomicAdd(&hist[b >> S], 1);
+        }
+        __syncthreads();
+        for (int b = threadIdx.x; b < nb; b += kBlock)
+            if (hist[b]) atomicAdd(&bucket_cnt[b], hist[b]);
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_bucket_scatter(const int32_t *__restrict__ u,
+                                                           const int32_t *__restrict__ v,
+                                                           int64_t E, int32_t n, int32_t S,
+                                                           int32_t nb, int32_t *bucket_cur,
+                                                           int32_t *bsrc, int32_t *bdst) {
+    __shared__ int32_t hist[kMaxBuckets];
+    const int64_t ntiles = (E + kTileEdges - 1) / kTileEdges;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        for (int b = threadIdx.x; b < nb; b += kBlock) hist[b] = 0;
+        __syncthreads();
+        const int64_t e0 = t * (int64_t)kTileEdges, e1 = min(E, e0 + kTileEdges);
+        for (int64_t i = e0 + threadIdx.x; i < e1; i += kBlock) {
+            const int32_t a = u[i], b = v[i];
+            if ((uint32_t)a >= (uint32_t)n || (uint32_t)b >= (uint32_t)n || a == b) continue;
+            atomicAdd(&hist[a >> S], 1);
+            atomicAdd(&hist[b >> S], 1);
+        }
+        __syncthreads();
+        // reserve each bucket's share: hist becomes the tile's write cursor
+        for (int b = threadIdx.x; b < nb; b += kBlock)
+            if (hist[b]) hist[b] = atomicAdd(&bucket_cur[b], hist[b]);
+        __syncthreads();
+        for (int64_t i = e0 + threadIdx.x; i < e1; i += kBlock) {
+            const int32_t a = u[i], b = v[i];
+            if ((uint32_t)a >= (uint32_t)n || (uint32_t)b >= (uint32_t)n || a == b) continue;
+            const int32_t pa = atomicAdd(&hist[a >> S], 1);
+            bsrc[pa] = a;
+            bdst[pa] = b;
+            const int32_t pb = atomicAdd(&hist[b >> S], 1);
+            bsrc[pb] = b;
+            bdst[pb] = a;
+        }
+        __syncthreads();
+    }
+}
+
+// One block per bucket: row offsets of its 2^S sources and their arcs.
+__global__ void __launch_bounds__(kBucketNT) k_bucket_rows(const int32_t *__restrict__ bucket_off,
+                                                           const int32_t *__restrict__ bsrc,
+                                                           const int32_t *__restrict__ bdst,
+                                                           int32_t n, int32_t S, int32_t nb,
+                                                           int32_t *raw_off, int32_t *raw_adj) {
+    constexpr int PER = kMaxBucketIds / kBucketNT;
+    __shared__ int32_t cnt[kMaxBucketIds + 1];
+    __shared__ int32_t s_sum[kBucketNT / kWave];
+    const int32_t ids = 1 << S;
+    for (int32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int32_t base = b << S;
+        const int32_t a0 = bucket_off[b], a1 = bucket_off[b + 1];
+        for (int32_t i = threadIdx.x; i < ids; i += kBucketNT) cnt[i] = 0;
+        __syncthreads();
+        for (int32_t i = a0 + threadIdx.x; i < a1; i += kBucketNT) atomicAdd(&cnt[bsrc[i] - base], 1);
+        __syncthreads();
+        int32_t val[PER];
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int32_t i = threadIdx.x * PER + q;
+            val[q] = i < ids ? cnt[i] : 0;
+        }
+        __syncthreads();
+        // exclusive prefix of the counts: cnt[i] becomes the first slot of row base+i
+        block_prefix<kBucketNT, PER>(val, ids, cnt, s_sum);
+        for (int32_t i = threadIdx.x; i < ids; i += kBucketNT) {
+            const int32_t vtx = base + i;
+            if (vtx < n) raw_off[vtx] = a0 + cnt[i];
+        }
+        __syncthreads();
+        for (int32_t i = a0 + threadIdx.x; i < a1; i += kBucketNT) {
+            const int32_t p = atomicAdd(&cnt[bsrc[i] - base], 1);
+            raw_adj[a0 + p] = bdst[i];
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) raw_off[n] = bucket_off[nb];
 }
 
 // Sorts row entries held one per lane (lanes >= L hold INT_MAX) ascending.
@@ -349,12 +466,22 @@ struct BuildLayout {
     int64_t *meta;
     // scratch
     int32_t *cnt, *raw_off, *raw_adj, *ucnt, *outcnt, *big_list;
+    int32_t S, nb;                                  // buckets of 2^S source ids (S = 0: none)
+    int32_t *bucket_cnt, *bucket_off, *bucket_cur, *bsrc, *bdst;
     int64_t *scan_tmp;
     uint32_t *flags, *bitmaps;
     int64_t words;
     int nbig_blocks;
     uint64_t graph_bytes, scratch_bytes;
 };
+
+// Bucket shift for n vertices: the smallest S >= 12 with at most
+// kMaxBuckets buckets of 2^S ids, or 0 when 2^S would exceed kMaxBucketIds.
+int32_t bucket_shift(int32_t n) {
+    int32_t S = 12;
+    while (((int64_t)n + (1ll << S) - 1) >> S > kMaxBuckets) S++;
+    return (1 << S) <= kMaxBucketIds ? S : 0;
+}
 
 BuildLayout layout(int32_t n, int64_t E, void *gmem, void *smem) {
     BuildLayout L{};
@@ -375,6 +502,15 @@ BuildLayout layout(int32_t n, int64_t E, void *gmem, void *smem) {
     L.big_list = s.take<int32_t>((uint64_t)n + 1);
     L.scan_tmp = s.take<int64_t>(scan_tmp_words((uint64_t)n + 1));
     L.flags = s.take<uint32_t>(F_WORDS);
+    L.S = bucket_shift(n);
+    if (L.S > 0) {
+        L.nb = (int32_t)(((int64_t)n + (1ll << L.S) - 1) >> L.S);
+        L.bucket_cnt = s.take<int32_t>((uint64_t)L.nb + 1);
+        L.bucket_off = s.take<int32_t>((uint64_t)L.nb + 1);
+        L.bucket_cur = s.take<int32_t>((uint64_t)L.nb + 1);
+        L.bsrc = s.take<int32_t>((uint64_t)(2 * E));
+        L.bdst = s.take<int32_t>((uint64_t)(2 * E));
+    }
     L.words = ((int64_t)n + 31) / 32;
     // bitmap sorters: as many concurrent workgroups as fit in 64 MiB, 1..256
     int64_t per = L.words * 4;
@@ -538,19 +674,39 @@ gpm_status graph_from_csr(int32_t n, const int32_t *d_off, const int32_t *d_adj,
 static gpm_status enqueue_build(int32_t n, const int32_t *d_u, const int32_t *d_v, int64_t E,
                          const BuildLayout &L, hipStream_t st) {
     Span whole("graph_build", st);
-    GPM_HIP(fill_u32(L.cnt, 0, (uint64_t)n + 1, st));
     GPM_HIP(fill_u32(L.flags, 0, F_WORDS, st));
-    if (E > 0) {
-        hipLaunchKernelGGL(k_count_raw, dim3(flat_grid(E)), dim3(kBlock), 0, st, d_u, d_v, E, n,
-                           L.cnt, L.flags);
-        GPM_LAUNCH_CHECK("k_count_raw");
-    }
-    GPM_HIP(exclusive_scan_i32(L.cnt, L.raw_off, (uint64_t)n, L.scan_tmp, st));
-    GPM_HIP(fill_u32(L.cnt, 0, (uint64_t)n + 1, st));
-    if (E > 0) {
-        hipLaunchKernelGGL(k_scatter_raw, dim3(flat_grid(E)), dim3(kBlock), 0, st, d_u, d_v, E,
-                           n, L.raw_off, L.cnt, L.raw_adj);
-        GPM_LAUNCH_CHECK("k_scatter_raw");
+    if (E > 0 && L.S > 0) {
+        const int64_t tiles = (E + kTileEdges - 1) / kTileEdges;
+        const unsigned tgrid = (unsigned)std::min<int64_t>(tiles, (int64_t)cu_count() * 8);
+        GPM_HIP(fill_u32(L.bucket_cnt, 0, (uint64_t)L.nb + 1, st));
+        hipLaunchKernelGGL(k_bucket_count, dim3(tgrid), dim3(kBlock), 0, st, d_u, d_v, E, n, L.S,
+                           L.nb, L.bucket_cnt, L.flags);
+        GPM_LAUNCH_CHECK("k_bucket_count");
+        GPM_HIP(exclusive_scan_i32(L.bucket_cnt, L.bucket_off, (uint64_t)L.nb, L.scan_tmp, st));
+        GPM_HIP(hipMemcpyAsync(L.bucket_cur, L.bucket_off, sizeof(int32_t) * (size_t)L.nb,
+                               hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_bucket_scatter, dim3(tgrid), dim3(kBlock), 0, st, d_u, d_v, E, n,
+                           L.S, L.nb, L.bucket_cur, L.bsrc, L.bdst);
+        GPM_LAUNCH_CHECK("k_bucket_scatter");
+        hipLaunchKernelGGL(k_bucket_rows,
+                           dim3((unsigned)std::min<int64_t>(L.nb, (int64_t)cu_count() * 2)),
+                           dim3(kBucketNT), 0, st, L.bucket_off, L.bsrc, L.bdst, n, L.S, L.nb,
+                           L.raw_off, L.raw_adj);
+        GPM_LAUNCH_CHECK("k_bucket_rows");
+    } else {
+        GPM_HIP(fill_u32(L.cnt, 0, (uint64_t)n + 1, st));
+        if (E > 0) {
+            hipLaunchKernelGGL(k_count_raw, dim3(flat_grid(E)), dim3(kBlock), 0, st, d_u, d_v, E,
+                               n, L.cnt, L.flags);
+            GPM_LAUNCH_CHECK("k_count_raw");
+        }
+        GPM_HIP(exclusive_scan_i32(L.cnt, L.raw_off, (uint64_t)n, L.scan_tmp, st));
+        GPM_HIP(fill_u32(L.cnt, 0, (uint64_t)n + 1, st));
+        if (E > 0) {
+            hipLaunchKernelGGL(k_scatter_raw, dim3(flat_grid(E)), dim3(kBlock), 0, st, d_u, d_v,
+                               E, n, L.raw_off, L.cnt, L.raw_adj);
+            GPM_LAUNCH_CHECK("k_scatter_raw");
+        }
     }
     hipLaunchKernelGGL(k_sort_rows, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.raw_off,
                        L.raw_adj, n, L.ucnt, L.big_list, L.flags);
