@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(NT) k_tc_block(const int32_t *__restrict__ dag
     constexpr int H = 4 * DMAX;
     constexpr int PER = (DMAX + NT - 1) / NT;
     static_assert(DMAX <= 32767, "local indices are kept as int16");
-    __shared__ int32_t keys[H];
+    __shared__ __align__(16) int32_t keys[H];
     __shared__ int16_t vals[MODE == TC_ARCS ? H : 1];
     __shared__ int32_t pre[DMAX + 1];
     __shared__ int32_t offj[DMAX];
@@ -223,8 +223,8 @@ __global__ void __launch_bounds__(NT) k_tc_block(const int32_t *__restrict__ dag
                 ((q1 - q0 + NW - 1) / NW + U * kWave - 1) / (U * kWave) * (U * kWave);
             const int32_t qa = min(q1, q0 + wid * per_wave);
             const int32_t qz = min(q1, qa + per_wave);
-            walk_pairs<U>(pre, offj, dag_adj, d, qa, qz, [&](int32_t jj, int32_t e_vw, int32_t w) {
-                const int32_t slot = lds_hash_find(keys, hb, w);
+            walk_lookup<U>(pre, offj, dag_adj, d, qa, qz, keys, hb,
+                    [&](int32_t jj, int32_t e_vw, int32_t w, int32_t slot) {
                 if (slot >= 0) {
                     acc++;
                     if (MODE == TC_ARCS) {
@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(kWave) k_clique_wave(const int32_t *__restrict
                                                        unsigned long long *res3,
                                                        unsigned long long *res4, RowEmitter em) {
     __shared__ uint64_t rows[kWave];
-    __shared__ int32_t keys[4 * kWave];
+    __shared__ __align__(16) int32_t keys[4 * kWave];
     __shared__ int16_t vals[4 * kWave];
     __shared__ int32_t pre[kWave + 1], offj[kWave];
     __shared__ int32_t verts[LIST ? kWave : 1];
@@ -346,8 +346,8 @@ __global__ void __launch_bounds__(kWave) k_clique_wave(const int32_t *__restrict
         rows[lane] = 0;
         stage_root<kWave, 1>(dag_off, dag_adj, s, d, keys, vals, hb, pre, offj, nullptr, nullptr,
                              LIST ? verts : nullptr);
-        walk_pairs<2>(pre, offj, dag_adj, d, 0, pre[d], [&](int32_t j, int32_t, int32_t w) {
-            const int32_t slot = lds_hash_find(keys, hb, w);
+        walk_lookup<2>(pre, offj, dag_adj, d, 0, pre[d], keys, hb,
+                [&](int32_t j, int32_t, int32_t w, int32_t slot) {
             if (slot >= 0) atomicOr((unsigned long long *)&rows[j], 1ull << vals[slot]);
         });
         __syncthreads();

@@ -160,8 +160,12 @@ __device__ __forceinline__ void atomic_add_u128(unsigned long long *p, unsigned 
 // vertex is one of a root's out-neighbours (and to find its local index)
 // with one or two LDS reads instead of a binary search.
 
+// Open addressing with linear probing in LDS; a key's probe sequence starts
+// at the first slot of a bucket of 4, so a lookup can read 4 slots at once
+// (one 16-byte LDS read) and visits the slots in the order an insert does.
+// Key arrays are 16-byte aligned with at least 64 slots.
 __device__ __forceinline__ uint32_t lds_hash_slot(int32_t key, int32_t bits) {
-    return ((uint32_t)key * 0x9E3779B1u) >> (32 - bits);
+    return (((uint32_t)key * 0x9E3779B1u) >> (32 - bits)) & ~3u;
 }
 
 // Smallest table size exponent with 2^bits >= 4 * d (load factor <= 1/4),
@@ -270,18 +274,27 @@ __device__ void stage_root(const int32_t *__restrict__ dag_off, const int32_t *_
     __syncthreads();
 }
 
-// Calls f(j, e_vw, w) for every pair q in [qa, qz) of a staged root with d
-// out-neighbours, one pair per lane, U tiles of 64 pairs per step with their
-// loads of w issued together.  A lane finds the segment of its pair by
-// walking forward from the segment of the previous step's last pair (one
-// binary search per call), so a tile costs one LDS read per segment
-// boundary it crosses.  Wave-uniform qa and qz.
+// Calls f(j, e_vw, w, slot) for every pair q in [qa, qz) of a staged root
+// with d out-neighbours: w is the end of arc e_vw (v = v_j) and slot the
+// hash slot of w in keys (2^bits slots), or -1 when w is not an
+// out-neighbour of the root.  One pair per lane, U tiles of 64 pairs per
+// step, and every round trip to memory is shared by the step's U tiles:
+//   - segment: when the step lies inside the current segment j (the usual
+//     case: segments are long), its pairs take e = offj[j] + q from two
+//     wave-uniform reads; otherwise each lane walks forward from j;
+//   - the U loads of w are issued together;
+//   - the lookups read a bucket of 4 slots per tile and round, all tiles in
+//     the same round, until every lane has a match or an empty slot.
+// Wave-uniform qa and qz.
 template <int U, class F>
-__device__ __forceinline__ void walk_pairs(const int32_t *pre, const int32_t *offj,
-                                           const int32_t *__restrict__ dag_adj, int32_t d,
-                                           int32_t qa, int32_t qz, F &&f) {
+__device__ __forceinline__ void walk_lookup(const int32_t *pre, const int32_t *offj,
+                                            const int32_t *__restrict__ dag_adj, int32_t d,
+                                            int32_t qa, int32_t qz, const int32_t *keys,
+                                            int32_t bits, F &&f) {
     if (qa >= qz) return;
     const int lane = lane_id();
+    const uint32_t bmask = (1u << (bits - 2)) - 1u;   // buckets of 4 slots
+    const int4 *kb = reinterpret_cast<const int4 *>(keys);
     int32_t lo = 0, hi = d;   // last j with pre[j] <= qa
     while (hi - lo > 1) {
         const int32_t mid = (lo + hi) >> 1;
@@ -289,23 +302,61 @@ __device__ __forceinline__ void walk_pairs(const int32_t *pre, const int32_t *of
     }
     int32_t j = lo;
     for (int32_t qb = qa; qb < qz; qb += U * 64) {
-        int32_t jj[U], e[U], w[U];
-        int32_t jc = j;
+        int32_t jj[U], e[U], w[U], slot[U];
+        uint32_t b[U];
+        const int32_t seg_end = pre[j + 1], seg_base = offj[j];
+        if (qb + U * 64 <= seg_end) {
 #pragma unroll
-        for (int t = 0; t < U; t++) {
-            const int32_t q = qb + t * 64 + lane;
-            if (q < qz)
-                while (pre[jc + 1] <= q) jc++;
-            jj[t] = jc;
-            e[t] = offj[jc] + q;
+            for (int t = 0; t < U; t++) {
+                jj[t] = j;
+                e[t] = seg_base + qb + t * 64 + lane;
+            }
+        } else {
+            int32_t jc = j;
+#pragma unroll
+            for (int t = 0; t < U; t++) {
+                const int32_t q = qb + t * 64 + lane;
+                if (q < qz)
+                    while (pre[jc + 1] <= q) jc++;
+                jj[t] = jc;
+                e[t] = offj[jc] + q;
+            }
         }
 #pragma unroll
         for (int t = 0; t < U; t++)
             w[t] = qb + t * 64 + lane < qz ? dag_adj[e[t]] : -1;
 #pragma unroll
+        for (int t = 0; t < U; t++) {
+            b[t] = lds_hash_slot(w[t], bits) >> 2;
+            slot[t] = w[t] >= 0 ? -2 : -1;   // -2: still looking
+        }
+        for (;;) {
+            int4 kv[U];
+#pragma unroll
+            for (int t = 0; t < U; t++)
+                if (slot[t] == -2) kv[t] = kb[b[t]];
+            bool more = false;
+#pragma unroll
+            for (int t = 0; t < U; t++) {
+                if (slot[t] != -2) continue;
+                const int4 k = kv[t];
+                const int32_t s0 = (int32_t)b[t] * 4;
+                if (k.x == w[t]) slot[t] = s0;
+                else if (k.y == w[t]) slot[t] = s0 + 1;
+                else if (k.z == w[t]) slot[t] = s0 + 2;
+                else if (k.w == w[t]) slot[t] = s0 + 3;
+                else if ((k.x | k.y | k.z | k.w) < 0) slot[t] = -1;
+                else {
+                    b[t] = (b[t] + 1u) & bmask;
+                    more = true;
+                }
+            }
+            if (!__any(more)) break;
+        }
+#pragma unroll
         for (int t = 0; t < U; t++)
-            if (qb + t * 64 + lane < qz) f(jj[t], e[t], w[t]);
-        j = __shfl(jc, 63, 64);
+            if (qb + t * 64 + lane < qz) f(jj[t], e[t], w[t], slot[t]);
+        j = __shfl(jj[U - 1], 63, 64);
     }
 }
 

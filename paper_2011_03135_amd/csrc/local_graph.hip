@@ -32,6 +32,11 @@ constexpr int kMidMaxD = 256;
 constexpr int kBigMaxD = 1024;
 constexpr int kMidThreads = 256;
 constexpr int kBigThreads = 1024;
+// the big class's roots of out-degree 257..512 run at this bound: a third of
+// the LDS, three workgroups per CU
+constexpr int kHalfMaxD = 512;
+constexpr int kHalfThreads = 512;
+constexpr int kHalfBlocksPerCu = 3;
 constexpr uint64_t kSlice5 = 1 << 20;  // local triangles per 5-clique slice
 constexpr int32_t kMaxSlices = 1024;
 
@@ -77,7 +82,7 @@ struct Lds {
 // the 1024-bound rows (128 KiB) and the table fit the 160 KiB of LDS.
 template <int DMAX> struct LgHash {
     static constexpr int kSlots = 2 * DMAX;
-    static constexpr int kBits = DMAX == 1024 ? 11 : (DMAX == 256 ? 9 : 7);
+    static constexpr int kBits = DMAX == 1024 ? 11 : (DMAX == 512 ? 10 : (DMAX == 256 ? 9 : 7));
     static_assert((1 << kBits) == kSlots, "slots must be a power of two");
 };
 
@@ -96,7 +101,7 @@ __device__ void build_rows(const int32_t *__restrict__ off, const int32_t *__res
                            int32_t *verts = nullptr) {
     constexpr int PER = (DMAX + NT - 1) / NT;
     constexpr int NW = NT / kWave;
-    constexpr int U = 2;
+    constexpr int U = DMAX <= 256 ? 2 : 4;
     const int32_t s = dag_off[u];
     if (RANK) {
         // rank of each out-neighbour among the others, by (degree, id); the
@@ -124,8 +129,8 @@ __device__ void build_rows(const int32_t *__restrict__ off, const int32_t *__res
     const int32_t per_wave = ((npairs + NW - 1) / NW + U * kWave - 1) / (U * kWave) * (U * kWave);
     const int32_t qa = min(npairs, (int32_t)(threadIdx.x / kWave) * per_wave);
     const int32_t qz = min(npairs, qa + per_wave);
-    walk_pairs<U>(pre, offj, dag_adj, d, qa, qz, [&](int32_t j, int32_t, int32_t w) {
-        const int32_t slot = lds_hash_find(keys, hb, w);
+    walk_lookup<U>(pre, offj, dag_adj, d, qa, qz, keys, hb,
+            [&](int32_t j, int32_t, int32_t w, int32_t slot) {
         if (slot >= 0) {
             const int32_t a = RANK ? (int32_t)lidx[j] : j;
             const int32_t b = vals[slot];
@@ -167,20 +172,91 @@ __device__ __forceinline__ void edge_at(const uint64_t *rows, const int32_t *pre
     j = wj * 64 + select_bit64(ri[wj], rr);
 }
 
-// 4-cliques: workgroup per root (atomic cursor over the class list).  With
-// LIST every 4-clique (u, v_i, v_j, v_x) is emitted instead of counted.
-template <int DMAX, int NT, bool LIST>
-__global__ void __launch_bounds__(NT) k_lg4(const int32_t *__restrict__ dag_off,
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
+    return uniform64(x);
+}
+
+// Triangles of a local graph in degree order (d vertices, W words per row,
+// every row holding only bits above its own index): the sum over local
+// edges a -> b of |row_a & row_b|.  The work is cut into pieces (t, q): rows
+// 64t..64t+63 (one per lane, in registers) against the columns b of word q
+// (q >= t).  b runs over the union of the 64 rows' bits in word q in a
+// wave-uniform loop, so row_b is a broadcast LDS read, and the AND +
+// population count covers the words from q up.  Pieces go round robin to the
+// workgroup's waves in order of q, i.e. from the costliest (W - q words per
+// column) down.  Returns the calling lane's share.
+template <int W>
+__device__ uint64_t local_tri(const uint64_t *rows, int32_t d, int wib, int nw) {
+    const int lane = lane_id();
+    constexpr int kPieces = W * (W + 1) / 2;
+    uint64_t acc = 0;
+    for (int p = wib; p < kPieces; p += nw) {
+        int q = 0;
+        while ((q + 1) * (q + 2) / 2 <= p) q++;
+        const int t = p - q * (q + 1) / 2;
+        const int32_t a = t * kWave + lane;
+        if (t * kWave >= d) continue;
+        uint32_t part = 0;
+#pragma unroll
+        for (int qq = 0; qq < W; qq++) {
+            if (qq != q) continue;
+            uint64_t X[W];
+#pragma unroll
+            for (int w = qq; w < W; w++) X[w] = a < d ? rows[a * W + w] : 0ull;
+            uint64_t m = wave_or64(X[qq]);
+            while (m) {
+                const int bp = __builtin_ctzll(m);
+                m &= m - 1ull;
+                const uint64_t *yb = rows + (qq * kWave + bp) * W;
+                uint32_t sc = 0;
+#pragma unroll
+                for (int w = qq; w < W; w++) sc += (uint32_t)__popcll(X[w] & yb[w]);
+                part += (uint32_t)((X[qq] >> bp) & 1ull) * sc;
+            }
+        }
+        acc += part;
+    }
+    return acc;
+}
+
+template <int WLO, int WHI>
+__device__ __forceinline__ uint64_t local_tri_dispatch(int32_t W, const uint64_t *rows, int32_t d,
+                                                       int wib, int nw) {
+    if constexpr (WLO > WHI) {
+        return 0;
+    } else {
+        if (W == WLO) return local_tri<WLO>(rows, d, wib, nw);
+        return local_tri_dispatch<WLO + 1, WHI>(W, rows, d, wib, nw);
+    }
+}
+
+// 4-cliques: workgroup per root (atomic cursor over the class list; roots of
+// out-degree <= dlo are left to another launch); the root's 4-cliques are the
+// triangles of its local graph.  RANK puts the local graph in degree order
+// and counts its triangles with local_tri, else they are counted per local
+// edge.  With LIST every 4-clique (u, v_i, v_j, v_x) is emitted instead.
+template <int DMAX, int NT, bool LIST, bool RANK>
+__global__ void __launch_bounds__(NT, DMAX == kHalfMaxD ? 6 : 1) k_lg4(const int32_t *__restrict__ off,
+                                            const int32_t *__restrict__ dag_off,
                                             const int32_t *__restrict__ dag_adj,
                                             const int32_t *__restrict__ roots,
-                                            const int32_t *__restrict__ nroots_p,
+                                            const int32_t *__restrict__ nroots_p, int32_t dlo,
                                             uint32_t *cursor, unsigned long long *result,
                                             unsigned long long *res3, RowEmitter em) {
     __shared__ uint64_t rows[DMAX * (DMAX / 64)];
-    __shared__ int32_t keys[LgHash<DMAX>::kSlots];
+    __shared__ __align__(16) int32_t keys[LgHash<DMAX>::kSlots];
     __shared__ int16_t vals[LgHash<DMAX>::kSlots];
     __shared__ int32_t offj[DMAX], pre[DMAX + 1];
     __shared__ int32_t verts[LIST ? DMAX : 1];
+    __shared__ int16_t lidx[RANK ? DMAX : 1];
     __shared__ Lds<NT> sh;
     const int tid = threadIdx.x;
     const int32_t nroots = *nroots_p;
@@ -193,27 +269,32 @@ __global__ void __launch_bounds__(NT) k_lg4(const int32_t *__restrict__ dag_off,
         if (r >= nroots) break;
         const int32_t u = roots[r];
         const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
-        build_rows<DMAX, NT, false>(nullptr, dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj,
-                                     nullptr, sh.s_sum, LIST ? verts : nullptr);
+        if (d <= dlo || d > DMAX) continue;
+        build_rows<DMAX, NT, RANK>(off, dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj,
+                                   RANK ? lidx : nullptr, sh.s_sum, LIST ? verts : nullptr);
         const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
         if (res3 && tid == 0 && ne) atomicAdd(res3, (unsigned long long)ne);   // triangles at u
-        for (int32_t e = tid; e < ne; e += NT) {
-            int32_t i, j;
-            edge_at(rows, pre, d, W, e, i, j);
-            const uint64_t *ri = rows + i * W, *rj = rows + j * W;
-            if constexpr (LIST) {
-                for (int32_t w = 0; w < W; w++) {
-                    uint64_t m = ri[w] & rj[w];
-                    while (m) {
-                        const int32_t x = w * 64 + __builtin_ctzll(m);
-                        m &= m - 1ull;
-                        const int32_t q[4] = {u, verts[i], verts[j], verts[x]};
-                        emit_vertices<4>(em, q);
+        if constexpr (LIST || !RANK) {
+            for (int32_t e = tid; e < ne; e += NT) {
+                int32_t i, j;
+                edge_at(rows, pre, d, W, e, i, j);
+                const uint64_t *ri = rows + i * W, *rj = rows + j * W;
+                if constexpr (LIST) {
+                    for (int32_t w = 0; w < W; w++) {
+                        uint64_t m = ri[w] & rj[w];
+                        while (m) {
+                            const int32_t x = w * 64 + __builtin_ctzll(m);
+                            m &= m - 1ull;
+                            const int32_t q[4] = {u, verts[i], verts[j], verts[x]};
+                            emit_vertices<4>(em, q);
+                        }
                     }
+                } else {
+                    for (int32_t w = 0; w < W; w++) acc += __popcll(ri[w] & rj[w]);
                 }
-            } else {
-                for (int32_t w = 0; w < W; w++) acc += __popcll(ri[w] & rj[w]);
             }
+        } else if (ne) {
+            acc += local_tri_dispatch<1, DMAX / kWave>(W, rows, d, tid / kWave, NT / kWave);
         }
         __syncthreads();
     }
@@ -228,18 +309,18 @@ __global__ void __launch_bounds__(NT) k_lg4(const int32_t *__restrict__ dag_off,
 // 5-cliques, step 1: rows of every root (local indices in degree order) to
 // HBM, and local triangle counts for slicing.
 template <int DMAX, int NT>
-__global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ off,
+__global__ void __launch_bounds__(NT, DMAX == kHalfMaxD ? 6 : 1) k_lg_build(const int32_t *__restrict__ off,
                                                  const int32_t *__restrict__ dag_off,
                                                  const int32_t *__restrict__ dag_adj,
                                                  const int32_t *__restrict__ roots,
-                                                 const int32_t *__restrict__ nroots_p,
+                                                 const int32_t *__restrict__ nroots_p, int32_t dlo,
                                                  uint32_t *cursor, const int64_t *__restrict__ rowoff,
                                                  uint64_t *grows, int32_t *slices,
                                                  unsigned long long *units,
                                                  unsigned long long *res3,
                                                  unsigned long long *res4) {
     __shared__ uint64_t rows[DMAX * (DMAX / 64)];
-    __shared__ int32_t keys[LgHash<DMAX>::kSlots];
+    __shared__ __align__(16) int32_t keys[LgHash<DMAX>::kSlots];
     __shared__ int16_t vals[LgHash<DMAX>::kSlots];
     __shared__ int16_t lidx[DMAX];
     __shared__ int32_t offj[DMAX], pre[DMAX + 1];
@@ -256,6 +337,7 @@ __global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ off
         if (r >= nroots) break;
         const int32_t u = roots[r];
         const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
+        if (d <= dlo || d > DMAX) continue;
         build_rows<DMAX, NT, true>(off, dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj,
                                    lidx, sh.s_sum, verts);
         uint64_t *dst = grows + rowoff[r];
@@ -265,15 +347,9 @@ __global__ void __launch_bounds__(NT) k_lg_build(const int32_t *__restrict__ off
         for (int32_t i = tid; i < d; i += NT) dverts[i] = verts[i];
         const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
         if (res3 && tid == 0 && ne) atomicAdd(res3, (unsigned long long)ne);   // triangles at u
-        // local triangles (the 4-cliques at u) = candidates summed over local
-        // edges: the 5-clique work
-        uint64_t tri = 0;
-        for (int32_t e = tid; e < ne; e += NT) {
-            int32_t i, j;
-            edge_at(rows, pre, d, W, e, i, j);
-            const uint64_t *ri = rows + i * W, *rj = rows + j * W;
-            for (int32_t w = 0; w < W; w++) tri += __popcll(ri[w] & rj[w]);
-        }
+        // local triangles (the 4-cliques at u): the 5-clique work
+        uint64_t tri = ne ? local_tri_dispatch<1, DMAX / kWave>(W, rows, d, tid / kWave, NT / kWave)
+                          : 0;
         tri = wave_sum(tri);
         if (lane_id() == 0 && tri) atomicAdd((unsigned long long *)&sh.s_tri, (unsigned long long)tri);
         __syncthreads();
@@ -316,12 +392,6 @@ __global__ void k_lg_words(const int32_t *dag_off, const int32_t *roots, const i
 // keeps all 64 lanes busy.
 // LDS is dynamic: rows (dmax x ceil(dmax/64) words for the class's largest
 // out-degree), then per wave a member list of DMAX int16.
-
-__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
 
 template <int W>
 __device__ uint64_t lg5_vertex(const uint64_t *rows, const uint64_t *ri, int32_t c, int16_t *mem) {
@@ -603,7 +673,7 @@ __global__ void __launch_bounds__(NT) k_lg5_mid(const int32_t *__restrict__ off,
     constexpr int WLO = 2, WHI = WMAX;   // out-degrees 65..DMAX
     constexpr int kMaxExtra = 3;         // k <= 8
     __shared__ uint64_t rows[DMAX * WMAX];
-    __shared__ int32_t keys[LgHash<DMAX>::kSlots];
+    __shared__ __align__(16) int32_t keys[LgHash<DMAX>::kSlots];
     __shared__ int16_t vals[LgHash<DMAX>::kSlots];
     __shared__ int16_t lidx[DMAX];
     __shared__ int32_t offj[DMAX], pre[DMAX + 1];
@@ -714,11 +784,21 @@ gpm_status lg5_class(const gpm_graph *g, int32_t k, LgWs &L, const int32_t *list
     GPM_LAUNCH_CHECK("k_lg_words");
     GPM_HIP(exclusive_scan_i64(L.words, rowoff, (uint64_t)n, L.scan_tmp, st));
     GPM_HIP(fill_u32(L.slices, 0, (uint64_t)n + 1, st));
+    if constexpr (DMAX > kHalfMaxD) {
+        // roots of out-degree up to kHalfMaxD at the smaller bound, the rest here
+        Span sp("k_lg_build<512>", st);
+        hipLaunchKernelGGL((k_lg_build<kHalfMaxD, kHalfThreads>),
+                           dim3((unsigned)cu_count() * kHalfBlocksPerCu), dim3(kHalfThreads), 0,
+                           st, g->off, g->dag_off, g->dag_adj, list, cnt, kMidMaxD, cursors + 2,
+                           rowoff, rows, L.slices, units, res3, res4);
+    }
+    GPM_LAUNCH_CHECK("k_lg_build<512>");
     {
         Span sp(nb, st);
         hipLaunchKernelGGL((k_lg_build<DMAX, NT>), dim3((unsigned)cu_count() * (NT <= 256 ? 8 : 1)),
-                           dim3(NT), 0, st, g->off, g->dag_off, g->dag_adj, list, cnt, cursors + 0,
-                           rowoff, rows, L.slices, units, res3, res4);
+                           dim3(NT), 0, st, g->off, g->dag_off, g->dag_adj, list, cnt,
+                           DMAX > kHalfMaxD ? kHalfMaxD : 0, cursors + 0, rowoff, rows, L.slices,
+                           units, res3, res4);
     }
     GPM_LAUNCH_CHECK("k_lg_build");
     GPM_HIP(exclusive_scan_i32(L.slices, toff, (uint64_t)n, L.scan_tmp, st));
@@ -771,29 +851,45 @@ gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, cons
     GPM_HIP(fill_u32(L.ctl, 0, 16, st));
     GPM_HIP(fill_u32(L.units, 0, 8, st));
     if (k == 4) {
+        const RowEmitter none{};
         {
             Span sp("k_lg4<1024>", st);
             if (em)
-                hipLaunchKernelGGL((k_lg4<kBigMaxD, kBigThreads, true>), dim3((unsigned)cu_count()),
-                                   dim3(kBigThreads), 0, st, g->dag_off, g->dag_adj, list_b, cnt_b,
-                                   L.ctl + 0, res, res3, *em);
+                hipLaunchKernelGGL((k_lg4<kBigMaxD, kBigThreads, true, true>),
+                                   dim3((unsigned)cu_count()), dim3(kBigThreads), 0, st, g->off,
+                                   g->dag_off, g->dag_adj, list_b, cnt_b, kHalfMaxD, L.ctl + 0, res,
+                                   res3, *em);
             else
-                hipLaunchKernelGGL((k_lg4<kBigMaxD, kBigThreads, false>),
-                                   dim3((unsigned)cu_count()), dim3(kBigThreads), 0, st, g->dag_off,
-                                   g->dag_adj, list_b, cnt_b, L.ctl + 0, res, res3, RowEmitter{});
+                hipLaunchKernelGGL((k_lg4<kBigMaxD, kBigThreads, false, true>),
+                                   dim3((unsigned)cu_count()), dim3(kBigThreads), 0, st, g->off,
+                                   g->dag_off, g->dag_adj, list_b, cnt_b, kHalfMaxD, L.ctl + 0, res,
+                                   res3, none);
         }
         GPM_LAUNCH_CHECK("k_lg4<1024>");
         {
-            Span sp("k_lg4<256>", st);
+            Span sp("k_lg4<512>", st);
+            const dim3 grid((unsigned)cu_count() * kHalfBlocksPerCu);
             if (em)
-                hipLaunchKernelGGL((k_lg4<kMidMaxD, kMidThreads, true>),
-                                   dim3((unsigned)cu_count() * 8), dim3(kMidThreads), 0, st,
-                                   g->dag_off, g->dag_adj, list_m, cnt_m, L.ctl + 1, res, res3, *em);
+                hipLaunchKernelGGL((k_lg4<kHalfMaxD, kHalfThreads, true, true>), grid,
+                                   dim3(kHalfThreads), 0, st, g->off, g->dag_off, g->dag_adj,
+                                   list_b, cnt_b, kMidMaxD, L.ctl + 2, res, res3, *em);
             else
-                hipLaunchKernelGGL((k_lg4<kMidMaxD, kMidThreads, false>),
-                                   dim3((unsigned)cu_count() * 8), dim3(kMidThreads), 0, st,
-                                   g->dag_off, g->dag_adj, list_m, cnt_m, L.ctl + 1, res, res3,
-                                   RowEmitter{});
+                hipLaunchKernelGGL((k_lg4<kHalfMaxD, kHalfThreads, false, true>), grid,
+                                   dim3(kHalfThreads), 0, st, g->off, g->dag_off, g->dag_adj,
+                                   list_b, cnt_b, kMidMaxD, L.ctl + 2, res, res3, none);
+        }
+        GPM_LAUNCH_CHECK("k_lg4<512>");
+        {
+            Span sp("k_lg4<256>", st);
+            const dim3 grid((unsigned)cu_count() * 8);
+            if (em)
+                hipLaunchKernelGGL((k_lg4<kMidMaxD, kMidThreads, true, false>), grid,
+                                   dim3(kMidThreads), 0, st, g->off, g->dag_off, g->dag_adj,
+                                   list_m, cnt_m, 0, L.ctl + 1, res, res3, *em);
+            else
+                hipLaunchKernelGGL((k_lg4<kMidMaxD, kMidThreads, false, false>), grid,
+                                   dim3(kMidThreads), 0, st, g->off, g->dag_off, g->dag_adj,
+                                   list_m, cnt_m, 0, L.ctl + 1, res, res3, none);
         }
         GPM_LAUNCH_CHECK("k_lg4<256>");
         return GPM_OK;
@@ -809,11 +905,11 @@ gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, cons
         if (em)
             hipLaunchKernelGGL((k_lg5_mid<kMidMaxD, kMidThreads, true>), grid, dim3(kMidThreads), 0,
                                st, g->off, g->dag_off, g->dag_adj, list_m, cnt_m, k - 5,
-                               L.ctl + 4, res, res3, res4, *em);
+                               L.ctl + 6, res, res3, res4, *em);
         else
             hipLaunchKernelGGL((k_lg5_mid<kMidMaxD, kMidThreads, false>), grid, dim3(kMidThreads),
                                0, st, g->off, g->dag_off, g->dag_adj, list_m, cnt_m, k - 5,
-                               L.ctl + 4, res, res3, res4, RowEmitter{});
+                               L.ctl + 6, res, res3, res4, RowEmitter{});
     }
     GPM_LAUNCH_CHECK("k_lg5_mid");
     return GPM_OK;
