@@ -330,26 +330,28 @@ __device__ __forceinline__ void walk_lookup(const int32_t *pre, const int32_t *o
             b[t] = lds_hash_slot(w[t], bits) >> 2;
             slot[t] = w[t] >= 0 ? -2 : -1;   // -2: still looking
         }
+        // branch-free rounds: every lane reads its current bucket (settled
+        // lanes re-read theirs) and only pending lanes take the result
         for (;;) {
             int4 kv[U];
 #pragma unroll
-            for (int t = 0; t < U; t++)
-                if (slot[t] == -2) kv[t] = kb[b[t]];
+            for (int t = 0; t < U; t++) kv[t] = kb[b[t]];
             bool more = false;
 #pragma unroll
             for (int t = 0; t < U; t++) {
-                if (slot[t] != -2) continue;
                 const int4 k = kv[t];
-                const int32_t s0 = (int32_t)b[t] * 4;
-                if (k.x == w[t]) slot[t] = s0;
-                else if (k.y == w[t]) slot[t] = s0 + 1;
-                else if (k.z == w[t]) slot[t] = s0 + 2;
-                else if (k.w == w[t]) slot[t] = s0 + 3;
-                else if ((k.x | k.y | k.z | k.w) < 0) slot[t] = -1;
-                else {
-                    b[t] = (b[t] + 1u) & bmask;
-                    more = true;
-                }
+                const int32_t x = w[t];
+                const uint32_t hit = (uint32_t)(k.x == x) | ((uint32_t)(k.y == x) << 1) |
+                                     ((uint32_t)(k.z == x) << 2) | ((uint32_t)(k.w == x) << 3);
+                const bool empty = (k.x | k.y | k.z | k.w) < 0;
+                const int32_t at = (int32_t)(b[t] * 4u + (uint32_t)__builtin_ctz(hit | 16u));
+                const int32_t hm = -(int32_t)(hit != 0u);   // all ones on a match
+                const int32_t r = (at & hm) | ((empty ? -1 : -2) & ~hm);
+                const bool pend = slot[t] == -2;
+                const bool next = pend && r == -2;
+                slot[t] = pend ? r : slot[t];
+                b[t] = next ? ((b[t] + 1u) & bmask) : b[t];
+                more = more || next;
             }
             if (!__any(more)) break;
         }
