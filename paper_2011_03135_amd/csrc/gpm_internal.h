@@ -291,6 +291,9 @@ __device__ __forceinline__ void walk_lookup(const int32_t *pre, const int32_t *o
                                             const int32_t *__restrict__ dag_adj, int32_t d,
                                             int32_t qa, int32_t qz, const int32_t *keys,
                                             int32_t bits, F &&f) {
+    // qa, qz, the segment j and the step bounds live in scalar registers
+    qa = __builtin_amdgcn_readfirstlane(qa);
+    qz = __builtin_amdgcn_readfirstlane(qz);
     if (qa >= qz) return;
     const int lane = lane_id();
     const uint32_t bmask = (1u << (bits - 2)) - 1u;   // buckets of 4 slots
@@ -298,37 +301,42 @@ __device__ __forceinline__ void walk_lookup(const int32_t *pre, const int32_t *o
     int32_t lo = 0, hi = d;   // last j with pre[j] <= qa
     while (hi - lo > 1) {
         const int32_t mid = (lo + hi) >> 1;
-        if (pre[mid] <= qa) lo = mid; else hi = mid;
+        if (__builtin_amdgcn_readfirstlane(pre[mid]) <= qa) lo = mid; else hi = mid;
     }
-    int32_t j = lo;
+    int32_t j = __builtin_amdgcn_readfirstlane(lo);
     for (int32_t qb = qa; qb < qz; qb += U * 64) {
         int32_t jj[U], e[U], w[U], slot[U];
         uint32_t b[U];
-        const int32_t seg_end = pre[j + 1], seg_base = offj[j];
+        const int32_t seg_end = __builtin_amdgcn_readfirstlane(pre[j + 1]);
         if (qb + U * 64 <= seg_end) {
+            // every pair of the step is in segment j (its arcs exist even
+            // for lanes past qz)
+            const int32_t base = __builtin_amdgcn_readfirstlane(offj[j]) + qb + lane;
 #pragma unroll
             for (int t = 0; t < U; t++) {
                 jj[t] = j;
-                e[t] = seg_base + qb + t * 64 + lane;
+                e[t] = base + t * 64;
             }
         } else {
+            // lanes past qz take the step's last pair, so every arc exists
             int32_t jc = j;
 #pragma unroll
             for (int t = 0; t < U; t++) {
-                const int32_t q = qb + t * 64 + lane;
-                if (q < qz)
-                    while (pre[jc + 1] <= q) jc++;
+                const int32_t q = min(qb + t * 64 + lane, qz - 1);
+                while (pre[jc + 1] <= q) jc++;
                 jj[t] = jc;
                 e[t] = offj[jc] + q;
             }
         }
+        // arc indices are below 2^30, so byte offsets fit 32 bits
+        const char *adj_b = reinterpret_cast<const char *>(dag_adj);
 #pragma unroll
         for (int t = 0; t < U; t++)
-            w[t] = qb + t * 64 + lane < qz ? dag_adj[e[t]] : -1;
+            w[t] = *reinterpret_cast<const int32_t *>(adj_b + ((uint32_t)e[t] << 2));
 #pragma unroll
         for (int t = 0; t < U; t++) {
             b[t] = lds_hash_slot(w[t], bits) >> 2;
-            slot[t] = w[t] >= 0 ? -2 : -1;   // -2: still looking
+            slot[t] = qb + t * 64 + lane < qz ? -2 : -1;   // -2: still looking
         }
         // branch-free rounds: every lane reads its current bucket (settled
         // lanes re-read theirs) and only pending lanes take the result
@@ -358,7 +366,7 @@ __device__ __forceinline__ void walk_lookup(const int32_t *pre, const int32_t *o
 #pragma unroll
         for (int t = 0; t < U; t++)
             if (qb + t * 64 + lane < qz) f(jj[t], e[t], w[t], slot[t]);
-        j = __shfl(jj[U - 1], 63, 64);
+        j = __builtin_amdgcn_readlane(jj[U - 1], 63);
     }
 }
 
