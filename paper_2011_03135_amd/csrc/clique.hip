@@ -180,7 +180,8 @@ __global__ void __launch_bounds__(NT) k_tc_block(const int32_t *__restrict__ dag
                                                  unsigned long long *result, uint32_t *te,
                                                  RowEmitter em) {
     constexpr int NW = NT / kWave;
-    constexpr int H = 4 * DMAX;
+    constexpr int F = DMAX <= 256 ? 8 : 4;   // slots per out-neighbour
+    constexpr int H = F * DMAX;
     constexpr int PER = (DMAX + NT - 1) / NT;
     static_assert(DMAX <= 32767, "local indices are kept as int16");
     __shared__ __align__(16) int32_t keys[H];
@@ -211,7 +212,7 @@ __global__ void __launch_bounds__(NT) k_tc_block(const int32_t *__restrict__ dag
             const int64_t w0 = wpre[a], w1 = wpre[a + 1];
             const int32_t u = act[a];
             const int32_t s = dag_off[u], d = dag_off[u + 1] - s;
-            const int32_t hb = lds_hash_bits(d);
+            const int32_t hb = lds_hash_bits(d, F);
             for (int i = tid; i < (1 << hb); i += NT) keys[i] = -1;
             stage_root<NT, PER>(dag_off, dag_adj, s, d, keys, MODE == TC_ARCS ? vals : nullptr,
                                 hb, pre, offj, s_sum, nullptr,
@@ -331,8 +332,8 @@ __global__ void __launch_bounds__(kWave) k_clique_wave(const int32_t *__restrict
                                                        unsigned long long *res3,
                                                        unsigned long long *res4, RowEmitter em) {
     __shared__ uint64_t rows[kWave];
-    __shared__ __align__(16) int32_t keys[4 * kWave];
-    __shared__ int16_t vals[4 * kWave];
+    __shared__ __align__(16) int32_t keys[8 * kWave];
+    __shared__ int16_t vals[8 * kWave];
     __shared__ int32_t pre[kWave + 1], offj[kWave];
     __shared__ int32_t verts[LIST ? kWave : 1];
     const int lane = lane_id();
@@ -341,7 +342,7 @@ __global__ void __launch_bounds__(kWave) k_clique_wave(const int32_t *__restrict
     for (int64_t r = blockIdx.x; r < nroots; r += gridDim.x) {
         const int32_t u = roots[r];
         const int32_t s = dag_off[u], d = dag_off[u + 1] - s;
-        const int32_t hb = lds_hash_bits(d);
+        const int32_t hb = lds_hash_bits(d, 8);
         for (int i = lane; i < (1 << hb); i += kWave) keys[i] = -1;
         rows[lane] = 0;
         stage_root<kWave, 1>(dag_off, dag_adj, s, d, keys, vals, hb, pre, offj, nullptr, nullptr,

@@ -77,12 +77,13 @@ struct Lds {
     uint64_t s_tri;
 };
 
-// Hash table of a local-graph block: 2 slots per out-neighbour at the class
-// bound (load factor <= 1/4 up to half the bound, <= 1/2 at the bound), so
-// the 1024-bound rows (128 KiB) and the table fit the 160 KiB of LDS.
+// Hash table of a local-graph block: 4 slots per out-neighbour at the class
+// bound (load factor <= 1/4); at the 1024 bound 2 (<= 1/4 up to half the
+// bound, <= 1/2 at the bound), so its rows (128 KiB) and the table fit the
+// 160 KiB of LDS.
 template <int DMAX> struct LgHash {
-    static constexpr int kSlots = 2 * DMAX;
-    static constexpr int kBits = DMAX == 1024 ? 11 : (DMAX == 512 ? 10 : (DMAX == 256 ? 9 : 7));
+    static constexpr int kSlots = DMAX >= 1024 ? 2 * DMAX : 4 * DMAX;
+    static constexpr int kBits = DMAX >= 1024 ? 11 : (DMAX == 512 ? 11 : (DMAX == 256 ? 10 : 8));
     static_assert((1 << kBits) == kSlots, "slots must be a power of two");
 };
 
