@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(NT) k_tc_block(const int32_t *__restrict__ dag
                                                  unsigned long long *result, uint32_t *te,
                                                  RowEmitter em) {
     constexpr int NW = NT / kWave;
-    constexpr int F = DMAX <= 256 ? 8 : 4;   // slots per out-neighbour
+    constexpr int F = DMAX <= 256 ? 16 : 4;   // slots per out-neighbour
     constexpr int H = F * DMAX;
     constexpr int PER = (DMAX + NT - 1) / NT;
     static_assert(DMAX <= 32767, "local indices are kept as int16");
