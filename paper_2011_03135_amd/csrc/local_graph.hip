@@ -185,6 +185,36 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
     return uniform64(x);
 }
 
+// part + the sum over the columns b of word q listed in m (wave-uniform) of
+// [bit b of X[q]] * sum over w >= q of popc(X[w] & row_b[w]).  The halves of
+// the word are walked one after the other, so the lane's bit test is one
+// bit-field extract of a 32-bit register and its product with the count one
+// 24-bit multiply-add; row_b is a broadcast LDS read.
+template <int W>
+__device__ __forceinline__ uint32_t pair_sweep(const uint64_t *rows, const uint64_t (&X)[W], int q,
+                                               uint64_t m, uint32_t part) {
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const uint32_t x = (uint32_t)(X[q] >> (32 * h));
+        uint32_t mh = (uint32_t)(m >> (32 * h));
+        while (mh) {
+            const int bp = __builtin_ctz(mh);
+            mh &= mh - 1u;
+            const uint64_t *yb = rows + (q * kWave + h * 32 + bp) * W;
+            uint32_t sc = 0;
+#pragma unroll
+            for (int w = q; w < W; w++) sc += (uint32_t)__popcll(X[w] & yb[w]);
+            // written as instructions: the compiler would otherwise turn the
+            // 0/1 product into a compare and a select
+            uint32_t bit, np;
+            asm("v_bfe_u32 %0, %1, %2, 1" : "=v"(bit) : "v"(x), "s"(bp));
+            asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(np) : "v"(bit), "v"(sc), "v"(part));
+            part = np;
+        }
+    }
+    return part;
+}
+
 // Triangles of a local graph in degree order (d vertices, W words per row,
 // every row holding only bits above its own index): the sum over local
 // edges a -> b of |row_a & row_b|.  The work is cut into pieces (t, q): rows
@@ -212,16 +242,7 @@ __device__ uint64_t local_tri(const uint64_t *rows, int32_t d, int wib, int nw) 
             uint64_t X[W];
 #pragma unroll
             for (int w = qq; w < W; w++) X[w] = a < d ? rows[a * W + w] : 0ull;
-            uint64_t m = wave_or64(X[qq]);
-            while (m) {
-                const int bp = __builtin_ctzll(m);
-                m &= m - 1ull;
-                const uint64_t *yb = rows + (qq * kWave + bp) * W;
-                uint32_t sc = 0;
-#pragma unroll
-                for (int w = qq; w < W; w++) sc += (uint32_t)__popcll(X[w] & yb[w]);
-                part += (uint32_t)((X[qq] >> bp) & 1ull) * sc;
-            }
+            part = pair_sweep<W>(rows, X, qq, wave_or64(X[qq]), part);
         }
         acc += part;
     }
@@ -427,15 +448,7 @@ __device__ uint64_t lg5_vertex(const uint64_t *rows, const uint64_t *ri, int32_t
             if (q < q0) continue;
             uint64_t m = R[q];
             if (q == q0) m &= ~((2ull << (p0 & 63)) - 1ull);   // members above p0
-            while (m) {
-                const int bp = __builtin_ctzll(m);
-                m &= m - 1ull;
-                const uint64_t *yb = rows + (q * 64 + bp) * W;
-                uint32_t sc = 0;
-#pragma unroll
-                for (int w = q; w < W; w++) sc += (uint32_t)__popcll(X[w] & yb[w]);
-                part += (uint32_t)((X[q] >> bp) & 1ull) * sc;
-            }
+            part = pair_sweep<W>(rows, X, q, m, part);
         }
         acc += part;
     }
