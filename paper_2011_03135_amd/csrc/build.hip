@@ -190,11 +190,13 @@ __global__ void __launch_bounds__(kBucketNT) k_bucket_rows(const int32_t *__rest
     if (blockIdx.x == 0 && threadIdx.x == 0) raw_off[n] = bucket_off[nb];
 }
 
-// Sorts row entries held one per lane (lanes >= L hold INT_MAX) ascending.
-__device__ __forceinline__ int32_t wave_bitonic_sort(int32_t x) {
-    const int lane = lane_id();
+// Sorts row entries held one per lane of each group of G lanes (lanes past
+// the row hold INT_MAX) ascending.
+template <int G>
+__device__ __forceinline__ int32_t group_bitonic_sort(int32_t x) {
+    const int lane = lane_id() & (G - 1);
 #pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
+    for (int k = 2; k <= G; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
             int32_t y = __shfl_xor(x, j, 64);
@@ -207,63 +209,102 @@ __device__ __forceinline__ int32_t wave_bitonic_sort(int32_t x) {
     return x;
 }
 
-// One wave per row: sort + unique in place; long rows are deferred.
+constexpr int kSmallRow = 16;   // rows sorted by a 16-lane group, 4 per wave
+
+// Short rows: each 16-lane group sorts + uniques one row of at most 16
+// entries in place (4 consecutive rows per wave); rows beyond kSortLds go to
+// the bitmap sorter's list, the rest are left to k_sort_rows.  Most rows of
+// power-law graphs are short.
+__global__ void __launch_bounds__(kBlock) k_sort_small_rows(const int32_t *__restrict__ raw_off,
+                                                            int32_t *raw_adj, int32_t n,
+                                                            int32_t *ucnt, int32_t *big_list,
+                                                            uint32_t *flags) {
+    const int lane = lane_id(), gl = lane & (kSmallRow - 1), grp = lane / kSmallRow;
+    const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    constexpr int kRows = kWave / kSmallRow;
+    for (int64_t r0 = wave0 * kRows; r0 < n; r0 += nwaves * kRows) {
+        const int64_t row = r0 + grp;
+        const bool live = row < n;
+        const int32_t s = live ? raw_off[row] : 0;
+        const int32_t L = live ? raw_off[row + 1] - s : 0;
+        const bool small = L <= kSmallRow;
+        int32_t *r = raw_adj + s;
+        int32_t x = small && gl < L ? r[gl] : INT_MAX;
+        x = group_bitonic_sort<kSmallRow>(x);
+        const int32_t prev = __shfl(x, lane - 1, 64);
+        const bool keep = small && gl < L && (gl == 0 || x != prev);
+        const uint64_t mask = __ballot(keep);
+        const uint32_t gmask = (uint32_t)(mask >> (grp * kSmallRow)) & ((1u << kSmallRow) - 1u);
+        if (keep) r[__popc(gmask & ((1u << gl) - 1u))] = x;
+        if (live && gl == 0) {
+            if (small) ucnt[row] = __popc(gmask);
+            else if (L > kSortLds) big_list[atomicAdd(&flags[F_BIG_COUNT], 1u)] = (int32_t)row;
+        }
+    }
+}
+
+// Rows of kSmallRow+1 .. kSortLds entries, a wave each: sort + unique in
+// place.  A wave scans 64 rows at a time and visits the ones in range (no
+// list, so no contended counter).
 __global__ void __launch_bounds__(kBlock) k_sort_rows(const int32_t *__restrict__ raw_off,
-                                                      int32_t *raw_adj, int32_t n, int32_t *ucnt,
-                                                      int32_t *big_list, uint32_t *flags) {
+                                                      int32_t *raw_adj, int32_t n,
+                                                      int32_t *ucnt) {
     __shared__ int32_t lds[kWavesPerBlock][kSortLds];
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
     int32_t *buf = lds[wib];
     const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + wib;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t row = wave0; row < n; row += nwaves) {
-        const int32_t s = raw_off[row];
-        const int32_t L = raw_off[row + 1] - s;
-        int32_t *r = raw_adj + s;
-        if (L <= 64) {
-            int32_t x = lane < L ? r[lane] : INT_MAX;
-            x = wave_bitonic_sort(x);
-            int32_t prev = __shfl_up(x, 1, 64);
-            bool keep = lane < L && (lane == 0 || x != prev);
-            uint64_t mask = __ballot(keep);
-            if (keep) r[lanes_below(mask)] = x;
-            if (lane == 0) ucnt[row] = __popcll(mask);
-        } else if (L <= kSortLds) {
-            int P = 128;
-            while (P < L) P <<= 1;
-            for (int i = lane; i < P; i += kWave) buf[i] = i < L ? r[i] : INT_MAX;
-            wave_sync();
-            for (int k = 2; k <= P; k <<= 1) {
-                for (int j = k >> 1; j > 0; j >>= 1) {
-                    for (int t = lane; t < P / 2; t += kWave) {
-                        int i = (t / j) * 2 * j + (t % j);
-                        int p = i + j;
-                        int32_t a = buf[i], b = buf[p];
-                        bool ascending = (i & k) == 0;
-                        if ((a > b) == ascending) {
-                            buf[i] = b;
-                            buf[p] = a;
-                        }
-                    }
-                    wave_sync();
-                }
-            }
-            int32_t count = 0;
-            for (int base = 0; base < L; base += kWave) {
-                int i = base + lane;
-                int32_t x = i < L ? buf[i] : INT_MAX;
-                bool keep = i < L && (i == 0 || x != buf[i - 1]);
+    for (int64_t c0 = wave0 * kWave; c0 < n; c0 += nwaves * kWave) {
+        const int64_t mine = c0 + lane;
+        const int32_t Lm = mine < n ? raw_off[mine + 1] - raw_off[mine] : 0;
+        uint64_t todo = __ballot(Lm > kSmallRow && Lm <= kSortLds);
+        while (todo) {
+            const int32_t row = (int32_t)(c0 + __builtin_ctzll(todo));
+            todo &= todo - 1ull;
+            const int32_t s = raw_off[row];
+            const int32_t L = raw_off[row + 1] - s;
+            int32_t *r = raw_adj + s;
+            if (L <= 64) {
+                int32_t x = lane < L ? r[lane] : INT_MAX;
+                x = group_bitonic_sort<kWave>(x);
+                int32_t prev = __shfl_up(x, 1, 64);
+                bool keep = lane < L && (lane == 0 || x != prev);
                 uint64_t mask = __ballot(keep);
-                if (keep) r[count + lanes_below(mask)] = x;
-                count += __popcll(mask);
-            }
-            if (lane == 0) ucnt[row] = count;
-            wave_sync();
-        } else {
-            if (lane == 0) {
-                uint32_t slot = atomicAdd(&flags[F_BIG_COUNT], 1u);
-                big_list[slot] = (int32_t)row;
+                if (keep) r[lanes_below(mask)] = x;
+                if (lane == 0) ucnt[row] = __popcll(mask);
+            } else if (L <= kSortLds) {
+                int P = 128;
+                while (P < L) P <<= 1;
+                for (int i = lane; i < P; i += kWave) buf[i] = i < L ? r[i] : INT_MAX;
+                wave_sync();
+                for (int k = 2; k <= P; k <<= 1) {
+                    for (int j = k >> 1; j > 0; j >>= 1) {
+                        for (int t = lane; t < P / 2; t += kWave) {
+                            int i = (t / j) * 2 * j + (t % j);
+                            int p = i + j;
+                            int32_t a = buf[i], b = buf[p];
+                            bool ascending = (i & k) == 0;
+                            if ((a > b) == ascending) {
+                                buf[i] = b;
+                                buf[p] = a;
+                            }
+                        }
+                        wave_sync();
+                    }
+                }
+                int32_t count = 0;
+                for (int base = 0; base < L; base += kWave) {
+                    int i = base + lane;
+                    int32_t x = i < L ? buf[i] : INT_MAX;
+                    bool keep = i < L && (i == 0 || x != buf[i - 1]);
+                    uint64_t mask = __ballot(keep);
+                    if (keep) r[count + lanes_below(mask)] = x;
+                    count += __popcll(mask);
+                }
+                if (lane == 0) ucnt[row] = count;
+                wave_sync();
             }
         }
     }
@@ -320,18 +361,29 @@ __global__ void __launch_bounds__(kBlock) k_sort_big_rows(const int32_t *__restr
     }
 }
 
+// Copies the unique rows into the final CSR and counts each vertex's arcs
+// in the degree order (degrees are the unique counts).
 __global__ void __launch_bounds__(kBlock) k_compact_rows(const int32_t *__restrict__ raw_off,
                                                          const int32_t *__restrict__ raw_adj,
                                                          const int32_t *__restrict__ off,
+                                                         const int32_t *__restrict__ deg,
                                                          int32_t *adj, int32_t n,
-                                                         uint32_t *flags) {
+                                                         int32_t *outcnt, uint32_t *flags) {
     const int lane = lane_id();
     const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     int32_t maxd = 0;
     for (int64_t row = wave0; row < n; row += nwaves) {
+        const int32_t u = (int32_t)row;
         const int32_t src = raw_off[row], dst = off[row], L = off[row + 1] - dst;
-        for (int32_t i = lane; i < L; i += kWave) adj[dst + i] = raw_adj[src + i];
+        int32_t c = 0;
+        for (int32_t i = lane; i < L; i += kWave) {
+            const int32_t v = raw_adj[src + i];
+            adj[dst + i] = v;
+            c += rank_less(L, u, deg[v], v) ? 1 : 0;
+        }
+        c = wave_sum(c);
+        if (lane == 0) outcnt[u] = c;
         maxd = L > maxd ? L : maxd;
     }
     if (lane == 0 && maxd > 0) atomicMax(&flags[F_MAX_DEG], (uint32_t)maxd);
@@ -708,19 +760,19 @@ static gpm_status enqueue_build(int32_t n, const int32_t *d_u, const int32_t *d_
             GPM_LAUNCH_CHECK("k_scatter_raw");
         }
     }
-    hipLaunchKernelGGL(k_sort_rows, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.raw_off,
-                       L.raw_adj, n, L.ucnt, L.big_list, L.flags);
+    hipLaunchKernelGGL(k_sort_small_rows, dim3(wave_grid(((int64_t)n + 3) / 4)), dim3(kBlock), 0,
+                       st, L.raw_off, L.raw_adj, n, L.ucnt, L.big_list, L.flags);
+    GPM_LAUNCH_CHECK("k_sort_small_rows");
+    hipLaunchKernelGGL(k_sort_rows, dim3(wave_grid(((int64_t)n + kWave - 1) / kWave)),
+                       dim3(kBlock), 0, st, L.raw_off, L.raw_adj, n, L.ucnt);
     GPM_LAUNCH_CHECK("k_sort_rows");
     hipLaunchKernelGGL(k_sort_big_rows, dim3(L.nbig_blocks), dim3(kBlock), 0, st, L.raw_off,
                        L.raw_adj, L.ucnt, L.big_list, L.flags, L.bitmaps, L.words);
     GPM_LAUNCH_CHECK("k_sort_big_rows");
     GPM_HIP(exclusive_scan_i32(L.ucnt, L.off, (uint64_t)n, L.scan_tmp, st));
     hipLaunchKernelGGL(k_compact_rows, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.raw_off,
-                       L.raw_adj, L.off, L.adj, n, L.flags);
+                       L.raw_adj, L.off, L.ucnt, L.adj, n, L.outcnt, L.flags);
     GPM_LAUNCH_CHECK("k_compact_rows");
-    hipLaunchKernelGGL(k_orient_count, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.off, L.adj, n,
-                       L.outcnt);
-    GPM_LAUNCH_CHECK("k_orient_count");
     GPM_HIP(exclusive_scan_i32(L.outcnt, L.dag_off, (uint64_t)n, L.scan_tmp, st));
     hipLaunchKernelGGL(k_orient_fill, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.off, L.adj,
                        L.dag_off, n, E, L.dag_adj, L.dag_src, L.flags);
