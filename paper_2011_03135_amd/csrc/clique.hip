@@ -224,21 +224,26 @@ __global__ void __launch_bounds__(NT) k_tc_block(const int32_t *__restrict__ dag
                 ((q1 - q0 + NW - 1) / NW + U * kWave - 1) / (U * kWave) * (U * kWave);
             const int32_t qa = min(q1, q0 + wid * per_wave);
             const int32_t qz = min(q1, qa + per_wave);
-            walk_lookup<U>(pre, offj, dag_adj, d, qa, qz, keys, hb,
-                    [&](int32_t jj, int32_t e_vw, int32_t w, int32_t slot) {
-                if (slot >= 0) {
-                    acc++;
-                    if (MODE == TC_ARCS) {
-                        atomicAdd(&cnt[jj], 1u);
-                        atomicAdd(&cnt[vals[slot]], 1u);
-                        atomicAdd(&te[e_vw], 1u);
+            if constexpr (MODE == TC_COUNT) {
+                const uint64_t c = walk_count<U>(pre, offj, dag_adj, d, qa, qz, keys, hb);
+                if (lane == 0) acc += c;
+            } else {
+                walk_lookup<U>(pre, offj, dag_adj, d, qa, qz, keys, hb,
+                        [&](int32_t jj, int32_t e_vw, int32_t w, int32_t slot) {
+                    if (slot >= 0) {
+                        acc++;
+                        if (MODE == TC_ARCS) {
+                            atomicAdd(&cnt[jj], 1u);
+                            atomicAdd(&cnt[vals[slot]], 1u);
+                            atomicAdd(&te[e_vw], 1u);
+                        }
+                        if (MODE == TC_LIST) {
+                            const int32_t tri[3] = {u, verts[jj], w};
+                            emit_vertices<3>(em, tri);
+                        }
                     }
-                    if (MODE == TC_LIST) {
-                        const int32_t tri[3] = {u, verts[jj], w};
-                        emit_vertices<3>(em, tri);
-                    }
-                }
-            });
+                });
+            }
             __syncthreads();
             if (MODE == TC_ARCS) {
                 for (int32_t i = tid; i < d; i += NT) {

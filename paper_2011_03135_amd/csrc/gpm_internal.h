@@ -372,6 +372,81 @@ __device__ __forceinline__ void walk_lookup(const int32_t *pre, const int32_t *o
     }
 }
 
+// Count-only form of walk_lookup: the number of pairs q in [qa, qz) whose
+// end w is an out-neighbour of the root, wave-uniform.  No slot is needed,
+// so each round's hits are a lane mask (compare results are lane masks
+// already) counted on the scalar unit, and the lanes still looking are a
+// mask too: about a third of walk_lookup's vector instructions per tile.
+template <int U>
+__device__ __forceinline__ uint64_t walk_count(const int32_t *pre, const int32_t *offj,
+                                               const int32_t *__restrict__ dag_adj, int32_t d,
+                                               int32_t qa, int32_t qz, const int32_t *keys,
+                                               int32_t bits) {
+    qa = __builtin_amdgcn_readfirstlane(qa);
+    qz = __builtin_amdgcn_readfirstlane(qz);
+    uint64_t total = 0;
+    if (qa >= qz) return 0;
+    const int lane = lane_id();
+    const uint32_t bmask = (1u << (bits - 2)) - 1u;
+    const int4 *kb = reinterpret_cast<const int4 *>(keys);
+    int32_t lo = 0, hi = d;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (__builtin_amdgcn_readfirstlane(pre[mid]) <= qa) lo = mid; else hi = mid;
+    }
+    int32_t j = __builtin_amdgcn_readfirstlane(lo);
+    const char *adj_b = reinterpret_cast<const char *>(dag_adj);
+    for (int32_t qb = qa; qb < qz; qb += U * 64) {
+        int32_t jl = j, e[U], w[U];
+        uint32_t b[U];
+        uint64_t pend[U];
+        const int32_t seg_end = __builtin_amdgcn_readfirstlane(pre[j + 1]);
+        if (qb + U * 64 <= seg_end) {
+            const int32_t base = __builtin_amdgcn_readfirstlane(offj[j]) + qb + lane;
+#pragma unroll
+            for (int t = 0; t < U; t++) e[t] = base + t * 64;
+        } else {
+            int32_t jc = j;
+#pragma unroll
+            for (int t = 0; t < U; t++) {
+                const int32_t q = min(qb + t * 64 + lane, qz - 1);
+                while (pre[jc + 1] <= q) jc++;
+                e[t] = offj[jc] + q;
+            }
+            jl = jc;
+        }
+#pragma unroll
+        for (int t = 0; t < U; t++) {
+            w[t] = *reinterpret_cast<const int32_t *>(adj_b + ((uint32_t)e[t] << 2));
+            pend[t] = __ballot(qb + t * 64 + lane < qz);
+        }
+#pragma unroll
+        for (int t = 0; t < U; t++) b[t] = lds_hash_slot(w[t], bits) >> 2;
+        for (;;) {
+            int4 kv[U];
+#pragma unroll
+            for (int t = 0; t < U; t++) kv[t] = kb[b[t]];
+            uint64_t more = 0;
+#pragma unroll
+            for (int t = 0; t < U; t++) {
+                const int4 k = kv[t];
+                const int32_t x = w[t];
+                // one lane mask per compare, combined on the scalar unit
+                const uint64_t hit = __ballot(k.x == x) | __ballot(k.y == x) |
+                                     __ballot(k.z == x) | __ballot(k.w == x);
+                const uint64_t empty = __ballot((k.x | k.y | k.z | k.w) < 0);
+                total += (uint64_t)__popcll(hit & pend[t]);
+                pend[t] &= ~(hit | empty);
+                b[t] = (b[t] + 1u) & bmask;
+                more |= pend[t];
+            }
+            if (!more) break;
+        }
+        j = __builtin_amdgcn_readlane(jl, 63);
+    }
+    return total;
+}
+
 // splitmix64 finaliser, for the listing checksum.
 __device__ __forceinline__ uint64_t fmix64(uint64_t z) {
     z ^= z >> 30; z *= 0xBF58476D1CE4E5B9ull;
