@@ -335,13 +335,15 @@ __device__ __forceinline__ void walk_lookup(const int32_t *pre, const int32_t *o
 #pragma unroll
         for (int t = 0; t < U; t++)
             w[t] = *reinterpret_cast<const int32_t *>(adj_b + ((uint32_t)e[t] << 2));
+        bool pend[U];   // lane still looking (lane masks: the logic runs on the scalar unit)
 #pragma unroll
         for (int t = 0; t < U; t++) {
             b[t] = lds_hash_slot(w[t], bits) >> 2;
-            slot[t] = qb + t * 64 + lane < qz ? -2 : -1;   // -2: still looking
+            slot[t] = -1;
+            pend[t] = qb + t * 64 + lane < qz;
         }
-        // branch-free rounds: every lane reads its current bucket (settled
-        // lanes re-read theirs) and only pending lanes take the result
+        // rounds: every lane reads its current bucket (settled lanes re-read
+        // theirs) and only pending lanes take the result
         for (;;) {
             int4 kv[U];
 #pragma unroll
@@ -351,17 +353,14 @@ __device__ __forceinline__ void walk_lookup(const int32_t *pre, const int32_t *o
             for (int t = 0; t < U; t++) {
                 const int4 k = kv[t];
                 const int32_t x = w[t];
-                const uint32_t hit = (uint32_t)(k.x == x) | ((uint32_t)(k.y == x) << 1) |
-                                     ((uint32_t)(k.z == x) << 2) | ((uint32_t)(k.w == x) << 3);
+                const bool c0 = k.x == x, c1 = k.y == x, c2 = k.z == x, c3 = k.w == x;
+                const bool hit = c0 || c1 || c2 || c3;
                 const bool empty = (k.x | k.y | k.z | k.w) < 0;
-                const int32_t at = (int32_t)(b[t] * 4u + (uint32_t)__builtin_ctz(hit | 16u));
-                const int32_t hm = -(int32_t)(hit != 0u);   // all ones on a match
-                const int32_t r = (at & hm) | ((empty ? -1 : -2) & ~hm);
-                const bool pend = slot[t] == -2;
-                const bool next = pend && r == -2;
-                slot[t] = pend ? r : slot[t];
-                b[t] = next ? ((b[t] + 1u) & bmask) : b[t];
-                more = more || next;
+                const int32_t at = (int32_t)(b[t] * 4u) + (c0 ? 0 : (c1 ? 1 : (c2 ? 2 : 3)));
+                slot[t] = pend[t] && hit ? at : slot[t];
+                pend[t] = pend[t] && !hit && !empty;
+                b[t] = (b[t] + 1u) & bmask;
+                more = more || pend[t];
             }
             if (!__any(more)) break;
         }
