@@ -690,7 +690,7 @@ static gpm_status tc_class(const gpm_graph *g, CliqueWs &W, int32_t want, int32_
     GPM_LAUNCH_CHECK("k_chunk_map");
     {
         Span sp(name, st);
-        hipLaunchKernelGGL((k_tc_block<DMAX, NT, MODE, 2>),
+        hipLaunchKernelGGL((k_tc_block<DMAX, NT, MODE, MODE == TC_COUNT ? 4 : 2>),
                            dim3((unsigned)(cu_count() * blocks_per_cu)), dim3(NT), 0, st,
                            g->dag_off, g->dag_adj, list, wpre, first, info, W.ctl + cls_idx,
                            tau, res, te, em);
