@@ -210,6 +210,61 @@ __device__ __forceinline__ int32_t group_bitonic_sort(int32_t x) {
 }
 
 constexpr int kSmallRow = 16;   // rows sorted by a 16-lane group, 4 per wave
+constexpr int kRegRow = 512;    // rows up to this length sort in registers
+
+// Sorts + uniques one row of L <= 64 R entries in place with one wave, all in
+// registers: entry i sits in lane i % 64 of x[i / 64], so bitonic partners
+// closer than 64 are a lane exchange and farther ones a register pair of
+// the same lane.  The row is read in full before any write, so in place is
+// safe.  Returns the unique count.
+template <int R>
+__device__ int32_t wave_sort_row_regs(int32_t *r, int32_t L) {
+    const int lane = lane_id();
+    int32_t x[R];
+#pragma unroll
+    for (int q = 0; q < R; q++) x[q] = q * kWave + lane < L ? r[q * kWave + lane] : INT_MAX;
+#pragma unroll
+    for (int k = 2; k <= R * kWave; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= kWave) {
+                const int jr = j / kWave;
+#pragma unroll
+                for (int q = 0; q < R; q++) {
+                    if (q & jr) continue;
+                    const bool ascending = ((q * kWave) & k) == 0;   // k >= 128 here
+                    const int32_t a = x[q], b = x[q | jr];
+                    const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
+                    x[q] = ascending ? lo : hi;
+                    x[q | jr] = ascending ? hi : lo;
+                }
+            } else {
+                const bool lower = (lane & j) == 0;
+#pragma unroll
+                for (int q = 0; q < R; q++) {
+                    const int32_t y = __shfl_xor(x[q], j, 64);
+                    const bool ascending = ((q * kWave + lane) & k) == 0;
+                    const int32_t lo = x[q] < y ? x[q] : y, hi = x[q] < y ? y : x[q];
+                    x[q] = (lower == ascending) ? lo : hi;
+                }
+            }
+        }
+    }
+    int32_t count = 0;
+    int32_t last = INT_MAX;   // the previous register's lane-63 entry
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+        const int32_t i = q * kWave + lane;
+        int32_t prev = __shfl_up(x[q], 1, 64);
+        if (lane == 0) prev = last;
+        const bool keep = i < L && (i == 0 || x[q] != prev);
+        const uint64_t mask = __ballot(keep);
+        if (keep) r[count + lanes_below(mask)] = x[q];
+        count += __popcll(mask);
+        last = __builtin_amdgcn_readlane(x[q], 63);
+    }
+    return count;
+}
 
 // Short rows: each 16-lane group sorts + uniques one row of at most 16
 // entries in place (4 consecutive rows per wave); rows beyond kSortLds go to
@@ -244,13 +299,16 @@ __global__ void __launch_bounds__(kBlock) k_sort_small_rows(const int32_t *__res
     }
 }
 
-// Rows of kSmallRow+1 .. kSortLds entries, a wave each: sort + unique in
-// place.  A wave scans 64 rows at a time and visits the ones in range (no
-// list, so no contended counter).
+// Rows of kSmallRow+1 .. kRegRow entries (LDS = false: in registers) or
+// kRegRow+1 .. kSortLds entries (LDS = true: bitonic passes in LDS), a wave
+// each: sort + unique in place.  A wave scans 64 rows at a time and visits
+// the ones in range (no list, so no contended counter); the rare long rows
+// get a launch of their own so the register sorter needs no LDS.
+template <bool LDS>
 __global__ void __launch_bounds__(kBlock) k_sort_rows(const int32_t *__restrict__ raw_off,
                                                       int32_t *raw_adj, int32_t n,
                                                       int32_t *ucnt) {
-    __shared__ int32_t lds[kWavesPerBlock][kSortLds];
+    __shared__ int32_t lds[kWavesPerBlock][LDS ? kSortLds : 1];
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
     int32_t *buf = lds[wib];
@@ -259,14 +317,21 @@ __global__ void __launch_bounds__(kBlock) k_sort_rows(const int32_t *__restrict_
     for (int64_t c0 = wave0 * kWave; c0 < n; c0 += nwaves * kWave) {
         const int64_t mine = c0 + lane;
         const int32_t Lm = mine < n ? raw_off[mine + 1] - raw_off[mine] : 0;
-        uint64_t todo = __ballot(Lm > kSmallRow && Lm <= kSortLds);
+        const int32_t lo = LDS ? kRegRow : kSmallRow, hi = LDS ? kSortLds : kRegRow;
+        uint64_t todo = __ballot(Lm > lo && Lm <= hi);
         while (todo) {
             const int32_t row = (int32_t)(c0 + __builtin_ctzll(todo));
             todo &= todo - 1ull;
             const int32_t s = raw_off[row];
             const int32_t L = raw_off[row + 1] - s;
             int32_t *r = raw_adj + s;
-            if (L <= 64) {
+            if (!LDS && L > 64) {
+                int32_t c;
+                if (L <= 128) c = wave_sort_row_regs<2>(r, L);
+                else if (L <= 256) c = wave_sort_row_regs<4>(r, L);
+                else c = wave_sort_row_regs<8>(r, L);
+                if (lane == 0) ucnt[row] = c;
+            } else if (!LDS) {
                 int32_t x = lane < L ? r[lane] : INT_MAX;
                 x = group_bitonic_sort<kWave>(x);
                 int32_t prev = __shfl_up(x, 1, 64);
@@ -274,7 +339,7 @@ __global__ void __launch_bounds__(kBlock) k_sort_rows(const int32_t *__restrict_
                 uint64_t mask = __ballot(keep);
                 if (keep) r[lanes_below(mask)] = x;
                 if (lane == 0) ucnt[row] = __popcll(mask);
-            } else if (L <= kSortLds) {
+            } else {
                 int P = 128;
                 while (P < L) P <<= 1;
                 for (int i = lane; i < P; i += kWave) buf[i] = i < L ? r[i] : INT_MAX;
@@ -763,9 +828,12 @@ static gpm_status enqueue_build(int32_t n, const int32_t *d_u, const int32_t *d_
     hipLaunchKernelGGL(k_sort_small_rows, dim3(wave_grid(((int64_t)n + 3) / 4)), dim3(kBlock), 0,
                        st, L.raw_off, L.raw_adj, n, L.ucnt, L.big_list, L.flags);
     GPM_LAUNCH_CHECK("k_sort_small_rows");
-    hipLaunchKernelGGL(k_sort_rows, dim3(wave_grid(((int64_t)n + kWave - 1) / kWave)),
+    hipLaunchKernelGGL(k_sort_rows<false>, dim3(wave_grid(((int64_t)n + kWave - 1) / kWave)),
                        dim3(kBlock), 0, st, L.raw_off, L.raw_adj, n, L.ucnt);
     GPM_LAUNCH_CHECK("k_sort_rows");
+    hipLaunchKernelGGL(k_sort_rows<true>, dim3(wave_grid(((int64_t)n + kWave - 1) / kWave)),
+                       dim3(kBlock), 0, st, L.raw_off, L.raw_adj, n, L.ucnt);
+    GPM_LAUNCH_CHECK("k_sort_rows<lds>");
     hipLaunchKernelGGL(k_sort_big_rows, dim3(L.nbig_blocks), dim3(kBlock), 0, st, L.raw_off,
                        L.raw_adj, L.ucnt, L.big_list, L.flags, L.bitmaps, L.words);
     GPM_LAUNCH_CHECK("k_sort_big_rows");
