@@ -426,6 +426,61 @@ __global__ void __launch_bounds__(kBlock) k_sort_big_rows(const int32_t *__restr
     }
 }
 
+// The same with the bitmap in LDS (n <= kLdsBitmapIds): one workgroup of
+// kBigNT threads per CU; clearing and scanning the bitmap stay on chip.
+constexpr int kBigNT = 1024;
+constexpr int64_t kLdsBitmapIds = 150 * 1024 * 8;   // 150 KiB of bits
+
+__global__ void __launch_bounds__(kBigNT) k_sort_big_rows_lds(const int32_t *__restrict__ raw_off,
+                                                              int32_t *raw_adj, int32_t *ucnt,
+                                                              const int32_t *big_list,
+                                                              const uint32_t *flags,
+                                                              int32_t words) {
+    extern __shared__ uint32_t bm[];
+    __shared__ int32_t sh[kBigNT / kWave];
+    constexpr int NW = kBigNT / kWave;
+    const int tid = threadIdx.x, lanew = tid & 63, wid = tid >> 6;
+    const uint32_t nbig = flags[F_BIG_COUNT];
+    for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
+        const int32_t row = big_list[b];
+        const int32_t s = raw_off[row];
+        const int32_t L = raw_off[row + 1] - s;
+        int32_t *r = raw_adj + s;
+        for (int32_t w = tid; w < words; w += kBigNT) bm[w] = 0u;
+        __syncthreads();
+        for (int32_t i = tid; i < L; i += kBigNT) {
+            const uint32_t x = (uint32_t)r[i];
+            atomicOr(&bm[x >> 5], 1u << (x & 31));
+        }
+        __syncthreads();
+        int32_t running = 0;
+        for (int32_t w0 = 0; w0 < words; w0 += kBigNT) {
+            const int32_t w = w0 + tid;
+            uint32_t word = w < words ? bm[w] : 0u;
+            const int32_t c = __popc(word);
+            const int32_t inc = wave_incl_scan(c);
+            if (lanew == 63) sh[wid] = inc;
+            __syncthreads();
+            int32_t before = 0, total = 0;
+#pragma unroll
+            for (int q = 0; q < NW; q++) {
+                before += q < wid ? sh[q] : 0;
+                total += sh[q];
+            }
+            int32_t pos = running + before + inc - c;
+            while (word) {
+                const int bit = __builtin_ctz(word);
+                word &= word - 1;
+                r[pos++] = w * 32 + bit;
+            }
+            running += total;
+            __syncthreads();
+        }
+        if (tid == 0) ucnt[row] = running;
+        __syncthreads();
+    }
+}
+
 // Copies the unique rows into the final CSR and counts each vertex's arcs
 // in the degree order (degrees are the unique counts).
 __global__ void __launch_bounds__(kBlock) k_compact_rows(const int32_t *__restrict__ raw_off,
@@ -834,8 +889,13 @@ static gpm_status enqueue_build(int32_t n, const int32_t *d_u, const int32_t *d_
     hipLaunchKernelGGL(k_sort_rows<true>, dim3(wave_grid(((int64_t)n + kWave - 1) / kWave)),
                        dim3(kBlock), 0, st, L.raw_off, L.raw_adj, n, L.ucnt);
     GPM_LAUNCH_CHECK("k_sort_rows<lds>");
-    hipLaunchKernelGGL(k_sort_big_rows, dim3(L.nbig_blocks), dim3(kBlock), 0, st, L.raw_off,
-                       L.raw_adj, L.ucnt, L.big_list, L.flags, L.bitmaps, L.words);
+    if (n <= kLdsBitmapIds)
+        hipLaunchKernelGGL(k_sort_big_rows_lds, dim3((unsigned)cu_count()), dim3(kBigNT),
+                           (size_t)L.words * 4, st, L.raw_off, L.raw_adj, L.ucnt, L.big_list,
+                           L.flags, (int32_t)L.words);
+    else
+        hipLaunchKernelGGL(k_sort_big_rows, dim3(L.nbig_blocks), dim3(kBlock), 0, st, L.raw_off,
+                           L.raw_adj, L.ucnt, L.big_list, L.flags, L.bitmaps, L.words);
     GPM_LAUNCH_CHECK("k_sort_big_rows");
     GPM_HIP(exclusive_scan_i32(L.ucnt, L.off, (uint64_t)n, L.scan_tmp, st));
     hipLaunchKernelGGL(k_compact_rows, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.raw_off,

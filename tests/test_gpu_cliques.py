@@ -52,10 +52,25 @@ def build_cases():
         noisy_stream(701, list(zip(mid.u.tolist(), mid.v.tolist())), 2),
         graphgen.complete_graph(40),
         graphgen.EdgeList(5, np.zeros(0, np.int32), np.zeros(0, np.int32), "empty"),
+        wide_id_range(),
     ]
 
 
-@pytest.mark.parametrize("case", range(6))
+def wide_id_range():
+    """n = 1.3M ids (above the on-chip bitmap of the long-row sorter): a
+    3000-entry row plus random edges, each listed twice."""
+    n = 1_300_000
+    rng = np.random.default_rng(11)
+    hub = np.zeros(3000, np.int64)
+    ends = rng.choice(np.arange(1, n), size=3000, replace=False)
+    a = rng.integers(0, n, size=20000)
+    b = rng.integers(0, n, size=20000)
+    u = np.concatenate([hub, ends, a, b]).astype(np.int32)
+    v = np.concatenate([ends, hub, b, a]).astype(np.int32)
+    return graphgen.EdgeList(n, u, v, "wide")
+
+
+@pytest.mark.parametrize("case", range(7))
 def test_build_matches_oracle(gpm, case):
     e = build_cases()[case]
     print(f"build case {case} {e.name} n={e.n} E={e.num_input_edges}", flush=True)
