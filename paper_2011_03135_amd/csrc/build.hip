@@ -114,40 +114,81 @@ __global__ void __launch_bounds__(kBlock) k_bucket_count(const int32_t *__restri
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_bucket_scatter(const int32_t *__restrict__ u,
-                                                           const int32_t *__restrict__ v,
-                                                           int64_t E, int32_t n, int32_t S,
-                                                           int32_t nb, int32_t *bucket_cur,
-                                                           int32_t *bsrc, int32_t *bdst) {
-    __shared__ int32_t hist[kMaxBuckets];
-    const int64_t ntiles = (E + kTileEdges - 1) / kTileEdges;
+// Moves a tile's arcs into their buckets through LDS: the arcs are first
+// placed in bucket order in LDS (LDS histogram, block prefix, one global
+// atomic per bucket for the tile's share), then copied out with consecutive
+// threads writing consecutive slots of a bucket, so each bucket's share
+// leaves as one contiguous run instead of scattered 4-byte stores.  LDS
+// (dynamic): hist, prefix and global base per bucket, then the tile's arcs.
+constexpr int kScatterNT = 1024;
+
+__global__ void __launch_bounds__(kScatterNT) k_bucket_scatter(const int32_t *__restrict__ u,
+                                                               const int32_t *__restrict__ v,
+                                                               int64_t E, int32_t n, int32_t S,
+                                                               int32_t nb, int32_t tile_edges,
+                                                               int32_t *bucket_cur, int32_t *bsrc,
+                                                               int32_t *bdst) {
+    constexpr int PER = kMaxBuckets / kScatterNT;
+    extern __shared__ int32_t sm[];
+    int32_t *hist = sm, *lpre = hist + nb, *gbase = lpre + nb + 1;
+    int32_t *s_sum = gbase + nb, *ssrc = s_sum + kScatterNT / kWave;
+    int32_t *sdst = ssrc + 2 * tile_edges;
+    const int tid = threadIdx.x;
+    const int64_t ntiles = (E + tile_edges - 1) / tile_edges;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        for (int b = threadIdx.x; b < nb; b += kBlock) hist[b] = 0;
+        for (int b = tid; b < nb; b += kScatterNT) hist[b] = 0;
         __syncthreads();
-        const int64_t e0 = t * (int64_t)kTileEdges, e1 = min(E, e0 + kTileEdges);
-        for (int64_t i = e0 + threadIdx.x; i < e1; i += kBlock) {
+        const int64_t e0 = t * (int64_t)tile_edges, e1 = min(E, e0 + tile_edges);
+        for (int64_t i = e0 + tid; i < e1; i += kScatterNT) {
             const int32_t a = u[i], b = v[i];
             if ((uint32_t)a >= (uint32_t)n || (uint32_t)b >= (uint32_t)n || a == b) continue;
             atomicAdd(&hist[a >> S], 1);
             atomicAdd(&hist[b >> S], 1);
         }
         __syncthreads();
-        // reserve each bucket's share: hist becomes the tile's write cursor
-        for (int b = threadIdx.x; b < nb; b += kBlock)
-            if (hist[b]) hist[b] = atomicAdd(&bucket_cur[b], hist[b]);
+        int32_t val[PER];
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int b = tid * PER + q;
+            val[q] = b < nb ? hist[b] : 0;
+        }
+        block_prefix<kScatterNT, PER>(val, nb, lpre, s_sum);
+        // the tile's share of each bucket; hist becomes the LDS cursor
+        for (int b = tid; b < nb; b += kScatterNT) {
+            const int32_t c = hist[b];
+            gbase[b] = c ? atomicAdd(&bucket_cur[b], c) : 0;
+            hist[b] = lpre[b];
+        }
         __syncthreads();
-        for (int64_t i = e0 + threadIdx.x; i < e1; i += kBlock) {
+        for (int64_t i = e0 + tid; i < e1; i += kScatterNT) {
             const int32_t a = u[i], b = v[i];
             if ((uint32_t)a >= (uint32_t)n || (uint32_t)b >= (uint32_t)n || a == b) continue;
             const int32_t pa = atomicAdd(&hist[a >> S], 1);
-            bsrc[pa] = a;
-            bdst[pa] = b;
+            ssrc[pa] = a;
+            sdst[pa] = b;
             const int32_t pb = atomicAdd(&hist[b >> S], 1);
-            bsrc[pb] = b;
-            bdst[pb] = a;
+            ssrc[pb] = b;
+            sdst[pb] = a;
+        }
+        __syncthreads();
+        const int32_t total = lpre[nb];
+        for (int32_t i = tid; i < total; i += kScatterNT) {
+            int32_t lo = 0, hi = nb;   // last bucket with lpre <= i
+            while (hi - lo > 1) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (lpre[mid] <= i) lo = mid; else hi = mid;
+            }
+            const int32_t g = gbase[lo] + (i - lpre[lo]);
+            bsrc[g] = ssrc[i];
+            bdst[g] = sdst[i];
         }
         __syncthreads();
     }
+}
+
+// Dynamic LDS of k_bucket_scatter for nb buckets and a tile of te edges.
+size_t scatter_lds_bytes(int32_t nb, int32_t te) {
+    return ((size_t)3 * nb + 1 + kScatterNT / kWave + 4 * (size_t)te) * 4;
 }
 
 // One block per bucket: row offsets of its 2^S sources and their arcs.
@@ -857,8 +898,15 @@ static gpm_status enqueue_build(int32_t n, const int32_t *d_u, const int32_t *d_
         GPM_HIP(exclusive_scan_i32(L.bucket_cnt, L.bucket_off, (uint64_t)L.nb, L.scan_tmp, st));
         GPM_HIP(hipMemcpyAsync(L.bucket_cur, L.bucket_off, sizeof(int32_t) * (size_t)L.nb,
                                hipMemcpyDeviceToDevice, st));
-        hipLaunchKernelGGL(k_bucket_scatter, dim3(tgrid), dim3(kBlock), 0, st, d_u, d_v, E, n,
-                           L.S, L.nb, L.bucket_cur, L.bsrc, L.bdst);
+        // the largest tile (up to kTileEdges, a multiple of 1024) whose arcs
+        // fit in LDS next to the bucket tables
+        int32_t te = kTileEdges;
+        while (te > 1024 && scatter_lds_bytes(L.nb, te) > (size_t)150 * 1024) te -= 1024;
+        const int64_t stiles = (E + te - 1) / te;
+        hipLaunchKernelGGL(k_bucket_scatter,
+                           dim3((unsigned)std::min<int64_t>(stiles, (int64_t)cu_count())),
+                           dim3(kScatterNT), scatter_lds_bytes(L.nb, te), st, d_u, d_v, E, n,
+                           L.S, L.nb, te, L.bucket_cur, L.bsrc, L.bdst);
         GPM_LAUNCH_CHECK("k_bucket_scatter");
         hipLaunchKernelGGL(k_bucket_rows,
                            dim3((unsigned)std::min<int64_t>(L.nb, (int64_t)cu_count() * 2)),
