@@ -530,23 +530,47 @@ __global__ void __launch_bounds__(kBlock) k_compact_rows(const int32_t *__restri
                                                          const int32_t *__restrict__ deg,
                                                          int32_t *adj, int32_t n,
                                                          int32_t *outcnt, uint32_t *flags) {
-    const int lane = lane_id();
+    const int lane = lane_id(), gl = lane & (kSmallRow - 1), grp = lane / kSmallRow;
     const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    constexpr int kRows = kWave / kSmallRow;
     int32_t maxd = 0;
-    for (int64_t row = wave0; row < n; row += nwaves) {
+    // 4 rows per wave: rows of <= 16 entries by a 16-lane group each, longer
+    // ones by the whole wave after them
+    for (int64_t r0 = wave0 * kRows; r0 < n; r0 += nwaves * kRows) {
+        const int64_t row = r0 + grp;
+        const bool live = row < n;
         const int32_t u = (int32_t)row;
-        const int32_t src = raw_off[row], dst = off[row], L = off[row + 1] - dst;
-        int32_t c = 0;
-        for (int32_t i = lane; i < L; i += kWave) {
-            const int32_t v = raw_adj[src + i];
-            adj[dst + i] = v;
-            c += rank_less(L, u, deg[v], v) ? 1 : 0;
-        }
-        c = wave_sum(c);
-        if (lane == 0) outcnt[u] = c;
+        const int32_t src = live ? raw_off[row] : 0, dst = live ? off[row] : 0;
+        const int32_t L = live ? off[row + 1] - dst : 0;
         maxd = L > maxd ? L : maxd;
+        const bool small = L <= kSmallRow;
+        int32_t c = 0;
+        if (small && gl < L) {
+            const int32_t v = raw_adj[src + gl];
+            adj[dst + gl] = v;
+            c = rank_less(L, u, deg[v], v) ? 1 : 0;
+        }
+#pragma unroll
+        for (int o = kSmallRow / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+        if (live && small && gl == 0) outcnt[u] = c;
+        uint64_t longm = __ballot(live && !small && gl == 0);
+        while (longm) {
+            const int g = __builtin_ctzll(longm) / kSmallRow;
+            longm &= longm - 1ull;
+            const int32_t w = (int32_t)(r0 + g);
+            const int32_t ws = raw_off[w], wd = off[w], wl = off[w + 1] - wd;
+            int32_t cw = 0;
+            for (int32_t i = lane; i < wl; i += kWave) {
+                const int32_t v = raw_adj[ws + i];
+                adj[wd + i] = v;
+                cw += rank_less(wl, w, deg[v], v) ? 1 : 0;
+            }
+            cw = wave_sum(cw);
+            if (lane == 0) outcnt[w] = cw;
+        }
     }
+    maxd = wave_max(maxd);
     if (lane == 0 && maxd > 0) atomicMax(&flags[F_MAX_DEG], (uint32_t)maxd);
 }
 
@@ -575,37 +599,67 @@ __global__ void __launch_bounds__(kBlock) k_orient_fill(const int32_t *__restric
                                                         const int32_t *__restrict__ dag_off,
                                                         int32_t n, int64_t cap, int32_t *dag_adj,
                                                         int32_t *dag_src, uint32_t *flags) {
-    const int lane = lane_id();
+    const int lane = lane_id(), gl = lane & (kSmallRow - 1), grp = lane / kSmallRow;
     const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    constexpr int kRows = kWave / kSmallRow;
     int32_t maxo = 0;
-    for (int64_t row = wave0; row < n; row += nwaves) {
-        const int32_t u = (int32_t)row;
-        const int32_t s = off[u], du = off[u + 1] - s;
-        int32_t base = dag_off[u];
-        for (int32_t i0 = 0; i0 < du; i0 += kWave) {
-            int32_t i = i0 + lane;
-            int32_t v = i < du ? adj[s + i] : 0;
-            bool keep = false;
-            if (i < du) {
-                int32_t dv = off[v + 1] - off[v];
-                keep = rank_less(du, u, dv, v);
-            }
-            uint64_t mask = __ballot(keep);
-            if (keep) {
-                int32_t p = base + lanes_below(mask);
-                if (p < cap) {
-                    dag_adj[p] = v;
-                    dag_src[p] = u;
-                } else {
-                    atomicOr(&flags[F_ERR], 4u);   // more arcs than the storage holds
-                }
-            }
-            base += __popcll(mask);
+    // 4 rows per wave: rows of <= 16 entries by a 16-lane group each, longer
+    // ones by the whole wave after them
+    for (int64_t r0 = wave0 * kRows; r0 < n; r0 += nwaves * kRows) {
+        const int64_t row = r0 + grp;
+        const bool live = row < n;
+        const int32_t su = live ? off[row] : 0, dsu = live ? off[row + 1] - su : 0;
+        const bool small = dsu <= kSmallRow;
+        int32_t v = 0;
+        bool keep = false;
+        if (small && gl < dsu) {
+            v = adj[su + gl];
+            keep = rank_less(dsu, (int32_t)row, off[v + 1] - off[v], v);
         }
-        int32_t d = base - dag_off[u];
-        maxo = d > maxo ? d : maxo;
+        const uint32_t gmask =
+            (uint32_t)(__ballot(keep) >> (grp * kSmallRow)) & ((1u << kSmallRow) - 1u);
+        if (keep) {
+            const int32_t p = dag_off[row] + __popc(gmask & ((1u << gl) - 1u));
+            if (p < cap) {
+                dag_adj[p] = v;
+                dag_src[p] = (int32_t)row;
+            } else {
+                atomicOr(&flags[F_ERR], 4u);   // more arcs than the storage holds
+            }
+        }
+        maxo = max(maxo, __popc(gmask));
+        uint64_t longm = __ballot(live && !small && gl == 0);
+        while (longm) {
+            const int32_t u = (int32_t)(r0 + __builtin_ctzll(longm) / kSmallRow);
+            longm &= longm - 1ull;
+            const int32_t s = off[u], du = off[u + 1] - s;
+            int32_t base = dag_off[u];
+            for (int32_t i0 = 0; i0 < du; i0 += kWave) {
+                int32_t i = i0 + lane;
+                int32_t v = i < du ? adj[s + i] : 0;
+                bool keep = false;
+                if (i < du) {
+                    int32_t dv = off[v + 1] - off[v];
+                    keep = rank_less(du, u, dv, v);
+                }
+                uint64_t mask = __ballot(keep);
+                if (keep) {
+                    int32_t p = base + lanes_below(mask);
+                    if (p < cap) {
+                        dag_adj[p] = v;
+                        dag_src[p] = u;
+                    } else {
+                        atomicOr(&flags[F_ERR], 4u);   // more arcs than the storage holds
+                    }
+                }
+                base += __popcll(mask);
+            }
+            int32_t d = base - dag_off[u];
+            maxo = d > maxo ? d : maxo;
+        }
     }
+    maxo = wave_max(maxo);
     if (lane == 0 && maxo > 0) atomicMax(&flags[F_MAX_OUT], (uint32_t)maxo);
 }
 
