@@ -28,6 +28,7 @@ enum Flag : int {
     F_BIG_COUNT = 1,  // rows routed to the bitmap sorter
     F_MAX_DEG = 2,
     F_MAX_OUT = 3,
+    F_MED_COUNT = 4,  // rows routed to the LDS sorter
     F_WORDS = 16,
 };
 
@@ -308,13 +309,14 @@ __device__ int32_t wave_sort_row_regs(int32_t *r, int32_t L) {
 }
 
 // Short rows: each 16-lane group sorts + uniques one row of at most 16
-// entries in place (4 consecutive rows per wave); rows beyond kSortLds go to
-// the bitmap sorter's list, the rest are left to k_sort_rows.  Most rows of
-// power-law graphs are short.
+// entries in place (4 consecutive rows per wave).  Rows beyond kRegRow go to
+// lists (the LDS sorter's up to kSortLds, the bitmap sorter's beyond), which
+// spread these few long rows, crowded at the hub ids, over all waves; the
+// rest are left to k_sort_rows.  Most rows of power-law graphs are short.
 __global__ void __launch_bounds__(kBlock) k_sort_small_rows(const int32_t *__restrict__ raw_off,
                                                             int32_t *raw_adj, int32_t n,
-                                                            int32_t *ucnt, int32_t *big_list,
-                                                            uint32_t *flags) {
+                                                            int32_t *ucnt, int32_t *med_list,
+                                                            int32_t *big_list, uint32_t *flags) {
     const int lane = lane_id(), gl = lane & (kSmallRow - 1), grp = lane / kSmallRow;
     const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -336,32 +338,42 @@ __global__ void __launch_bounds__(kBlock) k_sort_small_rows(const int32_t *__res
         if (live && gl == 0) {
             if (small) ucnt[row] = __popc(gmask);
             else if (L > kSortLds) big_list[atomicAdd(&flags[F_BIG_COUNT], 1u)] = (int32_t)row;
+            else if (L > kRegRow) med_list[atomicAdd(&flags[F_MED_COUNT], 1u)] = (int32_t)row;
         }
     }
 }
 
-// Rows of kSmallRow+1 .. kRegRow entries (LDS = false: in registers) or
-// kRegRow+1 .. kSortLds entries (LDS = true: bitonic passes in LDS), a wave
-// each: sort + unique in place.  A wave scans 64 rows at a time and visits
-// the ones in range (no list, so no contended counter); the rare long rows
-// get a launch of their own so the register sorter needs no LDS.
+// Rows of kSmallRow+1 .. kRegRow entries (LDS = false: in registers; a wave
+// scans 64 rows at a time and visits the ones in range, no list, so no
+// contended counter) or the listed rows of kRegRow+1 .. kSortLds entries
+// (LDS = true: bitonic passes in LDS), a wave each: sort + unique in place.
+// The rare long rows get a launch of their own so the register sorter needs
+// no LDS.
 template <bool LDS>
 __global__ void __launch_bounds__(kBlock) k_sort_rows(const int32_t *__restrict__ raw_off,
                                                       int32_t *raw_adj, int32_t n,
-                                                      int32_t *ucnt) {
+                                                      int32_t *ucnt, const int32_t *med_list,
+                                                      const uint32_t *flags) {
     __shared__ int32_t lds[kWavesPerBlock][LDS ? kSortLds : 1];
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
     int32_t *buf = lds[wib];
     const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + wib;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t c0 = wave0 * kWave; c0 < n; c0 += nwaves * kWave) {
-        const int64_t mine = c0 + lane;
-        const int32_t Lm = mine < n ? raw_off[mine + 1] - raw_off[mine] : 0;
-        const int32_t lo = LDS ? kRegRow : kSmallRow, hi = LDS ? kSortLds : kRegRow;
-        uint64_t todo = __ballot(Lm > lo && Lm <= hi);
+    const int64_t nmed = LDS ? (int64_t)flags[F_MED_COUNT] : 0;
+    const int64_t nitems = LDS ? nmed : ((int64_t)n + kWave - 1) / kWave;
+    for (int64_t it = wave0; it < nitems; it += nwaves) {
+        const int64_t c0 = it * kWave;
+        uint64_t todo;
+        if (LDS) {
+            todo = 1ull;
+        } else {
+            const int64_t mine = c0 + lane;
+            const int32_t Lm = mine < n ? raw_off[mine + 1] - raw_off[mine] : 0;
+            todo = __ballot(Lm > kSmallRow && Lm <= kRegRow);
+        }
         while (todo) {
-            const int32_t row = (int32_t)(c0 + __builtin_ctzll(todo));
+            const int32_t row = LDS ? med_list[it] : (int32_t)(c0 + __builtin_ctzll(todo));
             todo &= todo - 1ull;
             const int32_t s = raw_off[row];
             const int32_t L = raw_off[row + 1] - s;
@@ -732,7 +744,7 @@ struct BuildLayout {
     int32_t *off, *adj, *dag_off, *dag_adj, *dag_src;
     int64_t *meta;
     // scratch
-    int32_t *cnt, *raw_off, *raw_adj, *ucnt, *outcnt, *big_list;
+    int32_t *cnt, *raw_off, *raw_adj, *ucnt, *outcnt, *big_list, *med_list;
     int32_t S, nb;                                  // buckets of 2^S source ids (S = 0: none)
     int32_t *bucket_cnt, *bucket_off, *bucket_cur, *bsrc, *bdst;
     int64_t *scan_tmp;
@@ -767,6 +779,7 @@ BuildLayout layout(int32_t n, int64_t E, void *gmem, void *smem) {
     L.ucnt = s.take<int32_t>((uint64_t)n + 1);
     L.outcnt = s.take<int32_t>((uint64_t)n + 1);
     L.big_list = s.take<int32_t>((uint64_t)n + 1);
+    L.med_list = s.take<int32_t>((uint64_t)n + 1);
     L.scan_tmp = s.take<int64_t>(scan_tmp_words((uint64_t)n + 1));
     L.flags = s.take<uint32_t>(F_WORDS);
     L.S = bucket_shift(n);
@@ -983,13 +996,14 @@ static gpm_status enqueue_build(int32_t n, const int32_t *d_u, const int32_t *d_
         }
     }
     hipLaunchKernelGGL(k_sort_small_rows, dim3(wave_grid(((int64_t)n + 3) / 4)), dim3(kBlock), 0,
-                       st, L.raw_off, L.raw_adj, n, L.ucnt, L.big_list, L.flags);
+                       st, L.raw_off, L.raw_adj, n, L.ucnt, L.med_list, L.big_list, L.flags);
     GPM_LAUNCH_CHECK("k_sort_small_rows");
     hipLaunchKernelGGL(k_sort_rows<false>, dim3(wave_grid(((int64_t)n + kWave - 1) / kWave)),
-                       dim3(kBlock), 0, st, L.raw_off, L.raw_adj, n, L.ucnt);
+                       dim3(kBlock), 0, st, L.raw_off, L.raw_adj, n, L.ucnt, L.med_list,
+                       L.flags);
     GPM_LAUNCH_CHECK("k_sort_rows");
-    hipLaunchKernelGGL(k_sort_rows<true>, dim3(wave_grid(((int64_t)n + kWave - 1) / kWave)),
-                       dim3(kBlock), 0, st, L.raw_off, L.raw_adj, n, L.ucnt);
+    hipLaunchKernelGGL(k_sort_rows<true>, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.raw_off,
+                       L.raw_adj, n, L.ucnt, L.med_list, L.flags);
     GPM_LAUNCH_CHECK("k_sort_rows<lds>");
     if (n <= kLdsBitmapIds)
         hipLaunchKernelGGL(k_sort_big_rows_lds, dim3((unsigned)cu_count()), dim3(kBigNT),
