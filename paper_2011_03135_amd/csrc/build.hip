@@ -754,11 +754,14 @@ struct BuildLayout {
     uint64_t graph_bytes, scratch_bytes;
 };
 
-// Bucket shift for n vertices: the smallest S >= 12 with at most
-// kMaxBuckets buckets of 2^S ids, or 0 when 2^S would exceed kMaxBucketIds.
+// Bucket shift for n vertices: the smallest S >= 10 with at most
+// kTargetBuckets buckets of 2^S ids, or 0 when 2^S would exceed
+// kMaxBucketIds.  About 1024 buckets keep the hub ids' bucket (power-law
+// graphs put their hubs at low ids) from dominating the per-bucket pass.
+constexpr int kTargetBuckets = 1024;
 int32_t bucket_shift(int32_t n) {
-    int32_t S = 12;
-    while (((int64_t)n + (1ll << S) - 1) >> S > kMaxBuckets) S++;
+    int32_t S = 10;
+    while (((int64_t)n + (1ll << S) - 1) >> S > kTargetBuckets) S++;
     return (1 << S) <= kMaxBucketIds ? S : 0;
 }
 
