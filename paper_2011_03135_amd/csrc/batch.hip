@@ -420,17 +420,18 @@ gpm_status batch_autotune(const gpm_graph *g, const int32_t *d_voff, int32_t G, 
     for (const gpm_batch_config &c : cands) {
         rc = batch_run(g, d_voff, G, k, &c, ws, ws_bytes, d_counts, st);   // warm-up
         if (rc) break;
-        hipEventRecord(e0, st);
-        for (int r = 0; r < reps && !rc; r++)
+        hipError_t he = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && !rc && he == hipSuccess; r++)
             rc = batch_run(g, d_voff, G, k, &c, ws, ws_bytes, d_counts, st);
-        hipEventRecord(e1, st);
         if (rc) break;
-        if (hipEventSynchronize(e1) != hipSuccess) {
-            rc = hip_fail(hipGetLastError(), "autotune timing");
+        if (he == hipSuccess) he = hipEventRecord(e1, st);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) {
+            rc = hip_fail(he, "autotune timing");
             break;
         }
-        float ms = 0.0f;
-        hipEventElapsedTime(&ms, e0, e1);
         ms /= (float)reps;
         if (best_t < 0.0f || ms < best_t) {
             best_t = ms;
@@ -439,8 +440,8 @@ gpm_status batch_autotune(const gpm_graph *g, const int32_t *d_voff, int32_t G, 
     }
     if (!rc) rc = batch_run(g, d_voff, G, k, best, ws, ws_bytes, d_counts, st);
     if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = hip_fail(hipGetLastError(), "autotune");
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (best_ms) *best_ms = best_t;
     return rc;
 }

@@ -76,6 +76,7 @@ struct Job {
     gpm_response resp;
     gpm_pattern pat;
     uint64_t ws_bytes = 0, ws_off = 0;
+    uint64_t ws_alloc = 0;   // bytes taken from the pool (at least 256)
 };
 
 }  // namespace
@@ -140,7 +141,8 @@ void finish(gpm_server *s, Job *j) {
 }
 
 void run(gpm_server *s) {
-    hipSetDevice(s->dev);
+    // without the device every request fails rather than running elsewhere
+    const bool dev_ok = hipSetDevice(s->dev) == hipSuccess;
     const int slots = s->cfg.max_slots;
     std::unique_lock<std::mutex> lock(s->mu);
     for (;;) {
@@ -156,7 +158,7 @@ void run(gpm_server *s) {
             } else {
                 for (int v = 0; v < 7; v++) j->resp.values[v] = s->pinned[8 * i + v];
             }
-            s->pool->release(j->ws_off, j->ws_bytes);
+            s->pool->release(j->ws_off, j->ws_alloc);
             s->slot_job[i] = nullptr;
             finish(s, j);
             progress = true;
@@ -168,15 +170,16 @@ void run(gpm_server *s) {
             if (free_slot < 0) break;
             Job *j = s->queue.front();
             uint64_t off;
-            if (!s->pool->alloc(std::max<uint64_t>(j->ws_bytes, 256), off)) break;  // wait for memory
+            j->ws_alloc = std::max<uint64_t>(j->ws_bytes, 256);
+            if (!s->pool->alloc(j->ws_alloc, off)) break;  // wait for memory
             s->queue.pop_front();
             j->ws_off = off;
             j->resp.t_admit = now_s();
-            gpm_status rc = launch(s, free_slot, j);
+            gpm_status rc = dev_ok ? launch(s, free_slot, j) : GPM_DEVICE_ERROR;
             if (rc) {
                 j->resp.status = rc;
                 j->resp.t_done = now_s();
-                s->pool->release(off, std::max<uint64_t>(j->ws_bytes, 256));
+                s->pool->release(off, j->ws_alloc);
                 finish(s, j);
             } else {
                 s->slot_job[free_slot] = j;
@@ -217,7 +220,11 @@ gpm_status gpm_server_create(const gpm_server_config *cfg, gpm_server **out) {
     s->cfg = *cfg;
     s->result_bytes = result_bytes;
     s->pool = new Pool(cfg->pool_bytes - result_bytes);
-    hipGetDevice(&s->dev);
+    if (hipGetDevice(&s->dev) != hipSuccess) {
+        delete s->pool;
+        delete s;
+        return gpm::fail(GPM_DEVICE_ERROR, "no current HIP device");
+    }
     {
         const int pct = cfg->cu_percent > 0 ? cfg->cu_percent : 50;
         s->cu_limit = std::max(1, gpm::cu_count() * pct / 100);
@@ -225,10 +232,14 @@ gpm_status gpm_server_create(const gpm_server_config *cfg, gpm_server **out) {
     for (int i = 0; i < cfg->max_slots; i++) {
         hipStream_t st;
         hipEvent_t ev;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
             gpm_server_destroy(s);
-            return gpm::fail(GPM_DEVICE_ERROR, "stream or event creation failed");
+            return gpm::fail(GPM_DEVICE_ERROR, "stream creation failed");
+        }
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipStreamDestroy(st);
+            gpm_server_destroy(s);
+            return gpm::fail(GPM_DEVICE_ERROR, "event creation failed");
         }
         s->streams.push_back(st);
         s->events.push_back(ev);

@@ -194,8 +194,14 @@ bool timing_on() { return g_timing; }
 void span_begin(const char *name, hipStream_t s) {
     std::lock_guard<std::mutex> lock(g_tmu);
     Rec r{name, nullptr, nullptr, -1};
-    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
-    hipEventRecord(r.a, s);
+    // timing is best effort: a span whose events cannot be made or recorded
+    // keeps its place (so nesting stays paired) and reads back as no time
+    if (hipEventCreate(&r.a) != hipSuccess) r.a = nullptr;
+    if (hipEventCreate(&r.b) != hipSuccess) r.b = nullptr;
+    if (r.a && r.b && hipEventRecord(r.a, s) != hipSuccess) {
+        (void)hipEventDestroy(r.a);
+        r.a = nullptr;
+    }
     g_open.push_back(g_recs.size());
     g_recs.push_back(r);
 }
@@ -205,7 +211,10 @@ void span_end(hipStream_t s) {
     if (g_open.empty()) return;
     size_t i = g_open.back();
     g_open.pop_back();
-    hipEventRecord(g_recs[i].b, s);
+    if (g_recs[i].a && g_recs[i].b && hipEventRecord(g_recs[i].b, s) != hipSuccess) {
+        (void)hipEventDestroy(g_recs[i].a);
+        g_recs[i].a = nullptr;
+    }
 }
 
 void timing_set(bool on) {
@@ -220,15 +229,17 @@ int timing_read(const char **names, float *ms, uint64_t *units, int cap) {
     int k = 0;
     for (auto &r : g_recs) {
         float t = -1.f;
-        if (hipEventSynchronize(r.b) == hipSuccess) (void)hipEventElapsedTime(&t, r.a, r.b);
+        if (r.a && r.b && hipEventSynchronize(r.b) == hipSuccess &&
+            hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+            t = -1.f;
         if (k < cap) {
             keep.push_back(r.name);
             if (ms) ms[k] = t;
             if (units) units[k] = r.unit_slot >= 0 ? g_units[r.unit_slot] : 0;
         }
         k++;
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
+        if (r.a) (void)hipEventDestroy(r.a);
+        if (r.b) (void)hipEventDestroy(r.b);
     }
     if (names)
         for (int i = 0; i < (int)keep.size(); i++) names[i] = keep[i].c_str();
