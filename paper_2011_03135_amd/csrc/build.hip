@@ -310,9 +310,9 @@ __device__ int32_t wave_sort_row_regs(int32_t *r, int32_t L) {
 
 // Short rows: each 16-lane group sorts + uniques one row of at most 16
 // entries in place (4 consecutive rows per wave).  Rows beyond kRegRow go to
-// lists (the LDS sorter's up to kSortLds, the bitmap sorter's beyond), which
-// spread these few long rows, crowded at the hub ids, over all waves; the
-// rest are left to k_sort_rows.  Most rows of power-law graphs are short.
+// lists (the LDS sorter's up to kSortLds, the bitmap sorter's beyond), from
+// which the sorters' waves take one row each; the rest are left to
+// k_sort_rows.  Most rows of power-law graphs are short.
 __global__ void __launch_bounds__(kBlock) k_sort_small_rows(const int32_t *__restrict__ raw_off,
                                                             int32_t *raw_adj, int32_t n,
                                                             int32_t *ucnt, int32_t *med_list,
@@ -756,8 +756,8 @@ struct BuildLayout {
 
 // Bucket shift for n vertices: the smallest S >= 10 with at most
 // kTargetBuckets buckets of 2^S ids, or 0 when 2^S would exceed
-// kMaxBucketIds.  About 1024 buckets keep the hub ids' bucket (power-law
-// graphs put their hubs at low ids) from dominating the per-bucket pass.
+// kMaxBucketIds.  About 1024 buckets (4 per CU at 256 CUs) keep a bucket
+// that holds a hub's arcs from dominating the per-bucket pass.
 constexpr int kTargetBuckets = 1024;
 int32_t bucket_shift(int32_t n) {
     int32_t S = 10;
