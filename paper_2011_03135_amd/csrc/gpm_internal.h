@@ -192,18 +192,6 @@ __device__ __forceinline__ void lds_hash_insert(int32_t *keys, int16_t *vals, in
     }
 }
 
-// Slot holding key, or -1 when absent.
-__device__ __forceinline__ int32_t lds_hash_find(const int32_t *keys, int32_t bits, int32_t key) {
-    const uint32_t mask = (1u << bits) - 1u;
-    uint32_t h = lds_hash_slot(key, bits);
-    for (;;) {
-        const int32_t k = keys[h];
-        if (k == key) return (int32_t)h;
-        if (k < 0) return -1;
-        h = (h + 1) & mask;
-    }
-}
-
 // Block-wide exclusive scan of PER values per thread (thread t owns entries
 // t*PER .. t*PER+PER-1): pre[i+1] = sum of entries 0..i for i < d, pre[0] =
 // 0.  s_sum holds NT/64 words of LDS.  Ends with a barrier.
