@@ -53,6 +53,8 @@ def _load():
         lib.orc_list_diamonds.argtypes = [i32, p, p, i32, p, u64, p, p, p]
         lib.orc_list_c4.argtypes = [i32, p, p, i32, p, u64, p, p, p]
         lib.orc_wedges.argtypes = [i32, p, p]
+        lib.orc_pattern_count.argtypes = [i32, p, p, i32, i32, p, i32, i32, p]
+        lib.orc_pattern_count.restype = ctypes.c_int
         lib.orc_clique_count_sampled.argtypes = [i32, p, p, i32, i32, i32, p]
         lib.orc_clique_count_sampled.restype = ctypes.c_int
         for f in (lib.orc_clique_count, lib.orc_clique_list, lib.orc_edge_triangles,
@@ -196,3 +198,19 @@ def batch_motifs(batch, k, threads=1):
         off, adj = canonical_csr(e.n, e.u, e.v)
         out.append(motif3(off, adj, threads) if k == 3 else motif4(off, adj, threads))
     return out
+
+
+def pattern_count(off, adj, k, edges, induced, threads=0):
+    """Embeddings of the connected pattern with k vertices and the given
+    edge list (pairs of pattern vertices): vertex-induced (motif counting)
+    or edge-induced (subgraph listing), Section 2's problem definitions.
+    Plain definition: injective maps onto edges (and non-edges when
+    induced) counted by backtracking, divided by the pattern's automorphism
+    count.  Returns (count, automorphisms)."""
+    off, adj, n = _prep(off, adj)
+    pe = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1))
+    out = np.zeros(3, dtype=np.uint64)
+    _check(_load().orc_pattern_count(n, _ptr(off), _ptr(adj), int(k), int(pe.shape[0] // 2),
+                                     _ptr(pe), int(bool(induced)), int(threads), _ptr(out)),
+           "pattern_count")
+    return _u128(out[0], out[1]), int(out[2])

@@ -589,3 +589,124 @@ int orc_wedges(int32_t n, const int64_t *off, uint64_t *out)
     put128(out, w);
     return ORC_OK;
 }
+
+/* ------------------------------------------------ any connected pattern --- */
+/*
+ * Embeddings of a connected pattern P (k <= 8 vertices, edge list pe[2*ne])
+ * in G (Section 2: subgraph listing counts edge-induced embeddings, motif
+ * counting vertex-induced ones).  Written as the plain definition: count
+ * every injective map f from P's vertices to G's with f(a)f(b) an edge of G
+ * for each pattern edge ab (and, vertex-induced, a non-edge for each pattern
+ * non-edge), then divide by |Aut(P)|, the number of such maps per
+ * embedding.  No symmetry breaking.  Pattern vertices are visited in BFS
+ * order from vertex 0 so each one after the first has an earlier neighbour
+ * whose row supplies its candidates.
+ */
+static int has_edge(const int64_t *off, const int32_t *adj, int32_t u, int32_t v)
+{
+    int64_t lo = off[u], hi = off[u + 1];
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (adj[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo < off[u + 1] && adj[lo] == v;
+}
+
+struct pat {
+    int k, induced;
+    int order[8];          /* pattern vertex visited at step i */
+    int adjm[8][8];        /* pattern adjacency by vertex */
+    int anchor[8];         /* an earlier step adjacent to step i */
+};
+
+static u128 maps_from(const int64_t *off, const int32_t *adj, const struct pat *p,
+                      int32_t *img, int step)
+{
+    if (step == p->k) return 1;
+    const int pv = p->order[step];
+    const int32_t a = img[p->anchor[step]];
+    u128 total = 0;
+    for (int64_t e = off[a]; e < off[a + 1]; e++) {
+        const int32_t v = adj[e];
+        int ok = 1;
+        for (int s = 0; s < step && ok; s++) {
+            if (img[s] == v) { ok = 0; break; }
+            const int adjacent = p->adjm[pv][p->order[s]];
+            if (s == p->anchor[step]) continue;
+            const int edge = has_edge(off, adj, img[s], v);
+            if (adjacent && !edge) ok = 0;
+            if (!adjacent && p->induced && edge) ok = 0;
+        }
+        if (!ok) continue;
+        img[step] = v;
+        total += maps_from(off, adj, p, img, step + 1);
+    }
+    return total;
+}
+
+static int next_perm(int *a, int n)
+{
+    int i = n - 2;
+    while (i >= 0 && a[i] >= a[i + 1]) i--;
+    if (i < 0) return 0;
+    int j = n - 1;
+    while (a[j] <= a[i]) j--;
+    int t = a[i]; a[i] = a[j]; a[j] = t;
+    for (int l = i + 1, r = n - 1; l < r; l++, r--) { t = a[l]; a[l] = a[r]; a[r] = t; }
+    return 1;
+}
+
+/* out[0..1]: embeddings (low, high); out[2]: |Aut(P)|. */
+int orc_pattern_count(int32_t n, const int64_t *off, const int32_t *adj, int32_t k, int32_t ne,
+                      const int32_t *pe, int32_t induced, int32_t threads, uint64_t *out)
+{
+    if (n < 0 || k < 2 || k > 8 || ne < k - 1 || !pe || !out) return ORC_BAD_ARG;
+    struct pat p;
+    memset(&p, 0, sizeof(p));
+    p.k = k;
+    p.induced = induced != 0;
+    for (int i = 0; i < ne; i++) {
+        const int a = pe[2 * i], b = pe[2 * i + 1];
+        if (a < 0 || b < 0 || a >= k || b >= k || a == b) return ORC_BAD_ARG;
+        p.adjm[a][b] = p.adjm[b][a] = 1;
+    }
+    /* BFS order from vertex 0; the anchor of each step is its BFS parent */
+    int seen[8] = {0}, parent_step[8] = {0}, head = 0, tail = 0;
+    p.order[tail++] = 0;
+    seen[0] = 1;
+    while (head < tail) {
+        const int x = p.order[head];
+        for (int y = 0; y < k; y++)
+            if (p.adjm[x][y] && !seen[y]) {
+                seen[y] = 1;
+                parent_step[tail] = head;
+                p.order[tail++] = y;
+            }
+        head++;
+    }
+    if (tail != k) return ORC_BAD_ARG;   /* not connected */
+    for (int i = 1; i < k; i++) p.anchor[i] = parent_step[i];
+    /* |Aut(P)|: permutations preserving adjacency */
+    int perm[8];
+    for (int i = 0; i < k; i++) perm[i] = i;
+    uint64_t aut = 0;
+    do {
+        int ok = 1;
+        for (int a = 0; a < k && ok; a++)
+            for (int b = 0; b < k; b++)
+                if (p.adjm[a][b] != p.adjm[perm[a]][perm[b]]) { ok = 0; break; }
+        aut += ok;
+    } while (next_perm(perm, k));
+    u128 total = 0;
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
+    for (int32_t r = 0; r < n; r++) {
+        int32_t img[8];
+        img[0] = r;
+        total += maps_from(off, adj, &p, img, 1);
+    }
+    if (total % aut != 0) return ORC_BAD_ARG;   /* cannot happen for a valid pattern */
+    put128(out, total / aut);
+    out[2] = aut;
+    return ORC_OK;
+}

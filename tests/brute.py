@@ -104,3 +104,36 @@ def edge_induced_embeddings(adj, pattern_edges):
 def clique_sets(adj, k):
     return {vs for vs in combinations(range(len(adj)), k)
             if all(b in adj[a] for a, b in combinations(vs, 2))}
+
+
+# connected patterns of 3..5 vertices for the general-pattern tests: (k, edges)
+PATTERNS_ANY = {
+    "wedge": (3, [(0, 1), (1, 2)]),
+    "triangle": (3, [(0, 1), (1, 2), (0, 2)]),
+    **{name: (4, e) for name, e in PATTERNS4.items()},
+    "5-path": (5, [(0, 1), (1, 2), (2, 3), (3, 4)]),
+    "4-star": (5, [(0, 1), (0, 2), (0, 3), (0, 4)]),
+    "5-cycle": (5, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 0)]),
+    "house": (5, [(0, 1), (1, 2), (2, 3), (3, 0), (2, 4), (3, 4)]),
+    "bull": (5, [(0, 1), (1, 2), (0, 2), (1, 3), (2, 4)]),
+    "gem": (5, [(0, 1), (0, 2), (0, 3), (0, 4), (1, 2), (2, 3), (3, 4)]),
+    "5-clique": (5, [(a, b) for a in range(5) for b in range(a + 1, 5)]),
+}
+
+
+def pattern_embeddings(adj, k, pattern_edges, induced):
+    """Number of embeddings of a connected k-vertex pattern: vertex-induced,
+    the k-sets whose induced subgraph is isomorphic to it; edge-induced, the
+    distinct edge sets F (spanning k vertices) isomorphic to it."""
+    target = canon(k, pattern_edges)
+    ne = len(pattern_edges)
+    count = 0
+    for vs in combinations(range(len(adj)), k):
+        ind = induced_edges(adj, vs)
+        if induced:
+            count += len(ind) == ne and canon(k, ind) == target
+            continue
+        for F in combinations(ind, ne):
+            if len({x for e in F for x in e}) == k and canon(k, list(F)) == target:
+                count += 1
+    return count

@@ -230,3 +230,57 @@ def test_canonical_csr_rules():
     assert rows == {0: [2], 1: [3], 2: [0], 3: [1]}
     with pytest.raises(ValueError):
         canonical_csr(4, np.array([0]), np.array([4]))
+
+
+# ------------------------------------------- any connected pattern ---------
+
+PATTERN_TINY = [(s, n, p) for s in (1, 2, 3) for n in (6, 8) for p in (0.35, 0.7)]
+
+
+@pytest.mark.parametrize("seed,n,p", PATTERN_TINY)
+@pytest.mark.parametrize("induced", [False, True])
+def test_pattern_count_brute_force(seed, n, p, induced):
+    g = random_tiny(seed, n, p)
+    off, adj = csr(g)
+    sets = brute.adjacency_sets(g.n, g.u, g.v)
+    for name, (k, edges) in brute.PATTERNS_ANY.items():
+        got, _ = oracle.pattern_count(off, adj, k, edges, induced)
+        assert got == brute.pattern_embeddings(sets, k, edges, induced), (name, induced)
+
+
+def test_pattern_count_closed_forms():
+    off, adj = csr(graphgen.complete_graph(9))
+    P = brute.PATTERNS_ANY
+    for k in (3, 4, 5):
+        name = {3: "triangle", 4: "4-clique", 5: "5-clique"}[k]
+        assert oracle.pattern_count(off, adj, k, P[name][1], True)[0] == math.comb(9, k)
+    # edge-induced 4-cycles in K_n: 3 per 4-set; 5-cycles: 12 per 5-set
+    assert oracle.pattern_count(off, adj, 4, P["4-cycle"][1], False)[0] == 3 * math.comb(9, 4)
+    assert oracle.pattern_count(off, adj, 5, P["5-cycle"][1], False)[0] == 12 * math.comb(9, 5)
+    # any induced non-clique pattern is absent from a clique
+    assert oracle.pattern_count(off, adj, 5, P["house"][1], True)[0] == 0
+    # edge-induced stars and wedges: sum over centres of C(d, leaves)
+    g = graphgen.erdos_renyi(120, 0.08, 5)
+    off, adj = csr(g)
+    deg = np.diff(off)
+    assert oracle.pattern_count(off, adj, 3, P["wedge"][1], False)[0] == \
+        sum(math.comb(int(x), 2) for x in deg)
+    assert oracle.pattern_count(off, adj, 5, P["4-star"][1], False)[0] == \
+        sum(math.comb(int(x), 4) for x in deg)
+    # automorphism counts
+    assert oracle.pattern_count(off, adj, 5, P["5-cycle"][1], False)[1] == 10
+    assert oracle.pattern_count(off, adj, 5, P["house"][1], False)[1] == 2
+
+
+def test_pattern_count_matches_other_routes():
+    """Vertex-induced 4-patterns equal the 4-motif counts (back-substitution
+    route); edge-induced diamond and 4-cycle equal the listing totals."""
+    g = graphgen.erdos_renyi(70, 0.15, 9)
+    off, adj = csr(g)
+    want = oracle.motif4(off, adj)
+    for i, name in enumerate(oracle.MOTIF4_NAMES):
+        assert oracle.pattern_count(off, adj, 4, brute.PATTERNS4[name], True)[0] == want[i], name
+    assert oracle.pattern_count(off, adj, 4, brute.PATTERNS4["diamond"], False)[0] == \
+        oracle.list_diamonds(off, adj)[0]
+    assert oracle.pattern_count(off, adj, 4, brute.PATTERNS4["4-cycle"], False)[0] == \
+        oracle.list_c4(off, adj)[0]
