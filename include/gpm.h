@@ -95,9 +95,14 @@ gpm_status gpm_pattern_clique(int32_t k, uint32_t flags, gpm_pattern *out);
 /* Plan chosen for a pattern (Section 4.3 enablement rules: orientation
  * iff the pattern is a clique, |E| = |V|(|V|-1)/2 (Appendix B.2); a
  * matching order with partial orders for other single explicit patterns). */
-#define GPM_PLAN_CLIQUE_DAG     1   /* triangles and k-cliques, k <= 5 */
+#define GPM_PLAN_CLIQUE_DAG     1   /* triangles and k-cliques, k <= 8 */
 #define GPM_PLAN_SL_DIAMOND     2   /* edge-induced diamond listing/counting */
 #define GPM_PLAN_SL_4CYCLE      3   /* edge-induced 4-cycle listing/counting */
+/* Any other connected pattern of 2..6 vertices, vertex- or edge-induced:
+ * counting only (gpm_list returns GPM_UNSUPPORTED).  A matching order with
+ * partial orders derived from the pattern's automorphisms (Appendix B.1);
+ * one wave per root vertex searches depth first. */
+#define GPM_PLAN_GENERIC        4
 /* Returns the plan for (graph-independent) pattern p, or GPM_UNSUPPORTED. */
 gpm_status gpm_pattern_plan(const gpm_pattern *p, int32_t *plan);
 

@@ -28,6 +28,9 @@ gpm_status motif_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes)
 gpm_status motif_run(const gpm_graph *g, int32_t k, void *ws, uint64_t ws_bytes,
                      unsigned long long *d_counts, hipStream_t st);
 gpm_status sl_workspace_bytes(const gpm_graph *g, int32_t plan, bool list, uint64_t *bytes);
+bool generic_pattern_ok(const gpm_pattern *p);
+gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, unsigned long long *out,
+                         hipStream_t st);
 gpm_status sl_run(const gpm_graph *g, int32_t plan, bool list, void *ws, uint64_t ws_bytes,
                   unsigned long long *d_count, int32_t *d_buf, uint64_t cap,
                   unsigned long long *d_result, hipStream_t st);
@@ -156,6 +159,20 @@ gpm_status gpm_pattern_clique(int32_t k, uint32_t flags, gpm_pattern *out) {
 gpm_status gpm_pattern_plan(const gpm_pattern *p, int32_t *plan) {
     if (!p || !plan) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
     const int32_t k = p->k, ne = p->n_edges;
+    // the struct may come from the caller directly: check it as
+    // gpm_pattern_from_edges would before reading its edges
+    if (k < 2 || k > GPM_MAX_PATTERN_VERTICES || ne < k - 1 || ne > k * (k - 1) / 2)
+        return fail(GPM_INVALID_ARGUMENT, "pattern size or edge count out of range");
+    uint64_t seen = 0;
+    for (int32_t i = 0; i < ne; i++) {
+        const int32_t a = p->edges[i][0], b = p->edges[i][1];
+        if (a < 0 || b < 0 || a >= k || b >= k || a == b)
+            return fail(GPM_INVALID_ARGUMENT, "pattern edge endpoint out of range or a loop");
+        const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
+        const uint64_t bit = 1ull << (lo * GPM_MAX_PATTERN_VERTICES + hi);
+        if (seen & bit) return fail(GPM_INVALID_ARGUMENT, "repeated pattern edge");
+        seen |= bit;
+    }
     const bool vertex_induced = (p->flags & GPM_VERTEX_INDUCED) != 0;
     // Orientation iff the pattern is a clique, |E| = |V|(|V|-1)/2; for a
     // clique, vertex- and edge-induced embeddings coincide.
@@ -175,8 +192,9 @@ gpm_status gpm_pattern_plan(const gpm_pattern *p, int32_t *plan) {
         if (ne == 5 && deg3 == 2 && deg2 == 2) { *plan = GPM_PLAN_SL_DIAMOND; return GPM_OK; }
         if (ne == 4 && deg2 == 4) { *plan = GPM_PLAN_SL_4CYCLE; return GPM_OK; }
     }
-    return fail(GPM_UNSUPPORTED,
-                "implemented patterns: k-cliques (3..8), edge-induced diamond and 4-cycle");
+    if (!gpm::generic_pattern_ok(p)) return GPM_UNSUPPORTED;   // error text set by the check
+    *plan = GPM_PLAN_GENERIC;
+    return GPM_OK;
 }
 
 gpm_status gpm_graph_build_bytes(int32_t n, int64_t n_input_edges, uint64_t *graph_bytes,
@@ -233,6 +251,11 @@ gpm_status gpm_workspace_bytes(const gpm_graph *g, const gpm_pattern *p, uint64_
     if (rc) return rc;
     const bool list = (p->flags & GPM_LIST) != 0;
     if (plan == GPM_PLAN_CLIQUE_DAG) return gpm::clique_workspace_bytes(g, p->k, list, bytes);
+    if (plan == GPM_PLAN_GENERIC) {
+        if (list) return fail(GPM_UNSUPPORTED, "listing of general patterns is not implemented");
+        *bytes = 256;   // no workspace; the argument must still be a valid buffer
+        return GPM_OK;
+    }
     return gpm::sl_workspace_bytes(g, plan, list, bytes);
 }
 
@@ -250,6 +273,7 @@ gpm_status gpm_count(const gpm_graph *g, const gpm_pattern *p, void *d_ws, uint6
     unsigned long long *out = reinterpret_cast<unsigned long long *>(d_count);
     if (plan == GPM_PLAN_CLIQUE_DAG)
         return gpm::clique_run(g, p->k, false, d_ws, ws_bytes, out, nullptr, 0, nullptr, st);
+    if (plan == GPM_PLAN_GENERIC) return gpm::generic_count(g, p, out, st);
     return gpm::sl_run(g, plan, false, d_ws, ws_bytes, out, nullptr, 0, nullptr, st);
 }
 
@@ -268,6 +292,8 @@ gpm_status gpm_list(const gpm_graph *g, const gpm_pattern *p, void *d_ws, uint64
     unsigned long long *res = reinterpret_cast<unsigned long long *>(d_result);
     if (plan == GPM_PLAN_CLIQUE_DAG)
         return gpm::clique_run(g, p->k, true, d_ws, ws_bytes, nullptr, d_buf, cap, res, st);
+    if (plan == GPM_PLAN_GENERIC)
+        return fail(GPM_UNSUPPORTED, "listing of general patterns is not implemented");
     return gpm::sl_run(g, plan, true, d_ws, ws_bytes, nullptr, d_buf, cap, res, st);
 }
 

@@ -1,0 +1,297 @@
+// Counting any connected pattern of up to 6 vertices, vertex- or
+// edge-induced (Section 2 problem statement: subgraph listing counts
+// edge-induced embeddings, motif counting vertex-induced ones), for the
+// patterns the specialised plans do not cover.
+//
+// Plan (host).  A matching order that keeps every step after the first
+// adjacent to an earlier one (greedy: most pattern edges back to the steps
+// placed so far, then highest degree), and symmetry-breaking partial orders
+// taken from the pattern's automorphism group (Appendix B.1 leaves them to
+// the implementation): while the group is not trivial, the first step whose
+// vertex v has a non-trivial orbit gets f(v) < f(u) for every other u of
+// the orbit, and the group shrinks to v's stabiliser.  Each embedding is
+// then matched exactly once.
+//
+// Kernel.  A wave per root vertex (step 0) runs the depth-first search with
+// a per-wave stack in LDS.  At step s the candidates are a row of the
+// symmetric CSR: that of the already matched backward neighbour with the
+// fewest entries, cut by binary search to the range the partial orders
+// allow.  Lanes test 64 candidates at a time against the other backward
+// neighbours (binary search in their sorted rows), the non-neighbours when
+// vertex-induced, and distinctness; the survivors are a lane mask.  At the
+// last step the mask's population count is the count; otherwise the wave
+// descends into its candidates one by one.
+#include <algorithm>
+#include <vector>
+
+#include "gpm_internal.h"
+
+namespace gpm {
+
+namespace {
+
+constexpr int kGenMaxK = 6;
+constexpr int kGenNT = 256;   // 4 waves per workgroup, one root each
+
+struct GenPlan {
+    int32_t k;
+    int32_t induced;
+    uint32_t back_adj[kGenMaxK];   // earlier steps adjacent to step s in the pattern
+    uint32_t back_non[kGenMaxK];   // earlier steps not adjacent to step s
+    uint32_t above[kGenMaxK];      // earlier steps t with f(s) > f(t) required
+    uint32_t below[kGenMaxK];      // earlier steps t with f(s) < f(t) required
+};
+
+// Orders a wave's LDS writes before its later reads (lanes of one wave).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ bool row_has(const int32_t *__restrict__ off,
+                                        const int32_t *__restrict__ adj, int32_t u, int32_t v) {
+    int32_t lo = off[u], hi = off[u + 1];
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (adj[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo < off[u + 1] && adj[lo] == v;
+}
+
+// First index in [lo, hi) of the sorted row segment with adj[i] >= x.
+__device__ __forceinline__ int32_t lower_idx(const int32_t *__restrict__ adj, int32_t lo,
+                                             int32_t hi, int32_t x) {
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (adj[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+struct GenWave {
+    int32_t m[kGenMaxK];           // matched vertex per step
+    int32_t pos[kGenMaxK], end[kGenMaxK], pivot[kGenMaxK];
+    uint64_t mask[kGenMaxK];       // candidates of the current chunk not yet descended into
+    int32_t cand[kGenMaxK][kWave];
+};
+
+__global__ void __launch_bounds__(kGenNT) k_generic(const int32_t *__restrict__ off,
+                                                    const int32_t *__restrict__ adj, int32_t n,
+                                                    GenPlan P, unsigned long long *result) {
+    __shared__ GenWave sw[kGenNT / kWave];
+    const int lane = lane_id(), wib = threadIdx.x / kWave;
+    GenWave &S = sw[wib];
+    const int64_t wave0 = (int64_t)blockIdx.x * (kGenNT / kWave) + wib;
+    const int64_t nwaves = (int64_t)gridDim.x * (kGenNT / kWave);
+    const int32_t last = P.k - 1;
+    uint64_t count = 0;   // wave-uniform
+    // candidates of step s: the allowed range of the smallest backward row
+    auto open_step = [&](int32_t s) {
+        int32_t best = -1, best_len = 0;
+        for (int t = 0; t < s; t++) {
+            if (!((P.back_adj[s] >> t) & 1u)) continue;
+            const int32_t mt = S.m[t];
+            const int32_t len = off[mt + 1] - off[mt];
+            if (best < 0 || len < best_len) {
+                best = t;
+                best_len = len;
+            }
+        }
+        const int32_t mp = S.m[best];
+        int32_t lo = off[mp], hi = off[mp + 1];
+        for (int t = 0; t < s; t++) {
+            if ((P.above[s] >> t) & 1u) lo = lower_idx(adj, lo, hi, S.m[t] + 1);
+            if ((P.below[s] >> t) & 1u) hi = lower_idx(adj, lo, hi, S.m[t]);
+        }
+        if (lane == 0) {
+            S.pivot[s] = best;
+            S.pos[s] = lo;
+            S.end[s] = max(lo, hi);
+            S.mask[s] = 0ull;
+        }
+        wave_sync();
+    };
+    for (int64_t root = wave0; root < n; root += nwaves) {
+        if (lane == 0) S.m[0] = (int32_t)root;
+        wave_sync();
+        open_step(1);
+        int32_t s = 1;
+        while (s >= 1) {
+            uint64_t msk = S.mask[s];
+            if (msk == 0ull) {
+                const int32_t p = S.pos[s], e = S.end[s];
+                if (p >= e) {
+                    s--;
+                    continue;
+                }
+                const int32_t i = p + lane;
+                const int32_t v = i < e ? adj[i] : -1;
+                bool ok = i < e;
+                const int32_t piv = S.pivot[s];
+                for (int t = 0; t < s && ok; t++) {
+                    if (t == piv) continue;
+                    const int32_t mt = S.m[t];
+                    if (v == mt) {
+                        ok = false;
+                        break;
+                    }
+                    if ((P.back_adj[s] >> t) & 1u) ok = row_has(off, adj, mt, v);
+                    else if (P.induced && ((P.back_non[s] >> t) & 1u)) ok = !row_has(off, adj, mt, v);
+                }
+                msk = __ballot(ok);
+                wave_sync();
+                if (lane == 0) S.pos[s] = p + kWave;
+                if (s == last) {
+                    count += (uint64_t)__popcll(msk);
+                    wave_sync();
+                    continue;
+                }
+                S.cand[s][lane] = v;
+                if (lane == 0) S.mask[s] = msk;
+                wave_sync();
+                if (msk == 0ull) continue;
+            }
+            // descend into the next candidate of step s
+            const int c = __builtin_ctzll(msk);
+            if (lane == 0) {
+                S.mask[s] = msk & (msk - 1ull);
+                S.m[s] = S.cand[s][c];
+            }
+            wave_sync();
+            s++;
+            open_step(s);
+        }
+        wave_sync();
+    }
+    if (lane == 0 && count) atomicAdd(result, (unsigned long long)count);
+}
+
+// ------------------------------------------------------------ planning --
+
+bool connected(int k, const bool (&a)[8][8]) {
+    int seen = 1, stack[8], sp = 0;
+    stack[sp++] = 0;
+    while (sp) {
+        const int x = stack[--sp];
+        for (int y = 0; y < k; y++)
+            if (a[x][y] && !((seen >> y) & 1)) {
+                seen |= 1 << y;
+                stack[sp++] = y;
+            }
+    }
+    return seen == (1 << k) - 1;
+}
+
+gpm_status make_plan(const gpm_pattern *p, GenPlan &P) {
+    const int k = p->k;
+    if (k < 2 || k > kGenMaxK)
+        return fail(GPM_UNSUPPORTED, "general patterns: 2 to 6 vertices");
+    if (p->n_edges < k - 1 || p->n_edges > k * (k - 1) / 2)
+        return fail(GPM_INVALID_ARGUMENT, "edge count impossible for a connected pattern");
+    bool a[8][8] = {};
+    int deg[8] = {};
+    for (int i = 0; i < p->n_edges; i++) {
+        const int x = p->edges[i][0], y = p->edges[i][1];
+        if (x < 0 || y < 0 || x >= k || y >= k || x == y)
+            return fail(GPM_INVALID_ARGUMENT, "pattern edge endpoint out of range or a loop");
+        a[x][y] = a[y][x] = true;
+    }
+    for (int x = 0; x < k; x++)
+        for (int y = 0; y < k; y++) deg[x] += a[x][y];
+    if (!connected(k, a)) return fail(GPM_UNSUPPORTED, "the pattern is not connected");
+    // matching order: highest degree first, then most edges back to the
+    // placed vertices (ties: higher degree, then lower id)
+    int order[8], pos[8];
+    bool placed[8] = {};
+    for (int s = 0; s < k; s++) {
+        int best = -1, best_back = -1;
+        for (int x = 0; x < k; x++) {
+            if (placed[x]) continue;
+            int back = 0;
+            for (int t = 0; t < s; t++) back += a[x][order[t]];
+            if (s > 0 && back == 0) continue;
+            if (back > best_back || (back == best_back && deg[x] > deg[best])) {
+                best = x;
+                best_back = back;
+            }
+        }
+        order[s] = best;
+        pos[best] = s;
+        placed[best] = true;
+    }
+    // automorphisms, as maps on pattern vertices
+    std::vector<std::vector<int>> group;
+    std::vector<int> perm(k);
+    for (int i = 0; i < k; i++) perm[i] = i;
+    do {
+        bool ok = true;
+        for (int x = 0; x < k && ok; x++)
+            for (int y = 0; y < k; y++)
+                if (a[x][y] != a[perm[x]][perm[y]]) {
+                    ok = false;
+                    break;
+                }
+        if (ok) group.push_back(perm);
+    } while (std::next_permutation(perm.begin(), perm.end()));
+    P = GenPlan{};
+    P.k = k;
+    P.induced = (p->flags & GPM_VERTEX_INDUCED) != 0;
+    // partial orders from the stabiliser chain, taken in matching order
+    while (group.size() > 1) {
+        int v = -1;
+        std::vector<int> orbit;
+        for (int s = 0; s < k && v < 0; s++) {
+            const int x = order[s];
+            std::vector<int> o;
+            for (auto &g : group)
+                if (std::find(o.begin(), o.end(), g[x]) == o.end()) o.push_back(g[x]);
+            if (o.size() > 1) {
+                v = x;
+                orbit = o;
+            }
+        }
+        for (int u : orbit) {
+            if (u == v) continue;
+            // f(v) < f(u), checked at the later of the two steps
+            if (pos[u] > pos[v]) P.above[pos[u]] |= 1u << pos[v];
+            else P.below[pos[v]] |= 1u << pos[u];
+        }
+        std::vector<std::vector<int>> stab;
+        for (auto &g : group)
+            if (g[v] == v) stab.push_back(g);
+        group.swap(stab);
+    }
+    for (int s = 0; s < k; s++)
+        for (int t = 0; t < s; t++) {
+            if (a[order[s]][order[t]]) P.back_adj[s] |= 1u << t;
+            else P.back_non[s] |= 1u << t;
+        }
+    return GPM_OK;
+}
+
+}  // namespace
+
+bool generic_pattern_ok(const gpm_pattern *p) {
+    GenPlan P;
+    return make_plan(p, P) == GPM_OK;
+}
+
+gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, unsigned long long *out,
+                         hipStream_t st) {
+    GenPlan P;
+    gpm_status rc = make_plan(p, P);
+    if (rc) return rc;
+    GPM_HIP(fill_u32(reinterpret_cast<uint32_t *>(out), 0, 2, st));
+    if (g->n == 0) return GPM_OK;
+    Span sp("k_generic", st);
+    // a wave per root, as many as fit (grid-stride beyond that)
+    const unsigned blocks = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>(((int64_t)g->n + kGenNT / kWave - 1) / (kGenNT / kWave),
+                             (int64_t)cu_count() * 8));
+    hipLaunchKernelGGL(k_generic, dim3(blocks), dim3(kGenNT), 0, st, g->off, g->adj, g->n, P, out);
+    GPM_LAUNCH_CHECK("k_generic");
+    return GPM_OK;
+}
+
+}  // namespace gpm

@@ -49,10 +49,23 @@ def test_patterns_and_plans():
     # the triangle given as an edge list is a clique (orientation applies)
     p = gpm.pattern(3, [(0, 1), (0, 2), (1, 2)], gpm.VERTEX_INDUCED)
     assert load().gpm_pattern_plan(ctypes.byref(p), ctypes.byref(plan)) == 0 and plan.value == 1
-    # a vertex-induced diamond, a 4-path: not planned
-    for pat in (gpm.diamond(gpm.VERTEX_INDUCED), gpm.pattern(4, [(0, 1), (1, 2), (2, 3)],
-                                                              gpm.EDGE_INDUCED)):
-        assert load().gpm_pattern_plan(ctypes.byref(pat), ctypes.byref(plan)) == 5
+    # a vertex-induced diamond, a 4-path, a house: the general plan
+    house = [(0, 1), (1, 2), (2, 3), (3, 0), (2, 4), (3, 4)]
+    for pat in (gpm.diamond(gpm.VERTEX_INDUCED),
+                gpm.pattern(4, [(0, 1), (1, 2), (2, 3)], gpm.EDGE_INDUCED),
+                gpm.pattern(5, house, gpm.VERTEX_INDUCED)):
+        assert load().gpm_pattern_plan(ctypes.byref(pat), ctypes.byref(plan)) == 0
+        assert plan.value == 4
+    # 7 vertices: beyond the general plan
+    pat = gpm.pattern(7, [(i, i + 1) for i in range(6)], gpm.EDGE_INDUCED)
+    assert load().gpm_pattern_plan(ctypes.byref(pat), ctypes.byref(plan)) == 5
+    # a structurally invalid pattern handed in directly is rejected, not planned
+    bad = Pattern()
+    bad.k, bad.n_edges = 4, 3
+    for i, (a, b) in enumerate([(0, 1), (1, 2), (2, 9)]):
+        bad.edges[i][0], bad.edges[i][1] = a, b
+    bad.flags = gpm.EDGE_INDUCED
+    assert load().gpm_pattern_plan(ctypes.byref(bad), ctypes.byref(plan)) != 0
     with pytest.raises(GpmError):
         gpm.pattern(4, [(0, 1), (2, 3)], gpm.EDGE_INDUCED)            # disconnected
     with pytest.raises(GpmError):

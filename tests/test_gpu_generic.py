@@ -1,0 +1,103 @@
+"""General connected patterns (2..6 vertices, vertex- or edge-induced)
+counted on the device against the oracle's plain enumeration."""
+import numpy as np
+import pytest
+
+import brute
+import graphgen
+import oracle
+from gpu_util import build
+
+pytestmark = pytest.mark.gpu
+
+EXTRA = {
+    "edge": (2, [(0, 1)]),
+    "6-cycle": (6, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5), (5, 0)]),
+    "domino": (6, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5), (5, 0), (1, 4)]),
+    "6-path": (6, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5)]),
+    "tadpole": (6, [(0, 1), (1, 2), (2, 0), (2, 3), (3, 4), (4, 5)]),
+}
+PATTERNS = {**brute.PATTERNS_ANY, **EXTRA}
+
+
+@pytest.fixture(scope="module")
+def gpm():
+    import paper_2011_03135_amd as m
+    m.load()
+    return m
+
+
+def hub_graph():
+    """ER(100, 0.06) plus a hub joined to 45 vertices: skewed degrees that
+    the oracle's plain enumeration still finishes in seconds."""
+    base = graphgen.erdos_renyi(100, 0.06, 3)
+    rng = np.random.default_rng(3)
+    ends = rng.choice(np.arange(1, 100), size=45, replace=False).astype(np.int32)
+    u = np.concatenate([base.u, np.zeros(45, np.int32)])
+    v = np.concatenate([base.v, ends])
+    return graphgen.EdgeList(100, u, v, "hub")
+
+
+def graphs():
+    return [graphgen.erdos_renyi(80, 0.1, 1),
+            graphgen.erdos_renyi(150, 0.05, 2),
+            hub_graph(),
+            graphgen.complete_graph(9),
+            graphgen.star_graph(40)]
+
+
+@pytest.mark.parametrize("gi", range(5))
+@pytest.mark.parametrize("induced", [False, True])
+def test_patterns_vs_oracle(gpm, gi, induced):
+    e = graphs()[gi]
+    print(f"graph {gi} n={e.n} induced={induced}", flush=True)
+    g = build(gpm, e)
+    off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+    flags = gpm.VERTEX_INDUCED if induced else gpm.EDGE_INDUCED
+    for name, (k, edges) in PATTERNS.items():
+        want, _ = oracle.pattern_count(off, adj, k, edges, induced)
+        got = gpm.count(g, gpm.pattern(k, edges, flags))
+        assert got == want, (name, induced)
+
+
+def test_relabelled_pattern_same_count(gpm):
+    """The same pattern under another vertex numbering (another matching
+    order and other partial orders) gives the same count."""
+    e = graphgen.erdos_renyi(120, 0.07, 4)
+    g = build(gpm, e)
+    house = [(0, 1), (1, 2), (2, 3), (3, 0), (2, 4), (3, 4)]
+    perm = [3, 0, 4, 1, 2]
+    relabel = [(perm[a], perm[b]) for a, b in house]
+    for flags in (gpm.EDGE_INDUCED, gpm.VERTEX_INDUCED):
+        assert gpm.count(g, gpm.pattern(5, house, flags)) == \
+            gpm.count(g, gpm.pattern(5, relabel, flags))
+
+
+def test_generic_closed_forms_rmat(gpm):
+    """Properties that hold at any size: edge-induced wedges and 3-stars are
+    sums of binomials of the degrees; vertex-induced 4-paths and 4-cycles
+    equal the 4-motif counts of the local-count route."""
+    e = graphgen.rmat(11, seed=7)
+    g = build(gpm, e)
+    off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+    deg = np.diff(off).astype(object)
+    P = brute.PATTERNS_ANY
+    assert gpm.count(g, gpm.pattern(3, P["wedge"][1], gpm.EDGE_INDUCED)) == \
+        sum(d * (d - 1) // 2 for d in deg)
+    assert gpm.count(g, gpm.pattern(4, P["3-star"][1], gpm.EDGE_INDUCED)) == \
+        sum(d * (d - 1) * (d - 2) // 6 for d in deg)
+    motifs = gpm.motif_count(g, 4)
+    names = list(gpm.MOTIF4_NAMES)
+    for name in ("4-path", "4-cycle", "tailed-triangle"):
+        got = gpm.count(g, gpm.pattern(4, P[name][1], gpm.VERTEX_INDUCED))
+        assert got == motifs[names.index(name)], name
+
+
+def test_generic_errors(gpm):
+    e = graphgen.erdos_renyi(30, 0.2, 5)
+    g = build(gpm, e)
+    house = [(0, 1), (1, 2), (2, 3), (3, 0), (2, 4), (3, 4)]
+    with pytest.raises(gpm.GpmError):
+        gpm.list_embeddings(g, gpm.pattern(5, house, gpm.EDGE_INDUCED | gpm.LIST), 16)
+    with pytest.raises(gpm.GpmError):
+        gpm.count(g, gpm.pattern(7, [(i, i + 1) for i in range(6)], gpm.EDGE_INDUCED))
