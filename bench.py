@@ -244,6 +244,35 @@ def serve_leg(gpm, torch, g20, scale, requests, warmup):
     return stats
 
 
+def generic_leg(gpm, torch, scale, reps=3):
+    """The general-pattern plan on one pattern whose count the local-count
+    route also gives: the vertex-induced 4-cycle on RMAT-`scale`."""
+    import graphgen
+    e = graphgen.rmat(scale, seed=scale)
+    g = gpm.Graph.build(e.n, torch.from_numpy(e.u).cuda(), torch.from_numpy(e.v).cuda())
+    c4 = gpm.pattern(4, [(0, 1), (1, 2), (2, 3), (3, 0)], gpm.VERTEX_INDUCED)
+    got = gpm.count(g, c4)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        got = gpm.count(g, c4)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    mc = gpm.motif_count(g, 4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mc = gpm.motif_count(g, 4)
+    torch.cuda.synchronize()
+    lc_ms = (time.perf_counter() - t0) * 1e3 / reps
+    return {"workload": f"rmat{scale}: vertex-induced 4-cycle, general plan (k_generic) "
+                        f"vs the 4-motif local-count route",
+            "count": got, "equals_motif_count": got == mc[2], "ms": ms,
+            "matches_per_sec": got / (ms * 1e-3), "m": g.m,
+            "edges_per_sec": g.m / (ms * 1e-3), "lc_route_ms_all_six_motifs": lc_ms,
+            "lc_route_speedup": ms / lc_ms}
+
+
 def copy_calibration():
     import torch
     n = 1 << 30
@@ -271,6 +300,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--serve-warmup", type=int, default=500)
+    ap.add_argument("--no-generic", action="store_true")
+    ap.add_argument("--generic-only", action="store_true",
+                    help="time only the general-pattern leg (for kernel traces) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device three times (reference kernel "
                          "for scaling hardware byte counters) and exit")
@@ -291,6 +323,9 @@ def main():
     gpm.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.generic_only:
+        print(json.dumps({"generic_pattern": generic_leg(gpm, torch, 14)}))
+        return
     e = graphgen.rmat(args.scale, seed=args.scale)
     u = torch.from_numpy(e.u).to(dev)
     v = torch.from_numpy(e.v).to(dev)
@@ -402,6 +437,9 @@ def main():
     }
     if not args.no_batch:
         res["batched_vs_plain"] = batch_leg(gpm, torch, args.batch_graphs, args.plain_graphs, 20)
+    if not args.no_generic:
+        log("general pattern")
+        res["generic_pattern"] = generic_leg(gpm, torch, 14)
     if not args.no_serve:
         log("serving load")
         g_res = gpm.Graph.build(e.n, u, v)
