@@ -12,8 +12,10 @@
 // the orbit, and the group shrinks to v's stabiliser.  Each embedding is
 // then matched exactly once.
 //
-// Kernel.  A wave per root vertex (step 0) runs the depth-first search with
-// a per-wave stack in LDS.  At step s the candidates are a row of the
+// Kernel.  Waves take the arcs of the symmetric CSR 64 at a time (steps 0
+// and 1, one arc per lane, so a hub's search is spread over its arcs) and
+// run the depth-first search below each surviving arc with a per-wave stack
+// in LDS.  At step s >= 2 the candidates are a row of the
 // symmetric CSR: that of the already matched backward neighbour with the
 // fewest entries, cut by binary search to the range the partial orders
 // allow.  Lanes test 64 candidates at a time against the other backward
@@ -112,57 +114,90 @@ __global__ void __launch_bounds__(kGenNT) k_generic(const int32_t *__restrict__ 
         }
         wave_sync();
     };
-    for (int64_t root = wave0; root < n; root += nwaves) {
-        if (lane == 0) S.m[0] = (int32_t)root;
-        wave_sync();
-        open_step(1);
-        int32_t s = 1;
-        while (s >= 1) {
-            uint64_t msk = S.mask[s];
-            if (msk == 0ull) {
-                const int32_t p = S.pos[s], e = S.end[s];
-                if (p >= e) {
-                    s--;
-                    continue;
-                }
-                const int32_t i = p + lane;
-                const int32_t v = i < e ? adj[i] : -1;
-                bool ok = i < e;
-                const int32_t piv = S.pivot[s];
-                for (int t = 0; t < s && ok; t++) {
-                    if (t == piv) continue;
-                    const int32_t mt = S.m[t];
-                    if (v == mt) {
-                        ok = false;
-                        break;
-                    }
-                    if ((P.back_adj[s] >> t) & 1u) ok = row_has(off, adj, mt, v);
-                    else if (P.induced && ((P.back_non[s] >> t) & 1u)) ok = !row_has(off, adj, mt, v);
-                }
-                msk = __ballot(ok);
-                wave_sync();
-                if (lane == 0) S.pos[s] = p + kWave;
-                if (s == last) {
-                    count += (uint64_t)__popcll(msk);
-                    wave_sync();
-                    continue;
-                }
-                S.cand[s][lane] = v;
-                if (lane == 0) S.mask[s] = msk;
-                wave_sync();
-                if (msk == 0ull) continue;
+    // steps 0 and 1 come from the arcs of the symmetric CSR, 64 per wave
+    // and step (one per lane), so a hub's search is spread over its arcs
+    // rather than left to one wave
+    const int32_t narcs = off[n];
+    for (int64_t c0 = wave0 * kWave; c0 < narcs; c0 += nwaves * kWave) {
+        const int64_t a = c0 + lane;
+        bool arc_ok = a < narcs;
+        int32_t r = 0, v1 = 0;
+        if (arc_ok) {
+            int32_t lo = 0, hi = n;   // the row of arc a: last r with off[r] <= a
+            while (hi - lo > 1) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (off[mid] <= a) lo = mid; else hi = mid;
             }
-            // descend into the next candidate of step s
-            const int c = __builtin_ctzll(msk);
+            r = lo;
+            v1 = adj[a];
+            if ((P.above[1] & 1u) && v1 < r) arc_ok = false;
+            if ((P.below[1] & 1u) && v1 > r) arc_ok = false;
+        }
+        uint64_t amask = __ballot(arc_ok);
+        if (last == 1) {
+            count += (uint64_t)__popcll(amask);
+            continue;
+        }
+        S.cand[0][lane] = r;
+        S.cand[1][lane] = v1;
+        wave_sync();
+        while (amask) {
+            const int ca = __builtin_ctzll(amask);
+            amask &= amask - 1ull;
             if (lane == 0) {
-                S.mask[s] = msk & (msk - 1ull);
-                S.m[s] = S.cand[s][c];
+                S.m[0] = S.cand[0][ca];
+                S.m[1] = S.cand[1][ca];
             }
             wave_sync();
-            s++;
-            open_step(s);
+            open_step(2);
+            int32_t s = 2;
+            while (s >= 2) {
+                uint64_t msk = S.mask[s];
+                if (msk == 0ull) {
+                    const int32_t p = S.pos[s], e = S.end[s];
+                    if (p >= e) {
+                        s--;
+                        continue;
+                    }
+                    const int32_t i = p + lane;
+                    const int32_t v = i < e ? adj[i] : -1;
+                    bool ok = i < e;
+                    const int32_t piv = S.pivot[s];
+                    for (int t = 0; t < s && ok; t++) {
+                        if (t == piv) continue;
+                        const int32_t mt = S.m[t];
+                        if (v == mt) {
+                            ok = false;
+                            break;
+                        }
+                        if ((P.back_adj[s] >> t) & 1u) ok = row_has(off, adj, mt, v);
+                        else if (P.induced && ((P.back_non[s] >> t) & 1u)) ok = !row_has(off, adj, mt, v);
+                    }
+                    msk = __ballot(ok);
+                    wave_sync();
+                    if (lane == 0) S.pos[s] = p + kWave;
+                    if (s == last) {
+                        count += (uint64_t)__popcll(msk);
+                        wave_sync();
+                        continue;
+                    }
+                    S.cand[s][lane] = v;
+                    if (lane == 0) S.mask[s] = msk;
+                    wave_sync();
+                    if (msk == 0ull) continue;
+                }
+                // descend into the next candidate of step s
+                const int c = __builtin_ctzll(msk);
+                if (lane == 0) {
+                    S.mask[s] = msk & (msk - 1ull);
+                    S.m[s] = S.cand[s][c];
+                }
+                wave_sync();
+                s++;
+                open_step(s);
+            }
+            wave_sync();
         }
-        wave_sync();
     }
     if (lane == 0 && count) atomicAdd(result, (unsigned long long)count);
 }
@@ -285,9 +320,10 @@ gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, unsigned long
     GPM_HIP(fill_u32(reinterpret_cast<uint32_t *>(out), 0, 2, st));
     if (g->n == 0) return GPM_OK;
     Span sp("k_generic", st);
-    // a wave per root, as many as fit (grid-stride beyond that)
+    // a wave per 64 arcs, as many as fit (grid-stride beyond that)
+    const int64_t chunks = (2 * g->m + kWave - 1) / kWave;
     const unsigned blocks = (unsigned)std::max<int64_t>(
-        1, std::min<int64_t>(((int64_t)g->n + kGenNT / kWave - 1) / (kGenNT / kWave),
+        1, std::min<int64_t>((chunks + kGenNT / kWave - 1) / (kGenNT / kWave),
                              (int64_t)cu_count() * 8));
     hipLaunchKernelGGL(k_generic, dim3(blocks), dim3(kGenNT), 0, st, g->off, g->adj, g->n, P, out);
     GPM_LAUNCH_CHECK("k_generic");
