@@ -13,6 +13,8 @@
  *   - k-motif counting for k = 3, 4, vertex-induced, connected patterns only
  *     (problem 4), by local counting (Section 5, the wedge equation; the
  *     3-motif and 4-motif local-counting listings of Appendix A);
+ *   - k-motif counting for k = 3, 4, 5 by pattern-oblivious enumeration
+ *     (Section 4: vertex extension, connectivity codes);
  *   - the same motif counts for a batch of small graphs in one launch.
  *
  * Conventions shared by every entry point.
@@ -101,7 +103,8 @@ gpm_status gpm_pattern_clique(int32_t k, uint32_t flags, gpm_pattern *out);
 /* Any other connected pattern of 2..6 vertices, vertex- or edge-induced:
  * counting only (gpm_list returns GPM_UNSUPPORTED).  A matching order with
  * partial orders derived from the pattern's automorphisms (Appendix B.1);
- * one wave per root vertex searches depth first. */
+ * waves take the graph's arcs 64 at a time and search depth first below
+ * each. */
 #define GPM_PLAN_GENERIC        4
 /* Returns the plan for (graph-independent) pattern p, or GPM_UNSUPPORTED. */
 gpm_status gpm_pattern_plan(const gpm_pattern *p, int32_t *plan);
@@ -226,6 +229,33 @@ gpm_status gpm_motif_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *by
  * held and every count fit in 64 bits, nonzero otherwise. */
 gpm_status gpm_motif_count(const gpm_graph *g, int32_t k, void *d_ws, uint64_t ws_bytes,
                            uint64_t *d_counts, void *stream);
+
+/* Pattern-oblivious motif counting (Section 4, high-level Sandslash: vertex
+ * extension of canonical embeddings with memoised connectivity codes, each
+ * finished embedding classified by its code; Section 2 problem 4).  Every
+ * connected vertex-induced k-vertex subgraph is enumerated once, so the
+ * cost grows with their number: this is the route without the
+ * local-counting formulas, for k = 3, 4 (the same values as
+ * gpm_motif_count) and for k = 5, which has no formula route here.
+ *
+ * gpm_motif_classes(k): the number of motif classes, 2, 6 or 21 for
+ * k = 3, 4, 5 (0 otherwise).  gpm_motif_class_pattern(k, i, out): the
+ * pattern of class i (vertex-induced flag set).  Classes of k = 3 and 4 are
+ * in gpm_motif_count's order; those of k = 5 are ordered by edge count, then
+ * by the canonical code (the smallest, over vertex orders, of the number
+ * whose bit l(l-1)/2 + j is set iff pattern vertices j < l are adjacent).
+ * Host only; GPM_UNSUPPORTED for k outside [3, 5], GPM_INVALID_ARGUMENT for
+ * i outside [0, classes). */
+int32_t gpm_motif_classes(int32_t k);
+gpm_status gpm_motif_class_pattern(int32_t k, int32_t index, gpm_pattern *out);
+
+/* Workspace needed by gpm_motif_count_enum(g, k): 12 bytes per arc of the
+ * symmetric CSR plus a little (the work-unit numbering). */
+gpm_status gpm_motif_enum_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes);
+/* Writes d_counts (device uint64[gpm_motif_classes(k)]) = the induced count
+ * of every class, k = 3, 4 or 5.  GPM_UNSUPPORTED for other k. */
+gpm_status gpm_motif_count_enum(const gpm_graph *g, int32_t k, void *d_ws, uint64_t ws_bytes,
+                                uint64_t *d_counts, void *stream);
 
 /* ------------------------------------------------------------ batch --- */
 

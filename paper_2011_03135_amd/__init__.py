@@ -8,6 +8,7 @@ binding raises if the built library is missing; there is no fallback.
     g = gpm.Graph.build(n, u, v)            # u, v: int32 CUDA tensors
     gpm.count(g, gpm.clique(4))             # exact int
     gpm.motif_count(g, 4)                   # 6 induced 4-motif counts
+    gpm.motif_count_enum(g, 5)              # 21 induced 5-motif counts
 """
 from .binding import (  # noqa: F401
     GpmError,
@@ -26,6 +27,9 @@ from .binding import (  # noqa: F401
     list_embeddings,
     load,
     motif_count,
+    motif_classes,
+    motif_class_pattern,
+    motif_count_enum,
     pattern,
     timing_enable,
     timing_read,

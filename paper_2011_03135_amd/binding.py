@@ -77,6 +77,10 @@ def load():
         "gpm_clique_counts": ([P, i32, P, u64, P, P], i32),
         "gpm_motif_workspace_bytes": ([P, i32, P], i32),
         "gpm_motif_count": ([P, i32, P, u64, P, P], i32),
+        "gpm_motif_classes": ([i32], i32),
+        "gpm_motif_class_pattern": ([i32, i32, P], i32),
+        "gpm_motif_enum_workspace_bytes": ([P, i32, P], i32),
+        "gpm_motif_count_enum": ([P, i32, P, u64, P, P], i32),
         "gpm_batch_workspace_bytes": ([i32, i32, P], i32),
         "gpm_batch_motif_count": ([P, P, i32, i32, P, u64, P, P], i32),
         "gpm_batch_default_config": ([P], i32),
@@ -342,6 +346,38 @@ def motif_count(g, k, stream=None, ws=None, out=None):
     if vals[-1] != 0:
         raise GpmError(7, f"motif combination check failed (status word {vals[-1]})")
     return vals[:-1]
+
+
+def motif_classes(k):
+    """gpm_motif_classes: number of k-vertex motif classes (0 if k is unsupported)."""
+    return int(load().gpm_motif_classes(int(k)))
+
+
+def motif_class_pattern(k, index):
+    """gpm_motif_class_pattern -> list of the class's edges (a, b), a < b."""
+    p = Pattern()
+    _check(load().gpm_motif_class_pattern(int(k), int(index), ctypes.byref(p)))
+    return [(p.edges[i][0], p.edges[i][1]) for i in range(p.n_edges)]
+
+
+def motif_enum_workspace_bytes(g, k):
+    b = ctypes.c_uint64()
+    _check(load().gpm_motif_enum_workspace_bytes(g.handle, int(k), ctypes.byref(b)))
+    return b.value
+
+
+def motif_count_enum(g, k, stream=None, ws=None, out=None):
+    """gpm_motif_count_enum -> list of exact ints, one per motif class."""
+    nbytes = motif_enum_workspace_bytes(g, k)
+    if ws is None or ws.numel() < nbytes:
+        ws = _buffer(nbytes, g.device)
+    nout = motif_classes(k)
+    res = out if out is not None else torch.zeros(nout, dtype=torch.int64, device=g.device)
+    _check(load().gpm_motif_count_enum(g.handle, int(k), _ptr(ws), ws.numel(), _ptr(res),
+                                       _stream(stream)))
+    if out is not None:
+        return out
+    return [_u64(x) for x in res.tolist()]
 
 
 class BatchConfig(ctypes.Structure):

@@ -34,6 +34,11 @@ gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, unsigned long
 gpm_status sl_run(const gpm_graph *g, int32_t plan, bool list, void *ws, uint64_t ws_bytes,
                   unsigned long long *d_count, int32_t *d_buf, uint64_t cap,
                   unsigned long long *d_result, hipStream_t st);
+int motif_classes(int k);
+gpm_status motif_class_pattern(int k, int idx, gpm_pattern *out);
+gpm_status motif_enum_workspace_bytes(const gpm_graph *g, uint64_t *bytes);
+gpm_status motif_enum_count(const gpm_graph *g, int k, void *ws, uint64_t ws_bytes,
+                            unsigned long long *out, hipStream_t st);
 gpm_status batch_workspace_bytes(int32_t G, int32_t k, uint64_t *bytes);
 gpm_status batch_default_config(gpm_batch_config *c);
 gpm_status batch_run(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,
@@ -334,6 +339,33 @@ gpm_status gpm_motif_count(const gpm_graph *g, int32_t k, void *d_ws, uint64_t w
     if (!d_ws || !aligned256(d_ws)) return fail(GPM_INVALID_ARGUMENT, "workspace NULL or unaligned");
     return gpm::motif_run(g, k, d_ws, ws_bytes, reinterpret_cast<unsigned long long *>(d_counts),
                           static_cast<hipStream_t>(stream));
+}
+
+int32_t gpm_motif_classes(int32_t k) { return gpm::motif_classes(k); }
+
+gpm_status gpm_motif_class_pattern(int32_t k, int32_t index, gpm_pattern *out) {
+    if (!out) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    return gpm::motif_class_pattern(k, index, out);
+}
+
+gpm_status gpm_motif_enum_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes) {
+    gpm_status rc = check_graph(g);
+    if (rc) return rc;
+    if (k < 3 || k > 5) return fail(GPM_UNSUPPORTED, "motif size must be 3, 4 or 5");
+    if (!bytes) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    return gpm::motif_enum_workspace_bytes(g, bytes);
+}
+
+gpm_status gpm_motif_count_enum(const gpm_graph *g, int32_t k, void *d_ws, uint64_t ws_bytes,
+                                uint64_t *d_counts, void *stream) {
+    gpm_status rc = check_graph(g);
+    if (rc) return rc;
+    if (k < 3 || k > 5) return fail(GPM_UNSUPPORTED, "motif size must be 3, 4 or 5");
+    if (!d_counts) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    if (!d_ws || !aligned256(d_ws)) return fail(GPM_INVALID_ARGUMENT, "workspace NULL or unaligned");
+    return gpm::motif_enum_count(g, k, d_ws, ws_bytes,
+                                 reinterpret_cast<unsigned long long *>(d_counts),
+                                 static_cast<hipStream_t>(stream));
 }
 
 gpm_status gpm_batch_workspace_bytes(int32_t G, int32_t k, uint64_t *bytes) {

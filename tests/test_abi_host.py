@@ -120,3 +120,36 @@ def test_new_entry_points_validate_on_host(lib):
     assert lib.gpm_batch_default_config(None) == 1
     assert lib.gpm_batch_motif_count_config(None, None, 1, 4, None, None, 0, None, None) == 1
     assert lib.gpm_batch_autotune(None, None, 1, 4, None, 0, None, None, 1, None, None) == 1
+
+
+def test_motif_catalogue():
+    """The motif classes are the connected graphs on k vertices, one per
+    isomorphism class: 2, 6 and 21 of them for k = 3, 4, 5 (the counts of
+    connected unlabelled graphs), k = 3 and 4 in the local-counting order."""
+    import brute
+    import paper_2011_03135_amd as gpm
+    from paper_2011_03135_amd.binding import GpmError
+    for k, want in ((3, 2), (4, 6), (5, 21)):
+        assert gpm.motif_classes(k) == want
+        pats = [gpm.motif_class_pattern(k, i) for i in range(want)]
+        forms = set()
+        for e in pats:
+            assert all(0 <= a < b < k for a, b in e)
+            assert len(set(e)) == len(e)
+            assert brute.connected(k, e)
+            forms.add(brute.canon(k, e))
+        assert len(forms) == want
+        if k == 5:
+            assert [len(e) for e in pats] == sorted(len(e) for e in pats)
+    named3 = [brute.canon(3, brute.PATTERNS3[n]) for n in gpm.MOTIF3_NAMES]
+    assert [brute.canon(3, gpm.motif_class_pattern(3, i)) for i in range(2)] == named3
+    named4 = [brute.canon(4, brute.PATTERNS4[n]) for n in gpm.MOTIF4_NAMES]
+    assert [brute.canon(4, gpm.motif_class_pattern(4, i)) for i in range(6)] == named4
+    for k in (2, 6):
+        assert gpm.motif_classes(k) == 0
+        with pytest.raises(GpmError) as ei:
+            gpm.motif_class_pattern(k, 0)
+        assert ei.value.status == 5
+    with pytest.raises(GpmError) as ei:
+        gpm.motif_class_pattern(5, 21)
+    assert ei.value.status == 1
