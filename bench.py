@@ -273,6 +273,56 @@ def generic_leg(gpm, torch, scale, reps=3):
             "lc_route_speedup": ms / lc_ms}
 
 
+def motif_enum_leg(gpm, torch, scale4=12, scale5=10, reps=3):
+    """Pattern-oblivious motif counting (vertex extension of canonical
+    embeddings, connectivity codes; no counting formulas): the 4-motifs of
+    RMAT-`scale4` against the local-count route's time for the same six
+    counts, and the 21 5-motifs of RMAT-`scale5`, which only this route
+    gives."""
+    import graphgen
+
+    def timed(fn):
+        out = fn()   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) * 1e3 / reps
+
+    def without_map(fn):
+        # the same kernel taking connectivity from binary searches in the
+        # embedding's rows instead of the per-wave connectivity map
+        os.environ["GPM_MOTIF_MNC"] = "0"
+        try:
+            return timed(fn)
+        finally:
+            del os.environ["GPM_MOTIF_MNC"]
+
+    e = graphgen.rmat(scale4, seed=scale4)
+    g = gpm.Graph.build(e.n, torch.from_numpy(e.u).cuda(), torch.from_numpy(e.v).cuda())
+    ws = torch.empty(gpm.motif_enum_workspace_bytes(g, 4), dtype=torch.uint8, device="cuda")
+    run4 = lambda: gpm.motif_count_enum(g, 4, ws=ws)   # noqa: E731
+    c4, ms4 = timed(run4)
+    c4_off, ms4_off = without_map(run4)
+    lc4, lc_ms = timed(lambda: gpm.motif_count(g, 4))
+    e5 = graphgen.rmat(scale5, seed=scale5)
+    g5 = gpm.Graph.build(e5.n, torch.from_numpy(e5.u).cuda(), torch.from_numpy(e5.v).cuda())
+    ws5 = torch.empty(gpm.motif_enum_workspace_bytes(g5, 5), dtype=torch.uint8, device="cuda")
+    run5 = lambda: gpm.motif_count_enum(g5, 5, ws=ws5)   # noqa: E731
+    c5, ms5 = timed(run5)
+    c5_off, ms5_off = without_map(run5)
+    return {"workload": f"rmat{scale4} 4-motifs and rmat{scale5} 5-motifs by enumeration "
+                        f"(k_motif_enum) vs the 4-motif local-count route",
+            "motif4": {"counts": c4, "equals_local_count_route": c4 == lc4, "ms": ms4,
+                       "subgraphs_per_sec": sum(c4) / (ms4 * 1e-3),
+                       "ms_without_connectivity_map": ms4_off, "same_without_map": c4 == c4_off,
+                       "local_count_route_ms": lc_ms, "local_count_speedup": ms4 / lc_ms},
+            "motif5": {"counts": c5, "ms": ms5, "subgraphs_per_sec": sum(c5) / (ms5 * 1e-3),
+                       "ms_without_connectivity_map": ms5_off,
+                       "same_without_map": c5 == c5_off}}
+
+
 def copy_calibration():
     import torch
     n = 1 << 30
@@ -301,6 +351,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--no-generic", action="store_true")
+    ap.add_argument("--no-motif-enum", action="store_true")
+    ap.add_argument("--motif-enum-only", action="store_true",
+                    help="time only the pattern-oblivious motif leg (for kernel traces) and exit")
     ap.add_argument("--generic-only", action="store_true",
                     help="time only the general-pattern leg (for kernel traces) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -325,6 +378,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.generic_only:
         print(json.dumps({"generic_pattern": generic_leg(gpm, torch, 14)}))
+        return
+    if args.motif_enum_only:
+        print(json.dumps({"motif_enumeration": motif_enum_leg(gpm, torch)}))
         return
     e = graphgen.rmat(args.scale, seed=args.scale)
     u = torch.from_numpy(e.u).to(dev)
@@ -440,6 +496,9 @@ def main():
     if not args.no_generic:
         log("general pattern")
         res["generic_pattern"] = generic_leg(gpm, torch, 14)
+    if not args.no_motif_enum:
+        log("motif enumeration")
+        res["motif_enumeration"] = motif_enum_leg(gpm, torch)
     if not args.no_serve:
         log("serving load")
         g_res = gpm.Graph.build(e.n, u, v)

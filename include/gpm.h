@@ -253,7 +253,12 @@ gpm_status gpm_motif_class_pattern(int32_t k, int32_t index, gpm_pattern *out);
  * symmetric CSR plus a little (the work-unit numbering). */
 gpm_status gpm_motif_enum_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes);
 /* Writes d_counts (device uint64[gpm_motif_classes(k)]) = the induced count
- * of every class, k = 3, 4 or 5.  GPM_UNSUPPORTED for other k. */
+ * of every class, k = 3, 4 or 5.  GPM_UNSUPPORTED for other k.  For k >= 4
+ * on graphs of at most 16384 vertices each wave keeps a connectivity map in
+ * LDS (Section 4, memoised neighbourhood connectivity: 4 bits per vertex,
+ * the positions of the embedding it is adjacent to); elsewhere, or with the
+ * environment variable GPM_MOTIF_MNC=0, the same bits come from binary
+ * searches in the embedding's rows.  Both give the same counts. */
 gpm_status gpm_motif_count_enum(const gpm_graph *g, int32_t k, void *d_ws, uint64_t ws_bytes,
                                 uint64_t *d_counts, void *stream);
 

@@ -30,6 +30,7 @@ from .binding import (  # noqa: F401
     motif_classes,
     motif_class_pattern,
     motif_count_enum,
+    motif_enum_workspace_bytes,
     pattern,
     timing_enable,
     timing_read,

@@ -35,6 +35,7 @@
 // last level the lanes' codes are tallied per distinct code into per-wave
 // class counters; otherwise the wave descends into the survivors one by one.
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 #include <vector>
 
@@ -49,6 +50,7 @@ constexpr int kMeNT = 256;
 constexpr int kMeWaves = kMeNT / kWave;
 constexpr int kMeCodes = 1 << (kMeMaxK * (kMeMaxK - 1) / 2);
 constexpr int kMeMaxClass = 21;
+constexpr int32_t kMncMaxN = 16384;   // graphs up to this size keep a connectivity map per wave
 
 struct MotifEnumPlan {
     uint8_t cls[kMeCodes];   // motif class of each embedding code (0xff: not a code)
@@ -125,20 +127,25 @@ __global__ void k_me_chunks(const int32_t *__restrict__ off, const int32_t *__re
     }
 }
 
-template <int K>
+template <int K, bool MNC>
 __global__ void __launch_bounds__(kMeNT) k_motif_enum(const int32_t *__restrict__ off,
                                                       const int32_t *__restrict__ adj, int32_t n,
                                                       const int64_t *__restrict__ chunk_off,
                                                       unsigned long long *cursor,
                                                       MotifEnumPlan P, int32_t nclass,
+                                                      int32_t map_stride,
                                                       unsigned long long *counts) {
     constexpr int kCodes = 1 << (K * (K - 1) / 2);
     __shared__ MeWave sw[kMeWaves];
     __shared__ uint8_t cls[kCodes];
+    extern __shared__ uint32_t me_maps[];   // MNC: kMeWaves maps of map_stride words
     const int lane = lane_id(), wib = threadIdx.x / kWave;
     MeWave &S = sw[wib];
+    uint32_t *map = me_maps + (size_t)wib * map_stride;
     for (int i = threadIdx.x; i < kCodes; i += kMeNT) cls[i] = P.cls[i];
     if (lane < kMeMaxClass) S.cnt[lane] = 0ull;
+    if (MNC)
+        for (int i = lane; i < map_stride; i += kWave) map[i] = 0;
     __syncthreads();
     const int64_t nwaves = (int64_t)gridDim.x * kMeWaves;
     const int64_t wave0 = (int64_t)blockIdx.x * kMeWaves + wib;
@@ -168,6 +175,22 @@ __global__ void __launch_bounds__(kMeNT) k_motif_enum(const int32_t *__restrict_
             S.pos[l] = 0;
             S.lim[l] = c;
             S.mask[l] = 0ull;
+        }
+        me_wave_sync();
+    };
+
+    // Connectivity map (MNC): a 4-bit entry per vertex, 8 to a word; bit j
+    // of w's entry is set iff w is adjacent to the vertex at position j
+    // (positions 0..3 are the ones a later vertex can look back to), kept
+    // for the placed positions only.  Neighbouring ids share a word, so the
+    // updates are LDS atomics.
+    auto mark = [&](int32_t v, uint32_t bit, bool set) {
+        const int32_t e = off[v + 1];
+        for (int32_t i = off[v] + lane; i < e; i += kWave) {
+            const int32_t w = adj[i];
+            const uint32_t b = bit << ((w & 7) * 4);
+            if (set) atomicOr(map + (w >> 3), b);
+            else atomicAnd(map + (w >> 3), ~b);
         }
         me_wave_sync();
     };
@@ -211,6 +234,10 @@ __global__ void __launch_bounds__(kMeNT) k_motif_enum(const int32_t *__restrict_
                 S.code[2] = 1u;   // v1 ~ v0
             }
             me_wave_sync();
+            if (MNC) {
+                mark(S.m[0], 1u, true);
+                mark(S.m[1], 2u, true);
+            }
             open_level(2);
             if (lane == 0) {
                 S.pos[2] = (int32_t)(c - chunk_off[a]) * kWave;
@@ -224,6 +251,7 @@ __global__ void __launch_bounds__(kMeNT) k_motif_enum(const int32_t *__restrict_
                     const int32_t p = S.pos[l];
                     if (p >= S.lim[l]) {
                         l--;
+                        if (MNC && l >= 2) mark(S.m[l], 1u << l, false);
                         continue;
                     }
                     const int32_t q = p + lane;
@@ -233,11 +261,17 @@ __global__ void __launch_bounds__(kMeNT) k_motif_enum(const int32_t *__restrict_
                         if (q >= S.cum[l][i]) src = i;
                     const int32_t u = valid ? adj[S.lo[l][src] + (q - S.cum[l][src])] : 0;
                     uint32_t b = 1u << src;
-                    for (int j = 0; j < l; j++) {
-                        if (j == src || !valid) continue;
-                        if (me_row_has(off, adj, S.m[j], u)) {
-                            if (j < src) valid = false;   // an earlier first neighbour
-                            else b |= 1u << j;
+                    if (MNC) {
+                        if (valid) b = (map[u >> 3] >> ((u & 7) * 4)) & ((1u << l) - 1u);
+                        // an earlier first neighbour
+                        if (b & ((1u << src) - 1u)) valid = false;
+                    } else {
+                        for (int j = 0; j < l; j++) {
+                            if (j == src || !valid) continue;
+                            if (me_row_has(off, adj, S.m[j], u)) {
+                                if (j < src) valid = false;   // an earlier first neighbour
+                                else b |= 1u << j;
+                            }
                         }
                     }
                     if (lane == 0) S.pos[l] = p + kWave;
@@ -271,10 +305,15 @@ __global__ void __launch_bounds__(kMeNT) k_motif_enum(const int32_t *__restrict_
                     S.code[l + 1] = S.code[l] | (S.bits[l][cs] << (l * (l - 1) / 2));
                 }
                 me_wave_sync();
+                if (MNC) mark(S.m[l], 1u << l, true);
                 l++;
                 open_level(l);
             }
             me_wave_sync();
+            if (MNC) {
+                mark(S.m[0], 1u, false);
+                mark(S.m[1], 2u, false);
+            }
             c = a_end;
             if (c >= c_end) break;
         }
@@ -442,20 +481,22 @@ gpm_status motif_enum_count(const gpm_graph *g, int k, void *ws, uint64_t ws_byt
     // persistent: at most 8 workgroups per CU, fewer for small graphs
     const unsigned blocks = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((narcs + kMeWaves - 1) / kMeWaves, (int64_t)cu_count() * 8));
-    switch (k) {
-    case 3:
-        hipLaunchKernelGGL(k_motif_enum<3>, dim3(blocks), dim3(kMeNT), 0, st, g->off, g->adj, g->n,
-                           chunk_off, cursor, plans[k], nclass, out);
-        break;
-    case 4:
-        hipLaunchKernelGGL(k_motif_enum<4>, dim3(blocks), dim3(kMeNT), 0, st, g->off, g->adj, g->n,
-                           chunk_off, cursor, plans[k], nclass, out);
-        break;
-    default:
-        hipLaunchKernelGGL(k_motif_enum<5>, dim3(blocks), dim3(kMeNT), 0, st, g->off, g->adj, g->n,
-                           chunk_off, cursor, plans[k], nclass, out);
-        break;
-    }
+    // the connectivity map needs 4 bits per vertex per wave in LDS; k = 3
+    // gains nothing from it (its one lookup per candidate is no cheaper than
+    // marking the two rows)
+    const char *env = getenv("GPM_MOTIF_MNC");
+    const bool mnc = k >= 4 && g->n <= kMncMaxN && !(env && env[0] == '0');
+    const int32_t stride = mnc ? (g->n + 7) / 8 : 0;   // words
+    const size_t dyn = (size_t)kMeWaves * stride * sizeof(uint32_t);
+#define ME_LAUNCH(KK, M)                                                                    \
+    hipLaunchKernelGGL((k_motif_enum<KK, M>), dim3(blocks), dim3(kMeNT), dyn, st, g->off,  \
+                       g->adj, g->n, chunk_off, cursor, plans[k], nclass, stride, out)
+    if (k == 3) ME_LAUNCH(3, false);
+    else if (k == 4 && mnc) ME_LAUNCH(4, true);
+    else if (k == 4) ME_LAUNCH(4, false);
+    else if (mnc) ME_LAUNCH(5, true);
+    else ME_LAUNCH(5, false);
+#undef ME_LAUNCH
     GPM_LAUNCH_CHECK("k_motif_enum");
     return GPM_OK;
 }

@@ -124,3 +124,33 @@ def test_two_routes_agree_rmat(gpm):
         g = build(gpm, e)
         assert gpm.motif_count_enum(g, 3) == gpm.motif_count(g, 3)
         assert gpm.motif_count_enum(g, 4) == gpm.motif_count(g, 4)
+
+
+@pytest.mark.parametrize("gi", [0, 2, 4])
+def test_without_connectivity_map(gpm, gi, monkeypatch):
+    """GPM_MOTIF_MNC=0 takes the connectivity bits from binary searches in
+    the embedding's rows instead of the per-wave map: same counts."""
+    e = graphs()[gi]
+    print(f"graph {gi} n={e.n}", flush=True)
+    g = build(gpm, e)
+    off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+    monkeypatch.setenv("GPM_MOTIF_MNC", "0")
+    assert gpm.motif_count_enum(g, 4) == oracle.motif4(off, adj)
+    want = [oracle.pattern_count(off, adj, 5, gpm.motif_class_pattern(5, i), True)[0]
+            for i in range(21)]
+    assert gpm.motif_count_enum(g, 5) == want
+
+
+def test_map_on_and_off_agree(gpm, monkeypatch):
+    """RMAT-12 (map on by default) and a sparse graph above the map's vertex
+    limit (map off): both settings and the local-count route agree."""
+    e = graphgen.rmat(12, seed=5)
+    g = build(gpm, e)
+    on = gpm.motif_count_enum(g, 4)
+    monkeypatch.setenv("GPM_MOTIF_MNC", "0")
+    assert gpm.motif_count_enum(g, 4) == on == gpm.motif_count(g, 4)
+    monkeypatch.delenv("GPM_MOTIF_MNC")
+    big = graphgen.erdos_renyi(20000, 6.0 / 20000, 6)
+    gb = build(gpm, big)
+    assert gpm.motif_count_enum(gb, 4) == gpm.motif_count(gb, 4)
+    assert gpm.motif_count_enum(gb, 3) == gpm.motif_count(gb, 3)
