@@ -103,8 +103,8 @@ gpm_status gpm_pattern_clique(int32_t k, uint32_t flags, gpm_pattern *out);
 /* Any other connected pattern of 2..6 vertices, vertex- or edge-induced:
  * counting only (gpm_list returns GPM_UNSUPPORTED).  A matching order with
  * partial orders derived from the pattern's automorphisms (Appendix B.1);
- * waves take the graph's arcs 64 at a time and search depth first below
- * each. */
+ * waves take work units of 64 third-vertex candidates below one edge and
+ * search depth first below each. */
 #define GPM_PLAN_GENERIC        4
 /* Returns the plan for (graph-independent) pattern p, or GPM_UNSUPPORTED. */
 gpm_status gpm_pattern_plan(const gpm_pattern *p, int32_t *plan);

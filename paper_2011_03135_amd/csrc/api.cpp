@@ -29,8 +29,9 @@ gpm_status motif_run(const gpm_graph *g, int32_t k, void *ws, uint64_t ws_bytes,
                      unsigned long long *d_counts, hipStream_t st);
 gpm_status sl_workspace_bytes(const gpm_graph *g, int32_t plan, bool list, uint64_t *bytes);
 bool generic_pattern_ok(const gpm_pattern *p);
-gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, unsigned long long *out,
-                         hipStream_t st);
+uint64_t generic_workspace_bytes(const gpm_graph *g);
+gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, void *ws, uint64_t ws_bytes,
+                         unsigned long long *out, hipStream_t st);
 gpm_status sl_run(const gpm_graph *g, int32_t plan, bool list, void *ws, uint64_t ws_bytes,
                   unsigned long long *d_count, int32_t *d_buf, uint64_t cap,
                   unsigned long long *d_result, hipStream_t st);
@@ -258,7 +259,7 @@ gpm_status gpm_workspace_bytes(const gpm_graph *g, const gpm_pattern *p, uint64_
     if (plan == GPM_PLAN_CLIQUE_DAG) return gpm::clique_workspace_bytes(g, p->k, list, bytes);
     if (plan == GPM_PLAN_GENERIC) {
         if (list) return fail(GPM_UNSUPPORTED, "listing of general patterns is not implemented");
-        *bytes = 256;   // no workspace; the argument must still be a valid buffer
+        *bytes = gpm::generic_workspace_bytes(g);
         return GPM_OK;
     }
     return gpm::sl_workspace_bytes(g, plan, list, bytes);
@@ -278,7 +279,7 @@ gpm_status gpm_count(const gpm_graph *g, const gpm_pattern *p, void *d_ws, uint6
     unsigned long long *out = reinterpret_cast<unsigned long long *>(d_count);
     if (plan == GPM_PLAN_CLIQUE_DAG)
         return gpm::clique_run(g, p->k, false, d_ws, ws_bytes, out, nullptr, 0, nullptr, st);
-    if (plan == GPM_PLAN_GENERIC) return gpm::generic_count(g, p, out, st);
+    if (plan == GPM_PLAN_GENERIC) return gpm::generic_count(g, p, d_ws, ws_bytes, out, st);
     return gpm::sl_run(g, plan, false, d_ws, ws_bytes, out, nullptr, 0, nullptr, st);
 }
 

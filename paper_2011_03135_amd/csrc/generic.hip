@@ -12,13 +12,14 @@
 // the orbit, and the group shrinks to v's stabiliser.  Each embedding is
 // then matched exactly once.
 //
-// Kernel.  Waves take the arcs of the symmetric CSR 64 at a time (steps 0
-// and 1, one arc per lane, so a hub's search is spread over its arcs) and
-// run the depth-first search below each surviving arc with a per-wave stack
-// in LDS.  At step s >= 2 the candidates are a row of the
-// symmetric CSR: that of the already matched backward neighbour with the
-// fewest entries, cut by binary search to the range the partial orders
-// allow.  Lanes test 64 candidates at a time against the other backward
+// Kernels.  Steps 0 and 1 are the arcs of the symmetric CSR.  A first pass
+// counts, per arc the partial orders accept, the 64-candidate chunks of
+// step 2; their exclusive scan numbers the work units (arc, chunk), which
+// waves take from an atomic cursor, running the depth-first search below
+// the chunk with a per-wave stack in LDS.  At step s >= 2 the candidates
+// are a row of the symmetric CSR: that of the already matched backward
+// neighbour with the fewest entries, cut by binary search to the range the
+// partial orders allow.  Lanes test 64 candidates at a time against the other backward
 // neighbours (binary search in their sorted rows), the non-neighbours when
 // vertex-induced, and distinctness; the survivors are a lane mask.  At the
 // last step the mask's population count is the count; otherwise the wave
@@ -78,15 +79,69 @@ struct GenWave {
     int32_t cand[kGenMaxK][kWave];
 };
 
+// The row of arc a of a CSR: the last r with off[r] <= a.
+__device__ __forceinline__ int32_t gen_arc_row(const int32_t *__restrict__ off, int32_t n,
+                                               int64_t a) {
+    int32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= a) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Candidates of step 2 below the arc (m0, m1): the row of the backward
+// neighbour with fewer entries (the first on a tie), cut by binary search to
+// the range the partial orders allow.  The search kernel's step opening
+// makes the same choice, so the chunk numbering below matches it.
+__device__ __forceinline__ int32_t gen_step2_len(const GenPlan &P, const int32_t *__restrict__ off,
+                                                 const int32_t *__restrict__ adj, int32_t m0,
+                                                 int32_t m1) {
+    const bool b0 = P.back_adj[2] & 1u, b1 = (P.back_adj[2] >> 1) & 1u;
+    const int32_t l0 = off[m0 + 1] - off[m0], l1 = off[m1 + 1] - off[m1];
+    const int32_t mp = (b0 && (!b1 || l0 <= l1)) ? m0 : m1;
+    int32_t lo = off[mp], hi = off[mp + 1];
+    if (P.above[2] & 1u) lo = lower_idx(adj, lo, hi, m0 + 1);
+    if (P.below[2] & 1u) hi = lower_idx(adj, lo, hi, m0);
+    if ((P.above[2] >> 1) & 1u) lo = lower_idx(adj, lo, hi, m1 + 1);
+    if ((P.below[2] >> 1) & 1u) hi = lower_idx(adj, lo, hi, m1);
+    return max(0, hi - lo);
+}
+
+// Per arc of the symmetric CSR (steps 0 and 1): 0 if the partial orders
+// between the two steps reject it; else, for two-vertex patterns 1 (the arc
+// is a match), otherwise the number of 64-candidate chunks of step 2.
+__global__ void k_gen_chunks(const int32_t *__restrict__ off, const int32_t *__restrict__ adj,
+                             int32_t n, GenPlan P, int32_t *__restrict__ chunks) {
+    const int64_t narcs = off[n];
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < narcs;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = gen_arc_row(off, n, a), v1 = adj[a];
+        bool ok = true;
+        if ((P.above[1] & 1u) && v1 < r) ok = false;
+        if ((P.below[1] & 1u) && v1 > r) ok = false;
+        int32_t c = 0;
+        if (ok) c = P.k == 2 ? 1 : (gen_step2_len(P, off, adj, r, v1) + kWave - 1) / kWave;
+        chunks[a] = c;
+    }
+}
+
+// Two-vertex patterns: the count is the number of accepted arcs.
+__global__ void k_gen_total(const int64_t *__restrict__ total, unsigned long long *out) {
+    if (threadIdx.x == 0) out[0] = (unsigned long long)*total;
+}
+
 __global__ void __launch_bounds__(kGenNT) k_generic(const int32_t *__restrict__ off,
                                                     const int32_t *__restrict__ adj, int32_t n,
-                                                    GenPlan P, unsigned long long *result) {
+                                                    GenPlan P, const int64_t *__restrict__ chunk_off,
+                                                    unsigned long long *cursor,
+                                                    unsigned long long *result) {
     __shared__ GenWave sw[kGenNT / kWave];
     const int lane = lane_id(), wib = threadIdx.x / kWave;
     GenWave &S = sw[wib];
-    const int64_t wave0 = (int64_t)blockIdx.x * (kGenNT / kWave) + wib;
-    const int64_t nwaves = (int64_t)gridDim.x * (kGenNT / kWave);
     const int32_t last = P.k - 1;
+    const int64_t narcs = off[n];
+    const int64_t nchunks = chunk_off[narcs];
     uint64_t count = 0;   // wave-uniform
     // candidates of step s: the allowed range of the smallest backward row
     auto open_step = [&](int32_t s) {
@@ -114,90 +169,78 @@ __global__ void __launch_bounds__(kGenNT) k_generic(const int32_t *__restrict__ 
         }
         wave_sync();
     };
-    // steps 0 and 1 come from the arcs of the symmetric CSR, 64 per wave
-    // and step (one per lane), so a hub's search is spread over its arcs
-    // rather than left to one wave
-    const int32_t narcs = off[n];
-    for (int64_t c0 = wave0 * kWave; c0 < narcs; c0 += nwaves * kWave) {
-        const int64_t a = c0 + lane;
-        bool arc_ok = a < narcs;
-        int32_t r = 0, v1 = 0;
-        if (arc_ok) {
-            int32_t lo = 0, hi = n;   // the row of arc a: last r with off[r] <= a
-            while (hi - lo > 1) {
-                const int32_t mid = (lo + hi) >> 1;
-                if (off[mid] <= a) lo = mid; else hi = mid;
-            }
-            r = lo;
-            v1 = adj[a];
-            if ((P.above[1] & 1u) && v1 < r) arc_ok = false;
-            if ((P.below[1] & 1u) && v1 > r) arc_ok = false;
+    // a work unit is one 64-candidate chunk of step 2 below one arc (steps
+    // 0 and 1), with the whole search below it; units come from an atomic
+    // cursor, so a hub's arcs and chunks spread over the grid
+    for (;;) {
+        unsigned long long got = 0;
+        if (lane == 0) got = atomicAdd(cursor, 1ull);
+        const int64_t c = (int64_t)__shfl(got, 0);
+        if (c >= nchunks) break;   // wave-uniform
+        int64_t lo = 0, hi = narcs;   // the arc of unit c: last a with chunk_off[a] <= c
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (chunk_off[mid] <= c) lo = mid; else hi = mid;
         }
-        uint64_t amask = __ballot(arc_ok);
-        if (last == 1) {
-            count += (uint64_t)__popcll(amask);
-            continue;
+        const int64_t a = lo;
+        if (lane == 0) {
+            S.m[0] = gen_arc_row(off, n, a);
+            S.m[1] = adj[a];
         }
-        S.cand[0][lane] = r;
-        S.cand[1][lane] = v1;
         wave_sync();
-        while (amask) {
-            const int ca = __builtin_ctzll(amask);
-            amask &= amask - 1ull;
-            if (lane == 0) {
-                S.m[0] = S.cand[0][ca];
-                S.m[1] = S.cand[1][ca];
-            }
-            wave_sync();
-            open_step(2);
-            int32_t s = 2;
-            while (s >= 2) {
-                uint64_t msk = S.mask[s];
-                if (msk == 0ull) {
-                    const int32_t p = S.pos[s], e = S.end[s];
-                    if (p >= e) {
-                        s--;
-                        continue;
-                    }
-                    const int32_t i = p + lane;
-                    const int32_t v = i < e ? adj[i] : -1;
-                    bool ok = i < e;
-                    const int32_t piv = S.pivot[s];
-                    for (int t = 0; t < s && ok; t++) {
-                        if (t == piv) continue;
-                        const int32_t mt = S.m[t];
-                        if (v == mt) {
-                            ok = false;
-                            break;
-                        }
-                        if ((P.back_adj[s] >> t) & 1u) ok = row_has(off, adj, mt, v);
-                        else if (P.induced && ((P.back_non[s] >> t) & 1u)) ok = !row_has(off, adj, mt, v);
-                    }
-                    msk = __ballot(ok);
-                    wave_sync();
-                    if (lane == 0) S.pos[s] = p + kWave;
-                    if (s == last) {
-                        count += (uint64_t)__popcll(msk);
-                        wave_sync();
-                        continue;
-                    }
-                    S.cand[s][lane] = v;
-                    if (lane == 0) S.mask[s] = msk;
-                    wave_sync();
-                    if (msk == 0ull) continue;
-                }
-                // descend into the next candidate of step s
-                const int c = __builtin_ctzll(msk);
-                if (lane == 0) {
-                    S.mask[s] = msk & (msk - 1ull);
-                    S.m[s] = S.cand[s][c];
-                }
-                wave_sync();
-                s++;
-                open_step(s);
-            }
-            wave_sync();
+        open_step(2);
+        if (lane == 0) {
+            S.pos[2] += (int32_t)(c - chunk_off[a]) * kWave;
+            S.end[2] = min(S.end[2], S.pos[2] + kWave);
         }
+        wave_sync();
+        int32_t s = 2;
+        while (s >= 2) {
+            uint64_t msk = S.mask[s];
+            if (msk == 0ull) {
+                const int32_t p = S.pos[s], e = S.end[s];
+                if (p >= e) {
+                    s--;
+                    continue;
+                }
+                const int32_t i = p + lane;
+                const int32_t v = i < e ? adj[i] : -1;
+                bool ok = i < e;
+                const int32_t piv = S.pivot[s];
+                for (int t = 0; t < s && ok; t++) {
+                    if (t == piv) continue;
+                    const int32_t mt = S.m[t];
+                    if (v == mt) {
+                        ok = false;
+                        break;
+                    }
+                    if ((P.back_adj[s] >> t) & 1u) ok = row_has(off, adj, mt, v);
+                    else if (P.induced && ((P.back_non[s] >> t) & 1u)) ok = !row_has(off, adj, mt, v);
+                }
+                msk = __ballot(ok);
+                wave_sync();
+                if (lane == 0) S.pos[s] = p + kWave;
+                if (s == last) {
+                    count += (uint64_t)__popcll(msk);
+                    wave_sync();
+                    continue;
+                }
+                S.cand[s][lane] = v;
+                if (lane == 0) S.mask[s] = msk;
+                wave_sync();
+                if (msk == 0ull) continue;
+            }
+            // descend into the next candidate of step s
+            const int cs = __builtin_ctzll(msk);
+            if (lane == 0) {
+                S.mask[s] = msk & (msk - 1ull);
+                S.m[s] = S.cand[s][cs];
+            }
+            wave_sync();
+            s++;
+            open_step(s);
+        }
+        wave_sync();
     }
     if (lane == 0 && count) atomicAdd(result, (unsigned long long)count);
 }
@@ -312,20 +355,55 @@ bool generic_pattern_ok(const gpm_pattern *p) {
     return make_plan(p, P) == GPM_OK;
 }
 
-gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, unsigned long long *out,
-                         hipStream_t st) {
+static void gen_layout(Carve &cv, int64_t narcs, int32_t **chunks, int64_t **chunk_off,
+                       int64_t **tmp, unsigned long long **cursor) {
+    *chunks = cv.take<int32_t>((uint64_t)std::max<int64_t>(narcs, 1));
+    *chunk_off = cv.take<int64_t>((uint64_t)narcs + 1);
+    *tmp = cv.take<int64_t>(scan_tmp_words((uint64_t)narcs));
+    *cursor = cv.take<unsigned long long>(1);
+}
+
+uint64_t generic_workspace_bytes(const gpm_graph *g) {
+    Carve cv(nullptr, 0);
+    int32_t *a;
+    int64_t *b, *c;
+    unsigned long long *d;
+    gen_layout(cv, 2 * g->m, &a, &b, &c, &d);
+    return cv.used;
+}
+
+gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, void *ws, uint64_t ws_bytes,
+                         unsigned long long *out, hipStream_t st) {
     GenPlan P;
     gpm_status rc = make_plan(p, P);
     if (rc) return rc;
+    const int64_t narcs = 2 * g->m;
+    Carve cv(ws, ws_bytes);
+    int32_t *chunks;
+    int64_t *chunk_off, *tmp;
+    unsigned long long *cursor;
+    gen_layout(cv, narcs, &chunks, &chunk_off, &tmp, &cursor);
+    if (!cv.fits()) return fail(GPM_INVALID_ARGUMENT, "workspace too small");
     GPM_HIP(fill_u32(reinterpret_cast<uint32_t *>(out), 0, 2, st));
-    if (g->n == 0) return GPM_OK;
+    if (g->m == 0) return GPM_OK;
     Span sp("k_generic", st);
-    // a wave per 64 arcs, as many as fit (grid-stride beyond that)
-    const int64_t chunks = (2 * g->m + kWave - 1) / kWave;
+    GPM_HIP(fill_u32(cursor, 0, 2, st));
+    const unsigned cblocks = (unsigned)std::min<int64_t>((narcs + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_gen_chunks, dim3(cblocks), dim3(256), 0, st, g->off, g->adj, g->n, P,
+                       chunks);
+    GPM_LAUNCH_CHECK("k_gen_chunks");
+    GPM_HIP(exclusive_scan_i64(chunks, chunk_off, (uint64_t)narcs, tmp, st));
+    if (P.k == 2) {
+        hipLaunchKernelGGL(k_gen_total, dim3(1), dim3(64), 0, st, chunk_off + narcs, out);
+        GPM_LAUNCH_CHECK("k_gen_total");
+        return GPM_OK;
+    }
+    // persistent: at most 8 workgroups per CU, fewer for small graphs
     const unsigned blocks = (unsigned)std::max<int64_t>(
-        1, std::min<int64_t>((chunks + kGenNT / kWave - 1) / (kGenNT / kWave),
+        1, std::min<int64_t>((narcs + kGenNT / kWave - 1) / (kGenNT / kWave),
                              (int64_t)cu_count() * 8));
-    hipLaunchKernelGGL(k_generic, dim3(blocks), dim3(kGenNT), 0, st, g->off, g->adj, g->n, P, out);
+    hipLaunchKernelGGL(k_generic, dim3(blocks), dim3(kGenNT), 0, st, g->off, g->adj, g->n, P,
+                       chunk_off, cursor, out);
     GPM_LAUNCH_CHECK("k_generic");
     return GPM_OK;
 }
