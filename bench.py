@@ -245,32 +245,43 @@ def serve_leg(gpm, torch, g20, scale, requests, warmup):
 
 
 def generic_leg(gpm, torch, scale, reps=3):
-    """The general-pattern plan on one pattern whose count the local-count
-    route also gives: the vertex-induced 4-cycle on RMAT-`scale`."""
+    """The general-pattern plan on two patterns whose counts the local-count
+    route also gives, the vertex-induced 4-cycle and 4-path on RMAT-`scale`,
+    with and without the per-wave connectivity map."""
     import graphgen
     e = graphgen.rmat(scale, seed=scale)
     g = gpm.Graph.build(e.n, torch.from_numpy(e.u).cuda(), torch.from_numpy(e.v).cuda())
-    c4 = gpm.pattern(4, [(0, 1), (1, 2), (2, 3), (3, 0)], gpm.VERTEX_INDUCED)
-    got = gpm.count(g, c4)   # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        got = gpm.count(g, c4)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / reps
-    mc = gpm.motif_count(g, 4)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        mc = gpm.motif_count(g, 4)
-    torch.cuda.synchronize()
-    lc_ms = (time.perf_counter() - t0) * 1e3 / reps
-    return {"workload": f"rmat{scale}: vertex-induced 4-cycle, general plan (k_generic) "
-                        f"vs the 4-motif local-count route",
-            "count": got, "equals_motif_count": got == mc[2], "ms": ms,
-            "matches_per_sec": got / (ms * 1e-3), "m": g.m,
-            "edges_per_sec": g.m / (ms * 1e-3), "lc_route_ms_all_six_motifs": lc_ms,
-            "lc_route_speedup": ms / lc_ms}
+
+    def timed(fn):
+        out = fn()   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) * 1e3 / reps
+
+    mc, lc_ms = timed(lambda: gpm.motif_count(g, 4))
+    names = list(gpm.MOTIF4_NAMES)
+    res = {"workload": f"rmat{scale}: vertex-induced 4-cycle and 4-path, general plan "
+                       f"(k_generic) vs the 4-motif local-count route",
+           "m": g.m, "lc_route_ms_all_six_motifs": lc_ms}
+    for name, edges in (("4-cycle", [(0, 1), (1, 2), (2, 3), (3, 0)]),
+                        ("4-path", [(0, 1), (1, 2), (2, 3)])):
+        p = gpm.pattern(4, edges, gpm.VERTEX_INDUCED)
+        got, ms = timed(lambda: gpm.count(g, p))
+        # the same plan taking adjacency from binary searches in the matched
+        # vertices' rows instead of the connectivity map
+        os.environ["GPM_MNC"] = "0"
+        try:
+            got_off, ms_off = timed(lambda: gpm.count(g, p))
+        finally:
+            del os.environ["GPM_MNC"]
+        res[name] = {"count": got, "equals_motif_count": got == mc[names.index(name)],
+                     "ms": ms, "matches_per_sec": got / (ms * 1e-3),
+                     "ms_without_connectivity_map": ms_off, "same_without_map": got == got_off,
+                     "lc_route_speedup": ms / lc_ms}
+    return res
 
 
 def motif_enum_leg(gpm, torch, scale4=12, scale5=10, reps=3):
@@ -293,11 +304,11 @@ def motif_enum_leg(gpm, torch, scale4=12, scale5=10, reps=3):
     def without_map(fn):
         # the same kernel taking connectivity from binary searches in the
         # embedding's rows instead of the per-wave connectivity map
-        os.environ["GPM_MOTIF_MNC"] = "0"
+        os.environ["GPM_MNC"] = "0"
         try:
             return timed(fn)
         finally:
-            del os.environ["GPM_MOTIF_MNC"]
+            del os.environ["GPM_MNC"]
 
     e = graphgen.rmat(scale4, seed=scale4)
     g = gpm.Graph.build(e.n, torch.from_numpy(e.u).cuda(), torch.from_numpy(e.v).cuda())
@@ -377,7 +388,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.generic_only:
-        print(json.dumps({"generic_pattern": generic_leg(gpm, torch, 14)}))
+        print(json.dumps({"generic_pattern": generic_leg(gpm, torch, 13)}))
         return
     if args.motif_enum_only:
         print(json.dumps({"motif_enumeration": motif_enum_leg(gpm, torch)}))
@@ -495,7 +506,7 @@ def main():
         res["batched_vs_plain"] = batch_leg(gpm, torch, args.batch_graphs, args.plain_graphs, 20)
     if not args.no_generic:
         log("general pattern")
-        res["generic_pattern"] = generic_leg(gpm, torch, 14)
+        res["generic_pattern"] = generic_leg(gpm, torch, 13)
     if not args.no_motif_enum:
         log("motif enumeration")
         res["motif_enumeration"] = motif_enum_leg(gpm, torch)

@@ -104,7 +104,11 @@ gpm_status gpm_pattern_clique(int32_t k, uint32_t flags, gpm_pattern *out);
  * counting only (gpm_list returns GPM_UNSUPPORTED).  A matching order with
  * partial orders derived from the pattern's automorphisms (Appendix B.1);
  * waves take work units of 64 third-vertex candidates below one edge and
- * search depth first below each. */
+ * search depth first below each.  Patterns of up to 5 vertices on graphs of
+ * up to 8192 vertices test adjacency through a per-wave connectivity map
+ * in LDS (Section 4, memoised neighbourhood connectivity), others by binary
+ * search in the matched vertices' rows; GPM_MNC=0 in the environment forces
+ * the latter.  Both give the same counts. */
 #define GPM_PLAN_GENERIC        4
 /* Returns the plan for (graph-independent) pattern p, or GPM_UNSUPPORTED. */
 gpm_status gpm_pattern_plan(const gpm_pattern *p, int32_t *plan);
@@ -257,7 +261,7 @@ gpm_status gpm_motif_enum_workspace_bytes(const gpm_graph *g, int32_t k, uint64_
  * on graphs of at most 16384 vertices each wave keeps a connectivity map in
  * LDS (Section 4, memoised neighbourhood connectivity: 4 bits per vertex,
  * the positions of the embedding it is adjacent to); elsewhere, or with the
- * environment variable GPM_MOTIF_MNC=0, the same bits come from binary
+ * environment variable GPM_MNC=0, the same bits come from binary
  * searches in the embedding's rows.  Both give the same counts. */
 gpm_status gpm_motif_count_enum(const gpm_graph *g, int32_t k, void *d_ws, uint64_t ws_bytes,
                                 uint64_t *d_counts, void *stream);

@@ -25,6 +25,7 @@
 // last step the mask's population count is the count; otherwise the wave
 // descends into its candidates one by one.
 #include <algorithm>
+#include <cstdlib>
 #include <vector>
 
 #include "gpm_internal.h"
@@ -34,7 +35,8 @@ namespace gpm {
 namespace {
 
 constexpr int kGenMaxK = 6;
-constexpr int kGenNT = 256;   // 4 waves per workgroup, one root each
+constexpr int kGenNT = 256;             // 4 waves per workgroup
+constexpr int32_t kGenMncMaxN = 8192;    // graphs up to this size keep a connectivity map per wave
 
 struct GenPlan {
     int32_t k;
@@ -131,14 +133,34 @@ __global__ void k_gen_total(const int64_t *__restrict__ total, unsigned long lon
     if (threadIdx.x == 0) out[0] = (unsigned long long)*total;
 }
 
+template <bool MNC>
 __global__ void __launch_bounds__(kGenNT) k_generic(const int32_t *__restrict__ off,
                                                     const int32_t *__restrict__ adj, int32_t n,
                                                     GenPlan P, const int64_t *__restrict__ chunk_off,
-                                                    unsigned long long *cursor,
+                                                    unsigned long long *cursor, int32_t map_stride,
                                                     unsigned long long *result) {
     __shared__ GenWave sw[kGenNT / kWave];
+    extern __shared__ uint32_t gen_maps[];   // MNC: a map of map_stride words per wave
     const int lane = lane_id(), wib = threadIdx.x / kWave;
     GenWave &S = sw[wib];
+    uint32_t *map = gen_maps + (size_t)wib * map_stride;
+    if (MNC)
+        for (int i = lane; i < map_stride; i += kWave) map[i] = 0;
+    wave_sync();
+    // Connectivity map (Section 4, memoised neighbourhood connectivity): a
+    // 4-bit entry per vertex, 8 to a word; bit t of w's entry is set iff w
+    // is adjacent to the vertex matched at step t, kept for the matched
+    // steps up to 3 (what a 5-vertex pattern's last step looks back to).
+    auto mark = [&](int32_t v, uint32_t bit, bool set) {
+        const int32_t e = off[v + 1];
+        for (int32_t i = off[v] + lane; i < e; i += kWave) {
+            const int32_t w = adj[i];
+            const uint32_t b = bit << ((w & 7) * 4);
+            if (set) atomicOr(map + (w >> 3), b);
+            else atomicAnd(map + (w >> 3), ~b);
+        }
+        wave_sync();
+    };
     const int32_t last = P.k - 1;
     const int64_t narcs = off[n];
     const int64_t nchunks = chunk_off[narcs];
@@ -188,6 +210,10 @@ __global__ void __launch_bounds__(kGenNT) k_generic(const int32_t *__restrict__ 
             S.m[1] = adj[a];
         }
         wave_sync();
+        if (MNC) {
+            mark(S.m[0], 1u, true);
+            mark(S.m[1], 2u, true);
+        }
         open_step(2);
         if (lane == 0) {
             S.pos[2] += (int32_t)(c - chunk_off[a]) * kWave;
@@ -201,21 +227,31 @@ __global__ void __launch_bounds__(kGenNT) k_generic(const int32_t *__restrict__ 
                 const int32_t p = S.pos[s], e = S.end[s];
                 if (p >= e) {
                     s--;
+                    if (MNC && s >= 2) mark(S.m[s], 1u << s, false);
                     continue;
                 }
                 const int32_t i = p + lane;
                 const int32_t v = i < e ? adj[i] : -1;
                 bool ok = i < e;
                 const int32_t piv = S.pivot[s];
-                for (int t = 0; t < s && ok; t++) {
-                    if (t == piv) continue;
-                    const int32_t mt = S.m[t];
-                    if (v == mt) {
-                        ok = false;
-                        break;
+                if (MNC) {
+                    for (int t = 0; t < s; t++) ok = ok && v != S.m[t];
+                    if (ok) {
+                        const uint32_t bits = (map[v >> 3] >> ((v & 7) * 4)) & ((1u << s) - 1u);
+                        ok = (bits & P.back_adj[s]) == P.back_adj[s] &&
+                             !(P.induced && (bits & P.back_non[s]));
                     }
-                    if ((P.back_adj[s] >> t) & 1u) ok = row_has(off, adj, mt, v);
-                    else if (P.induced && ((P.back_non[s] >> t) & 1u)) ok = !row_has(off, adj, mt, v);
+                } else {
+                    for (int t = 0; t < s && ok; t++) {
+                        if (t == piv) continue;
+                        const int32_t mt = S.m[t];
+                        if (v == mt) {
+                            ok = false;
+                            break;
+                        }
+                        if ((P.back_adj[s] >> t) & 1u) ok = row_has(off, adj, mt, v);
+                        else if (P.induced && ((P.back_non[s] >> t) & 1u)) ok = !row_has(off, adj, mt, v);
+                    }
                 }
                 msk = __ballot(ok);
                 wave_sync();
@@ -237,10 +273,15 @@ __global__ void __launch_bounds__(kGenNT) k_generic(const int32_t *__restrict__ 
                 S.m[s] = S.cand[s][cs];
             }
             wave_sync();
+            if (MNC) mark(S.m[s], 1u << s, true);
             s++;
             open_step(s);
         }
         wave_sync();
+        if (MNC) {
+            mark(S.m[0], 1u, false);
+            mark(S.m[1], 2u, false);
+        }
     }
     if (lane == 0 && count) atomicAdd(result, (unsigned long long)count);
 }
@@ -402,8 +443,19 @@ gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, void *ws, uin
     const unsigned blocks = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((narcs + kGenNT / kWave - 1) / (kGenNT / kWave),
                              (int64_t)cu_count() * 8));
-    hipLaunchKernelGGL(k_generic, dim3(blocks), dim3(kGenNT), 0, st, g->off, g->adj, g->n, P,
-                       chunk_off, cursor, out);
+    // the connectivity map: 4 bits per vertex per wave in LDS, for patterns
+    // of at most 5 vertices on graphs of at most 8192 vertices (larger maps
+    // cost more occupancy than the searches they save)
+    const char *env = getenv("GPM_MNC");
+    const bool mnc = P.k <= 5 && g->n <= kGenMncMaxN && !(env && env[0] == '0');
+    const int32_t stride = mnc ? (g->n + 7) / 8 : 0;
+    const size_t dyn = (size_t)(kGenNT / kWave) * stride * sizeof(uint32_t);
+    if (mnc)
+        hipLaunchKernelGGL(k_generic<true>, dim3(blocks), dim3(kGenNT), dyn, st, g->off, g->adj,
+                           g->n, P, chunk_off, cursor, stride, out);
+    else
+        hipLaunchKernelGGL(k_generic<false>, dim3(blocks), dim3(kGenNT), 0, st, g->off, g->adj,
+                           g->n, P, chunk_off, cursor, 0, out);
     GPM_LAUNCH_CHECK("k_generic");
     return GPM_OK;
 }

@@ -484,7 +484,7 @@ gpm_status motif_enum_count(const gpm_graph *g, int k, void *ws, uint64_t ws_byt
     // the connectivity map needs 4 bits per vertex per wave in LDS; k = 3
     // gains nothing from it (its one lookup per candidate is no cheaper than
     // marking the two rows)
-    const char *env = getenv("GPM_MOTIF_MNC");
+    const char *env = getenv("GPM_MNC");
     const bool mnc = k >= 4 && g->n <= kMncMaxN && !(env && env[0] == '0');
     const int32_t stride = mnc ? (g->n + 7) / 8 : 0;   // words
     const size_t dyn = (size_t)kMeWaves * stride * sizeof(uint32_t);

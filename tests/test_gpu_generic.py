@@ -101,3 +101,34 @@ def test_generic_errors(gpm):
         gpm.list_embeddings(g, gpm.pattern(5, house, gpm.EDGE_INDUCED | gpm.LIST), 16)
     with pytest.raises(gpm.GpmError):
         gpm.count(g, gpm.pattern(7, [(i, i + 1) for i in range(6)], gpm.EDGE_INDUCED))
+
+
+@pytest.mark.parametrize("gi", [0, 2])
+def test_without_connectivity_map(gpm, gi, monkeypatch):
+    """GPM_MNC=0: adjacency from binary searches instead of the per-wave map
+    (patterns of up to 5 vertices use the map by default)."""
+    e = graphs()[gi]
+    print(f"graph {gi} n={e.n}", flush=True)
+    g = build(gpm, e)
+    off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+    monkeypatch.setenv("GPM_MNC", "0")
+    for induced in (False, True):
+        flags = gpm.VERTEX_INDUCED if induced else gpm.EDGE_INDUCED
+        for name, (k, edges) in PATTERNS.items():
+            if k > 5:
+                continue
+            want, _ = oracle.pattern_count(off, adj, k, edges, induced)
+            assert gpm.count(g, gpm.pattern(k, edges, flags)) == want, (name, induced)
+
+
+def test_map_limit(gpm):
+    """A graph above the map's vertex limit (binary searches) and the
+    local-count route agree on the induced 4-cycles and 4-paths."""
+    e = graphgen.erdos_renyi(20000, 8.0 / 20000, 12)
+    g = build(gpm, e)
+    motifs = gpm.motif_count(g, 4)
+    names = list(gpm.MOTIF4_NAMES)
+    P = brute.PATTERNS_ANY
+    for name in ("4-path", "4-cycle"):
+        got = gpm.count(g, gpm.pattern(4, P[name][1], gpm.VERTEX_INDUCED))
+        assert got == motifs[names.index(name)], name

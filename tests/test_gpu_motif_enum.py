@@ -128,13 +128,13 @@ def test_two_routes_agree_rmat(gpm):
 
 @pytest.mark.parametrize("gi", [0, 2, 4])
 def test_without_connectivity_map(gpm, gi, monkeypatch):
-    """GPM_MOTIF_MNC=0 takes the connectivity bits from binary searches in
+    """GPM_MNC=0 takes the connectivity bits from binary searches in
     the embedding's rows instead of the per-wave map: same counts."""
     e = graphs()[gi]
     print(f"graph {gi} n={e.n}", flush=True)
     g = build(gpm, e)
     off, adj = oracle.canonical_csr(e.n, e.u, e.v)
-    monkeypatch.setenv("GPM_MOTIF_MNC", "0")
+    monkeypatch.setenv("GPM_MNC", "0")
     assert gpm.motif_count_enum(g, 4) == oracle.motif4(off, adj)
     want = [oracle.pattern_count(off, adj, 5, gpm.motif_class_pattern(5, i), True)[0]
             for i in range(21)]
@@ -147,10 +147,51 @@ def test_map_on_and_off_agree(gpm, monkeypatch):
     e = graphgen.rmat(12, seed=5)
     g = build(gpm, e)
     on = gpm.motif_count_enum(g, 4)
-    monkeypatch.setenv("GPM_MOTIF_MNC", "0")
+    monkeypatch.setenv("GPM_MNC", "0")
     assert gpm.motif_count_enum(g, 4) == on == gpm.motif_count(g, 4)
-    monkeypatch.delenv("GPM_MOTIF_MNC")
+    monkeypatch.delenv("GPM_MNC")
     big = graphgen.erdos_renyi(20000, 6.0 / 20000, 6)
     gb = build(gpm, big)
     assert gpm.motif_count_enum(gb, 4) == gpm.motif_count(gb, 4)
     assert gpm.motif_count_enum(gb, 3) == gpm.motif_count(gb, 3)
+
+
+def test_union_and_relabel_invariance(gpm):
+    """Counts of a disjoint union are the sums of the parts' counts (with
+    isolated vertices between them), and relabelling changes nothing."""
+    parts = [graphgen.erdos_renyi(60, 0.12, 21), graphgen.complete_graph(7),
+             graphgen.EdgeList(9, np.zeros(0, np.int32), np.zeros(0, np.int32), "isolated"),
+             hub_graph()]
+    for k in (3, 4, 5):
+        want = [sum(x) for x in zip(*(gpm.motif_count_enum(build(gpm, p), k)
+                                      for p in parts if p.u.shape[0] > 0))]
+        union = graphgen.disjoint_union(parts)
+        assert gpm.motif_count_enum(build(gpm, union), k) == want
+        assert gpm.motif_count_enum(build(gpm, graphgen.relabel(union, 8)), k) == want
+
+
+def test_graph_capture_replays(gpm):
+    """The call records only kernels (fills instead of memsets), so it can be
+    captured in a HIP graph and replayed."""
+    import torch
+    e = graphgen.rmat(11, seed=3)
+    g = build(gpm, e)
+    for k in (3, 4):
+        eager = torch.tensor(gpm.motif_count_enum(g, k), dtype=torch.int64, device="cuda")
+        ws = torch.empty(gpm.motif_enum_workspace_bytes(g, k), dtype=torch.uint8, device="cuda")
+        out = torch.zeros_like(eager)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            gpm.motif_count_enum(g, k, ws=ws, out=out)   # warm up outside capture
+        torch.cuda.current_stream().wait_stream(s)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            gpm.motif_count_enum(g, k, ws=ws, out=out)
+        for r in range(4):
+            out.zero_()
+            junk = torch.randn(1000, device="cuda").sum()   # eager work between replays
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out, eager), (k, r)
+            del junk
