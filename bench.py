@@ -284,6 +284,39 @@ def generic_leg(gpm, torch, scale, reps=3):
     return res
 
 
+def local_graph_leg(gpm, torch, scale, reps=3):
+    """4- and 5-clique counts on RMAT-`scale` through the local-graph
+    kernels (the default) and through the depth-first search without local
+    graphs (GPM_LG=0): the search on a local graph of the paper, as an
+    ablation."""
+    import graphgen
+    e = graphgen.rmat(scale, seed=scale)
+    g = gpm.Graph.build(e.n, torch.from_numpy(e.u).cuda(), torch.from_numpy(e.v).cuda())
+
+    def timed(fn):
+        out = fn()   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) * 1e3 / reps
+
+    res = {"workload": f"rmat{scale}: 4- and 5-clique counts with and without local graphs",
+           "m": g.m}
+    for k in (4, 5):
+        p = gpm.clique(k)
+        c, ms = timed(lambda: gpm.count(g, p))
+        os.environ["GPM_LG"] = "0"
+        try:
+            c_off, ms_off = timed(lambda: gpm.count(g, p))
+        finally:
+            del os.environ["GPM_LG"]
+        res[f"clique{k}"] = {"count": c, "ms": ms, "ms_without_local_graphs": ms_off,
+                             "same": c == c_off, "local_graph_speedup": ms_off / ms}
+    return res
+
+
 def motif_enum_leg(gpm, torch, scale4=12, scale5=10, reps=3):
     """Pattern-oblivious motif counting (vertex extension of canonical
     embeddings, connectivity codes; no counting formulas): the 4-motifs of
@@ -363,6 +396,9 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--no-generic", action="store_true")
     ap.add_argument("--no-motif-enum", action="store_true")
+    ap.add_argument("--no-lg-ablation", action="store_true")
+    ap.add_argument("--lg-ablation-only", action="store_true",
+                    help="time only the local-graph ablation leg (for kernel traces) and exit")
     ap.add_argument("--motif-enum-only", action="store_true",
                     help="time only the pattern-oblivious motif leg (for kernel traces) and exit")
     ap.add_argument("--generic-only", action="store_true",
@@ -389,6 +425,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.generic_only:
         print(json.dumps({"generic_pattern": generic_leg(gpm, torch, 13)}))
+        return
+    if args.lg_ablation_only:
+        print(json.dumps({"local_graph_ablation": local_graph_leg(gpm, torch, 14)}))
         return
     if args.motif_enum_only:
         print(json.dumps({"motif_enumeration": motif_enum_leg(gpm, torch)}))
@@ -510,6 +549,9 @@ def main():
     if not args.no_motif_enum:
         log("motif enumeration")
         res["motif_enumeration"] = motif_enum_leg(gpm, torch)
+    if not args.no_lg_ablation:
+        log("local-graph ablation")
+        res["local_graph_ablation"] = local_graph_leg(gpm, torch, 14)
     if not args.no_serve:
         log("serving load")
         g_res = gpm.Graph.build(e.n, u, v)

@@ -97,6 +97,10 @@ gpm_status gpm_pattern_clique(int32_t k, uint32_t flags, gpm_pattern *out);
 /* Plan chosen for a pattern (Section 4.3 enablement rules: orientation
  * iff the pattern is a clique, |E| = |V|(|V|-1)/2 (Appendix B.2); a
  * matching order with partial orders for other single explicit patterns). */
+/* Cliques of k >= 4 are searched on local graphs (Section 5) for
+ * out-degrees up to 1024; GPM_LG=0 in the environment sends them to the
+ * depth-first search without local graphs instead (same results; for
+ * comparison). */
 #define GPM_PLAN_CLIQUE_DAG     1   /* triangles and k-cliques, k <= 8 */
 #define GPM_PLAN_SL_DIAMOND     2   /* edge-induced diamond listing/counting */
 #define GPM_PLAN_SL_4CYCLE      3   /* edge-induced 4-cycle listing/counting */

@@ -30,6 +30,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 
 namespace gpm {
 
@@ -574,9 +575,13 @@ int64_t chunk_bound(const gpm_graph *g) {
 }
 
 // The generic DFS serves out-degrees above 1024 and listings of k >= 6;
-// everything else runs on the triangle and local-graph kernels.
+// everything else runs on the triangle and local-graph kernels.  GPM_LG=0 in
+// the environment sends k >= 4 to the generic DFS as well (the search
+// without local graphs, for comparison).
 bool uses_generic(const gpm_graph *g, int32_t k, bool list) {
-    return g->max_out_degree > kTcMax || (list && k > 5);
+    const char *env = getenv("GPM_LG");
+    const bool no_lg = k >= 4 && env && env[0] == '0';
+    return g->max_out_degree > kTcMax || (list && k > 5) || no_lg;
 }
 
 CliqueWs clique_layout(const gpm_graph *g, int32_t k, bool list, void *base) {

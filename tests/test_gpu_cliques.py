@@ -357,3 +357,20 @@ def test_rmat_clique_counts_golden(gpm, scale):
     for k in (3, 4, 5):
         print(f"rmat{scale} k={k}", flush=True)
         assert gpm.count(g, gpm.clique(k)) == gold[f"clique{k}"], k
+
+
+@pytest.mark.parametrize("case", [1, 3, 4])
+def test_without_local_graphs(gpm, case, monkeypatch):
+    """GPM_LG=0 sends k >= 4 to the depth-first search without local graphs:
+    the same counts, and the same listing totals and checksums."""
+    e = clique_cases()[case]
+    print(f"clique case {case} {e.name}", flush=True)
+    g = build(gpm, e)
+    want = {k: gpm.count(g, gpm.clique(k)) for k in (4, 5)}
+    lists = {k: gpm.list_embeddings(g, gpm.clique(k, gpm.VERTEX_INDUCED | gpm.LIST), 1 << 16)[:3]
+             for k in (4, 5)}
+    monkeypatch.setenv("GPM_LG", "0")
+    for k in (4, 5):
+        assert gpm.count(g, gpm.clique(k)) == want[k], k
+        got = gpm.list_embeddings(g, gpm.clique(k, gpm.VERTEX_INDUCED | gpm.LIST), 1 << 16)
+        assert got[0] == lists[k][0] and got[2] == lists[k][2], k
