@@ -59,7 +59,7 @@ MEASURED_TRAFFIC = {
     "kernel": "k_lg5<1024>",
     "source": "paper_2011_03135_amd/csrc/local_graph.hip",
     "source_sha256_prefix": "cc3a8fbff81d4584",
-    "bytes_read": 267814 * 1024 * 2,
+    "bytes_read": 268083 * 1024 * 2,
     "bytes_written": 959 * 1024,
 }
 
