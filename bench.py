@@ -284,6 +284,31 @@ def generic_leg(gpm, torch, scale, reps=3):
     return res
 
 
+def large_k_leg(gpm, torch, plan=((16, 8), (18, 7), (20, 6))):
+    """k-clique counts for growing k (the paper's large-pattern experiment):
+    for each (scale, kmax), RMAT-`scale` and k = 4..kmax, one timed
+    gpm_count call each (after a warm-up call for k <= 6; the larger k run
+    for seconds, where a launch's start-up cost does not show)."""
+    import graphgen
+    out = []
+    for scale, kmax in plan:
+        e = graphgen.rmat(scale, seed=scale)
+        g = gpm.Graph.build(e.n, torch.from_numpy(e.u).cuda(), torch.from_numpy(e.v).cuda())
+        for k in range(4, kmax + 1):
+            p = gpm.clique(k)
+            if k <= 6:
+                gpm.count(g, p)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c = gpm.count(g, p)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            log(f"rmat{scale} {k}-cliques: {c} in {ms:.1f} ms")
+            out.append({"scale": scale, "k": k, "count": c, "ms": ms,
+                        "cliques_per_sec": c / (ms * 1e-3)})
+    return {"workload": "k-clique counts on RMAT graphs for growing k", "runs": out}
+
+
 def local_graph_leg(gpm, torch, scale, reps=3):
     """4- and 5-clique counts on RMAT-`scale` through the local-graph
     kernels (the default) and through the depth-first search without local
@@ -397,6 +422,8 @@ def main():
     ap.add_argument("--no-generic", action="store_true")
     ap.add_argument("--no-motif-enum", action="store_true")
     ap.add_argument("--no-lg-ablation", action="store_true")
+    ap.add_argument("--large-k-only", action="store_true",
+                    help="only count k-cliques for k = 4..8 on RMAT-16/18/20 (minutes) and exit")
     ap.add_argument("--lg-ablation-only", action="store_true",
                     help="time only the local-graph ablation leg (for kernel traces) and exit")
     ap.add_argument("--motif-enum-only", action="store_true",
@@ -425,6 +452,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.generic_only:
         print(json.dumps({"generic_pattern": generic_leg(gpm, torch, 13)}))
+        return
+    if args.large_k_only:
+        print(json.dumps({"large_k_cliques": large_k_leg(gpm, torch)}))
         return
     if args.lg_ablation_only:
         print(json.dumps({"local_graph_ablation": local_graph_leg(gpm, torch, 14)}))
