@@ -55,6 +55,8 @@ def _load():
         lib.orc_wedges.argtypes = [i32, p, p]
         lib.orc_pattern_count.argtypes = [i32, p, p, i32, i32, p, i32, i32, p]
         lib.orc_pattern_count.restype = ctypes.c_int
+        lib.orc_core_numbers.argtypes = [i32, p, p, p]
+        lib.orc_core_numbers.restype = ctypes.c_int
         lib.orc_clique_count_sampled.argtypes = [i32, p, p, i32, i32, i32, p]
         lib.orc_clique_count_sampled.restype = ctypes.c_int
         for f in (lib.orc_clique_count, lib.orc_clique_list, lib.orc_edge_triangles,
@@ -198,6 +200,16 @@ def batch_motifs(batch, k, threads=1):
         off, adj = canonical_csr(e.n, e.u, e.v)
         out.append(motif3(off, adj, threads) if k == 3 else motif4(off, adj, threads))
     return out
+
+
+def core_numbers(off, adj):
+    """Core number of every vertex (the core values of Appendix B.2's
+    core-based orientation): by bucket peeling, a vertex's remaining degree
+    when it is removed."""
+    off, adj, n = _prep(off, adj)
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    _check(_load().orc_core_numbers(n, _ptr(off), _ptr(adj), _ptr(out)), "core_numbers")
+    return out[:n]
 
 
 def pattern_count(off, adj, k, edges, induced, threads=0):

@@ -113,7 +113,27 @@ static int64_t merge_into(const int32_t *a, int64_t na, const int32_t *b, int64_
 /* Degeneracy order (Batagelj and Zaversnik bucket peeling): vertices are
  * removed one at a time, always one of least remaining degree; pos[v] is
  * v's removal step, a total order on the vertices. */
+static int core_peel(int32_t n, const int64_t *off, const int32_t *adj, int32_t *pos,
+                     int32_t *core);
+
 static int core_positions(int32_t n, const int64_t *off, const int32_t *adj, int32_t *pos)
+{
+    return core_peel(n, off, adj, pos, NULL);
+}
+
+/* Core numbers (Appendix B.2's core values): a vertex's remaining degree
+ * when the peeling removes it is the largest k whose k-core holds it. */
+int orc_core_numbers(int32_t n, const int64_t *off, const int32_t *adj, int32_t *core)
+{
+    int32_t *pos = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!pos) return ORC_NO_MEMORY;
+    int rc = core_peel(n, off, adj, pos, core);
+    free(pos);
+    return rc;
+}
+
+static int core_peel(int32_t n, const int64_t *off, const int32_t *adj, int32_t *pos,
+                     int32_t *core)
 {
     size_t nn = (size_t)(n > 0 ? n : 1);
     int32_t *d = malloc(sizeof(int32_t) * nn);
@@ -136,6 +156,7 @@ static int core_positions(int32_t n, const int64_t *off, const int32_t *adj, int
     for (int32_t i = 0; i < n; i++) {
         int32_t v = vert[i];
         pos[v] = i;
+        if (core) core[v] = d[v];
         for (int64_t e = off[v]; e < off[v + 1]; e++) {
             int32_t u = adj[e];
             if (d[u] > d[v]) {                  /* u not yet removed: lower its degree */

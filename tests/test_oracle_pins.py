@@ -284,3 +284,49 @@ def test_pattern_count_matches_other_routes():
         oracle.list_diamonds(off, adj)[0]
     assert oracle.pattern_count(off, adj, 4, brute.PATTERNS4["4-cycle"], False)[0] == \
         oracle.list_c4(off, adj)[0]
+
+
+# ------------------------------------------------------------ core numbers --
+def brute_core_numbers(n, u, v):
+    """The definition: the k-core is what remains after deleting vertices of
+    degree < k until none is left; a vertex's core number is the largest k
+    whose k-core holds it."""
+    adj = brute.adjacency_sets(n, u, v)
+    core = [0] * n
+    k = 1
+    alive = set(range(n))
+    while alive:
+        changed = True
+        while changed:
+            changed = False
+            for x in list(alive):
+                if sum(1 for y in adj[x] if y in alive) < k:
+                    alive.discard(x)
+                    changed = True
+        for x in alive:
+            core[x] = k
+        k += 1
+    return core
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_core_numbers_brute_force(seed):
+    e = graphgen.erdos_renyi(40, 0.12 + 0.04 * seed, 300 + seed)
+    off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+    assert list(oracle.core_numbers(off, adj)) == brute_core_numbers(e.n, e.u, e.v)
+
+
+def test_core_numbers_closed_forms():
+    cases = [(graphgen.complete_graph(9), lambda i: 8),
+             (graphgen.star_graph(30), lambda i: 1),
+             (graphgen.cycle_graph(25), lambda i: 2),
+             (graphgen.path_graph(12), lambda i: 1),
+             (graphgen.complete_bipartite(4, 9), lambda i: 4)]
+    for e, want in cases:
+        off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+        assert list(oracle.core_numbers(off, adj)) == [want(i) for i in range(e.n)], e.name
+    # K_5 and a pendant path hanging off it: 4 on the clique, 1 on the path
+    u = [a for a in range(5) for b in range(a + 1, 5)] + [4, 5, 6]
+    v = [b for a in range(5) for b in range(a + 1, 5)] + [5, 6, 7]
+    off, adj = oracle.canonical_csr(8, np.array(u, np.int32), np.array(v, np.int32))
+    assert list(oracle.core_numbers(off, adj)) == [4, 4, 4, 4, 4, 1, 1, 1]
