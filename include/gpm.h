@@ -183,6 +183,24 @@ gpm_status gpm_graph_get_info(const gpm_graph *g, gpm_graph_info *info);
 /* Frees the host handle (not the caller's device memory).  NULL is a no-op. */
 void gpm_graph_release(gpm_graph *g);
 
+/* Orientation of the graph's DAG (Appendix B.2: by degree, the build's
+ * default, or by core value).  GPM_ORIENT_CORE computes every vertex's core
+ * number (the largest k whose k-core holds it) and rebuilds the DAG with
+ * arc u -> v iff (core(u), deg(u), u) < (core(v), deg(v), v), degrees
+ * capped at 2^(31 - bits of the largest core) - 1; GPM_ORIENT_DEGREE
+ * rebuilds the degree order (deg(u), u) < (deg(v), v).  The DAG arrays are rewritten in
+ * place in the graph's storage and the handle's max_out_degree is updated;
+ * counts do not depend on the orientation.  d_core (device int32[n], may be
+ * NULL) receives the core numbers; they are computed (for d_core) under
+ * either order.  d_scratch is only used during the call; the call
+ * synchronises the stream (the peeling reads a counter per round).  Must
+ * not run while other work on the same graph is in flight. */
+#define GPM_ORIENT_DEGREE 1
+#define GPM_ORIENT_CORE   2
+gpm_status gpm_graph_orient_bytes(const gpm_graph *g, uint64_t *scratch_bytes);
+gpm_status gpm_graph_orient(gpm_graph *g, int32_t order, void *d_scratch, uint64_t scratch_bytes,
+                            int32_t *d_core, void *stream);
+
 /* ------------------------------------------------- counting, listing --- */
 
 /* Workspace needed by gpm_count / gpm_list for pattern p on graph g. */

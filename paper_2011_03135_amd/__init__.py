@@ -35,6 +35,8 @@ from .binding import (  # noqa: F401
     timing_enable,
     timing_read,
     workspace_bytes,
+    ORIENT_DEGREE,
+    ORIENT_CORE,
     MOTIF3_NAMES,
     MOTIF4_NAMES,
     VERTEX_INDUCED,

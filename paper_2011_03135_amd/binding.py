@@ -11,6 +11,8 @@ VERTEX_INDUCED = 0x1
 EDGE_INDUCED = 0x2
 LIST = 0x4
 
+ORIENT_DEGREE = 1
+ORIENT_CORE = 2
 MOTIF3_NAMES = ("wedge", "triangle")
 MOTIF4_NAMES = ("3-star", "4-path", "4-cycle", "tailed-triangle", "diamond", "4-clique")
 
@@ -77,6 +79,8 @@ def load():
         "gpm_clique_counts": ([P, i32, P, u64, P, P], i32),
         "gpm_motif_workspace_bytes": ([P, i32, P], i32),
         "gpm_motif_count": ([P, i32, P, u64, P, P], i32),
+        "gpm_graph_orient_bytes": ([P, P], i32),
+        "gpm_graph_orient": ([P, i32, P, u64, P, P], i32),
         "gpm_motif_classes": ([i32], i32),
         "gpm_motif_class_pattern": ([i32, i32, P], i32),
         "gpm_motif_enum_workspace_bytes": ([P, i32, P], i32),
@@ -225,6 +229,28 @@ class Graph:
                                          1 if validate else 0, _ptr(storage), gb, _ptr(scratch),
                                          sb, _stream(stream), ctypes.byref(h)))
         return cls(h, storage, off.device)
+
+    def orient(self, order, stream=None, scratch=None, core_out=None):
+        """gpm_graph_orient: rebuild the DAG by degree (ORIENT_DEGREE) or by
+        core value (ORIENT_CORE); returns the core numbers (int32 device
+        tensor) when core_out is True or a tensor to fill, else None."""
+        nb = ctypes.c_uint64()
+        _check(load().gpm_graph_orient_bytes(self._h, ctypes.byref(nb)))
+        if scratch is None or scratch.numel() < nb.value:
+            scratch = _buffer(nb.value, self.device)
+        core = None
+        if core_out is True:
+            core = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
+        elif core_out is not None and core_out is not False:
+            core = core_out
+        _check(load().gpm_graph_orient(self._h, int(order), _ptr(scratch), scratch.numel(),
+                                       _ptr(core) if core is not None else None,
+                                       _stream(stream)))
+        info = _GraphInfo()
+        _check(load().gpm_graph_get_info(self._h, ctypes.byref(info)))
+        self.max_out_degree = info.max_out_degree
+        self._info = info
+        return core[:self.n] if core is not None else None
 
     def csr(self):
         """(off, adj) views (int32 device tensors) of the symmetric CSR."""

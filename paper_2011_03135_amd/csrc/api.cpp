@@ -35,6 +35,9 @@ gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, void *ws, uin
 gpm_status sl_run(const gpm_graph *g, int32_t plan, bool list, void *ws, uint64_t ws_bytes,
                   unsigned long long *d_count, int32_t *d_buf, uint64_t cap,
                   unsigned long long *d_result, hipStream_t st);
+uint64_t orient_scratch_bytes(const gpm_graph *g);
+gpm_status graph_orient(gpm_graph *g, int32_t order, void *scratch, uint64_t scratch_bytes,
+                        int32_t *d_core, hipStream_t st);
 int motif_classes(int k);
 gpm_status motif_class_pattern(int k, int idx, gpm_pattern *out);
 gpm_status motif_enum_workspace_bytes(const gpm_graph *g, uint64_t *bytes);
@@ -247,6 +250,26 @@ gpm_status gpm_graph_get_info(const gpm_graph *g, gpm_graph_info *info) {
 }
 
 void gpm_graph_release(gpm_graph *g) { delete g; }
+
+gpm_status gpm_graph_orient_bytes(const gpm_graph *g, uint64_t *scratch_bytes) {
+    gpm_status rc = check_graph(g);
+    if (rc) return rc;
+    if (!scratch_bytes) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    *scratch_bytes = gpm::orient_scratch_bytes(g);
+    return GPM_OK;
+}
+
+gpm_status gpm_graph_orient(gpm_graph *g, int32_t order, void *d_scratch, uint64_t scratch_bytes,
+                            int32_t *d_core, void *stream) {
+    gpm_status rc = check_graph(g);
+    if (rc) return rc;
+    if (order != GPM_ORIENT_DEGREE && order != GPM_ORIENT_CORE)
+        return fail(GPM_INVALID_ARGUMENT, "order must be GPM_ORIENT_DEGREE or GPM_ORIENT_CORE");
+    if (!d_scratch || !aligned256(d_scratch))
+        return fail(GPM_INVALID_ARGUMENT, "scratch NULL or unaligned");
+    return gpm::graph_orient(g, order, d_scratch, scratch_bytes, d_core,
+                             static_cast<hipStream_t>(stream));
+}
 
 gpm_status gpm_workspace_bytes(const gpm_graph *g, const gpm_pattern *p, uint64_t *bytes) {
     gpm_status rc = check_graph(g);

@@ -743,6 +743,7 @@ struct BuildLayout {
     // graph storage
     int32_t *off, *adj, *dag_off, *dag_adj, *dag_src;
     int64_t *meta;
+    int32_t *okey;
     // scratch
     int32_t *cnt, *raw_off, *raw_adj, *ucnt, *outcnt, *big_list, *med_list;
     int32_t S, nb;                                  // buckets of 2^S source ids (S = 0: none)
@@ -774,6 +775,7 @@ BuildLayout layout(int32_t n, int64_t E, void *gmem, void *smem) {
     L.dag_adj = g.take<int32_t>((uint64_t)E);
     L.dag_src = g.take<int32_t>((uint64_t)E);
     L.meta = g.take<int64_t>(8);
+    L.okey = g.take<int32_t>((uint64_t)n + 1);
     L.graph_bytes = g.used;
     Carve s(smem, ~0ull);
     L.cnt = s.take<int32_t>((uint64_t)n + 1);
@@ -866,6 +868,8 @@ gpm_status graph_build(int32_t n, const int32_t *d_u, const int32_t *d_v, int64_
     g->dag_off = L.dag_off;
     g->dag_adj = L.dag_adj;
     g->dag_src = L.dag_src;
+    g->okey = nullptr;
+    g->okey_buf = L.okey;
     *out = g;
     return GPM_OK;
 }
@@ -949,6 +953,8 @@ gpm_status graph_from_csr(int32_t n, const int32_t *d_off, const int32_t *d_adj,
     g->dag_off = L.dag_off;
     g->dag_adj = L.dag_adj;
     g->dag_src = L.dag_src;
+    g->okey = nullptr;
+    g->okey_buf = L.okey;
     *out = g;
     return GPM_OK;
 }

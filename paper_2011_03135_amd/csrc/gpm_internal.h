@@ -18,6 +18,11 @@ struct gpm_graph {
     int32_t *dag_off;   // [n+1] oriented CSR offsets
     int32_t *dag_adj;   // [m]
     int32_t *dag_src;   // [m] source of each arc
+    // orientation key: arc u -> v iff (key(u), u) < (key(v), v); nullptr
+    // means the degree, else okey[v] (the core-value key, in okey_buf: n + 1
+    // int32 of the graph storage)
+    int32_t *okey;
+    int32_t *okey_buf;
 };
 
 namespace gpm {

@@ -90,12 +90,14 @@ template <int DMAX> struct LgHash {
 // Builds the local graph of root u (d out-neighbours, W words per row) in
 // LDS: row a gets bit b for every pair (v, w) of the root with v, w the
 // out-neighbours of local indices a and b.  Local indices are positions in
-// the out-list, or with RANK positions in the degree order (off = the
-// symmetric CSR offsets give the degrees; lidx, d entries, receives them),
-// which makes every row hold only bits above its own index.
+// the out-list, or with RANK positions in the DAG's order: by (key, id), the
+// key being okey[v] when the graph is oriented by core value, else the
+// degree (off = the symmetric CSR offsets); lidx, d entries, receives them.
+// That makes every row hold only bits above its own index.
 // keys/vals/pre/offj are the root's staging area; ends with a barrier.
 template <int DMAX, int NT, bool RANK>
-__device__ void build_rows(const int32_t *__restrict__ off, const int32_t *__restrict__ dag_off,
+__device__ void build_rows(const int32_t *__restrict__ off, const int32_t *__restrict__ okey,
+                           const int32_t *__restrict__ dag_off,
                            const int32_t *__restrict__ dag_adj, int32_t u, int32_t d, int32_t W,
                            uint64_t *rows, int32_t *keys, int16_t *vals, int32_t *pre,
                            int32_t *offj, int16_t *lidx, int32_t *s_sum,
@@ -110,7 +112,8 @@ __device__ void build_rows(const int32_t *__restrict__ off, const int32_t *__res
         uint64_t *key = rows;
         for (int32_t i = threadIdx.x; i < d; i += NT) {
             const int32_t v = dag_adj[s + i];
-            key[i] = ((uint64_t)(uint32_t)(off[v + 1] - off[v]) << 32) | (uint32_t)v;
+            const int32_t kv = okey ? okey[v] : off[v + 1] - off[v];
+            key[i] = ((uint64_t)(uint32_t)kv << 32) | (uint32_t)v;
         }
         __syncthreads();
         for (int32_t i = threadIdx.x; i < d; i += NT) {
@@ -267,6 +270,7 @@ __device__ __forceinline__ uint64_t local_tri_dispatch(int32_t W, const uint64_t
 // edge.  With LIST every 4-clique (u, v_i, v_j, v_x) is emitted instead.
 template <int DMAX, int NT, bool LIST, bool RANK>
 __global__ void __launch_bounds__(NT, DMAX == kHalfMaxD ? 6 : 1) k_lg4(const int32_t *__restrict__ off,
+                                            const int32_t *__restrict__ okey,
                                             const int32_t *__restrict__ dag_off,
                                             const int32_t *__restrict__ dag_adj,
                                             const int32_t *__restrict__ roots,
@@ -292,7 +296,7 @@ __global__ void __launch_bounds__(NT, DMAX == kHalfMaxD ? 6 : 1) k_lg4(const int
         const int32_t u = roots[r];
         const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
         if (d <= dlo || d > DMAX) continue;
-        build_rows<DMAX, NT, RANK>(off, dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj,
+        build_rows<DMAX, NT, RANK>(off, okey, dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj,
                                    RANK ? lidx : nullptr, sh.s_sum, LIST ? verts : nullptr);
         const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
         if (res3 && tid == 0 && ne) atomicAdd(res3, (unsigned long long)ne);   // triangles at u
@@ -332,6 +336,7 @@ __global__ void __launch_bounds__(NT, DMAX == kHalfMaxD ? 6 : 1) k_lg4(const int
 // HBM, and local triangle counts for slicing.
 template <int DMAX, int NT>
 __global__ void __launch_bounds__(NT, DMAX == kHalfMaxD ? 6 : 1) k_lg_build(const int32_t *__restrict__ off,
+                                                 const int32_t *__restrict__ okey,
                                                  const int32_t *__restrict__ dag_off,
                                                  const int32_t *__restrict__ dag_adj,
                                                  const int32_t *__restrict__ roots,
@@ -360,7 +365,7 @@ __global__ void __launch_bounds__(NT, DMAX == kHalfMaxD ? 6 : 1) k_lg_build(cons
         const int32_t u = roots[r];
         const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
         if (d <= dlo || d > DMAX) continue;
-        build_rows<DMAX, NT, true>(off, dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj,
+        build_rows<DMAX, NT, true>(off, okey, dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj,
                                    lidx, sh.s_sum, verts);
         uint64_t *dst = grows + rowoff[r];
         for (int32_t i = tid; i < d * W; i += NT) dst[i] = rows[i];
@@ -674,6 +679,7 @@ __global__ void __launch_bounds__(1024) k_lg5(const int32_t *__restrict__ dag_of
 // trip through HBM.
 template <int DMAX, int NT, bool LIST>
 __global__ void __launch_bounds__(NT) k_lg5_mid(const int32_t *__restrict__ off,
+                                                const int32_t *__restrict__ okey,
                                                 const int32_t *__restrict__ dag_off,
                                                 const int32_t *__restrict__ dag_adj,
                                                 const int32_t *__restrict__ roots,
@@ -706,7 +712,7 @@ __global__ void __launch_bounds__(NT) k_lg5_mid(const int32_t *__restrict__ off,
         if (r >= nroots) break;
         const int32_t u = roots[r];
         const int32_t d = dag_off[u + 1] - dag_off[u], W = (d + 63) >> 6;
-        build_rows<DMAX, NT, true>(off, dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj,
+        build_rows<DMAX, NT, true>(off, okey, dag_off, dag_adj, u, d, W, rows, keys, vals, pre, offj,
                                    lidx, sh.s_sum, verts);
         if (res3 || res4) {
             const int32_t ne = row_prefix<DMAX, NT>(rows, d, W, pre, sh.s_sum);
@@ -803,14 +809,14 @@ gpm_status lg5_class(const gpm_graph *g, int32_t k, LgWs &L, const int32_t *list
         Span sp("k_lg_build<512>", st);
         hipLaunchKernelGGL((k_lg_build<kHalfMaxD, kHalfThreads>),
                            dim3((unsigned)cu_count() * kHalfBlocksPerCu), dim3(kHalfThreads), 0,
-                           st, g->off, g->dag_off, g->dag_adj, list, cnt, kMidMaxD, cursors + 2,
+                           st, g->off, g->okey, g->dag_off, g->dag_adj, list, cnt, kMidMaxD, cursors + 2,
                            rowoff, rows, L.slices, units, res3, res4);
     }
     GPM_LAUNCH_CHECK("k_lg_build<512>");
     {
         Span sp(nb, st);
         hipLaunchKernelGGL((k_lg_build<DMAX, NT>), dim3((unsigned)cu_count() * (NT <= 256 ? 8 : 1)),
-                           dim3(NT), 0, st, g->off, g->dag_off, g->dag_adj, list, cnt,
+                           dim3(NT), 0, st, g->off, g->okey, g->dag_off, g->dag_adj, list, cnt,
                            DMAX > kHalfMaxD ? kHalfMaxD : 0, cursors + 0, rowoff, rows, L.slices,
                            units, res3, res4);
     }
@@ -871,13 +877,13 @@ gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, cons
             if (em)
                 hipLaunchKernelGGL((k_lg4<kBigMaxD, kBigThreads, true, true>),
                                    dim3((unsigned)cu_count()), dim3(kBigThreads), 0, st, g->off,
-                                   g->dag_off, g->dag_adj, list_b, cnt_b, kHalfMaxD, L.ctl + 0, res,
-                                   res3, *em);
+                                   g->okey, g->dag_off, g->dag_adj, list_b, cnt_b, kHalfMaxD,
+                                   L.ctl + 0, res, res3, *em);
             else
                 hipLaunchKernelGGL((k_lg4<kBigMaxD, kBigThreads, false, true>),
                                    dim3((unsigned)cu_count()), dim3(kBigThreads), 0, st, g->off,
-                                   g->dag_off, g->dag_adj, list_b, cnt_b, kHalfMaxD, L.ctl + 0, res,
-                                   res3, none);
+                                   g->okey, g->dag_off, g->dag_adj, list_b, cnt_b, kHalfMaxD,
+                                   L.ctl + 0, res, res3, none);
         }
         GPM_LAUNCH_CHECK("k_lg4<1024>");
         {
@@ -885,11 +891,11 @@ gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, cons
             const dim3 grid((unsigned)cu_count() * kHalfBlocksPerCu);
             if (em)
                 hipLaunchKernelGGL((k_lg4<kHalfMaxD, kHalfThreads, true, true>), grid,
-                                   dim3(kHalfThreads), 0, st, g->off, g->dag_off, g->dag_adj,
+                                   dim3(kHalfThreads), 0, st, g->off, g->okey, g->dag_off, g->dag_adj,
                                    list_b, cnt_b, kMidMaxD, L.ctl + 2, res, res3, *em);
             else
                 hipLaunchKernelGGL((k_lg4<kHalfMaxD, kHalfThreads, false, true>), grid,
-                                   dim3(kHalfThreads), 0, st, g->off, g->dag_off, g->dag_adj,
+                                   dim3(kHalfThreads), 0, st, g->off, g->okey, g->dag_off, g->dag_adj,
                                    list_b, cnt_b, kMidMaxD, L.ctl + 2, res, res3, none);
         }
         GPM_LAUNCH_CHECK("k_lg4<512>");
@@ -898,11 +904,11 @@ gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, cons
             const dim3 grid((unsigned)cu_count() * 8);
             if (em)
                 hipLaunchKernelGGL((k_lg4<kMidMaxD, kMidThreads, true, false>), grid,
-                                   dim3(kMidThreads), 0, st, g->off, g->dag_off, g->dag_adj,
+                                   dim3(kMidThreads), 0, st, g->off, g->okey, g->dag_off, g->dag_adj,
                                    list_m, cnt_m, 0, L.ctl + 1, res, res3, *em);
             else
                 hipLaunchKernelGGL((k_lg4<kMidMaxD, kMidThreads, false, false>), grid,
-                                   dim3(kMidThreads), 0, st, g->off, g->dag_off, g->dag_adj,
+                                   dim3(kMidThreads), 0, st, g->off, g->okey, g->dag_off, g->dag_adj,
                                    list_m, cnt_m, 0, L.ctl + 1, res, res3, none);
         }
         GPM_LAUNCH_CHECK("k_lg4<256>");
@@ -918,11 +924,11 @@ gpm_status lg_cliques(const gpm_graph *g, int32_t k, const int32_t *list_m, cons
         const dim3 grid((unsigned)cu_count() * 8);
         if (em)
             hipLaunchKernelGGL((k_lg5_mid<kMidMaxD, kMidThreads, true>), grid, dim3(kMidThreads), 0,
-                               st, g->off, g->dag_off, g->dag_adj, list_m, cnt_m, k - 5,
+                               st, g->off, g->okey, g->dag_off, g->dag_adj, list_m, cnt_m, k - 5,
                                L.ctl + 6, res, res3, res4, *em);
         else
             hipLaunchKernelGGL((k_lg5_mid<kMidMaxD, kMidThreads, false>), grid, dim3(kMidThreads),
-                               0, st, g->off, g->dag_off, g->dag_adj, list_m, cnt_m, k - 5,
+                               0, st, g->off, g->okey, g->dag_off, g->dag_adj, list_m, cnt_m, k - 5,
                                L.ctl + 6, res, res3, res4, RowEmitter{});
     }
     GPM_LAUNCH_CHECK("k_lg5_mid");

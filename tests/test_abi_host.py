@@ -95,6 +95,8 @@ def test_null_arguments_rejected(lib):
     assert lib.gpm_count(None, None, None, 0, None, None) == 1
     assert lib.gpm_motif_count(None, 4, None, 0, None, None) == 1
     assert lib.gpm_graph_get_info(None, None) == 1
+    assert lib.gpm_graph_orient(None, 2, None, 0, None, None) == 1
+    assert lib.gpm_graph_orient_bytes(None, None) == 1
     assert b"NULL" in lib.gpm_last_error() or lib.gpm_last_error() != b""
 
 
