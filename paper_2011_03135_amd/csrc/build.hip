@@ -675,6 +675,14 @@ __global__ void __launch_bounds__(kBlock) k_orient_fill(const int32_t *__restric
     if (lane == 0 && maxo > 0) atomicMax(&flags[F_MAX_OUT], (uint32_t)maxo);
 }
 
+// Orientation key of the degree order, key[v] = deg(v): the local-graph
+// kernels rank each root's out-neighbours by (key, id), as the DAG does.
+__global__ void k_degree_key(const int32_t *__restrict__ off, int32_t n, int32_t *key) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        key[v] = off[v + 1] - off[v];
+}
+
 __global__ void k_meta(const int32_t *off, const int32_t *dag_off, int32_t n,
                        const uint32_t *flags, int64_t *meta) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -820,6 +828,13 @@ unsigned flat_grid(int64_t items) {
 
 }  // namespace
 
+hipError_t degree_key(const int32_t *off, int32_t n, int32_t *key, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<int64_t>(((int64_t)n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_degree_key, dim3(blocks), dim3(256), 0, st, off, n, key);
+    return hipGetLastError();
+}
+
 static gpm_status enqueue_build(int32_t n, const int32_t *d_u, const int32_t *d_v, int64_t E,
                                 const BuildLayout &L, hipStream_t st);
 
@@ -868,8 +883,7 @@ gpm_status graph_build(int32_t n, const int32_t *d_u, const int32_t *d_v, int64_
     g->dag_off = L.dag_off;
     g->dag_adj = L.dag_adj;
     g->dag_src = L.dag_src;
-    g->okey = nullptr;
-    g->okey_buf = L.okey;
+    g->okey = L.okey;
     *out = g;
     return GPM_OK;
 }
@@ -934,6 +948,7 @@ gpm_status graph_from_csr(int32_t n, const int32_t *d_off, const int32_t *d_adj,
         hipLaunchKernelGGL(k_orient_fill, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.off, L.adj,
                            L.dag_off, n, nnz / 2, L.dag_adj, L.dag_src, flags);
         GPM_LAUNCH_CHECK("k_orient_fill");
+        GPM_HIP(degree_key(L.off, n, L.okey, st));
         hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, st, L.off, L.dag_off, n, flags, L.meta);
         GPM_LAUNCH_CHECK("k_meta");
     }
@@ -953,8 +968,7 @@ gpm_status graph_from_csr(int32_t n, const int32_t *d_off, const int32_t *d_adj,
     g->dag_off = L.dag_off;
     g->dag_adj = L.dag_adj;
     g->dag_src = L.dag_src;
-    g->okey = nullptr;
-    g->okey_buf = L.okey;
+    g->okey = L.okey;
     *out = g;
     return GPM_OK;
 }
@@ -1030,6 +1044,7 @@ static gpm_status enqueue_build(int32_t n, const int32_t *d_u, const int32_t *d_
     hipLaunchKernelGGL(k_orient_fill, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.off, L.adj,
                        L.dag_off, n, E, L.dag_adj, L.dag_src, L.flags);
     GPM_LAUNCH_CHECK("k_orient_fill");
+    GPM_HIP(degree_key(L.off, n, L.okey, st));
     hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, st, L.off, L.dag_off, n, L.flags, L.meta);
     GPM_LAUNCH_CHECK("k_meta");
     return GPM_OK;

@@ -301,9 +301,9 @@ gpm_status graph_orient(gpm_graph *g, int32_t order, void *scratch, uint64_t scr
             // the local-graph kernels order each root's out-neighbours by the
             // same key, so it is kept with the graph
             hipLaunchKernelGGL(k_core_key, dim3(vgrid(n)), dim3(kCoreBlock), 0, st, g->off,
-                               W.core, n, 31 - bits, g->okey_buf);
+                               W.core, n, 31 - bits, g->okey);
             GPM_LAUNCH_CHECK("k_core_key");
-            key = g->okey_buf;
+            key = g->okey;
         }
     }
     hipLaunchKernelGGL(k_key_count, dim3(wgrid(n)), dim3(kCoreBlock), 0, st, g->off, g->adj, n,
@@ -314,11 +314,11 @@ gpm_status graph_orient(gpm_graph *g, int32_t order, void *scratch, uint64_t scr
     hipLaunchKernelGGL(k_key_fill, dim3(wgrid(n)), dim3(kCoreBlock), 0, st, g->off, g->adj, n,
                        key, g->dag_off, g->dag_adj, g->dag_src, W.ctl);
     GPM_LAUNCH_CHECK("k_key_fill");
+    if (!key) GPM_HIP(degree_key(g->off, n, g->okey, st));
     uint32_t maxo = 0;
     gpm_status rc = read_u32(W.ctl + C_MAX_OUT, &maxo, 1, st);
     if (rc) return rc;
     g->max_out_degree = (int32_t)maxo;
-    g->okey = key ? g->okey_buf : nullptr;
     return GPM_OK;
 }
 

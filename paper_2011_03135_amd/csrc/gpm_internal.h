@@ -18,11 +18,9 @@ struct gpm_graph {
     int32_t *dag_off;   // [n+1] oriented CSR offsets
     int32_t *dag_adj;   // [m]
     int32_t *dag_src;   // [m] source of each arc
-    // orientation key: arc u -> v iff (key(u), u) < (key(v), v); nullptr
-    // means the degree, else okey[v] (the core-value key, in okey_buf: n + 1
-    // int32 of the graph storage)
+    // [n+1] orientation key: arc u -> v iff (okey[u], u) < (okey[v], v);
+    // the degrees after a build, the core-value key after a core orientation
     int32_t *okey;
-    int32_t *okey_buf;
 };
 
 namespace gpm {
@@ -68,6 +66,8 @@ struct Carve {
 // Fill n 32-bit words with a value (a kernel, so it may sit in a captured
 // graph where memset nodes are avoided).
 hipError_t fill_u32(void *p, uint32_t value, uint64_t n, hipStream_t s);
+// key[v] = off[v + 1] - off[v] for v < n (the degree order's key).
+hipError_t degree_key(const int32_t *off, int32_t n, int32_t *key, hipStream_t s);
 // Exclusive scan of n int32 counts into out[0..n] (out[n] = total), using
 // tmp (scan_tmp_words(n) int64 words).  in and out may alias.
 uint64_t scan_tmp_words(uint64_t n);

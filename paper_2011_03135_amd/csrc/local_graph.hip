@@ -90,10 +90,10 @@ template <int DMAX> struct LgHash {
 // Builds the local graph of root u (d out-neighbours, W words per row) in
 // LDS: row a gets bit b for every pair (v, w) of the root with v, w the
 // out-neighbours of local indices a and b.  Local indices are positions in
-// the out-list, or with RANK positions in the DAG's order: by (key, id), the
-// key being okey[v] when the graph is oriented by core value, else the
-// degree (off = the symmetric CSR offsets); lidx, d entries, receives them.
-// That makes every row hold only bits above its own index.
+// the out-list, or with RANK positions in the DAG's order, by (okey, id)
+// (the graph's orientation key: degrees, or the core-value key); lidx, d
+// entries, receives them.  That makes every row hold only bits above its
+// own index.
 // keys/vals/pre/offj are the root's staging area; ends with a barrier.
 template <int DMAX, int NT, bool RANK>
 __device__ void build_rows(const int32_t *__restrict__ off, const int32_t *__restrict__ okey,
@@ -112,8 +112,7 @@ __device__ void build_rows(const int32_t *__restrict__ off, const int32_t *__res
         uint64_t *key = rows;
         for (int32_t i = threadIdx.x; i < d; i += NT) {
             const int32_t v = dag_adj[s + i];
-            const int32_t kv = okey ? okey[v] : off[v + 1] - off[v];
-            key[i] = ((uint64_t)(uint32_t)kv << 32) | (uint32_t)v;
+            key[i] = ((uint64_t)(uint32_t)okey[v] << 32) | (uint32_t)v;
         }
         __syncthreads();
         for (int32_t i = threadIdx.x; i < d; i += NT) {
