@@ -58,8 +58,8 @@ OPS_PER_LOCAL_TRIANGLE = 4
 MEASURED_TRAFFIC = {
     "kernel": "k_lg5<1024>",
     "source": "paper_2011_03135_amd/csrc/local_graph.hip",
-    "source_sha256_prefix": "cc3a8fbff81d4584",
-    "bytes_read": 268083 * 1024 * 2,
+    "source_sha256_prefix": "639ca4f1ad3b6742",
+    "bytes_read": 267714 * 1024 * 2,
     "bytes_written": 959 * 1024,
 }
 
