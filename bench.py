@@ -392,6 +392,29 @@ def motif_enum_leg(gpm, torch, scale4=12, scale5=10, reps=3):
                        "same_without_map": c5 == c5_off}}
 
 
+# The paper's own CPU figures (Sec. 6: input-graph table, TC and k-clique
+# tables), context only: real graphs, another machine, no RMAT.  #E counts
+# arcs, so undirected edges/s = (#E / 2) / time.
+PAPER_CONTEXT = {
+    "machine": "4-socket Intel Xeon Gold 5120, 2.2 GHz, 56 cores, 56 threads, 190 GB",
+    "graphs_arcs": {"Lj": 86e6, "Or": 234e6, "Tw4": 2405e6, "Fr": 3612e6, "Uk": 6604e6},
+    "tc_seconds_hi": {"Lj": 0.3, "Or": 1.8, "Tw4": 57.2, "Fr": 44.9, "Uk": 24.5},
+    "clique4_seconds_hi_lo": {"Lj": [0.6, 0.7], "Or": [2.4, 1.9], "Tw4": [1676.8, 681.8],
+                              "Fr": [166.2, 60.4], "Uk": [2481.2, 2451.7]},
+    "clique5_seconds_hi_lo": {"Lj": [13.9, 14.2], "Or": [7.4, 4.8], "Fr": [194.9, 64.3]},
+}
+
+
+def paper_context():
+    c = dict(PAPER_CONTEXT)
+    arcs = c["graphs_arcs"]
+    c["tc_edges_per_sec_hi"] = {k: arcs[k] / 2 / t for k, t in c["tc_seconds_hi"].items()}
+    c["clique4_edges_per_sec_lo"] = {k: arcs[k] / 2 / t[1]
+                                     for k, t in c["clique4_seconds_hi_lo"].items()}
+    c["note"] = "the paper's numbers on its machine and graphs; not this workload, not a target"
+    return c
+
+
 def copy_calibration():
     import torch
     n = 1 << 30
@@ -570,6 +593,7 @@ def main():
         "phases_ms": {k: round(x, 4) for k, x in phases.items()},
         "roofline": roof,
         "phase_rooflines": phase_roof,
+        "paper_context": paper_context(),
     }
     if not args.no_batch:
         res["batched_vs_plain"] = batch_leg(gpm, torch, args.batch_graphs, args.plain_graphs, 20)
