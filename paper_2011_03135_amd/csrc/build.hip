@@ -535,13 +535,16 @@ __global__ void __launch_bounds__(kBigNT) k_sort_big_rows_lds(const int32_t *__r
 }
 
 // Copies the unique rows into the final CSR and counts each vertex's arcs
-// in the degree order (degrees are the unique counts).
+// in the degree order (degrees are the unique counts); keep[i] records
+// whether arc i points up in that order, so the fill does not look the
+// degrees up again.
 __global__ void __launch_bounds__(kBlock) k_compact_rows(const int32_t *__restrict__ raw_off,
                                                          const int32_t *__restrict__ raw_adj,
                                                          const int32_t *__restrict__ off,
                                                          const int32_t *__restrict__ deg,
                                                          int32_t *adj, int32_t n,
-                                                         int32_t *outcnt, uint32_t *flags) {
+                                                         int32_t *outcnt, uint8_t *keep,
+                                                         uint32_t *flags) {
     const int lane = lane_id(), gl = lane & (kSmallRow - 1), grp = lane / kSmallRow;
     const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -562,6 +565,7 @@ __global__ void __launch_bounds__(kBlock) k_compact_rows(const int32_t *__restri
             const int32_t v = raw_adj[src + gl];
             adj[dst + gl] = v;
             c = rank_less(L, u, deg[v], v) ? 1 : 0;
+            keep[dst + gl] = (uint8_t)c;
         }
 #pragma unroll
         for (int o = kSmallRow / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
@@ -576,7 +580,9 @@ __global__ void __launch_bounds__(kBlock) k_compact_rows(const int32_t *__restri
             for (int32_t i = lane; i < wl; i += kWave) {
                 const int32_t v = raw_adj[ws + i];
                 adj[wd + i] = v;
-                cw += rank_less(wl, w, deg[v], v) ? 1 : 0;
+                const int32_t up = rank_less(wl, w, deg[v], v) ? 1 : 0;
+                keep[wd + i] = (uint8_t)up;
+                cw += up;
             }
             cw = wave_sum(cw);
             if (lane == 0) outcnt[w] = cw;
@@ -588,7 +594,8 @@ __global__ void __launch_bounds__(kBlock) k_compact_rows(const int32_t *__restri
 
 __global__ void __launch_bounds__(kBlock) k_orient_count(const int32_t *__restrict__ off,
                                                          const int32_t *__restrict__ adj,
-                                                         int32_t n, int32_t *outcnt) {
+                                                         int32_t n, int32_t *outcnt,
+                                                         uint8_t *keep) {
     const int lane = lane_id();
     const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -599,7 +606,9 @@ __global__ void __launch_bounds__(kBlock) k_orient_count(const int32_t *__restri
         for (int32_t i = lane; i < du; i += kWave) {
             int32_t v = adj[s + i];
             int32_t dv = off[v + 1] - off[v];
-            c += rank_less(du, u, dv, v) ? 1 : 0;
+            const int32_t up = rank_less(du, u, dv, v) ? 1 : 0;
+            keep[s + i] = (uint8_t)up;
+            c += up;
         }
         c = wave_sum(c);
         if (lane == 0) outcnt[u] = c;
@@ -608,6 +617,7 @@ __global__ void __launch_bounds__(kBlock) k_orient_count(const int32_t *__restri
 
 __global__ void __launch_bounds__(kBlock) k_orient_fill(const int32_t *__restrict__ off,
                                                         const int32_t *__restrict__ adj,
+                                                        const uint8_t *__restrict__ up,
                                                         const int32_t *__restrict__ dag_off,
                                                         int32_t n, int64_t cap, int32_t *dag_adj,
                                                         int32_t *dag_src, uint32_t *flags) {
@@ -627,7 +637,7 @@ __global__ void __launch_bounds__(kBlock) k_orient_fill(const int32_t *__restric
         bool keep = false;
         if (small && gl < dsu) {
             v = adj[su + gl];
-            keep = rank_less(dsu, (int32_t)row, off[v + 1] - off[v], v);
+            keep = up[su + gl] != 0;
         }
         const uint32_t gmask =
             (uint32_t)(__ballot(keep) >> (grp * kSmallRow)) & ((1u << kSmallRow) - 1u);
@@ -651,10 +661,7 @@ __global__ void __launch_bounds__(kBlock) k_orient_fill(const int32_t *__restric
                 int32_t i = i0 + lane;
                 int32_t v = i < du ? adj[s + i] : 0;
                 bool keep = false;
-                if (i < du) {
-                    int32_t dv = off[v + 1] - off[v];
-                    keep = rank_less(du, u, dv, v);
-                }
+                if (i < du) keep = up[s + i] != 0;
                 uint64_t mask = __ballot(keep);
                 if (keep) {
                     int32_t p = base + lanes_below(mask);
@@ -754,6 +761,7 @@ struct BuildLayout {
     int32_t *okey;
     // scratch
     int32_t *cnt, *raw_off, *raw_adj, *ucnt, *outcnt, *big_list, *med_list;
+    uint8_t *keep;                                  // per final arc: points up in the order
     int32_t S, nb;                                  // buckets of 2^S source ids (S = 0: none)
     int32_t *bucket_cnt, *bucket_off, *bucket_cur, *bsrc, *bdst;
     int64_t *scan_tmp;
@@ -793,6 +801,7 @@ BuildLayout layout(int32_t n, int64_t E, void *gmem, void *smem) {
     L.outcnt = s.take<int32_t>((uint64_t)n + 1);
     L.big_list = s.take<int32_t>((uint64_t)n + 1);
     L.med_list = s.take<int32_t>((uint64_t)n + 1);
+    L.keep = s.take<uint8_t>((uint64_t)(2 * E));
     L.scan_tmp = s.take<int64_t>(scan_tmp_words((uint64_t)n + 1));
     L.flags = s.take<uint32_t>(F_WORDS);
     L.S = bucket_shift(n);
@@ -898,6 +907,7 @@ gpm_status graph_from_csr_bytes(int32_t n, int64_t nnz, uint64_t *gb, uint64_t *
     s.take<int32_t>((uint64_t)n + 1);                              // out-degrees
     s.take<int64_t>(scan_tmp_words((uint64_t)n + 1));
     s.take<uint32_t>(F_WORDS);
+    s.take<uint8_t>((uint64_t)nnz);                                // arc points up
     *sb = s.used;
     return GPM_OK;
 }
@@ -920,6 +930,7 @@ gpm_status graph_from_csr(int32_t n, const int32_t *d_off, const int32_t *d_adj,
     int32_t *outcnt = sc.take<int32_t>((uint64_t)n + 1);
     int64_t *scan_tmp = sc.take<int64_t>(scan_tmp_words((uint64_t)n + 1));
     uint32_t *flags = sc.take<uint32_t>(F_WORDS);
+    uint8_t *up = sc.take<uint8_t>((uint64_t)nnz);
     {
         Span whole("graph_from_csr", st);
         GPM_HIP(fill_u32(flags, 0, F_WORDS, st));
@@ -942,11 +953,11 @@ gpm_status graph_from_csr(int32_t n, const int32_t *d_off, const int32_t *d_adj,
         GPM_HIP(hipStreamSynchronize(st));
         if (meta[4] != 0) return fail(GPM_NOT_CANONICAL, "the CSR is not in canonical form");
         hipLaunchKernelGGL(k_orient_count, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.off, L.adj,
-                           n, outcnt);
+                           n, outcnt, up);
         GPM_LAUNCH_CHECK("k_orient_count");
         GPM_HIP(exclusive_scan_i32(outcnt, L.dag_off, (uint64_t)n, scan_tmp, st));
         hipLaunchKernelGGL(k_orient_fill, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.off, L.adj,
-                           L.dag_off, n, nnz / 2, L.dag_adj, L.dag_src, flags);
+                           up, L.dag_off, n, nnz / 2, L.dag_adj, L.dag_src, flags);
         GPM_LAUNCH_CHECK("k_orient_fill");
         GPM_HIP(degree_key(L.off, n, L.okey, st));
         hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, st, L.off, L.dag_off, n, flags, L.meta);
@@ -1038,11 +1049,11 @@ static gpm_status enqueue_build(int32_t n, const int32_t *d_u, const int32_t *d_
     GPM_LAUNCH_CHECK("k_sort_big_rows");
     GPM_HIP(exclusive_scan_i32(L.ucnt, L.off, (uint64_t)n, L.scan_tmp, st));
     hipLaunchKernelGGL(k_compact_rows, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.raw_off,
-                       L.raw_adj, L.off, L.ucnt, L.adj, n, L.outcnt, L.flags);
+                       L.raw_adj, L.off, L.ucnt, L.adj, n, L.outcnt, L.keep, L.flags);
     GPM_LAUNCH_CHECK("k_compact_rows");
     GPM_HIP(exclusive_scan_i32(L.outcnt, L.dag_off, (uint64_t)n, L.scan_tmp, st));
     hipLaunchKernelGGL(k_orient_fill, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.off, L.adj,
-                       L.dag_off, n, E, L.dag_adj, L.dag_src, L.flags);
+                       L.keep, L.dag_off, n, E, L.dag_adj, L.dag_src, L.flags);
     GPM_LAUNCH_CHECK("k_orient_fill");
     GPM_HIP(degree_key(L.off, n, L.okey, st));
     hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, st, L.off, L.dag_off, n, L.flags, L.meta);
