@@ -284,7 +284,7 @@ def generic_leg(gpm, torch, scale, reps=3):
     return res
 
 
-def large_k_leg(gpm, torch, plan=((16, 8), (18, 7), (20, 6))):
+def large_k_leg(gpm, torch, plan=((12, 9), (16, 8), (18, 7), (20, 6))):
     """k-clique counts for growing k (the paper's large-pattern experiment):
     for each (scale, kmax), RMAT-`scale` and k = 4..kmax, one timed
     gpm_count call each (after a warm-up call for k <= 6; the larger k run
@@ -446,7 +446,7 @@ def main():
     ap.add_argument("--no-motif-enum", action="store_true")
     ap.add_argument("--no-lg-ablation", action="store_true")
     ap.add_argument("--large-k-only", action="store_true",
-                    help="only count k-cliques for k = 4..8 on RMAT-16/18/20 (minutes) and exit")
+                    help="only count k-cliques for k = 4..9 on RMAT-12/16/18/20 (minutes) and exit")
     ap.add_argument("--lg-ablation-only", action="store_true",
                     help="time only the local-graph ablation leg (for kernel traces) and exit")
     ap.add_argument("--motif-enum-only", action="store_true",

@@ -74,8 +74,8 @@ const char *gpm_version(void);
 #define GPM_EDGE_INDUCED   0x2u
 #define GPM_LIST           0x4u   /* listing; absent means counting */
 
-#define GPM_MAX_PATTERN_VERTICES 8
-#define GPM_MAX_PATTERN_EDGES    28
+#define GPM_MAX_PATTERN_VERTICES 9
+#define GPM_MAX_PATTERN_EDGES    36
 
 /* A pattern is an edge list on vertices 0..k-1 (Section 3.1: patterns are
  * given as edge lists, e.g. the triangle {(0,1),(0,2),(1,2)}). */
@@ -88,7 +88,7 @@ typedef struct gpm_pattern {
 
 /* Builds the pattern from an edge list (uv holds n_edges pairs, host
  * memory).  Rejects loops, repeated edges, ids outside [0, k), disconnected
- * patterns and k outside [2, 8] with GPM_INVALID_ARGUMENT. */
+ * patterns and k outside [2, 9] with GPM_INVALID_ARGUMENT. */
 gpm_status gpm_pattern_from_edges(int32_t k, int32_t n_edges, const int32_t *uv,
                                   uint32_t flags, gpm_pattern *out);
 /* The k-clique (helper named in Section 3.1); flags as above. */
@@ -101,7 +101,7 @@ gpm_status gpm_pattern_clique(int32_t k, uint32_t flags, gpm_pattern *out);
  * out-degrees up to 1024; GPM_LG=0 in the environment sends them to the
  * depth-first search without local graphs instead (same results; for
  * comparison). */
-#define GPM_PLAN_CLIQUE_DAG     1   /* triangles and k-cliques, k <= 8 */
+#define GPM_PLAN_CLIQUE_DAG     1   /* triangles and k-cliques, k <= 9 */
 #define GPM_PLAN_SL_DIAMOND     2   /* edge-induced diamond listing/counting */
 #define GPM_PLAN_SL_4CYCLE      3   /* edge-induced 4-cycle listing/counting */
 /* Any other connected pattern of 2..6 vertices, vertex- or edge-induced:
@@ -368,7 +368,7 @@ typedef struct gpm_server_config {
     uint64_t pool_bytes;
 } gpm_server_config;
 
-#define GPM_QUERY_CLIQUE 1  /* k-clique count, k = 3..8 (triangles: k = 3) */
+#define GPM_QUERY_CLIQUE 1  /* k-clique count, k = 3..9 (triangles: k = 3) */
 #define GPM_QUERY_MOTIF  2  /* induced k-motif counts, k = 3 or 4 */
 
 typedef struct gpm_request {

@@ -29,7 +29,7 @@ class GpmError(RuntimeError):
 
 class Pattern(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("n_edges", ctypes.c_int32),
-                ("edges", (ctypes.c_int32 * 2) * 28), ("flags", ctypes.c_uint32)]
+                ("edges", (ctypes.c_int32 * 2) * 36), ("flags", ctypes.c_uint32)]
 
 
 class _GraphInfo(ctypes.Structure):

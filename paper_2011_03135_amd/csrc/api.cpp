@@ -120,7 +120,7 @@ gpm_status gpm_pattern_from_edges(int32_t k, int32_t n_edges, const int32_t *uv,
                                   gpm_pattern *out) {
     if (!out) return fail(GPM_INVALID_ARGUMENT, "out is NULL");
     if (k < 2 || k > GPM_MAX_PATTERN_VERTICES)
-        return fail(GPM_INVALID_ARGUMENT, "pattern size k must be in [2, 8]");
+        return fail(GPM_INVALID_ARGUMENT, "pattern size k must be in [2, 9]");
     if (n_edges < k - 1 || n_edges > k * (k - 1) / 2 || (n_edges > 0 && !uv))
         return fail(GPM_INVALID_ARGUMENT, "edge count impossible for a connected pattern");
     uint32_t ind = flags & (GPM_VERTEX_INDUCED | GPM_EDGE_INDUCED);
@@ -133,15 +133,14 @@ gpm_status gpm_pattern_from_edges(int32_t k, int32_t n_edges, const int32_t *uv,
     p.k = k;
     p.n_edges = n_edges;
     p.flags = flags;
-    uint64_t seen = 0;
+    bool seen[GPM_MAX_PATTERN_VERTICES][GPM_MAX_PATTERN_VERTICES] = {};
     for (int32_t i = 0; i < n_edges; i++) {
         int32_t a = uv[2 * i], b = uv[2 * i + 1];
         if (a < 0 || b < 0 || a >= k || b >= k || a == b)
             return fail(GPM_INVALID_ARGUMENT, "pattern edge endpoint out of range or a loop");
         int32_t lo = a < b ? a : b, hi = a < b ? b : a;
-        uint64_t bit = 1ull << (lo * GPM_MAX_PATTERN_VERTICES + hi);
-        if (seen & bit) return fail(GPM_INVALID_ARGUMENT, "repeated pattern edge");
-        seen |= bit;
+        if (seen[lo][hi]) return fail(GPM_INVALID_ARGUMENT, "repeated pattern edge");
+        seen[lo][hi] = true;
         p.edges[i][0] = a;
         p.edges[i][1] = b;
     }
@@ -153,7 +152,7 @@ gpm_status gpm_pattern_from_edges(int32_t k, int32_t n_edges, const int32_t *uv,
 
 gpm_status gpm_pattern_clique(int32_t k, uint32_t flags, gpm_pattern *out) {
     if (k < 2 || k > GPM_MAX_PATTERN_VERTICES)
-        return fail(GPM_INVALID_ARGUMENT, "clique size must be in [2, 8]");
+        return fail(GPM_INVALID_ARGUMENT, "clique size must be in [2, 9]");
     int32_t uv[GPM_MAX_PATTERN_EDGES * 2];
     int32_t ne = 0;
     for (int32_t a = 0; a < k; a++)
@@ -172,21 +171,20 @@ gpm_status gpm_pattern_plan(const gpm_pattern *p, int32_t *plan) {
     // gpm_pattern_from_edges would before reading its edges
     if (k < 2 || k > GPM_MAX_PATTERN_VERTICES || ne < k - 1 || ne > k * (k - 1) / 2)
         return fail(GPM_INVALID_ARGUMENT, "pattern size or edge count out of range");
-    uint64_t seen = 0;
+    bool seen[GPM_MAX_PATTERN_VERTICES][GPM_MAX_PATTERN_VERTICES] = {};
     for (int32_t i = 0; i < ne; i++) {
         const int32_t a = p->edges[i][0], b = p->edges[i][1];
         if (a < 0 || b < 0 || a >= k || b >= k || a == b)
             return fail(GPM_INVALID_ARGUMENT, "pattern edge endpoint out of range or a loop");
         const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
-        const uint64_t bit = 1ull << (lo * GPM_MAX_PATTERN_VERTICES + hi);
-        if (seen & bit) return fail(GPM_INVALID_ARGUMENT, "repeated pattern edge");
-        seen |= bit;
+        if (seen[lo][hi]) return fail(GPM_INVALID_ARGUMENT, "repeated pattern edge");
+        seen[lo][hi] = true;
     }
     const bool vertex_induced = (p->flags & GPM_VERTEX_INDUCED) != 0;
     // Orientation iff the pattern is a clique, |E| = |V|(|V|-1)/2; for a
     // clique, vertex- and edge-induced embeddings coincide.
     if (ne == k * (k - 1) / 2 && k >= 3) {
-        if (k > 8) return fail(GPM_UNSUPPORTED, "cliques up to 8 vertices");
+        if (k > 9) return fail(GPM_UNSUPPORTED, "cliques up to 9 vertices");
         *plan = GPM_PLAN_CLIQUE_DAG;
         return GPM_OK;
     }

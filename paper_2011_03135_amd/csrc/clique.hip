@@ -17,12 +17,12 @@
 //                   prefix of its out-neighbours; each pair is a membership
 //                   test of w in N+(u).  Optionally adds 1 to the triangle
 //                   count of each of the triangle's three arcs.
-//   k_clique_wave   k = 4..8, roots with out-degree <= 64: one wave builds
+//   k_clique_wave   k = 4..9, roots with out-degree <= 64: one wave builds
 //                   the local graph on N+(u) as 64-bit adjacency rows in LDS
 //                   and counts cliques with AND + popcount.
-//   (local_graph.hip) k = 4..8, roots with out-degree 65..1024: workgroup
+//   (local_graph.hip) k = 4..9, roots with out-degree 65..1024: workgroup
 //                   local graphs in LDS.
-//   k_clique_generic  any k in [3, 8] when an out-degree exceeds 1024, and
+//   k_clique_generic  any k in [3, 9] when an out-degree exceeds 1024, and
 //                   listing: one wave per root, depth-first with candidate
 //                   sets in a per-wave global scratch, wave-cooperative
 //                   intersections.
@@ -390,9 +390,9 @@ __global__ void __launch_bounds__(kWave) k_clique_wave(const int32_t *__restrict
 
 constexpr int kMidMaxD = 256;
 
-// ------------------------------------------------- generic DFS (k <= 8) ---
+// ------------------------------------------------- generic DFS (k <= 9) ---
 
-constexpr int kGenMaxK = 8;
+constexpr int kGenMaxK = 9;
 
 struct ListOut {
     int32_t *buf;
@@ -659,7 +659,7 @@ gpm_status launch_local(const gpm_graph *g, CliqueWs &W, const int32_t *cnt_s,
     {
         static const char *const kNames[] = {"k_clique_wave<4>", "k_clique_wave<5>",
                                              "k_clique_wave<6>", "k_clique_wave<7>",
-                                             "k_clique_wave<8>"};
+                                             "k_clique_wave<8>", "k_clique_wave<9>"};
         Span sp(kNames[K - 4], st);
         if (em)
             hipLaunchKernelGGL((k_clique_wave<K, true>), dim3((unsigned)(cu_count() * 32)),
@@ -677,7 +677,7 @@ gpm_status launch_local(const gpm_graph *g, CliqueWs &W, const int32_t *cnt_s,
 }  // namespace
 
 gpm_status clique_workspace_bytes(const gpm_graph *g, int32_t k, bool list, uint64_t *bytes) {
-    if (k < 3 || k > kGenMaxK) return fail(GPM_UNSUPPORTED, "clique size must be in [3, 8]");
+    if (k < 3 || k > kGenMaxK) return fail(GPM_UNSUPPORTED, "clique size must be in [3, 9]");
     *bytes = clique_layout(g, k, list, nullptr).bytes;
     return GPM_OK;
 }
@@ -799,7 +799,8 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
             case 5: rc = launch_local<5>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st, pem); break;
             case 6: rc = launch_local<6>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st); break;
             case 7: rc = launch_local<7>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st); break;
-            default: rc = launch_local<8>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st); break;
+            case 8: rc = launch_local<8>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st); break;
+            default: rc = launch_local<9>(g, W, cnt_s, cnt_m, cnt_b, res, nullptr, nullptr, st); break;
             }
             if (rc) return rc;
         }

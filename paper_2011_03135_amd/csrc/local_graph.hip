@@ -690,7 +690,7 @@ __global__ void __launch_bounds__(NT) k_lg5_mid(const int32_t *__restrict__ off,
     constexpr int NW = NT / kWave;
     constexpr int WMAX = DMAX / 64;
     constexpr int WLO = 2, WHI = WMAX;   // out-degrees 65..DMAX
-    constexpr int kMaxExtra = 3;         // k <= 8
+    constexpr int kMaxExtra = 4;         // k <= 9
     __shared__ uint64_t rows[DMAX * WMAX];
     __shared__ __align__(16) int32_t keys[LgHash<DMAX>::kSlots];
     __shared__ int16_t vals[LgHash<DMAX>::kSlots];
@@ -857,7 +857,7 @@ gpm_status lg_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes) {
     return GPM_OK;
 }
 
-// Counts k-cliques (k = 4..8) rooted at the two workgroup classes: list_m
+// Counts k-cliques (k = 4..9) rooted at the two workgroup classes: list_m
 // (out-degree 65..256) and list_b (257..1024), device counts cnt_m, cnt_b,
 // into *res.  res3 / res4 (may be null) also receive the triangles and (for
 // k = 5) the 4-cliques rooted at the same roots.

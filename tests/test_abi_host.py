@@ -75,7 +75,11 @@ def test_patterns_and_plans():
     with pytest.raises(GpmError):
         gpm.clique(3, gpm.VERTEX_INDUCED | gpm.EDGE_INDUCED)          # both flags
     with pytest.raises(GpmError):
-        gpm.clique(9)                                                 # too large
+        gpm.clique(10)                                                # too large
+    pat9 = gpm.clique(9)                                              # 36 edges fit
+    assert pat9.n_edges == 36
+    assert load().gpm_pattern_plan(ctypes.byref(pat9), ctypes.byref(plan)) == 0
+    assert plan.value == 1
     assert isinstance(Pattern(), ctypes.Structure)
 
 

@@ -173,12 +173,12 @@ def test_clique_counts(gpm, case):
         assert gpm.count(g, gpm.clique(k)) == want, (e.name, k)
 
 
-@pytest.mark.parametrize("n", [66, 100])
+@pytest.mark.parametrize("n", [40, 66, 100])
 def test_dense_local_graphs_large_k(gpm, n):
-    """k = 6..8 on complete graphs (local rows of 2 words, level-1 sets of up
-    to n - 2 members)."""
+    """k = 6..9 on complete graphs (local rows of 1 or 2 words, level-1 sets
+    of up to n - 2 members)."""
     g = build(gpm, graphgen.complete_graph(n))
-    for k in (6, 7, 8):
+    for k in (6, 7, 8, 9) if n <= 66 else (6, 7, 8):
         print(f"complete graph n={n} k={k}", flush=True)
         assert gpm.count(g, gpm.clique(k)) == math.comb(n, k)
 
@@ -374,3 +374,25 @@ def test_without_local_graphs(gpm, case, monkeypatch):
         assert gpm.count(g, gpm.clique(k)) == want[k], k
         got = gpm.list_embeddings(g, gpm.clique(k, gpm.VERTEX_INDUCED | gpm.LIST), 1 << 16)
         assert got[0] == lists[k][0] and got[2] == lists[k][2], k
+
+
+def test_nine_cliques(gpm, monkeypatch):
+    """9-cliques: the oracle on a dense random graph (wave class, and the
+    depth-first kernel without local graphs), e_9 of the part sizes on a
+    complete multipartite graph, and the 9-clique listing's total and
+    checksum."""
+    e = graphgen.erdos_renyi(120, 0.55, 19)
+    g = build(gpm, e)
+    off, adj = canonical_csr(e.n, e.u, e.v)
+    want = oracle.clique_count(off, adj, 9)
+    print(f"ER 9-cliques {want}", flush=True)
+    assert want > 0
+    assert gpm.count(g, gpm.clique(9)) == want
+    total, chk, _ = oracle.clique_list(off, adj, 9, cap=16)
+    t, w, c, _ = gpm.list_embeddings(g, gpm.clique(9, gpm.VERTEX_INDUCED | gpm.LIST), 16)
+    assert (t, w, c) == (total, min(16, total), chk)
+    parts = [5] * 12 + [3] * 4
+    gm = build(gpm, graphgen.complete_multipartite(parts))
+    assert gpm.count(gm, gpm.clique(9)) == elementary_symmetric(parts, 9)
+    monkeypatch.setenv("GPM_LG", "0")
+    assert gpm.count(g, gpm.clique(9)) == want
