@@ -69,5 +69,5 @@ def test_rejects_oversized_and_invalid(gpm, graphs):
     with pytest.raises(gpm.GpmError):
         srv.submit(graphs[-1], QUERY_MOTIF, 4)      # workspace larger than the pool
     with pytest.raises(gpm.GpmError):
-        srv.submit(graphs[0], QUERY_CLIQUE, 9)      # unsupported clique size
+        srv.submit(graphs[0], QUERY_CLIQUE, 10)     # unsupported clique size
     srv.close()
