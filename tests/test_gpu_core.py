@@ -93,7 +93,8 @@ def test_core_numbers_and_orientation(gpm, gi):
 
 def test_core_orientation_all_counts_rmat(gpm):
     """RMAT-14 under the core orientation: cliques up to 6, listings (total
-    and checksum), motifs, diamonds and 4-cycles equal the degree order's."""
+    and checksum), motifs (both routes), diamonds, 4-cycles and a general
+    pattern equal the degree order's."""
     e = graphgen.rmat(14, seed=14)
     g = build(gpm, e)
     off, adj = oracle.canonical_csr(e.n, e.u, e.v)
@@ -104,6 +105,8 @@ def test_core_orientation_all_counts_rmat(gpm):
                 for k in (3, 4, 5)]
         out += [gpm.motif_count(g, 3), gpm.motif_count(g, 4), gpm.clique_counts(g, 5)]
         out += [gpm.count(g, gpm.diamond()), gpm.count(g, gpm.cycle4())]
+        out += [gpm.motif_count_enum(g, 4),
+                gpm.count(g, gpm.pattern(4, [(0, 1), (1, 2), (2, 3)], gpm.VERTEX_INDUCED))]
         return out
 
     before = snapshot()
