@@ -9,8 +9,8 @@
 // next sub-round.  Each vertex is removed once, when the decrement that
 // takes it to L is the one that sees L + 1, so the frontier lists never
 // repeat a vertex.  Levels with nothing to remove are skipped by taking the
-// smallest remaining degree.  The host drives the levels and reads one
-// counter per sub-round.
+// smallest remaining degree.  The host drives the levels; sub-rounds are
+// queued two at a time between reads of the counters.
 //
 // Orientation: arc u -> v iff (key(u), u) < (key(v), v); each row's arcs
 // keep ascending id order.  By degree, key = the degree (the build's
@@ -21,6 +21,7 @@
 // as second key 702, against 707 by degree and 639 for the degeneracy).
 #include <algorithm>
 #include <climits>
+#include <mutex>
 
 #include "gpm_internal.h"
 
@@ -31,8 +32,10 @@ namespace {
 constexpr int kCoreBlock = 256;
 constexpr int kCoreWaves = kCoreBlock / kWave;
 
-// ctl words
-enum { C_MIN_DEG = 0, C_LIVE = 1, C_CNT0 = 2, C_CNT1 = 3, C_MAX_OUT = 4, C_WORDS = 8 };
+// ctl words: smallest degree left, vertices removed so far, the scan's and
+// the sub-rounds' frontier sizes (two alternating slots)
+enum { C_MIN_DEG = 0, C_REMOVED = 1, C_SCAN = 2, C_CNT0 = 3, C_CNT1 = 4, C_MAX_OUT = 5,
+       C_WORDS = 8 };
 
 __global__ void __launch_bounds__(kCoreBlock) k_core_init(const int32_t *__restrict__ off,
                                                           int32_t n, int32_t *deg,
@@ -44,54 +47,48 @@ __global__ void __launch_bounds__(kCoreBlock) k_core_init(const int32_t *__restr
     }
 }
 
-// ctl[C_MIN_DEG] = smallest remaining degree, ctl[C_LIVE] = vertices left.
-__global__ void __launch_bounds__(kCoreBlock) k_core_stats(int32_t n, const int32_t *deg,
-                                                           const int32_t *core, uint32_t *ctl) {
-    int32_t mn = INT_MAX, live = 0;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x) {
-        if (core[v] < 0) {
-            mn = min(mn, deg[v]);
-            live++;
-        }
-    }
-    mn = -wave_max(-mn);
-    live = wave_sum(live);
-    if (lane_id() == 0 && live > 0) {
-        atomicMin(ctl + C_MIN_DEG, (uint32_t)mn);
-        atomicAdd(ctl + C_LIVE, (uint32_t)live);
-    }
-}
-
-// Removes every live vertex of remaining degree <= level into F.
+// Removes every live vertex of remaining degree <= level into F (count in
+// ctl[C_SCAN]) and leaves the smallest degree among the live vertices it
+// keeps in ctl[C_MIN_DEG], for skipping empty levels.
 __global__ void __launch_bounds__(kCoreBlock) k_core_scan(int32_t n, const int32_t *deg,
                                                           int32_t *core, int32_t level,
-                                                          int32_t *F, uint32_t *cnt) {
+                                                          int32_t *F, uint32_t *ctl) {
     const int lane = lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int32_t mn = INT_MAX;
     for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < n; v0 += stride) {
         const int64_t v = v0 + threadIdx.x;
-        const bool take = v < n && core[v] < 0 && deg[v] <= level;
+        const bool live = v < n && core[v] < 0;
+        const int32_t d = live ? deg[v] : INT_MAX;
+        const bool take = live && d <= level;
         if (take) core[v] = level;
+        else mn = min(mn, d);
         const uint64_t mask = __ballot(take);
         if (!mask) continue;
         uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(cnt, (uint32_t)__popcll(mask));
+        if (lane == 0) {
+            base = atomicAdd(ctl + C_SCAN, (uint32_t)__popcll(mask));
+            atomicAdd(ctl + C_REMOVED, (uint32_t)__popcll(mask));
+        }
         base = __shfl(base, 0);
         if (take) F[base + lanes_below(mask)] = (int32_t)v;
     }
+    mn = -wave_max(-mn);
+    if (lane == 0 && mn != INT_MAX) atomicMin(ctl + C_MIN_DEG, (uint32_t)mn);
 }
 
 // One sub-round: a wave per removed vertex lowers its live neighbours'
-// degrees; those reaching `level` are removed into F2.
+// degrees; those reaching `level` are removed into F2.  The frontier's size
+// is read on the device, so sub-rounds can be queued without a host trip.
 __global__ void __launch_bounds__(kCoreBlock) k_core_process(const int32_t *__restrict__ off,
                                                              const int32_t *__restrict__ adj,
                                                              int32_t *deg, int32_t *core,
                                                              int32_t level, const int32_t *F,
-                                                             int32_t cnt, int32_t *F2,
-                                                             uint32_t *cnt2) {
+                                                             const uint32_t *cnt_in, int32_t *F2,
+                                                             uint32_t *cnt2, uint32_t *removed) {
     const int lane = lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * kCoreWaves;
+    const int64_t cnt = *cnt_in;
     for (int64_t i = (int64_t)blockIdx.x * kCoreWaves + threadIdx.x / kWave; i < cnt;
          i += nwaves) {
         const int32_t v = F[i];
@@ -113,7 +110,10 @@ __global__ void __launch_bounds__(kCoreBlock) k_core_process(const int32_t *__re
             const uint64_t mask = __ballot(app);
             if (!mask) continue;
             uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(cnt2, (uint32_t)__popcll(mask));
+            if (lane == 0) {
+                base = atomicAdd(cnt2, (uint32_t)__popcll(mask));
+                atomicAdd(removed, (uint32_t)__popcll(mask));
+            }
             base = __shfl(base, 0);
             if (app) F2[base + lanes_below(mask)] = u;
         }
@@ -220,9 +220,26 @@ unsigned wgrid(int64_t rows) {
         1, std::min<int64_t>((rows + kCoreWaves - 1) / kCoreWaves, (int64_t)cu_count() * 16));
 }
 
+// A small pinned host buffer for the per-round counters (allocated once per
+// process; pageable copies cost several times more per round trip).
+uint32_t *pinned_words() {
+    static std::mutex mu;
+    static uint32_t *p = nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!p) {
+        void *q = nullptr;
+        if (hipHostMalloc(&q, 64, hipHostMallocDefault) == hipSuccess) p = static_cast<uint32_t *>(q);
+    }
+    return p;
+}
+
 gpm_status read_u32(const uint32_t *d, uint32_t *h, int count, hipStream_t st) {
-    GPM_HIP(hipMemcpyAsync(h, d, sizeof(uint32_t) * count, hipMemcpyDeviceToHost, st));
+    uint32_t *pin = pinned_words();
+    GPM_HIP(hipMemcpyAsync(pin ? pin : h, d, sizeof(uint32_t) * count, hipMemcpyDeviceToHost,
+                           st));
     GPM_HIP(hipStreamSynchronize(st));
+    if (pin)
+        for (int i = 0; i < count; i++) h[i] = pin[i];
     return GPM_OK;
 }
 
@@ -234,46 +251,58 @@ uint64_t orient_scratch_bytes(const gpm_graph *g) {
     return b;
 }
 
+// Sub-rounds queued per host round trip: most levels need one to three.
+constexpr int kRoundsPerTrip = 2;
+
 static gpm_status core_numbers_run(const gpm_graph *g, const CoreWs &W, hipStream_t st,
                                    int32_t *max_core) {
     const int32_t n = g->n;
     hipLaunchKernelGGL(k_core_init, dim3(vgrid(n)), dim3(kCoreBlock), 0, st, g->off, n, W.deg,
                        W.core);
     GPM_LAUNCH_CHECK("k_core_init");
+    GPM_HIP(fill_u32(W.ctl, 0, C_WORDS, st));
+    const unsigned pgrid = (unsigned)std::max(1, cu_count() * 4);
     int32_t level = 0;
     *max_core = 0;
-    for (;;) {
+    uint32_t removed = 0;
+    while (removed < (uint32_t)n) {
         GPM_HIP(fill_u32(W.ctl + C_MIN_DEG, 0xffffffffu, 1, st));
-        GPM_HIP(fill_u32(W.ctl + C_LIVE, 0, 3, st));
-        hipLaunchKernelGGL(k_core_stats, dim3(vgrid(n)), dim3(kCoreBlock), 0, st, n, W.deg,
-                           W.core, W.ctl);
-        GPM_LAUNCH_CHECK("k_core_stats");
-        uint32_t h[2];
-        gpm_status rc = read_u32(W.ctl, h, 2, st);
-        if (rc) return rc;
-        if (h[C_LIVE] == 0) break;
-        level = std::max(level, (int32_t)h[C_MIN_DEG]);
-        *max_core = level;
+        GPM_HIP(fill_u32(W.ctl + C_SCAN, 0, 1, st));
         hipLaunchKernelGGL(k_core_scan, dim3(vgrid(n)), dim3(kCoreBlock), 0, st, n, W.deg, W.core,
-                           level, W.F, W.ctl + C_CNT0);
+                           level, W.F, W.ctl);
         GPM_LAUNCH_CHECK("k_core_scan");
-        uint32_t cnt = 0;
-        rc = read_u32(W.ctl + C_CNT0, &cnt, 1, st);
-        if (rc) return rc;
+        // sub-rounds: the scan's frontier (F, count in C_SCAN), then
+        // alternating F2 / F with counts in C_CNT0 / C_CNT1
+        const uint32_t *cin = W.ctl + C_SCAN;
         int32_t *cur = W.F, *nxt = W.F2;
         int slot = C_CNT0;
-        while (cnt > 0) {
-            const int nslot = slot == C_CNT0 ? C_CNT1 : C_CNT0;
-            GPM_HIP(fill_u32(W.ctl + nslot, 0, 1, st));
-            hipLaunchKernelGGL(k_core_process, dim3(wgrid(cnt)), dim3(kCoreBlock), 0, st, g->off,
-                               g->adj, W.deg, W.core, level, cur, (int32_t)cnt, nxt,
-                               W.ctl + nslot);
-            GPM_LAUNCH_CHECK("k_core_process");
-            rc = read_u32(W.ctl + nslot, &cnt, 1, st);
+        uint32_t h[8];
+        bool first = true;
+        for (;;) {
+            for (int r = 0; r < kRoundsPerTrip; r++) {
+                GPM_HIP(fill_u32(W.ctl + slot, 0, 1, st));
+                hipLaunchKernelGGL(k_core_process, dim3(pgrid), dim3(kCoreBlock), 0, st, g->off,
+                                   g->adj, W.deg, W.core, level, cur, cin, nxt, W.ctl + slot,
+                                   W.ctl + C_REMOVED);
+                GPM_LAUNCH_CHECK("k_core_process");
+                cin = W.ctl + slot;
+                slot = slot == C_CNT0 ? C_CNT1 : C_CNT0;
+                std::swap(cur, nxt);
+            }
+            gpm_status rc = read_u32(W.ctl, h, C_WORDS, st);
             if (rc) return rc;
-            std::swap(cur, nxt);
-            slot = nslot;
+            if (first && h[C_SCAN] == 0) break;   // nothing at this level
+            first = false;
+            if (h[cin - W.ctl] == 0) break;   // the last sub-round removed nothing
         }
+        removed = h[C_REMOVED];
+        if (h[C_SCAN] == 0) {
+            // skip to the smallest remaining degree
+            if (h[C_MIN_DEG] == 0xffffffffu) break;
+            level = std::max(level + 1, (int32_t)h[C_MIN_DEG]);
+            continue;
+        }
+        *max_core = level;
         level++;
     }
     return GPM_OK;
