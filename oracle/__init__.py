@@ -55,6 +55,8 @@ def _load():
         lib.orc_wedges.argtypes = [i32, p, p]
         lib.orc_pattern_count.argtypes = [i32, p, p, i32, i32, p, i32, i32, p]
         lib.orc_pattern_count.restype = ctypes.c_int
+        lib.orc_pattern_list.argtypes = [i32, p, p, i32, i32, p, i32, p, u64, p, p, p]
+        lib.orc_pattern_list.restype = ctypes.c_int
         lib.orc_core_numbers.argtypes = [i32, p, p, p]
         lib.orc_core_numbers.restype = ctypes.c_int
         lib.orc_clique_count_sampled.argtypes = [i32, p, p, i32, i32, i32, p]
@@ -200,6 +202,17 @@ def batch_motifs(batch, k, threads=1):
         off, adj = canonical_csr(e.n, e.u, e.v)
         out.append(motif3(off, adj, threads) if k == 3 else motif4(off, adj, threads))
     return out
+
+
+def pattern_list(off, adj, k, edges, induced, cap=0):
+    """Embeddings of a connected pattern, each once: (total, checksum, rows)
+    with row i = the data vertices of pattern vertices 0..k-1, the
+    representative being the lexicographically smallest of the embedding's
+    automorphic maps.  Checksum key: the ascending vertex tuple
+    (vertex-induced) or the ascending edge codes (edge-induced)."""
+    pe = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1))
+    return _listing(_load().orc_pattern_list, off, adj, cap, int(k), int(k),
+                    int(pe.shape[0] // 2), _ptr(pe), int(bool(induced)))
 
 
 def core_numbers(off, adj):

@@ -731,3 +731,141 @@ int orc_pattern_count(int32_t n, const int64_t *off, const int32_t *adj, int32_t
     out[2] = aut;
     return ORC_OK;
 }
+
+
+/* Listing of a connected pattern's embeddings (Section 2, subgraph listing;
+ * vertex- or edge-induced as in orc_pattern_count).  Each embedding is
+ * reported once: among the |Aut(P)| injective maps that give it, the one
+ * whose image vector (f(0), ..., f(k-1)) is lexicographically smallest.
+ * Rows hold f(0..k-1); the checksum term uses the key of the comment above
+ * (vertex tuple or edge codes, ascending). */
+struct plist {
+    const struct pat *p;
+    int ne;
+    int pe[28][2];
+    int naut;
+    int *aut;              /* naut maps of k entries */
+    struct list_sink sink;
+    uint64_t total, sum;
+};
+
+static void plist_found(struct plist *L, const int32_t *img)
+{
+    const struct pat *p = L->p;
+    const int k = p->k;
+    int32_t f[8];
+    for (int s = 0; s < k; s++) f[p->order[s]] = img[s];
+    for (int t = 0; t < L->naut; t++) {
+        const int *sg = L->aut + (size_t)t * k;
+        for (int x = 0; x < k; x++) {
+            const int32_t g = f[sg[x]];
+            if (g < f[x]) return;          /* an automorphic copy comes first */
+            if (g > f[x]) break;
+        }
+    }
+    uint64_t key[28];
+    int len;
+    if (p->induced) {
+        for (int x = 0; x < k; x++) key[x] = (uint64_t)(uint32_t)f[x];
+        len = k;
+    } else {
+        for (int i = 0; i < L->ne; i++) {
+            const uint32_t a = (uint32_t)f[L->pe[i][0]], b = (uint32_t)f[L->pe[i][1]];
+            key[i] = a < b ? ((uint64_t)a << 32) | b : ((uint64_t)b << 32) | a;
+        }
+        len = L->ne;
+    }
+    sort_u64(key, len);
+    L->sum += key_hash(key, len);
+    L->total++;
+    sink_emit(&L->sink, f, k);
+}
+
+static void plist_from(const int64_t *off, const int32_t *adj, struct plist *L, int32_t *img,
+                       int step)
+{
+    const struct pat *p = L->p;
+    if (step == p->k) { plist_found(L, img); return; }
+    const int pv = p->order[step];
+    const int32_t a = img[p->anchor[step]];
+    for (int64_t e = off[a]; e < off[a + 1]; e++) {
+        const int32_t v = adj[e];
+        int ok = 1;
+        for (int s = 0; s < step && ok; s++) {
+            if (img[s] == v) { ok = 0; break; }
+            const int adjacent = p->adjm[pv][p->order[s]];
+            if (s == p->anchor[step]) continue;
+            const int edge = has_edge(off, adj, img[s], v);
+            if (adjacent && !edge) ok = 0;
+            if (!adjacent && p->induced && edge) ok = 0;
+        }
+        if (!ok) continue;
+        img[step] = v;
+        plist_from(off, adj, L, img, step + 1);
+    }
+}
+
+int orc_pattern_list(int32_t n, const int64_t *off, const int32_t *adj, int32_t k, int32_t ne,
+                     const int32_t *pe, int32_t induced, int32_t *buf, uint64_t cap,
+                     uint64_t *total, uint64_t *written, uint64_t *checksum)
+{
+    if (n < 0 || k < 2 || k > 8 || ne < k - 1 || ne > 28 || !pe || !total || !written ||
+        !checksum)
+        return ORC_BAD_ARG;
+    struct pat p;
+    memset(&p, 0, sizeof(p));
+    p.k = k;
+    p.induced = induced != 0;
+    struct plist L;
+    memset(&L, 0, sizeof(L));
+    L.p = &p;
+    L.ne = ne;
+    for (int i = 0; i < ne; i++) {
+        const int a = pe[2 * i], b = pe[2 * i + 1];
+        if (a < 0 || b < 0 || a >= k || b >= k || a == b) return ORC_BAD_ARG;
+        p.adjm[a][b] = p.adjm[b][a] = 1;
+        L.pe[i][0] = a;
+        L.pe[i][1] = b;
+    }
+    int seen[8] = {0}, parent_step[8] = {0}, head = 0, tail = 0;
+    p.order[tail++] = 0;
+    seen[0] = 1;
+    while (head < tail) {
+        const int x = p.order[head];
+        for (int y = 0; y < k; y++)
+            if (p.adjm[x][y] && !seen[y]) {
+                seen[y] = 1;
+                parent_step[tail] = head;
+                p.order[tail++] = y;
+            }
+        head++;
+    }
+    if (tail != k) return ORC_BAD_ARG;
+    for (int i = 1; i < k; i++) p.anchor[i] = parent_step[i];
+    int perm[8];
+    size_t fact = 1;
+    for (int i = 2; i <= k; i++) fact *= (size_t)i;
+    L.aut = malloc(sizeof(int) * fact * (size_t)k);
+    if (!L.aut) return ORC_NO_MEMORY;
+    for (int i = 0; i < k; i++) perm[i] = i;
+    do {
+        int ok = 1;
+        for (int a = 0; a < k && ok; a++)
+            for (int b = 0; b < k; b++)
+                if (p.adjm[a][b] != p.adjm[perm[a]][perm[b]]) { ok = 0; break; }
+        if (ok) memcpy(L.aut + (size_t)L.naut++ * k, perm, sizeof(int) * (size_t)k);
+    } while (next_perm(perm, k));
+    L.sink.buf = buf;
+    L.sink.cap = buf ? cap : 0;
+    L.sink.written = 0;
+    for (int32_t r = 0; r < n; r++) {
+        int32_t img[8];
+        img[0] = r;
+        plist_from(off, adj, &L, img, 1);
+    }
+    free(L.aut);
+    *total = L.total;
+    *written = L.sink.written < L.sink.cap ? L.sink.written : L.sink.cap;
+    *checksum = L.sum;
+    return ORC_OK;
+}

@@ -330,3 +330,45 @@ def test_core_numbers_closed_forms():
     v = [b for a in range(5) for b in range(a + 1, 5)] + [5, 6, 7]
     off, adj = oracle.canonical_csr(8, np.array(u, np.int32), np.array(v, np.int32))
     assert list(oracle.core_numbers(off, adj)) == [4, 4, 4, 4, 4, 1, 1, 1]
+
+
+def brute_pattern_keys(A, k, edges, induced):
+    """Every embedding of the pattern by brute force, as its canonical key:
+    the vertex set (vertex-induced) or the edge set (edge-induced)."""
+    target = brute.canon(k, edges)
+    keys = set()
+    for vs in combinations(range(len(A)), k):
+        ind = brute.induced_edges(A, vs)
+        if induced:
+            if len(ind) == len(edges) and brute.canon(k, ind) == target:
+                keys.add(tuple(vs))
+            continue
+        for F in combinations(ind, len(edges)):
+            if len({x for e in F for x in e}) == k and brute.canon(k, list(F)) == target:
+                keys.add(frozenset(tuple(sorted((vs[a], vs[b]))) for a, b in F))
+    return keys
+
+
+@pytest.mark.parametrize("seed,n,p", TINY[::4])
+@pytest.mark.parametrize("induced", [False, True])
+def test_pattern_list_brute_force(seed, n, p, induced):
+    g = random_tiny(seed, n, p)
+    off, adj = csr(g)
+    A = brute.adjacency_sets(g.n, g.u, g.v)
+    for name in ("wedge", "4-path", "4-cycle", "diamond", "house", "4-star"):
+        k, edges = brute.PATTERNS_ANY[name]
+        want = brute_pattern_keys(A, k, edges, induced)
+        total, chk, rows = oracle.pattern_list(off, adj, k, edges, induced, cap=10 ** 6)
+        assert total == len(want), name
+        got = set()
+        for r in rows.tolist():
+            if induced:
+                got.add(tuple(sorted(r)))
+            else:
+                got.add(frozenset(tuple(sorted((r[a], r[b]))) for a, b in edges))
+        assert got == want, name
+        if induced:
+            assert chk == sum(_hash(list(key)) for key in want) % (1 << 64)
+        else:
+            assert chk == sum(_hash([_ecode(a, b) for a, b in key]) for key in want) % (1 << 64)
+        assert total == oracle.pattern_count(off, adj, k, edges, induced)[0]
