@@ -104,8 +104,9 @@ gpm_status gpm_pattern_clique(int32_t k, uint32_t flags, gpm_pattern *out);
 #define GPM_PLAN_CLIQUE_DAG     1   /* triangles and k-cliques, k <= 9 */
 #define GPM_PLAN_SL_DIAMOND     2   /* edge-induced diamond listing/counting */
 #define GPM_PLAN_SL_4CYCLE      3   /* edge-induced 4-cycle listing/counting */
-/* Any other connected pattern of 2..6 vertices, vertex- or edge-induced:
- * counting only (gpm_list returns GPM_UNSUPPORTED).  A matching order with
+/* Any other connected pattern of 2..6 vertices, vertex- or edge-induced,
+ * counted or listed (gpm_list's conventions; each embedding once, written
+ * as the data vertices of pattern vertices 0..k-1).  A matching order with
  * partial orders derived from the pattern's automorphisms (Appendix B.1);
  * waves take work units of 64 third-vertex candidates below one edge and
  * search depth first below each.  Patterns of up to 5 vertices on graphs of

@@ -30,6 +30,8 @@ gpm_status motif_run(const gpm_graph *g, int32_t k, void *ws, uint64_t ws_bytes,
 gpm_status sl_workspace_bytes(const gpm_graph *g, int32_t plan, bool list, uint64_t *bytes);
 bool generic_pattern_ok(const gpm_pattern *p);
 uint64_t generic_workspace_bytes(const gpm_graph *g);
+gpm_status generic_list(const gpm_graph *g, const gpm_pattern *p, void *ws, uint64_t ws_bytes,
+                        int32_t *buf, uint64_t cap, unsigned long long *result, hipStream_t st);
 gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, void *ws, uint64_t ws_bytes,
                          unsigned long long *out, hipStream_t st);
 gpm_status sl_run(const gpm_graph *g, int32_t plan, bool list, void *ws, uint64_t ws_bytes,
@@ -279,7 +281,6 @@ gpm_status gpm_workspace_bytes(const gpm_graph *g, const gpm_pattern *p, uint64_
     const bool list = (p->flags & GPM_LIST) != 0;
     if (plan == GPM_PLAN_CLIQUE_DAG) return gpm::clique_workspace_bytes(g, p->k, list, bytes);
     if (plan == GPM_PLAN_GENERIC) {
-        if (list) return fail(GPM_UNSUPPORTED, "listing of general patterns is not implemented");
         *bytes = gpm::generic_workspace_bytes(g);
         return GPM_OK;
     }
@@ -320,7 +321,7 @@ gpm_status gpm_list(const gpm_graph *g, const gpm_pattern *p, void *d_ws, uint64
     if (plan == GPM_PLAN_CLIQUE_DAG)
         return gpm::clique_run(g, p->k, true, d_ws, ws_bytes, nullptr, d_buf, cap, res, st);
     if (plan == GPM_PLAN_GENERIC)
-        return fail(GPM_UNSUPPORTED, "listing of general patterns is not implemented");
+        return gpm::generic_list(g, p, d_ws, ws_bytes, d_buf, cap, res, st);
     return gpm::sl_run(g, plan, true, d_ws, ws_bytes, nullptr, d_buf, cap, res, st);
 }
 

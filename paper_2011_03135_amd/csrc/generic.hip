@@ -35,6 +35,7 @@ namespace gpm {
 namespace {
 
 constexpr int kGenMaxK = 6;
+constexpr int kGenMaxE = kGenMaxK * (kGenMaxK - 1) / 2;
 constexpr int kGenNT = 256;             // 4 waves per workgroup
 constexpr int32_t kGenMncMaxN = 8192;    // graphs up to this size keep a connectivity map per wave
 
@@ -45,7 +46,81 @@ struct GenPlan {
     uint32_t back_non[kGenMaxK];   // earlier steps not adjacent to step s
     uint32_t above[kGenMaxK];      // earlier steps t with f(s) > f(t) required
     uint32_t below[kGenMaxK];      // earlier steps t with f(s) < f(t) required
+    int32_t vert[kGenMaxK];        // pattern vertex matched at step s (listing rows)
+    int32_t ne;                    // pattern edges, as pairs of steps (listing keys)
+    int32_t estep[kGenMaxE][2];
 };
+
+// Emits one embedding (listing): row f (pattern vertex order, k entries) and
+// the checksum term of its key, the ascending vertex tuple (vertex-induced)
+// or the ascending edge codes min << 32 | max (edge-induced); m holds the
+// data vertex of every step.  May be called from divergent code.
+__device__ __forceinline__ void gen_emit(RowEmitter &em, const GenPlan &P,
+                                         const int32_t (&m)[kGenMaxK]) {
+    int32_t f[kGenMaxK];
+    uint64_t key[kGenMaxE];
+#pragma unroll
+    for (int i = 0; i < kGenMaxE; i++) key[i] = ~0ull;
+#pragma unroll
+    for (int s = 0; s < kGenMaxK; s++) f[s] = 0;
+#pragma unroll
+    for (int s = 0; s < kGenMaxK; s++)
+        if (s < P.k) {
+#pragma unroll
+            for (int x = 0; x < kGenMaxK; x++)
+                if (x == P.vert[s]) f[x] = m[s];
+        }
+    int len;
+    if (P.induced) {
+#pragma unroll
+        for (int x = 0; x < kGenMaxK; x++)
+            if (x < P.k) key[x] = (uint64_t)(uint32_t)f[x];
+        len = P.k;
+    } else {
+#pragma unroll
+        for (int i = 0; i < kGenMaxE; i++)
+            if (i < P.ne) {
+                uint32_t a = 0, b = 0;
+#pragma unroll
+                for (int s = 0; s < kGenMaxK; s++) {
+                    if (s == P.estep[i][0]) a = (uint32_t)m[s];
+                    if (s == P.estep[i][1]) b = (uint32_t)m[s];
+                }
+                key[i] = a < b ? ((uint64_t)a << 32) | b : ((uint64_t)b << 32) | a;
+            }
+        len = P.ne;
+    }
+    // ascending (the padding, all ones, stays at the end)
+#pragma unroll
+    for (int i = 1; i < kGenMaxE; i++)
+#pragma unroll
+        for (int j = kGenMaxE - 1; j >= i; j--) {
+            const uint64_t x = key[j - 1], y = key[j];
+            key[j - 1] = x < y ? x : y;
+            key[j] = x < y ? y : x;
+        }
+    uint64_t h = (uint64_t)len;
+#pragma unroll
+    for (int i = 0; i < kGenMaxE; i++)
+        if (i < len) h = fmix64((h ^ key[i]) + 0x9E3779B97F4A7C15ull);
+    em.hsum += h;
+    em.count++;
+    const uint64_t mask = __ballot(1);
+    const int leader = __builtin_ctzll(mask);
+    const bool ask = __shfl(em.cached, leader, 64) < em.cap;
+    if (!ask) return;
+    unsigned long long base = 0;
+    if (lane_id() == leader) base = atomicAdd(em.slot_ctr, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    em.cached = base + (uint64_t)__popcll(mask);
+    const uint64_t slot = base + (uint64_t)lanes_below(mask);
+    if (slot < em.cap) {
+        int32_t *o = em.buf + slot * (uint64_t)P.k;
+#pragma unroll
+        for (int x = 0; x < kGenMaxK; x++)
+            if (x < P.k) o[x] = f[x];
+    }
+}
 
 // Orders a wave's LDS writes before its later reads (lanes of one wave).
 __device__ __forceinline__ void wave_sync() {
@@ -133,12 +208,12 @@ __global__ void k_gen_total(const int64_t *__restrict__ total, unsigned long lon
     if (threadIdx.x == 0) out[0] = (unsigned long long)*total;
 }
 
-template <bool MNC>
+template <bool MNC, bool LIST>
 __global__ void __launch_bounds__(kGenNT) k_generic(const int32_t *__restrict__ off,
                                                     const int32_t *__restrict__ adj, int32_t n,
                                                     GenPlan P, const int64_t *__restrict__ chunk_off,
                                                     unsigned long long *cursor, int32_t map_stride,
-                                                    unsigned long long *result) {
+                                                    unsigned long long *result, RowEmitter em) {
     __shared__ GenWave sw[kGenNT / kWave];
     extern __shared__ uint32_t gen_maps[];   // MNC: a map of map_stride words per wave
     const int lane = lane_id(), wib = threadIdx.x / kWave;
@@ -257,7 +332,16 @@ __global__ void __launch_bounds__(kGenNT) k_generic(const int32_t *__restrict__ 
                 wave_sync();
                 if (lane == 0) S.pos[s] = p + kWave;
                 if (s == last) {
-                    count += (uint64_t)__popcll(msk);
+                    if (LIST) {
+                        if (ok) {
+                            int32_t mm[kGenMaxK];
+#pragma unroll
+                            for (int t = 0; t < kGenMaxK; t++) mm[t] = t < s ? S.m[t] : v;
+                            gen_emit(em, P, mm);
+                        }
+                    } else {
+                        count += (uint64_t)__popcll(msk);
+                    }
                     wave_sync();
                     continue;
                 }
@@ -283,7 +367,34 @@ __global__ void __launch_bounds__(kGenNT) k_generic(const int32_t *__restrict__ 
             mark(S.m[1], 2u, false);
         }
     }
-    if (lane == 0 && count) atomicAdd(result, (unsigned long long)count);
+    if (LIST) row_emitter_flush(em, result);
+    else if (lane == 0 && count) atomicAdd(result, (unsigned long long)count);
+}
+
+// Listing of two-vertex patterns: every arc the partial orders accept.
+__global__ void k_gen_list2(const int32_t *__restrict__ off, const int32_t *__restrict__ adj,
+                            int32_t n, GenPlan P, unsigned long long *result, RowEmitter em) {
+    const int64_t narcs = off[n];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // every lane runs the same number of iterations (the flush is wave-wide)
+    for (int64_t a0 = (int64_t)blockIdx.x * blockDim.x; a0 < narcs; a0 += stride) {
+        const int64_t a = a0 + threadIdx.x;
+        if (a < narcs) {
+            const int32_t r = gen_arc_row(off, n, a), v1 = adj[a];
+            bool ok = true;
+            if ((P.above[1] & 1u) && v1 < r) ok = false;
+            if ((P.below[1] & 1u) && v1 > r) ok = false;
+            if (ok) {
+                int32_t mm[kGenMaxK] = {r, v1};
+                gen_emit(em, P, mm);
+            }
+        }
+    }
+    row_emitter_flush(em, result);
+}
+
+__global__ void k_gen_finish_list(unsigned long long *result, uint64_t cap) {
+    if (threadIdx.x == 0) result[1] = result[0] < cap ? result[0] : cap;
 }
 
 // ------------------------------------------------------------ planning --
@@ -386,6 +497,12 @@ gpm_status make_plan(const gpm_pattern *p, GenPlan &P) {
             if (a[order[s]][order[t]]) P.back_adj[s] |= 1u << t;
             else P.back_non[s] |= 1u << t;
         }
+    for (int s = 0; s < k; s++) P.vert[s] = order[s];
+    P.ne = p->n_edges;
+    for (int i = 0; i < p->n_edges; i++) {
+        P.estep[i][0] = pos[p->edges[i][0]];
+        P.estep[i][1] = pos[p->edges[i][1]];
+    }
     return GPM_OK;
 }
 
@@ -401,7 +518,7 @@ static void gen_layout(Carve &cv, int64_t narcs, int32_t **chunks, int64_t **chu
     *chunks = cv.take<int32_t>((uint64_t)std::max<int64_t>(narcs, 1));
     *chunk_off = cv.take<int64_t>((uint64_t)narcs + 1);
     *tmp = cv.take<int64_t>(scan_tmp_words((uint64_t)narcs));
-    *cursor = cv.take<unsigned long long>(1);
+    *cursor = cv.take<unsigned long long>(2);   // work cursor, listing slot counter
 }
 
 uint64_t generic_workspace_bytes(const gpm_graph *g) {
@@ -413,8 +530,11 @@ uint64_t generic_workspace_bytes(const gpm_graph *g) {
     return cv.used;
 }
 
-gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, void *ws, uint64_t ws_bytes,
-                         unsigned long long *out, hipStream_t st) {
+// Counting (list == false: out[0] = the count) or listing (out = {total,
+// written, checksum}, rows into buf) of a general pattern.
+static gpm_status generic_run(const gpm_graph *g, const gpm_pattern *p, bool list, void *ws,
+                              uint64_t ws_bytes, int32_t *buf, uint64_t cap,
+                              unsigned long long *out, hipStream_t st) {
     GenPlan P;
     gpm_status rc = make_plan(p, P);
     if (rc) return rc;
@@ -425,11 +545,20 @@ gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, void *ws, uin
     unsigned long long *cursor;
     gen_layout(cv, narcs, &chunks, &chunk_off, &tmp, &cursor);
     if (!cv.fits()) return fail(GPM_INVALID_ARGUMENT, "workspace too small");
-    GPM_HIP(fill_u32(reinterpret_cast<uint32_t *>(out), 0, 2, st));
+    GPM_HIP(fill_u32(reinterpret_cast<uint32_t *>(out), 0, list ? 6 : 2, st));
     if (g->m == 0) return GPM_OK;
-    Span sp("k_generic", st);
-    GPM_HIP(fill_u32(cursor, 0, 2, st));
+    Span sp(list ? "k_generic_list" : "k_generic", st);
+    GPM_HIP(fill_u32(cursor, 0, 4, st));
+    RowEmitter em{cursor + 1, buf, list ? cap : 0, 0, 0, 0};
     const unsigned cblocks = (unsigned)std::min<int64_t>((narcs + 255) / 256, 4096);
+    if (list && P.k == 2) {
+        hipLaunchKernelGGL(k_gen_list2, dim3(cblocks), dim3(256), 0, st, g->off, g->adj, g->n, P,
+                           out, em);
+        GPM_LAUNCH_CHECK("k_gen_list2");
+        hipLaunchKernelGGL(k_gen_finish_list, dim3(1), dim3(64), 0, st, out, cap);
+        GPM_LAUNCH_CHECK("k_gen_finish_list");
+        return GPM_OK;
+    }
     hipLaunchKernelGGL(k_gen_chunks, dim3(cblocks), dim3(256), 0, st, g->off, g->adj, g->n, P,
                        chunks);
     GPM_LAUNCH_CHECK("k_gen_chunks");
@@ -449,15 +578,31 @@ gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, void *ws, uin
     const char *env = getenv("GPM_MNC");
     const bool mnc = P.k <= 5 && g->n <= kGenMncMaxN && !(env && env[0] == '0');
     const int32_t stride = mnc ? (g->n + 7) / 8 : 0;
-    const size_t dyn = (size_t)(kGenNT / kWave) * stride * sizeof(uint32_t);
-    if (mnc)
-        hipLaunchKernelGGL(k_generic<true>, dim3(blocks), dim3(kGenNT), dyn, st, g->off, g->adj,
-                           g->n, P, chunk_off, cursor, stride, out);
-    else
-        hipLaunchKernelGGL(k_generic<false>, dim3(blocks), dim3(kGenNT), 0, st, g->off, g->adj,
-                           g->n, P, chunk_off, cursor, 0, out);
+    const size_t dyn = mnc ? (size_t)(kGenNT / kWave) * stride * sizeof(uint32_t) : 0;
+#define GEN_LAUNCH(M, L)                                                                       \
+    hipLaunchKernelGGL((k_generic<M, L>), dim3(blocks), dim3(kGenNT), dyn, st, g->off, g->adj,  \
+                       g->n, P, chunk_off, cursor, stride, out, em)
+    if (mnc && list) GEN_LAUNCH(true, true);
+    else if (mnc) GEN_LAUNCH(true, false);
+    else if (list) GEN_LAUNCH(false, true);
+    else GEN_LAUNCH(false, false);
+#undef GEN_LAUNCH
     GPM_LAUNCH_CHECK("k_generic");
+    if (list) {
+        hipLaunchKernelGGL(k_gen_finish_list, dim3(1), dim3(64), 0, st, out, cap);
+        GPM_LAUNCH_CHECK("k_gen_finish_list");
+    }
     return GPM_OK;
+}
+
+gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, void *ws, uint64_t ws_bytes,
+                         unsigned long long *out, hipStream_t st) {
+    return generic_run(g, p, false, ws, ws_bytes, nullptr, 0, out, st);
+}
+
+gpm_status generic_list(const gpm_graph *g, const gpm_pattern *p, void *ws, uint64_t ws_bytes,
+                        int32_t *buf, uint64_t cap, unsigned long long *result, hipStream_t st) {
+    return generic_run(g, p, true, ws, ws_bytes, buf, cap, result, st);
 }
 
 }  // namespace gpm

@@ -93,12 +93,56 @@ def test_generic_closed_forms_rmat(gpm):
         assert got == motifs[names.index(name)], name
 
 
+def _keys(rows, edges, induced):
+    if induced:
+        return {tuple(sorted(r)) for r in rows}
+    return {frozenset(tuple(sorted((r[a], r[b]))) for a, b in edges) for r in rows}
+
+
+@pytest.mark.parametrize("gi", [0, 2])
+@pytest.mark.parametrize("induced", [False, True])
+def test_listing_vs_oracle(gpm, gi, induced):
+    """Listing: the same embeddings (as canonical keys), total and checksum
+    as the oracle's listing; a truncated listing keeps total and checksum
+    and writes valid embeddings only."""
+    e = graphs()[gi]
+    print(f"graph {gi} n={e.n} induced={induced}", flush=True)
+    g = build(gpm, e)
+    off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+    flags = (gpm.VERTEX_INDUCED if induced else gpm.EDGE_INDUCED) | gpm.LIST
+    for name in ("edge", "wedge", "4-path", "tailed-triangle", "house", "bull", "6-path"):
+        k, edges = PATTERNS[name]
+        full = 1 << 21
+        total, chk, rows = oracle.pattern_list(off, adj, k, edges, induced, cap=full)
+        t, w, c, got = gpm.list_embeddings(g, gpm.pattern(k, edges, flags), full)
+        assert (t, w, c) == (total, min(total, full), chk), name
+        if total <= full:
+            assert _keys(got.cpu().tolist(), edges, induced) == \
+                _keys(rows.tolist(), edges, induced), name
+        cap = max(1, total // 3)
+        t, w, c, got = gpm.list_embeddings(g, gpm.pattern(k, edges, flags), cap)
+        assert (t, w, c) == (total, min(cap, total), chk), name
+        if total <= full:
+            assert _keys(got.cpu().tolist(), edges, induced) <= \
+                _keys(rows.tolist(), edges, induced), name
+
+
+def test_listing_without_map(gpm, monkeypatch):
+    e = graphs()[0]
+    g = build(gpm, e)
+    off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+    monkeypatch.setenv("GPM_MNC", "0")
+    k, edges = PATTERNS["house"]
+    for induced in (False, True):
+        flags = (gpm.VERTEX_INDUCED if induced else gpm.EDGE_INDUCED) | gpm.LIST
+        total, chk, _ = oracle.pattern_list(off, adj, k, edges, induced, cap=0)
+        t, w, c, _ = gpm.list_embeddings(g, gpm.pattern(k, edges, flags), 1 << 16)
+        assert (t, c) == (total, chk)
+
+
 def test_generic_errors(gpm):
     e = graphgen.erdos_renyi(30, 0.2, 5)
     g = build(gpm, e)
-    house = [(0, 1), (1, 2), (2, 3), (3, 0), (2, 4), (3, 4)]
-    with pytest.raises(gpm.GpmError):
-        gpm.list_embeddings(g, gpm.pattern(5, house, gpm.EDGE_INDUCED | gpm.LIST), 16)
     with pytest.raises(gpm.GpmError):
         gpm.count(g, gpm.pattern(7, [(i, i + 1) for i in range(6)], gpm.EDGE_INDUCED))
 
