@@ -281,6 +281,14 @@ def generic_leg(gpm, torch, scale, reps=3):
                      "ms": ms, "matches_per_sec": got / (ms * 1e-3),
                      "ms_without_connectivity_map": ms_off, "same_without_map": got == got_off,
                      "lc_route_speedup": ms / lc_ms}
+    # listing the 4-cycles: every embedding hashed into the checksum, the
+    # first 2^20 written out
+    pl = gpm.pattern(4, [(0, 1), (1, 2), (2, 3), (3, 0)], gpm.VERTEX_INDUCED | gpm.LIST)
+    ws = torch.empty(gpm.workspace_bytes(g, pl), dtype=torch.uint8, device="cuda")
+    (t, w, c, _), lms = timed(lambda: gpm.list_embeddings(g, pl, 1 << 20, ws=ws))
+    res["4-cycle listing"] = {"total": t, "written": w, "ms": lms,
+                              "equals_count": t == res["4-cycle"]["count"],
+                              "embeddings_per_sec": t / (lms * 1e-3)}
     return res
 
 
