@@ -317,6 +317,45 @@ def large_k_leg(gpm, torch, plan=((12, 9), (16, 8), (18, 7), (20, 6))):
     return {"workload": "k-clique counts on RMAT graphs for growing k", "runs": out}
 
 
+def core_orient_leg(gpm, torch, scale=20, reps=3):
+    """The core-value orientation on RMAT-`scale`: the device core
+    decomposition and DAG rebuild (gpm_graph_orient), then the 3-/4-/5-clique
+    counts under each orientation."""
+    import graphgen
+    e = graphgen.rmat(scale, seed=scale)
+    g = gpm.Graph.build(e.n, torch.from_numpy(e.u).cuda(), torch.from_numpy(e.v).cuda())
+
+    def cliques():
+        out = {}
+        for k in (3, 4, 5):
+            p = gpm.clique(k)
+            gpm.count(g, p)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                c = gpm.count(g, p)
+            torch.cuda.synchronize()
+            out[f"clique{k}"] = {"count": c, "ms": (time.perf_counter() - t0) * 1e3 / reps}
+        return out
+
+    res = {"workload": f"rmat{scale}: core-value orientation vs degree orientation"}
+    res["degree_order"] = dict(cliques(), max_out_degree=g.max_out_degree)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    core = g.orient(gpm.ORIENT_CORE, core_out=True)
+    torch.cuda.synchronize()
+    res["orient_core_ms"] = (time.perf_counter() - t0) * 1e3
+    res["degeneracy"] = int(core.max()) if g.n else 0
+    res["core_order"] = dict(cliques(), max_out_degree=g.max_out_degree)
+    t0 = time.perf_counter()
+    g.orient(gpm.ORIENT_DEGREE)
+    torch.cuda.synchronize()
+    res["orient_degree_ms"] = (time.perf_counter() - t0) * 1e3
+    res["same_counts"] = all(res["degree_order"][f"clique{k}"]["count"] ==
+                             res["core_order"][f"clique{k}"]["count"] for k in (3, 4, 5))
+    return res
+
+
 def local_graph_leg(gpm, torch, scale, reps=3):
     """4- and 5-clique counts on RMAT-`scale` through the local-graph
     kernels (the default) and through the depth-first search without local
@@ -453,6 +492,8 @@ def main():
     ap.add_argument("--no-generic", action="store_true")
     ap.add_argument("--no-motif-enum", action="store_true")
     ap.add_argument("--no-lg-ablation", action="store_true")
+    ap.add_argument("--core-only", action="store_true",
+                    help="only time the core-value orientation on RMAT-20 and exit")
     ap.add_argument("--large-k-only", action="store_true",
                     help="only count k-cliques for k = 4..9 on RMAT-12/16/18/20 (minutes) and exit")
     ap.add_argument("--lg-ablation-only", action="store_true",
@@ -483,6 +524,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.generic_only:
         print(json.dumps({"generic_pattern": generic_leg(gpm, torch, 13)}))
+        return
+    if args.core_only:
+        print(json.dumps({"core_orientation": core_orient_leg(gpm, torch)}))
         return
     if args.large_k_only:
         print(json.dumps({"large_k_cliques": large_k_leg(gpm, torch)}))

@@ -73,8 +73,17 @@ __global__ void __launch_bounds__(kCoreBlock) k_core_scan(int32_t n, const int32
         base = __shfl(base, 0);
         if (take) F[base + lanes_below(mask)] = (int32_t)v;
     }
+    // one atomic per workgroup: a per-wave atomic on one word serialises
+    // thousands of waves
+    __shared__ int32_t wmin[kCoreWaves];
     mn = -wave_max(-mn);
-    if (lane == 0 && mn != INT_MAX) atomicMin(ctl + C_MIN_DEG, (uint32_t)mn);
+    if (lane == 0) wmin[threadIdx.x / kWave] = mn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t b = wmin[0];
+        for (int w = 1; w < kCoreWaves; w++) b = min(b, wmin[w]);
+        if (b != INT_MAX) atomicMin(ctl + C_MIN_DEG, (uint32_t)b);
+    }
 }
 
 // One sub-round: a wave per removed vertex lowers its live neighbours'
@@ -268,7 +277,7 @@ static gpm_status core_numbers_run(const gpm_graph *g, const CoreWs &W, hipStrea
     while (removed < (uint32_t)n) {
         GPM_HIP(fill_u32(W.ctl + C_MIN_DEG, 0xffffffffu, 1, st));
         GPM_HIP(fill_u32(W.ctl + C_SCAN, 0, 1, st));
-        hipLaunchKernelGGL(k_core_scan, dim3(vgrid(n)), dim3(kCoreBlock), 0, st, n, W.deg, W.core,
+        hipLaunchKernelGGL(k_core_scan, dim3(pgrid), dim3(kCoreBlock), 0, st, n, W.deg, W.core,
                            level, W.F, W.ctl);
         GPM_LAUNCH_CHECK("k_core_scan");
         // sub-rounds: the scan's frontier (F, count in C_SCAN), then
