@@ -195,3 +195,15 @@ def test_graph_capture_replays(gpm):
             torch.cuda.synchronize()
             assert torch.equal(out, eager), (k, r)
             del junk
+
+
+def test_5_motifs_above_map_limit(gpm):
+    """A sparse graph above the map's vertex limit (binary searches): the 21
+    5-motif counts equal the oracle's class by class."""
+    e = graphgen.erdos_renyi(20000, 3.0 / 20000, 31)
+    g = build(gpm, e)
+    off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+    want = [oracle.pattern_count(off, adj, 5, gpm.motif_class_pattern(5, i), True)[0]
+            for i in range(21)]
+    assert sum(want) > 0
+    assert gpm.motif_count_enum(g, 5) == want
