@@ -130,21 +130,34 @@ def phase_roofline(name, ms, off, adj, kmin):
             "frac": ach / HBM_PEAK_GBS, "alg_bytes": b, "arcs": arcs, "pairs": pairs, "ms": ms}
 
 
-def cpu_baseline(e, fraction_inv, ks, threads):
+def cpu_baseline(e, stride, ks, threads, gpu_counts):
+    """The oracle (unchanged) on a bounded share of the step's work: its
+    core-ordered DAG is built first, outside the timed region (the paper
+    times mining, not preprocessing), then the k-cliques rooted at every
+    `stride`-th vertex of the core order are counted for every k of the
+    step.  The rate is the whole graph's edges over the share's time scaled
+    by the stride; clique_share says how much of the step's output the share
+    covered."""
     import oracle
     off, adj = oracle.canonical_csr(e.n, e.u, e.v)
     m = adj.shape[0] // 2
     t0 = time.perf_counter()
-    for k in ks:
-        oracle.clique_count_sampled(off, adj, k, fraction_inv, threads)
+    dag = oracle.CoreDag(off, adj)
+    prep = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sampled = [dag.clique_count_sampled(k, stride, 0, threads) for k in ks]
     dt = time.perf_counter() - t0
+    dag.close()
     return {
-        "value": (m / fraction_inv) / dt,
+        "value": m / (dt * stride),
         "unit": "edges/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"cliques k={list(ks)} rooted at every {fraction_inv}-th vertex of the core "
-                  f"order of the same rmat graph ({dt:.1f} s); rate = (m / {fraction_inv}) / time",
+        "sample": f"cliques k={list(ks)} rooted at every {stride}-th vertex of the core order "
+                  f"of the same rmat graph ({dt:.1f} s, DAG prebuilt in {prep:.1f} s outside "
+                  f"the timing); rate = m / (time * {stride})",
+        "sampled_counts": sampled,
+        "clique_share": sum(sampled) / max(1, sum(gpu_counts)),
     }
 
 
@@ -666,7 +679,7 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline")
         threads = len(os.sched_getaffinity(0))
-        res["cpu_baseline"] = cpu_baseline(e, args.cpu_fraction, ks, threads)
+        res["cpu_baseline"] = cpu_baseline(e, args.cpu_fraction, ks, threads, counts)
     print(json.dumps(res))
 
 

@@ -115,7 +115,12 @@ gpm_status gpm_pattern_clique(int32_t k, uint32_t flags, gpm_pattern *out);
  * search in the matched vertices' rows; GPM_MNC=0 in the environment forces
  * the latter.  Both give the same counts. */
 #define GPM_PLAN_GENERIC        4
-/* Returns the plan for (graph-independent) pattern p, or GPM_UNSUPPORTED. */
+/* Returns the plan for (graph-independent) pattern p, or GPM_UNSUPPORTED.
+ * A struct built by the caller is checked as gpm_pattern_from_edges would
+ * check it (sizes, edges, connectivity, and flags: exactly one of
+ * GPM_VERTEX_INDUCED and GPM_EDGE_INDUCED, no unknown bit), else
+ * GPM_INVALID_ARGUMENT.  Every counting and listing entry point runs this
+ * check first. */
 gpm_status gpm_pattern_plan(const gpm_pattern *p, int32_t *plan);
 
 /* ------------------------------------------------------------- graph --- */
@@ -210,25 +215,34 @@ gpm_status gpm_graph_orient(gpm_graph *g, int32_t order, void *d_scratch, uint64
 gpm_status gpm_workspace_bytes(const gpm_graph *g, const gpm_pattern *p, uint64_t *bytes);
 
 /* Counts the embeddings of p in g (Section 2: unique subgraphs, each
- * automorphism class once): triangles and k-cliques (k <= 5) for
- * vertex-induced cliques; edge-induced diamonds and 4-cycles.  Writes one
- * uint64 to d_count (device).  p must not carry GPM_LIST. */
+ * automorphism class once), by the plan gpm_pattern_plan picks:
+ * triangles and k-cliques for k <= 9 (either induced flag: for a clique the
+ * two coincide); edge-induced diamonds and 4-cycles; any other connected
+ * pattern of 2..6 vertices, vertex- or edge-induced, by the general plan.
+ * Writes one uint64 to d_count (device).  p must not carry GPM_LIST.  A
+ * workspace smaller than gpm_workspace_bytes gives GPM_OUT_OF_MEMORY before
+ * anything is enqueued (d_count untouched). */
 gpm_status gpm_count(const gpm_graph *g, const gpm_pattern *p, void *d_ws, uint64_t ws_bytes,
                      uint64_t *d_count, void *stream);
 
-/* Lists the embeddings of p in g.  Embedding number i (in an unspecified
- * order) is written to d_buf[i*k .. i*k+k-1] as the data vertices matched
- * to pattern vertices 0..k-1, for i < cap.  d_result (device uint64[3])
+/* Lists the embeddings of p in g: the patterns gpm_count counts, cliques
+ * of k <= 9 included.  Embedding number i (in an unspecified order) is
+ * written to d_buf[i*k .. i*k+k-1] as the data vertices matched to pattern
+ * vertices 0..k-1 of p as the caller labelled it (every pattern edge (a, b)
+ * lands on a graph edge), for i < cap.  d_result (device uint64[3])
  * receives {total, written, checksum}: total counts every embedding even
  * past cap, written = min(total, cap), and checksum is the sum modulo 2^64,
  * over all embeddings, of a per-embedding hash of its canonical key:
  *     h = L; for each key element c in ascending order:
  *         h = fmix64((h XOR c) + 0x9E3779B97F4A7C15)
  * (fmix64 = the splitmix64 finaliser), with key = the ascending vertex
- * tuple (vertex-induced) or the ascending edge codes (min << 32 | max)
- * (edge-induced), L its length.  written < total means the listing was
- * truncated (GPM_TRUNCATED is not returned, since the call is
- * asynchronous).  p must carry GPM_LIST. */
+ * tuple for vertex-induced patterns and for cliques (whose vertex- and
+ * edge-induced embeddings are the same vertex sets), and the ascending edge
+ * codes (min << 32 | max) for the other edge-induced patterns; L is the
+ * key's length.  written < total means the listing was truncated
+ * (GPM_TRUNCATED is not returned, since the call is asynchronous).  p must
+ * carry GPM_LIST.  A workspace smaller than gpm_workspace_bytes gives
+ * GPM_OUT_OF_MEMORY before anything is enqueued (outputs untouched). */
 gpm_status gpm_list(const gpm_graph *g, const gpm_pattern *p, void *d_ws, uint64_t ws_bytes,
                     int32_t *d_buf, uint64_t cap, uint64_t *d_result, void *stream);
 
@@ -388,6 +402,11 @@ typedef struct gpm_response {
     int32_t n_values;       /* 1 (clique) or 2 / 6 (motif) */
     uint64_t values[7];     /* counts (motif: plus the status word) */
     double t_submit, t_admit, t_done;   /* seconds on gpm_server_now()'s clock */
+    /* device clock: seconds from an event the server records at creation to
+     * events recorded on the slot's stream just before and just after the
+     * request's work (so d_end - d_start bounds its kernels' span on the
+     * device); -1 if the device times could not be read */
+    double d_start, d_end;
 } gpm_response;
 
 /* Creates the server and its scheduler thread.  Streams (default priority)

@@ -59,8 +59,14 @@ def _load():
         lib.orc_pattern_list.restype = ctypes.c_int
         lib.orc_core_numbers.argtypes = [i32, p, p, p]
         lib.orc_core_numbers.restype = ctypes.c_int
-        lib.orc_clique_count_sampled.argtypes = [i32, p, p, i32, i32, i32, p]
+        lib.orc_clique_count_sampled.argtypes = [i32, p, p, i32, i32, i32, i32, p]
         lib.orc_clique_count_sampled.restype = ctypes.c_int
+        lib.orc_dag_build.argtypes = [i32, p, p, ctypes.POINTER(ctypes.c_void_p)]
+        lib.orc_dag_build.restype = ctypes.c_int
+        lib.orc_dag_free.argtypes = [p]
+        lib.orc_dag_free.restype = None
+        lib.orc_dag_clique_count_sampled.argtypes = [p, i32, i32, i32, i32, p]
+        lib.orc_dag_clique_count_sampled.restype = ctypes.c_int
         for f in (lib.orc_clique_count, lib.orc_clique_list, lib.orc_edge_triangles,
                   lib.orc_motif4_noninduced, lib.orc_list_diamonds, lib.orc_list_c4,
                   lib.orc_wedges):
@@ -97,14 +103,46 @@ def clique_count(off, adj, k, threads=0):
     return _u128(out[0], out[1])
 
 
-def clique_count_sampled(off, adj, k, stride, threads=0):
-    """k-cliques whose first vertex (core order) has position % stride == 0;
-    a bounded share of clique_count's work, used only for CPU timing."""
+def clique_count_sampled(off, adj, k, stride, offset=0, threads=0):
+    """k-cliques whose first vertex in the core order has position p with
+    p % stride == offset: one share of clique_count's roots.  The shares over
+    offset = 0..stride-1 add up to clique_count."""
     off, adj, n = _prep(off, adj)
     out = np.zeros(2, dtype=np.uint64)
     _check(_load().orc_clique_count_sampled(n, _ptr(off), _ptr(adj), int(k), int(threads),
-                                            int(stride), _ptr(out)), "clique_count_sampled")
+                                            int(stride), int(offset), _ptr(out)),
+           "clique_count_sampled")
     return _u128(out[0], out[1])
+
+
+class CoreDag:
+    """The core-ordered DAG of a canonical CSR, built once (the oracle's
+    preprocessing), for clique counts rooted at a share of the vertices."""
+
+    def __init__(self, off, adj):
+        off, adj, n = _prep(off, adj)
+        self._h = ctypes.c_void_p()
+        _check(_load().orc_dag_build(n, _ptr(off), _ptr(adj), ctypes.byref(self._h)),
+               "dag_build")
+
+    def clique_count_sampled(self, k, stride, offset=0, threads=0):
+        """As the module-level clique_count_sampled, on the prebuilt DAG."""
+        out = np.zeros(2, dtype=np.uint64)
+        _check(_load().orc_dag_clique_count_sampled(self._h, int(k), int(threads), int(stride),
+                                                    int(offset), _ptr(out)),
+               "dag_clique_count_sampled")
+        return _u128(out[0], out[1])
+
+    def close(self):
+        if self._h:
+            _load().orc_dag_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def triangle_count(off, adj, threads=0):

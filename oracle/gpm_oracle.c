@@ -245,39 +245,80 @@ int orc_clique_count(int32_t n, const int64_t *off, const int32_t *adj, int32_t 
     return ORC_OK;
 }
 
-/* Timing sample of orc_clique_count: only the cliques whose first vertex in
- * the core order has a position divisible by `stride` (a bounded, seeded
- * share of the roots).  Used to time the oracle on part of a workload. */
-int orc_clique_count_sampled(int32_t n, const int64_t *off, const int32_t *adj, int32_t k,
-                             int32_t threads, int32_t stride, uint64_t *out)
+/* The core-ordered DAG built once, for counting cliques rooted at chosen
+ * vertices (a share of the roots) without rebuilding it per call.  pos is
+ * each vertex's position in the core order, o / a the out-lists. */
+struct orc_dag {
+    int32_t n, maxout;
+    int32_t *pos;
+    int64_t *o;
+    int32_t *a;
+};
+
+int orc_dag_build(int32_t n, const int64_t *off, const int32_t *adj, struct orc_dag **out)
 {
-    if (n < 0 || k < 3 || stride < 1 || !out) return ORC_BAD_ARG;
-    int32_t *pos = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    if (!pos) return ORC_NO_MEMORY;
-    int rc = core_positions(n, off, adj, pos);
-    if (rc) { free(pos); return rc; }
-    int64_t *o; int32_t *a; int32_t mo;
-    rc = core_dag(n, off, adj, &o, &a, &mo);
-    if (rc) { free(pos); return rc; }
+    if (n < 0 || !out) return ORC_BAD_ARG;
+    struct orc_dag *g = calloc(1, sizeof(*g));
+    if (!g) return ORC_NO_MEMORY;
+    g->n = n;
+    g->pos = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!g->pos) { free(g); return ORC_NO_MEMORY; }
+    int rc = core_positions(n, off, adj, g->pos);
+    if (!rc) rc = core_dag(n, off, adj, &g->o, &g->a, &g->maxout);
+    if (rc) { free(g->pos); free(g); return rc; }
+    *out = g;
+    return ORC_OK;
+}
+
+void orc_dag_free(struct orc_dag *g)
+{
+    if (!g) return;
+    free(g->pos); free(g->o); free(g->a); free(g);
+}
+
+/* Number of k-cliques (k >= 3) whose first vertex in the core order has a
+ * position p with p % stride == offset.  Every clique has exactly one first
+ * vertex, so the counts over offsets 0..stride-1 add up to orc_clique_count,
+ * and stride 1 is orc_clique_count itself.  Used to time the oracle on a
+ * bounded share of a workload's roots. */
+int orc_dag_clique_count_sampled(const struct orc_dag *g, int32_t k, int32_t threads,
+                                 int32_t stride, int32_t offset, uint64_t *out)
+{
+    if (!g || k < 3 || stride < 1 || offset < 0 || offset >= stride || !out) return ORC_BAD_ARG;
+    const int64_t *o = g->o;
+    const int32_t *a = g->a, *pos = g->pos;
     u128 total = 0;
     int failed = 0;
     if (threads > 0) omp_set_num_threads(threads);
 #pragma omp parallel reduction(+ : total) reduction(| : failed)
     {
-        int32_t *scratch = malloc(sizeof(int32_t) * ((size_t)mo * (size_t)k + 1));
+        int32_t *scratch = malloc(sizeof(int32_t) * ((size_t)g->maxout * (size_t)k + 1));
         if (!scratch) failed = 1;
 #pragma omp for schedule(dynamic, 64)
-        for (int32_t v = 0; v < n; v++) {
-            if (!scratch || pos[v] % stride != 0) continue;
+        for (int32_t v = 0; v < g->n; v++) {
+            if (!scratch || pos[v] % stride != offset) continue;
             int64_t d = o[v + 1] - o[v];
             if (d >= k - 1) total += clique_extend(o, a, a + o[v], d, k - 1, scratch);
         }
         free(scratch);
     }
-    free(o); free(a); free(pos);
     if (failed) return ORC_NO_MEMORY;
     put128(out, total);
     return ORC_OK;
+}
+
+/* The same share, building (and freeing) the core-ordered DAG in the call. */
+int orc_clique_count_sampled(int32_t n, const int64_t *off, const int32_t *adj, int32_t k,
+                             int32_t threads, int32_t stride, int32_t offset, uint64_t *out)
+{
+    if (n < 0 || k < 3 || stride < 1 || offset < 0 || offset >= stride || !out)
+        return ORC_BAD_ARG;
+    struct orc_dag *g;
+    int rc = orc_dag_build(n, off, adj, &g);
+    if (rc) return rc;
+    rc = orc_dag_clique_count_sampled(g, k, threads, stride, offset, out);
+    orc_dag_free(g);
+    return rc;
 }
 
 /* Lists every k-clique (k >= 3) as its ascending vertex tuple.  The first

@@ -488,7 +488,8 @@ class Response(ctypes.Structure):
                 ("status", ctypes.c_int32), ("n_values", ctypes.c_int32),
                 ("values", ctypes.c_uint64 * 7),
                 ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
-                ("t_done", ctypes.c_double)]
+                ("t_done", ctypes.c_double),
+                ("d_start", ctypes.c_double), ("d_end", ctypes.c_double)]
 
     def counts(self):
         return [int(self.values[i]) for i in range(self.n_values)]

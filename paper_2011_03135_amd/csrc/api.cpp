@@ -2,6 +2,7 @@
 // dispatch.  Host code only; kernels live in the .hip translation units.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -34,6 +35,8 @@ gpm_status generic_list(const gpm_graph *g, const gpm_pattern *p, void *ws, uint
                         int32_t *buf, uint64_t cap, unsigned long long *result, hipStream_t st);
 gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, void *ws, uint64_t ws_bytes,
                          unsigned long long *out, hipStream_t st);
+gpm_status permute_rows4(int32_t *buf, uint64_t cap, const unsigned long long *result,
+                         const int32_t perm[4], hipStream_t st);
 gpm_status sl_run(const gpm_graph *g, int32_t plan, bool list, void *ws, uint64_t ws_bytes,
                   unsigned long long *d_count, int32_t *d_buf, uint64_t cap,
                   unsigned long long *d_result, hipStream_t st);
@@ -85,6 +88,28 @@ void degree_sig(const gpm_pattern *p, int32_t *deg) {
 gpm_status check_graph(const gpm_graph *g) {
     if (!g) return fail(GPM_INVALID_ARGUMENT, "graph is NULL");
     return GPM_OK;
+}
+
+// The subgraph-listing kernels write a diamond as (a, b, c, d) with a-b its
+// diagonal and a 4-cycle in cycle order, i.e. as maps of these labelled
+// patterns.  For the caller's labelling P of the same shape, perm[p] is the
+// column of the kernel's row that holds pattern vertex p of P: an
+// isomorphism phi from P onto the kernel's pattern (every edge (a, b) of P
+// lands on an edge (phi(a), phi(b))), found by trying the 24 orders.
+void sl_column_perm(const gpm_pattern *p, int32_t plan, int32_t perm[4]) {
+    static const int32_t kDiamond[5][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}};
+    static const int32_t kCycle[4][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}};
+    bool q[4][4] = {};
+    const int32_t (*qe)[2] = plan == GPM_PLAN_SL_DIAMOND ? kDiamond : kCycle;
+    const int nq = plan == GPM_PLAN_SL_DIAMOND ? 5 : 4;
+    for (int i = 0; i < nq; i++) q[qe[i][0]][qe[i][1]] = q[qe[i][1]][qe[i][0]] = true;
+    int32_t phi[4] = {0, 1, 2, 3};
+    do {
+        bool ok = true;
+        for (int i = 0; i < p->n_edges && ok; i++) ok = q[phi[p->edges[i][0]]][phi[p->edges[i][1]]];
+        if (ok) break;
+    } while (std::next_permutation(phi, phi + 4));
+    for (int i = 0; i < 4; i++) perm[i] = phi[i];
 }
 
 }  // namespace
@@ -173,6 +198,11 @@ gpm_status gpm_pattern_plan(const gpm_pattern *p, int32_t *plan) {
     // gpm_pattern_from_edges would before reading its edges
     if (k < 2 || k > GPM_MAX_PATTERN_VERTICES || ne < k - 1 || ne > k * (k - 1) / 2)
         return fail(GPM_INVALID_ARGUMENT, "pattern size or edge count out of range");
+    const uint32_t ind = p->flags & (GPM_VERTEX_INDUCED | GPM_EDGE_INDUCED);
+    if (ind != GPM_VERTEX_INDUCED && ind != GPM_EDGE_INDUCED)
+        return fail(GPM_INVALID_ARGUMENT, "exactly one of GPM_VERTEX_INDUCED, GPM_EDGE_INDUCED");
+    if (p->flags & ~(GPM_VERTEX_INDUCED | GPM_EDGE_INDUCED | GPM_LIST))
+        return fail(GPM_INVALID_ARGUMENT, "unknown pattern flag");
     bool seen[GPM_MAX_PATTERN_VERTICES][GPM_MAX_PATTERN_VERTICES] = {};
     for (int32_t i = 0; i < ne; i++) {
         const int32_t a = p->edges[i][0], b = p->edges[i][1];
@@ -182,6 +212,8 @@ gpm_status gpm_pattern_plan(const gpm_pattern *p, int32_t *plan) {
         if (seen[lo][hi]) return fail(GPM_INVALID_ARGUMENT, "repeated pattern edge");
         seen[lo][hi] = true;
     }
+    if (!connected_pattern(k, ne, p->edges))
+        return fail(GPM_INVALID_ARGUMENT, "pattern is not connected (connected patterns only)");
     const bool vertex_induced = (p->flags & GPM_VERTEX_INDUCED) != 0;
     // Orientation iff the pattern is a clique, |E| = |V|(|V|-1)/2; for a
     // clique, vertex- and edge-induced embeddings coincide.
@@ -322,7 +354,12 @@ gpm_status gpm_list(const gpm_graph *g, const gpm_pattern *p, void *d_ws, uint64
         return gpm::clique_run(g, p->k, true, d_ws, ws_bytes, nullptr, d_buf, cap, res, st);
     if (plan == GPM_PLAN_GENERIC)
         return gpm::generic_list(g, p, d_ws, ws_bytes, d_buf, cap, res, st);
-    return gpm::sl_run(g, plan, true, d_ws, ws_bytes, nullptr, d_buf, cap, res, st);
+    rc = gpm::sl_run(g, plan, true, d_ws, ws_bytes, nullptr, d_buf, cap, res, st);
+    if (rc) return rc;
+    int32_t perm[4];
+    sl_column_perm(p, plan, perm);
+    if (perm[0] == 0 && perm[1] == 1 && perm[2] == 2 && perm[3] == 3) return GPM_OK;
+    return gpm::permute_rows4(d_buf, cap, res, perm, st);
 }
 
 gpm_status gpm_clique_counts_workspace_bytes(const gpm_graph *g, int32_t kmax, uint64_t *bytes) {

@@ -230,11 +230,17 @@ unsigned wgrid(int64_t rows) {
 }
 
 // A small pinned host buffer for the per-round counters (allocated once per
-// process; pageable copies cost several times more per round trip).
-uint32_t *pinned_words() {
+// process; pageable copies cost several times more per round trip).  It is
+// shared by every thread, so read_u32 holds its mutex from the copy to the
+// copy-out: concurrent orientations (other graphs, other streams, other
+// threads) take turns at the buffer instead of reading each other's words.
+std::mutex &pinned_mutex() {
     static std::mutex mu;
+    return mu;
+}
+
+uint32_t *pinned_words_locked() {
     static uint32_t *p = nullptr;
-    std::lock_guard<std::mutex> lock(mu);
     if (!p) {
         void *q = nullptr;
         if (hipHostMalloc(&q, 64, hipHostMallocDefault) == hipSuccess) p = static_cast<uint32_t *>(q);
@@ -243,7 +249,8 @@ uint32_t *pinned_words() {
 }
 
 gpm_status read_u32(const uint32_t *d, uint32_t *h, int count, hipStream_t st) {
-    uint32_t *pin = pinned_words();
+    std::lock_guard<std::mutex> lock(pinned_mutex());
+    uint32_t *pin = pinned_words_locked();
     GPM_HIP(hipMemcpyAsync(pin ? pin : h, d, sizeof(uint32_t) * count, hipMemcpyDeviceToHost,
                            st));
     GPM_HIP(hipStreamSynchronize(st));

@@ -544,7 +544,7 @@ static gpm_status generic_run(const gpm_graph *g, const gpm_pattern *p, bool lis
     int64_t *chunk_off, *tmp;
     unsigned long long *cursor;
     gen_layout(cv, narcs, &chunks, &chunk_off, &tmp, &cursor);
-    if (!cv.fits()) return fail(GPM_INVALID_ARGUMENT, "workspace too small");
+    if (!cv.fits()) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
     GPM_HIP(fill_u32(reinterpret_cast<uint32_t *>(out), 0, list ? 6 : 2, st));
     if (g->m == 0) return GPM_OK;
     Span sp(list ? "k_generic_list" : "k_generic", st);

@@ -15,7 +15,7 @@
 // minus the neighbours of v_0..v_{i-1}.
 //
 // Connectivity codes (Section 4, memoised embedding connectivity;
-// Appendix C's example): the vertex added at position l contributes l bits,
+// Appendix B.6's example): the vertex added at position l contributes l bits,
 // bit j set iff it is adjacent to v_j; the embedding's code is the
 // concatenation (pair (j, l) at bit l(l-1)/2 + j, 10 bits for k = 5).  The
 // prefix for positions below l is kept with the embedding, so only the new
@@ -468,7 +468,7 @@ gpm_status motif_enum_count(const gpm_graph *g, int k, void *ws, uint64_t ws_byt
     int64_t *chunk_off, *tmp;
     unsigned long long *cursor;
     me_layout(cv, narcs, &chunks, &chunk_off, &tmp, &cursor);
-    if (!cv.fits()) return fail(GPM_INVALID_ARGUMENT, "workspace too small");
+    if (!cv.fits()) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
     const int nclass = motif_classes(k);
     GPM_HIP(fill_u32(reinterpret_cast<uint32_t *>(out), 0, 2 * (uint64_t)nclass, st));
     if (g->m == 0) return GPM_OK;

@@ -87,6 +87,10 @@ struct gpm_server {
     Pool *pool = nullptr;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
+    // per slot: timing events recorded on the slot's stream before and after
+    // a request's work, read against `ref` (recorded once at creation)
+    std::vector<hipEvent_t> ev_start, ev_end;
+    hipEvent_t ref = nullptr;
     std::vector<Job *> slot_job;
     uint64_t *pinned = nullptr;    // per slot: 8 words
     std::mutex mu;
@@ -121,6 +125,7 @@ gpm_status launch(gpm_server *s, int i, Job *j) {
     void *ws = pool + s->result_bytes + j->ws_off;
     hipStream_t st = s->streams[i];
     gpm_status rc;
+    GPM_HIP(hipEventRecord(s->ev_start[i], st));
     // size this request's persistent grids for its share of the device
     gpm::set_cu_limit(s->cu_limit);
     if (j->req.kind == GPM_QUERY_CLIQUE)
@@ -129,6 +134,7 @@ gpm_status launch(gpm_server *s, int i, Job *j) {
         rc = gpm_motif_count(j->req.graph, j->req.k, ws, j->ws_bytes, d_res, st);
     gpm::set_cu_limit(0);
     if (rc) return rc;
+    GPM_HIP(hipEventRecord(s->ev_end[i], st));
     GPM_HIP(hipMemcpyAsync(s->pinned + 8 * i, d_res, 64, hipMemcpyDeviceToHost, st));
     GPM_HIP(hipEventRecord(s->events[i], st));
     return GPM_OK;
@@ -157,6 +163,14 @@ void run(gpm_server *s) {
                 j->resp.status = GPM_DEVICE_ERROR;
             } else {
                 for (int v = 0; v < 7; v++) j->resp.values[v] = s->pinned[8 * i + v];
+                float a = 0.f, b = 0.f;
+                if (hipEventElapsedTime(&a, s->ref, s->ev_start[i]) == hipSuccess &&
+                    hipEventElapsedTime(&b, s->ref, s->ev_end[i]) == hipSuccess) {
+                    j->resp.d_start = 1e-3 * a;
+                    j->resp.d_end = 1e-3 * b;
+                } else {
+                    j->resp.d_start = j->resp.d_end = -1.0;
+                }
             }
             s->pool->release(j->ws_off, j->ws_alloc);
             s->slot_job[i] = nullptr;
@@ -244,6 +258,28 @@ gpm_status gpm_server_create(const gpm_server_config *cfg, gpm_server **out) {
         s->streams.push_back(st);
         s->events.push_back(ev);
         s->slot_job.push_back(nullptr);
+        hipEvent_t ea, eb;
+        if (hipEventCreate(&ea) != hipSuccess) {
+            gpm_server_destroy(s);
+            return gpm::fail(GPM_DEVICE_ERROR, "event creation failed");
+        }
+        if (hipEventCreate(&eb) != hipSuccess) {
+            (void)hipEventDestroy(ea);
+            gpm_server_destroy(s);
+            return gpm::fail(GPM_DEVICE_ERROR, "event creation failed");
+        }
+        s->ev_start.push_back(ea);
+        s->ev_end.push_back(eb);
+    }
+    if (hipEventCreate(&s->ref) != hipSuccess) {
+        s->ref = nullptr;
+        gpm_server_destroy(s);
+        return gpm::fail(GPM_DEVICE_ERROR, "event creation failed");
+    }
+    if (hipEventRecord(s->ref, s->streams[0]) != hipSuccess ||
+        hipEventSynchronize(s->ref) != hipSuccess) {
+        gpm_server_destroy(s);
+        return gpm::fail(GPM_DEVICE_ERROR, "reference event failed");
     }
     void *pin = nullptr;
     if (hipHostMalloc(&pin, (size_t)cfg->max_slots * 64, hipHostMallocDefault) != hipSuccess) {
@@ -310,6 +346,9 @@ void gpm_server_destroy(gpm_server *s) {
     if (s->worker.joinable()) s->worker.join();
     for (auto st : s->streams) (void)hipStreamDestroy(st);
     for (auto ev : s->events) (void)hipEventDestroy(ev);
+    for (auto ev : s->ev_start) (void)hipEventDestroy(ev);
+    for (auto ev : s->ev_end) (void)hipEventDestroy(ev);
+    if (s->ref) (void)hipEventDestroy(s->ref);
     if (s->pinned) (void)hipHostFree(s->pinned);
     for (auto *j : s->queue) delete j;
     delete s->pool;

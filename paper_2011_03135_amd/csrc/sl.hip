@@ -361,4 +361,34 @@ gpm_status sl_run(const gpm_graph *g, int32_t plan, bool list, void *ws, uint64_
     return GPM_OK;
 }
 
+// Column permutation of the written rows of a 4-vertex listing:
+// row'[p] = row[perm[p]] for the first min(result[1], cap) rows (result[1]
+// = rows written, set by the listing before this runs on the stream).
+struct Perm4 {
+    int32_t p[4];
+};
+
+__global__ void k_permute_rows4(int32_t *buf, uint64_t cap, const unsigned long long *result,
+                                Perm4 perm) {
+    const uint64_t w = result[1] < cap ? result[1] : cap;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < w; i += stride) {
+        int4 *r = reinterpret_cast<int4 *>(buf + 4 * i);
+        const int4 x = *r;
+        const int32_t v[4] = {x.x, x.y, x.z, x.w};
+        *r = make_int4(v[perm.p[0]], v[perm.p[1]], v[perm.p[2]], v[perm.p[3]]);
+    }
+}
+
+gpm_status permute_rows4(int32_t *buf, uint64_t cap, const unsigned long long *result,
+                         const int32_t perm[4], hipStream_t st) {
+    if (cap == 0) return GPM_OK;
+    Perm4 p;
+    for (int i = 0; i < 4; i++) p.p[i] = perm[i];
+    const unsigned blocks = (unsigned)std::min<uint64_t>((cap + 255) / 256, (uint64_t)cu_count() * 8);
+    hipLaunchKernelGGL(k_permute_rows4, dim3(blocks), dim3(256), 0, st, buf, cap, result, p);
+    GPM_LAUNCH_CHECK("k_permute_rows4");
+    return GPM_OK;
+}
+
 }  // namespace gpm

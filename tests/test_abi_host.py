@@ -66,6 +66,17 @@ def test_patterns_and_plans():
         bad.edges[i][0], bad.edges[i][1] = a, b
     bad.flags = gpm.EDGE_INDUCED
     assert load().gpm_pattern_plan(ctypes.byref(bad), ctypes.byref(plan)) != 0
+    # flags of a caller-built struct: exactly one induced flag, no unknown bit
+    for flags in (0, gpm.LIST, gpm.VERTEX_INDUCED | gpm.EDGE_INDUCED, gpm.EDGE_INDUCED | 0x100):
+        q = gpm.cycle4()
+        q.flags = flags
+        assert load().gpm_pattern_plan(ctypes.byref(q), ctypes.byref(plan)) == 1, flags
+    # a disconnected struct handed in directly is rejected too
+    q = Pattern()
+    q.k, q.n_edges, q.flags = 4, 3, gpm.EDGE_INDUCED
+    for i, (a, b) in enumerate([(0, 1), (1, 2), (0, 2)]):
+        q.edges[i][0], q.edges[i][1] = a, b
+    assert load().gpm_pattern_plan(ctypes.byref(q), ctypes.byref(plan)) == 1
     with pytest.raises(GpmError):
         gpm.pattern(4, [(0, 1), (2, 3)], gpm.EDGE_INDUCED)            # disconnected
     with pytest.raises(GpmError):

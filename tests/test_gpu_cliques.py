@@ -291,6 +291,20 @@ def test_clique_listing(gpm, k):
         assert all((a, b) in A for i, a in enumerate(r) for b in r[i + 1:])
 
 
+@pytest.mark.parametrize("k", [3, 4])
+def test_edge_induced_clique_listing_key(gpm, k):
+    """A clique's vertex- and edge-induced embeddings are the same vertex
+    sets, and the listing keys both by the ascending vertex tuple: the
+    edge-induced flag gives the oracle's clique listing too."""
+    e = graphgen.erdos_renyi(60, 0.35, 4)
+    g = build(gpm, e)
+    off, adj = canonical_csr(e.n, e.u, e.v)
+    total, chk, rows = oracle.clique_list(off, adj, k, cap=10 ** 6)
+    t, w, c, got = gpm.list_embeddings(g, gpm.clique(k, gpm.EDGE_INDUCED | gpm.LIST), 10 ** 6)
+    assert (t, w, c) == (total, total, chk)
+    assert {tuple(sorted(r)) for r in got.cpu().tolist()} == {tuple(sorted(r)) for r in rows.tolist()}
+
+
 def hub_graph(seed=3):
     """Roots in every out-degree class: 300 hubs (350 leaf edges each, random
     hub-hub edges p = 0.15), root A adjacent to all hubs (out-degree 300,

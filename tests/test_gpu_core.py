@@ -123,3 +123,40 @@ def test_orient_errors(gpm):
     with pytest.raises(GpmError) as ei:
         g.orient(7)
     assert ei.value.status == 1
+
+
+def test_concurrent_orientations_from_two_threads(gpm):
+    """Two host threads orient two different graphs on their own streams at
+    the same time (the peeling reads its counters through one shared pinned
+    buffer); both core arrays equal the oracle's."""
+    import threading
+    es = [graphgen.rmat(12, seed=12), graphgen.rmat(13, seed=13)]
+    gs = [build(gpm, e) for e in es]
+    want = []
+    for e in es:
+        off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+        want.append(oracle.core_numbers(off, adj))
+    torch.cuda.synchronize()
+    got = [None, None]
+    errors = []
+
+    def work(i):
+        try:
+            s = torch.cuda.Stream()
+            for _ in range(3):
+                with torch.cuda.stream(s):
+                    core = gs[i].orient(gpm.ORIENT_CORE, stream=s, core_out=True)
+                s.synchronize()
+                got[i] = core.cpu().numpy()
+                assert np.array_equal(got[i], want[i])
+        except Exception as ex:   # reported by the main thread
+            errors.append(repr(ex))
+
+    ts = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errors, errors
+    for i in range(2):
+        assert np.array_equal(got[i], want[i])

@@ -3,6 +3,7 @@ import json
 import os
 
 import numpy as np
+import torch
 import pytest
 
 import graphgen
@@ -85,17 +86,90 @@ def test_sl_truncated(gpm, name):
     assert len(sets) == cap and sets <= valid
 
 
-def test_rmat18_sl_golden(gpm):
+def edge_code_set(off, adj):
+    n = off.shape[0] - 1
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(off))
+    return np.sort(src * (1 << 32) + adj.astype(np.int64))
+
+
+def rows_are_maps(rows, pattern_edges, codes):
+    """Every row maps every pattern edge onto a graph edge, with distinct
+    vertices (vectorised over the rows)."""
+    rows = rows.astype(np.int64)
+    for a in range(rows.shape[1]):
+        for b in range(a + 1, rows.shape[1]):
+            if np.any(rows[:, a] == rows[:, b]):
+                return False
+    for a, b in pattern_edges:
+        c = rows[:, a] * (1 << 32) + rows[:, b]
+        pos = np.searchsorted(codes, c)
+        if np.any(pos >= codes.shape[0]) or np.any(codes[np.minimum(pos, codes.shape[0] - 1)] != c):
+            return False
+    return True
+
+
+RELABELLED = {
+    # the diamond with diagonal (2, 3) and tips 0, 1
+    "diamond": [(2, 3), (2, 0), (2, 1), (3, 0), (3, 1)],
+    # the 4-cycle 0-2-1-3-0
+    "4-cycle": [(0, 2), (2, 1), (1, 3), (3, 0)],
+}
+
+
+@pytest.mark.parametrize("name", PATS)
+def test_sl_relabelled_pattern_rows(gpm, name):
+    """A diamond or 4-cycle labelled differently from the listing kernels'
+    own order still gets rows that map its own pattern vertices: every
+    pattern edge lands on a graph edge, and the embeddings are the oracle's."""
+    e = graphgen.rmat(11, seed=43)
+    g = build(gpm, e)
+    off, adj = canonical_csr(e.n, e.u, e.v)
+    ofn = oracle.list_diamonds if name == "diamond" else oracle.list_c4
+    total, chk, rows = ofn(off, adj, cap=2 * 10 ** 6)
+    edges = RELABELLED[name]
+    lpat = gpm.pattern(4, edges, gpm.EDGE_INDUCED | gpm.LIST)
+    t, w, c, got = gpm.list_embeddings(g, lpat, 2 * 10 ** 6)
+    assert (t, w, c) == (total, total, chk)
+    got = got.cpu().numpy()
+    assert rows_are_maps(got, edges, edge_code_set(off, adj))
+    # as edge sets, the embeddings are the oracle's
+    sets = {frozenset(tuple(sorted((int(r[a]), int(r[b])))) for a, b in edges) for r in got}
+    assert sets == edge_sets(name, rows.tolist())
+
+
+def test_rmat18_sl_full_cap(gpm):
+    """The listing configuration at scale: RMAT-18 edge-induced diamonds and
+    4-cycles with a 2^26-row buffer.  Totals and checksums equal the oracle's
+    golden values, the buffer is filled, and 10^5 sampled rows are real
+    embeddings (every pattern edge a graph edge, distinct edge sets)."""
     if not os.path.exists(GOLDEN):
         pytest.skip("golden counts not generated")
     with open(GOLDEN) as f:
         gold = json.load(f).get("rmat18", {})
     if "sl_4-cycle" not in gold:
         pytest.skip("rmat18 listing golden values not generated")
-    g = build(gpm, graphgen.rmat(18, seed=18))
-    for name, pat, lpat in (("diamond", gpm.diamond(), gpm.diamond(gpm.EDGE_INDUCED | gpm.LIST)),
-                            ("4-cycle", gpm.cycle4(), gpm.cycle4(gpm.EDGE_INDUCED | gpm.LIST))):
+    e = graphgen.rmat(18, seed=18)
+    g = build(gpm, e)
+    off, adj = canonical_csr(e.n, e.u, e.v)
+    codes = edge_code_set(off, adj)
+    cap = 1 << 26
+    rng = np.random.default_rng(2026)
+    for name, lpat, edges in (
+            ("diamond", gpm.diamond(gpm.EDGE_INDUCED | gpm.LIST),
+             [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3)]),
+            ("4-cycle", gpm.cycle4(gpm.EDGE_INDUCED | gpm.LIST),
+             [(0, 1), (1, 2), (2, 3), (3, 0)])):
         want = gold[f"sl_{name}"]
-        assert gpm.count(g, pat) == want["total"]
-        t, w, c, _ = gpm.list_embeddings(g, lpat, 1 << 20)
-        assert (t, w, c) == (want["total"], min(1 << 20, want["total"]), want["checksum"])
+        cpat = gpm.diamond() if name == "diamond" else gpm.cycle4()
+        assert gpm.count(g, cpat) == want["total"]
+        print(f"rmat18 {name} listing, cap 2^26", flush=True)
+        t, w, c, rows = gpm.list_embeddings(g, lpat, cap)
+        assert (t, w, c) == (want["total"], cap, want["checksum"])
+        idx = torch.from_numpy(rng.choice(cap, size=10 ** 5, replace=False)).cuda()
+        sample = rows[idx].cpu().numpy()
+        del rows
+        torch.cuda.empty_cache()
+        assert rows_are_maps(sample, edges, codes)
+        keys = {tuple(sorted(tuple(sorted((int(r[a]), int(r[b])))) for a, b in edges))
+                for r in sample}
+        assert len(keys) == sample.shape[0]

@@ -372,3 +372,38 @@ def test_pattern_list_brute_force(seed, n, p, induced):
         else:
             assert chk == sum(_hash([_ecode(a, b) for a, b in key]) for key in want) % (1 << 64)
         assert total == oracle.pattern_count(off, adj, k, edges, induced)[0]
+
+
+@pytest.mark.parametrize("n,k,stride", [(12, 3, 1), (12, 4, 5), (17, 5, 3), (9, 3, 9)])
+def test_clique_count_sampled_complete_graph(n, k, stride):
+    """In K_n the vertex at position p of any total order has n - 1 - p later
+    neighbours, all adjacent, so the k-cliques it starts are C(n-1-p, k-1):
+    each share of the roots has a closed form, whatever the order."""
+    off, adj = csr(graphgen.complete_graph(n))
+    dag = oracle.CoreDag(off, adj)
+    for o in range(stride):
+        want = sum(C(n - 1 - p, k - 1) for p in range(o, n, stride))
+        assert oracle.clique_count_sampled(off, adj, k, stride, o) == want
+        assert dag.clique_count_sampled(k, stride, o) == want
+    dag.close()
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_clique_count_sampled_shares_add_up(k):
+    """Every clique has exactly one first vertex, so the shares over all
+    offsets add up to the clique count: on a complete multipartite graph
+    (closed form e_k) and on an RMAT graph (the pinned clique count)."""
+    parts = [3, 9, 1, 1, 6]
+    off, adj = csr(graphgen.complete_multipartite(parts))
+    assert sum(oracle.clique_count_sampled(off, adj, k, 4, o) for o in range(4)) == esym(parts, k)
+    g = graphgen.rmat(12, seed=7)
+    off, adj = csr(g)
+    dag = oracle.CoreDag(off, adj)
+    full = oracle.clique_count(off, adj, k)
+    assert dag.clique_count_sampled(k, 1) == full
+    shares = [dag.clique_count_sampled(k, 7, o) for o in range(7)]
+    assert sum(shares) == full
+    assert all(0 < s < full for s in shares)
+    dag.close()
+    with pytest.raises(RuntimeError):
+        oracle.clique_count_sampled(off, adj, k, 7, 7)
