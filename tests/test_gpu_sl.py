@@ -121,7 +121,7 @@ def test_sl_relabelled_pattern_rows(gpm, name):
     """A diamond or 4-cycle labelled differently from the listing kernels'
     own order still gets rows that map its own pattern vertices: every
     pattern edge lands on a graph edge, and the embeddings are the oracle's."""
-    e = graphgen.rmat(11, seed=43)
+    e = graphgen.erdos_renyi(300, 0.15, 8)
     g = build(gpm, e)
     off, adj = canonical_csr(e.n, e.u, e.v)
     ofn = oracle.list_diamonds if name == "diamond" else oracle.list_c4
