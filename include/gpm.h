@@ -328,6 +328,22 @@ gpm_status gpm_batch_motif_count(const gpm_graph *g, const int32_t *d_voff, int3
                                  int32_t k, void *d_ws, uint64_t ws_bytes,
                                  uint64_t *d_counts, void *stream);
 
+/* gpm_batch_motif_count for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same computation, results and kernels, with the work area that
+ * gpm_batch_motif_count takes as d_ws held instead in a static device array
+ * of GPM_BATCH_STATIC_SCRATCH_BYTES that the library keeps on each device
+ * it runs on until the process ends.  The caller passes inputs and outputs
+ * only.  No memory of any kind is allocated (no timing spans are recorded
+ * either).  G above GPM_BATCH_STATIC_MAX_GRAPHS gives GPM_OUT_OF_MEMORY
+ * before anything is enqueued.  Calls on one device share that device's
+ * array: calls that overlap in time on the same device (other streams,
+ * other threads) race and must be ordered by the caller. */
+#define GPM_BATCH_STATIC_SCRATCH_BYTES (4u << 20)
+#define GPM_BATCH_STATIC_MAX_GRAPHS 1045492
+gpm_status gpm_batch_motif_count_static(const gpm_graph *g, const int32_t *d_voff, int32_t G,
+                                        int32_t k, uint64_t *d_counts, void *stream);
+
 /* How a batch is mined.  Graphs are mined largest first by teams of
  * threads, one graph per team at a time, each graph's adjacency held as bit
  * rows in LDS.  Graphs of 257..1024 vertices always go to 256-thread teams;

@@ -18,6 +18,7 @@ from .binding import (  # noqa: F401
     batch_autotune,
     batch_default_config,
     batch_motif_count,
+    batch_motif_count_static,
     clique,
     clique_counts,
     count,

@@ -90,6 +90,7 @@ def load():
         "gpm_batch_default_config": ([P], i32),
         "gpm_batch_motif_count_config": ([P, P, i32, i32, P, P, u64, P, P], i32),
         "gpm_batch_autotune": ([P, P, i32, i32, P, u64, P, P, i32, P, P], i32),
+        "gpm_batch_motif_count_static": ([P, P, i32, i32, P, P], i32),
         "gpm_timing_enable": ([i32], i32),
         "gpm_timing_read": ([P, P, P, i32], i32),
         "gpm_server_create": ([P, P], i32),
@@ -453,6 +454,24 @@ def batch_motif_count(g, voff, k, stream=None, ws=None, out=None, config=None):
         _check(load().gpm_batch_motif_count_config(g.handle, _ptr(voff.contiguous()), G, int(k),
                                                    ctypes.byref(config), _ptr(ws), ws.numel(),
                                                    _ptr(res), _stream(stream)))
+    return res
+
+
+BATCH_STATIC_SCRATCH_BYTES = 4 << 20
+BATCH_STATIC_MAX_GRAPHS = 1045492
+
+
+def batch_motif_count_static(g, voff, k, stream=None, out=None):
+    """gpm_batch_motif_count_static: the batch's work area in the library's
+    static device scratch (no workspace argument, nothing allocated by the
+    library) -> int64 tensor [G, 3 or 7] (uint64 bits)."""
+    G = int(voff.shape[0] - 1)
+    if voff.dtype != torch.int32 or not voff.is_cuda:
+        raise TypeError("voff must be an int32 CUDA tensor")
+    width = 3 if k == 3 else 7
+    res = out if out is not None else torch.zeros((G, width), dtype=torch.int64, device=g.device)
+    _check(load().gpm_batch_motif_count_static(g.handle, _ptr(voff.contiguous()), G, int(k),
+                                               _ptr(res), _stream(stream)))
     return res
 
 

@@ -53,6 +53,8 @@ gpm_status batch_default_config(gpm_batch_config *c);
 gpm_status batch_run(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,
                      const gpm_batch_config *cfg, void *ws, uint64_t ws_bytes,
                      unsigned long long *d_counts, hipStream_t st);
+gpm_status batch_run_static(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,
+                            unsigned long long *d_counts, hipStream_t st);
 gpm_status batch_autotune(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,
                           void *ws, uint64_t ws_bytes, unsigned long long *d_counts,
                           hipStream_t st, int32_t reps, gpm_batch_config *best, float *best_ms);
@@ -468,6 +470,17 @@ gpm_status gpm_batch_motif_count(const gpm_graph *g, const int32_t *d_voff, int3
     gpm_batch_config cfg;
     gpm::batch_default_config(&cfg);
     return gpm_batch_motif_count_config(g, d_voff, G, k, &cfg, d_ws, ws_bytes, d_counts, stream);
+}
+
+gpm_status gpm_batch_motif_count_static(const gpm_graph *g, const int32_t *d_voff, int32_t G,
+                                        int32_t k, uint64_t *d_counts, void *stream) {
+    gpm_status rc = check_graph(g);
+    if (rc) return rc;
+    if (!d_voff || !d_counts) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    if (G < 1) return fail(GPM_INVALID_ARGUMENT, "G must be >= 1");
+    if (k != 3 && k != 4) return fail(GPM_UNSUPPORTED, "motif size must be 3 or 4");
+    return gpm::batch_run_static(g, d_voff, G, k, reinterpret_cast<unsigned long long *>(d_counts),
+                                 static_cast<hipStream_t>(stream));
 }
 
 gpm_status gpm_batch_autotune(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,

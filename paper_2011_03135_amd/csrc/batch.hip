@@ -27,6 +27,8 @@
 #include "gpm_internal.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <vector>
 
 namespace gpm {
@@ -443,6 +445,66 @@ gpm_status batch_autotune(const gpm_graph *g, const int32_t *d_voff, int32_t G, 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (best_ms) *best_ms = best_t;
+    return rc;
+}
+
+// ------------------------------------------------- static scratch entry --
+// gpm_batch_motif_count_static: the batch's work area (histogram, tier
+// cursors, the largest-first graph order: batch_workspace_bytes) lives in a
+// file-scope device array instead of a caller workspace, so the call makes
+// no allocation of any kind.  Each device holds its own copy of the array;
+// its address is looked up once per device (the host-side name of a
+// __device__ array is not a device address) and kept.  Every call on a
+// device uses that device's copy: calls that overlap in time on one device
+// race on it.  batch_run clears what must start at zero (histogram, cursors)
+// with fill kernels before use, so whatever an earlier call left there does
+// not matter.
+static __device__ __align__(256) unsigned char scratch[GPM_BATCH_STATIC_SCRATCH_BYTES];
+static_assert((kWsHead + GPM_BATCH_STATIC_MAX_GRAPHS) * 4 <= GPM_BATCH_STATIC_SCRATCH_BYTES &&
+                  (kWsHead + GPM_BATCH_STATIC_MAX_GRAPHS + 1) * 4 > GPM_BATCH_STATIC_SCRATCH_BYTES,
+              "GPM_BATCH_STATIC_MAX_GRAPHS is the largest batch the static scratch holds");
+
+namespace {
+
+gpm_status static_scratch(void **out) {
+    int dev = 0;
+    GPM_HIP(hipGetDevice(&dev));
+    static std::mutex mu;
+    static std::map<int, void *> ptrs;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = ptrs.find(dev);
+    if (it != ptrs.end()) {
+        *out = it->second;
+        return GPM_OK;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    ptrs[dev] = p;
+    *out = p;
+    return GPM_OK;
+}
+
+}  // namespace
+
+gpm_status batch_run_static(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,
+                            unsigned long long *d_counts, hipStream_t st) {
+    uint64_t need = 0;
+    batch_workspace_bytes(G, k, &need);
+    if (need > GPM_BATCH_STATIC_SCRATCH_BYTES)
+        return fail(GPM_OUT_OF_MEMORY,
+                    "batch too large for the static scratch: G = " + std::to_string(G) +
+                        " needs " + std::to_string(need) + " bytes, the static scratch holds " +
+                        std::to_string((uint64_t)GPM_BATCH_STATIC_SCRATCH_BYTES) +
+                        " (at most GPM_BATCH_STATIC_MAX_GRAPHS graphs)");
+    void *ws = nullptr;
+    gpm_status rc = static_scratch(&ws);
+    if (rc) return rc;
+    gpm_batch_config cfg;
+    batch_default_config(&cfg);
+    spans_suppress(true);
+    rc = batch_run(g, d_voff, G, k, &cfg, ws, GPM_BATCH_STATIC_SCRATCH_BYTES, d_counts, st);
+    spans_suppress(false);
     return rc;
 }
 

@@ -83,6 +83,9 @@ hipError_t exclusive_scan_64(const int64_t *in, int64_t *out, uint64_t n, int64_
 // Optional kernel timing (off by default): when on, span_begin/span_end
 // bracket a launch with HIP events recorded on its stream.
 bool timing_on();
+// While on, the calling thread records no timing spans (for entry points
+// that must not allocate).
+void spans_suppress(bool on);
 void timing_set(bool on);
 int timing_read(const char **names, float *ms, uint64_t *units, int cap);
 // Attaches work units (a device uint64, copied when this is called, in

@@ -172,7 +172,15 @@ unsigned long long *g_units = nullptr;   // pinned host slots
 int g_units_used = 0;
 }  // namespace
 
+// Set while an entry point that must not allocate runs on this thread: its
+// kernels record no spans (a span creates events and, for work units, a
+// pinned host buffer).
+static thread_local bool tls_no_spans = false;
+
+void spans_suppress(bool on) { tls_no_spans = on; }
+
 void span_units(const unsigned long long *d_units, hipStream_t s) {
+    if (tls_no_spans) return;
     std::lock_guard<std::mutex> lock(g_tmu);
     if (!g_timing || g_open.empty()) return;
     if (!g_units) {
@@ -189,7 +197,7 @@ void span_units(const unsigned long long *d_units, hipStream_t s) {
                          hipMemcpyDeviceToHost, s);
 }
 
-bool timing_on() { return g_timing; }
+bool timing_on() { return g_timing && !tls_no_spans; }
 
 void span_begin(const char *name, hipStream_t s) {
     std::lock_guard<std::mutex> lock(g_tmu);
