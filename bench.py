@@ -162,6 +162,14 @@ def cpu_baseline(e, stride, ks, threads, gpu_counts):
 
 
 def batch_leg(gpm, torch, G, plain_graphs, replays):
+    """20,000 random geometric graphs, induced 4-motif counts.  Batched: one
+    fused persistent launch per tier (configuration picked by the
+    autotuner) replayed from a HIP graph.  Plain, same kernels: one
+    gpm_batch_motif_count call per graph (G = 1, the graph's own vertex
+    range of the same union graph), stream-serialised, no capture.  Plain,
+    general call: gpm_motif_count on each graph built on its own, timed on
+    `plain_graphs` graphs and scaled to all."""
+    import ctypes
     import graphgen
     dev = torch.device("cuda:0")
     batch = graphgen.rgg_batch(G, seed=2020)
@@ -191,7 +199,35 @@ def batch_leg(gpm, torch, G, plain_graphs, replays):
     torch.cuda.synchronize()
     batched_ms = a.elapsed_time(b) / replays
     batched = out.cpu().numpy()
-    # plain: one motif call per graph on graphs built beforehand
+
+    # plain, same kernels: G calls with G = 1 on the graph's offset pair
+    lib = gpm.binding.load()
+    ws1 = torch.empty(gpm.binding.batch_workspace_bytes(1, 4), dtype=torch.uint8, device=dev)
+    out1 = torch.zeros((G, 7), dtype=torch.int64, device=dev)
+    cfgp = ctypes.byref(cfg)
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    gh, wsp, wsn = g.handle, ctypes.c_void_p(ws1.data_ptr()), ws1.numel()
+    vp = [ctypes.c_void_p(voff.data_ptr() + 4 * i) for i in range(G)]
+    op = [ctypes.c_void_p(out1.data_ptr() + 56 * i) for i in range(G)]
+
+    def plain_loop():
+        for i in range(G):
+            rc = lib.gpm_batch_motif_count_config(gh, vp[i], 1, 4, cfgp, wsp, wsn, op[i], st)
+            if rc:
+                raise RuntimeError(f"gpm_batch_motif_count_config failed: {rc}")
+
+    plain_loop()   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a.record()
+    plain_loop()
+    b.record()
+    torch.cuda.synchronize()
+    plain_same_ms = a.elapsed_time(b)
+    plain_same_wall_ms = (time.perf_counter() - t0) * 1e3
+    same_kernels_equal = bool(np.array_equal(out1.cpu().numpy(), batched))
+
+    # plain, general call: one gpm_motif_count per separately built graph
     P = min(plain_graphs, G)
     graphs = []
     for i in range(P):
@@ -215,19 +251,104 @@ def batch_leg(gpm, torch, G, plain_graphs, replays):
         "batched_ms": batched_ms,
         "autotuned_config": cfg.as_dict(), "autotune_ms": tuned_ms,
         "graphs_per_sec_batched": G / (batched_ms * 1e-3),
-        "plain_ms_measured": plain_ms, "plain_graphs_measured": P,
-        "plain_ms_for_all": plain_equiv,
-        "speedup": plain_equiv / batched_ms,
-        "plain_equals_batched": same,
+        "plain_same_kernels": {
+            "what": "one gpm_batch_motif_count call per graph (G = 1), same configuration, "
+                    "stream-serialised, no graph capture",
+            "ms": plain_same_ms, "host_wall_ms": plain_same_wall_ms,
+            "graphs_per_sec": G / (plain_same_ms * 1e-3),
+            "equals_batched": same_kernels_equal},
+        "speedup": plain_same_ms / batched_ms,
+        "plain_general_call": {
+            "what": "one gpm_motif_count call per separately built graph (the general "
+                    "local-count pipeline, dozens of launches per graph)",
+            "ms_measured": plain_ms, "graphs_measured": P, "ms_for_all": plain_equiv,
+            "speedup_vs_batched": plain_equiv / batched_ms,
+            "equals_batched": same},
         "batched_status_ok": bool((batched[:, 6] == 0).all()),
     }
+
+
+def device_concurrency(resps):
+    """Mean number of requests in flight on the device: the sum of the
+    requests' device spans (events on their slot streams before and after
+    their work) over the span from the first start to the last end."""
+    spans = [(r.d_start, r.d_end) for r in resps if r.d_start >= 0.0]
+    if not spans:
+        return None
+    busy = sum(b - a for a, b in spans)
+    total = max(b for _, b in spans) - min(a for a, _ in spans)
+    return busy / total if total > 0 else None
+
+
+def serve_compare(gpm, torch, graphs, n_requests=1000, seed=502):
+    """The same seeded request list (query and graph drawn uniformly) run
+    plain (one synchronous library call after another on one stream, as a
+    client without the server would) and through the server, all requests
+    submitted at once (a saturating load), with one slot and with four.
+    Throughput = requests / wall time; latency = submission to result on
+    the host."""
+    from paper_2011_03135_amd.binding import QUERY_CLIQUE, Server
+    from paper_2011_03135_amd.serve import QUERIES, percentile
+    rng = np.random.default_rng(seed)
+    gi = rng.integers(0, len(graphs), size=n_requests)
+    qi = rng.integers(0, len(QUERIES), size=n_requests)
+
+    def plain_call(g, q):
+        _, kind, k = QUERIES[q]
+        if kind == QUERY_CLIQUE:
+            return [gpm.count(g, gpm.clique(k))]
+        return gpm.motif_count(g, k)
+
+    for g in graphs:                      # warm-up: every query on every graph once
+        for q in range(len(QUERIES)):
+            plain_call(g, q)
+    torch.cuda.synchronize()
+    lat, plain_res = [], []
+    t0 = time.perf_counter()
+    for j in range(n_requests):
+        ts = time.perf_counter()
+        plain_res.append(plain_call(graphs[gi[j]], qi[j]))
+        lat.append(time.perf_counter() - ts)
+    t_plain = time.perf_counter() - t0
+    res = {"requests": n_requests, "seed": seed,
+           "plain": {"throughput_rps": n_requests / t_plain, "wall_s": t_plain,
+                     "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99)}}
+
+    def served(slots, cu_percent):
+        srv = Server(max_slots=slots, pool_bytes=48 << 30, cu_percent=cu_percent)
+        t0 = Server.now()
+        for j in range(n_requests):
+            _, kind, k = QUERIES[qi[j]]
+            srv.submit(graphs[gi[j]], kind, k, tag=j)
+        done = {}
+        while len(done) < n_requests:
+            for r in srv.poll():
+                done[r.tag] = r
+            time.sleep(0.0002)
+        srv.close()
+        rs = [done[j] for j in range(n_requests)]
+        wall = max(r.t_done for r in rs) - t0
+        lat = [r.t_done - r.t_submit for r in rs]
+        return {"slots": slots, "cu_percent": cu_percent,
+                "throughput_rps": n_requests / wall, "wall_s": wall,
+                "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+                "device_requests_in_flight": device_concurrency(rs),
+                "failed": sum(1 for r in rs if r.status != 0),
+                "equals_plain": all(rs[j].counts() == plain_res[j] for j in range(n_requests))}
+
+    for slots, pct in ((1, 100), (4, 50), (4, 100)):
+        key = f"server_{slots}slot" + ("" if slots == 1 else f"_cu{pct}")
+        res[key] = served(slots, pct)
+        res[key]["vs_plain"] = res[key]["throughput_rps"] / res["plain"]["throughput_rps"]
+    return res
 
 
 def serve_leg(gpm, torch, g20, scale, requests, warmup):
     """Open-loop serving load: Poisson arrivals at 500 requests/s, each a
     query drawn uniformly from {TC, 4-clique, 3-motif, 4-motif} on one of 8
     resident graphs drawn uniformly (RMAT scales 12..18 and the step's
-    scale-20 graph).  Every request recomputes its answer."""
+    scale-20 graph).  Every request recomputes its answer.  Then the same
+    kind of mix saturating the server, against plain back-to-back calls."""
     import graphgen
     from paper_2011_03135_amd.serve import run_load
     dev = torch.device("cuda:0")
@@ -254,7 +375,107 @@ def serve_leg(gpm, torch, g20, scale, requests, warmup):
     stats["below_capacity"] = {k: low[k] for k in ("offered_rate", "requests", "throughput_rps",
                                                    "p50_ms", "p99_ms", "mean_queue_ms", "failed",
                                                    "per_query")}
+    log("serving: served vs plain")
+    stats["served_vs_plain"] = serve_compare(gpm, torch, graphs)
     return stats
+
+
+def c4_wedges(off, adj):
+    """Wedges x - y - z the 4-cycle kernels scan: y below x and z below x in
+    the degree order (x the cycle's top vertex), z != x.  For each arc
+    y -> x (y below x) that is the number of y's neighbours ranked below x,
+    i.e. x's position among y's neighbours sorted by rank."""
+    n = off.shape[0] - 1
+    deg = np.diff(off).astype(np.int64)
+    rank_key = deg * (1 << 32) + np.arange(n, dtype=np.int64)      # (degree, id)
+    rows = np.repeat(np.arange(n, dtype=np.int64), deg)
+    key = rank_key[adj.astype(np.int64)]
+    # positions within each row after sorting the row by rank
+    order = np.lexsort((key, rows))
+    pos = np.empty_like(order)
+    pos[order] = np.arange(order.shape[0]) - np.repeat(off[:-1].astype(np.int64), deg)
+    up = key > rank_key[rows]                    # arcs y -> x with x above y
+    return int(pos[up].sum()), int(up.sum())
+
+
+def motif_leg(gpm, torch, scale=18, cap=1 << 26, reps=3):
+    """The motif and listing workload: RMAT-`scale` (seed = scale), induced
+    3- and 4-motif counts (local counting) and edge-induced diamond and
+    4-cycle listing into a `cap`-row buffer (total and checksum over every
+    embedding).  Each call timed with HIP events on its stream; the 4-motif
+    call's kernels from the library's timing spans; the 4-cycle kernels
+    against the HBM roofline on the bytes of the wedges they scan."""
+    import graphgen
+    e = graphgen.rmat(scale, seed=scale)
+    g = gpm.Graph.build(e.n, torch.from_numpy(e.u).cuda(), torch.from_numpy(e.v).cuda())
+    stream = torch.cuda.current_stream()
+    gold = {}
+    gp = os.path.join(ROOT, "tests", "golden", "rmat_counts.json")
+    if os.path.exists(gp):
+        with open(gp) as f:
+            gold = json.load(f).get(f"rmat{scale}", {})
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            out = fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return out, a.elapsed_time(b) / reps
+
+    res = {"workload": f"rmat{scale}: induced 3-/4-motif counts, edge-induced diamond and "
+                       f"4-cycle listing (buffer {cap} rows)", "m": g.m}
+    ws3 = torch.empty(gpm.binding.motif_workspace_bytes(g, 3), dtype=torch.uint8, device="cuda")
+    ws4 = torch.empty(gpm.binding.motif_workspace_bytes(g, 4), dtype=torch.uint8, device="cuda")
+    o3 = torch.zeros(3, dtype=torch.int64, device="cuda")
+    o4 = torch.zeros(7, dtype=torch.int64, device="cuda")
+    _, ms3 = timed(lambda: gpm.motif_count(g, 3, ws=ws3, out=o3))
+    _, ms4 = timed(lambda: gpm.motif_count(g, 4, ws=ws4, out=o4))
+    m3 = [int(x) for x in o3.tolist()]
+    m4 = [int(x) for x in o4.tolist()]
+    res["motif3"] = {"counts": m3[:2], "status_word": m3[2], "ms": ms3,
+                     "edges_per_sec": g.m / (ms3 * 1e-3),
+                     "equals_golden": m3[:2] == gold.get("motif3")}
+    res["motif4"] = {"counts": m4[:6], "status_word": m4[6], "ms": ms4,
+                     "edges_per_sec": g.m / (ms4 * 1e-3),
+                     "equals_golden": m4[:6] == gold.get("motif4")}
+    # the 4-motif call's kernels
+    torch.cuda.synchronize()
+    gpm.timing_enable(True)
+    gpm.motif_count(g, 4, ws=ws4, out=o4)
+    torch.cuda.synchronize()
+    gpm.timing_enable(False)
+    phases = {}
+    for name, ms, _ in gpm.timing_read():
+        phases[name] = phases.get(name, 0.0) + ms
+    res["motif4"]["phases_ms"] = {k: round(x, 4) for k, x in phases.items()}
+    off_h = g.csr()[0].cpu().numpy().astype(np.int64)
+    adj_h = g.csr()[1].cpu().numpy()
+    wedges, arcs_up = c4_wedges(off_h, adj_h)
+    c4_ms = sum(x for k, x in phases.items() if k.startswith("k_c4"))
+    b_c4 = 8 * wedges + 12 * arcs_up
+    res["motif4"]["c4_roofline"] = {
+        "kernels": sorted(k for k in phases if k.startswith("k_c4")), "bound": "hbm",
+        "alg_bytes": b_c4, "wedges": wedges, "ms": c4_ms,
+        "achieved": b_c4 / (c4_ms * 1e-3) / 1e9 if c4_ms > 0 else None, "unit": "GB/s",
+        "peak": HBM_PEAK_GBS,
+        "frac": b_c4 / (c4_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if c4_ms > 0 else None,
+        "bytes_model": "8 B per scanned wedge x - y - z (z and its degree) + 12 B per arc "
+                       "y -> x (the middle's row bounds and id)"}
+    for name, lpat in (("diamond", gpm.diamond(gpm.EDGE_INDUCED | gpm.LIST)),
+                       ("4-cycle", gpm.cycle4(gpm.EDGE_INDUCED | gpm.LIST))):
+        wsl = torch.empty(gpm.workspace_bytes(g, lpat), dtype=torch.uint8, device="cuda")
+        (t, w, c, _), ms = timed(lambda: gpm.list_embeddings(g, lpat, cap, ws=wsl))
+        want = gold.get(f"sl_{name}", {})
+        res[f"list_{name}"] = {"total": t, "written": w, "checksum": c, "ms": ms,
+                               "embeddings_per_sec": t / (ms * 1e-3),
+                               "equals_golden": (t, c) == (want.get("total"),
+                                                           want.get("checksum"))}
+        torch.cuda.empty_cache()
+    return res
 
 
 def generic_leg(gpm, torch, scale, reps=3):
@@ -498,7 +719,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=20000)
-    ap.add_argument("--plain-graphs", type=int, default=20000)
+    ap.add_argument("--plain-graphs", type=int, default=2000,
+                    help="graphs timed for the general per-graph call (scaled to all)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--serve-warmup", type=int, default=500)
@@ -513,6 +735,9 @@ def main():
                     help="time only the local-graph ablation leg (for kernel traces) and exit")
     ap.add_argument("--motif-enum-only", action="store_true",
                     help="time only the pattern-oblivious motif leg (for kernel traces) and exit")
+    ap.add_argument("--motif-only", action="store_true",
+                    help="time only the RMAT-18 motif and listing leg (for kernel traces) and exit")
+    ap.add_argument("--no-motif", action="store_true")
     ap.add_argument("--generic-only", action="store_true",
                     help="time only the general-pattern leg (for kernel traces) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -537,6 +762,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.generic_only:
         print(json.dumps({"generic_pattern": generic_leg(gpm, torch, 13)}))
+        return
+    if args.motif_only:
+        print(json.dumps({"motifs_listing": motif_leg(gpm, torch)}))
         return
     if args.core_only:
         print(json.dumps({"core_orientation": core_orient_leg(gpm, torch)}))
@@ -662,6 +890,9 @@ def main():
     }
     if not args.no_batch:
         res["batched_vs_plain"] = batch_leg(gpm, torch, args.batch_graphs, args.plain_graphs, 20)
+    if not args.no_motif:
+        log("motifs and listing (rmat18)")
+        res["motifs_listing"] = motif_leg(gpm, torch)
     if not args.no_generic:
         log("general pattern")
         res["generic_pattern"] = generic_leg(gpm, torch, 13)

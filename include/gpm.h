@@ -310,8 +310,10 @@ gpm_status gpm_motif_count_enum(const gpm_graph *g, int32_t k, void *d_ws, uint6
 /* Batched motif counting over G small graphs held as ONE graph g (their
  * disjoint union, built with gpm_graph_build from the concatenated edge
  * streams with vertex ids shifted per graph): graph i owns vertices
- * d_voff[i] .. d_voff[i+1]-1 (device int32[G+1], ascending, d_voff[0] = 0,
- * d_voff[G] = n).  No edge may join two graphs.  Writes d_counts (device
+ * d_voff[i] .. d_voff[i+1]-1 (device int32[G+1], ascending, within [0, n];
+ * d_voff needs only 4-byte alignment and may point into a longer offset
+ * array, so any run of consecutive graphs of the union, one graph
+ * included, can be mined on its own).  No edge may join two graphs.  Writes d_counts (device
  * uint64[G][k == 3 ? 3 : 7]) row i = gpm_motif_count's output for graph i:
  * the k = 3 or k = 4 induced motif counts (Section 2, motif counting; the
  * local-count identities of Section 5), then a status word: 0, or an OR of

@@ -71,6 +71,19 @@ def test_batch_equals_plain(gpm):
         assert got[i][:6] == gpm.motif_count(gi, 4)
 
 
+def test_batch_sub_ranges(gpm):
+    """d_voff may point into the union's offset array: one graph (G = 1) or
+    a run of graphs mined alone give the full batch's rows for them."""
+    batch = graphgen.rgg_batch(60, seed=21)
+    g, voff = union_graph(gpm, batch)
+    full = gpm.batch_motif_count(g, voff, 4)
+    for i in (0, 7, 59):
+        one = gpm.batch_motif_count(g, voff[i:i + 2], 4)
+        assert torch.equal(one[0], full[i]), i
+    run = gpm.batch_motif_count(g, voff[10:31], 4)
+    assert torch.equal(run, full[10:30])
+
+
 def test_batch_graph_capture_replays(gpm):
     batch = graphgen.rgg_batch(500, seed=99)
     g, voff = union_graph(gpm, batch)
