@@ -51,16 +51,17 @@ INT32_VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 OPS_PER_LOCAL_TRIANGLE = 4
 
 
-# HBM bytes per launch of the dominant kernel from two rocprofv3 counter runs
-# (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a 1 GiB copy
+# Bytes beyond L2 per launch of the dominant kernel from two rocprofv3 counter
+# runs: TCC EA read requests x 128 B (32 B for TCC_EA0_RDREQ_32B) and write
+# requests x 64 B (TCC_EA0_WRREQ_64B) or 32 B
 # (profiles/rmat20_cliques_hbm_traffic.md); valid only while the kernel's
 # source is the one measured.
 MEASURED_TRAFFIC = {
     "kernel": "k_lg5<1024>",
     "source": "paper_2011_03135_amd/csrc/local_graph.hip",
     "source_sha256_prefix": "6d6b79d50bf0a512",
-    "bytes_read": 268315 * 1024 * 2,
-    "bytes_written": 959 * 1024,
+    "bytes_read": 4295646 * 128,
+    "bytes_written": 30690 * 32,
 }
 
 
