@@ -97,10 +97,11 @@ gpm_status gpm_pattern_clique(int32_t k, uint32_t flags, gpm_pattern *out);
 /* Plan chosen for a pattern (Section 4.3 enablement rules: orientation
  * iff the pattern is a clique, |E| = |V|(|V|-1)/2 (Appendix B.2); a
  * matching order with partial orders for other single explicit patterns). */
-/* Cliques of k >= 4 are searched on local graphs (Section 5) for
- * out-degrees up to 1024; GPM_LG=0 in the environment sends them to the
- * depth-first search without local graphs instead (same results; for
- * comparison). */
+/* Cliques of k >= 4 are searched on local graphs (Section 5) from roots of
+ * out-degree up to 1024; roots above that (hubs) are split into one task
+ * per out-arc (Section 4.1) and searched depth first below the arc.
+ * GPM_LG=0 in the environment sends every root to the depth-first search
+ * without local graphs instead (same results; for comparison). */
 #define GPM_PLAN_CLIQUE_DAG     1   /* triangles and k-cliques, k <= 9 */
 #define GPM_PLAN_SL_DIAMOND     2   /* edge-induced diamond listing/counting */
 #define GPM_PLAN_SL_4CYCLE      3   /* edge-induced 4-cycle listing/counting */
@@ -252,8 +253,10 @@ gpm_status gpm_list(const gpm_graph *g, const gpm_pattern *p, void *d_ws, uint64
  * the 5-cliques at u as its 4-cliques, so one build per root serves every
  * size (the per-size calls of gpm_count build it once per size).  Writes
  * d_counts (device uint64[kmax - 2]) = {3-cliques, 4-cliques[, 5-cliques]},
- * the same values as gpm_count per size.  kmax must be 4 or 5; graphs with
- * an out-degree above 1024 give GPM_UNSUPPORTED (count per size instead). */
+ * the same values as gpm_count per size.  kmax must be 4 or 5.  Roots of
+ * out-degree above 1024 (too large for the local graph in LDS) are split
+ * into one task per out-arc and searched depth first below the arc, with
+ * the same counts. */
 gpm_status gpm_clique_counts_workspace_bytes(const gpm_graph *g, int32_t kmax, uint64_t *bytes);
 gpm_status gpm_clique_counts(const gpm_graph *g, int32_t kmax, void *d_ws, uint64_t ws_bytes,
                              uint64_t *d_counts, void *stream);

@@ -83,9 +83,10 @@ __device__ __forceinline__ int64_t last_le_i64(const int64_t *a, int64_t n, int6
 // ------------------------------------------------------------ task build --
 
 // Classes of roots by out-degree.
-enum RootClass : int { RC_NONE = 0, RC_SMALL = 1, RC_MID = 2, RC_BIG = 3 };
+enum RootClass : int { RC_NONE = 0, RC_SMALL = 1, RC_MID = 2, RC_BIG = 3, RC_HUB = 4 };
 
-// Per root: class and pair work W_u = sum over v in N+(u) of d+(v).
+// Per root: class and pair work W_u = sum over v in N+(u) of d+(v).  Roots
+// above big_max are hubs (their arcs become tasks of their own; no work sum).
 __global__ void __launch_bounds__(kBlock) k_root_work(const int32_t *__restrict__ dag_off,
                                                       const int32_t *__restrict__ dag_adj,
                                                       int32_t n, int32_t min_out, int32_t small_max,
@@ -98,6 +99,13 @@ __global__ void __launch_bounds__(kBlock) k_root_work(const int32_t *__restrict_
         const int32_t s = dag_off[r], d = dag_off[r + 1] - s;
         int c = RC_NONE;
         if (d >= min_out && d <= big_max) c = d <= small_max ? RC_SMALL : (d <= mid_max ? RC_MID : RC_BIG);
+        if (d >= min_out && d > big_max) {
+            if (lane == 0) {
+                cls[r] = RC_HUB;
+                work[r] = 0;
+            }
+            continue;
+        }
         int64_t w = 0;
         if (c != RC_NONE)
             for (int32_t i = lane; i < d; i += kWave) {
@@ -542,6 +550,185 @@ __global__ void k_finish_listing(unsigned long long *result, uint64_t cap) {
     if (threadIdx.x == 0 && blockIdx.x == 0) result[1] = result[0] < cap ? result[0] : cap;
 }
 
+// ----------------------------------------------- hub roots (d+ > 1024) ---
+//
+// Roots whose out-degree exceeds the largest class (their N+(u) does not fit
+// the LDS staging of the triangle and local-graph kernels) are split at edge
+// granularity (Section 4.1's task model): every arc u -> v of such a root is
+// a task of its own, taken by one wave from a flattened index space over the
+// hub roots' arcs.  The wave intersects N+(u) and N+(v) (lanes walk the
+// shorter list and binary-search the longer) into its scratch and searches
+// depth first below the result as k_clique_generic does.
+
+enum HubMode : int {
+    HUB_COUNT = 0,   // count K-cliques (and triangles / 4-cliques into res3 / res4)
+    HUB_ARCS = 1,    // K = 3: count triangles and add 1 per triangle to each of its arcs
+    HUB_LIST = 2,    // list K-cliques through the row emitter
+};
+
+// Per hub root r (list hubs[0..nh)), its out-degree: the arc counts whose
+// scan numbers the tasks.
+__global__ void k_hub_arcs(const int32_t *dag_off, const int32_t *hubs, const int32_t *nh_p,
+                           int32_t *cnt) {
+    const int32_t nh = *nh_p;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nh;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = hubs[i];
+        cnt[i] = dag_off[u + 1] - dag_off[u];
+    }
+}
+
+template <int K, int MODE>
+__global__ void __launch_bounds__(kBlock) k_clique_hub(const int32_t *__restrict__ dag_off,
+                                                       const int32_t *__restrict__ dag_adj,
+                                                       const int32_t *__restrict__ hubs,
+                                                       const int64_t *__restrict__ hpre,
+                                                       const int32_t *__restrict__ nh_p,
+                                                       int32_t maxout, int32_t *scratch,
+                                                       unsigned long long *res,
+                                                       unsigned long long *res3,
+                                                       unsigned long long *res4, uint32_t *te,
+                                                       RowEmitter em) {
+    static_assert(K >= 3 && K <= kGenMaxK, "clique size");
+    static_assert(MODE != HUB_ARCS || K == 3, "arc counts are triangle counts");
+    const int lane = lane_id();
+    const int64_t wave_gid = (int64_t)blockIdx.x * kWPB + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWPB;
+    int32_t *mine = scratch + wave_gid * (int64_t)(kGenMaxK - 2) * maxout;
+    const int32_t nh = *nh_p;
+    const int64_t total = hpre[nh];
+    // fused counts need every 4-clique below an arc, so only K's own
+    // pruning applies when no 4-cliques are asked for
+    const int32_t need2 = (res4 && K > 4) ? 2 : K - 2;
+    uint64_t acc = 0, acc3 = 0, acc4 = 0;
+    for (int64_t t = wave_gid; t < total; t += nwaves) {
+        const int32_t r = (int32_t)last_le_i64(hpre, (int64_t)nh + 1, t);
+        const int32_t u = hubs[r];
+        const int32_t s = dag_off[u], d = dag_off[u + 1] - s;
+        const int32_t e = s + (int32_t)(t - hpre[r]);
+        const int32_t v = dag_adj[e];
+        const int32_t vs = dag_off[v], vd = dag_off[v + 1] - vs;
+        if constexpr (MODE == HUB_ARCS || (K == 3 && MODE == HUB_LIST)) {
+            // every common out-neighbour w closes the triangle (u, v, w)
+            const bool u_short = d <= vd;
+            const int32_t *a = u_short ? dag_adj + s : dag_adj + vs;
+            const int32_t *b = u_short ? dag_adj + vs : dag_adj + s;
+            const int32_t na = u_short ? d : vd, nb = u_short ? vd : d;
+            uint32_t c = 0;
+            for (int32_t i0 = 0; i0 < na; i0 += kWave) {
+                const int32_t i = i0 + lane;
+                bool hit = false;
+                int32_t x = 0, p = 0;
+                if (i < na) {
+                    x = a[i];
+                    p = lower_bound_i32(b, nb, x);
+                    hit = p < nb && b[p] == x;
+                }
+                if (hit) {
+                    if constexpr (MODE == HUB_ARCS) {
+                        // arcs u -> w and v -> w
+                        atomicAdd(&te[(u_short ? s + i : s + p)], 1u);
+                        atomicAdd(&te[(u_short ? vs + p : vs + i)], 1u);
+                    } else {
+                        const int32_t tri[3] = {u, v, x};
+                        emit_vertices<3>(em, tri);
+                    }
+                }
+                c += (uint32_t)__popcll(__ballot(hit));
+            }
+            if (lane == 0) {
+                acc += c;
+                if (MODE == HUB_ARCS && c) atomicAdd(&te[e], c);   // arc u -> v
+            }
+            continue;
+        } else {
+            if constexpr (K == 3) {
+                const int32_t c = wave_intersect<false>(dag_adj + s, d, dag_adj + vs, vd, nullptr);
+                if (lane == 0) acc += (uint64_t)c;
+                continue;
+            } else {
+                // level 1: C = N+(u) ∩ N+(v), the triangles on the arc
+                const int32_t c2 = wave_intersect<true>(dag_adj + s, d, dag_adj + vs, vd, mine);
+                wave_sync();
+                if (res3 && lane == 0) acc3 += (uint64_t)c2;
+                if (c2 < need2) continue;
+                const int32_t *cand[kGenMaxK];
+                int32_t csz[kGenMaxK], it[kGenMaxK], pv[kGenMaxK];
+                pv[0] = u;
+                pv[1] = v;
+                cand[2] = mine;
+                csz[2] = c2;
+                it[2] = 0;
+                constexpr int last = K - 2;   // level whose intersection is counted or listed
+                int l = 2;
+                while (l >= 2) {
+                    if (it[l] >= csz[l]) {
+                        l--;
+                        if (l >= 2) it[l]++;
+                        continue;
+                    }
+                    const int32_t w = cand[l][it[l]];
+                    pv[l] = w;
+                    const int32_t ws = dag_off[w], wd = dag_off[w + 1] - ws;
+                    if (l == last) {
+                        if constexpr (MODE == HUB_COUNT) {
+                            const int32_t c = wave_intersect<false>(cand[l], csz[l], dag_adj + ws,
+                                                                    wd, nullptr);
+                            if (lane == 0) acc += (uint64_t)c;
+                        } else {
+                            const int32_t *a = cand[l], *b = dag_adj + ws;
+                            const int32_t na = csz[l], nb = wd;
+                            for (int32_t i0 = 0; i0 < na; i0 += kWave) {
+                                const int32_t i = i0 + lane;
+                                if (i < na) {
+                                    const int32_t x = a[i];
+                                    const int32_t p = lower_bound_i32(b, nb, x);
+                                    if (p < nb && b[p] == x) {
+                                        int32_t q[K];
+#pragma unroll
+                                        for (int z = 0; z < K - 1; z++) q[z] = pv[z];
+                                        q[K - 1] = x;
+                                        emit_vertices<K>(em, q);
+                                    }
+                                }
+                            }
+                        }
+                        it[l]++;
+                    } else {
+                        int32_t *out = mine + (int64_t)(l - 1) * maxout;
+                        const int32_t c = wave_intersect<true>(cand[l], csz[l], dag_adj + ws, wd,
+                                                               out);
+                        wave_sync();
+                        if (res4 && l == 2 && lane == 0) acc4 += (uint64_t)c;
+                        if (c >= K - 1 - l) {
+                            l++;
+                            cand[l] = out;
+                            csz[l] = c;
+                            it[l] = 0;
+                        } else {
+                            it[l]++;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (MODE == HUB_LIST) {
+        row_emitter_flush(em, res);
+        return;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0 && acc) atomicAdd(res, (unsigned long long)acc);
+    if (res3) {
+        acc3 = wave_sum(acc3);
+        if (lane == 0 && acc3) atomicAdd(res3, (unsigned long long)acc3);
+    }
+    if (res4) {
+        acc4 = wave_sum(acc4);
+        if (lane == 0 && acc4) atomicAdd(res4, (unsigned long long)acc4);
+    }
+}
+
 // ------------------------------------------------------------ host side --
 
 // Triangle classes by out-degree: (1, 64] one wave per block, (64, 256] and
@@ -556,9 +743,9 @@ struct CliqueWs {
     unsigned long long *result;   // [8]: count, -, pairs of each triangle class
     uint32_t *ctl;                // [32]: cursors, per-class {nact, nchunks}, class counts
     int32_t *work, *cls, *flag, *pos;
-    int32_t *list_s, *list_m, *list_b;
+    int32_t *list_s, *list_m, *list_b, *list_h;
     int32_t *lwork;               // compacted work of one class (reused)
-    int64_t *wpre_s, *wpre_m, *wpre_b;
+    int64_t *wpre_s, *wpre_m, *wpre_b, *wpre_h;
     int32_t *first_s, *first_m, *first_b;
     int64_t *scan_tmp;
     void *lg;                     // local-graph workspace (k = 4, 5)
@@ -574,15 +761,26 @@ int64_t chunk_bound(const gpm_graph *g) {
     return w / kTauMin + 2;
 }
 
-// The generic DFS serves out-degrees above 1024 and listings of k >= 6;
-// everything else runs on the triangle and local-graph kernels.  GPM_LG=0 in
-// the environment sends k >= 4 to the generic DFS as well (the search
-// without local graphs, for comparison).
-bool uses_generic(const gpm_graph *g, int32_t k, bool list) {
+// The generic DFS (a wave per root) serves listings of k >= 6; every other
+// count and listing runs on the triangle and local-graph kernels, with roots
+// of out-degree above 1024 split per arc (k_clique_hub).  GPM_LG=0 in the
+// environment sends every root of k >= 4 to the per-arc depth-first search
+// instead: the search without local graphs, equally load-balanced, for
+// comparison.
+bool lg_disabled(int32_t k) {
     const char *env = getenv("GPM_LG");
-    const bool no_lg = k >= 4 && env && env[0] == '0';
-    return g->max_out_degree > kTcMax || (list && k > 5) || no_lg;
+    return k >= 4 && env && env[0] == '0';
 }
+
+bool uses_generic(const gpm_graph *g, int32_t k, bool list) {
+    (void)g;
+    return list && k > 5;
+}
+
+// Roots above the largest class go to k_clique_hub.
+bool has_hubs(const gpm_graph *g) { return g->max_out_degree > kTcMax; }
+
+bool uses_hub_kernel(const gpm_graph *g, int32_t k) { return has_hubs(g) || lg_disabled(k); }
 
 CliqueWs clique_layout(const gpm_graph *g, int32_t k, bool list, void *base) {
     CliqueWs W{};
@@ -597,10 +795,12 @@ CliqueWs clique_layout(const gpm_graph *g, int32_t k, bool list, void *base) {
     W.list_s = c.take<int32_t>(n1);
     W.list_m = c.take<int32_t>(n1);
     W.list_b = c.take<int32_t>(n1);
+    W.list_h = c.take<int32_t>(n1);
     W.lwork = c.take<int32_t>(n1);
     W.wpre_s = c.take<int64_t>(n1);
     W.wpre_m = c.take<int64_t>(n1);
     W.wpre_b = c.take<int64_t>(n1);
+    W.wpre_h = c.take<int64_t>(n1);
     W.scan_tmp = c.take<int64_t>(scan_tmp_words(n1));
     bool generic = uses_generic(g, k, list);
     if (!generic && k == 3) {
@@ -608,11 +808,11 @@ CliqueWs clique_layout(const gpm_graph *g, int32_t k, bool list, void *base) {
         W.first_m = c.take<int32_t>((uint64_t)chunk_bound(g));
         W.first_b = c.take<int32_t>((uint64_t)chunk_bound(g));
     }
-    if (!generic && k >= 4) {
+    if (!generic && k >= 4 && !lg_disabled(k)) {
         lg_workspace_bytes(g, k, &W.lg_bytes);
         W.lg = c.take<char>(W.lg_bytes);
     }
-    if (generic) {
+    if (generic || uses_hub_kernel(g, k)) {
         W.gen_waves = persistent_blocks(kWPB, 8) * kWPB;
         W.gen_scratch = c.take<int32_t>((uint64_t)W.gen_waves * (kGenMaxK - 2) *
                                         (uint64_t)std::max(1, g->max_out_degree));
@@ -648,6 +848,39 @@ hipError_t build_class(const gpm_graph *g, CliqueWs &W, int32_t want, int32_t *l
     return exclusive_scan_i64(W.lwork, wpre, (uint64_t)n, W.scan_tmp, st);
 }
 
+// Cliques (or, K = 3 with HUB_ARCS, per-arc triangle counts) rooted at the
+// hub roots, the roots above the largest class; W.cls must hold the classes
+// from k_root_work.  Nothing is launched on graphs without hubs.
+template <int K, int MODE>
+gpm_status hub_launch(const gpm_graph *g, CliqueWs &W, unsigned long long *res,
+                      unsigned long long *res3, unsigned long long *res4, uint32_t *te,
+                      const RowEmitter &em, hipStream_t st, bool all_roots = false) {
+    if (!has_hubs(g) && !all_roots) return GPM_OK;
+    const int32_t n = g->n;
+    int32_t *cnt_h = (int32_t *)(W.ctl + 15);
+    GPM_HIP(build_class(g, W, RC_HUB, W.list_h, nullptr, st));
+    GPM_HIP(hipMemcpyAsync(cnt_h, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
+    GPM_HIP(fill_u32(W.lwork, 0, (uint64_t)n + 1, st));
+    hipLaunchKernelGGL(k_hub_arcs, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, g->dag_off,
+                       W.list_h, cnt_h, W.lwork);
+    GPM_LAUNCH_CHECK("k_hub_arcs");
+    GPM_HIP(exclusive_scan_i64(W.lwork, W.wpre_h, (uint64_t)n, W.scan_tmp, st));
+    {
+        static const char *const kNames[] = {"k_clique_hub<3>", "k_clique_hub<4>",
+                                             "k_clique_hub<5>", "k_clique_hub<6>",
+                                             "k_clique_hub<7>", "k_clique_hub<8>",
+                                             "k_clique_hub<9>"};
+        Span sp(kNames[K - 3], st);
+        hipLaunchKernelGGL((k_clique_hub<K, MODE>), dim3((unsigned)(W.gen_waves / kWPB)),
+                           dim3(kBlock), 0, st, g->dag_off, g->dag_adj, W.list_h,
+                           (const int64_t *)W.wpre_h, (const int32_t *)cnt_h,
+                           std::max(1, g->max_out_degree), W.gen_scratch, res, res3, res4, te,
+                           em);
+    }
+    GPM_LAUNCH_CHECK("k_clique_hub");
+    return GPM_OK;
+}
+
 template <int K>
 gpm_status launch_local(const gpm_graph *g, CliqueWs &W, const int32_t *cnt_s,
                         const int32_t *cnt_m, const int32_t *cnt_b, unsigned long long *res,
@@ -671,7 +904,10 @@ gpm_status launch_local(const gpm_graph *g, CliqueWs &W, const int32_t *cnt_s,
                                res3, res4, RowEmitter{});
     }
     GPM_LAUNCH_CHECK("k_clique_wave");
-    return GPM_OK;
+    if constexpr (K <= 5) {
+        if (em) return hub_launch<K, HUB_LIST>(g, W, res, nullptr, nullptr, nullptr, *em, st);
+    }
+    return hub_launch<K, HUB_COUNT>(g, W, res, res3, res4, nullptr, RowEmitter{}, st);
 }
 
 }  // namespace
@@ -728,17 +964,18 @@ static gpm_status tc_launch(const gpm_graph *g, CliqueWs &W, unsigned long long 
                                                      : (arcs ? "k_tc_block<256,arcs>" : "k_tc_block<256>"),
                                      res, te, em, st);
     if (rc) return rc;
-    return tc_class<kTcSmall, 64, MODE>(g, W, RC_SMALL, W.list_s, W.wpre_s, W.first_s, 0,
-                                        kTauSmall, 32,
-                                        MODE == TC_LIST ? "k_tc_block<64,list>"
-                                                        : (arcs ? "k_tc_block<64,arcs>" : "k_tc_block<64>"),
-                                        res, te, em, st);
+    rc = tc_class<kTcSmall, 64, MODE>(g, W, RC_SMALL, W.list_s, W.wpre_s, W.first_s, 0,
+                                      kTauSmall, 32,
+                                      MODE == TC_LIST ? "k_tc_block<64,list>"
+                                                      : (arcs ? "k_tc_block<64,arcs>" : "k_tc_block<64>"),
+                                      res, te, em, st);
+    if (rc) return rc;
+    constexpr int HM = MODE == TC_LIST ? HUB_LIST : (MODE == TC_ARCS ? HUB_ARCS : HUB_COUNT);
+    return hub_launch<3, HM>(g, W, res, nullptr, nullptr, te, em, st);
 }
 
 gpm_status triangle_arc_counts(const gpm_graph *g, void *ws, uint64_t ws_bytes, uint32_t *te,
                                unsigned long long *tri, hipStream_t st) {
-    if (g->max_out_degree > kTcMax)
-        return fail(GPM_UNSUPPORTED, "per-edge triangle counts need every out-degree <= 1024");
     CliqueWs W = clique_layout(g, 3, false, ws);
     if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
     return tc_launch<TC_ARCS>(g, W, tri, te, st);
@@ -777,6 +1014,23 @@ gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64
     } else if (k == 3) {
         gpm_status rc = list ? tc_launch<TC_LIST>(g, W, res, nullptr, st, em)
                              : tc_launch<TC_COUNT>(g, W, res, nullptr, st);
+        if (rc) return rc;
+    } else if (lg_disabled(k)) {
+        // every root with out-degree >= k - 1 is a hub: one task per out-arc
+        hipLaunchKernelGGL(k_root_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st,
+                           g->dag_off, g->dag_adj, n, k - 1, 0, 0, 0, W.work, W.cls);
+        GPM_LAUNCH_CHECK("k_root_work");
+        gpm_status rc;
+        switch (k) {
+        case 4: rc = list ? hub_launch<4, HUB_LIST>(g, W, res, nullptr, nullptr, nullptr, em, st, true)
+                          : hub_launch<4, HUB_COUNT>(g, W, res, nullptr, nullptr, nullptr, em, st, true); break;
+        case 5: rc = list ? hub_launch<5, HUB_LIST>(g, W, res, nullptr, nullptr, nullptr, em, st, true)
+                          : hub_launch<5, HUB_COUNT>(g, W, res, nullptr, nullptr, nullptr, em, st, true); break;
+        case 6: rc = hub_launch<6, HUB_COUNT>(g, W, res, nullptr, nullptr, nullptr, em, st, true); break;
+        case 7: rc = hub_launch<7, HUB_COUNT>(g, W, res, nullptr, nullptr, nullptr, em, st, true); break;
+        case 8: rc = hub_launch<8, HUB_COUNT>(g, W, res, nullptr, nullptr, nullptr, em, st, true); break;
+        default: rc = hub_launch<9, HUB_COUNT>(g, W, res, nullptr, nullptr, nullptr, em, st, true); break;
+        }
         if (rc) return rc;
     } else {
         hipLaunchKernelGGL(k_root_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st,
@@ -824,29 +1078,40 @@ gpm_status clique_multi_workspace_bytes(const gpm_graph *g, int32_t kmax, uint64
 gpm_status clique_multi_run(const gpm_graph *g, int32_t kmax, void *ws, uint64_t ws_bytes,
                             unsigned long long *d_counts, hipStream_t st) {
     if (kmax < 4 || kmax > 5) return fail(GPM_UNSUPPORTED, "kmax must be 4 or 5");
-    if (g->max_out_degree > kTcMax)
-        return fail(GPM_UNSUPPORTED, "fused clique counts need every out-degree <= 1024");
     CliqueWs W = clique_layout(g, kmax, false, ws);
     if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
     const int32_t n = g->n;
     unsigned long long *res = W.result;   // [0] k = kmax, [1] triangles, [2] 4-cliques (kmax 5)
     GPM_HIP(fill_u32(res, 0, 16, st));
     GPM_HIP(fill_u32(W.ctl, 0, 32, st));
-    hipLaunchKernelGGL(k_root_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st, g->dag_off,
-                       g->dag_adj, n, 2, 64, kMidMaxD, kTcMax, W.work, W.cls);
-    GPM_LAUNCH_CHECK("k_root_work");
-    int32_t *cnt_s = (int32_t *)(W.ctl + 12), *cnt_m = (int32_t *)(W.ctl + 13),
-            *cnt_b = (int32_t *)(W.ctl + 14);
-    GPM_HIP(build_class(g, W, RC_BIG, W.list_b, nullptr, st));
-    GPM_HIP(hipMemcpyAsync(cnt_b, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
-    GPM_HIP(build_class(g, W, RC_MID, W.list_m, nullptr, st));
-    GPM_HIP(hipMemcpyAsync(cnt_m, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
-    GPM_HIP(build_class(g, W, RC_SMALL, W.list_s, nullptr, st));
-    GPM_HIP(hipMemcpyAsync(cnt_s, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
-    gpm_status rc = kmax == 4
-                        ? launch_local<4>(g, W, cnt_s, cnt_m, cnt_b, res, res + 1, nullptr, st)
-                        : launch_local<5>(g, W, cnt_s, cnt_m, cnt_b, res, res + 1, res + 2, st);
-    if (rc) return rc;
+    if (lg_disabled(kmax)) {
+        // without local graphs: every root of out-degree >= 2 per arc
+        hipLaunchKernelGGL(k_root_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st,
+                           g->dag_off, g->dag_adj, n, 2, 0, 0, 0, W.work, W.cls);
+        GPM_LAUNCH_CHECK("k_root_work");
+        gpm_status rc =
+            kmax == 4 ? hub_launch<4, HUB_COUNT>(g, W, res, res + 1, nullptr, nullptr,
+                                                 RowEmitter{}, st, true)
+                      : hub_launch<5, HUB_COUNT>(g, W, res, res + 1, res + 2, nullptr,
+                                                 RowEmitter{}, st, true);
+        if (rc) return rc;
+    } else {
+        hipLaunchKernelGGL(k_root_work, dim3(grid_for(n, kWPB, 16)), dim3(kBlock), 0, st, g->dag_off,
+                           g->dag_adj, n, 2, 64, kMidMaxD, kTcMax, W.work, W.cls);
+        GPM_LAUNCH_CHECK("k_root_work");
+        int32_t *cnt_s = (int32_t *)(W.ctl + 12), *cnt_m = (int32_t *)(W.ctl + 13),
+                *cnt_b = (int32_t *)(W.ctl + 14);
+        GPM_HIP(build_class(g, W, RC_BIG, W.list_b, nullptr, st));
+        GPM_HIP(hipMemcpyAsync(cnt_b, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
+        GPM_HIP(build_class(g, W, RC_MID, W.list_m, nullptr, st));
+        GPM_HIP(hipMemcpyAsync(cnt_m, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
+        GPM_HIP(build_class(g, W, RC_SMALL, W.list_s, nullptr, st));
+        GPM_HIP(hipMemcpyAsync(cnt_s, W.pos + n, 4, hipMemcpyDeviceToDevice, st));
+        gpm_status rc = kmax == 4
+                            ? launch_local<4>(g, W, cnt_s, cnt_m, cnt_b, res, res + 1, nullptr, st)
+                            : launch_local<5>(g, W, cnt_s, cnt_m, cnt_b, res, res + 1, res + 2, st);
+        if (rc) return rc;
+    }
     // d_counts = {triangles, 4-cliques[, 5-cliques]}
     GPM_HIP(hipMemcpyAsync(d_counts, res + 1, 8, hipMemcpyDeviceToDevice, st));
     if (kmax == 4) {

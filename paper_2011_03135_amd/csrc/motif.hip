@@ -189,16 +189,12 @@ unsigned grid_for(int64_t items, int per_block, int cap_per_cu) {
 }  // namespace
 
 gpm_status motif_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes) {
-    if (k == 4 && g->max_out_degree > 1024)
-        return fail(GPM_UNSUPPORTED, "4-motif counting needs every out-degree <= 1024");
     *bytes = motif_layout(g, k, nullptr).bytes;
     return GPM_OK;
 }
 
 gpm_status motif_run(const gpm_graph *g, int32_t k, void *ws, uint64_t ws_bytes,
                      unsigned long long *d_counts, hipStream_t st) {
-    if (k == 4 && g->max_out_degree > 1024)
-        return fail(GPM_UNSUPPORTED, "4-motif counting needs every out-degree <= 1024");
     MotifWs W = motif_layout(g, k, ws);
     if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
     const int32_t n = g->n;

@@ -331,8 +331,6 @@ C4CountWs c4count_layout(const gpm_graph *g, bool list, void *base) {
 }  // namespace
 
 gpm_status sl_workspace_bytes(const gpm_graph *g, int32_t plan, bool list, uint64_t *bytes) {
-    if (g->max_out_degree > 1024)
-        return fail(GPM_UNSUPPORTED, "subgraph listing needs every out-degree <= 1024");
     if (plan == GPM_PLAN_SL_DIAMOND) {
         *bytes = diamond_layout(g, list, nullptr).bytes;
         return GPM_OK;
@@ -346,8 +344,6 @@ gpm_status sl_workspace_bytes(const gpm_graph *g, int32_t plan, bool list, uint6
 gpm_status sl_run(const gpm_graph *g, int32_t plan, bool list, void *ws, uint64_t ws_bytes,
                   unsigned long long *d_count, int32_t *d_buf, uint64_t cap,
                   unsigned long long *d_result, hipStream_t st) {
-    if (g->max_out_degree > 1024)
-        return fail(GPM_UNSUPPORTED, "subgraph listing needs every out-degree <= 1024");
     if (plan == GPM_PLAN_SL_DIAMOND)
         return diamond_run(g, list, ws, ws_bytes, d_count, d_buf, cap, d_result, st);
     C4CountWs W = c4count_layout(g, list, ws);

@@ -383,11 +383,14 @@ def test_without_local_graphs(gpm, case, monkeypatch):
     want = {k: gpm.count(g, gpm.clique(k)) for k in (4, 5)}
     lists = {k: gpm.list_embeddings(g, gpm.clique(k, gpm.VERTEX_INDUCED | gpm.LIST), 1 << 16)[:3]
              for k in (4, 5)}
+    want3 = gpm.count(g, gpm.clique(3))
     monkeypatch.setenv("GPM_LG", "0")
     for k in (4, 5):
         assert gpm.count(g, gpm.clique(k)) == want[k], k
         got = gpm.list_embeddings(g, gpm.clique(k, gpm.VERTEX_INDUCED | gpm.LIST), 1 << 16)
         assert got[0] == lists[k][0] and got[2] == lists[k][2], k
+    assert gpm.clique_counts(g, 4) == [want3, want[4]]
+    assert gpm.clique_counts(g, 5) == [want3, want[4], want[5]]
 
 
 def test_nine_cliques(gpm, monkeypatch):
