@@ -512,9 +512,17 @@ def generic_leg(gpm, torch, scale, reps=3):
             got_off, ms_off = timed(lambda: gpm.count(g, p))
         finally:
             del os.environ["GPM_MNC"]
+        # and without degree filtering
+        os.environ["GPM_DF"] = "0"
+        try:
+            got_nodf, ms_nodf = timed(lambda: gpm.count(g, p))
+        finally:
+            del os.environ["GPM_DF"]
         res[name] = {"count": got, "equals_motif_count": got == mc[names.index(name)],
                      "ms": ms, "matches_per_sec": got / (ms * 1e-3),
                      "ms_without_connectivity_map": ms_off, "same_without_map": got == got_off,
+                     "ms_without_degree_filter": ms_nodf,
+                     "same_without_degree_filter": got == got_nodf,
                      "lc_route_speedup": ms / lc_ms}
     # listing the 4-cycles: every embedding hashed into the checksum, the
     # first 2^20 written out

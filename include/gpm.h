@@ -116,6 +116,22 @@ gpm_status gpm_pattern_clique(int32_t k, uint32_t flags, gpm_pattern *out);
  * search in the matched vertices' rows; GPM_MNC=0 in the environment forces
  * the latter.  Both give the same counts. */
 #define GPM_PLAN_GENERIC        4
+/* How the general plan (GPM_PLAN_GENERIC) searches pattern p.  order[s]
+ * (k entries) is the pattern vertex matched at step s: the greedy of
+ * Appendix B.3 (each step adjacent to an earlier one; the sub-pattern with
+ * more internal partial orders first, then the denser one; then the higher
+ * degree, then the lower id; the first two steps an edge carrying a
+ * partial order when one exists).  less[x] (k entries) is the set of
+ * pattern vertices y (bit y) with f(x) < f(y) required of every match f:
+ * the symmetry-breaking partial orders of Appendix B.1, from the stabiliser
+ * chain of the automorphism group with vertices taken by degree (highest
+ * first, then lowest id), so that each embedding is matched exactly once.
+ * Every step also skips data vertices of smaller degree than its pattern
+ * vertex (degree filtering, Section 4.3; GPM_DF=0 in the environment turns
+ * it off, with the same results).  Host only.  GPM_UNSUPPORTED for patterns
+ * on another plan. */
+gpm_status gpm_pattern_matching_order(const gpm_pattern *p, int32_t *order, uint32_t *less);
+
 /* Returns the plan for (graph-independent) pattern p, or GPM_UNSUPPORTED.
  * A struct built by the caller is checked as gpm_pattern_from_edges would
  * check it (sizes, edges, connectivity, and flags: exactly one of

@@ -26,6 +26,7 @@ from .binding import (  # noqa: F401
     cycle4,
     library_path,
     list_embeddings,
+    matching_order,
     load,
     motif_count,
     motif_classes,

@@ -66,6 +66,7 @@ def load():
         "gpm_pattern_from_edges": ([i32, i32, P, u32, P], i32),
         "gpm_pattern_clique": ([i32, u32, P], i32),
         "gpm_pattern_plan": ([P, P], i32),
+        "gpm_pattern_matching_order": ([P, P, P], i32),
         "gpm_graph_build_bytes": ([i32, i64, P, P], i32),
         "gpm_graph_build": ([i32, P, P, i64, P, u64, P, u64, P, P], i32),
         "gpm_graph_from_csr_bytes": ([i32, i64, P, P], i32),
@@ -142,6 +143,17 @@ def pattern(k, edges, flags):
     p = Pattern()
     _check(lib.gpm_pattern_from_edges(int(k), len(edges), flat, int(flags), ctypes.byref(p)))
     return p
+
+
+def matching_order(p):
+    """gpm_pattern_matching_order -> (order, less): the general plan's
+    matching order (pattern vertex per step) and its partial orders, less[x]
+    = the set of pattern vertices y with f(x) < f(y) required."""
+    order = (ctypes.c_int32 * 9)()
+    less = (ctypes.c_uint32 * 9)()
+    _check(load().gpm_pattern_matching_order(ctypes.byref(p), order, less))
+    return ([order[i] for i in range(p.k)],
+            [{y for y in range(p.k) if (less[x] >> y) & 1} for x in range(p.k)])
 
 
 def clique(k, flags=VERTEX_INDUCED):

@@ -30,6 +30,7 @@ gpm_status motif_run(const gpm_graph *g, int32_t k, void *ws, uint64_t ws_bytes,
                      unsigned long long *d_counts, hipStream_t st);
 gpm_status sl_workspace_bytes(const gpm_graph *g, int32_t plan, bool list, uint64_t *bytes);
 bool generic_pattern_ok(const gpm_pattern *p);
+gpm_status generic_describe(const gpm_pattern *p, int32_t *order, uint32_t *less);
 uint64_t generic_workspace_bytes(const gpm_graph *g);
 gpm_status generic_list(const gpm_graph *g, const gpm_pattern *p, void *ws, uint64_t ws_bytes,
                         int32_t *buf, uint64_t cap, unsigned long long *result, hipStream_t st);
@@ -238,6 +239,16 @@ gpm_status gpm_pattern_plan(const gpm_pattern *p, int32_t *plan) {
     if (!gpm::generic_pattern_ok(p)) return GPM_UNSUPPORTED;   // error text set by the check
     *plan = GPM_PLAN_GENERIC;
     return GPM_OK;
+}
+
+gpm_status gpm_pattern_matching_order(const gpm_pattern *p, int32_t *order, uint32_t *less) {
+    if (!p || !order || !less) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    int32_t plan;
+    gpm_status rc = gpm_pattern_plan(p, &plan);
+    if (rc) return rc;
+    if (plan != GPM_PLAN_GENERIC)
+        return fail(GPM_UNSUPPORTED, "the pattern is not on the general plan");
+    return gpm::generic_describe(p, order, less);
 }
 
 gpm_status gpm_graph_build_bytes(int32_t n, int64_t n_input_edges, uint64_t *graph_bytes,

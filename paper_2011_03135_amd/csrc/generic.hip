@@ -47,6 +47,7 @@ struct GenPlan {
     uint32_t above[kGenMaxK];      // earlier steps t with f(s) > f(t) required
     uint32_t below[kGenMaxK];      // earlier steps t with f(s) < f(t) required
     int32_t vert[kGenMaxK];        // pattern vertex matched at step s (listing rows)
+    int32_t dmin[kGenMaxK];        // degree filter: smallest data degree step s accepts
     int32_t ne;                    // pattern edges, as pairs of steps (listing keys)
     int32_t estep[kGenMaxE][2];
 };
@@ -197,6 +198,10 @@ __global__ void k_gen_chunks(const int32_t *__restrict__ off, const int32_t *__r
         bool ok = true;
         if ((P.above[1] & 1u) && v1 < r) ok = false;
         if ((P.below[1] & 1u) && v1 > r) ok = false;
+        // degree filter (Section 4.3): a data vertex below its pattern
+        // vertex's degree cannot take it
+        if (ok && P.dmin[0] > 1 && off[r + 1] - off[r] < P.dmin[0]) ok = false;
+        if (ok && P.dmin[1] > 1 && off[v1 + 1] - off[v1] < P.dmin[1]) ok = false;
         int32_t c = 0;
         if (ok) c = P.k == 2 ? 1 : (gen_step2_len(P, off, adj, r, v1) + kWave - 1) / kWave;
         chunks[a] = c;
@@ -308,6 +313,7 @@ __global__ void __launch_bounds__(kGenNT) k_generic(const int32_t *__restrict__ 
                 const int32_t i = p + lane;
                 const int32_t v = i < e ? adj[i] : -1;
                 bool ok = i < e;
+                if (ok && P.dmin[s] > 1) ok = off[v + 1] - off[v] >= P.dmin[s];
                 const int32_t piv = S.pivot[s];
                 if (MNC) {
                     for (int t = 0; t < s; t++) ok = ok && v != S.m[t];
@@ -413,7 +419,8 @@ bool connected(int k, const bool (&a)[8][8]) {
     return seen == (1 << k) - 1;
 }
 
-gpm_status make_plan(const gpm_pattern *p, GenPlan &P) {
+gpm_status make_plan(const gpm_pattern *p, GenPlan &P, int32_t *order_out = nullptr,
+                     uint32_t *less_out = nullptr) {
     const int k = p->k;
     if (k < 2 || k > kGenMaxK)
         return fail(GPM_UNSUPPORTED, "general patterns: 2 to 6 vertices");
@@ -430,26 +437,6 @@ gpm_status make_plan(const gpm_pattern *p, GenPlan &P) {
     for (int x = 0; x < k; x++)
         for (int y = 0; y < k; y++) deg[x] += a[x][y];
     if (!connected(k, a)) return fail(GPM_UNSUPPORTED, "the pattern is not connected");
-    // matching order: highest degree first, then most edges back to the
-    // placed vertices (ties: higher degree, then lower id)
-    int order[8], pos[8];
-    bool placed[8] = {};
-    for (int s = 0; s < k; s++) {
-        int best = -1, best_back = -1;
-        for (int x = 0; x < k; x++) {
-            if (placed[x]) continue;
-            int back = 0;
-            for (int t = 0; t < s; t++) back += a[x][order[t]];
-            if (s > 0 && back == 0) continue;
-            if (back > best_back || (back == best_back && deg[x] > deg[best])) {
-                best = x;
-                best_back = back;
-            }
-        }
-        order[s] = best;
-        pos[best] = s;
-        placed[best] = true;
-    }
     // automorphisms, as maps on pattern vertices
     std::vector<std::vector<int>> group;
     std::vector<int> perm(k);
@@ -464,15 +451,20 @@ gpm_status make_plan(const gpm_pattern *p, GenPlan &P) {
                 }
         if (ok) group.push_back(perm);
     } while (std::next_permutation(perm.begin(), perm.end()));
-    P = GenPlan{};
-    P.k = k;
-    P.induced = (p->flags & GPM_VERTEX_INDUCED) != 0;
-    // partial orders from the stabiliser chain, taken in matching order
+    // symmetry-breaking partial orders (Appendix B.1) from the stabiliser
+    // chain, vertices taken by degree (highest first, then lowest id): while
+    // the group is not trivial, the first vertex v with a non-trivial orbit
+    // gets f(v) < f(u) for every other u of its orbit, and the group shrinks
+    // to v's stabiliser.  less[x] = the vertices y with f(x) < f(y).
+    int byd[8];
+    for (int i = 0; i < k; i++) byd[i] = i;
+    std::stable_sort(byd, byd + k, [&](int x, int y) { return deg[x] > deg[y]; });
+    uint32_t less[8] = {};
     while (group.size() > 1) {
         int v = -1;
         std::vector<int> orbit;
-        for (int s = 0; s < k && v < 0; s++) {
-            const int x = order[s];
+        for (int i = 0; i < k && v < 0; i++) {
+            const int x = byd[i];
             std::vector<int> o;
             for (auto &g : group)
                 if (std::find(o.begin(), o.end(), g[x]) == o.end()) o.push_back(g[x]);
@@ -481,23 +473,91 @@ gpm_status make_plan(const gpm_pattern *p, GenPlan &P) {
                 orbit = o;
             }
         }
-        for (int u : orbit) {
-            if (u == v) continue;
-            // f(v) < f(u), checked at the later of the two steps
-            if (pos[u] > pos[v]) P.above[pos[u]] |= 1u << pos[v];
-            else P.below[pos[v]] |= 1u << pos[u];
-        }
+        for (int u : orbit)
+            if (u != v) less[v] |= 1u << u;
         std::vector<std::vector<int>> stab;
         for (auto &g : group)
             if (g[v] == v) stab.push_back(g);
         group.swap(stab);
     }
+    // matching order (Appendix B.3, the greedy it takes from DualSim): every
+    // step after the first adjacent to an earlier one; at each step the
+    // sub-pattern of the placed vertices plus the candidate with (1) more
+    // internal partial orders, then (2) more edges; then (ours) the higher
+    // degree, then the lower id.  The first two steps are chosen together:
+    // an edge carrying a partial order before any other.
+    auto po_between = [&](int x, int y) {
+        return (int)(((less[x] >> y) & 1u) + ((less[y] >> x) & 1u));
+    };
+    int order[8], pos[8];
+    bool placed[8] = {};
+    {
+        int bx = -1, by = -1, bpo = -1, bdeg = -1;
+        for (int x = 0; x < k; x++)
+            for (int y = 0; y < k; y++) {
+                if (x == y || !a[x][y]) continue;
+                const int po = po_between(x, y), dg = deg[x] + deg[y];
+                // x first: the higher degree of the two (then the lower id)
+                if (deg[x] < deg[y] || (deg[x] == deg[y] && x > y)) continue;
+                if (po > bpo || (po == bpo && dg > bdeg)) {
+                    bx = x;
+                    by = y;
+                    bpo = po;
+                    bdeg = dg;
+                }
+            }
+        order[0] = bx;
+        order[1] = k > 1 ? by : -1;
+        for (int s = 0; s < (k > 1 ? 2 : 1); s++) {
+            pos[order[s]] = s;
+            placed[order[s]] = true;
+        }
+    }
+    for (int s = 2; s < k; s++) {
+        int best = -1, best_po = -1, best_back = -1;
+        for (int x = 0; x < k; x++) {
+            if (placed[x]) continue;
+            int back = 0, po = 0;
+            for (int t = 0; t < s; t++) {
+                back += a[x][order[t]];
+                po += po_between(x, order[t]);
+            }
+            if (back == 0) continue;
+            if (po > best_po || (po == best_po && back > best_back) ||
+                (po == best_po && back == best_back && deg[x] > deg[best])) {
+                best = x;
+                best_po = po;
+                best_back = back;
+            }
+        }
+        order[s] = best;
+        pos[best] = s;
+        placed[best] = true;
+    }
+    P = GenPlan{};
+    P.k = k;
+    P.induced = (p->flags & GPM_VERTEX_INDUCED) != 0;
+    // the partial orders as step constraints, checked at the later step
+    for (int x = 0; x < k; x++)
+        for (int y = 0; y < k; y++)
+            if ((less[x] >> y) & 1u) {
+                if (pos[y] > pos[x]) P.above[pos[y]] |= 1u << pos[x];
+                else P.below[pos[x]] |= 1u << pos[y];
+            }
+    // degree filter (Section 4.3), unless GPM_DF=0 in the environment
+    const char *df_env = getenv("GPM_DF");
+    const bool df = !(df_env && df_env[0] == '0');
+    for (int s = 0; s < k; s++) P.dmin[s] = df ? deg[order[s]] : 0;
     for (int s = 0; s < k; s++)
         for (int t = 0; t < s; t++) {
             if (a[order[s]][order[t]]) P.back_adj[s] |= 1u << t;
             else P.back_non[s] |= 1u << t;
         }
     for (int s = 0; s < k; s++) P.vert[s] = order[s];
+    if (order_out)
+        for (int s = 0; s < k; s++) order_out[s] = order[s];
+    if (less_out)
+        for (int x = 0; x < k; x++) less_out[x] = less[x];
     P.ne = p->n_edges;
     for (int i = 0; i < p->n_edges; i++) {
         P.estep[i][0] = pos[p->edges[i][0]];
@@ -511,6 +571,11 @@ gpm_status make_plan(const gpm_pattern *p, GenPlan &P) {
 bool generic_pattern_ok(const gpm_pattern *p) {
     GenPlan P;
     return make_plan(p, P) == GPM_OK;
+}
+
+gpm_status generic_describe(const gpm_pattern *p, int32_t *order, uint32_t *less) {
+    GenPlan P;
+    return make_plan(p, P, order, less);
 }
 
 static void gen_layout(Carve &cv, int64_t narcs, int32_t **chunks, int64_t **chunk_off,

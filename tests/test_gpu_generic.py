@@ -60,6 +60,30 @@ def test_patterns_vs_oracle(gpm, gi, induced):
         assert got == want, (name, induced)
 
 
+def test_degree_filter_off_same_counts(gpm, monkeypatch):
+    """Degree filtering (Section 4.3) only skips candidates that cannot
+    match: with GPM_DF=0 every count, and a listing's total and checksum,
+    are the same."""
+    e = hub_graph()
+    g = build(gpm, e)
+    pats = [(name, PATTERNS[name]) for name in ("4-cycle", "4-path", "house", "5-cycle",
+                                                   "domino", "tadpole")]
+    want = {}
+    for name, (k, edges) in pats:
+        for flags in (gpm.EDGE_INDUCED, gpm.VERTEX_INDUCED):
+            want[(name, flags)] = gpm.count(g, gpm.pattern(k, edges, flags))
+    house = gpm.pattern(5, [(0, 1), (1, 2), (2, 3), (3, 0), (2, 4), (3, 4)],
+                        gpm.EDGE_INDUCED | gpm.LIST)
+    lw = gpm.list_embeddings(g, house, 1 << 16)[:3]
+    monkeypatch.setenv("GPM_DF", "0")
+    for name, (k, edges) in pats:
+        for flags in (gpm.EDGE_INDUCED, gpm.VERTEX_INDUCED):
+            assert gpm.count(g, gpm.pattern(k, edges, flags)) == want[(name, flags)], name
+    house = gpm.pattern(5, [(0, 1), (1, 2), (2, 3), (3, 0), (2, 4), (3, 4)],
+                        gpm.EDGE_INDUCED | gpm.LIST)
+    assert gpm.list_embeddings(g, house, 1 << 16)[:3] == lw
+
+
 def test_relabelled_pattern_same_count(gpm):
     """The same pattern under another vertex numbering (another matching
     order and other partial orders) gives the same count."""
