@@ -29,6 +29,7 @@ enum Flag : int {
     F_MAX_DEG = 2,
     F_MAX_OUT = 3,
     F_MED_COUNT = 4,  // rows routed to the LDS sorter
+    F_DEG16 = 5,      // vertices of degree above 65535
     F_WORDS = 16,
 };
 
@@ -549,7 +550,7 @@ __global__ void __launch_bounds__(kBlock) k_compact_rows(const int32_t *__restri
     const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     constexpr int kRows = kWave / kSmallRow;
-    int32_t maxd = 0;
+    int32_t maxd = 0, big16 = 0;
     // 4 rows per wave: rows of <= 16 entries by a 16-lane group each, longer
     // ones by the whole wave after them
     for (int64_t r0 = wave0 * kRows; r0 < n; r0 += nwaves * kRows) {
@@ -559,6 +560,7 @@ __global__ void __launch_bounds__(kBlock) k_compact_rows(const int32_t *__restri
         const int32_t src = live ? raw_off[row] : 0, dst = live ? off[row] : 0;
         const int32_t L = live ? off[row + 1] - dst : 0;
         maxd = L > maxd ? L : maxd;
+        big16 += (gl == 0 && L > 65535) ? 1 : 0;
         const bool small = L <= kSmallRow;
         int32_t c = 0;
         if (small && gl < L) {
@@ -590,6 +592,8 @@ __global__ void __launch_bounds__(kBlock) k_compact_rows(const int32_t *__restri
     }
     maxd = wave_max(maxd);
     if (lane == 0 && maxd > 0) atomicMax(&flags[F_MAX_DEG], (uint32_t)maxd);
+    big16 = wave_sum(big16);
+    if (lane == 0 && big16 > 0) atomicAdd(&flags[F_DEG16], (uint32_t)big16);
 }
 
 __global__ void __launch_bounds__(kBlock) k_orient_count(const int32_t *__restrict__ off,
@@ -699,6 +703,7 @@ __global__ void k_meta(const int32_t *off, const int32_t *dag_off, int32_t n,
         meta[3] = flags[F_MAX_OUT];
         meta[4] = flags[F_ERR];
         meta[5] = flags[F_BIG_COUNT];
+        meta[6] = flags[F_DEG16];
     }
 }
 
@@ -715,7 +720,7 @@ __global__ void __launch_bounds__(kBlock) k_check_csr(const int32_t *__restrict_
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     if (blockIdx.x == 0 && threadIdx.x == 0 && (off[0] != 0 || (int64_t)off[n] != nnz))
         atomicOr(&flags[F_ERR], 2u);
-    int32_t maxd = 0;
+    int32_t maxd = 0, big16 = 0;
     for (int64_t row = wave0; row < n; row += nwaves) {
         const int32_t u = (int32_t)row;
         const int32_t s = off[u], e = off[u + 1];
@@ -724,6 +729,7 @@ __global__ void __launch_bounds__(kBlock) k_check_csr(const int32_t *__restrict_
             continue;
         }
         maxd = max(maxd, e - s);
+        big16 += (lane == 0 && e - s > 65535) ? 1 : 0;
         bool bad = false;
         for (int32_t i = s + lane; i < e; i += kWave) {
             const int32_t w = adj[i];
@@ -752,6 +758,8 @@ __global__ void __launch_bounds__(kBlock) k_check_csr(const int32_t *__restrict_
     }
     maxd = wave_max(maxd);
     if (lane == 0 && maxd > 0) atomicMax(&flags[F_MAX_DEG], (uint32_t)maxd);
+    big16 = wave_sum(big16);
+    if (lane == 0 && big16 > 0) atomicAdd(&flags[F_DEG16], (uint32_t)big16);
 }
 
 struct BuildLayout {
@@ -875,7 +883,7 @@ gpm_status graph_build(int32_t n, const int32_t *d_u, const int32_t *d_v, int64_
     if (rc2 != GPM_OK) return rc2;
 
     int64_t meta[8] = {0};
-    GPM_HIP(hipMemcpyAsync(meta, L.meta, sizeof(int64_t) * 6, hipMemcpyDeviceToHost, st));
+    GPM_HIP(hipMemcpyAsync(meta, L.meta, sizeof(int64_t) * 7, hipMemcpyDeviceToHost, st));
     GPM_HIP(hipStreamSynchronize(st));
     if (meta[4] != 0) return fail(GPM_NOT_CANONICAL, "an input vertex id is outside [0, n)");
     if (meta[0] % 2 != 0 || meta[1] * 2 != meta[0])
@@ -887,6 +895,7 @@ gpm_status graph_build(int32_t n, const int32_t *d_u, const int32_t *d_v, int64_
     g->m = meta[1];
     g->max_degree = (int32_t)meta[2];
     g->max_out_degree = (int32_t)meta[3];
+    g->n_deg_over_65535 = (int32_t)meta[6];
     g->off = L.off;
     g->adj = L.adj;
     g->dag_off = L.dag_off;
@@ -949,7 +958,7 @@ gpm_status graph_from_csr(int32_t n, const int32_t *d_off, const int32_t *d_adj,
         // orientation needs a valid CSR: read the check result first
         int64_t meta[8] = {0};
         hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, st, L.off, L.off, n, flags, L.meta);
-        GPM_HIP(hipMemcpyAsync(meta, L.meta, sizeof(int64_t) * 6, hipMemcpyDeviceToHost, st));
+        GPM_HIP(hipMemcpyAsync(meta, L.meta, sizeof(int64_t) * 7, hipMemcpyDeviceToHost, st));
         GPM_HIP(hipStreamSynchronize(st));
         if (meta[4] != 0) return fail(GPM_NOT_CANONICAL, "the CSR is not in canonical form");
         hipLaunchKernelGGL(k_orient_count, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.off, L.adj,
@@ -964,7 +973,7 @@ gpm_status graph_from_csr(int32_t n, const int32_t *d_off, const int32_t *d_adj,
         GPM_LAUNCH_CHECK("k_meta");
     }
     int64_t meta[8] = {0};
-    GPM_HIP(hipMemcpyAsync(meta, L.meta, sizeof(int64_t) * 6, hipMemcpyDeviceToHost, st));
+    GPM_HIP(hipMemcpyAsync(meta, L.meta, sizeof(int64_t) * 7, hipMemcpyDeviceToHost, st));
     GPM_HIP(hipStreamSynchronize(st));
     if (meta[4] != 0 || meta[0] != nnz || meta[1] * 2 != meta[0])
         return fail(GPM_NOT_CANONICAL, "the CSR is not symmetric");
@@ -974,6 +983,7 @@ gpm_status graph_from_csr(int32_t n, const int32_t *d_off, const int32_t *d_adj,
     g->m = meta[1];
     g->max_degree = (int32_t)meta[2];
     g->max_out_degree = (int32_t)meta[3];
+    g->n_deg_over_65535 = (int32_t)meta[6];
     g->off = L.off;
     g->adj = L.adj;
     g->dag_off = L.dag_off;

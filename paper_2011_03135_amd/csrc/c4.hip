@@ -295,17 +295,21 @@ __global__ void __launch_bounds__(kBlock) k_c4_light(const int32_t *__restrict__
 // y of x it takes the segment of N(y) inside the part (from the part table,
 // else by binary search in N(y)), and the block walks the concatenated
 // segments, one wedge per lane: each wedge to a z ranked below x adds the
-// count of earlier wedges to that z (the C(c, 2) sum).
-constexpr int kCountPartZ = 32768;   // z-range of a counting task (128 KiB of counters)
+// count of earlier wedges to that z (the C(c, 2) sum).  A counter
+// c(x, z) never exceeds deg(z), and z, ranked below x, is never the
+// top-ranked vertex, so when at most one vertex has a degree above 65535
+// the counters are 16 bits, two to a word, and a part spans 65536 ids
+// instead of 32768: half the tasks, segments twice as long.
+constexpr int kCountWords = 32768;   // LDS counter words of a counting task (128 KiB)
 constexpr int kHeavyNT = 1024;
 constexpr int kSegMaxParts = 256;    // part table only for graphs of at most 256 parts
 constexpr uint64_t kSegMaxBytes = 2ull << 30;
 
-// Part table: seg[p * n + y] = {first arc of N(y) with end >= p * kCountPartZ,
+// Part table: seg[p * n + y] = {first arc of N(y) with end >= p * zpart,
 // number of arcs of N(y) with end in part p}.
 __global__ void __launch_bounds__(kBlock) k_c4_seg(const int32_t *__restrict__ off,
                                                    const int32_t *__restrict__ adj, int32_t n,
-                                                   int32_t nparts, int2 *seg) {
+                                                   int32_t nparts, int32_t zpart, int2 *seg) {
     __shared__ int32_t s_bnd[kWPB][kSegMaxParts + 1];
     const int lane = lane_id();
     int32_t *bnd = s_bnd[threadIdx.x / kWave];
@@ -314,11 +318,11 @@ __global__ void __launch_bounds__(kBlock) k_c4_seg(const int32_t *__restrict__ o
     for (int64_t y = wave0; y < n; y += nwaves) {
         const int32_t s = off[y], d = off[y + 1] - s;
         for (int32_t i = lane; i < d; i += kWave) {
-            const int32_t pc = adj[s + i] / kCountPartZ;
-            const int32_t pp = i == 0 ? -1 : adj[s + i - 1] / kCountPartZ;
+            const int32_t pc = adj[s + i] / zpart;
+            const int32_t pp = i == 0 ? -1 : adj[s + i - 1] / zpart;
             for (int32_t q = pp + 1; q <= pc; q++) bnd[q] = i;
         }
-        const int32_t plast = d > 0 ? adj[s + d - 1] / kCountPartZ : -1;
+        const int32_t plast = d > 0 ? adj[s + d - 1] / zpart : -1;
         for (int32_t q = plast + 1 + lane; q <= nparts; q += kWave) bnd[q] = d;
         wave_sync();
         for (int32_t q = lane; q < nparts; q += kWave)
@@ -341,11 +345,11 @@ __global__ void __launch_bounds__(kHeavyNT) k_c4_heavy(const int32_t *__restrict
                                                        const int32_t *__restrict__ adeg,
                                                        const int32_t *__restrict__ list,
                                                        const int32_t *__restrict__ count_p,
-                                                       int32_t n, int32_t nparts,
+                                                       int32_t n, int32_t nparts, int32_t narrow,
                                                        const int2 *__restrict__ seg,
                                                        uint32_t *cursor, unsigned long long *out) {
     constexpr int NW = kHeavyNT / kWave;
-    __shared__ uint32_t cnt[kCountPartZ];
+    __shared__ uint32_t cnt[kCountWords];
     __shared__ int32_t s_pre[kHeavyNT + 1];
     __shared__ int32_t s_off[kHeavyNT];    // segment start arc minus its pair prefix
     __shared__ int32_t s_sum[NW];
@@ -354,7 +358,8 @@ __global__ void __launch_bounds__(kHeavyNT) k_c4_heavy(const int32_t *__restrict
     const int32_t nheavy = *count_p;
     const uint64_t ntasks = (uint64_t)nheavy * (uint64_t)nparts;
     uint64_t acc = 0;
-    for (int i = tid; i < kCountPartZ; i += kHeavyNT) cnt[i] = 0;
+    const int32_t zpart = narrow ? 2 * kCountWords : kCountWords;
+    for (int i = tid; i < kCountWords; i += kHeavyNT) cnt[i] = 0;
     for (;;) {
         if (tid == 0) s_task = atomicAdd(cursor, 1u);
         __syncthreads();
@@ -363,7 +368,7 @@ __global__ void __launch_bounds__(kHeavyNT) k_c4_heavy(const int32_t *__restrict
         if (t >= ntasks) break;
         const int32_t part = (int32_t)(t / (uint64_t)nheavy);
         const int32_t x = list[t % (uint64_t)nheavy];
-        const int32_t z0 = part * kCountPartZ, z1 = z0 + kCountPartZ;
+        const int32_t z0 = part * zpart, z1 = z0 + zpart;
         const int32_t s = off[x], dx = off[x + 1] - s;
         for (int32_t c0 = 0; c0 < dx; c0 += kHeavyNT) {
             const int32_t i = c0 + tid;
@@ -403,13 +408,22 @@ __global__ void __launch_bounds__(kHeavyNT) k_c4_heavy(const int32_t *__restrict
                     j = s_pre[w] <= q ? seg_of(s_pre, w, kHeavyNT, q) : seg_of(s_pre, j0, w, q);
                     const int32_t e = s_off[j] + q;
                     const int32_t z = adj[e];
-                    if (rank_less(adeg[e], z, dx, x)) acc += atomicAdd(&cnt[z - z0], 1u);
+                    if (rank_less(adeg[e], z, dx, x)) {
+                        // each wedge to z adds the number of earlier ones
+                        const uint32_t zz = (uint32_t)(z - z0);
+                        if (narrow) {
+                            const uint32_t sh = (zz & 1u) * 16u;
+                            acc += (atomicAdd(&cnt[zz >> 1], 1u << sh) >> sh) & 0xffffu;
+                        } else {
+                            acc += atomicAdd(&cnt[zz], 1u);
+                        }
+                    }
                 }
                 j0 = __shfl(j, kWave - 1, kWave);
             }
             __syncthreads();
         }
-        for (int i = tid; i < kCountPartZ; i += kHeavyNT) cnt[i] = 0;
+        for (int i = tid; i < kCountWords; i += kHeavyNT) cnt[i] = 0;
         __syncthreads();
     }
     acc = wave_sum(acc);
@@ -683,7 +697,16 @@ struct C4Ws {
     uint64_t bytes;
 };
 
-int32_t count_parts(const gpm_graph *g) { return (g->n + kCountPartZ - 1) / kCountPartZ; }
+// 16-bit counters when at most one vertex (the top-ranked one, never a
+// cycle's z) has a degree above 65535
+bool narrow_counts(const gpm_graph *g) { return g->n_deg_over_65535 <= 1; }
+
+int32_t count_zpart(const gpm_graph *g) { return narrow_counts(g) ? 2 * kCountWords : kCountWords; }
+
+int32_t count_parts(const gpm_graph *g) {
+    const int32_t z = count_zpart(g);
+    return (int32_t)(((int64_t)g->n + z - 1) / z);
+}
 
 bool seg_table(const gpm_graph *g) {
     const int32_t np = count_parts(g);
@@ -765,13 +788,13 @@ gpm_status c4_run(const gpm_graph *g, bool list, void *ws, uint64_t ws_bytes,
                            W.deg, 2 * g->m, W.adeg);
         if (W.seg)
             hipLaunchKernelGGL(k_c4_seg, dim3(grid_for(n, kWPB, 8)), dim3(kBlock), 0, st, g->off,
-                               g->adj, n, cparts, W.seg);
+                               g->adj, n, cparts, count_zpart(g), W.seg);
         GPM_LAUNCH_CHECK("k_c4_seg");
         {
             Span sp("k_c4_heavy", st);
             hipLaunchKernelGGL(k_c4_heavy, dim3((unsigned)cu_count()), dim3(kHeavyNT), 0, st,
-                               g->off, g->adj, W.adeg, W.heavy, cnt_heavy, n, cparts, W.seg,
-                               W.ctl + 0, out128);
+                               g->off, g->adj, W.adeg, W.heavy, cnt_heavy, n, cparts,
+                               narrow_counts(g) ? 1 : 0, W.seg, W.ctl + 0, out128);
         }
         GPM_LAUNCH_CHECK("k_c4_heavy");
         {

@@ -13,6 +13,7 @@ struct gpm_graph {
     int64_t m;
     int32_t max_degree;
     int32_t max_out_degree;
+    int32_t n_deg_over_65535;   // vertices of degree above 65535
     int32_t *off;       // [n+1] symmetric CSR offsets
     int32_t *adj;       // [2m]
     int32_t *dag_off;   // [n+1] oriented CSR offsets

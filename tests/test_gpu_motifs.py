@@ -69,3 +69,28 @@ def test_rmat18_motifs_golden(gpm):
     g = build(gpm, graphgen.rmat(18, seed=18))
     assert gpm.motif_count(g, 3) == gold["motif3"]
     assert gpm.motif_count(g, 4) == gold["motif4"]
+
+
+def C(n, k):
+    from math import comb
+    return comb(n, k)
+
+
+def test_four_cycle_counter_widths(gpm):
+    """The 4-cycle counters are 16 bits when at most one vertex has a degree
+    above 65535 (a star's centre of degree 70,000 next to K_{3,300}) and 32
+    bits otherwise (K_{2,70000}: two such vertices, a counter reaching
+    70,000); closed forms for both: K_{a,b} holds C(a,2) C(b,2) 4-cycles and
+    a C(b,3) + b C(a,3) 3-stars."""
+    star_k = graphgen.disjoint_union([graphgen.star_graph(70000),
+                                      graphgen.complete_bipartite(3, 300)])
+    g = build(gpm, star_k)
+    c4 = C(3, 2) * C(300, 2)
+    assert gpm.count(g, gpm.cycle4()) == c4
+    claws = C(70000, 3) + 3 * C(300, 3) + 300 * C(3, 3)
+    assert gpm.motif_count(g, 4) == [claws, 0, c4, 0, 0, 0]
+    kb = graphgen.complete_bipartite(2, 70000)
+    g = build(gpm, kb)
+    c4 = C(2, 2) * C(70000, 2)
+    assert gpm.count(g, gpm.cycle4()) == c4
+    assert gpm.motif_count(g, 4) == [2 * C(70000, 3), 0, c4, 0, 0, 0]
