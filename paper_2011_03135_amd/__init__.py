@@ -32,6 +32,8 @@ from .binding import (  # noqa: F401
     motif_classes,
     motif_class_pattern,
     motif_count_enum,
+    motif_count_formula,
+    motif_formula_workspace_bytes,
     motif_enum_workspace_bytes,
     pattern,
     timing_enable,

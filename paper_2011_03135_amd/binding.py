@@ -86,6 +86,8 @@ def load():
         "gpm_motif_class_pattern": ([i32, i32, P], i32),
         "gpm_motif_enum_workspace_bytes": ([P, i32, P], i32),
         "gpm_motif_count_enum": ([P, i32, P, u64, P, P], i32),
+        "gpm_motif_formula_workspace_bytes": ([P, i32, P], i32),
+        "gpm_motif_count_formula": ([P, i32, P, u64, P, P], i32),
         "gpm_batch_workspace_bytes": ([i32, i32, P], i32),
         "gpm_batch_motif_count": ([P, P, i32, i32, P, u64, P, P], i32),
         "gpm_batch_default_config": ([P], i32),
@@ -417,6 +419,30 @@ def motif_count_enum(g, k, stream=None, ws=None, out=None):
     if out is not None:
         return out
     return [_u64(x) for x in res.tolist()]
+
+
+def motif_formula_workspace_bytes(g, k=5):
+    b = ctypes.c_uint64()
+    _check(load().gpm_motif_formula_workspace_bytes(g.handle, int(k), ctypes.byref(b)))
+    return b.value
+
+
+def motif_count_formula(g, k=5, stream=None, ws=None, out=None):
+    """gpm_motif_count_formula -> the 21 induced 5-motif counts (exact ints),
+    by local-count formulas and back-substitution.  With `out` (int64 device
+    tensor of 22 entries) the call only enqueues and returns `out`."""
+    nbytes = motif_formula_workspace_bytes(g, k)
+    if ws is None or ws.numel() < nbytes:
+        ws = _buffer(nbytes, g.device)
+    res = out if out is not None else torch.zeros(22, dtype=torch.int64, device=g.device)
+    _check(load().gpm_motif_count_formula(g.handle, int(k), _ptr(ws), ws.numel(), _ptr(res),
+                                          _stream(stream)))
+    if out is not None:
+        return out
+    vals = [_u64(x) for x in res.tolist()]
+    if vals[-1] != 0:
+        raise GpmError(7, f"formula check failed (status word {vals[-1]})")
+    return vals[:-1]
 
 
 class BatchConfig(ctypes.Structure):

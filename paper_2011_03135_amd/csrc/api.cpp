@@ -49,6 +49,9 @@ gpm_status motif_class_pattern(int k, int idx, gpm_pattern *out);
 gpm_status motif_enum_workspace_bytes(const gpm_graph *g, uint64_t *bytes);
 gpm_status motif_enum_count(const gpm_graph *g, int k, void *ws, uint64_t ws_bytes,
                             unsigned long long *out, hipStream_t st);
+gpm_status motif_formula_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes);
+gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t ws_bytes,
+                               unsigned long long *d_counts, hipStream_t st);
 gpm_status batch_workspace_bytes(int32_t G, int32_t k, uint64_t *bytes);
 gpm_status batch_default_config(gpm_batch_config *c);
 gpm_status batch_run(const gpm_graph *g, const int32_t *d_voff, int32_t G, int32_t k,
@@ -439,6 +442,25 @@ gpm_status gpm_motif_count_enum(const gpm_graph *g, int32_t k, void *d_ws, uint6
     return gpm::motif_enum_count(g, k, d_ws, ws_bytes,
                                  reinterpret_cast<unsigned long long *>(d_counts),
                                  static_cast<hipStream_t>(stream));
+}
+
+gpm_status gpm_motif_formula_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes) {
+    gpm_status rc = check_graph(g);
+    if (rc) return rc;
+    if (!bytes) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    return gpm::motif_formula_workspace_bytes(g, k, bytes);
+}
+
+gpm_status gpm_motif_count_formula(const gpm_graph *g, int32_t k, void *d_ws, uint64_t ws_bytes,
+                                   uint64_t *d_counts, void *stream) {
+    gpm_status rc = check_graph(g);
+    if (rc) return rc;
+    if (k != 5) return fail(GPM_UNSUPPORTED, "formula motif counting is for k = 5");
+    if (!d_counts) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    if (!d_ws || !aligned256(d_ws)) return fail(GPM_INVALID_ARGUMENT, "workspace NULL or unaligned");
+    return gpm::motif_formula_count(g, k, d_ws, ws_bytes,
+                                    reinterpret_cast<unsigned long long *>(d_counts),
+                                    static_cast<hipStream_t>(stream));
 }
 
 gpm_status gpm_batch_workspace_bytes(int32_t G, int32_t k, uint64_t *bytes) {

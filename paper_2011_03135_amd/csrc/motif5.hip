@@ -1,0 +1,398 @@
+// Induced 5-motif counts by formulas (the counting-by-formula approach the
+// paper names in Section 7; the method here follows the idea of ESCAPE,
+// Pinar, Seshadhri and Vishal, WWW 2017: non-induced counts, most of them
+// from local counts, then exact back-substitution).
+//
+// For the 21 connected 5-vertex graphs H (classes in gpm_motif_class_pattern
+// order: by edge count, then by canonical code), N(P) = number of subgraphs
+// (edge sets) isomorphic to P and I(H) = number of induced copies satisfy
+//     N(P) = sum over H of c(P, H) I(H),
+// c(P, H) = number of spanning subgraphs of H isomorphic to P (c(H, H) = 1,
+// zero unless H has more edges), so I follows by back-substitution from the
+// densest class down.  The matrix c is built on the host by brute force over
+// the edge subsets of each class.
+//
+// Eight N(P) have closed forms in local counts: degrees d, per-edge triangle
+// counts T_e (the Section 5 local counts, from the triangle kernels), per
+// vertex t_v = triangles at v, s_v = sum of the neighbours' degrees and
+// q_v = sum of (neighbour degree - 1)^2, and the totals T and N(C4):
+//   star K1,4   sum_v C(d_v, 4)
+//   chair       sum over ordered arcs (c, x) of C(d_c - 1, 2)(d_x - 1) - T_cx (d_c - 2)
+//   5-path      sum_c [(s_c - d_c)^2 - q_c] / 2 - (2 sum_v t_v d_v - 9T) - 4 N(C4)
+//   cricket     sum_c t_c C(d_c - 2, 2)
+//   bull        sum_e T_e [(d_x - 2)(d_y - 2) - (T_e - 1)]
+//   tadpole     sum_c t_c (s_c - d_c) - (2 sum_v t_v d_v - 6T) - 2 sum_e T_e (T_e - 1)
+//   bowtie      sum_v C(t_v, 2) - 2 sum_e C(T_e, 2)
+//   dart        sum_e C(T_e, 2)(d_x + d_y - 6)
+// (each derived by counting the choices of the pattern's free vertices
+// around its cut vertex or edge and subtracting the choices that collide).
+// The other thirteen, whose copies are far fewer (a dense core with at most
+// a pendant: the search ends in a population count), are counted by the
+// general plan as edge-induced patterns, K5 by the clique kernels.
+#include "gpm_internal.h"
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+namespace gpm {
+
+gpm_status clique_workspace_bytes(const gpm_graph *g, int32_t k, bool list, uint64_t *bytes);
+gpm_status clique_run(const gpm_graph *g, int32_t k, bool list, void *ws, uint64_t ws_bytes,
+                      unsigned long long *d_count, int32_t *d_buf, uint64_t cap,
+                      unsigned long long *d_result, hipStream_t st);
+gpm_status triangle_arc_counts(const gpm_graph *g, void *ws, uint64_t ws_bytes, uint32_t *te,
+                               unsigned long long *tri, hipStream_t st);
+gpm_status c4_workspace_bytes(const gpm_graph *g, bool list, uint64_t *bytes);
+gpm_status c4_run(const gpm_graph *g, bool list, void *ws, uint64_t ws_bytes,
+                  unsigned long long *out128, int32_t *d_buf, uint64_t cap,
+                  unsigned long long *d_result, hipStream_t st);
+uint64_t generic_workspace_bytes(const gpm_graph *g);
+gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, void *ws, uint64_t ws_bytes,
+                         unsigned long long *out, hipStream_t st);
+gpm_status motif_class_pattern(int k, int idx, gpm_pattern *out);
+
+namespace {
+
+typedef unsigned __int128 u128;
+
+constexpr int kClasses = 21;
+constexpr int kBlock = 256;
+
+// Classes with a closed form, and the accumulator pair (plus, minus) of each.
+enum Formula : int { F_STAR, F_CHAIR, F_PATH, F_CRICKET, F_BULL, F_TADPOLE, F_BOWTIE, F_DART,
+                     F_COUNT };
+constexpr int kFormulaClass[F_COUNT] = {0, 1, 2, 3, 4, 6, 11, 8};
+constexpr int kK5Class = 20;
+
+struct Back {
+    uint16_t c[kClasses][kClasses];   // c[P][H], spanning copies of P in H
+    int32_t formula_of[kClasses];     // F_* or -1
+};
+
+// Accumulators: 2 u64 words per u128.
+enum Acc : int {
+    A_PLUS = 0,                       // F_COUNT u128: positive parts
+    A_MINUS = A_PLUS + 2 * F_COUNT,   // F_COUNT u128: subtracted parts
+    A_TRI = A_MINUS + 2 * F_COUNT,    // u64: triangles (from the arc counts)
+    A_C4 = A_TRI + 2,                 // u128: 4-cycles (edge sets)
+    A_GEN = A_C4 + 2,                 // kClasses u64: counts of the enumerated classes
+    A_WORDS = A_GEN + kClasses,
+};
+
+__device__ __forceinline__ u128 binom2(uint64_t n) { return n < 2 ? 0 : (u128)n * (n - 1) / 2; }
+__device__ __forceinline__ u128 binom4(uint64_t n) {
+    return n < 4 ? 0 : (u128)n * (n - 1) / 2 * (n - 2) / 3 * (n - 3) / 4;
+}
+
+__device__ __forceinline__ u128 wave_sum_u128(u128 x) {
+    uint64_t lo = (uint64_t)x, hi = (uint64_t)(x >> 64);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t lo2 = __shfl_xor(lo, o, 64), hi2 = __shfl_xor(hi, o, 64);
+        const uint64_t s = lo + lo2;
+        hi = hi + hi2 + (s < lo ? 1 : 0);
+        lo = s;
+    }
+    return ((u128)hi << 64) | lo;
+}
+
+// Per vertex: t_v from the arc triangle counts (each arc adds its count to
+// both ends; every triangle at v lies on two of v's arcs).
+__global__ void k_vertex_tri(const int32_t *__restrict__ dag_src, const int32_t *__restrict__ dag_adj,
+                             const uint32_t *__restrict__ te, int64_t m,
+                             unsigned long long *__restrict__ t2) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = te[e];
+        if (c) {
+            atomicAdd(&t2[dag_src[e]], (unsigned long long)c);
+            atomicAdd(&t2[dag_adj[e]], (unsigned long long)c);
+        }
+    }
+}
+
+// One wave per vertex: s_v, q_v over the neighbours, then the vertex terms
+// of the formulas.
+__global__ void __launch_bounds__(kBlock) k_f5_vertex(const int32_t *__restrict__ off,
+                                                      const int32_t *__restrict__ adj, int32_t n,
+                                                      const unsigned long long *__restrict__ t2,
+                                                      unsigned long long *acc) {
+    const int lane = lane_id();
+    const int64_t wave0 = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+    u128 plus[F_COUNT] = {}, minus[F_COUNT] = {};
+    for (int64_t v = wave0; v < n; v += nwaves) {
+        const int32_t s0 = off[v], dv = off[v + 1] - s0;
+        uint64_t s = 0, q = 0;
+        for (int32_t i = lane; i < dv; i += kWave) {
+            const int32_t w = adj[s0 + i];
+            const uint64_t dw = (uint64_t)(off[w + 1] - off[w]);
+            s += dw;
+            q += (dw - 1) * (dw - 1);
+        }
+        s = wave_sum(s);
+        q = wave_sum(q);
+        if (lane != 0) continue;
+        const uint64_t d = (uint64_t)dv, t = t2[v] / 2;
+        plus[F_STAR] += binom4(d);
+        // 5-path: pairs of neighbours b < b' of the middle, (d_b - 1)(d_b' - 1)
+        const u128 sd = (u128)(s - d);
+        plus[F_PATH] += (sd * sd - (u128)q) / 2;
+        minus[F_PATH] += (u128)2 * t * d;
+        if (d >= 2) plus[F_CRICKET] += (u128)t * binom2(d - 2);
+        plus[F_TADPOLE] += (u128)t * (s - d);
+        minus[F_TADPOLE] += (u128)2 * t * d;
+        plus[F_BOWTIE] += binom2(t);
+    }
+#pragma unroll
+    for (int f = 0; f < F_COUNT; f++) {
+        const u128 p = wave_sum_u128(plus[f]), mm = wave_sum_u128(minus[f]);
+        if (lane == 0) {
+            if (p) atomic_add_u128(acc + A_PLUS + 2 * f, p);
+            if (mm) atomic_add_u128(acc + A_MINUS + 2 * f, mm);
+        }
+    }
+}
+
+// One thread per undirected edge (an arc of the DAG): the edge terms.
+__global__ void __launch_bounds__(kBlock) k_f5_edge(const int32_t *__restrict__ off,
+                                                    const int32_t *__restrict__ dag_src,
+                                                    const int32_t *__restrict__ dag_adj,
+                                                    const uint32_t *__restrict__ te, int64_t m,
+                                                    unsigned long long *acc) {
+    const int lane = lane_id();
+    u128 plus[F_COUNT] = {}, minus[F_COUNT] = {};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x; e0 < m; e0 += stride) {
+        const int64_t e = e0 + threadIdx.x;
+        if (e >= m) continue;
+        const int32_t x = dag_src[e], y = dag_adj[e];
+        const uint64_t dx = (uint64_t)(off[x + 1] - off[x]), dy = (uint64_t)(off[y + 1] - off[y]);
+        const uint64_t T = te[e];
+        // chair, both orientations: centre c, its neighbour x on the long arm
+        plus[F_CHAIR] += binom2(dx - 1) * (dy - 1) + binom2(dy - 1) * (dx - 1);
+        if (T) {
+            // a triangle on the edge puts both ends at degree >= 2
+            minus[F_CHAIR] += (u128)T * ((dx - 2) + (dy - 2));
+            plus[F_BULL] += (u128)T * ((dx - 2) * (dy - 2));
+            minus[F_BULL] += (u128)T * (T - 1);
+            minus[F_TADPOLE] += (u128)2 * T * (T - 1);
+            minus[F_BOWTIE] += 2 * binom2(T);
+            // two triangles on the edge put both ends at degree >= 3
+            if (T >= 2) plus[F_DART] += binom2(T) * (dx + dy - 6);
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < F_COUNT; f++) {
+        const u128 p = wave_sum_u128(plus[f]), mm = wave_sum_u128(minus[f]);
+        if (lane == 0) {
+            if (p) atomic_add_u128(acc + A_PLUS + 2 * f, p);
+            if (mm) atomic_add_u128(acc + A_MINUS + 2 * f, mm);
+        }
+    }
+}
+
+__device__ __forceinline__ u128 load128(const unsigned long long *p) {
+    return ((u128)p[1] << 64) | p[0];
+}
+
+// Totals of the formulas, then back-substitution from the densest class.
+// out[0..20] = induced counts, out[21] = status (1: a formula or a
+// subtraction went negative, 2: a count does not fit 64 bits).
+__global__ void k_f5_combine(const unsigned long long *acc, Back B, unsigned long long *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    unsigned long long bad = 0;
+    const u128 T = (u128)acc[A_TRI];
+    const u128 nc4 = load128(acc + A_C4);
+    u128 N[kClasses];
+    for (int h = 0; h < kClasses; h++) {
+        const int f = B.formula_of[h];
+        if (f < 0) {
+            N[h] = (u128)acc[A_GEN + h];
+            continue;
+        }
+        u128 p = load128(acc + A_PLUS + 2 * f), mm = load128(acc + A_MINUS + 2 * f);
+        // the global terms of the 5-path and the tadpole
+        if (f == F_PATH) {
+            p += 9 * T;
+            mm += 4 * nc4;
+        }
+        if (f == F_TADPOLE) p += 6 * T;
+        if (p < mm) bad |= 1;
+        N[h] = p - mm;
+    }
+    u128 I[kClasses];
+    for (int h = kClasses - 1; h >= 0; h--) {
+        u128 sub = 0;
+        for (int k = h + 1; k < kClasses; k++) sub += (u128)B.c[h][k] * I[k];
+        if (N[h] < sub) bad |= 1;
+        I[h] = N[h] - sub;
+        if (I[h] >> 64) bad |= 2;
+        out[h] = (unsigned long long)I[h];
+    }
+    out[kClasses] = bad;
+}
+
+__global__ void k_copy_u64(const unsigned long long *src, unsigned long long *dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+// Host: canonical form of a 5-vertex edge set (smallest sorted edge list
+// over the 120 vertex orders).
+uint32_t canon5(const int (*e)[2], int ne) {
+    int p[5] = {0, 1, 2, 3, 4};
+    uint32_t best = ~0u;
+    do {
+        uint32_t code = 0;
+        for (int i = 0; i < ne; i++) {
+            int a = p[e[i][0]], b = p[e[i][1]];
+            if (a > b) std::swap(a, b);
+            // bit of pair (a, b), a < b, in a 10-bit set
+            const int bit = a * (9 - a) / 2 + (b - a - 1);
+            code |= 1u << bit;
+        }
+        best = std::min(best, code);
+    } while (std::next_permutation(p, p + 5));
+    return best;
+}
+
+bool connected5(const int (*e)[2], int ne) {
+    int reach = 1;
+    for (int it = 0; it < 5; it++)
+        for (int i = 0; i < ne; i++) {
+            const int a = 1 << e[i][0], b = 1 << e[i][1];
+            if ((reach & a) || (reach & b)) reach |= a | b;
+        }
+    return reach == 31;
+}
+
+const Back &back_matrix() {
+    static Back B;
+    static bool made = false;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    if (made) return B;
+    gpm_pattern cls[kClasses];
+    uint32_t code[kClasses];
+    for (int h = 0; h < kClasses; h++) {
+        motif_class_pattern(5, h, &cls[h]);
+        int e[10][2];
+        for (int i = 0; i < cls[h].n_edges; i++) {
+            e[i][0] = cls[h].edges[i][0];
+            e[i][1] = cls[h].edges[i][1];
+        }
+        code[h] = canon5(e, cls[h].n_edges);
+    }
+    for (int p = 0; p < kClasses; p++)
+        for (int h = 0; h < kClasses; h++) B.c[p][h] = 0;
+    for (int h = 0; h < kClasses; h++) {
+        const int ne = cls[h].n_edges;
+        for (uint32_t sub = 1; sub < (1u << ne); sub++) {
+            int e[10][2], k = 0, seen = 0;
+            for (int i = 0; i < ne; i++)
+                if ((sub >> i) & 1u) {
+                    e[k][0] = cls[h].edges[i][0];
+                    e[k][1] = cls[h].edges[i][1];
+                    seen |= (1 << e[k][0]) | (1 << e[k][1]);
+                    k++;
+                }
+            if (seen != 31 || !connected5(e, k)) continue;
+            const uint32_t c = canon5(e, k);
+            for (int p = 0; p < kClasses; p++)
+                if (code[p] == c) B.c[p][h]++;
+        }
+    }
+    for (int h = 0; h < kClasses; h++) B.formula_of[h] = -1;
+    for (int f = 0; f < F_COUNT; f++) B.formula_of[kFormulaClass[f]] = f;
+    made = true;
+    return B;
+}
+
+struct F5Ws {
+    unsigned long long *acc, *t2;
+    uint32_t *te;
+    void *shared;
+    uint64_t shared_bytes, bytes;
+};
+
+F5Ws f5_layout(const gpm_graph *g, void *base) {
+    F5Ws W{};
+    Carve c(base, ~0ull);
+    W.acc = c.take<unsigned long long>(A_WORDS);
+    W.t2 = c.take<unsigned long long>((uint64_t)g->n + 1);
+    W.te = c.take<uint32_t>((uint64_t)g->m + 1);
+    uint64_t b3 = 0, b5 = 0, bc4 = 0;
+    clique_workspace_bytes(g, 3, false, &b3);
+    clique_workspace_bytes(g, 5, false, &b5);
+    c4_workspace_bytes(g, false, &bc4);
+    W.shared_bytes = std::max({b3, b5, bc4, generic_workspace_bytes(g)});
+    W.shared = c.take<char>(W.shared_bytes);
+    W.bytes = c.used;
+    return W;
+}
+
+unsigned grid_for(int64_t items, int per_block, int cap_per_cu) {
+    int64_t b = (items + per_block - 1) / per_block;
+    int64_t cap = (int64_t)cu_count() * cap_per_cu;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+}  // namespace
+
+gpm_status motif_formula_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes) {
+    if (k != 5) return fail(GPM_UNSUPPORTED, "formula motif counting is for k = 5");
+    *bytes = f5_layout(g, nullptr).bytes;
+    return GPM_OK;
+}
+
+gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t ws_bytes,
+                               unsigned long long *d_counts, hipStream_t st) {
+    if (k != 5) return fail(GPM_UNSUPPORTED, "formula motif counting is for k = 5");
+    F5Ws W = f5_layout(g, ws);
+    if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
+    const Back &B = back_matrix();
+    const int32_t n = g->n;
+    const int64_t m = g->m;
+    GPM_HIP(fill_u32(W.acc, 0, 2 * (uint64_t)A_WORDS, st));
+    GPM_HIP(fill_u32(W.t2, 0, 2 * ((uint64_t)n + 1), st));
+    if (m > 0) GPM_HIP(fill_u32(W.te, 0, (uint64_t)m, st));
+    // local counts: triangles per edge (and their total), per vertex
+    gpm_status rc = triangle_arc_counts(g, W.shared, W.shared_bytes, W.te, W.acc + A_TRI, st);
+    if (rc) return rc;
+    {
+        Span sp("k_f5_local", st);
+        if (m > 0) {
+            hipLaunchKernelGGL(k_vertex_tri, dim3(grid_for(m, kBlock, 8)), dim3(kBlock), 0, st,
+                               g->dag_src, g->dag_adj, W.te, m, W.t2);
+            hipLaunchKernelGGL(k_f5_edge, dim3(grid_for(m, kBlock, 8)), dim3(kBlock), 0, st,
+                               g->off, g->dag_src, g->dag_adj, W.te, m, W.acc);
+        }
+        hipLaunchKernelGGL(k_f5_vertex, dim3(grid_for(n, kBlock / kWave, 8)), dim3(kBlock), 0,
+                           st, g->off, g->adj, n, W.t2, W.acc);
+    }
+    GPM_LAUNCH_CHECK("k_f5_local");
+    // 4-cycles (edge sets), for the 5-path
+    rc = c4_run(g, false, W.shared, W.shared_bytes, W.acc + A_C4, nullptr, 0, nullptr, st);
+    if (rc) return rc;
+    // the enumerated classes: K5 by the clique kernels, the rest by the
+    // general plan as edge-induced patterns
+    for (int h = 0; h < kClasses; h++) {
+        if (B.formula_of[h] >= 0) continue;
+        unsigned long long *slot = W.acc + A_GEN + h;
+        if (h == kK5Class) {
+            rc = clique_run(g, 5, false, W.shared, W.shared_bytes, slot, nullptr, 0, nullptr, st);
+        } else {
+            gpm_pattern p;
+            motif_class_pattern(5, h, &p);
+            p.flags = GPM_EDGE_INDUCED;
+            rc = generic_count(g, &p, W.shared, W.shared_bytes, slot, st);
+        }
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_f5_combine, dim3(1), dim3(64), 0, st, W.acc, B, d_counts);
+    GPM_LAUNCH_CHECK("k_f5_combine");
+    return GPM_OK;
+}
+
+}  // namespace gpm

@@ -100,6 +100,11 @@ def test_motif_and_fused_workspace_too_small(gpm, graph):
         rc = lib.gpm_motif_count_enum(graph.handle, k, P(ws), ws.numel(), P(out), stream())
         assert rc == OOM, k
         assert untouched(out)
+    out = sentinel(22)
+    ws = small_ws(gpm.motif_formula_workspace_bytes(graph, 5))
+    rc = lib.gpm_motif_count_formula(graph.handle, 5, P(ws), ws.numel(), P(out), stream())
+    assert rc == OOM
+    assert untouched(out)
     for kmax in (4, 5):
         out = sentinel(3)
         ws = small_ws(gpm.binding.clique_counts_workspace_bytes(graph, kmax))

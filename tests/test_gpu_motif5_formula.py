@@ -1,0 +1,80 @@
+"""Induced 5-motif counts by formulas (local counts, the general plan for
+the dense classes, back-substitution) against the oracle class by class,
+against closed forms, and against the enumeration route."""
+from math import comb
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from gpu_util import build
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpm():
+    import paper_2011_03135_amd as m
+    m.load()
+    return m
+
+
+def hub_graph():
+    base = graphgen.erdos_renyi(90, 0.08, 5)
+    rng = np.random.default_rng(5)
+    ends = rng.choice(np.arange(1, 90), size=40, replace=False).astype(np.int32)
+    return graphgen.EdgeList(90, np.concatenate([base.u, np.zeros(40, np.int32)]),
+                             np.concatenate([base.v, ends]), "hub")
+
+
+def cases():
+    return [graphgen.erdos_renyi(40, 0.2, 1),
+            graphgen.erdos_renyi(60, 0.12, 2),
+            graphgen.rmat(8, seed=3),
+            hub_graph(),
+            graphgen.disjoint_union([graphgen.complete_graph(7), graphgen.cycle_graph(8),
+                                     graphgen.star_graph(9)]),
+            graphgen.EdgeList(6, np.zeros(0, np.int32), np.zeros(0, np.int32), "empty")]
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_formula_route_vs_oracle(gpm, case):
+    e = cases()[case]
+    print(f"5-motif formula case {case} {e.name}", flush=True)
+    g = build(gpm, e)
+    off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+    want = [oracle.pattern_count(off, adj, 5, gpm.motif_class_pattern(5, i), True)[0]
+            for i in range(21)]
+    assert gpm.motif_count_formula(g, 5) == want
+
+
+def test_formula_route_closed_forms(gpm):
+    def only(i, v):
+        out = [0] * 21
+        out[i] = v
+        return out
+    assert gpm.motif_count_formula(build(gpm, graphgen.complete_graph(9)), 5) == only(20, comb(9, 5))
+    assert gpm.motif_count_formula(build(gpm, graphgen.star_graph(30)), 5) == only(0, comb(30, 4))
+    assert gpm.motif_count_formula(build(gpm, graphgen.cycle_graph(11)), 5) == only(2, 11)
+    # K_{3,6}: 4-stars centred on the small side, K_{2,3} either way round
+    want = [0] * 21
+    want[0] = 3 * comb(6, 4)
+    want[10] = comb(3, 2) * comb(6, 3) + comb(3, 3) * comb(6, 2)
+    assert gpm.motif_count_formula(build(gpm, graphgen.complete_bipartite(3, 6)), 5) == want
+
+
+@pytest.mark.parametrize("scale", [10, 12])
+def test_formula_route_equals_enumeration(gpm, scale):
+    """The two device routes, formulas and pattern-oblivious enumeration,
+    give the same 21 counts on RMAT graphs."""
+    g = build(gpm, graphgen.rmat(scale, seed=scale))
+    print(f"rmat{scale} 5-motifs", flush=True)
+    assert gpm.motif_count_formula(g, 5) == gpm.motif_count_enum(g, 5)
+
+
+def test_formula_route_rejects(gpm):
+    from paper_2011_03135_amd.binding import GpmError
+    g = build(gpm, graphgen.erdos_renyi(30, 0.2, 3))
+    with pytest.raises(GpmError):
+        gpm.motif_count_formula(g, 4)
