@@ -329,17 +329,23 @@ gpm_status gpm_motif_count_enum(const gpm_graph *g, int32_t k, void *d_ws, uint6
  * 2017).  The non-induced count N(P) of every connected 5-vertex pattern --
  * the number of its copies as edge sets -- is obtained, then the induced
  * counts by exact back-substitution through N(P) = sum over H of
- * c(P, H) I(H), c(P, H) the spanning copies of P in H.  Eight N(P) (the
- * 4-star, chair, 5-path, cricket, bull, tadpole, bowtie and dart, whose
- * copies are the most numerous) come from closed forms in local counts:
- * degrees, per-edge triangle counts (Section 5), per-vertex triangle
- * counts, neighbour-degree sums and the number of 4-cycles.  The other
- * thirteen (a two-connected core, at most with one pendant) are counted by
- * the general plan as edge-induced patterns, the 5-clique by the clique
- * kernels.  Writes d_counts (device uint64[22]): the 21 classes in
- * gpm_motif_class_pattern order (the same values as gpm_motif_count_enum),
- * then a status word, 0 when every subtraction stayed non-negative and
- * every count fits 64 bits.  k must be 5 (GPM_UNSUPPORTED otherwise). */
+ * c(P, H) I(H), c(P, H) the spanning copies of P in H.  Fifteen N(P)
+ * (the 4-star, chair, 5-path, cricket, bull, 4-cycle with a pendant,
+ * tadpole, dart, diamond with a pendant at a tip, bowtie, house, 4-clique
+ * with a pendant, three triangles on one edge, a vertex joined to a
+ * 4-path, and a 4-clique with a vertex joined to two of it) come from
+ * closed forms in local counts: degrees, per-edge triangle counts
+ * (Section 5), per-vertex triangle counts, neighbour-degree sums, sums
+ * over the triangles, the 4-cycles and the 4-cliques, and the numbers of
+ * 4-cycles and 4-cliques.  The other six classes (the 5-cycle, K_{2,3}, two
+ * triangles on an edge whose tips share a third neighbour, the wheel, K5
+ * minus an edge and K5), whose induced copies are few, are counted
+ * directly as vertex-induced patterns by the general plan, the 5-clique by
+ * the clique kernels.  Writes d_counts (device uint64[22]): the 21
+ * classes in gpm_motif_class_pattern order (the same values as
+ * gpm_motif_count_enum), then a status word, 0 when every subtraction
+ * stayed non-negative and every count fits 64 bits.  k must be 5
+ * (GPM_UNSUPPORTED otherwise). */
 gpm_status gpm_motif_formula_workspace_bytes(const gpm_graph *g, int32_t k, uint64_t *bytes);
 gpm_status gpm_motif_count_formula(const gpm_graph *g, int32_t k, void *d_ws, uint64_t ws_bytes,
                                    uint64_t *d_counts, void *stream);

@@ -199,12 +199,13 @@ __device__ __forceinline__ uint32_t hash_slot(int32_t z) {
 }
 
 // Stages apex x's in-neighbours y (ranked below x): base[j] = off[y_j],
-// pre[j+1] = prefix of d(y_j), ylist[j] = y_j.  Returns the wedge work.
+// pre[j+1] = prefix of d(y_j), ylist[j] = y_j, arcs[j] = the arc x -> y_j.
+// Returns the wedge work.
 __device__ __forceinline__ int32_t stage_in(const int32_t *__restrict__ off,
                                             const int32_t *__restrict__ adj,
                                             const int32_t *__restrict__ deg, int32_t x, int32_t s,
                                             int32_t dx, int32_t *pre, int32_t *base, int32_t *ylist,
-                                            int32_t &ny) {
+                                            int32_t &ny, int32_t *arcs = nullptr) {
     const int lane = lane_id();
     int32_t carry = 0;
     ny = 0;
@@ -224,6 +225,7 @@ __device__ __forceinline__ int32_t stage_in(const int32_t *__restrict__ off,
             base[p] = off[y];
             pre[p + 1] = carry + inc;
             if (ylist) ylist[p] = y;
+            if (arcs) arcs[p] = s + i;
         }
         carry += __shfl(inc, 63, 64);
         ny += __popcll(mask);
@@ -233,30 +235,63 @@ __device__ __forceinline__ int32_t stage_in(const int32_t *__restrict__ off,
     return carry;
 }
 
-// Light apexes: one wave each, LDS hash z -> count, wedge by wedge.
+// Sums over the 4-cycles, from the wedges once their groups are complete:
+// a wedge x - y - z whose group holds c wedges lies on c - 1 cycles, and
+// each cycle has two wedges (middles y and y') from its apex x to its
+// opposite vertex z, so
+//   sum over cycles of (d_x + d_y + d_z + d_y')  is half the sum over
+//       wedges of (c - 1)(d_x + d_z + 2 d_y)                (cs[0..1], doubled)
+//   sum over cycles of the triangle counts of its four edges  is the sum
+//       over wedges of (c - 1)(T_xy + T_yz)                  (cs[2..3])
+// (tsym: triangle count per arc of the symmetric CSR).
+struct CycleSums {
+    uint64_t deg2 = 0, tri = 0;
+    __device__ __forceinline__ void add(uint32_t c, uint32_t dx, uint32_t dy, uint32_t dz,
+                                        uint32_t txy, uint32_t tyz) {
+        const uint64_t k = c - 1u;
+        deg2 += k * ((uint64_t)dx + dz + 2ull * dy);
+        tri += k * ((uint64_t)txy + tyz);
+    }
+    __device__ __forceinline__ void flush(unsigned long long *cs) {
+        const u128 a = wave_sum_u128((u128)deg2), b = wave_sum_u128((u128)tri);
+        if (lane_id() == 0) {
+            if (a) atomic_add_u128(cs, a);
+            if (b) atomic_add_u128(cs + 2, b);
+        }
+    }
+};
+
+// Light apexes: one wave each, LDS hash z -> count, wedge by wedge.  With
+// CS, a second walk over the apex's wedges adds the cycle sums.
+template <bool CS>
 __global__ void __launch_bounds__(kBlock) k_c4_light(const int32_t *__restrict__ off,
                                                      const int32_t *__restrict__ adj,
                                                      const int32_t *__restrict__ deg,
                                                      const int32_t *__restrict__ adeg,
                                                      const int32_t *__restrict__ list,
                                                      const int32_t *__restrict__ count_p,
-                                                     unsigned long long *out) {
+                                                     unsigned long long *out,
+                                                     const uint32_t *__restrict__ tsym,
+                                                     unsigned long long *cs) {
     __shared__ int32_t s_key[kWPB][kHashSlots];
     __shared__ uint32_t s_cnt[kWPB][kHashSlots];
     __shared__ int32_t s_pre[kWPB][kLightW + 1];
     __shared__ int32_t s_base[kWPB][kLightW];
+    __shared__ int32_t s_arc[CS ? kWPB : 1][CS ? kLightW : 1];
     const int lane = lane_id(), wib = threadIdx.x / kWave;
     int32_t *key = s_key[wib], *pre = s_pre[wib], *base = s_base[wib];
+    int32_t *arcs = CS ? s_arc[wib] : nullptr;
     uint32_t *cnt = s_cnt[wib];
     const int32_t count = *count_p;
     const int64_t wave0 = (int64_t)blockIdx.x * kWPB + wib;
     const int64_t nwaves = (int64_t)gridDim.x * kWPB;
     for (int i = lane; i < kHashSlots; i += kWave) { key[i] = -1; cnt[i] = 0; }
     uint64_t acc = 0;
+    CycleSums sums;
     for (int64_t r = wave0; r < count; r += nwaves) {
         const int32_t x = list[r], s = off[x], dx = off[x + 1] - s;
         int32_t ny;
-        const int32_t W = stage_in(off, adj, deg, x, s, dx, pre, base, nullptr, ny);
+        const int32_t W = stage_in(off, adj, deg, x, s, dx, pre, base, nullptr, ny, arcs);
         for (int32_t qb = 0; qb < W; qb += kWave) {
             const int32_t q = qb + lane;
             if (q < W) {
@@ -281,12 +316,30 @@ __global__ void __launch_bounds__(kBlock) k_c4_light(const int32_t *__restrict__
             }
         }
         wave_sync();
+        if (CS) {
+            for (int32_t qb = 0; qb < W; qb += kWave) {
+                const int32_t q = qb + lane;
+                if (q < W) {
+                    const int32_t j = last_le_i32(pre, ny + 1, q);
+                    const int32_t e = base[j] + (q - pre[j]);
+                    const int32_t z = adj[e];
+                    if (rank_less(adeg[e], z, dx, x)) {
+                        uint32_t h = hash_slot(z);
+                        while (key[h] != z) h = (h + 1) & (kHashSlots - 1);
+                        sums.add(cnt[h], (uint32_t)dx, (uint32_t)(pre[j + 1] - pre[j]),
+                                 (uint32_t)adeg[e], tsym[arcs[j]], tsym[e]);
+                    }
+                }
+            }
+            wave_sync();
+        }
         for (int i = lane; i < kHashSlots; i += kWave)
             if (key[i] != -1) { key[i] = -1; cnt[i] = 0; }
         wave_sync();
     }
     acc = wave_sum(acc);
     if (lane == 0 && acc) atomic_add_u128(out, (u128)acc);
+    if (CS) sums.flush(cs);
 }
 
 // Heavy apexes, counting.  Task (z-part p, apex x), part-major so that the
@@ -340,6 +393,10 @@ __device__ __forceinline__ int32_t seg_of(const int32_t *pre, int32_t lo, int32_
     return lo;
 }
 
+//
+// With CS, a second walk over the task's wedges, once its counters are
+// complete, adds the cycle sums (CycleSums above).
+template <bool CS>
 __global__ void __launch_bounds__(kHeavyNT) k_c4_heavy(const int32_t *__restrict__ off,
                                                        const int32_t *__restrict__ adj,
                                                        const int32_t *__restrict__ adeg,
@@ -347,17 +404,22 @@ __global__ void __launch_bounds__(kHeavyNT) k_c4_heavy(const int32_t *__restrict
                                                        const int32_t *__restrict__ count_p,
                                                        int32_t n, int32_t nparts, int32_t narrow,
                                                        const int2 *__restrict__ seg,
-                                                       uint32_t *cursor, unsigned long long *out) {
+                                                       uint32_t *cursor, unsigned long long *out,
+                                                       const uint32_t *__restrict__ tsym,
+                                                       unsigned long long *cs) {
     constexpr int NW = kHeavyNT / kWave;
     __shared__ uint32_t cnt[kCountWords];
     __shared__ int32_t s_pre[kHeavyNT + 1];
     __shared__ int32_t s_off[kHeavyNT];    // segment start arc minus its pair prefix
     __shared__ int32_t s_sum[NW];
+    __shared__ uint32_t s_dy[CS ? kHeavyNT : 1];    // d(y) of each segment
+    __shared__ uint32_t s_txy[CS ? kHeavyNT : 1];   // triangles on the arc x -> y
     __shared__ uint32_t s_task;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     const int32_t nheavy = *count_p;
     const uint64_t ntasks = (uint64_t)nheavy * (uint64_t)nparts;
     uint64_t acc = 0;
+    CycleSums sums;
     const int32_t zpart = narrow ? 2 * kCountWords : kCountWords;
     for (int i = tid; i < kCountWords; i += kHeavyNT) cnt[i] = 0;
     for (;;) {
@@ -370,6 +432,7 @@ __global__ void __launch_bounds__(kHeavyNT) k_c4_heavy(const int32_t *__restrict
         const int32_t x = list[t % (uint64_t)nheavy];
         const int32_t z0 = part * zpart, z1 = z0 + zpart;
         const int32_t s = off[x], dx = off[x + 1] - s;
+        for (int pass = 0; pass < (CS ? 2 : 1); pass++)
         for (int32_t c0 = 0; c0 < dx; c0 += kHeavyNT) {
             const int32_t i = c0 + tid;
             int32_t len[1] = {0}, start = 0;
@@ -386,6 +449,10 @@ __global__ void __launch_bounds__(kHeavyNT) k_c4_heavy(const int32_t *__restrict
                         const int32_t hi = lo + lower_bound_i32(adj + oy + lo, dy - lo, z1);
                         start = oy + lo;
                         len[0] = hi - lo;
+                    }
+                    if (CS) {
+                        s_dy[tid] = (uint32_t)dy;
+                        s_txy[tid] = tsym[s + i];
                     }
                 }
             }
@@ -408,14 +475,18 @@ __global__ void __launch_bounds__(kHeavyNT) k_c4_heavy(const int32_t *__restrict
                     j = s_pre[w] <= q ? seg_of(s_pre, w, kHeavyNT, q) : seg_of(s_pre, j0, w, q);
                     const int32_t e = s_off[j] + q;
                     const int32_t z = adj[e];
-                    if (rank_less(adeg[e], z, dx, x)) {
-                        // each wedge to z adds the number of earlier ones
+                    const int32_t dz = adeg[e];
+                    if (rank_less(dz, z, dx, x)) {
                         const uint32_t zz = (uint32_t)(z - z0);
-                        if (narrow) {
-                            const uint32_t sh = (zz & 1u) * 16u;
-                            acc += (atomicAdd(&cnt[zz >> 1], 1u << sh) >> sh) & 0xffffu;
+                        const uint32_t sh = narrow ? (zz & 1u) * 16u : 0u;
+                        uint32_t *cw = narrow ? &cnt[zz >> 1] : &cnt[zz];
+                        if (pass == 0) {
+                            // each wedge to z adds the number of earlier ones
+                            acc += narrow ? (atomicAdd(cw, 1u << sh) >> sh) & 0xffffu
+                                          : atomicAdd(cw, 1u);
                         } else {
-                            acc += atomicAdd(&cnt[zz], 1u);
+                            const uint32_t c = narrow ? (*cw >> sh) & 0xffffu : *cw;
+                            sums.add(c, (uint32_t)dx, s_dy[j], (uint32_t)dz, s_txy[j], tsym[e]);
                         }
                     }
                 }
@@ -428,6 +499,7 @@ __global__ void __launch_bounds__(kHeavyNT) k_c4_heavy(const int32_t *__restrict
     }
     acc = wave_sum(acc);
     if (lane == 0 && acc) atomic_add_u128(out, (u128)acc);
+    if (CS) sums.flush(cs);
 }
 
 // --------------------------------------------------------------- listing ---
@@ -752,11 +824,15 @@ gpm_status c4_workspace_bytes(const gpm_graph *g, bool list, uint64_t *bytes) {
 }
 
 // Counting (list == false): adds the number of 4-cycles to out128 (two
-// 64-bit words, zero on entry).  Listing: fills d_result {total, written,
-// checksum} (zeroed here) and d_buf rows (x, y1, z, y2) in cycle order.
+// 64-bit words, zero on entry); with cs (four words, zero on entry) and
+// tsym (triangles per arc of the symmetric CSR) also the cycle sums of
+// CycleSums.  Listing: fills d_result {total, written, checksum} (zeroed
+// here) and d_buf rows (x, y1, z, y2) in cycle order.
 gpm_status c4_run(const gpm_graph *g, bool list, void *ws, uint64_t ws_bytes,
                   unsigned long long *out128, int32_t *d_buf, uint64_t cap,
-                  unsigned long long *d_result, hipStream_t st) {
+                  unsigned long long *d_result, hipStream_t st,
+                  const uint32_t *tsym, unsigned long long *cs) {
+    if (list && cs) return fail(GPM_INVALID_ARGUMENT, "cycle sums are a counting mode");
     C4Ws W = c4_layout(g, list, ws);
     if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
     if (list && g->max_degree > kWedgeCap)
@@ -790,17 +866,29 @@ gpm_status c4_run(const gpm_graph *g, bool list, void *ws, uint64_t ws_bytes,
             hipLaunchKernelGGL(k_c4_seg, dim3(grid_for(n, kWPB, 8)), dim3(kBlock), 0, st, g->off,
                                g->adj, n, cparts, count_zpart(g), W.seg);
         GPM_LAUNCH_CHECK("k_c4_seg");
-        {
-            Span sp("k_c4_heavy", st);
-            hipLaunchKernelGGL(k_c4_heavy, dim3((unsigned)cu_count()), dim3(kHeavyNT), 0, st,
+        if (cs) {
+            Span sp("k_c4_heavy<sums>", st);
+            hipLaunchKernelGGL(k_c4_heavy<true>, dim3((unsigned)cu_count()), dim3(kHeavyNT), 0, st,
                                g->off, g->adj, W.adeg, W.heavy, cnt_heavy, n, cparts,
-                               narrow_counts(g) ? 1 : 0, W.seg, W.ctl + 0, out128);
+                               narrow_counts(g) ? 1 : 0, W.seg, W.ctl + 0, out128, tsym, cs);
+        } else {
+            Span sp("k_c4_heavy", st);
+            hipLaunchKernelGGL(k_c4_heavy<false>, dim3((unsigned)cu_count()), dim3(kHeavyNT), 0, st,
+                               g->off, g->adj, W.adeg, W.heavy, cnt_heavy, n, cparts,
+                               narrow_counts(g) ? 1 : 0, W.seg, W.ctl + 0, out128, nullptr,
+                               nullptr);
         }
         GPM_LAUNCH_CHECK("k_c4_heavy");
-        {
+        if (cs) {
+            Span sp("k_c4_light<sums>", st);
+            hipLaunchKernelGGL(k_c4_light<true>, dim3((unsigned)persistent_blocks(kWPB, 4)),
+                               dim3(kBlock), 0, st, g->off, g->adj, W.deg, W.adeg, W.light,
+                               cnt_light, out128, tsym, cs);
+        } else {
             Span sp("k_c4_light", st);
-            hipLaunchKernelGGL(k_c4_light, dim3((unsigned)persistent_blocks(kWPB, 4)), dim3(kBlock),
-                               0, st, g->off, g->adj, W.deg, W.adeg, W.light, cnt_light, out128);
+            hipLaunchKernelGGL(k_c4_light<false>, dim3((unsigned)persistent_blocks(kWPB, 4)),
+                               dim3(kBlock), 0, st, g->off, g->adj, W.deg, W.adeg, W.light,
+                               cnt_light, out128, nullptr, nullptr);
         }
         GPM_LAUNCH_CHECK("k_c4_light");
         return GPM_OK;

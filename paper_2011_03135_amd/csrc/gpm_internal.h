@@ -163,6 +163,19 @@ __device__ __forceinline__ void atomic_add_u128(unsigned long long *p, unsigned 
     if (hi) atomicAdd(p + 1, hi);
 }
 
+// Sum of a 128-bit value over the 64 lanes of a wave (every lane gets it).
+__device__ __forceinline__ unsigned __int128 wave_sum_u128(unsigned __int128 x) {
+    uint64_t lo = (uint64_t)x, hi = (uint64_t)(x >> 64);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t lo2 = __shfl_xor(lo, o, 64), hi2 = __shfl_xor(hi, o, 64);
+        const uint64_t s = lo + lo2;
+        hi = hi + hi2 + (s < lo ? 1 : 0);
+        lo = s;
+    }
+    return ((unsigned __int128)hi << 64) | lo;
+}
+
 // ------------------------------------------------- LDS membership hash ---
 // Open addressing with linear probing over a power-of-two table of int32
 // keys (-1 = empty) in LDS, multiplicative hashing.  Used to test whether a

@@ -34,25 +34,14 @@ gpm_status triangle_arc_counts(const gpm_graph *g, void *ws, uint64_t ws_bytes, 
 gpm_status c4_workspace_bytes(const gpm_graph *g, bool list, uint64_t *bytes);
 gpm_status c4_run(const gpm_graph *g, bool list, void *ws, uint64_t ws_bytes,
                   unsigned long long *out128, int32_t *d_buf, uint64_t cap,
-                  unsigned long long *d_result, hipStream_t st);
+                  unsigned long long *d_result, hipStream_t st,
+                  const uint32_t *tsym = nullptr, unsigned long long *cs = nullptr);
 
 namespace {
 
 typedef unsigned __int128 u128;
 
 constexpr int kBlock = 256;
-
-__device__ __forceinline__ u128 wave_sum_u128(u128 x) {
-    uint64_t lo = (uint64_t)x, hi = (uint64_t)(x >> 64);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        uint64_t lo2 = __shfl_xor(lo, o, 64), hi2 = __shfl_xor(hi, o, 64);
-        uint64_t s = lo + lo2;
-        hi = hi + hi2 + (s < lo ? 1 : 0);
-        lo = s;
-    }
-    return ((u128)hi << 64) | lo;
-}
 
 __global__ void k_degrees(const int32_t *off, int32_t n, int32_t *deg) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

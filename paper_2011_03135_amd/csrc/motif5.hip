@@ -12,23 +12,38 @@
 // densest class down.  The matrix c is built on the host by brute force over
 // the edge subsets of each class.
 //
-// Eight N(P) have closed forms in local counts: degrees d, per-edge triangle
-// counts T_e (the Section 5 local counts, from the triangle kernels), per
-// vertex t_v = triangles at v, s_v = sum of the neighbours' degrees and
-// q_v = sum of (neighbour degree - 1)^2, and the totals T and N(C4):
+// Fifteen N(P) have closed forms in local counts: degrees d, per-edge
+// triangle counts T_e (the Section 5 local counts, from the triangle
+// kernels), per vertex t_v = triangles at v, s_v = sum of the neighbours'
+// degrees and q_v = sum of (neighbour degree - 1)^2, the totals T, K4 and
+// N(C4), D = sum over edges of C(T_e, 2) (diamonds), two sums over the
+// 4-cycles C (of the degrees of their vertices, of the triangle counts of
+// their edges), two over the triangles and two over the 4-cliques:
 //   star K1,4   sum_v C(d_v, 4)
 //   chair       sum over ordered arcs (c, x) of C(d_c - 1, 2)(d_x - 1) - T_cx (d_c - 2)
 //   5-path      sum_c [(s_c - d_c)^2 - q_c] / 2 - (2 sum_v t_v d_v - 9T) - 4 N(C4)
 //   cricket     sum_c t_c C(d_c - 2, 2)
 //   bull        sum_e T_e [(d_x - 2)(d_y - 2) - (T_e - 1)]
+//   banner      sum_C sum_{v in C} (d_v - 2) - 2D          (4-cycle with a pendant)
 //   tadpole     sum_c t_c (s_c - d_c) - (2 sum_v t_v d_v - 6T) - 2 sum_e T_e (T_e - 1)
-//   bowtie      sum_v C(t_v, 2) - 2 sum_e C(T_e, 2)
 //   dart        sum_e C(T_e, 2)(d_x + d_y - 6)
+//   kite        sum over triangles of sum over their edges e of (T_e - 1) d(opposite vertex)
+//               - 4D - 12 K4                                  (pendant at a diamond's tip)
+//   bowtie      sum_v C(t_v, 2) - 2 sum_e C(T_e, 2)
+//   house       sum_C sum_{e in C} T_e - 4D
+//   K4+pendant  sum over 4-cliques of sum over their vertices of (d_v - 3)
+//   book        sum_e C(T_e, 3)                               (three triangles on an edge)
+//   gem         sum over triangles of sum over their vertices v of (T_vp - 1)(T_vq - 1)
+//               - 12 K4                                       (a vertex joined to a 4-path)
+//   K4+ear      sum over 4-cliques of sum over their edges of (T_e - 2)
+//                                                (a vertex joined to two vertices of a K4)
 // (each derived by counting the choices of the pattern's free vertices
-// around its cut vertex or edge and subtracting the choices that collide).
-// The other thirteen, whose copies are far fewer (a dense core with at most
-// a pendant: the search ends in a population count), are counted by the
-// general plan as edge-induced patterns, K5 by the clique kernels.
+// around a cut vertex, a cut edge, a 4-cycle or a triangle, and subtracting
+// the choices that collide: a chord of a 4-cycle, a fourth vertex closing a
+// K4).  The other six, whose induced copies are far fewer (the 5-cycle,
+// K_{2,3}, two triangles on an edge whose tips share a third neighbour, the
+// wheel, K5 minus an edge and K5), are counted directly as induced
+// patterns: by the general plan, K5 by the clique kernels.
 #include "gpm_internal.h"
 
 #include <algorithm>
@@ -46,7 +61,8 @@ gpm_status triangle_arc_counts(const gpm_graph *g, void *ws, uint64_t ws_bytes, 
 gpm_status c4_workspace_bytes(const gpm_graph *g, bool list, uint64_t *bytes);
 gpm_status c4_run(const gpm_graph *g, bool list, void *ws, uint64_t ws_bytes,
                   unsigned long long *out128, int32_t *d_buf, uint64_t cap,
-                  unsigned long long *d_result, hipStream_t st);
+                  unsigned long long *d_result, hipStream_t st,
+                  const uint32_t *tsym = nullptr, unsigned long long *cs = nullptr);
 uint64_t generic_workspace_bytes(const gpm_graph *g);
 gpm_status generic_count(const gpm_graph *g, const gpm_pattern *p, void *ws, uint64_t ws_bytes,
                          unsigned long long *out, hipStream_t st);
@@ -60,14 +76,14 @@ constexpr int kClasses = 21;
 constexpr int kBlock = 256;
 
 // Classes with a closed form, and the accumulator pair (plus, minus) of each.
-enum Formula : int { F_STAR, F_CHAIR, F_PATH, F_CRICKET, F_BULL, F_TADPOLE, F_BOWTIE, F_DART,
-                     F_COUNT };
-constexpr int kFormulaClass[F_COUNT] = {0, 1, 2, 3, 4, 6, 11, 8};
+enum Formula : int { F_STAR, F_CHAIR, F_PATH, F_CRICKET, F_BULL, F_BANNER, F_TADPOLE, F_DART,
+                     F_KITE, F_BOWTIE, F_HOUSE, F_K4PEND, F_BOOK, F_GEM, F_K4TWO, F_COUNT };
+constexpr int kFormulaClass[F_COUNT] = {0, 1, 2, 3, 4, 5, 6, 8, 9, 11, 12, 13, 14, 15, 17};
 constexpr int kK5Class = 20;
 
 struct Back {
     uint16_t c[kClasses][kClasses];   // c[P][H], spanning copies of P in H
-    int32_t formula_of[kClasses];     // F_* or -1
+    int32_t formula_of[kClasses];     // F_* or -1 (counted directly)
 };
 
 // Accumulators: 2 u64 words per u128.
@@ -76,25 +92,15 @@ enum Acc : int {
     A_MINUS = A_PLUS + 2 * F_COUNT,   // F_COUNT u128: subtracted parts
     A_TRI = A_MINUS + 2 * F_COUNT,    // u64: triangles (from the arc counts)
     A_C4 = A_TRI + 2,                 // u128: 4-cycles (edge sets)
-    A_GEN = A_C4 + 2,                 // kClasses u64: counts of the enumerated classes
-    A_WORDS = A_GEN + kClasses,
+    A_CYC = A_C4 + 2,                 // 2 u128: 4-cycle sums (degrees, doubled; edge triangles)
+    A_K4 = A_CYC + 4,                 // u64: 4-cliques
+    A_DIR = A_K4 + 2,                 // kClasses u64: induced counts of the direct classes
+    A_WORDS = A_DIR + kClasses,
 };
 
 __device__ __forceinline__ u128 binom2(uint64_t n) { return n < 2 ? 0 : (u128)n * (n - 1) / 2; }
 __device__ __forceinline__ u128 binom4(uint64_t n) {
     return n < 4 ? 0 : (u128)n * (n - 1) / 2 * (n - 2) / 3 * (n - 3) / 4;
-}
-
-__device__ __forceinline__ u128 wave_sum_u128(u128 x) {
-    uint64_t lo = (uint64_t)x, hi = (uint64_t)(x >> 64);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint64_t lo2 = __shfl_xor(lo, o, 64), hi2 = __shfl_xor(hi, o, 64);
-        const uint64_t s = lo + lo2;
-        hi = hi + hi2 + (s < lo ? 1 : 0);
-        lo = s;
-    }
-    return ((u128)hi << 64) | lo;
 }
 
 // Per vertex: t_v from the arc triangle counts (each arc adds its count to
@@ -178,9 +184,14 @@ __global__ void __launch_bounds__(kBlock) k_f5_edge(const int32_t *__restrict__ 
             plus[F_BULL] += (u128)T * ((dx - 2) * (dy - 2));
             minus[F_BULL] += (u128)T * (T - 1);
             minus[F_TADPOLE] += (u128)2 * T * (T - 1);
-            minus[F_BOWTIE] += 2 * binom2(T);
+            const u128 diamonds = binom2(T);
+            minus[F_BOWTIE] += 2 * diamonds;
+            minus[F_BANNER] += 2 * diamonds;
+            minus[F_HOUSE] += 4 * diamonds;
+            minus[F_KITE] += 4 * diamonds;
             // two triangles on the edge put both ends at degree >= 3
-            if (T >= 2) plus[F_DART] += binom2(T) * (dx + dy - 6);
+            if (T >= 2) plus[F_DART] += diamonds * (dx + dy - 6);
+            if (T >= 3) plus[F_BOOK] += diamonds * (T - 2) / 3;
         }
     }
 #pragma unroll
@@ -190,6 +201,141 @@ __global__ void __launch_bounds__(kBlock) k_f5_edge(const int32_t *__restrict__ 
             if (p) atomic_add_u128(acc + A_PLUS + 2 * f, p);
             if (mm) atomic_add_u128(acc + A_MINUS + 2 * f, mm);
         }
+    }
+}
+
+// tsym[a] = triangles on the edge of arc a of the symmetric CSR, from the
+// counts per arc of the DAG (one thread per DAG arc, a binary search in
+// each end's row).
+__global__ void __launch_bounds__(kBlock) k_tsym(const int32_t *__restrict__ off,
+                                                 const int32_t *__restrict__ adj,
+                                                 const int32_t *__restrict__ dag_src,
+                                                 const int32_t *__restrict__ dag_adj,
+                                                 const uint32_t *__restrict__ te, int64_t m,
+                                                 uint32_t *__restrict__ tsym) {
+    auto find = [&](int32_t u, int32_t v) {
+        int32_t lo = off[u], hi = off[u + 1];
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (adj[mid] < v) lo = mid + 1; else hi = mid;
+        }
+        return lo;
+    };
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = dag_src[e], v = dag_adj[e];
+        const uint32_t c = te[e];
+        tsym[find(u, v)] = c;
+        tsym[find(v, u)] = c;
+    }
+}
+
+// The triangle terms of the kite and the gem.  One wave per DAG arc
+// u -> v: lanes take w in N+(v) and look it up in N+(u) (rows ascending),
+// so each triangle u -> v -> w, u -> w is met once, with its three arcs.
+__global__ void __launch_bounds__(kBlock) k_f5_tri(const int32_t *__restrict__ off,
+                                                   const int32_t *__restrict__ dag_off,
+                                                   const int32_t *__restrict__ dag_src,
+                                                   const int32_t *__restrict__ dag_adj,
+                                                   const uint32_t *__restrict__ te, int64_t m,
+                                                   unsigned long long *acc) {
+    const int lane = lane_id();
+    const int64_t wave0 = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+    uint64_t kite = 0, gem = 0;
+    for (int64_t e = wave0; e < m; e += nwaves) {
+        const int32_t u = dag_src[e], v = dag_adj[e];
+        const uint32_t t_uv = te[e];
+        if (t_uv == 0) continue;   // wave-uniform
+        const int32_t su = dag_off[u], du = dag_off[u + 1] - su;
+        const int32_t sv = dag_off[v], dv = dag_off[v + 1] - sv;
+        const uint64_t deg_u = (uint64_t)(off[u + 1] - off[u]);
+        const uint64_t deg_v = (uint64_t)(off[v + 1] - off[v]);
+        for (int32_t i = lane; i < dv; i += kWave) {
+            const int32_t w = dag_adj[sv + i];
+            int32_t lo = 0, hi = du;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (dag_adj[su + mid] < w) lo = mid + 1; else hi = mid;
+            }
+            if (lo < du && dag_adj[su + lo] == w) {
+                const uint64_t a = t_uv - 1u, b = te[su + lo] - 1u, c = te[sv + i] - 1u;
+                const uint64_t deg_w = (uint64_t)(off[w + 1] - off[w]);
+                // edges uv, uw, vw; opposite vertices w, v, u
+                kite += a * deg_w + b * deg_v + c * deg_u;
+                // centres u (edges uv, uw), v (uv, vw), w (uw, vw)
+                gem += a * b + a * c + b * c;
+            }
+        }
+    }
+    const u128 k = wave_sum_u128((u128)kite), g = wave_sum_u128((u128)gem);
+    if (lane == 0) {
+        if (k) atomic_add_u128(acc + A_PLUS + 2 * F_KITE, k);
+        if (g) atomic_add_u128(acc + A_PLUS + 2 * F_GEM, g);
+    }
+}
+
+// The 4-clique terms.  One wave per DAG arc u -> v: lanes find the w of
+// N+(v) in N+(u) (the triangles u, v, w); for each such w in turn, lanes
+// take x in N+(w) and look it up in N+(u) and N+(v).  Each 4-clique
+// u -> v -> w -> x is met once, with its six arcs.
+__global__ void __launch_bounds__(kBlock) k_f5_k4(const int32_t *__restrict__ off,
+                                                  const int32_t *__restrict__ dag_off,
+                                                  const int32_t *__restrict__ dag_src,
+                                                  const int32_t *__restrict__ dag_adj,
+                                                  const uint32_t *__restrict__ te, int64_t m,
+                                                  unsigned long long *acc) {
+    const int lane = lane_id();
+    const int64_t wave0 = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+    auto find = [&](int32_t s0, int32_t len, int32_t x) {   // index in the row, or -1
+        int32_t lo = 0, hi = len;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (dag_adj[s0 + mid] < x) lo = mid + 1; else hi = mid;
+        }
+        return lo < len && dag_adj[s0 + lo] == x ? lo : -1;
+    };
+    uint64_t pend = 0, two = 0;
+    for (int64_t e = wave0; e < m; e += nwaves) {
+        const int32_t u = dag_src[e], v = dag_adj[e];
+        if (te[e] < 2) continue;   // wave-uniform: an edge of a 4-clique has two triangles
+        const int32_t su = dag_off[u], du = dag_off[u + 1] - su;
+        const int32_t sv = dag_off[v], dv = dag_off[v + 1] - sv;
+        const uint64_t deg_uv = (uint64_t)(off[u + 1] - off[u]) + (uint64_t)(off[v + 1] - off[v]);
+        for (int32_t i0 = 0; i0 < dv; i0 += kWave) {
+            const int32_t i = i0 + lane;
+            int32_t iw = -1, w = -1;
+            if (i < dv) {
+                w = dag_adj[sv + i];
+                iw = find(su, du, w);
+            }
+            uint64_t mask = __ballot(iw >= 0);
+            while (mask) {
+                const int src = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                const int32_t ww = __shfl(w, src, 64), iu_w = __shfl(iw, src, 64);
+                const int32_t iv_w = i0 + src;
+                const int32_t sw = dag_off[ww], dw = dag_off[ww + 1] - sw;
+                const uint64_t t3 = (uint64_t)te[e] + te[su + iu_w] + te[sv + iv_w];
+                const uint64_t deg_w = (uint64_t)(off[ww + 1] - off[ww]);
+                for (int32_t j = lane; j < dw; j += kWave) {
+                    const int32_t x = dag_adj[sw + j];
+                    const int32_t ixu = find(su, du, x);
+                    if (ixu < 0) continue;
+                    const int32_t ixv = find(sv, dv, x);
+                    if (ixv < 0) continue;
+                    const uint64_t deg_x = (uint64_t)(off[x + 1] - off[x]);
+                    pend += deg_uv + deg_w + deg_x - 12u;
+                    two += t3 + te[su + ixu] + te[sv + ixv] + te[sw + j] - 12u;
+                }
+            }
+        }
+    }
+    const u128 a = wave_sum_u128((u128)pend), b = wave_sum_u128((u128)two);
+    if (lane == 0) {
+        if (a) atomic_add_u128(acc + A_PLUS + 2 * F_K4PEND, a);
+        if (b) atomic_add_u128(acc + A_PLUS + 2 * F_K4TWO, b);
     }
 }
 
@@ -205,29 +351,44 @@ __global__ void k_f5_combine(const unsigned long long *acc, Back B, unsigned lon
     unsigned long long bad = 0;
     const u128 T = (u128)acc[A_TRI];
     const u128 nc4 = load128(acc + A_C4);
+    const u128 cyc_deg2 = load128(acc + A_CYC), cyc_tri = load128(acc + A_CYC + 2);
+    const u128 k4 = (u128)acc[A_K4];
+    if (cyc_deg2 & 1) bad |= 1;   // twice a sum
     u128 N[kClasses];
     for (int h = 0; h < kClasses; h++) {
         const int f = B.formula_of[h];
         if (f < 0) {
-            N[h] = (u128)acc[A_GEN + h];
+            N[h] = 0;
             continue;
         }
         u128 p = load128(acc + A_PLUS + 2 * f), mm = load128(acc + A_MINUS + 2 * f);
-        // the global terms of the 5-path and the tadpole
+        // the global terms
         if (f == F_PATH) {
             p += 9 * T;
             mm += 4 * nc4;
         }
         if (f == F_TADPOLE) p += 6 * T;
+        if (f == F_BANNER) {
+            p += cyc_deg2 / 2;
+            mm += 8 * nc4;
+        }
+        if (f == F_HOUSE) p += cyc_tri;
+        if (f == F_KITE || f == F_GEM) mm += 12 * k4;
         if (p < mm) bad |= 1;
         N[h] = p - mm;
     }
+    // densest first: a direct class is its count, a formula class its N
+    // minus the copies inside denser induced subgraphs
     u128 I[kClasses];
     for (int h = kClasses - 1; h >= 0; h--) {
-        u128 sub = 0;
-        for (int k = h + 1; k < kClasses; k++) sub += (u128)B.c[h][k] * I[k];
-        if (N[h] < sub) bad |= 1;
-        I[h] = N[h] - sub;
+        if (B.formula_of[h] < 0) {
+            I[h] = (u128)acc[A_DIR + h];
+        } else {
+            u128 sub = 0;
+            for (int k = h + 1; k < kClasses; k++) sub += (u128)B.c[h][k] * I[k];
+            if (N[h] < sub) bad |= 1;
+            I[h] = N[h] - sub;
+        }
         if (I[h] >> 64) bad |= 2;
         out[h] = (unsigned long long)I[h];
     }
@@ -311,7 +472,7 @@ const Back &back_matrix() {
 
 struct F5Ws {
     unsigned long long *acc, *t2;
-    uint32_t *te;
+    uint32_t *te, *tsym;
     void *shared;
     uint64_t shared_bytes, bytes;
 };
@@ -322,11 +483,14 @@ F5Ws f5_layout(const gpm_graph *g, void *base) {
     W.acc = c.take<unsigned long long>(A_WORDS);
     W.t2 = c.take<unsigned long long>((uint64_t)g->n + 1);
     W.te = c.take<uint32_t>((uint64_t)g->m + 1);
+    W.tsym = c.take<uint32_t>(2 * (uint64_t)g->m + 1);
     uint64_t b3 = 0, b5 = 0, bc4 = 0;
+    uint64_t b4 = 0;
     clique_workspace_bytes(g, 3, false, &b3);
+    clique_workspace_bytes(g, 4, false, &b4);
     clique_workspace_bytes(g, 5, false, &b5);
     c4_workspace_bytes(g, false, &bc4);
-    W.shared_bytes = std::max({b3, b5, bc4, generic_workspace_bytes(g)});
+    W.shared_bytes = std::max({b3, b4, b5, bc4, generic_workspace_bytes(g)});
     W.shared = c.take<char>(W.shared_bytes);
     W.bytes = c.used;
     return W;
@@ -367,25 +531,34 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
                                g->dag_src, g->dag_adj, W.te, m, W.t2);
             hipLaunchKernelGGL(k_f5_edge, dim3(grid_for(m, kBlock, 8)), dim3(kBlock), 0, st,
                                g->off, g->dag_src, g->dag_adj, W.te, m, W.acc);
+            hipLaunchKernelGGL(k_tsym, dim3(grid_for(m, kBlock, 8)), dim3(kBlock), 0, st, g->off,
+                               g->adj, g->dag_src, g->dag_adj, W.te, m, W.tsym);
+            hipLaunchKernelGGL(k_f5_tri, dim3(grid_for(m, kBlock / kWave, 16)), dim3(kBlock), 0,
+                               st, g->off, g->dag_off, g->dag_src, g->dag_adj, W.te, m, W.acc);
+            hipLaunchKernelGGL(k_f5_k4, dim3(grid_for(m, kBlock / kWave, 16)), dim3(kBlock), 0,
+                               st, g->off, g->dag_off, g->dag_src, g->dag_adj, W.te, m, W.acc);
         }
         hipLaunchKernelGGL(k_f5_vertex, dim3(grid_for(n, kBlock / kWave, 8)), dim3(kBlock), 0,
                            st, g->off, g->adj, n, W.t2, W.acc);
     }
     GPM_LAUNCH_CHECK("k_f5_local");
-    // 4-cycles (edge sets), for the 5-path
-    rc = c4_run(g, false, W.shared, W.shared_bytes, W.acc + A_C4, nullptr, 0, nullptr, st);
+    // 4-cycles (edge sets) and the sums over them
+    rc = c4_run(g, false, W.shared, W.shared_bytes, W.acc + A_C4, nullptr, 0, nullptr, st,
+                W.tsym, W.acc + A_CYC);
     if (rc) return rc;
-    // the enumerated classes: K5 by the clique kernels, the rest by the
-    // general plan as edge-induced patterns
+    rc = clique_run(g, 4, false, W.shared, W.shared_bytes, W.acc + A_K4, nullptr, 0, nullptr, st);
+    if (rc) return rc;
+    // the direct classes: K5 by the clique kernels, the rest by the general
+    // plan as vertex-induced patterns
     for (int h = 0; h < kClasses; h++) {
         if (B.formula_of[h] >= 0) continue;
-        unsigned long long *slot = W.acc + A_GEN + h;
+        unsigned long long *slot = W.acc + A_DIR + h;
         if (h == kK5Class) {
             rc = clique_run(g, 5, false, W.shared, W.shared_bytes, slot, nullptr, 0, nullptr, st);
         } else {
             gpm_pattern p;
             motif_class_pattern(5, h, &p);
-            p.flags = GPM_EDGE_INDUCED;
+            p.flags = GPM_VERTEX_INDUCED;
             rc = generic_count(g, &p, W.shared, W.shared_bytes, slot, st);
         }
         if (rc) return rc;

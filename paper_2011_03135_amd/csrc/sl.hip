@@ -25,7 +25,8 @@ gpm_status triangle_arc_counts(const gpm_graph *g, void *ws, uint64_t ws_bytes, 
 gpm_status c4_workspace_bytes(const gpm_graph *g, bool list, uint64_t *bytes);
 gpm_status c4_run(const gpm_graph *g, bool list, void *ws, uint64_t ws_bytes,
                   unsigned long long *out128, int32_t *d_buf, uint64_t cap,
-                  unsigned long long *d_result, hipStream_t st);
+                  unsigned long long *d_result, hipStream_t st,
+                  const uint32_t *tsym = nullptr, unsigned long long *cs = nullptr);
 
 namespace {
 

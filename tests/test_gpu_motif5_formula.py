@@ -78,3 +78,25 @@ def test_formula_route_rejects(gpm):
     g = build(gpm, graphgen.erdos_renyi(30, 0.2, 3))
     with pytest.raises(GpmError):
         gpm.motif_count_formula(g, 4)
+
+
+def test_formula_route_wide_counters(gpm):
+    """Two vertices of degree above 65535 (two stars with adjacent centres)
+    next to K_{3,300}: the 4-cycle counters and their cycle sums run with
+    32-bit counters.  Closed forms: a centre with its neighbours gives the
+    4-stars, a centre with two of its leaves and one of the other's gives
+    the chairs, K_{3,300} adds 3 C(300, 4) 4-stars and 3 C(300, 3) + C(300, 2)
+    copies of K_{2,3}."""
+    a = b = 70000
+    s1, s2 = graphgen.star_graph(a), graphgen.star_graph(b)
+    kb = graphgen.complete_bipartite(3, 300)
+    two = graphgen.disjoint_union([s1, s2, kb])
+    # join the two centres (vertex 0 of each star)
+    e = graphgen.EdgeList(two.n, np.concatenate([two.u, np.array([0], np.int32)]),
+                          np.concatenate([two.v, np.array([s1.n], np.int32)]), "double_star")
+    g = build(gpm, e)
+    want = [0] * 21
+    want[0] = comb(a + 1, 4) + comb(b + 1, 4) + 3 * comb(300, 4)
+    want[1] = comb(a, 2) * b + comb(b, 2) * a
+    want[10] = 3 * comb(300, 3) + comb(300, 2)
+    assert gpm.motif_count_formula(g, 5) == want
