@@ -632,12 +632,13 @@ def local_graph_leg(gpm, torch, scale, reps=3):
     return res
 
 
-def motif_enum_leg(gpm, torch, scale4=12, scale5=10, reps=3):
+def motif_enum_leg(gpm, torch, scale4=12, scale5=10, reps=3, enum5_large=False):
     """Pattern-oblivious motif counting (vertex extension of canonical
     embeddings, connectivity codes; no counting formulas): the 4-motifs of
     RMAT-`scale4` against the local-count route's time for the same six
     counts, and the 21 5-motifs of RMAT-`scale5` against the formula route
-    (which also runs on RMAT-`scale4`)."""
+    (which also runs on RMAT-`scale4`; with `enum5_large`, one enumeration
+    call there too, about 5 s)."""
     import graphgen
 
     def timed(fn):
@@ -671,17 +672,27 @@ def motif_enum_leg(gpm, torch, scale4=12, scale5=10, reps=3):
     run5 = lambda: gpm.motif_count_enum(g5, 5, ws=ws5)   # noqa: E731
     c5, ms5 = timed(run5)
     c5_off, ms5_off = without_map(run5)
-    # the formula route for the same 21 counts (local counts for the eight
-    # most numerous classes, the general plan for the rest, back-substitution)
+    # the formula route for the same 21 counts (closed forms in local counts
+    # for fifteen classes, the general plan for six, back-substitution)
     wsf = torch.empty(gpm.motif_formula_workspace_bytes(g5, 5), dtype=torch.uint8, device="cuda")
     f5, msf = timed(lambda: gpm.motif_count_formula(g5, 5, ws=wsf))
-    e12 = graphgen.rmat(scale4, seed=scale4)
-    g12 = gpm.Graph.build(e12.n, torch.from_numpy(e12.u).cuda(), torch.from_numpy(e12.v).cuda())
-    wsf12 = torch.empty(gpm.motif_formula_workspace_bytes(g12, 5), dtype=torch.uint8,
+    wsf12 = torch.empty(gpm.motif_formula_workspace_bytes(g, 5), dtype=torch.uint8,
                         device="cuda")
-    f12, msf12 = timed(lambda: gpm.motif_count_formula(g12, 5, ws=wsf12))
+    f12, msf12 = timed(lambda: gpm.motif_count_formula(g, 5, ws=wsf12))
+    large = {"ms": msf12, "subgraphs_per_sec": sum(f12) / (msf12 * 1e-3), "counts": f12}
+    if enum5_large:
+        del wsf12
+        ws12 = torch.empty(gpm.motif_enum_workspace_bytes(g, 5), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c12 = gpm.motif_count_enum(g, 5, ws=ws12)
+        torch.cuda.synchronize()
+        large["enumeration_ms_one_call"] = (time.perf_counter() - t0) * 1e3
+        large["enumeration_equals_formula"] = c12 == f12
+        large["formula_speedup"] = large["enumeration_ms_one_call"] / msf12
     return {"workload": f"rmat{scale4} 4-motifs and rmat{scale5} 5-motifs by enumeration "
-                        f"(k_motif_enum) vs the 4-motif local-count route",
+                        f"(k_motif_enum) vs the 4-motif local-count route and the 5-motif "
+                        f"formula route",
             "motif4": {"counts": c4, "equals_local_count_route": c4 == lc4, "ms": ms4,
                        "subgraphs_per_sec": sum(c4) / (ms4 * 1e-3),
                        "ms_without_connectivity_map": ms4_off, "same_without_map": c4 == c4_off,
@@ -691,8 +702,7 @@ def motif_enum_leg(gpm, torch, scale4=12, scale5=10, reps=3):
                        "same_without_map": c5 == c5_off,
                        "formula_route_ms": msf, "formula_equals_enumeration": f5 == c5,
                        "formula_speedup": ms5 / msf},
-            f"motif5_formula_rmat{scale4}": {"ms": msf12, "subgraphs_per_sec": sum(f12) / (msf12 * 1e-3),
-                                             "counts": f12}}
+            f"motif5_formula_rmat{scale4}": large}
 
 
 # The paper's own CPU figures (Sec. 6: input-graph table, TC and k-clique
@@ -757,6 +767,9 @@ def main():
                     help="time only the local-graph ablation leg (for kernel traces) and exit")
     ap.add_argument("--motif-enum-only", action="store_true",
                     help="time only the pattern-oblivious motif leg (for kernel traces) and exit")
+    ap.add_argument("--enum5-large", action="store_true",
+                    help="with --motif-enum-only: also time one 5-motif enumeration of "
+                         "RMAT-12 (about 5 s) against the formula route")
     ap.add_argument("--motif-only", action="store_true",
                     help="time only the RMAT-18 motif and listing leg (for kernel traces) and exit")
     ap.add_argument("--no-motif", action="store_true")
@@ -798,7 +811,8 @@ def main():
         print(json.dumps({"local_graph_ablation": local_graph_leg(gpm, torch, 14)}))
         return
     if args.motif_enum_only:
-        print(json.dumps({"motif_enumeration": motif_enum_leg(gpm, torch)}))
+        print(json.dumps({"motif_enumeration": motif_enum_leg(gpm, torch,
+                                                              enum5_large=args.enum5_large)}))
         return
     e = graphgen.rmat(args.scale, seed=args.scale)
     u = torch.from_numpy(e.u).to(dev)
