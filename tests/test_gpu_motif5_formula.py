@@ -100,3 +100,14 @@ def test_formula_route_wide_counters(gpm):
     want[1] = comb(a, 2) * b + comb(b, 2) * a
     want[10] = 3 * comb(300, 3) + comb(300, 2)
     assert gpm.motif_count_formula(g, 5) == want
+
+
+def test_formula_route_core_orientation(gpm):
+    """Under the core-value orientation (a different DAG: other triangle
+    arcs, other 4-clique roots) the formula route gives the same counts."""
+    g = build(gpm, graphgen.rmat(10, seed=10))
+    want = gpm.motif_count_formula(g, 5)
+    g.orient(gpm.ORIENT_CORE)
+    assert gpm.motif_count_formula(g, 5) == want
+    g.orient(gpm.ORIENT_DEGREE)
+    assert gpm.motif_count_formula(g, 5) == want
