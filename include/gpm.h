@@ -216,10 +216,10 @@ void gpm_graph_release(gpm_graph *g);
  * counts do not depend on the orientation.  d_core (device int32[n], may be
  * NULL) receives the core numbers; they are computed (for d_core) under
  * either order.  d_scratch is only used during the call; the call
- * synchronises the stream (the peeling reads its counters about once per
- * level, through a 64-byte pinned host buffer the first call allocates and
- * the process keeps).  Must not run while other work on the same graph is
- * in flight. */
+ * synchronises the stream (the peeling runs as device steps queued 32 at a
+ * time, and the host reads the peeling state after each batch through a
+ * 64-byte pinned host buffer the first call allocates and the process
+ * keeps).  Must not run while other work on the same graph is in flight. */
 #define GPM_ORIENT_DEGREE 1
 #define GPM_ORIENT_CORE   2
 gpm_status gpm_graph_orient_bytes(const gpm_graph *g, uint64_t *scratch_bytes);
