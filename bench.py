@@ -714,6 +714,43 @@ def motif_enum_leg(gpm, torch, scale4=12, scale5=10, reps=3, enum5_large=False):
             f"motif5_formula_rmat{scale4}": large}
 
 
+def tune_leg(gpm, torch, g, pats, ks, skip, reps=5):
+    """Per-graph tuning of the plain path's task granularity (untimed set-up,
+    once per graph): gpm_graph_autotune on the workload's graph, then each
+    clique count timed under the default and the chosen setting."""
+    default = g.tuning()
+    res = {"default": default}
+    if skip:
+        res["chosen"] = default
+        return res
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chosen = g.autotune()
+    torch.cuda.synchronize()
+    res["autotune_ms"] = (time.perf_counter() - t0) * 1e3
+    res["chosen"] = chosen
+
+    def per_count(t):
+        g.set_tuning(**t)
+        out = {}
+        for k, p in zip(ks, pats):
+            c = gpm.count(g, p)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(reps):
+                c = gpm.count(g, p)
+            torch.cuda.synchronize()
+            out[f"clique{k}"] = {"count": c, "ms": (time.perf_counter() - t1) * 1e3 / reps}
+        return out
+
+    res["ms_default"] = per_count(default)
+    res["ms_chosen"] = per_count(chosen)
+    res["same_counts"] = all(res["ms_default"][x]["count"] == res["ms_chosen"][x]["count"]
+                             for x in res["ms_default"])
+    g.set_tuning(**chosen)
+    return res
+
+
 # The paper's own CPU figures (Sec. 6: input-graph table, TC and k-clique
 # tables), context only: real graphs, another machine, no RMAT.  #E counts
 # arcs, so undirected edges/s = (#E / 2) / time.
@@ -758,6 +795,8 @@ def main():
     ap.add_argument("--cpu-fraction", type=int, default=48,
                     help="the CPU baseline times every F-th root")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default task granularity instead of tuning it on the graph")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=20000)
     ap.add_argument("--plain-graphs", type=int, default=2000,
@@ -835,16 +874,19 @@ def main():
     m = g0.m
     off_h = g0.csr()[0].cpu().numpy().astype(np.int64)
     adj_h = g0.csr()[1].cpu().numpy()
+    out = torch.zeros(len(ks), dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    tuning = tune_leg(gpm, torch, g0, pats, ks, args.no_autotune)
+    # the tuning can shrink the triangle chunks: size the workspace after it
     wsb = max([gpm.workspace_bytes(g0, p) for p in pats]
               + [gpm.binding.clique_counts_workspace_bytes(g0, args.kmax)])
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
-    out = torch.zeros(len(ks), dtype=torch.int64, device=dev)
-    stream = torch.cuda.current_stream()
 
     def step():
         # the step: device CSR build + orientation, then every clique count of
-        # the workload in one local-graph pass
+        # the workload in one local-graph pass (under the graph's tuning)
         g = gpm.Graph.build(e.n, u, v, storage=storage, scratch=scratch)
+        g.set_tuning(**tuning["chosen"])
         if args.kmax >= 4:
             gpm.clique_counts(g, args.kmax, ws=ws, out=out)
         else:
@@ -877,6 +919,7 @@ def main():
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
         ev[0].record(stream)
         g = gpm.Graph.build(e.n, u, v, storage=storage, scratch=scratch)
+        g.set_tuning(**tuning["chosen"])
         ev[1].record(stream)
         for i, p in enumerate(pats):
             gpm.count(g, p, ws=ws, out=sep[i:i + 1])
@@ -931,6 +974,7 @@ def main():
         "phases_ms": {k: round(x, 4) for k, x in phases.items()},
         "roofline": roof,
         "phase_rooflines": phase_roof,
+        "tuning": tuning,
         "paper_context": paper_context(),
     }
     if not args.no_batch:

@@ -226,6 +226,48 @@ gpm_status gpm_graph_orient_bytes(const gpm_graph *g, uint64_t *scratch_bytes);
 gpm_status gpm_graph_orient(gpm_graph *g, int32_t order, void *d_scratch, uint64_t scratch_bytes,
                             int32_t *d_core, void *stream);
 
+/* Task granularity of the plain path, kept per graph handle (Section 4.1
+ * splits the work into tasks and leaves their size open).  Triangle
+ * counting (and the per-edge triangle counts of local counting) splits the
+ * (root, out-neighbour) pair space of each out-degree class, (1, 64],
+ * (64, 256] and (256, 1024], into chunks of tc_tau pairs that
+ * cu_count * tc_blocks_per_cu persistent workgroups take from an atomic
+ * cursor; 5-clique counting splits each root of out-degree above 256 into
+ * tasks of about lg5_slice local triangles; k-cliques (k >= 4) at roots of
+ * out-degree up to 64 are counted a wave per root, roots dealt round robin
+ * to cu_count * clique_wave_blocks_per_cu one-wave workgroups.  Counts never
+ * depend on these.  A new handle starts at tc_tau = {8192, 16384, 65536},
+ * tc_blocks_per_cu = {32, 8, 4}, clique_wave_blocks_per_cu = 32,
+ * lg5_slice = 2^20.  Workspace sizes depend on tc_tau: query
+ * them after changing it (a workspace sized before a smaller tc_tau gives
+ * GPM_OUT_OF_MEMORY). */
+typedef struct gpm_tuning {
+    int64_t tc_tau[3];            /* pairs per chunk, [2048, 2^24] */
+    int32_t tc_blocks_per_cu[3];  /* workgroups per CU, [1, 64] */
+    int32_t clique_wave_blocks_per_cu;   /* [8, 1024] */
+    int64_t lg5_slice;            /* local triangles per task, [2^14, 2^28] */
+} gpm_tuning;
+
+/* Host only.  set: GPM_INVALID_ARGUMENT for a value outside its range (the
+ * handle keeps its tuning). */
+gpm_status gpm_graph_get_tuning(const gpm_graph *g, gpm_tuning *t);
+gpm_status gpm_graph_set_tuning(gpm_graph *g, const gpm_tuning *t);
+
+/* Autotuner: times triangle counting, 4-clique counting and (when the graph
+ * has roots of out-degree above 256) 5-clique counting on g under candidate
+ * settings, walking the knobs one at a time (each tc_tau x4, x2, /2, /4,
+ * each tc_blocks_per_cu x2, /2, two passes; clique_wave_blocks_per_cu x4,
+ * x2, /2; lg5_slice x4, x2, /2, /4) and
+ * keeping a change when it is at least 3% faster (median of three calls
+ * after a warm-up, HIP events on the stream).  Stores the result in the
+ * handle and, when chosen is not NULL, in *chosen.  d_ws: at least
+ * gpm_graph_autotune_bytes bytes, 256-byte aligned; the call synchronises
+ * the stream.  Must not run while other work on the same graph is in
+ * flight. */
+gpm_status gpm_graph_autotune_bytes(const gpm_graph *g, uint64_t *bytes);
+gpm_status gpm_graph_autotune(gpm_graph *g, void *d_ws, uint64_t ws_bytes, void *stream,
+                              gpm_tuning *chosen);
+
 /* ------------------------------------------------- counting, listing --- */
 
 /* Workspace needed by gpm_count / gpm_list for pattern p on graph g. */

@@ -32,6 +32,17 @@ class Pattern(ctypes.Structure):
                 ("edges", (ctypes.c_int32 * 2) * 36), ("flags", ctypes.c_uint32)]
 
 
+class Tuning(ctypes.Structure):
+    """gpm_tuning: task granularity of the plain path (per graph handle)."""
+    _fields_ = [("tc_tau", ctypes.c_int64 * 3), ("tc_blocks_per_cu", ctypes.c_int32 * 3),
+                ("clique_wave_blocks_per_cu", ctypes.c_int32), ("lg5_slice", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {"tc_tau": list(self.tc_tau), "tc_blocks_per_cu": list(self.tc_blocks_per_cu),
+                "clique_wave_blocks_per_cu": int(self.clique_wave_blocks_per_cu),
+                "lg5_slice": int(self.lg5_slice)}
+
+
 class _GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("max_degree", ctypes.c_int32),
                 ("m", ctypes.c_int64), ("max_out_degree", ctypes.c_int32),
@@ -82,6 +93,10 @@ def load():
         "gpm_motif_count": ([P, i32, P, u64, P, P], i32),
         "gpm_graph_orient_bytes": ([P, P], i32),
         "gpm_graph_orient": ([P, i32, P, u64, P, P], i32),
+        "gpm_graph_get_tuning": ([P, P], i32),
+        "gpm_graph_set_tuning": ([P, P], i32),
+        "gpm_graph_autotune_bytes": ([P, P], i32),
+        "gpm_graph_autotune": ([P, P, u64, P, P], i32),
         "gpm_motif_classes": ([i32], i32),
         "gpm_motif_class_pattern": ([i32, i32, P], i32),
         "gpm_motif_enum_workspace_bytes": ([P, i32, P], i32),
@@ -266,6 +281,40 @@ class Graph:
         self.max_out_degree = info.max_out_degree
         self._info = info
         return core[:self.n] if core is not None else None
+
+    def tuning(self):
+        """gpm_graph_get_tuning -> dict (tc_tau, tc_blocks_per_cu,
+        clique_wave_blocks_per_cu, lg5_slice)."""
+        t = Tuning()
+        _check(load().gpm_graph_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, tc_tau=None, tc_blocks_per_cu=None, clique_wave_blocks_per_cu=None,
+                   lg5_slice=None):
+        """gpm_graph_set_tuning; unnamed knobs keep their values."""
+        t = Tuning()
+        _check(load().gpm_graph_get_tuning(self._h, ctypes.byref(t)))
+        if tc_tau is not None:
+            t.tc_tau = (ctypes.c_int64 * 3)(*[int(x) for x in tc_tau])
+        if tc_blocks_per_cu is not None:
+            t.tc_blocks_per_cu = (ctypes.c_int32 * 3)(*[int(x) for x in tc_blocks_per_cu])
+        if clique_wave_blocks_per_cu is not None:
+            t.clique_wave_blocks_per_cu = int(clique_wave_blocks_per_cu)
+        if lg5_slice is not None:
+            t.lg5_slice = int(lg5_slice)
+        _check(load().gpm_graph_set_tuning(self._h, ctypes.byref(t)))
+
+    def autotune(self, stream=None, ws=None):
+        """gpm_graph_autotune: picks the tuning for this graph by timing it;
+        returns the chosen tuning (dict)."""
+        nb = ctypes.c_uint64()
+        _check(load().gpm_graph_autotune_bytes(self._h, ctypes.byref(nb)))
+        if ws is None or ws.numel() < nb.value:
+            ws = _buffer(nb.value, self.device)
+        t = Tuning()
+        _check(load().gpm_graph_autotune(self._h, _ptr(ws), ws.numel(), _stream(stream),
+                                         ctypes.byref(t)))
+        return t.as_dict()
 
     def csr(self):
         """(off, adj) views (int32 device tensors) of the symmetric CSR."""

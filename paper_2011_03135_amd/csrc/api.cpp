@@ -42,6 +42,11 @@ gpm_status sl_run(const gpm_graph *g, int32_t plan, bool list, void *ws, uint64_
                   unsigned long long *d_count, int32_t *d_buf, uint64_t cap,
                   unsigned long long *d_result, hipStream_t st);
 uint64_t orient_scratch_bytes(const gpm_graph *g);
+void tuning_get(const gpm_graph *g, gpm_tuning *t);
+gpm_status tuning_set(gpm_graph *g, const gpm_tuning *t);
+gpm_status autotune_bytes(const gpm_graph *g, uint64_t *bytes);
+gpm_status graph_autotune(gpm_graph *g, void *ws, uint64_t ws_bytes, hipStream_t st,
+                          gpm_tuning *chosen);
 gpm_status graph_orient(gpm_graph *g, int32_t order, void *scratch, uint64_t scratch_bytes,
                         int32_t *d_core, hipStream_t st);
 int motif_classes(int k);
@@ -317,6 +322,36 @@ gpm_status gpm_graph_orient(gpm_graph *g, int32_t order, void *d_scratch, uint64
         return fail(GPM_INVALID_ARGUMENT, "scratch NULL or unaligned");
     return gpm::graph_orient(g, order, d_scratch, scratch_bytes, d_core,
                              static_cast<hipStream_t>(stream));
+}
+
+gpm_status gpm_graph_get_tuning(const gpm_graph *g, gpm_tuning *t) {
+    gpm_status rc = check_graph(g);
+    if (rc) return rc;
+    if (!t) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    gpm::tuning_get(g, t);
+    return GPM_OK;
+}
+
+gpm_status gpm_graph_set_tuning(gpm_graph *g, const gpm_tuning *t) {
+    gpm_status rc = check_graph(g);
+    if (rc) return rc;
+    if (!t) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    return gpm::tuning_set(g, t);
+}
+
+gpm_status gpm_graph_autotune_bytes(const gpm_graph *g, uint64_t *bytes) {
+    gpm_status rc = check_graph(g);
+    if (rc) return rc;
+    if (!bytes) return fail(GPM_INVALID_ARGUMENT, "NULL argument");
+    return gpm::autotune_bytes(g, bytes);
+}
+
+gpm_status gpm_graph_autotune(gpm_graph *g, void *d_ws, uint64_t ws_bytes, void *stream,
+                              gpm_tuning *chosen) {
+    gpm_status rc = check_graph(g);
+    if (rc) return rc;
+    if (!d_ws || !aligned256(d_ws)) return fail(GPM_INVALID_ARGUMENT, "workspace NULL or unaligned");
+    return gpm::graph_autotune(g, d_ws, ws_bytes, static_cast<hipStream_t>(stream), chosen);
 }
 
 gpm_status gpm_workspace_bytes(const gpm_graph *g, const gpm_pattern *p, uint64_t *bytes) {

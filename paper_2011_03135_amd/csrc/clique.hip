@@ -732,12 +732,12 @@ __global__ void __launch_bounds__(kBlock) k_clique_hub(const int32_t *__restrict
 // ------------------------------------------------------------ host side --
 
 // Triangle classes by out-degree: (1, 64] one wave per block, (64, 256] and
-// (256, 1024] larger blocks sharing one staged root.  Chunk sizes in pairs:
-// every chunk costs one atomic on the class's cursor, and a few hundred
-// thousand atomics on one address cost milliseconds, so chunks stay large.
+// (256, 1024] larger blocks sharing one staged root.  Chunk sizes in pairs
+// (per graph, gpm_graph::tc_tau): every chunk costs one atomic on the
+// class's cursor, and a few hundred thousand atomics on one address cost
+// milliseconds, so chunks stay large; too large, and the last chunks leave
+// most of the grid idle.
 constexpr int32_t kTcSmall = 64, kTcMid = 256, kTcMax = 1024;
-constexpr int64_t kTauSmall = 8192, kTauMid = 16384, kTauBig = 65536;
-constexpr int64_t kTauMin = kTauSmall;
 
 struct CliqueWs {
     unsigned long long *result;   // [8]: count, -, pairs of each triangle class
@@ -758,7 +758,8 @@ struct CliqueWs {
 int64_t chunk_bound(const gpm_graph *g) {
     // total pair work = sum_v d-(v) d+(v) <= m * max_out; chunks = ceil(total / tau)
     int64_t w = g->m * (int64_t)std::max(g->max_out_degree, 1);
-    return w / kTauMin + 2;
+    const int64_t tau = std::min({g->tc_tau[0], g->tc_tau[1], g->tc_tau[2]});
+    return w / std::max<int64_t>(tau, 1) + 2;
 }
 
 // The generic DFS (a wave per root) serves listings of k >= 6; every other
@@ -895,11 +896,11 @@ gpm_status launch_local(const gpm_graph *g, CliqueWs &W, const int32_t *cnt_s,
                                              "k_clique_wave<8>", "k_clique_wave<9>"};
         Span sp(kNames[K - 4], st);
         if (em)
-            hipLaunchKernelGGL((k_clique_wave<K, true>), dim3((unsigned)(cu_count() * 32)),
+            hipLaunchKernelGGL((k_clique_wave<K, true>), dim3((unsigned)(cu_count() * g->cw_bpc)),
                                dim3(kWave), 0, st, g->dag_off, g->dag_adj, W.list_s, cnt_s, res,
                                res3, res4, *em);
         else
-            hipLaunchKernelGGL((k_clique_wave<K, false>), dim3((unsigned)(cu_count() * 32)),
+            hipLaunchKernelGGL((k_clique_wave<K, false>), dim3((unsigned)(cu_count() * g->cw_bpc)),
                                dim3(kWave), 0, st, g->dag_off, g->dag_adj, W.list_s, cnt_s, res,
                                res3, res4, RowEmitter{});
     }
@@ -955,17 +956,18 @@ static gpm_status tc_launch(const gpm_graph *g, CliqueWs &W, unsigned long long 
     GPM_LAUNCH_CHECK("k_root_work");
     const bool arcs = MODE == TC_ARCS;
     gpm_status rc = tc_class<kTcMax, 512, MODE>(
-        g, W, RC_BIG, W.list_b, W.wpre_b, W.first_b, 2, kTauBig, 4,
+        g, W, RC_BIG, W.list_b, W.wpre_b, W.first_b, 2, g->tc_tau[2], g->tc_bpc[2],
         MODE == TC_LIST ? "k_tc_block<1024,list>" : (arcs ? "k_tc_block<1024,arcs>" : "k_tc_block<1024>"),
         res, te, em, st);
     if (rc) return rc;
-    rc = tc_class<kTcMid, 256, MODE>(g, W, RC_MID, W.list_m, W.wpre_m, W.first_m, 1, kTauMid, 8,
+    rc = tc_class<kTcMid, 256, MODE>(g, W, RC_MID, W.list_m, W.wpre_m, W.first_m, 1,
+                                     g->tc_tau[1], g->tc_bpc[1],
                                      MODE == TC_LIST ? "k_tc_block<256,list>"
                                                      : (arcs ? "k_tc_block<256,arcs>" : "k_tc_block<256>"),
                                      res, te, em, st);
     if (rc) return rc;
     rc = tc_class<kTcSmall, 64, MODE>(g, W, RC_SMALL, W.list_s, W.wpre_s, W.first_s, 0,
-                                      kTauSmall, 32,
+                                      g->tc_tau[0], g->tc_bpc[0],
                                       MODE == TC_LIST ? "k_tc_block<64,list>"
                                                       : (arcs ? "k_tc_block<64,arcs>" : "k_tc_block<64>"),
                                       res, te, em, st);

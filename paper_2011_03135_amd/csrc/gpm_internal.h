@@ -22,6 +22,15 @@ struct gpm_graph {
     // [n+1] orientation key: arc u -> v iff (okey[u], u) < (okey[v], v);
     // the degrees after a build, the core-value key after a core orientation
     int32_t *okey;
+    // Task granularity of the plain path (gpm_tuning; gpm_graph_autotune
+    // picks them per graph): pairs per work chunk and workgroups per CU of
+    // the triangle classes (out-degree <= 64, <= 256, <= 1024), one-wave
+    // workgroups per CU of the clique kernel for roots of out-degree <= 64,
+    // and local triangles per 5-clique task
+    int64_t tc_tau[3] = {8192, 16384, 65536};
+    int32_t tc_bpc[3] = {32, 8, 4};
+    int32_t cw_bpc = 32;
+    int64_t lg5_slice = 1 << 20;
 };
 
 namespace gpm {

@@ -37,7 +37,6 @@ constexpr int kBigThreads = 1024;
 constexpr int kHalfMaxD = 512;
 constexpr int kHalfThreads = 512;
 constexpr int kHalfBlocksPerCu = 3;
-constexpr uint64_t kSlice5 = 1 << 20;  // local triangles per 5-clique slice
 constexpr int32_t kMaxSlices = 1024;
 
 __device__ __forceinline__ void wave_sync() {
@@ -344,7 +343,7 @@ __global__ void __launch_bounds__(NT, DMAX == kHalfMaxD ? 6 : 1) k_lg_build(cons
                                                  uint64_t *grows, int32_t *slices,
                                                  unsigned long long *units,
                                                  unsigned long long *res3,
-                                                 unsigned long long *res4) {
+                                                 unsigned long long *res4, uint64_t slice5) {
     __shared__ uint64_t rows[DMAX * (DMAX / 64)];
     __shared__ __align__(16) int32_t keys[LgHash<DMAX>::kSlots];
     __shared__ int16_t vals[LgHash<DMAX>::kSlots];
@@ -380,9 +379,9 @@ __global__ void __launch_bounds__(NT, DMAX == kHalfMaxD ? 6 : 1) k_lg_build(cons
         if (lane_id() == 0 && tri) atomicAdd((unsigned long long *)&sh.s_tri, (unsigned long long)tri);
         __syncthreads();
         if (tid == 0) {
-            // slices over local vertices: about kSlice5 local triangles each,
-            // at least 8 local vertices each
-            const uint64_t s_work = 1 + sh.s_tri / kSlice5;
+            // slices over local vertices: about slice5 local triangles each
+            // (per graph, gpm_graph::lg5_slice), at least 8 local vertices each
+            const uint64_t s_work = 1 + sh.s_tri / slice5;
             const uint64_t s_cap = (uint64_t)(d / 8 + 1);
             slices[r] = (int32_t)std::min<uint64_t>(kMaxSlices, std::min(s_work, s_cap));
             if (sh.s_tri) atomicAdd(units, (unsigned long long)sh.s_tri);
@@ -809,7 +808,7 @@ gpm_status lg5_class(const gpm_graph *g, int32_t k, LgWs &L, const int32_t *list
         hipLaunchKernelGGL((k_lg_build<kHalfMaxD, kHalfThreads>),
                            dim3((unsigned)cu_count() * kHalfBlocksPerCu), dim3(kHalfThreads), 0,
                            st, g->off, g->okey, g->dag_off, g->dag_adj, list, cnt, kMidMaxD, cursors + 2,
-                           rowoff, rows, L.slices, units, res3, res4);
+                           rowoff, rows, L.slices, units, res3, res4, (uint64_t)g->lg5_slice);
     }
     GPM_LAUNCH_CHECK("k_lg_build<512>");
     {
@@ -817,7 +816,7 @@ gpm_status lg5_class(const gpm_graph *g, int32_t k, LgWs &L, const int32_t *list
         hipLaunchKernelGGL((k_lg_build<DMAX, NT>), dim3((unsigned)cu_count() * (NT <= 256 ? 8 : 1)),
                            dim3(NT), 0, st, g->off, g->okey, g->dag_off, g->dag_adj, list, cnt,
                            DMAX > kHalfMaxD ? kHalfMaxD : 0, cursors + 0, rowoff, rows, L.slices,
-                           units, res3, res4);
+                           units, res3, res4, (uint64_t)g->lg5_slice);
     }
     GPM_LAUNCH_CHECK("k_lg_build");
     GPM_HIP(exclusive_scan_i32(L.slices, toff, (uint64_t)n, L.scan_tmp, st));
