@@ -59,16 +59,17 @@ OPS_PER_LOCAL_TRIANGLE = 4
 MEASURED_TRAFFIC = {
     "kernel": "k_lg5<1024>",
     "source": "paper_2011_03135_amd/csrc/local_graph.hip",
-    "source_sha256_prefix": "6d6b79d50bf0a512",
-    "bytes_read": 4295646 * 128,
+    "source_sha256_prefix": "0929cc93784b2dcc",
+    "lg5_slice": 1 << 20,   # the task size the counters were taken at
+    "bytes_read": 4307177 * 128,
     "bytes_written": 30690 * 32,
 }
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, lg5_slice):
     import hashlib
     t = MEASURED_TRAFFIC
-    if kernel != t["kernel"]:
+    if kernel != t["kernel"] or lg5_slice != t["lg5_slice"]:
         return None
     with open(os.path.join(ROOT, t["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest()[:16] != t["source_sha256_prefix"]:
@@ -95,13 +96,13 @@ def dag_class_bytes(off, adj, dmin, dmax, kmin):
     return 12 * arcs + 4 * pairs, arcs, pairs
 
 
-def roofline(dom, ms, units, off, adj):
+def roofline(dom, ms, units, off, adj, lg5_slice):
     if dom.startswith("k_lg5"):
         ops = OPS_PER_LOCAL_TRIANGLE * units
         ach = ops / (ms * 1e-3) / 1e12
         return {"kernel": dom, "bound": "alu", "achieved": ach, "peak": INT32_VALU_PEAK_TOPS,
                 "unit": "TOP/s (int32)", "frac": ach / INT32_VALU_PEAK_TOPS,
-                "traffic": measured_traffic(dom), "traffic_unit": "bytes per launch",
+                "traffic": measured_traffic(dom, lg5_slice), "traffic_unit": "bytes per launch",
                 "units_per_launch": units, "unit_name": "local triangles",
                 "ops_per_unit": OPS_PER_LOCAL_TRIANGLE, "avg_launch_ms": ms}
     if dom.startswith("k_tc_flat"):
@@ -935,7 +936,8 @@ def main():
         phases[name] = phases.get(name, 0.0) + ms / args.steps
         units[name] = units.get(name, 0) + un / args.steps
     dom = max((k for k in phases if k != "graph_build"), key=lambda k: phases[k])
-    roof = roofline(dom, phases[dom], int(units[dom]), off_h, adj_h)
+    roof = roofline(dom, phases[dom], int(units[dom]), off_h, adj_h,
+                    tuning["chosen"]["lg5_slice"])
     per_problem = {"graph_build": {"ms": phase_ms[0]}}
     for k, c, ms in zip(ks, sep_counts, phase_ms[1:]):
         per_problem[f"{k}-clique" if k > 3 else "TC"] = {
