@@ -68,12 +68,14 @@ gpm_status tuning_set(gpm_graph *g, const gpm_tuning *t) {
 gpm_status autotune_bytes(const gpm_graph *g, uint64_t *bytes) {
     gpm_graph tmp = *g;
     for (int c = 0; c < 3; c++) tmp.tc_tau[c] = kTauLo;
-    uint64_t b3 = 0, b5 = 0;
-    gpm_status rc = clique_workspace_bytes(&tmp, 3, false, &b3);
-    if (rc) return rc;
-    rc = clique_workspace_bytes(&tmp, 5, false, &b5);
-    if (rc) return rc;
-    *bytes = kResultBytes + std::max(b3, b5);   // k = 4 needs no more than k = 5
+    uint64_t most = 0;
+    for (int32_t k = 3; k <= 5; k++) {
+        uint64_t b = 0;
+        gpm_status rc = clique_workspace_bytes(&tmp, k, false, &b);
+        if (rc) return rc;
+        most = std::max(most, b);
+    }
+    *bytes = kResultBytes + most;
     return GPM_OK;
 }
 

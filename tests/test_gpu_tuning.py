@@ -119,3 +119,19 @@ def test_autotune_slices_on_a_graph_with_large_roots(gpm):
     assert g.tuning() == t
     assert [gpm.count(g, gpm.clique(k)) for k in (3, 4, 5)] == \
         [comb(300, 3), comb(300, 4), comb(300, 5)]
+
+
+@pytest.mark.parametrize("case", ["edgeless", "one_edge", "star"])
+def test_autotune_degenerate_graphs(gpm, case):
+    """Graphs with no triangle work at all: the tuner still returns a valid
+    setting and the counts stay exact."""
+    import numpy as np
+    e = {"edgeless": lambda: graphgen.EdgeList(5, np.zeros(0, np.int32), np.zeros(0, np.int32),
+                                               "edgeless"),
+         "one_edge": lambda: graphgen.EdgeList(2, np.array([0], np.int32),
+                                               np.array([1], np.int32), "one_edge"),
+         "star": lambda: graphgen.star_graph(40)}[case]()
+    g = build(gpm, e)
+    t = g.autotune()
+    assert g.tuning() == t
+    assert [gpm.count(g, gpm.clique(k)) for k in (3, 4, 5)] == [0, 0, 0]
