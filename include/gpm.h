@@ -260,7 +260,8 @@ gpm_status gpm_graph_set_tuning(gpm_graph *g, const gpm_tuning *t);
  * x2, /2; lg5_slice x4, x2, /2, /4) and
  * keeping a change when it is at least 3% faster (median of three calls
  * after a warm-up, HIP events on the stream).  Stores the result in the
- * handle and, when chosen is not NULL, in *chosen.  d_ws: at least
+ * handle and, when chosen is not NULL, in *chosen; on failure the handle
+ * keeps the tuning it had.  d_ws: at least
  * gpm_graph_autotune_bytes bytes, 256-byte aligned; the call synchronises
  * the stream.  Must not run while other work on the same graph is in
  * flight. */

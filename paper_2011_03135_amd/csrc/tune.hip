@@ -94,8 +94,9 @@ gpm_status graph_autotune(gpm_graph *g, void *ws, uint64_t ws_bytes, hipStream_t
         (void)hipEventDestroy(a);
         return fail(GPM_DEVICE_ERROR, "hipEventCreate failed");
     }
-    gpm_tuning cur;
+    gpm_tuning cur, orig;
     tuning_get(g, &cur);
+    orig = cur;
     gpm_status err = GPM_OK;
     // median of three timed calls after one warm-up; a failure ends the tuning
     auto timed = [&](int k) -> float {
@@ -162,7 +163,7 @@ gpm_status graph_autotune(gpm_graph *g, void *ws, uint64_t ws_bytes, hipStream_t
             if (t.lg5_slice != cur.lg5_slice) attempt(t, 5, best5);
         }
     }
-    put(g, cur);
+    put(g, err ? orig : cur);   // a failed tuning leaves the handle as it was
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (err) return err;
