@@ -215,11 +215,14 @@ void gpm_graph_release(gpm_graph *g);
  * place in the graph's storage and the handle's max_out_degree is updated;
  * counts do not depend on the orientation.  d_core (device int32[n], may be
  * NULL) receives the core numbers; they are computed (for d_core) under
- * either order.  d_scratch is only used during the call; the call
- * synchronises the stream (the peeling runs as device steps queued 32 at a
- * time, and the host reads the peeling state after each batch through a
- * 64-byte pinned host buffer the first call allocates and the process
- * keeps).  Must not run while other work on the same graph is in flight. */
+ * either order.  Core numbers come from the h-index fixed point (each
+ * vertex repeatedly takes the h-index of its neighbours' values, starting
+ * from an upper bound; rounds queued 8 at a time); graphs whose bound
+ * exceeds 4095 are peeled level by level instead (queued device steps).
+ * d_scratch is only used during the call; the call synchronises the stream
+ * (the host reads a few counters per batch through a 64-byte pinned host
+ * buffer the first call allocates and the process keeps).  Must not run
+ * while other work on the same graph is in flight. */
 #define GPM_ORIENT_DEGREE 1
 #define GPM_ORIENT_CORE   2
 gpm_status gpm_graph_orient_bytes(const gpm_graph *g, uint64_t *scratch_bytes);

@@ -1,6 +1,24 @@
 // Core numbers and the core-value orientation (Appendix B.2 names two
 // orientations for cliques: by degree and by core value).
 //
+// Core numbers as the fixed point of the h-index operator (Lu, Zhou, Zhang
+// and Stanley, Nature Communications 2016; Montresor, De Pellegrini and
+// Miorandi, 2013): starting from an upper bound (the degree, capped by the
+// largest h with at least h + 1 vertices of degree >= h), every vertex
+// repeatedly takes the h-index of its neighbours' values (the largest h such
+// that at least h of them are >= h).  Values only decrease and settle at the
+// core numbers.  Each round is one kernel over the vertices marked active:
+// a vertex is evaluated when a neighbour's value dropped below its own in
+// the previous round, updates in place, and marks the neighbours its drop
+// can affect; the run ends after a round without a change.  The h-index of
+// a vertex of degree <= 64 comes from ballots over its neighbours' values in
+// registers, of a larger one from an LDS histogram of min(value, own value)
+// (a wave's up to degree 512, a workgroup's above; at most 4096 bins, hence
+// the cap on the bound).  RMAT-14/16/18 take 20,
+// 29 and 59 rounds of the synchronous form against hundreds of peeling
+// levels.  Graphs whose bound exceeds 4095 (or that would need more than
+// kMaxRounds rounds) are peeled instead:
+//
 // Core numbers by level-synchronous peeling.  For level L = 0, 1, ...: every
 // vertex not yet removed whose remaining degree is at most L is removed with
 // core number L (a scan), and removing a vertex lowers its live neighbours'
@@ -30,6 +48,7 @@
 // as second key 702, against 707 by degree and 639 for the degeneracy).
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 #include <mutex>
 
 #include "gpm_internal.h"
@@ -48,7 +67,7 @@ constexpr int kCoreWaves = kCoreBlock / kWave;
 // out-degree
 enum { S_LEVEL = 0, S_MODE = 1, S_CIN = 2, S_FBUF = 3, S_LIVE = 4, S_LBUF = 5, S_FIRST = 6,
        S_MAXCORE = 7, S_DONE = 8, K_CNT = 9, K_MIN = 10, K_KEPT = 11, C_MAX_OUT = 12,
-       C_WORDS = 16 };
+       H_UB = 13, H_MAXC = 14, C_WORDS = 16 };
 enum { M_SCAN = 0, M_PROCESS = 1, M_END = 2 };
 
 __global__ void __launch_bounds__(kCoreBlock) k_core_init(const int32_t *__restrict__ off,
@@ -191,6 +210,278 @@ __global__ void __launch_bounds__(kCoreBlock) k_core_step(const int32_t *__restr
     ctl[S_DONE] = 0u;
 }
 
+// ------------------------------------------------ h-index fixed point ---
+constexpr int32_t kHBins = 4096;      // histogram bins: values capped below this
+constexpr int kHWaves = 4;            // waves per workgroup (a histogram each)
+constexpr int kMaxRounds = 4096;
+
+// Degree histogram (degrees capped at kHBins), counted per workgroup in LDS
+// first: most vertices share a few small degrees, and one global atomic per
+// vertex on those few words would queue for milliseconds.
+__global__ void __launch_bounds__(kCoreBlock) k_deg_hist(const int32_t *__restrict__ off,
+                                                         int32_t n, uint32_t *hist) {
+    __shared__ uint32_t local[kHBins + 1];
+    for (int32_t b = threadIdx.x; b <= kHBins; b += kCoreBlock) local[b] = 0u;
+    __syncthreads();
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&local[min(off[v + 1] - off[v], kHBins)], 1u);
+    __syncthreads();
+    for (int32_t b = threadIdx.x; b <= kHBins; b += kCoreBlock)
+        if (local[b]) atomicAdd(&hist[b], local[b]);
+}
+
+// Upper bound of every core number: the largest h with at least h + 1
+// vertices of degree >= h (a k-core has k + 1 vertices of degree >= k).
+// 0xffffffff when that reaches kHBins.  One workgroup: each thread sums a
+// run of bins, a suffix scan over the runs, then each thread finds the
+// largest qualifying h in its run.
+__global__ void __launch_bounds__(kCoreBlock) k_core_ub(const uint32_t *hist, uint32_t *ctl) {
+    __shared__ uint64_t s_part[kCoreWaves];
+    __shared__ int32_t s_best[kCoreWaves];
+    constexpr int32_t kBins = kHBins + 1;
+    constexpr int32_t kPer = (kBins + kCoreBlock - 1) / kCoreBlock;
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    const int32_t b0 = min(kBins, tid * kPer), b1 = min(kBins, b0 + kPer);
+    uint64_t own = 0;
+    for (int32_t b = b0; b < b1; b++) own += hist[b];
+    const uint64_t wscan = wave_incl_scan(own);
+    if (lane == kWave - 1) s_part[wid] = wscan;
+    __syncthreads();
+    uint64_t before = 0, total = 0;
+    for (int w = 0; w < kCoreWaves; w++) {
+        if (w < wid) before += s_part[w];
+        total += s_part[w];
+    }
+    uint64_t atleast = total - (before + wscan);   // vertices of degree >= b1
+    int32_t best = -1;
+    for (int32_t b = b1 - 1; b >= b0; b--) {
+        atleast += hist[b];
+        if (atleast >= (uint64_t)b + 1) {
+            best = b;
+            break;
+        }
+    }
+    best = wave_max(best);
+    if (lane == 0) s_best[wid] = best;
+    __syncthreads();
+    if (tid == 0) {
+        int32_t ub = 0;
+        for (int w = 0; w < kCoreWaves; w++) ub = max(ub, s_best[w]);
+        ctl[H_UB] = ub >= kHBins ? 0xffffffffu : (uint32_t)ub;
+    }
+}
+
+__global__ void __launch_bounds__(kCoreBlock) k_hcore_init(const int32_t *__restrict__ off,
+                                                           int32_t n, const uint32_t *ctl,
+                                                           int32_t *core, uint8_t *act) {
+    const int32_t ub = (int32_t)ctl[H_UB];
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        core[v] = min(off[v + 1] - off[v], ub);
+        act[v] = 1;
+    }
+}
+
+constexpr int32_t kBigD = 512;        // vertices of higher degree take a whole workgroup
+
+// One round (see above).  A wave takes 64 consecutive vertices and
+// evaluates the active ones of degree <= kBigD among them in turn; those of
+// higher degree go to big[] (count bigcnt[round]) for k_hcore_big.
+// cnt[round] counts the values that dropped; a round after one without a
+// drop does nothing.
+__global__ void __launch_bounds__(kCoreBlock) k_hcore_round(const int32_t *__restrict__ off,
+                                                            const int32_t *__restrict__ adj,
+                                                            int32_t n, int32_t *core,
+                                                            uint8_t *act_in, uint8_t *act_out,
+                                                            uint32_t *cnt, int32_t *big,
+                                                            uint32_t *bigcnt, int32_t round) {
+    __shared__ uint32_t s_hist[kHWaves][kBigD + 1];
+    if (round > 0 && cnt[round - 1] == 0) return;
+    const int lane = lane_id();
+    uint32_t *hist = s_hist[threadIdx.x / kWave];
+    const int64_t nwaves = (int64_t)gridDim.x * kHWaves;
+    uint32_t drops = 0;
+    for (int64_t c0 = ((int64_t)blockIdx.x * kHWaves + threadIdx.x / kWave) * kWave; c0 < n;
+         c0 += nwaves * kWave) {
+        const int64_t mine = c0 + lane;
+        const bool a = mine < n && act_in[mine];
+        if (a) act_in[mine] = 0;   // consumed; a neighbour's drop may set it again
+        uint64_t mask = __ballot(a);
+        while (mask) {
+            const int32_t v = (int32_t)(c0 + __builtin_ctzll(mask));
+            mask &= mask - 1ull;
+            const int32_t c = core[v];
+            const int32_t s = off[v], d = off[v + 1] - s;
+            if (c <= 0) continue;
+            if (d > kBigD) {
+                if (lane == 0) big[atomicAdd(&bigcnt[round], 1u)] = v;
+                continue;
+            }
+            int32_t h;
+            if (d <= kWave) {
+                const int32_t x = lane < d ? core[adj[s + lane]] : 0;
+                const int32_t k = __popcll(__ballot(x >= c));
+                if (k >= c) continue;
+                // the largest h in [k, c - 1] with at least h values >= h
+                int32_t lo = k, hi = c - 1;
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (__popcll(__ballot(x >= mid)) >= mid) lo = mid;
+                    else hi = mid - 1;
+                }
+                h = lo;
+            } else {
+                // histogram of min(value, c) over bins 0..c (c <= d <= kBigD);
+                // the previous vertex's reads of it come first
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                for (int32_t b = lane; b <= c; b += kWave) hist[b] = 0u;
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                // four gathers in flight per lane (d <= 512: at most two passes)
+                for (int32_t j0 = lane; j0 < d; j0 += 4 * kWave) {
+                    int32_t u[4], x[4];
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const int32_t j = j0 + q * kWave;
+                        u[q] = j < d ? adj[s + j] : -1;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; q++) x[q] = u[q] >= 0 ? core[u[q]] : -1;
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+                        if (x[q] >= 0) atomicAdd(&hist[min(x[q], c)], 1u);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                const int32_t k = (int32_t)hist[c];   // values >= c
+                if (k >= c) continue;
+                // lanes own runs of bins below c; S(b) = values >= b
+                const int32_t per = (c + kWave - 1) / kWave;
+                const int32_t b0 = min(c, lane * per), b1 = min(c, b0 + per);
+                uint32_t own = 0;
+                for (int32_t b = b0; b < b1; b++) own += hist[b];
+                const uint32_t upto = wave_incl_scan(own);
+                const uint32_t total = __shfl(upto, kWave - 1, kWave);
+                uint32_t run = (uint32_t)k + (total - upto);   // values >= b1
+                int32_t best = -1;
+                for (int32_t b = b1 - 1; b >= b0; b--) {
+                    run += hist[b];
+                    if (run >= (uint32_t)b) {
+                        best = b;
+                        break;
+                    }
+                }
+                h = wave_max(best);
+            }
+            if (h >= c) continue;
+            if (lane == 0) core[v] = h;
+            drops++;
+            // neighbours whose value is above h may drop in turn
+            for (int32_t j = lane; j < d; j += kWave) {
+                const int32_t u = adj[s + j];
+                if (core[u] > h) act_out[u] = 1;
+            }
+        }
+    }
+    if (lane == 0 && drops) atomicAdd(&cnt[round], drops);
+}
+
+// The round's vertices of degree above kBigD, a workgroup each: the same
+// evaluation with the workgroup's 256 threads (four gathers in flight each)
+// and one histogram in LDS.
+__global__ void __launch_bounds__(kCoreBlock) k_hcore_big(const int32_t *__restrict__ off,
+                                                          const int32_t *__restrict__ adj,
+                                                          int32_t *core, uint8_t *act_out,
+                                                          uint32_t *cnt, const int32_t *big,
+                                                          const uint32_t *bigcnt, int32_t round) {
+    __shared__ uint32_t hist[kHBins];
+    __shared__ uint32_t s_part[kCoreWaves];
+    __shared__ int32_t s_best[kCoreWaves];
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    const uint32_t nb = bigcnt[round];
+    uint32_t drops = 0;
+    for (uint32_t i = blockIdx.x; i < nb; i += gridDim.x) {
+        const int32_t v = big[i];
+        const int32_t c = core[v];   // only this workgroup changes it in this round
+        const int32_t s = off[v], d = off[v + 1] - s;
+        __syncthreads();   // the previous vertex's reads of hist come first
+        for (int32_t b = tid; b <= c; b += kCoreBlock) hist[b] = 0u;
+        __syncthreads();
+        for (int32_t j0 = tid; j0 < d; j0 += 4 * kCoreBlock) {
+            int32_t u[4], x[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int32_t j = j0 + q * kCoreBlock;
+                u[q] = j < d ? adj[s + j] : -1;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; q++) x[q] = u[q] >= 0 ? core[u[q]] : -1;
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (x[q] >= 0) atomicAdd(&hist[min(x[q], c)], 1u);
+        }
+        __syncthreads();
+        const int32_t k = (int32_t)hist[c];
+        if (k >= c) continue;   // the same for every thread
+        // threads own runs of bins below c; a workgroup scan of their sums
+        const int32_t per = (c + kCoreBlock - 1) / kCoreBlock;
+        const int32_t b0 = min(c, tid * per), b1 = min(c, b0 + per);
+        uint32_t own = 0;
+        for (int32_t b = b0; b < b1; b++) own += hist[b];
+        const uint32_t wscan = wave_incl_scan(own);
+        if (lane == kWave - 1) s_part[wid] = wscan;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (int w = 0; w < kCoreWaves; w++) {
+            if (w < wid) before += s_part[w];
+            total += s_part[w];
+        }
+        const uint32_t upto = before + wscan;
+        uint32_t run = (uint32_t)k + (total - upto);   // values >= b1
+        int32_t best = -1;
+        for (int32_t b = b1 - 1; b >= b0; b--) {
+            run += hist[b];
+            if (run >= (uint32_t)b) {
+                best = b;
+                break;
+            }
+        }
+        best = wave_max(best);
+        if (lane == 0) s_best[wid] = best;
+        __syncthreads();
+        int32_t h = -1;
+        for (int w = 0; w < kCoreWaves; w++) h = max(h, s_best[w]);
+        if (h >= c) continue;
+        if (tid == 0) {
+            core[v] = h;
+            drops++;
+        }
+        for (int32_t j = tid; j < d; j += kCoreBlock) {
+            const int32_t u = adj[s + j];
+            if (core[u] > h) act_out[u] = 1;
+        }
+    }
+    if (tid == 0 && drops) atomicAdd(&cnt[round], drops);
+}
+
+__global__ void __launch_bounds__(kCoreBlock) k_core_max(const int32_t *__restrict__ core,
+                                                         int32_t n, uint32_t *ctl) {
+    __shared__ int32_t s_mx[kCoreWaves];
+    int32_t mx = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        mx = max(mx, core[v]);
+    mx = wave_max(mx);
+    if (lane_id() == 0) s_mx[threadIdx.x / kWave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {   // one atomic per workgroup
+        for (int w = 1; w < kCoreWaves; w++) mx = max(mx, s_mx[w]);
+        if (mx > 0) atomicMax(ctl + H_MAXC, (uint32_t)mx);
+    }
+}
+
 __device__ __forceinline__ int32_t key_of(const int32_t *__restrict__ off,
                                           const int32_t *__restrict__ core, int32_t v) {
     return core ? core[v] : off[v + 1] - off[v];
@@ -264,6 +555,9 @@ struct CoreWs {
     int32_t *deg, *core, *F, *F2, *L, *L2, *outcnt;
     int64_t *scan_tmp;
     uint32_t *ctl;
+    uint32_t *hist, *rounds;   // degree histogram; drops per h-index round
+    uint32_t *bigcnt;          // high-degree vertices to evaluate per round (listed in F)
+    uint8_t *act0, *act1;      // active flags of the h-index rounds
 };
 
 CoreWs core_layout(int32_t n, void *base, uint64_t *bytes) {
@@ -279,6 +573,11 @@ CoreWs core_layout(int32_t n, void *base, uint64_t *bytes) {
     W.outcnt = c.take<int32_t>(n1);
     W.scan_tmp = c.take<int64_t>(scan_tmp_words(n1));
     W.ctl = c.take<uint32_t>(C_WORDS);
+    W.hist = c.take<uint32_t>(kHBins + 1);
+    W.rounds = c.take<uint32_t>(kMaxRounds);
+    W.bigcnt = c.take<uint32_t>(kMaxRounds);
+    W.act0 = c.take<uint8_t>(n1);
+    W.act1 = c.take<uint8_t>(n1);
     if (bytes) *bytes = c.used;
     return W;
 }
@@ -335,8 +634,66 @@ uint64_t orient_scratch_bytes(const gpm_graph *g) {
 // Steps queued per read of the state (RMAT-20 takes about 2,000 steps).
 constexpr int kStepsPerTrip = 32;
 
+// Rounds queued per read of the last round's count.
+constexpr int kRoundsPerTrip = 8;
+
+// The h-index fixed point; *done = false when the graph is left to the
+// peeling (bound above kHBins - 1, or more than kMaxRounds rounds), or with
+// GPM_CORE_PEEL=1 in the environment (for comparison).
+static gpm_status core_numbers_hindex(const gpm_graph *g, const CoreWs &W, hipStream_t st,
+                                      int32_t *max_core, bool *done) {
+    *done = false;
+    const char *env = getenv("GPM_CORE_PEEL");
+    if (env && env[0] == '1') return GPM_OK;
+    const int32_t n = g->n;
+    GPM_HIP(fill_u32(W.ctl, 0, C_WORDS, st));
+    GPM_HIP(fill_u32(W.hist, 0, kHBins + 1, st));
+    GPM_HIP(fill_u32(W.rounds, 0, kMaxRounds, st));
+    GPM_HIP(fill_u32(W.bigcnt, 0, kMaxRounds, st));
+    GPM_HIP(fill_u32(reinterpret_cast<uint32_t *>(W.act1), 0, ((uint64_t)n + 4) / 4, st));
+    hipLaunchKernelGGL(k_deg_hist, dim3(vgrid(n)), dim3(kCoreBlock), 0, st, g->off, n, W.hist);
+    hipLaunchKernelGGL(k_core_ub, dim3(1), dim3(kCoreBlock), 0, st, W.hist, W.ctl);
+    GPM_LAUNCH_CHECK("k_core_ub");
+    uint32_t h[C_WORDS];
+    gpm_status rc = read_u32(W.ctl, h, C_WORDS, st);
+    if (rc) return rc;
+    if (h[H_UB] == 0xffffffffu) return GPM_OK;
+    Span sp("k_hcore_round", st);
+    hipLaunchKernelGGL(k_hcore_init, dim3(vgrid(n)), dim3(kCoreBlock), 0, st, g->off, n, W.ctl,
+                       W.core, W.act0);
+    GPM_LAUNCH_CHECK("k_hcore_init");
+    const unsigned grid = (unsigned)std::max(1, cu_count() * 4);
+    for (int32_t r0 = 0; r0 < kMaxRounds; r0 += kRoundsPerTrip) {
+        for (int32_t r = r0; r < r0 + kRoundsPerTrip; r++) {
+            hipLaunchKernelGGL(k_hcore_round, dim3(grid), dim3(kHWaves * kWave), 0, st, g->off,
+                               g->adj, n, W.core, (r & 1) ? W.act1 : W.act0,
+                               (r & 1) ? W.act0 : W.act1, W.rounds, W.F, W.bigcnt, r);
+            hipLaunchKernelGGL(k_hcore_big, dim3(grid), dim3(kCoreBlock), 0, st, g->off, g->adj,
+                               W.core, (r & 1) ? W.act0 : W.act1, W.rounds, W.F, W.bigcnt, r);
+        }
+        GPM_LAUNCH_CHECK("k_hcore_round");
+        uint32_t last = 1;
+        rc = read_u32(W.rounds + r0 + kRoundsPerTrip - 1, &last, 1, st);
+        if (rc) return rc;
+        if (last == 0) {
+            hipLaunchKernelGGL(k_core_max, dim3(vgrid(n)), dim3(kCoreBlock), 0, st, W.core, n,
+                               W.ctl);
+            GPM_LAUNCH_CHECK("k_core_max");
+            rc = read_u32(W.ctl, h, C_WORDS, st);
+            if (rc) return rc;
+            *max_core = (int32_t)h[H_MAXC];
+            *done = true;
+            return GPM_OK;
+        }
+    }
+    return GPM_OK;   // not settled within kMaxRounds rounds: peel instead
+}
+
 static gpm_status core_numbers_run(const gpm_graph *g, const CoreWs &W, hipStream_t st,
                                    int32_t *max_core) {
+    bool done = false;
+    gpm_status hrc = core_numbers_hindex(g, W, st, max_core, &done);
+    if (hrc || done) return hrc;
     const int32_t n = g->n;
     hipLaunchKernelGGL(k_core_init, dim3(vgrid(n)), dim3(kCoreBlock), 0, st, g->off, n, W.deg,
                        W.core);

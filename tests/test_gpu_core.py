@@ -60,10 +60,15 @@ def dag_arcs_deg(dag, n):
     return np.repeat(np.arange(n), np.diff(do)).astype(np.int64), da.astype(np.int64)
 
 
+@pytest.mark.parametrize("method", ["hindex", "peel"])
 @pytest.mark.parametrize("gi", range(7))
-def test_core_numbers_and_orientation(gpm, gi):
+def test_core_numbers_and_orientation(gpm, gi, method, monkeypatch):
+    """Both core-number methods: the h-index fixed point (the default) and
+    the level-synchronous peeling (GPM_CORE_PEEL=1)."""
+    if method == "peel":
+        monkeypatch.setenv("GPM_CORE_PEEL", "1")
     e = graphs()[gi]
-    print(f"graph {gi} {e.name} n={e.n}", flush=True)
+    print(f"graph {gi} {e.name} n={e.n} {method}", flush=True)
     g = build(gpm, e)
     off, adj = oracle.canonical_csr(e.n, e.u, e.v)
     want_core = oracle.core_numbers(off, adj)
