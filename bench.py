@@ -463,15 +463,17 @@ def motif_leg(gpm, torch, scale=18, cap=1 << 26, reps=3):
     adj_h = g.csr()[1].cpu().numpy()
     wedges, arcs_up = c4_wedges(off_h, adj_h)
     c4_ms = sum(x for k, x in phases.items() if k.startswith("k_c4"))
-    b_c4 = 8 * wedges + 12 * arcs_up
+    b_c4 = 4 * wedges + 12 * arcs_up
     res["motif4"]["c4_roofline"] = {
         "kernels": sorted(k for k in phases if k.startswith("k_c4")), "bound": "hbm",
         "alg_bytes": b_c4, "wedges": wedges, "ms": c4_ms,
         "achieved": b_c4 / (c4_ms * 1e-3) / 1e9 if c4_ms > 0 else None, "unit": "GB/s",
         "peak": HBM_PEAK_GBS,
         "frac": b_c4 / (c4_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if c4_ms > 0 else None,
-        "bytes_model": "8 B per scanned wedge x - y - z (z and its degree) + 12 B per arc "
-                       "y -> x (the middle's row bounds and id)"}
+        "bytes_model": "4 B per scanned wedge x - y - z (the rank of z, in the graph "
+                       "relabelled by degree order) + 12 B per arc y -> x (the middle and its "
+                       "segment of the part table); wedges counted under the (degree, id) "
+                       "order, the kernels break degree ties in any order"}
     for name, lpat in (("diamond", gpm.diamond(gpm.EDGE_INDUCED | gpm.LIST)),
                        ("4-cycle", gpm.cycle4(gpm.EDGE_INDUCED | gpm.LIST))):
         wsl = torch.empty(gpm.workspace_bytes(g, lpat), dtype=torch.uint8, device="cuda")

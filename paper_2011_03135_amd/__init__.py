@@ -35,6 +35,7 @@ from .binding import (  # noqa: F401
     motif_count_formula,
     motif_formula_workspace_bytes,
     motif_enum_workspace_bytes,
+    motif_workspace_bytes,
     pattern,
     timing_enable,
     timing_read,

@@ -28,14 +28,13 @@ enum Flag : int {
     F_BIG_COUNT = 1,  // rows routed to the bitmap sorter
     F_MAX_DEG = 2,
     F_MAX_OUT = 3,
-    F_MED_COUNT = 4,  // rows routed to the LDS sorter
+    F_MED_COUNT = 4,  // rows routed to the one-row-per-wave register sort
     F_DEG16 = 5,      // vertices of degree above 65535
     F_WORDS = 16,
 };
 
 constexpr int kBlock = 256;                 // 4 waves
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kSortLds = 2048;              // per-wave LDS sort capacity (entries)
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -253,7 +252,8 @@ __device__ __forceinline__ int32_t group_bitonic_sort(int32_t x) {
 }
 
 constexpr int kSmallRow = 16;   // rows sorted by a 16-lane group, 4 per wave
-constexpr int kRegRow = 512;    // rows up to this length sort in registers
+constexpr int kScanRow = 512;   // rows up to this length sort in registers within a row scan
+constexpr int kRegRow = 2048;   // rows up to this length sort in registers, a wave each
 
 // Sorts + uniques one row of L <= 64 R entries in place with one wave, all in
 // registers: entry i sits in lane i % 64 of x[i / 64], so bitonic partners
@@ -310,10 +310,10 @@ __device__ int32_t wave_sort_row_regs(int32_t *r, int32_t L) {
 }
 
 // Short rows: each 16-lane group sorts + uniques one row of at most 16
-// entries in place (4 consecutive rows per wave).  Rows beyond kRegRow go to
-// lists (the LDS sorter's up to kSortLds, the bitmap sorter's beyond), from
-// which the sorters' waves take one row each; the rest are left to
-// k_sort_rows.  Most rows of power-law graphs are short.
+// entries in place (4 consecutive rows per wave).  Rows beyond kScanRow go
+// to lists (up to kRegRow the list of the wave-per-row register sort, the
+// bitmap sorter's beyond); the rest are left to k_sort_rows' row scan.  Most
+// rows of power-law graphs are short.
 __global__ void __launch_bounds__(kBlock) k_sort_small_rows(const int32_t *__restrict__ raw_off,
                                                             int32_t *raw_adj, int32_t n,
                                                             int32_t *ucnt, int32_t *med_list,
@@ -338,95 +338,64 @@ __global__ void __launch_bounds__(kBlock) k_sort_small_rows(const int32_t *__res
         if (keep) r[__popc(gmask & ((1u << gl) - 1u))] = x;
         if (live && gl == 0) {
             if (small) ucnt[row] = __popc(gmask);
-            else if (L > kSortLds) big_list[atomicAdd(&flags[F_BIG_COUNT], 1u)] = (int32_t)row;
-            else if (L > kRegRow) med_list[atomicAdd(&flags[F_MED_COUNT], 1u)] = (int32_t)row;
+            else if (L > kRegRow) big_list[atomicAdd(&flags[F_BIG_COUNT], 1u)] = (int32_t)row;
+            else if (L > kScanRow) med_list[atomicAdd(&flags[F_MED_COUNT], 1u)] = (int32_t)row;
         }
     }
 }
 
-// Rows of kSmallRow+1 .. kRegRow entries (LDS = false: in registers; a wave
-// scans 64 rows at a time and visits the ones in range, no list, so no
-// contended counter) or the listed rows of kRegRow+1 .. kSortLds entries
-// (LDS = true: bitonic passes in LDS), a wave each: sort + unique in place.
-// The rare long rows get a launch of their own so the register sorter needs
-// no LDS.
-template <bool LDS>
+// Rows of kSmallRow+1 .. kScanRow entries (LIST = false) or the listed rows
+// of kScanRow+1 .. kRegRow entries (LIST = true), sorted + uniqued in place
+// in registers, a wave per row.  Without the list a wave scans `span`
+// consecutive rows at a time (one lane each; no list, so no contended
+// counter) and sorts the ones in range one after the other; the host picks
+// span so that the grid's waves share the rows (a small graph gets one row
+// per wave).  The longer rows take a list so that they spread over the
+// waves, and an instantiation of their own so that the scan's register
+// count stays low.  The rare longest rows get the bitmap sorter.
+template <bool LIST>
 __global__ void __launch_bounds__(kBlock) k_sort_rows(const int32_t *__restrict__ raw_off,
-                                                      int32_t *raw_adj, int32_t n,
+                                                      int32_t *raw_adj, int32_t n, int32_t span,
                                                       int32_t *ucnt, const int32_t *med_list,
                                                       const uint32_t *flags) {
-    __shared__ int32_t lds[kWavesPerBlock][LDS ? kSortLds : 1];
     const int lane = lane_id();
-    const int wib = threadIdx.x / kWave;
-    int32_t *buf = lds[wib];
-    const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + wib;
+    const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-    const int64_t nmed = LDS ? (int64_t)flags[F_MED_COUNT] : 0;
-    const int64_t nitems = LDS ? nmed : ((int64_t)n + kWave - 1) / kWave;
+    const int64_t nitems = LIST ? (int64_t)flags[F_MED_COUNT] : ((int64_t)n + span - 1) / span;
     for (int64_t it = wave0; it < nitems; it += nwaves) {
-        const int64_t c0 = it * kWave;
-        uint64_t todo;
-        if (LDS) {
-            todo = 1ull;
-        } else {
+        const int64_t c0 = it * span;
+        uint64_t todo = 1ull;
+        if (!LIST) {
             const int64_t mine = c0 + lane;
-            const int32_t Lm = mine < n ? raw_off[mine + 1] - raw_off[mine] : 0;
-            todo = __ballot(Lm > kSmallRow && Lm <= kRegRow);
+            const int32_t Lm = lane < span && mine < n ? raw_off[mine + 1] - raw_off[mine] : 0;
+            todo = __ballot(Lm > kSmallRow && Lm <= kScanRow);
         }
         while (todo) {
-            const int32_t row = LDS ? med_list[it] : (int32_t)(c0 + __builtin_ctzll(todo));
+            const int32_t row = LIST ? med_list[it] : (int32_t)(c0 + __builtin_ctzll(todo));
             todo &= todo - 1ull;
             const int32_t s = raw_off[row];
             const int32_t L = raw_off[row + 1] - s;
             int32_t *r = raw_adj + s;
-            if (!LDS && L > 64) {
-                int32_t c;
-                if (L <= 128) c = wave_sort_row_regs<2>(r, L);
-                else if (L <= 256) c = wave_sort_row_regs<4>(r, L);
-                else c = wave_sort_row_regs<8>(r, L);
-                if (lane == 0) ucnt[row] = c;
-            } else if (!LDS) {
-                int32_t x = lane < L ? r[lane] : INT_MAX;
-                x = group_bitonic_sort<kWave>(x);
-                int32_t prev = __shfl_up(x, 1, 64);
-                bool keep = lane < L && (lane == 0 || x != prev);
-                uint64_t mask = __ballot(keep);
-                if (keep) r[lanes_below(mask)] = x;
-                if (lane == 0) ucnt[row] = __popcll(mask);
+            int32_t c;
+            if (LIST) {
+                if (L > 1024) c = wave_sort_row_regs<32>(r, L);
+                else c = wave_sort_row_regs<16>(r, L);
             } else {
-                int P = 128;
-                while (P < L) P <<= 1;
-                for (int i = lane; i < P; i += kWave) buf[i] = i < L ? r[i] : INT_MAX;
-                wave_sync();
-                for (int k = 2; k <= P; k <<= 1) {
-                    for (int j = k >> 1; j > 0; j >>= 1) {
-                        for (int t = lane; t < P / 2; t += kWave) {
-                            int i = (t / j) * 2 * j + (t % j);
-                            int p = i + j;
-                            int32_t a = buf[i], b = buf[p];
-                            bool ascending = (i & k) == 0;
-                            if ((a > b) == ascending) {
-                                buf[i] = b;
-                                buf[p] = a;
-                            }
-                        }
-                        wave_sync();
-                    }
-                }
-                int32_t count = 0;
-                for (int base = 0; base < L; base += kWave) {
-                    int i = base + lane;
-                    int32_t x = i < L ? buf[i] : INT_MAX;
-                    bool keep = i < L && (i == 0 || x != buf[i - 1]);
-                    uint64_t mask = __ballot(keep);
-                    if (keep) r[count + lanes_below(mask)] = x;
-                    count += __popcll(mask);
-                }
-                if (lane == 0) ucnt[row] = count;
-                wave_sync();
+                if (L > 256) c = wave_sort_row_regs<8>(r, L);
+                else if (L > 128) c = wave_sort_row_regs<4>(r, L);
+                else if (L > 64) c = wave_sort_row_regs<2>(r, L);
+                else c = wave_sort_row_regs<1>(r, L);
             }
+            if (lane == 0) ucnt[row] = c;
         }
     }
+}
+
+// Rows per scan of k_sort_rows: all 64 lanes once the rows outnumber the
+// grid's waves 64 to 1, fewer (down to one) below.
+int32_t sort_span(int32_t n) {
+    const int64_t waves = (int64_t)cu_count() * 16 * kWavesPerBlock;
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(kWave, ((int64_t)n + waves - 1) / waves));
 }
 
 // One workgroup per long row: set one bit per entry in a bitmap over the
@@ -1042,13 +1011,15 @@ static gpm_status enqueue_build(int32_t n, const int32_t *d_u, const int32_t *d_
     hipLaunchKernelGGL(k_sort_small_rows, dim3(wave_grid(((int64_t)n + 3) / 4)), dim3(kBlock), 0,
                        st, L.raw_off, L.raw_adj, n, L.ucnt, L.med_list, L.big_list, L.flags);
     GPM_LAUNCH_CHECK("k_sort_small_rows");
-    hipLaunchKernelGGL(k_sort_rows<false>, dim3(wave_grid(((int64_t)n + kWave - 1) / kWave)),
-                       dim3(kBlock), 0, st, L.raw_off, L.raw_adj, n, L.ucnt, L.med_list,
-                       L.flags);
+    {
+        const int32_t span = sort_span(n);
+        hipLaunchKernelGGL(k_sort_rows<false>, dim3(wave_grid(((int64_t)n + span - 1) / span)),
+                           dim3(kBlock), 0, st, L.raw_off, L.raw_adj, n, span, L.ucnt, nullptr,
+                           L.flags);
+        hipLaunchKernelGGL(k_sort_rows<true>, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.raw_off,
+                           L.raw_adj, n, 1, L.ucnt, L.med_list, L.flags);
+    }
     GPM_LAUNCH_CHECK("k_sort_rows");
-    hipLaunchKernelGGL(k_sort_rows<true>, dim3(wave_grid(n)), dim3(kBlock), 0, st, L.raw_off,
-                       L.raw_adj, n, L.ucnt, L.med_list, L.flags);
-    GPM_LAUNCH_CHECK("k_sort_rows<lds>");
     if (n <= kLdsBitmapIds)
         hipLaunchKernelGGL(k_sort_big_rows_lds, dim3((unsigned)cu_count()), dim3(kBigNT),
                            (size_t)L.words * 4, st, L.raw_off, L.raw_adj, L.ucnt, L.big_list,
@@ -1068,6 +1039,60 @@ static gpm_status enqueue_build(int32_t n, const int32_t *d_u, const int32_t *d_
     GPM_HIP(degree_key(L.off, n, L.okey, st));
     hipLaunchKernelGGL(k_meta, dim3(1), dim3(64), 0, st, L.off, L.dag_off, n, L.flags, L.meta);
     GPM_LAUNCH_CHECK("k_meta");
+    return GPM_OK;
+}
+
+// Sorting the rows of any CSR in place with the build's sorters (rows of
+// distinct ids in [0, n) stay whole; duplicates would be dropped and counted
+// out in ucnt).  The work area: counts, the two row lists, the flags and
+// the bitmap sorters' bitmaps.
+struct RowSortArea {
+    int32_t *ucnt, *big_list, *med_list;
+    uint32_t *flags, *bitmaps;
+    int64_t words;
+    int nbig_blocks;
+};
+
+RowSortArea row_sort_layout(int32_t n, void *base, uint64_t *bytes) {
+    RowSortArea A{};
+    Carve c(base, ~0ull);
+    A.ucnt = c.take<int32_t>((uint64_t)n + 1);
+    A.big_list = c.take<int32_t>((uint64_t)n + 1);
+    A.med_list = c.take<int32_t>((uint64_t)n + 1);
+    A.flags = c.take<uint32_t>(F_WORDS);
+    A.words = ((int64_t)n + 31) / 32;
+    const int64_t per = A.words * 4;
+    const int64_t nb = (64ll << 20) / (per > 0 ? per : 1);
+    A.nbig_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, nb));
+    A.bitmaps = c.take<uint32_t>((uint64_t)A.words * A.nbig_blocks);
+    if (bytes) *bytes = c.used;
+    return A;
+}
+
+uint64_t row_sort_bytes(int32_t n) {
+    uint64_t b = 0;
+    row_sort_layout(n, nullptr, &b);
+    return b;
+}
+
+gpm_status sort_rows(const int32_t *off, int32_t *adj, int32_t n, void *area, hipStream_t st) {
+    RowSortArea A = row_sort_layout(n, area, nullptr);
+    GPM_HIP(fill_u32(A.flags, 0, F_WORDS, st));
+    hipLaunchKernelGGL(k_sort_small_rows, dim3(wave_grid(((int64_t)n + 3) / 4)), dim3(kBlock), 0,
+                       st, off, adj, n, A.ucnt, A.med_list, A.big_list, A.flags);
+    const int32_t span = sort_span(n);
+    hipLaunchKernelGGL(k_sort_rows<false>, dim3(wave_grid(((int64_t)n + span - 1) / span)),
+                       dim3(kBlock), 0, st, off, adj, n, span, A.ucnt, nullptr, A.flags);
+    hipLaunchKernelGGL(k_sort_rows<true>, dim3(wave_grid(n)), dim3(kBlock), 0, st, off, adj, n, 1,
+                       A.ucnt, A.med_list, A.flags);
+    if (n <= kLdsBitmapIds)
+        hipLaunchKernelGGL(k_sort_big_rows_lds, dim3((unsigned)cu_count()), dim3(kBigNT),
+                           (size_t)A.words * 4, st, off, adj, A.ucnt, A.big_list, A.flags,
+                           (int32_t)A.words);
+    else
+        hipLaunchKernelGGL(k_sort_big_rows, dim3(A.nbig_blocks), dim3(kBlock), 0, st, off, adj,
+                           A.ucnt, A.big_list, A.flags, A.bitmaps, A.words);
+    GPM_LAUNCH_CHECK("sort_rows");
     return GPM_OK;
 }
 
