@@ -43,6 +43,7 @@ constexpr int kPartZ = 8192;         // z-range per heavy task (LDS counters)
 constexpr int kYChunk = kBlock;      // in-neighbours staged per round
 constexpr int kListBlocks = 512;     // workgroups of the heavy listing kernel
 constexpr int kWedgeCap = 1 << 18;   // per-workgroup wedge buffer (>= max degree)
+constexpr int kListUnroll = 4;       // pairs per lane in flight when listing
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -928,6 +929,7 @@ __global__ void __launch_bounds__(kBlock) k_c4_heavy_list(const int32_t *__restr
     __shared__ int32_t s_pre[kYChunk + 1];
     __shared__ int32_t s_start[kYChunk];
     __shared__ int32_t s_sum[kWPB];
+    __shared__ int64_t s_pp[kWPB][kWave];   // per wave: first pair of each of its 64 z
     __shared__ uint32_t s_task, s_z;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     const uint64_t ntasks = (uint64_t)(*count_p) * (uint64_t)nparts;
@@ -1026,31 +1028,57 @@ __global__ void __launch_bounds__(kBlock) k_c4_heavy_list(const int32_t *__restr
             for (int i = tid; i < kPartZ; i += kBlock) cur[i] = 0u;
             __syncthreads();
             walk(z0 + za, z0 + zb, 1);
-            // emit: waves take z values of [za, zb) in turn
+            // emit: waves take 64 consecutive z of [za, zb) at a time and
+            // share out the pairs of middles of all of them, one per lane
+            // (most groups hold one or two pairs, so a wave per z would
+            // leave most lanes idle)
             if (tid == 0) s_z = (uint32_t)za;
             __syncthreads();
+            int64_t *pp = s_pp[wid];
             for (;;) {
-                uint32_t zi = 0;
-                if (lane == 0) zi = atomicAdd(&s_z, 1u);
-                zi = __shfl(zi, 0, 64);
-                if ((int32_t)zi >= zb) break;
-                const int32_t o = cnt[zi] - cnt[za], c = cnt[zi + 1] - cnt[zi];
-                const int64_t np = (int64_t)c * (c - 1) / 2;
-                for (int64_t qb = 0; qb < np; qb += kWave) {
-                    const int64_t q = qb + lane;
-                    const bool active = q < np;
-                    int32_t y1 = 0, y2 = 0;
-                    if (active) {
-                        // q -> (i, j), i < j, q = j (j - 1) / 2 + i
-                        int64_t j = (int64_t)((1.0 + sqrt(1.0 + 8.0 * (double)q)) * 0.5);
-                        while (j * (j - 1) / 2 > q) j--;
-                        while ((j + 1) * j / 2 <= q) j++;
-                        const int64_t i = q - j * (j - 1) / 2;
-                        y1 = buf[o + i];
-                        y2 = buf[o + j];
+                uint32_t z1 = 0;
+                if (lane == 0) z1 = atomicAdd(&s_z, (uint32_t)kWave);
+                z1 = __shfl(z1, 0, 64);
+                if ((int32_t)z1 >= zb) break;
+                const int32_t zl = (int32_t)z1 + lane;
+                const int32_t cl = zl < zb ? cnt[zl + 1] - cnt[zl] : 0;
+                const int64_t npl = (int64_t)cl * (cl - 1) / 2;
+                const int64_t incl = wave_incl_scan(npl);
+                pp[lane] = incl - npl;   // first pair of this lane's z
+                const int64_t total = __shfl(incl, kWave - 1, 64);
+                wave_sync();
+                // kListUnroll pairs per lane per step: their middles' loads
+                // go out together before any is hashed
+                for (int64_t qb = 0; qb < total; qb += kWave * kListUnroll) {
+                    int32_t y1[kListUnroll], y2[kListUnroll], zz[kListUnroll];
+#pragma unroll
+                    for (int u = 0; u < kListUnroll; u++) {
+                        const int64_t q = qb + u * kWave + lane;
+                        y1[u] = y2[u] = zz[u] = 0;
+                        if (q < total) {
+                            // the lane (z) holding pair q: last l with pp[l] <= q
+                            int32_t l = 0;
+#pragma unroll
+                            for (int h = kWave / 2; h > 0; h >>= 1)
+                                if (pp[l + h] <= q) l += h;
+                            const int64_t r = q - pp[l];
+                            zz[u] = (int32_t)z1 + l;
+                            const int32_t o = cnt[zz[u]] - cnt[za];
+                            // r -> (i, j), i < j, r = j (j - 1) / 2 + i; the
+                            // single-precision root is off by at most one here
+                            int64_t j = (int64_t)((1.0f + sqrtf(1.0f + 8.0f * (float)r)) * 0.5f);
+                            while (j * (j - 1) / 2 > r) j--;
+                            while ((j + 1) * j / 2 <= r) j++;
+                            const int64_t i = r - j * (j - 1) / 2;
+                            y1[u] = buf[o + i];
+                            y2[u] = buf[o + j];
+                        }
                     }
-                    emit_c4(em, active, x, y1, z0 + (int32_t)zi, y2);
+#pragma unroll
+                    for (int u = 0; u < kListUnroll; u++)
+                        emit_c4(em, qb + u * kWave + lane < total, x, y1[u], z0 + zz[u], y2[u]);
                 }
+                wave_sync();
             }
             __syncthreads();
             za = zb;
