@@ -1047,36 +1047,54 @@ __global__ void __launch_bounds__(kBlock) k_c4_heavy_list(const int32_t *__restr
                 pp[lane] = incl - npl;   // first pair of this lane's z
                 const int64_t total = __shfl(incl, kWave - 1, 64);
                 wave_sync();
-                // kListUnroll pairs per lane per step: their middles' loads
-                // go out together before any is hashed
+                // each lane takes kListUnroll consecutive pairs per step:
+                // it decodes the first and steps through the rest (a new z's
+                // pairs start at (0, 1)), and their middles' loads go out
+                // together before any is hashed
                 for (int64_t qb = 0; qb < total; qb += kWave * kListUnroll) {
+                    const int64_t q0 = qb + (int64_t)lane * kListUnroll;
                     int32_t y1[kListUnroll], y2[kListUnroll], zz[kListUnroll];
+                    int32_t l = 0, o = 0, c = 0, i = 0, j = 0;
+                    // the lane (z) holding pair q: last l with pp[l] <= q
+                    auto find = [&](int64_t q) {
+                        l = 0;
+#pragma unroll
+                        for (int h = kWave / 2; h > 0; h >>= 1)
+                            if (pp[l + h] <= q) l += h;
+                        o = cnt[(int32_t)z1 + l] - cnt[za];
+                        c = cnt[(int32_t)z1 + l + 1] - cnt[(int32_t)z1 + l];
+                    };
+                    if (q0 < total) {
+                        find(q0);
+                        // r -> (i, j), i < j, r = j (j - 1) / 2 + i; the
+                        // single-precision root is off by at most one here
+                        const int64_t r = q0 - pp[l];
+                        int64_t jj = (int64_t)((1.0f + sqrtf(1.0f + 8.0f * (float)r)) * 0.5f);
+                        while (jj * (jj - 1) / 2 > r) jj--;
+                        while ((jj + 1) * jj / 2 <= r) jj++;
+                        j = (int32_t)jj;
+                        i = (int32_t)(r - jj * (jj - 1) / 2);
+                    }
 #pragma unroll
                     for (int u = 0; u < kListUnroll; u++) {
-                        const int64_t q = qb + u * kWave + lane;
+                        const int64_t q = q0 + u;
                         y1[u] = y2[u] = zz[u] = 0;
                         if (q < total) {
-                            // the lane (z) holding pair q: last l with pp[l] <= q
-                            int32_t l = 0;
-#pragma unroll
-                            for (int h = kWave / 2; h > 0; h >>= 1)
-                                if (pp[l + h] <= q) l += h;
-                            const int64_t r = q - pp[l];
+                            if (u > 0 && ++i == j) {
+                                i = 0;
+                                if (++j == c) {   // this z's pairs are done
+                                    find(q);
+                                    j = 1;
+                                }
+                            }
                             zz[u] = (int32_t)z1 + l;
-                            const int32_t o = cnt[zz[u]] - cnt[za];
-                            // r -> (i, j), i < j, r = j (j - 1) / 2 + i; the
-                            // single-precision root is off by at most one here
-                            int64_t j = (int64_t)((1.0f + sqrtf(1.0f + 8.0f * (float)r)) * 0.5f);
-                            while (j * (j - 1) / 2 > r) j--;
-                            while ((j + 1) * j / 2 <= r) j++;
-                            const int64_t i = r - j * (j - 1) / 2;
                             y1[u] = buf[o + i];
                             y2[u] = buf[o + j];
                         }
                     }
 #pragma unroll
                     for (int u = 0; u < kListUnroll; u++)
-                        emit_c4(em, qb + u * kWave + lane < total, x, y1[u], z0 + zz[u], y2[u]);
+                        emit_c4(em, q0 + u < total, x, y1[u], z0 + zz[u], y2[u]);
                 }
                 wave_sync();
             }
