@@ -43,7 +43,7 @@ constexpr int kPartZ = 8192;         // z-range per heavy task (LDS counters)
 constexpr int kYChunk = kBlock;      // in-neighbours staged per round
 constexpr int kListBlocks = 512;     // workgroups of the heavy listing kernel
 constexpr int kWedgeCap = 1 << 18;   // per-workgroup wedge buffer (>= max degree)
-constexpr int kListUnroll = 4;       // pairs per lane in flight when listing
+constexpr int kListUnroll = 8;       // pairs per lane in flight when listing
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
