@@ -35,6 +35,7 @@ typedef unsigned __int128 u128;
 constexpr int kBlock = 256;
 constexpr int kWPB = kBlock / kWave;
 constexpr int64_t kPairChunk = 1 << 16;
+constexpr int kPairUnroll = 8;   // consecutive pairs per lane when listing
 
 __device__ __forceinline__ int lower_bound_i32(const int32_t *a, int n, int32_t x) {
     int lo = 0, hi = n;
@@ -161,48 +162,70 @@ __global__ void __launch_bounds__(kBlock) k_diamond_list(const int32_t *__restri
                 t += __popcll(mask);
             }
             wave_sync();
-            for (int64_t qb = q0; qb < q1; qb += kWave) {
-                const int64_t q = qb + lane;
-                const bool active = q < q1;
-                int32_t cc = 0, dd = 0;
-                uint64_t h = 0;
-                if (active) {
-                    int64_t j = (int64_t)((1.0 + sqrt(1.0 + 8.0 * (double)q)) * 0.5);
-                    while (j * (j - 1) / 2 > q) j--;
-                    while ((j + 1) * j / 2 <= q) j++;
-                    const int64_t i = q - j * (j - 1) / 2;
-                    cc = com[i];
-                    dd = com[j];
-                    uint64_t k[5] = {edge_code(a, b), edge_code(a, cc), edge_code(a, dd),
-                                     edge_code(b, cc), edge_code(b, dd)};
+            // each lane takes kPairUnroll consecutive pairs (i, j), i < j,
+            // of the common neighbours: it decodes the first and steps
+            for (int64_t qb = q0; qb < q1; qb += kWave * kPairUnroll) {
+                const int64_t qs = qb + (int64_t)lane * kPairUnroll;
+                int32_t i = 0, j = 0;
+                if (qs < q1) {
+                    // q = j (j - 1) / 2 + i; the single-precision root is off
+                    // by at most one here
+                    int64_t jj = (int64_t)((1.0f + sqrtf(1.0f + 8.0f * (float)qs)) * 0.5f);
+                    while (jj * (jj - 1) / 2 > qs) jj--;
+                    while ((jj + 1) * jj / 2 <= qs) jj++;
+                    j = (int32_t)jj;
+                    i = (int32_t)(qs - jj * (jj - 1) / 2);
+                }
+                int32_t cc[kPairUnroll], dd[kPairUnroll];
 #pragma unroll
-                    for (int x = 1; x < 5; x++)
-#pragma unroll
-                        for (int y = 4; y >= x; y--) {
-                            const uint64_t lo = k[y - 1] < k[y] ? k[y - 1] : k[y];
-                            const uint64_t hi = k[y - 1] < k[y] ? k[y] : k[y - 1];
-                            k[y - 1] = lo;
-                            k[y] = hi;
+                for (int u = 0; u < kPairUnroll; u++) {
+                    cc[u] = dd[u] = 0;
+                    if (qs + u < q1) {
+                        if (u > 0 && ++i == j) {
+                            i = 0;
+                            ++j;
                         }
-                    h = 5;
+                        cc[u] = com[i];
+                        dd[u] = com[j];
+                    }
+                }
 #pragma unroll
-                    for (int x = 0; x < 5; x++) h = fmix64((h ^ k[x]) + 0x9E3779B97F4A7C15ull);
-                }
-                const uint64_t mask = __ballot(active);
-                const int n = __popcll(mask);
-                unsigned long long base = out.cap;
-                if (cached < out.cap) {
-                    if (lane == 0) base = atomicAdd(out.slot_ctr, (unsigned long long)n);
-                    base = __shfl(base, 0, 64);
-                    cached = base + n;
-                }
-                if (active) {
-                    count++;
-                    hsum += h;
-                    const uint64_t slot = base + lanes_below(mask);
-                    if (slot < out.cap) {
-                        int32_t *o = out.buf + slot * 4;
-                        o[0] = a; o[1] = b; o[2] = cc; o[3] = dd;
+                for (int u = 0; u < kPairUnroll; u++) {
+                    const bool active = qs + u < q1;
+                    uint64_t h = 0;
+                    if (active) {
+                        uint64_t k[5] = {edge_code(a, b), edge_code(a, cc[u]), edge_code(a, dd[u]),
+                                         edge_code(b, cc[u]), edge_code(b, dd[u])};
+#pragma unroll
+                        for (int x = 1; x < 5; x++)
+#pragma unroll
+                            for (int y = 4; y >= x; y--) {
+                                const uint64_t lo = k[y - 1] < k[y] ? k[y - 1] : k[y];
+                                const uint64_t hi = k[y - 1] < k[y] ? k[y] : k[y - 1];
+                                k[y - 1] = lo;
+                                k[y] = hi;
+                            }
+                        h = 5;
+#pragma unroll
+                        for (int x = 0; x < 5; x++) h = fmix64((h ^ k[x]) + 0x9E3779B97F4A7C15ull);
+                    }
+                    const uint64_t mask = __ballot(active);
+                    if (!mask) continue;
+                    const int n = __popcll(mask);
+                    unsigned long long base = out.cap;
+                    if (cached < out.cap) {
+                        if (lane == 0) base = atomicAdd(out.slot_ctr, (unsigned long long)n);
+                        base = __shfl(base, 0, 64);
+                        cached = base + n;
+                    }
+                    if (active) {
+                        count++;
+                        hsum += h;
+                        const uint64_t slot = base + lanes_below(mask);
+                        if (slot < out.cap) {
+                            int32_t *o = out.buf + slot * 4;
+                            o[0] = a; o[1] = b; o[2] = cc[u]; o[3] = dd[u];
+                        }
                     }
                 }
             }
