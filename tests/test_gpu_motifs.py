@@ -94,3 +94,33 @@ def test_four_cycle_counter_widths(gpm):
     c4 = C(2, 2) * C(70000, 2)
     assert gpm.count(g, gpm.cycle4()) == c4
     assert gpm.motif_count(g, 4) == [2 * C(70000, 3), 0, c4, 0, 0, 0]
+
+
+def test_four_cycles_without_part_table(gpm):
+    """A 5,000,000-vertex graph, too large for the heavy 4-cycle kernel's part
+    table (parts x n x 8 B above 2 GiB), so each middle's segment of a z-part
+    is found by binary search.  40 hubs joined to the same 300 middles and to
+    1,000 leaves each, every middle with 300 leaves of its own, the rest
+    isolated, ids scattered by a seeded permutation: the hubs' wedges end in
+    other hubs and in 90,000 middles' leaves, whose low ranks spread over
+    several parts.  The 4-cycles are those of K_{40,300}: C(40,2) C(300,2);
+    all six 4-motif counts against the oracle."""
+    n, hubs, mids, hub_leaves, mid_leaves = 5_000_000, 40, 300, 1000, 300
+    h = np.arange(hubs, dtype=np.int64)
+    m = hubs + np.arange(mids, dtype=np.int64)
+    u = [np.repeat(h, mids)]
+    v = [np.tile(m, hubs)]
+    base = hubs + mids
+    u.append(np.repeat(h, hub_leaves))
+    v.append(base + np.arange(hubs * hub_leaves, dtype=np.int64))
+    base += hubs * hub_leaves
+    u.append(np.repeat(m, mid_leaves))
+    v.append(base + np.arange(mids * mid_leaves, dtype=np.int64))
+    e = graphgen.EdgeList(n, np.concatenate(u).astype(np.int32),
+                          np.concatenate(v).astype(np.int32), "hubs_mids_leaves")
+    e = graphgen.relabel(e, 7)
+    print(f"four cycles without part table: n={e.n} m={e.u.shape[0]}", flush=True)
+    g = build(gpm, e)
+    assert gpm.count(g, gpm.cycle4()) == C(hubs, 2) * C(mids, 2)
+    off, adj = canonical_csr(e.n, e.u, e.v)
+    assert gpm.motif_count(g, 4) == oracle.motif4(off, adj)
