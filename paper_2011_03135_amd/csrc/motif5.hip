@@ -40,10 +40,16 @@
 // (each derived by counting the choices of the pattern's free vertices
 // around a cut vertex, a cut edge, a 4-cycle or a triangle, and subtracting
 // the choices that collide: a chord of a 4-cycle, a fourth vertex closing a
-// K4).  The other six, whose induced copies are far fewer (the 5-cycle,
-// K_{2,3}, two triangles on an edge whose tips share a third neighbour, the
-// wheel, K5 minus an edge and K5), are counted directly as induced
-// patterns: by the general plan, K5 by the clique kernels.
+// K4).  A sixteenth, the 5-cycle, comes from closed walks (Harary and
+// Manvel, 1971): a closed 5-walk is a 5-cycle (ten walks each) or a
+// triangle with one edge walked back and forth at one of its vertices, so
+//   5-cycle     [tr(A^5) - 30 T - 10 sum_v (d_v - 2) t_v] / 10
+// with tr(A^5) from each vertex's row of A^2 (graphs of up to kTrace5MaxN
+// vertices; above, the 5-cycle is counted directly).  The other five,
+// whose induced copies are far fewer (K_{2,3}, two triangles on an edge
+// whose tips share a third neighbour, the wheel, K5 minus an edge and K5),
+// are counted directly as induced patterns: by the general plan, K5 by the
+// clique kernels.
 #include "gpm_internal.h"
 
 #include <algorithm>
@@ -77,8 +83,11 @@ constexpr int kBlock = 256;
 
 // Classes with a closed form, and the accumulator pair (plus, minus) of each.
 enum Formula : int { F_STAR, F_CHAIR, F_PATH, F_CRICKET, F_BULL, F_BANNER, F_TADPOLE, F_DART,
-                     F_KITE, F_BOWTIE, F_HOUSE, F_K4PEND, F_BOOK, F_GEM, F_K4TWO, F_COUNT };
-constexpr int kFormulaClass[F_COUNT] = {0, 1, 2, 3, 4, 5, 6, 8, 9, 11, 12, 13, 14, 15, 17};
+                     F_KITE, F_BOWTIE, F_HOUSE, F_K4PEND, F_BOOK, F_GEM, F_K4TWO, F_C5, F_COUNT };
+constexpr int kFormulaClass[F_COUNT] = {0, 1, 2, 3, 4, 5, 6, 8, 9, 11, 12, 13, 14, 15, 17, 7};
+// the 5-cycle's formula needs tr(A^5), from dense 2-walk rows in LDS: graphs
+// of up to kTrace5MaxN vertices (above, the 5-cycle is counted directly)
+constexpr int32_t kTrace5MaxN = 16384;
 constexpr int kK5Class = 20;
 
 struct Back {
@@ -150,6 +159,8 @@ __global__ void __launch_bounds__(kBlock) k_f5_vertex(const int32_t *__restrict_
         plus[F_TADPOLE] += (u128)t * (s - d);
         minus[F_TADPOLE] += (u128)2 * t * d;
         plus[F_BOWTIE] += binom2(t);
+        // 5-cycles: 10 sum_v (d_v - 2) t_v, with t2 = 2 t_v
+        if (d >= 2) minus[F_C5] += (u128)5 * (d - 2) * t2[v];
     }
 #pragma unroll
     for (int f = 0; f < F_COUNT; f++) {
@@ -159,6 +170,55 @@ __global__ void __launch_bounds__(kBlock) k_f5_vertex(const int32_t *__restrict_
             if (mm) atomic_add_u128(acc + A_MINUS + 2 * f, mm);
         }
     }
+}
+
+// tr(A^5) = sum over vertices i of the closed 5-walks at i,
+//   (A^5)_ii = sum over j of P2(i, j) sum over k in N(j) of P2(i, k)
+// with P2(i, .) = row i of A^2 (2-walk counts; A^2 is symmetric).  A
+// workgroup per vertex i builds P2(i, .) densely in LDS (n entries) and
+// lists the j it reaches, sums over the listed j and their neighbours, then
+// clears what it set.  P2 <= n, so each product fits 64 bits; the sums are
+// 128-bit.
+__global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict__ off,
+                                                      const int32_t *__restrict__ adj, int32_t n,
+                                                      unsigned long long *acc) {
+    extern __shared__ uint32_t s_dyn[];
+    uint32_t *p2 = s_dyn;                               // n counters
+    int32_t *reach = reinterpret_cast<int32_t *>(s_dyn + n);   // the j with P2 > 0
+    __shared__ uint32_t s_nreach;
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    constexpr int NW = kBlock / kWave;
+    for (int32_t i = tid; i < n; i += kBlock) p2[i] = 0;
+    if (tid == 0) s_nreach = 0;
+    __syncthreads();
+    u128 tr = 0;
+    for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int32_t si = off[i], di = off[i + 1] - si;
+        // 2-walks i - x - j: a wave per middle x, lanes over N(x)
+        for (int32_t a = wid; a < di; a += NW) {
+            const int32_t x = adj[si + a], sx = off[x], dx = off[x + 1] - sx;
+            for (int32_t b = lane; b < dx; b += kWave) {
+                const int32_t j = adj[sx + b];
+                if (atomicAdd(&p2[j], 1u) == 0u) reach[atomicAdd(&s_nreach, 1u)] = j;
+            }
+        }
+        __syncthreads();
+        const int32_t nr = (int32_t)s_nreach;
+        // sum over the reached j of P2(i, j) times the P2 of j's neighbours
+        for (int32_t r = wid; r < nr; r += NW) {
+            const int32_t j = reach[r], sj = off[j], dj = off[j + 1] - sj;
+            const uint64_t pj = p2[j];
+            uint64_t sum = 0;
+            for (int32_t b = lane; b < dj; b += kWave) sum += p2[adj[sj + b]];
+            tr += (u128)(pj * sum);
+        }
+        __syncthreads();
+        for (int32_t r = tid; r < nr; r += kBlock) p2[reach[r]] = 0;
+        if (tid == 0) s_nreach = 0;
+        __syncthreads();
+    }
+    tr = wave_sum_u128(tr);
+    if (lane == 0 && tr) atomic_add_u128(acc + A_PLUS + 2 * F_C5, tr);
 }
 
 // One thread per undirected edge (an arc of the DAG): the edge terms.
@@ -374,8 +434,13 @@ __global__ void k_f5_combine(const unsigned long long *acc, Back B, unsigned lon
         }
         if (f == F_HOUSE) p += cyc_tri;
         if (f == F_KITE || f == F_GEM) mm += 12 * k4;
+        if (f == F_C5) mm += 30 * T;   // 5 tr(A^3) = 30 T
         if (p < mm) bad |= 1;
         N[h] = p - mm;
+        if (f == F_C5) {   // ten closed 5-walks per 5-cycle
+            if (N[h] % 10) bad |= 1;
+            N[h] /= 10;
+        }
     }
     // densest first: a direct class is its count, a formula class its N
     // minus the copies inside denser induced subgraphs
@@ -515,9 +580,13 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
     if (k != 5) return fail(GPM_UNSUPPORTED, "formula motif counting is for k = 5");
     F5Ws W = f5_layout(g, ws);
     if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
-    const Back &B = back_matrix();
+    // the 5-cycle by its trace formula where the 2-walk rows fit in LDS,
+    // else counted directly
+    Back B = back_matrix();
     const int32_t n = g->n;
     const int64_t m = g->m;
+    const bool trace5 = n <= kTrace5MaxN;
+    if (!trace5) B.formula_of[kFormulaClass[F_C5]] = -1;
     GPM_HIP(fill_u32(W.acc, 0, 2 * (uint64_t)A_WORDS, st));
     GPM_HIP(fill_u32(W.t2, 0, 2 * ((uint64_t)n + 1), st));
     if (m > 0) GPM_HIP(fill_u32(W.te, 0, (uint64_t)m, st));
@@ -542,6 +611,15 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
                            st, g->off, g->adj, n, W.t2, W.acc);
     }
     GPM_LAUNCH_CHECK("k_f5_local");
+    if (trace5 && m > 0) {
+        Span sp("k_f5_trace5", st);
+        const size_t shmem = (size_t)n * 8;   // P2 counters and the reached list
+        const int per_cu =
+            (int)std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / (int64_t)(shmem + 1024)));
+        hipLaunchKernelGGL(k_f5_trace5, dim3(grid_for(n, 1, per_cu)), dim3(kBlock), shmem, st,
+                           g->off, g->adj, n, W.acc);
+    }
+    GPM_LAUNCH_CHECK("k_f5_trace5");
     // 4-cycles (edge sets) and the sums over them
     rc = c4_run(g, false, W.shared, W.shared_bytes, W.acc + A_C4, nullptr, 0, nullptr, st,
                 W.tsym, W.acc + A_CYC);
