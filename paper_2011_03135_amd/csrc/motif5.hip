@@ -44,12 +44,15 @@
 // Manvel, 1971): a closed 5-walk is a 5-cycle (ten walks each) or a
 // triangle with one edge walked back and forth at one of its vertices, so
 //   5-cycle     [tr(A^5) - 30 T - 10 sum_v (d_v - 2) t_v] / 10
-// with tr(A^5) from each vertex's row of A^2 (graphs of up to kTrace5MaxN
-// vertices; above, the 5-cycle is counted directly).  The other five,
-// whose induced copies are far fewer (K_{2,3}, two triangles on an edge
-// whose tips share a third neighbour, the wheel, K5 minus an edge and K5),
-// are counted directly as induced patterns: by the general plan, K5 by the
-// clique kernels.
+// with tr(A^5) from each vertex's row of A^2, and a seventeenth from the
+// same rows: a K_{2,3} is its two degree-3 vertices and three of their
+// common neighbours,
+//   K_{2,3}     sum over vertex pairs u < v of C(c(u, v), 3)
+// with c(u, v) = (A^2)_uv (graphs of up to kTrace5MaxN vertices; above,
+// both are counted directly).  The other four, whose induced copies are
+// far fewer (two triangles on an edge whose tips share a third neighbour,
+// the wheel, K5 minus an edge and K5), are counted directly as induced
+// patterns: by the general plan, K5 by the clique kernels.
 #include "gpm_internal.h"
 
 #include <algorithm>
@@ -83,10 +86,12 @@ constexpr int kBlock = 256;
 
 // Classes with a closed form, and the accumulator pair (plus, minus) of each.
 enum Formula : int { F_STAR, F_CHAIR, F_PATH, F_CRICKET, F_BULL, F_BANNER, F_TADPOLE, F_DART,
-                     F_KITE, F_BOWTIE, F_HOUSE, F_K4PEND, F_BOOK, F_GEM, F_K4TWO, F_C5, F_COUNT };
-constexpr int kFormulaClass[F_COUNT] = {0, 1, 2, 3, 4, 5, 6, 8, 9, 11, 12, 13, 14, 15, 17, 7};
-// the 5-cycle's formula needs tr(A^5), from dense 2-walk rows in LDS: graphs
-// of up to kTrace5MaxN vertices (above, the 5-cycle is counted directly)
+                     F_KITE, F_BOWTIE, F_HOUSE, F_K4PEND, F_BOOK, F_GEM, F_K4TWO, F_C5, F_K23,
+                     F_COUNT };
+constexpr int kFormulaClass[F_COUNT] = {0, 1, 2, 3, 4, 5, 6, 8, 9, 11, 12, 13, 14, 15, 17, 7, 10};
+// the 5-cycle's and K_{2,3}'s formulas need each vertex's row of A^2, dense
+// in LDS: graphs of up to kTrace5MaxN vertices (above, both are counted
+// directly)
 constexpr int32_t kTrace5MaxN = 16384;
 constexpr int kK5Class = 20;
 
@@ -174,7 +179,9 @@ __global__ void __launch_bounds__(kBlock) k_f5_vertex(const int32_t *__restrict_
 
 // tr(A^5) = sum over vertices i of the closed 5-walks at i,
 //   (A^5)_ii = sum over j of P2(i, j) sum over k in N(j) of P2(i, k)
-// with P2(i, .) = row i of A^2 (2-walk counts; A^2 is symmetric).  A
+// with P2(i, .) = row i of A^2 (2-walk counts; A^2 is symmetric), and
+// N(K_{2,3}) = sum over vertex pairs i < j of C(P2(i, j), 3) (a K_{2,3} is
+// its two degree-3 vertices and three of their common neighbours).  A
 // workgroup per vertex i builds P2(i, .) densely in LDS (n entries) and
 // lists the j it reaches, sums over the listed j and their neighbours, then
 // clears what it set.  P2 <= n, so each product fits 64 bits; the sums are
@@ -191,7 +198,7 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
     for (int32_t i = tid; i < n; i += kBlock) p2[i] = 0;
     if (tid == 0) s_nreach = 0;
     __syncthreads();
-    u128 tr = 0;
+    u128 tr = 0, k23 = 0;
     for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
         const int32_t si = off[i], di = off[i + 1] - si;
         // 2-walks i - x - j: a wave per middle x, lanes over N(x)
@@ -204,6 +211,11 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
         }
         __syncthreads();
         const int32_t nr = (int32_t)s_nreach;
+        for (int32_t r = tid; r < nr; r += kBlock) {
+            const int32_t j = reach[r];
+            const uint64_t c = p2[j];
+            if (j > i && c >= 3) k23 += (u128)(c * (c - 1) * (c - 2) / 6);
+        }
         // sum over the reached j of P2(i, j) times the P2 of j's neighbours
         for (int32_t r = wid; r < nr; r += NW) {
             const int32_t j = reach[r], sj = off[j], dj = off[j + 1] - sj;
@@ -218,7 +230,9 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
         __syncthreads();
     }
     tr = wave_sum_u128(tr);
+    k23 = wave_sum_u128(k23);
     if (lane == 0 && tr) atomic_add_u128(acc + A_PLUS + 2 * F_C5, tr);
+    if (lane == 0 && k23) atomic_add_u128(acc + A_PLUS + 2 * F_K23, k23);
 }
 
 // One thread per undirected edge (an arc of the DAG): the edge terms.
@@ -580,13 +594,16 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
     if (k != 5) return fail(GPM_UNSUPPORTED, "formula motif counting is for k = 5");
     F5Ws W = f5_layout(g, ws);
     if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
-    // the 5-cycle by its trace formula where the 2-walk rows fit in LDS,
+    // the 5-cycle and K_{2,3} from the rows of A^2 where they fit in LDS,
     // else counted directly
     Back B = back_matrix();
     const int32_t n = g->n;
     const int64_t m = g->m;
     const bool trace5 = n <= kTrace5MaxN;
-    if (!trace5) B.formula_of[kFormulaClass[F_C5]] = -1;
+    if (!trace5) {
+        B.formula_of[kFormulaClass[F_C5]] = -1;
+        B.formula_of[kFormulaClass[F_K23]] = -1;
+    }
     GPM_HIP(fill_u32(W.acc, 0, 2 * (uint64_t)A_WORDS, st));
     GPM_HIP(fill_u32(W.t2, 0, 2 * ((uint64_t)n + 1), st));
     if (m > 0) GPM_HIP(fill_u32(W.te, 0, (uint64_t)m, st));

@@ -1,7 +1,8 @@
-"""The closed-walk form of the 5-cycle count that the 5-motif formula route
-uses (Harary and Manvel, 1971): a closed walk of length 5 either runs once
-around a 5-cycle (ten such walks per cycle: five starts, two directions) or
-goes around a triangle with one edge walked back and forth, so
+"""Closed forms the 5-motif formula route takes from the rows of A^2.  The
+5-cycle count from closed walks (Harary and Manvel, 1971): a closed walk of
+length 5 either runs once around a 5-cycle (ten such walks per cycle: five
+starts, two directions) or goes around a triangle with one edge walked back
+and forth, so
 
     N(C5) = [tr(A^5) - 5 tr(A^3) - 5 sum_v (d_v - 2) (A^3)_vv] / 10,
 
@@ -9,7 +10,8 @@ and with (A^3)_vv = 2 t_v, tr(A^3) = 6 T this is
 [tr(A^5) - 30 T - 10 sum_v (d_v - 2) t_v] / 10.  Checked here, on the CPU,
 against brute force over 5-vertex subsets and against the oracle's
 edge-induced pattern count, on graphs whose 5-cycle counts are also known
-in closed form."""
+in closed form.  And K_{2,3}: the sum over vertex pairs of C(common
+neighbours, 3)."""
 from itertools import combinations, permutations
 
 import numpy as np
@@ -85,5 +87,43 @@ def test_five_cycle_closed_walk_formula(case, closed):
     assert f == oracle.pattern_count(off, adj, 5, C5, induced=False)[0]
     if e.n <= 14:
         assert f == brute_c5(e.n, e.u, e.v)
+    if closed is not None:
+        assert f == closed
+
+
+K23 = [(0, 2), (0, 3), (0, 4), (1, 2), (1, 3), (1, 4)]
+
+
+def formula_k23(n, u, v):
+    """K_{2,3} edge sets: a pair of vertices (the degree-3 side) and three of
+    their common neighbours, so the sum over pairs of C(common, 3)."""
+    from math import comb
+    A = np.zeros((n, n), dtype=np.int64)
+    for a, b in zip(u, v):
+        if a != b:
+            A[a, b] = A[b, a] = 1
+    A2 = A @ A
+    iu = np.triu_indices(n, 1)
+    return sum(comb(int(c), 3) for c in A2[iu])
+
+
+@pytest.mark.parametrize("case,closed", [
+    ("k5", 10),          # C(5, 2) pairs, the other three vertices
+    ("k33", 6),          # a pair on one side, the whole other side
+    ("k28", 56),         # the pair of the 2-side, C(8, 3)
+    ("petersen", 0),     # two vertices share at most one neighbour
+    ("er14", None),
+    ("rmat6", None),
+])
+def test_k23_pair_formula(case, closed):
+    e = {"k5": lambda: graphgen.complete_graph(5),
+         "k33": lambda: graphgen.complete_bipartite(3, 3),
+         "k28": lambda: graphgen.complete_bipartite(2, 8),
+         "petersen": petersen,
+         "er14": lambda: graphgen.erdos_renyi(14, 0.4, 6),
+         "rmat6": lambda: graphgen.rmat(6, edge_factor=4, seed=6)}[case]()
+    f = formula_k23(e.n, e.u, e.v)
+    off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+    assert f == oracle.pattern_count(off, adj, 5, K23, induced=False)[0]
     if closed is not None:
         assert f == closed
