@@ -450,28 +450,23 @@ constexpr int kSegMaxParts = 256;    // part table only for graphs of at most 25
 constexpr uint64_t kSegMaxBytes = 2ull << 30;
 
 // Part table: seg[p * n + y] = {first entry of row y with value >= p * zpart,
-// number of entries of row y with value in part p}.
+// number of entries of row y with value in part p}.  A thread per row finds
+// each part's first entry by a binary search from the previous one, so the
+// threads of a wave write consecutive entries of each part's table row.
 __global__ void __launch_bounds__(kBlock) k_c4_seg(const int32_t *__restrict__ off,
                                                    const int32_t *__restrict__ adj, int32_t n,
                                                    int32_t nparts, int32_t zpart, int2 *seg) {
-    __shared__ int32_t s_bnd[kWPB][kSegMaxParts + 1];
-    const int lane = lane_id();
-    int32_t *bnd = s_bnd[threadIdx.x / kWave];
-    const int64_t wave0 = (int64_t)blockIdx.x * kWPB + threadIdx.x / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * kWPB;
-    for (int64_t y = wave0; y < n; y += nwaves) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t y = (int64_t)blockIdx.x * kBlock + threadIdx.x; y < n; y += stride) {
         const int32_t s = off[y], d = off[y + 1] - s;
-        for (int32_t i = lane; i < d; i += kWave) {
-            const int32_t pc = adj[s + i] / zpart;
-            const int32_t pp = i == 0 ? -1 : adj[s + i - 1] / zpart;
-            for (int32_t q = pp + 1; q <= pc; q++) bnd[q] = i;
+        int32_t lo = 0;
+        for (int32_t q = 0; q < nparts; q++) {
+            const int64_t zend = (int64_t)(q + 1) * zpart;
+            const int32_t hi = zend >= n ? d
+                                          : lo + lower_bound_i32(adj + s + lo, d - lo, (int32_t)zend);
+            seg[(int64_t)q * n + y] = make_int2(s + lo, hi - lo);
+            lo = hi;
         }
-        const int32_t plast = d > 0 ? adj[s + d - 1] / zpart : -1;
-        for (int32_t q = plast + 1 + lane; q <= nparts; q += kWave) bnd[q] = d;
-        wave_sync();
-        for (int32_t q = lane; q < nparts; q += kWave)
-            seg[(int64_t)q * n + y] = make_int2(s + bnd[q], bnd[q + 1] - bnd[q]);
-        wave_sync();
     }
 }
 
@@ -1263,7 +1258,7 @@ gpm_status c4_run(const gpm_graph *g, bool list, void *ws, uint64_t ws_bytes,
         if (rc) return rc;
         const int32_t cparts = count_parts(g);
         if (W.seg)
-            hipLaunchKernelGGL(k_c4_seg, dim3(grid_for(n, kWPB, 8)), dim3(kBlock), 0, st, W.roff,
+            hipLaunchKernelGGL(k_c4_seg, dim3(grid_for(n, kBlock, 8)), dim3(kBlock), 0, st, W.roff,
                                W.radj, n, cparts, count_zpart(g), W.seg);
         GPM_LAUNCH_CHECK("k_c4_seg");
         const int narrow = narrow_counts(g) ? 1 : 0;
