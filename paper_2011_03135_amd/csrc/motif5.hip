@@ -87,11 +87,12 @@ constexpr int kBlock = 256;
 // Classes with a closed form, and the accumulator pair (plus, minus) of each.
 enum Formula : int { F_STAR, F_CHAIR, F_PATH, F_CRICKET, F_BULL, F_BANNER, F_TADPOLE, F_DART,
                      F_KITE, F_BOWTIE, F_HOUSE, F_K4PEND, F_BOOK, F_GEM, F_K4TWO, F_C5, F_K23,
-                     F_COUNT };
-constexpr int kFormulaClass[F_COUNT] = {0, 1, 2, 3, 4, 5, 6, 8, 9, 11, 12, 13, 14, 15, 17, 7, 10};
-// the 5-cycle's and K_{2,3}'s formulas need each vertex's row of A^2, dense
-// in LDS: graphs of up to kTrace5MaxN vertices (above, both are counted
-// directly)
+                     F_TWIN, F_COUNT };
+constexpr int kFormulaClass[F_COUNT] = {0, 1, 2, 3, 4, 5, 6, 8, 9, 11, 12, 13, 14, 15, 17, 7, 10,
+                                        16};
+// the formulas of the 5-cycle, K_{2,3} and class 16 need each vertex's row
+// of A^2, dense in LDS: graphs of up to kTrace5MaxN vertices (above, the
+// three are counted directly)
 constexpr int32_t kTrace5MaxN = 16384;
 constexpr int kK5Class = 20;
 
@@ -113,6 +114,16 @@ enum Acc : int {
 };
 
 __device__ __forceinline__ u128 binom2(uint64_t n) { return n < 2 ? 0 : (u128)n * (n - 1) / 2; }
+
+// First position in the sorted a[0, len) holding a value >= x.
+__device__ __forceinline__ int32_t first_geq(const int32_t *a, int32_t len, int32_t x) {
+    int32_t lo = 0, hi = len;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
 __device__ __forceinline__ u128 binom4(uint64_t n) {
     return n < 4 ? 0 : (u128)n * (n - 1) / 2 * (n - 2) / 3 * (n - 3) / 4;
 }
@@ -181,10 +192,16 @@ __global__ void __launch_bounds__(kBlock) k_f5_vertex(const int32_t *__restrict_
 //   (A^5)_ii = sum over j of P2(i, j) sum over k in N(j) of P2(i, k)
 // with P2(i, .) = row i of A^2 (2-walk counts; A^2 is symmetric), and
 // N(K_{2,3}) = sum over vertex pairs i < j of C(P2(i, j), 3) (a K_{2,3} is
-// its two degree-3 vertices and three of their common neighbours).  A
+// its two degree-3 vertices and three of their common neighbours), and for
+// class 16 (two non-adjacent vertices c, d joined to a, b, e with a ~ b)
+//   S = sum over triangles {c, a, b} and common neighbours d != c of a, b
+//       of P2(c, d),
+// twice the sum over pairs {c, d} of (edges inside their common
+// neighbourhood) x (its size): each triangle at c, with c as the row.  A
 // workgroup per vertex i builds P2(i, .) densely in LDS (n entries) and
-// lists the j it reaches, sums over the listed j and their neighbours, then
-// clears what it set.  P2 <= n, so each product fits 64 bits; the sums are
+// lists the j it reaches, sums over the listed j and their neighbours,
+// marks N(i) in an LDS bitmap and walks the triangles at i, then clears
+// what it set.  P2 <= n, so each product fits 64 bits; the sums are
 // 128-bit.
 __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict__ off,
                                                       const int32_t *__restrict__ adj, int32_t n,
@@ -192,13 +209,16 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
     extern __shared__ uint32_t s_dyn[];
     uint32_t *p2 = s_dyn;                               // n counters
     int32_t *reach = reinterpret_cast<int32_t *>(s_dyn + n);   // the j with P2 > 0
+    uint32_t *nbm = s_dyn + 2 * (int64_t)n;             // bitmap of N(i)
+    const int32_t nbw = (n + 31) / 32;
     __shared__ uint32_t s_nreach;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     constexpr int NW = kBlock / kWave;
     for (int32_t i = tid; i < n; i += kBlock) p2[i] = 0;
+    for (int32_t i = tid; i < nbw; i += kBlock) nbm[i] = 0;
     if (tid == 0) s_nreach = 0;
     __syncthreads();
-    u128 tr = 0, k23 = 0;
+    u128 tr = 0, k23 = 0, twin = 0;
     for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
         const int32_t si = off[i], di = off[i + 1] - si;
         // 2-walks i - x - j: a wave per middle x, lanes over N(x)
@@ -224,15 +244,49 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
             for (int32_t b = lane; b < dj; b += kWave) sum += p2[adj[sj + b]];
             tr += (u128)(pj * sum);
         }
+        for (int32_t a = tid; a < di; a += kBlock) {
+            const int32_t x = adj[si + a];
+            atomicOr(&nbm[x >> 5], 1u << (x & 31));
+        }
+        __syncthreads();
+        // triangles {i, a, b}, a < b: a wave per a, b in N(a) marked in N(i);
+        // then the common neighbours d != i of a and b (the shorter row
+        // walked, the other searched) add P2(i, d)
+        for (int32_t ai = wid; ai < di; ai += NW) {
+            const int32_t a = adj[si + ai], sa = off[a], da = off[a + 1] - sa;
+            for (int32_t b0 = 0; b0 < da; b0 += kWave) {
+                const int32_t b = b0 + lane < da ? adj[sa + b0 + lane] : -1;
+                const bool tri = b > a && ((nbm[b >> 5] >> (b & 31)) & 1u);
+                uint64_t mask = __ballot(tri);
+                while (mask) {
+                    const int src = __builtin_ctzll(mask);
+                    mask &= mask - 1ull;
+                    const int32_t bb = __shfl(b, src, kWave);
+                    const int32_t sb = off[bb], db = off[bb + 1] - sb;
+                    const bool ashort = da <= db;
+                    const int32_t xs = ashort ? sa : sb, xd = ashort ? da : db;
+                    const int32_t ys = ashort ? sb : sa, yd = ashort ? db : da;
+                    for (int32_t k = lane; k < xd; k += kWave) {
+                        const int32_t d = adj[xs + k];
+                        if (d == i) continue;
+                        const int32_t pos = first_geq(adj + ys, yd, d);
+                        if (pos < yd && adj[ys + pos] == d) twin += (u128)p2[d];
+                    }
+                }
+            }
+        }
         __syncthreads();
         for (int32_t r = tid; r < nr; r += kBlock) p2[reach[r]] = 0;
+        for (int32_t a = tid; a < di; a += kBlock) nbm[adj[si + a] >> 5] = 0u;
         if (tid == 0) s_nreach = 0;
         __syncthreads();
     }
     tr = wave_sum_u128(tr);
     k23 = wave_sum_u128(k23);
+    twin = wave_sum_u128(twin);
     if (lane == 0 && tr) atomic_add_u128(acc + A_PLUS + 2 * F_C5, tr);
     if (lane == 0 && k23) atomic_add_u128(acc + A_PLUS + 2 * F_K23, k23);
+    if (lane == 0 && twin) atomic_add_u128(acc + A_PLUS + 2 * F_TWIN, twin);
 }
 
 // One thread per undirected edge (an arc of the DAG): the edge terms.
@@ -263,6 +317,7 @@ __global__ void __launch_bounds__(kBlock) k_f5_edge(const int32_t *__restrict__ 
             minus[F_BANNER] += 2 * diamonds;
             minus[F_HOUSE] += 4 * diamonds;
             minus[F_KITE] += 4 * diamonds;
+            minus[F_TWIN] += 4 * diamonds;
             // two triangles on the edge put both ends at degree >= 3
             if (T >= 2) plus[F_DART] += diamonds * (dx + dy - 6);
             if (T >= 3) plus[F_BOOK] += diamonds * (T - 2) / 3;
@@ -455,6 +510,10 @@ __global__ void k_f5_combine(const unsigned long long *acc, Back B, unsigned lon
             if (N[h] % 10) bad |= 1;
             N[h] /= 10;
         }
+        if (f == F_TWIN) {   // both orders of each pair {c, d}
+            if (N[h] & 1) bad |= 1;
+            N[h] /= 2;
+        }
     }
     // densest first: a direct class is its count, a formula class its N
     // minus the copies inside denser induced subgraphs
@@ -594,8 +653,8 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
     if (k != 5) return fail(GPM_UNSUPPORTED, "formula motif counting is for k = 5");
     F5Ws W = f5_layout(g, ws);
     if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
-    // the 5-cycle and K_{2,3} from the rows of A^2 where they fit in LDS,
-    // else counted directly
+    // the 5-cycle, K_{2,3} and class 16 from the rows of A^2 where they fit
+    // in LDS, else counted directly
     Back B = back_matrix();
     const int32_t n = g->n;
     const int64_t m = g->m;
@@ -603,6 +662,7 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
     if (!trace5) {
         B.formula_of[kFormulaClass[F_C5]] = -1;
         B.formula_of[kFormulaClass[F_K23]] = -1;
+        B.formula_of[kFormulaClass[F_TWIN]] = -1;
     }
     GPM_HIP(fill_u32(W.acc, 0, 2 * (uint64_t)A_WORDS, st));
     GPM_HIP(fill_u32(W.t2, 0, 2 * ((uint64_t)n + 1), st));
@@ -630,7 +690,8 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
     GPM_LAUNCH_CHECK("k_f5_local");
     if (trace5 && m > 0) {
         Span sp("k_f5_trace5", st);
-        const size_t shmem = (size_t)n * 8;   // P2 counters and the reached list
+        // P2 counters, the reached list, the bitmap of N(i)
+        const size_t shmem = (size_t)n * 8 + (size_t)((n + 31) / 32) * 4;
         const int per_cu =
             (int)std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / (int64_t)(shmem + 1024)));
         hipLaunchKernelGGL(k_f5_trace5, dim3(grid_for(n, 1, per_cu)), dim3(kBlock), shmem, st,

@@ -11,7 +11,8 @@ and with (A^3)_vv = 2 t_v, tr(A^3) = 6 T this is
 against brute force over 5-vertex subsets and against the oracle's
 edge-induced pattern count, on graphs whose 5-cycle counts are also known
 in closed form.  And K_{2,3}: the sum over vertex pairs of C(common
-neighbours, 3)."""
+neighbours, 3); and the class of two non-adjacent vertices joined to an edge
+and a fifth vertex, from pairs and triangles."""
 from itertools import combinations, permutations
 
 import numpy as np
@@ -125,5 +126,53 @@ def test_k23_pair_formula(case, closed):
     f = formula_k23(e.n, e.u, e.v)
     off, adj = oracle.canonical_csr(e.n, e.u, e.v)
     assert f == oracle.pattern_count(off, adj, 5, K23, induced=False)[0]
+    if closed is not None:
+        assert f == closed
+
+
+TWIN = [(0, 2), (1, 2), (0, 3), (1, 3), (2, 3), (0, 4), (1, 4)]   # class 16
+
+
+def formula_twin(n, u, v):
+    """Two non-adjacent vertices c, d joined to a, b, e with a ~ b: the pair
+    {c, d} is unique, so N = sum over pairs of E_cd (k_cd - 2), with k_cd
+    their common neighbours and E_cd the edges among them; that is S / 2 -
+    2 D, S the sum over triangles {c, a, b} and common neighbours d != c of
+    a and b of k_cd, and D the sum over edges of C(T_e, 2)."""
+    from math import comb
+    A = np.zeros((n, n), dtype=np.int64)
+    for a, b in zip(u, v):
+        if a != b:
+            A[a, b] = A[b, a] = 1
+    P2 = A @ A
+    S = 0
+    for c in range(n):
+        nc = np.nonzero(A[c])[0]
+        for ia in range(len(nc)):
+            for ib in range(ia + 1, len(nc)):
+                a, b = nc[ia], nc[ib]
+                if A[a, b]:
+                    S += int(sum(P2[c, d] for d in np.nonzero(A[a] & A[b])[0] if d != c))
+    D = sum(comb(int(P2[a, b]), 2) for a in range(n) for b in range(a + 1, n) if A[a, b])
+    assert S % 2 == 0
+    return S // 2 - 2 * D
+
+
+@pytest.mark.parametrize("case,closed", [
+    ("k5", 30),          # 10 pairs {c, d}, 3 edges among the other three, 1 choice of e
+    ("k33", 0),          # no edge among two vertices' common neighbours
+    ("er12", None),
+    ("er15", None),
+    ("rmat6", None),
+])
+def test_twin_pair_formula(case, closed):
+    e = {"k5": lambda: graphgen.complete_graph(5),
+         "k33": lambda: graphgen.complete_bipartite(3, 3),
+         "er12": lambda: graphgen.erdos_renyi(12, 0.5, 5),
+         "er15": lambda: graphgen.erdos_renyi(15, 0.45, 7),
+         "rmat6": lambda: graphgen.rmat(6, edge_factor=4, seed=6)}[case]()
+    f = formula_twin(e.n, e.u, e.v)
+    off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+    assert f == oracle.pattern_count(off, adj, 5, TWIN, induced=False)[0]
     if closed is not None:
         assert f == closed
