@@ -48,11 +48,17 @@
 // same rows: a K_{2,3} is its two degree-3 vertices and three of their
 // common neighbours,
 //   K_{2,3}     sum over vertex pairs u < v of C(c(u, v), 3)
-// with c(u, v) = (A^2)_uv (graphs of up to kTrace5MaxN vertices; above,
-// both are counted directly).  The other four, whose induced copies are
-// far fewer (two triangles on an edge whose tips share a third neighbour,
-// the wheel, K5 minus an edge and K5), are counted directly as induced
-// patterns: by the general plan, K5 by the clique kernels.
+// with c(u, v) = (A^2)_uv, and an eighteenth: class 16, two non-adjacent
+// vertices c, d joined to a, b, e with a ~ b, is its pair {c, d} with an
+// edge among their common neighbours and one more of them,
+//   class 16    sum over pairs {c, d} of E_cd (c(c, d) - 2)
+//               = [sum over triangles {c, a, b}, d != c in N(a) & N(b)
+//                  of c(c, d)] / 2 - 2D
+// (E_cd the edges among the pair's common neighbours; graphs of up to
+// kTrace5MaxN vertices; above, the three are counted directly).  The other
+// three, whose induced copies are far fewer (the wheel, K5 minus an edge
+// and K5), are counted directly as induced patterns: by the general plan,
+// K5 by the clique kernels.
 #include "gpm_internal.h"
 
 #include <algorithm>
