@@ -93,12 +93,12 @@ constexpr int kBlock = 256;
 // Classes with a closed form, and the accumulator pair (plus, minus) of each.
 enum Formula : int { F_STAR, F_CHAIR, F_PATH, F_CRICKET, F_BULL, F_BANNER, F_TADPOLE, F_DART,
                      F_KITE, F_BOWTIE, F_HOUSE, F_K4PEND, F_BOOK, F_GEM, F_K4TWO, F_C5, F_K23,
-                     F_TWIN, F_COUNT };
+                     F_TWIN, F_K5E, F_COUNT };
 constexpr int kFormulaClass[F_COUNT] = {0, 1, 2, 3, 4, 5, 6, 8, 9, 11, 12, 13, 14, 15, 17, 7, 10,
-                                        16};
-// the formulas of the 5-cycle, K_{2,3} and class 16 need each vertex's row
-// of A^2, dense in LDS: graphs of up to kTrace5MaxN vertices (above, the
-// three are counted directly)
+                                        16, 19};
+// the formulas of the 5-cycle, K_{2,3}, class 16 and K5 minus an edge need
+// each vertex's row of A^2 (and its neighbour bitmap), dense in LDS: graphs
+// of up to kTrace5MaxN vertices (above, the four are counted directly)
 constexpr int32_t kTrace5MaxN = 16384;
 constexpr int kK5Class = 20;
 
@@ -203,7 +203,11 @@ __global__ void __launch_bounds__(kBlock) k_f5_vertex(const int32_t *__restrict_
 //   S = sum over triangles {c, a, b} and common neighbours d != c of a, b
 //       of P2(c, d),
 // twice the sum over pairs {c, d} of (edges inside their common
-// neighbourhood) x (its size): each triangle at c, with c as the row.  A
+// neighbourhood) x (its size): each triangle at c, with c as the row; and
+// for K5 minus an edge, a triangle t with two vertices adjacent to all of
+// it, C(k4(t), 2) summed over the triangles, k4(t) = the common neighbours
+// of a and b also adjacent to c (each triangle is met at each of its three
+// vertices, so the sum is three times the count).  A
 // workgroup per vertex i builds P2(i, .) densely in LDS (n entries) and
 // lists the j it reaches, sums over the listed j and their neighbours,
 // marks N(i) in an LDS bitmap and walks the triangles at i, then clears
@@ -224,7 +228,7 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
     for (int32_t i = tid; i < nbw; i += kBlock) nbm[i] = 0;
     if (tid == 0) s_nreach = 0;
     __syncthreads();
-    u128 tr = 0, k23 = 0, twin = 0;
+    u128 tr = 0, k23 = 0, twin = 0, k5e = 0;
     for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
         const int32_t si = off[i], di = off[i + 1] - si;
         // 2-walks i - x - j: a wave per middle x, lanes over N(x)
@@ -272,12 +276,18 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
                     const bool ashort = da <= db;
                     const int32_t xs = ashort ? sa : sb, xd = ashort ? da : db;
                     const int32_t ys = ashort ? sb : sa, yd = ashort ? db : da;
+                    uint32_t q = 0;   // common neighbours of a, b adjacent to i
                     for (int32_t k = lane; k < xd; k += kWave) {
                         const int32_t d = adj[xs + k];
                         if (d == i) continue;
                         const int32_t pos = first_geq(adj + ys, yd, d);
-                        if (pos < yd && adj[ys + pos] == d) twin += (u128)p2[d];
+                        if (pos < yd && adj[ys + pos] == d) {
+                            twin += (u128)p2[d];
+                            q += (nbm[d >> 5] >> (d & 31)) & 1u;
+                        }
                     }
+                    q = wave_sum(q);
+                    if (lane == 0) k5e += (u128)q * (q - (q > 0)) / 2;
                 }
             }
         }
@@ -290,9 +300,11 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
     tr = wave_sum_u128(tr);
     k23 = wave_sum_u128(k23);
     twin = wave_sum_u128(twin);
+    k5e = wave_sum_u128(k5e);
     if (lane == 0 && tr) atomic_add_u128(acc + A_PLUS + 2 * F_C5, tr);
     if (lane == 0 && k23) atomic_add_u128(acc + A_PLUS + 2 * F_K23, k23);
     if (lane == 0 && twin) atomic_add_u128(acc + A_PLUS + 2 * F_TWIN, twin);
+    if (lane == 0 && k5e) atomic_add_u128(acc + A_PLUS + 2 * F_K5E, k5e);
 }
 
 // One thread per undirected edge (an arc of the DAG): the edge terms.
@@ -520,6 +532,10 @@ __global__ void k_f5_combine(const unsigned long long *acc, Back B, unsigned lon
             if (N[h] & 1) bad |= 1;
             N[h] /= 2;
         }
+        if (f == F_K5E) {   // each triangle at each of its vertices
+            if (N[h] % 3) bad |= 1;
+            N[h] /= 3;
+        }
     }
     // densest first: a direct class is its count, a formula class its N
     // minus the copies inside denser induced subgraphs
@@ -659,8 +675,8 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
     if (k != 5) return fail(GPM_UNSUPPORTED, "formula motif counting is for k = 5");
     F5Ws W = f5_layout(g, ws);
     if (W.bytes > ws_bytes) return fail(GPM_OUT_OF_MEMORY, "workspace smaller than required");
-    // the 5-cycle, K_{2,3} and class 16 from the rows of A^2 where they fit
-    // in LDS, else counted directly
+    // the 5-cycle, K_{2,3}, class 16 and K5 minus an edge from the rows of
+    // A^2 where they fit in LDS, else counted directly
     Back B = back_matrix();
     const int32_t n = g->n;
     const int64_t m = g->m;
@@ -669,6 +685,7 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
         B.formula_of[kFormulaClass[F_C5]] = -1;
         B.formula_of[kFormulaClass[F_K23]] = -1;
         B.formula_of[kFormulaClass[F_TWIN]] = -1;
+        B.formula_of[kFormulaClass[F_K5E]] = -1;
     }
     GPM_HIP(fill_u32(W.acc, 0, 2 * (uint64_t)A_WORDS, st));
     GPM_HIP(fill_u32(W.t2, 0, 2 * ((uint64_t)n + 1), st));

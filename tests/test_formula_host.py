@@ -11,8 +11,9 @@ and with (A^3)_vv = 2 t_v, tr(A^3) = 6 T this is
 against brute force over 5-vertex subsets and against the oracle's
 edge-induced pattern count, on graphs whose 5-cycle counts are also known
 in closed form.  And K_{2,3}: the sum over vertex pairs of C(common
-neighbours, 3); and the class of two non-adjacent vertices joined to an edge
-and a fifth vertex, from pairs and triangles."""
+neighbours, 3); the class of two non-adjacent vertices joined to an edge
+and a fifth vertex, from pairs and triangles; and K5 minus an edge, from
+the vertices adjacent to all of a triangle."""
 from itertools import combinations, permutations
 
 import numpy as np
@@ -174,5 +175,52 @@ def test_twin_pair_formula(case, closed):
     f = formula_twin(e.n, e.u, e.v)
     off, adj = oracle.canonical_csr(e.n, e.u, e.v)
     assert f == oracle.pattern_count(off, adj, 5, TWIN, induced=False)[0]
+    if closed is not None:
+        assert f == closed
+
+
+K5E = [(0, 1), (0, 2), (1, 2), (0, 3), (1, 3), (2, 3), (0, 4), (1, 4), (2, 4)]
+
+
+def formula_k5e(n, u, v):
+    """K5 minus an edge: a triangle t (its degree-4 vertices) and two
+    vertices adjacent to all of t, so the sum over triangles of C(k4(t), 2),
+    k4(t) = the vertices adjacent to all of t; taken over each triangle at
+    each of its three vertices, then divided by 3, as the kernel does."""
+    from math import comb
+    A = np.zeros((n, n), dtype=np.int64)
+    for a, b in zip(u, v):
+        if a != b:
+            A[a, b] = A[b, a] = 1
+    s = 0
+    for c in range(n):
+        nc = np.nonzero(A[c])[0]
+        for ia in range(len(nc)):
+            for ib in range(ia + 1, len(nc)):
+                a, b = nc[ia], nc[ib]
+                if A[a, b]:
+                    s += comb(int((A[a] & A[b] & A[c]).sum()), 2)
+    assert s % 3 == 0
+    return s // 3
+
+
+@pytest.mark.parametrize("case,closed", [
+    ("k5", 10),          # C(5, 3) triangles, one pair of the other two each
+    ("k6", 60),          # C(6, 3) triangles, C(3, 2) pairs each
+    ("k33", 0),
+    ("er12", None),
+    ("er15", None),
+    ("rmat6", None),
+])
+def test_k5e_triangle_formula(case, closed):
+    e = {"k5": lambda: graphgen.complete_graph(5),
+         "k6": lambda: graphgen.complete_graph(6),
+         "k33": lambda: graphgen.complete_bipartite(3, 3),
+         "er12": lambda: graphgen.erdos_renyi(12, 0.6, 5),
+         "er15": lambda: graphgen.erdos_renyi(15, 0.5, 7),
+         "rmat6": lambda: graphgen.rmat(6, edge_factor=4, seed=6)}[case]()
+    f = formula_k5e(e.n, e.u, e.v)
+    off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+    assert f == oracle.pattern_count(off, adj, 5, K5E, induced=False)[0]
     if closed is not None:
         assert f == closed
