@@ -54,11 +54,15 @@
 //   class 16    sum over pairs {c, d} of E_cd (c(c, d) - 2)
 //               = [sum over triangles {c, a, b}, d != c in N(a) & N(b)
 //                  of c(c, d)] / 2 - 2D
-// (E_cd the edges among the pair's common neighbours; graphs of up to
-// kTrace5MaxN vertices; above, the three are counted directly).  The other
-// three, whose induced copies are far fewer (the wheel, K5 minus an edge
-// and K5), are counted directly as induced patterns: by the general plan,
-// K5 by the clique kernels.
+// (E_cd the edges among the pair's common neighbours), and a nineteenth:
+// K5 minus an edge is a triangle t (its degree-4 vertices) with two
+// vertices adjacent to all of it,
+//   K5 - e      sum over triangles t of C(k4(t), 2)
+// (k4(t) the vertices adjacent to all of t; graphs of up to kTrace5MaxN
+// vertices; above, the four are counted directly).  The other two, whose
+// induced copies are far fewer (the wheel and K5), are counted directly as
+// induced patterns: the wheel by the general plan, K5 by the clique
+// kernels.
 #include "gpm_internal.h"
 
 #include <algorithm>
