@@ -125,14 +125,11 @@ enum Acc : int {
 
 __device__ __forceinline__ u128 binom2(uint64_t n) { return n < 2 ? 0 : (u128)n * (n - 1) / 2; }
 
-// First position in the sorted a[0, len) holding a value >= x.
-__device__ __forceinline__ int32_t first_geq(const int32_t *a, int32_t len, int32_t x) {
-    int32_t lo = 0, hi = len;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (a[mid] < x) lo = mid + 1; else hi = mid;
-    }
-    return lo;
+// Orders a wave's LDS writes before its later reads.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 __device__ __forceinline__ u128 binom4(uint64_t n) {
     return n < 4 ? 0 : (u128)n * (n - 1) / 2 * (n - 2) / 3 * (n - 3) / 4;
@@ -214,9 +211,9 @@ __global__ void __launch_bounds__(kBlock) k_f5_vertex(const int32_t *__restrict_
 // vertices, so the sum is three times the count).  A
 // workgroup per vertex i builds P2(i, .) densely in LDS (n entries) and
 // lists the j it reaches, sums over the listed j and their neighbours,
-// marks N(i) in an LDS bitmap and walks the triangles at i, then clears
-// what it set.  P2 <= n, so each product fits 64 bits; the sums are
-// 128-bit.
+// marks N(i) in an LDS bitmap and walks the triangles at i (each wave with
+// the bitmap of its a), then clears what it set.  P2 <= n, so each product
+// fits 64 bits; the sums are 128-bit.
 __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict__ off,
                                                       const int32_t *__restrict__ adj, int32_t n,
                                                       unsigned long long *acc) {
@@ -228,8 +225,9 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
     __shared__ uint32_t s_nreach;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     constexpr int NW = kBlock / kWave;
+    uint32_t *wbm = nbm + (int64_t)(1 + wid) * nbw;     // this wave's bitmap of N(a)
     for (int32_t i = tid; i < n; i += kBlock) p2[i] = 0;
-    for (int32_t i = tid; i < nbw; i += kBlock) nbm[i] = 0;
+    for (int32_t i = tid; i < (1 + NW) * nbw; i += kBlock) nbm[i] = 0;
     if (tid == 0) s_nreach = 0;
     __syncthreads();
     u128 tr = 0, k23 = 0, twin = 0, k5e = 0;
@@ -263,29 +261,34 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
             atomicOr(&nbm[x >> 5], 1u << (x & 31));
         }
         __syncthreads();
-        // triangles {i, a, b}, a < b: a wave per a, b in N(a) marked in N(i);
-        // then the common neighbours d != i of a and b (the shorter row
-        // walked, the other searched) add P2(i, d)
+        // triangles {i, a, b}: a wave per a, with N(a) marked in its own
+        // bitmap; each triangle taken at its end of larger (degree, id), a,
+        // walking the other end's row and testing N(a) (and N(i)) in LDS:
+        // the common neighbours d != i of a and b add P2(i, d)
         for (int32_t ai = wid; ai < di; ai += NW) {
             const int32_t a = adj[si + ai], sa = off[a], da = off[a + 1] - sa;
+            for (int32_t k = lane; k < da; k += kWave) {
+                const int32_t x = adj[sa + k];
+                atomicOr(&wbm[x >> 5], 1u << (x & 31));
+            }
+            wave_sync();
             for (int32_t b0 = 0; b0 < da; b0 += kWave) {
                 const int32_t b = b0 + lane < da ? adj[sa + b0 + lane] : -1;
-                const bool tri = b > a && ((nbm[b >> 5] >> (b & 31)) & 1u);
+                bool tri = false;
+                if (b >= 0 && ((nbm[b >> 5] >> (b & 31)) & 1u)) {
+                    const int32_t db = off[b + 1] - off[b];
+                    tri = db < da || (db == da && b < a);
+                }
                 uint64_t mask = __ballot(tri);
                 while (mask) {
                     const int src = __builtin_ctzll(mask);
                     mask &= mask - 1ull;
                     const int32_t bb = __shfl(b, src, kWave);
                     const int32_t sb = off[bb], db = off[bb + 1] - sb;
-                    const bool ashort = da <= db;
-                    const int32_t xs = ashort ? sa : sb, xd = ashort ? da : db;
-                    const int32_t ys = ashort ? sb : sa, yd = ashort ? db : da;
                     uint32_t q = 0;   // common neighbours of a, b adjacent to i
-                    for (int32_t k = lane; k < xd; k += kWave) {
-                        const int32_t d = adj[xs + k];
-                        if (d == i) continue;
-                        const int32_t pos = first_geq(adj + ys, yd, d);
-                        if (pos < yd && adj[ys + pos] == d) {
+                    for (int32_t k = lane; k < db; k += kWave) {
+                        const int32_t d = adj[sb + k];
+                        if (d != i && ((wbm[d >> 5] >> (d & 31)) & 1u)) {
                             twin += (u128)p2[d];
                             q += (nbm[d >> 5] >> (d & 31)) & 1u;
                         }
@@ -294,6 +297,9 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
                     if (lane == 0) k5e += (u128)q * (q - (q > 0)) / 2;
                 }
             }
+            wave_sync();
+            for (int32_t k = lane; k < da; k += kWave) wbm[adj[sa + k] >> 5] = 0u;
+            wave_sync();
         }
         __syncthreads();
         for (int32_t r = tid; r < nr; r += kBlock) p2[reach[r]] = 0;
@@ -717,8 +723,10 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
     GPM_LAUNCH_CHECK("k_f5_local");
     if (trace5 && m > 0) {
         Span sp("k_f5_trace5", st);
-        // P2 counters, the reached list, the bitmap of N(i)
-        const size_t shmem = (size_t)n * 8 + (size_t)((n + 31) / 32) * 4;
+        // P2 counters, the reached list, the bitmaps of N(i) and of each
+        // wave's N(a)
+        const size_t shmem =
+            (size_t)n * 8 + (size_t)((n + 31) / 32) * 4 * (1 + kBlock / kWave);
         const int per_cu =
             (int)std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / (int64_t)(shmem + 1024)));
         hipLaunchKernelGGL(k_f5_trace5, dim3(grid_for(n, 1, per_cu)), dim3(kBlock), shmem, st,
