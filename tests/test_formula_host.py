@@ -12,8 +12,9 @@ against brute force over 5-vertex subsets and against the oracle's
 edge-induced pattern count, on graphs whose 5-cycle counts are also known
 in closed form.  And K_{2,3}: the sum over vertex pairs of C(common
 neighbours, 3); the class of two non-adjacent vertices joined to an edge
-and a fifth vertex, from pairs and triangles; and K5 minus an edge, from
-the vertices adjacent to all of a triangle."""
+and a fifth vertex, from pairs and triangles; K5 minus an edge, from
+the vertices adjacent to all of a triangle; and the wheel, from the
+4-cycles in each vertex's neighbourhood."""
 from itertools import combinations, permutations
 
 import numpy as np
@@ -222,5 +223,69 @@ def test_k5e_triangle_formula(case, closed):
     f = formula_k5e(e.n, e.u, e.v)
     off, adj = oracle.canonical_csr(e.n, e.u, e.v)
     assert f == oracle.pattern_count(off, adj, 5, K5E, induced=False)[0]
+    if closed is not None:
+        assert f == closed
+
+
+WHEEL = [(0, 1), (1, 2), (2, 3), (3, 0), (0, 4), (1, 4), (2, 4), (3, 4)]
+
+
+def formula_wheel(n, u, v):
+    """The wheel (a hub joined to all four vertices of a 4-cycle): its hub
+    is its one vertex of degree 4, so the copies are the pairs (hub i,
+    4-cycle in G[N(i)]).  A 4-cycle x-p-y-q is taken at its largest vertex x
+    with y the vertex opposite x: for each x in N(i) and each y < x in N(i),
+    C(c(x, y), 2) with c(x, y) the common neighbours p < x of x and y inside
+    N(i), counted the way the kernel does, each increment of c adding the
+    count before it."""
+    A = np.zeros((n, n), dtype=np.int64)
+    for a, b in zip(u, v):
+        if a != b:
+            A[a, b] = A[b, a] = 1
+    total = 0
+    for i in range(n):
+        ni = set(np.nonzero(A[i])[0].tolist())
+        for x in sorted(ni):
+            cnt = {}
+            for p in np.nonzero(A[x])[0]:
+                if p >= x or p not in ni:
+                    continue
+                for y in np.nonzero(A[p])[0]:
+                    if y < x and y in ni:
+                        c = cnt.get(y, 0)
+                        total += c
+                        cnt[y] = c + 1
+    return total
+
+
+def wheel_graph(rim):
+    pairs = [(i, (i + 1) % rim) for i in range(rim)] + [(i, rim) for i in range(rim)]
+    return graphgen.graphs._as_edges(rim + 1, pairs, f"W{rim}")
+
+
+@pytest.mark.parametrize("case,closed", [
+    ("w4", 1),           # the pattern itself
+    ("w5", 0),           # a 5-rim: no 4-cycle around any vertex
+    ("k5", 15),          # 5 hubs, three 4-cycles in each K4
+    ("k6", 90),          # 6 hubs, fifteen 4-cycles in each K5
+    ("k2_2_2", 6),       # octahedron: each vertex's neighbourhood is one 4-cycle
+    ("k33", 0),
+    ("er12", None),
+    ("er15", None),
+    ("rmat6", None),
+])
+def test_wheel_neighbourhood_cycle_formula(case, closed):
+    e = {"w4": lambda: wheel_graph(4),
+         "w5": lambda: wheel_graph(5),
+         "k5": lambda: graphgen.complete_graph(5),
+         "k6": lambda: graphgen.complete_graph(6),
+         "k2_2_2": lambda: graphgen.complete_multipartite([2, 2, 2]),
+         "k33": lambda: graphgen.complete_bipartite(3, 3),
+         "er12": lambda: graphgen.erdos_renyi(12, 0.6, 5),
+         "er15": lambda: graphgen.erdos_renyi(15, 0.5, 7),
+         "rmat6": lambda: graphgen.rmat(6, edge_factor=4, seed=6)}[case]()
+    f = formula_wheel(e.n, e.u, e.v)
+    off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+    assert f == oracle.pattern_count(off, adj, 5, WHEEL, induced=False)[0]
     if closed is not None:
         assert f == closed
