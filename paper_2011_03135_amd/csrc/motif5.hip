@@ -97,12 +97,13 @@ constexpr int kBlock = 256;
 // Classes with a closed form, and the accumulator pair (plus, minus) of each.
 enum Formula : int { F_STAR, F_CHAIR, F_PATH, F_CRICKET, F_BULL, F_BANNER, F_TADPOLE, F_DART,
                      F_KITE, F_BOWTIE, F_HOUSE, F_K4PEND, F_BOOK, F_GEM, F_K4TWO, F_C5, F_K23,
-                     F_TWIN, F_K5E, F_COUNT };
+                     F_TWIN, F_K5E, F_WHEEL, F_COUNT };
 constexpr int kFormulaClass[F_COUNT] = {0, 1, 2, 3, 4, 5, 6, 8, 9, 11, 12, 13, 14, 15, 17, 7, 10,
-                                        16, 19};
-// the formulas of the 5-cycle, K_{2,3}, class 16 and K5 minus an edge need
-// each vertex's row of A^2 (and its neighbour bitmap), dense in LDS: graphs
-// of up to kTrace5MaxN vertices (above, the four are counted directly)
+                                        16, 19, 18};
+// the formulas of the 5-cycle, K_{2,3}, class 16, K5 minus an edge and the
+// wheel need dense per-vertex arrays in LDS (a row of A^2, neighbour
+// bitmaps, 16-bit counters): graphs of up to kTrace5MaxN vertices (above,
+// the five are counted directly)
 constexpr int32_t kTrace5MaxN = 16384;
 constexpr int kK5Class = 20;
 
@@ -120,7 +121,8 @@ enum Acc : int {
     A_CYC = A_C4 + 2,                 // 2 u128: 4-cycle sums (degrees, doubled; edge triangles)
     A_K4 = A_CYC + 4,                 // u64: 4-cliques
     A_DIR = A_K4 + 2,                 // kClasses u64: induced counts of the direct classes
-    A_WORDS = A_DIR + kClasses,
+    A_CURSOR = A_DIR + kClasses,      // u64: the wheel kernel's work cursor
+    A_WORDS = A_CURSOR + 1,
 };
 
 __device__ __forceinline__ u128 binom2(uint64_t n) { return n < 2 ? 0 : (u128)n * (n - 1) / 2; }
@@ -315,6 +317,114 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
     if (lane == 0 && k23) atomic_add_u128(acc + A_PLUS + 2 * F_K23, k23);
     if (lane == 0 && twin) atomic_add_u128(acc + A_PLUS + 2 * F_TWIN, twin);
     if (lane == 0 && k5e) atomic_add_u128(acc + A_PLUS + 2 * F_K5E, k5e);
+}
+
+// The wheel (a hub joined to all four vertices of a 4-cycle) has one
+// vertex of degree 4, its hub, so its copies are the pairs (i, 4-cycle in
+// G[N(i)]).  A 4-cycle x-p-y-q is taken at its largest vertex x, y the
+// vertex opposite x: C(c(x, y), 2) over the y < x in N(i), c(x, y) = the
+// common neighbours p < x of x and y in N(i).  A wave per arc (i, x), the
+// arcs taken kWheelArcs at a time from a cursor (consecutive arcs share i,
+// whose neighbours stay marked in the wave's LDS bitmap); c(x, .) in 16-bit
+// counters packed two to an LDS word (c < n <= kTrace5MaxN), each increment
+// adding the count before it (0 + 1 + ... + (c - 1) = C(c, 2)), then
+// cleared whole.  Rows are sorted, so only their entries below x are read,
+// kWheelU chunks of 64 in flight per wave.
+constexpr int kWheelArcs = 4;
+constexpr int kWheelU = 4;
+
+__host__ __device__ constexpr int32_t wheel_count_words(int32_t n) {
+    return ((n + 1) / 2 + 3) / 4 * 4;
+}
+__host__ __device__ constexpr int32_t wheel_words_per_wave(int32_t n) {
+    return wheel_count_words(n) + ((n + 31) / 32 + 3) / 4 * 4;
+}
+
+__device__ __forceinline__ bool marked(const uint32_t *bm, int32_t v) {
+    return (bm[v >> 5] >> (v & 31)) & 1u;
+}
+
+__global__ void __launch_bounds__(kBlock) k_f5_wheel(const int32_t *__restrict__ off,
+                                                     const int32_t *__restrict__ adj, int32_t n,
+                                                     int64_t arcs, unsigned long long *acc) {
+    extern __shared__ uint4 s_wheel[];
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    const int32_t cw = wheel_count_words(n), ww = wheel_words_per_wave(n);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(s_wheel) + (int64_t)wid * ww;
+    uint4 *cnt4 = reinterpret_cast<uint4 *>(cnt);
+    uint32_t *bm = cnt + cw;                    // N(i)
+    for (int32_t k = lane; k < ww; k += kWave) cnt[k] = 0u;
+    wave_sync();
+    u128 sum = 0;
+    int32_t cur = -1;   // the vertex whose neighbours are marked
+    const int64_t nblocks = (arcs + kWheelArcs - 1) / kWheelArcs;
+    for (;;) {
+        unsigned long long r = 0;
+        if (lane == 0) r = atomicAdd(acc + A_CURSOR, 1ull);
+        const int64_t b = __shfl((int64_t)r, 0, kWave);
+        if (b >= nblocks) break;
+        const int64_t t0 = b * kWheelArcs, t1 = t0 + kWheelArcs < arcs ? t0 + kWheelArcs : arcs;
+        // the row holding arc t0: off[i] <= t0 < off[i + 1]
+        int32_t lo = 0, hi = n;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (off[mid] <= t0) lo = mid; else hi = mid;
+        }
+        int32_t i = lo;
+        for (int64_t t = t0; t < t1; t++) {
+            while (off[i + 1] <= t) i++;
+            if (i != cur) {
+                if (cur >= 0)
+                    for (int32_t k = off[cur] + lane; k < off[cur + 1]; k += kWave)
+                        bm[adj[k] >> 5] = 0u;
+                wave_sync();
+                for (int32_t k = off[i] + lane; k < off[i + 1]; k += kWave) {
+                    const int32_t v = adj[k];
+                    atomicOr(&bm[v >> 5], 1u << (v & 31));
+                }
+                wave_sync();
+                cur = i;
+            }
+            const int32_t x = adj[t], sx = off[x], dx = off[x + 1] - sx;
+            bool touched = false;
+            for (int32_t k0 = 0; k0 < dx; k0 += kWave) {
+                const int32_t p = k0 + lane < dx ? adj[sx + k0 + lane] : INT32_MAX;
+                uint64_t mask = __ballot(p < x && marked(bm, p));
+                touched |= mask != 0ull;
+                while (mask) {
+                    const int src = __builtin_ctzll(mask);
+                    mask &= mask - 1ull;
+                    const int32_t pp = __shfl(p, src, kWave);
+                    const int32_t sp = off[pp], dp = off[pp + 1] - sp;
+                    for (int32_t j0 = 0; j0 < dp; j0 += kWave * kWheelU) {
+                        int32_t y[kWheelU];
+#pragma unroll
+                        for (int u = 0; u < kWheelU; u++) {
+                            const int32_t j = j0 + u * kWave + lane;
+                            y[u] = j < dp ? adj[sp + j] : INT32_MAX;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kWheelU; u++) {
+                            if (y[u] < x && marked(bm, y[u])) {
+                                const uint32_t sh = (uint32_t)(y[u] & 1) * 16u;
+                                const uint32_t old = atomicAdd(&cnt[y[u] >> 1], 1u << sh);
+                                sum += (old >> sh) & 0xFFFFu;
+                            }
+                        }
+                        if (__ballot(y[kWheelU - 1] >= x)) break;   // the rest are >= x
+                    }
+                }
+                if (__ballot(p >= x)) break;
+            }
+            if (touched) {
+                wave_sync();
+                for (int32_t k = lane; k < cw / 4; k += kWave) cnt4[k] = make_uint4(0u, 0u, 0u, 0u);
+                wave_sync();
+            }
+        }
+    }
+    sum = wave_sum_u128(sum);
+    if (lane == 0 && sum) atomic_add_u128(acc + A_PLUS + 2 * F_WHEEL, sum);
 }
 
 // One thread per undirected edge (an arc of the DAG): the edge terms.
@@ -696,6 +806,7 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
         B.formula_of[kFormulaClass[F_K23]] = -1;
         B.formula_of[kFormulaClass[F_TWIN]] = -1;
         B.formula_of[kFormulaClass[F_K5E]] = -1;
+        B.formula_of[kFormulaClass[F_WHEEL]] = -1;
     }
     GPM_HIP(fill_u32(W.acc, 0, 2 * (uint64_t)A_WORDS, st));
     GPM_HIP(fill_u32(W.t2, 0, 2 * ((uint64_t)n + 1), st));
@@ -733,6 +844,19 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
                            g->off, g->adj, n, W.acc);
     }
     GPM_LAUNCH_CHECK("k_f5_trace5");
+    if (trace5 && m > 0) {
+        Span sp("k_f5_wheel", st);
+        // per wave: the counters c(x, .) and the bitmap of N(i)
+        const size_t shmem = (size_t)wheel_words_per_wave(n) * 4 * (kBlock / kWave);
+        const int per_cu =
+            (int)std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / (int64_t)(shmem + 1024)));
+        const int64_t arcs = 2 * m;
+        hipLaunchKernelGGL(k_f5_wheel,
+                           dim3(grid_for((arcs + kWheelArcs - 1) / kWheelArcs, kBlock / kWave,
+                                         per_cu)),
+                           dim3(kBlock), shmem, st, g->off, g->adj, n, arcs, W.acc);
+    }
+    GPM_LAUNCH_CHECK("k_f5_wheel");
     // 4-cycles (edge sets) and the sums over them
     rc = c4_run(g, false, W.shared, W.shared_bytes, W.acc + A_C4, nullptr, 0, nullptr, st,
                 W.tsym, W.acc + A_CYC);
