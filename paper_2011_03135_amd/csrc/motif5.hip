@@ -58,11 +58,13 @@
 // K5 minus an edge is a triangle t (its degree-4 vertices) with two
 // vertices adjacent to all of it,
 //   K5 - e      sum over triangles t of C(k4(t), 2)
-// (k4(t) the vertices adjacent to all of t; graphs of up to kTrace5MaxN
-// vertices; above, the four are counted directly).  The other two, whose
-// induced copies are far fewer (the wheel and K5), are counted directly as
-// induced patterns: the wheel by the general plan, K5 by the clique
-// kernels.
+// (k4(t) the vertices adjacent to all of t), and a twentieth: the wheel
+// is its hub (its one vertex of degree 4) and a 4-cycle among the hub's
+// neighbours,
+//   wheel       sum over vertices i of N(C4) in G[N(i)]
+// (graphs of up to kTrace5MaxN vertices; above, these five are counted
+// directly as induced patterns by the general plan).  K5 is counted by the
+// clique kernels.
 #include "gpm_internal.h"
 
 #include <algorithm>
@@ -214,11 +216,16 @@ __global__ void __launch_bounds__(kBlock) k_f5_vertex(const int32_t *__restrict_
 // workgroup per vertex i builds P2(i, .) densely in LDS (n entries) and
 // lists the j it reaches, sums over the listed j and their neighbours,
 // marks N(i) in an LDS bitmap and walks the triangles at i (each wave with
-// the bitmap of its a), then clears what it set.  P2 <= n, so each product
+// the bitmap of its a, four triangles at a time, 16 lanes on each), then
+// clears what it set.  P2 <= n, so each product
 // fits 64 bits; the sums are 128-bit.
-__global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict__ off,
-                                                      const int32_t *__restrict__ adj, int32_t n,
-                                                      unsigned long long *acc) {
+constexpr int kTriLanes = 16;                   // lanes per triangle walked
+constexpr int kTriGroups = kWave / kTriLanes;   // triangles per wave at a time
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ off,
+                                                  const int32_t *__restrict__ adj, int32_t n,
+                                                  unsigned long long *acc) {
     extern __shared__ uint32_t s_dyn[];
     uint32_t *p2 = s_dyn;                               // n counters
     int32_t *reach = reinterpret_cast<int32_t *>(s_dyn + n);   // the j with P2 > 0
@@ -226,10 +233,11 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
     const int32_t nbw = (n + 31) / 32;
     __shared__ uint32_t s_nreach;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
-    constexpr int NW = kBlock / kWave;
+    const int grp = lane / kTriLanes, gl = lane % kTriLanes;
+    constexpr int NW = NT / kWave;
     uint32_t *wbm = nbm + (int64_t)(1 + wid) * nbw;     // this wave's bitmap of N(a)
-    for (int32_t i = tid; i < n; i += kBlock) p2[i] = 0;
-    for (int32_t i = tid; i < (1 + NW) * nbw; i += kBlock) nbm[i] = 0;
+    for (int32_t i = tid; i < n; i += NT) p2[i] = 0;
+    for (int32_t i = tid; i < (1 + NW) * nbw; i += NT) nbm[i] = 0;
     if (tid == 0) s_nreach = 0;
     __syncthreads();
     u128 tr = 0, k23 = 0, twin = 0, k5e = 0;
@@ -245,20 +253,24 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
         }
         __syncthreads();
         const int32_t nr = (int32_t)s_nreach;
-        for (int32_t r = tid; r < nr; r += kBlock) {
+        for (int32_t r = tid; r < nr; r += NT) {
             const int32_t j = reach[r];
             const uint64_t c = p2[j];
             if (j > i && c >= 3) k23 += (u128)(c * (c - 1) * (c - 2) / 6);
         }
-        // sum over the reached j of P2(i, j) times the P2 of j's neighbours
+        // sum over the reached j of P2(i, j) times the P2 of j's neighbours,
+        // (A^3)_ij; the term is symmetric in i and j, so each pair j != i is
+        // taken once, doubled, at its end of larger (degree, id), walking
+        // the row of the other
         for (int32_t r = wid; r < nr; r += NW) {
             const int32_t j = reach[r], sj = off[j], dj = off[j + 1] - sj;
-            const uint64_t pj = p2[j];
+            if (j != i && (dj > di || (dj == di && j > i))) continue;
+            const uint64_t pj = (uint64_t)p2[j] << (j != i);
             uint64_t sum = 0;
             for (int32_t b = lane; b < dj; b += kWave) sum += p2[adj[sj + b]];
             tr += (u128)(pj * sum);
         }
-        for (int32_t a = tid; a < di; a += kBlock) {
+        for (int32_t a = tid; a < di; a += NT) {
             const int32_t x = adj[si + a];
             atomicOr(&nbm[x >> 5], 1u << (x & 31));
         }
@@ -281,22 +293,27 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
                     const int32_t db = off[b + 1] - off[b];
                     tri = db < da || (db == da && b < a);
                 }
+                // kTriGroups triangles at a time, kTriLanes lanes each
                 uint64_t mask = __ballot(tri);
                 while (mask) {
-                    const int src = __builtin_ctzll(mask);
-                    mask &= mask - 1ull;
+                    uint64_t mm = mask;
+                    for (int g = 0; g < grp && mm; g++) mm &= mm - 1ull;
+                    const bool live = mm != 0ull;
+                    const int src = live ? __builtin_ctzll(mm) : 0;
+                    for (int g = 0; g < kTriGroups && mask; g++) mask &= mask - 1ull;
                     const int32_t bb = __shfl(b, src, kWave);
-                    const int32_t sb = off[bb], db = off[bb + 1] - sb;
+                    const int32_t sb = live ? off[bb] : 0, db = live ? off[bb + 1] - sb : 0;
                     uint32_t q = 0;   // common neighbours of a, b adjacent to i
-                    for (int32_t k = lane; k < db; k += kWave) {
+                    for (int32_t k = gl; k < db; k += kTriLanes) {
                         const int32_t d = adj[sb + k];
                         if (d != i && ((wbm[d >> 5] >> (d & 31)) & 1u)) {
                             twin += (u128)p2[d];
                             q += (nbm[d >> 5] >> (d & 31)) & 1u;
                         }
                     }
-                    q = wave_sum(q);
-                    if (lane == 0) k5e += (u128)q * (q - (q > 0)) / 2;
+#pragma unroll
+                    for (int o = kTriLanes / 2; o > 0; o >>= 1) q += __shfl_xor(q, o, kWave);
+                    if (gl == 0) k5e += (u128)q * (q - (q > 0)) / 2;
                 }
             }
             wave_sync();
@@ -304,8 +321,8 @@ __global__ void __launch_bounds__(kBlock) k_f5_trace5(const int32_t *__restrict_
             wave_sync();
         }
         __syncthreads();
-        for (int32_t r = tid; r < nr; r += kBlock) p2[reach[r]] = 0;
-        for (int32_t a = tid; a < di; a += kBlock) nbm[adj[si + a] >> 5] = 0u;
+        for (int32_t r = tid; r < nr; r += NT) p2[reach[r]] = 0;
+        for (int32_t a = tid; a < di; a += NT) nbm[adj[si + a] >> 5] = 0u;
         if (tid == 0) s_nreach = 0;
         __syncthreads();
     }
@@ -835,13 +852,25 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
     if (trace5 && m > 0) {
         Span sp("k_f5_trace5", st);
         // P2 counters, the reached list, the bitmaps of N(i) and of each
-        // wave's N(a)
-        const size_t shmem =
-            (size_t)n * 8 + (size_t)((n + 31) / 32) * 4 * (1 + kBlock / kWave);
+        // wave's N(a): the widest workgroup (16, 8 or 4 waves, one vertex
+        // each) whose LDS fits, so that a hub's triangles spread widest
+        auto shmem_of = [&](int nt) {
+            return (size_t)n * 8 + (size_t)((n + 31) / 32) * 4 * (1 + nt / kWave);
+        };
+        const int nt = shmem_of(1024) <= 160 * 1024 ? 1024 : shmem_of(512) <= 160 * 1024 ? 512 : 256;
+        const size_t shmem = shmem_of(nt);
         const int per_cu =
             (int)std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / (int64_t)(shmem + 1024)));
-        hipLaunchKernelGGL(k_f5_trace5, dim3(grid_for(n, 1, per_cu)), dim3(kBlock), shmem, st,
-                           g->off, g->adj, n, W.acc);
+        const dim3 grid(grid_for(n, 1, per_cu));
+        if (nt == 1024)
+            hipLaunchKernelGGL(k_f5_trace5<1024>, grid, dim3(1024), shmem, st, g->off, g->adj, n,
+                               W.acc);
+        else if (nt == 512)
+            hipLaunchKernelGGL(k_f5_trace5<512>, grid, dim3(512), shmem, st, g->off, g->adj, n,
+                               W.acc);
+        else
+            hipLaunchKernelGGL(k_f5_trace5<256>, grid, dim3(256), shmem, st, g->off, g->adj, n,
+                               W.acc);
     }
     GPM_LAUNCH_CHECK("k_f5_trace5");
     if (trace5 && m > 0) {
