@@ -124,7 +124,8 @@ enum Acc : int {
     A_K4 = A_CYC + 4,                 // u64: 4-cliques
     A_DIR = A_K4 + 2,                 // kClasses u64: induced counts of the direct classes
     A_CURSOR = A_DIR + kClasses,      // u64: the wheel kernel's work cursor
-    A_WORDS = A_CURSOR + 1,
+    A_TCURSOR = A_CURSOR + 1,         // u64: the A^2-row kernel's task cursor
+    A_WORDS = A_TCURSOR + 1,
 };
 
 __device__ __forceinline__ u128 binom2(uint64_t n) { return n < 2 ? 0 : (u128)n * (n - 1) / 2; }
@@ -213,25 +214,29 @@ __global__ void __launch_bounds__(kBlock) k_f5_vertex(const int32_t *__restrict_
 // it, C(k4(t), 2) summed over the triangles, k4(t) = the common neighbours
 // of a and b also adjacent to c (each triangle is met at each of its three
 // vertices, so the sum is three times the count).  A
-// workgroup per vertex i builds P2(i, .) densely in LDS (n entries) and
-// lists the j it reaches, sums over the listed j and their neighbours,
-// marks N(i) in an LDS bitmap and walks the triangles at i (each wave with
-// the bitmap of its a, four triangles at a time, 16 lanes on each), then
-// clears what it set.  P2 <= n, so each product
+// workgroup per task (i, part) builds P2(i, .) densely in LDS (n entries)
+// and lists the j it reaches; part 0 sums over the listed j and their
+// neighbours; each part marks N(i) in an LDS bitmap and walks the
+// triangles at i whose end a of larger degree is among its kTracePart
+// neighbours of i (each wave with the bitmap of its a, four triangles at a
+// time, 16 lanes on each), then clears what it set.  The tasks come from a
+// cursor, so a hub's parts run side by side.  P2 <= n, so each product
 // fits 64 bits; the sums are 128-bit.
+constexpr int32_t kTracePart = 128;             // neighbours a per triangle-walk task
 constexpr int kTriLanes = 16;                   // lanes per triangle walked
 constexpr int kTriGroups = kWave / kTriLanes;   // triangles per wave at a time
 
 template <int NT>
 __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ off,
                                                   const int32_t *__restrict__ adj, int32_t n,
-                                                  unsigned long long *acc) {
+                                                  int32_t nparts, unsigned long long *acc) {
     extern __shared__ uint32_t s_dyn[];
     uint32_t *p2 = s_dyn;                               // n counters
     int32_t *reach = reinterpret_cast<int32_t *>(s_dyn + n);   // the j with P2 > 0
     uint32_t *nbm = s_dyn + 2 * (int64_t)n;             // bitmap of N(i)
     const int32_t nbw = (n + 31) / 32;
     __shared__ uint32_t s_nreach;
+    __shared__ int64_t s_task;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     const int grp = lane / kTriLanes, gl = lane % kTriLanes;
     constexpr int NW = NT / kWave;
@@ -241,8 +246,20 @@ __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ of
     if (tid == 0) s_nreach = 0;
     __syncthreads();
     u128 tr = 0, k23 = 0, twin = 0, k5e = 0;
-    for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    // tasks (i, part) from a cursor, the parts from the last down, so that
+    // the vertices of highest degree start first
+    const int64_t ntasks = (int64_t)n * nparts;
+    for (;;) {
+        if (tid == 0) s_task = (int64_t)atomicAdd(acc + A_TCURSOR, 1ull);
+        __syncthreads();
+        const int64_t t = s_task;
+        __syncthreads();
+        if (t >= ntasks) break;
+        const int32_t part = nparts - 1 - (int32_t)(t / n), i = (int32_t)(t % n);
         const int32_t si = off[i], di = off[i + 1] - si;
+        const int32_t a_lo = part * kTracePart;
+        if (part > 0 && a_lo >= di) continue;
+        const int32_t a_hi = a_lo + kTracePart < di ? a_lo + kTracePart : di;
         // 2-walks i - x - j: a wave per middle x, lanes over N(x)
         for (int32_t a = wid; a < di; a += NW) {
             const int32_t x = adj[si + a], sx = off[x], dx = off[x + 1] - sx;
@@ -253,7 +270,7 @@ __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ of
         }
         __syncthreads();
         const int32_t nr = (int32_t)s_nreach;
-        for (int32_t r = tid; r < nr; r += NT) {
+        for (int32_t r = tid; r < nr && part == 0; r += NT) {
             const int32_t j = reach[r];
             const uint64_t c = p2[j];
             if (j > i && c >= 3) k23 += (u128)(c * (c - 1) * (c - 2) / 6);
@@ -262,7 +279,7 @@ __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ of
         // (A^3)_ij; the term is symmetric in i and j, so each pair j != i is
         // taken once, doubled, at its end of larger (degree, id), walking
         // the row of the other
-        for (int32_t r = wid; r < nr; r += NW) {
+        for (int32_t r = wid; r < nr && part == 0; r += NW) {
             const int32_t j = reach[r], sj = off[j], dj = off[j + 1] - sj;
             if (j != i && (dj > di || (dj == di && j > i))) continue;
             const uint64_t pj = (uint64_t)p2[j] << (j != i);
@@ -279,7 +296,7 @@ __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ of
         // bitmap; each triangle taken at its end of larger (degree, id), a,
         // walking the other end's row and testing N(a) (and N(i)) in LDS:
         // the common neighbours d != i of a and b add P2(i, d)
-        for (int32_t ai = wid; ai < di; ai += NW) {
+        for (int32_t ai = a_lo + wid; ai < a_hi; ai += NW) {
             const int32_t a = adj[si + ai], sa = off[a], da = off[a + 1] - sa;
             for (int32_t k = lane; k < da; k += kWave) {
                 const int32_t x = adj[sa + k];
@@ -861,16 +878,19 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
         const size_t shmem = shmem_of(nt);
         const int per_cu =
             (int)std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / (int64_t)(shmem + 1024)));
-        const dim3 grid(grid_for(n, 1, per_cu));
+        // a vertex's triangles split into parts of kTracePart neighbours
+        // a, each part a task that builds the row of A^2 again
+        const int32_t nparts = std::max<int32_t>(1, (g->max_degree + kTracePart - 1) / kTracePart);
+        const dim3 grid(grid_for((int64_t)n * nparts, 1, per_cu));
         if (nt == 1024)
             hipLaunchKernelGGL(k_f5_trace5<1024>, grid, dim3(1024), shmem, st, g->off, g->adj, n,
-                               W.acc);
+                               nparts, W.acc);
         else if (nt == 512)
             hipLaunchKernelGGL(k_f5_trace5<512>, grid, dim3(512), shmem, st, g->off, g->adj, n,
-                               W.acc);
+                               nparts, W.acc);
         else
             hipLaunchKernelGGL(k_f5_trace5<256>, grid, dim3(256), shmem, st, g->off, g->adj, n,
-                               W.acc);
+                               nparts, W.acc);
     }
     GPM_LAUNCH_CHECK("k_f5_trace5");
     if (trace5 && m > 0) {
