@@ -218,12 +218,12 @@ __global__ void __launch_bounds__(kBlock) k_f5_vertex(const int32_t *__restrict_
 // and lists the j it reaches; part 0 sums over the listed j and their
 // neighbours; each part marks N(i) in an LDS bitmap and walks the
 // triangles at i whose end a of larger degree is among its kTracePart
-// neighbours of i (each wave with the bitmap of its a, four triangles at a
-// time, 16 lanes on each), then clears what it set.  The tasks come from a
+// neighbours of i (each wave with the bitmap of its a, two triangles at a
+// time, 32 lanes on each), then clears what it set.  The tasks come from a
 // cursor, so a hub's parts run side by side.  P2 <= n, so each product
 // fits 64 bits; the sums are 128-bit.
 constexpr int32_t kTracePart = 128;             // neighbours a per triangle-walk task
-constexpr int kTriLanes = 16;                   // lanes per triangle walked
+constexpr int kTriLanes = 32;                   // lanes per triangle walked
 constexpr int kTriGroups = kWave / kTriLanes;   // triangles per wave at a time
 
 template <int NT>
