@@ -691,8 +691,8 @@ def motif_enum_leg(gpm, torch, scale4=12, scale5=10, reps=3, enum5_large=False):
     c5_off, ms5_off = without_map(run5)
     # the formula route for the same 21 counts (closed forms in local counts
     # for fifteen classes, the rows of A^2 and the triangles for four more,
-    # the general plan for the wheel, the clique kernels for K5,
-    # back-substitution)
+    # the 4-cycles in each neighbourhood for the wheel, the clique kernels
+    # for K5, back-substitution)
     wsf = torch.empty(gpm.motif_formula_workspace_bytes(g5, 5), dtype=torch.uint8, device="cuda")
     f5, msf = timed(lambda: gpm.motif_count_formula(g5, 5, ws=wsf))
     wsf12 = torch.empty(gpm.motif_formula_workspace_bytes(g, 5), dtype=torch.uint8,

@@ -383,17 +383,18 @@ gpm_status gpm_motif_count_enum(const gpm_graph *g, int32_t k, void *d_ws, uint6
  * closed forms in local counts: degrees, per-edge triangle counts
  * (Section 5), per-vertex triangle counts, neighbour-degree sums, sums
  * over the triangles, the 4-cycles and the 4-cliques, and the numbers of
- * 4-cycles and 4-cliques.  On graphs of up to 16,384 vertices four more
- * come from the rows of A^2 and the triangles: the 5-cycle's from closed
- * walks, [tr(A^5) - 30 T - 10 sum_v (d_v - 2) t_v] / 10 (T triangles, t_v
+ * 4-cycles and 4-cliques.  On graphs of up to 16,384 vertices five more
+ * come from the rows of A^2, the triangles and the neighbourhoods: the
+ * 5-cycle's from closed walks,
+ * [tr(A^5) - 30 T - 10 sum_v (d_v - 2) t_v] / 10 (T triangles, t_v
  * those at v), K_{2,3}'s as the sum over vertex pairs of C(common
  * neighbours, 3), that of two triangles on an edge whose tips share a
  * third neighbour from pairs and triangles, and K5 minus an edge's as the
- * sum over triangles of C(vertices adjacent to all three, 2); on larger
- * graphs the four are counted directly.  The other two classes (the wheel
- * and K5), whose induced copies are few, are counted directly: the wheel
- * as a vertex-induced pattern by the general plan, the 5-clique by the
- * clique kernels.  Writes d_counts (device uint64[22]): the 21
+ * sum over triangles of C(vertices adjacent to all three, 2), and the
+ * wheel's as the sum over vertices of the 4-cycles among their neighbours;
+ * on larger graphs the five are counted directly as vertex-induced
+ * patterns by the general plan.  K5 is counted by the clique kernels.
+ * Writes d_counts (device uint64[22]): the 21
  * classes in gpm_motif_class_pattern order (the same values as
  * gpm_motif_count_enum), then a status word, 0 when every subtraction
  * stayed non-negative and every count fits 64 bits.  k must be 5
