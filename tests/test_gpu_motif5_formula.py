@@ -1,5 +1,6 @@
-"""Induced 5-motif counts by formulas (local counts, the general plan for
-the dense classes, back-substitution) against the oracle class by class,
+"""Induced 5-motif counts by formulas (local counts, rows of A^2, the
+4-cycles in each neighbourhood, the clique kernels for K5, the general plan
+above the LDS limit, back-substitution) against the oracle class by class,
 against closed forms, and against the enumeration route."""
 from math import comb
 
@@ -110,4 +111,41 @@ def test_formula_route_core_orientation(gpm):
     g.orient(gpm.ORIENT_CORE)
     assert gpm.motif_count_formula(g, 5) == want
     g.orient(gpm.ORIENT_DEGREE)
+    assert gpm.motif_count_formula(g, 5) == want
+
+
+def big_hub():
+    """A vertex joined to all 150 vertices of a sparse random graph: its
+    triangles are walked in two tasks of at most 128 of its neighbours."""
+    base = graphgen.erdos_renyi(150, 0.05, 11)
+    hub = np.full(150, 150, np.int32)
+    return graphgen.EdgeList(151, np.concatenate([base.u, hub]),
+                             np.concatenate([base.v, np.arange(150, dtype=np.int32)]), "hub150")
+
+
+def padded(e, n, seed):
+    """e with isolated vertices up to n, ids permuted over all n."""
+    return graphgen.relabel(graphgen.EdgeList(n, e.u, e.v, f"{e.name}+{n - e.n}"), seed)
+
+
+@pytest.fixture(scope="module")
+def big_hub_counts(gpm):
+    e = big_hub()
+    off, adj = oracle.canonical_csr(e.n, e.u, e.v)
+    return e, [oracle.pattern_count(off, adj, 5, gpm.motif_class_pattern(5, i), True)[0]
+               for i in range(21)]
+
+
+@pytest.mark.parametrize("n", [151, 16384, 16385])
+def test_formula_route_hub_and_lds_limit(gpm, big_hub_counts, n):
+    """The hub graph alone, and padded with isolated vertices (which change
+    no count) to 16,384 vertices, the largest graph whose rows of A^2 and
+    wheel counters fit in LDS (the 512-thread form of the A^2-row kernel,
+    139 KB of counters and bitmaps per wheel workgroup), and to 16,385, where
+    the 5-cycle, K_{2,3}, class 16, K5 minus an edge and the wheel are
+    counted directly.  All equal the oracle's counts of the hub graph."""
+    e, want = big_hub_counts
+    assert want[18] > 0 and want[19] > 0   # wheels and K5 minus an edge
+    print(f"5-motif formula, hub graph on {n} vertices", flush=True)
+    g = build(gpm, e if n == e.n else padded(e, n, n))
     assert gpm.motif_count_formula(g, 5) == want
