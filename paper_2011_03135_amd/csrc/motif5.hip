@@ -106,7 +106,7 @@ constexpr int kFormulaClass[F_COUNT] = {0, 1, 2, 3, 4, 5, 6, 8, 9, 11, 12, 13, 1
 // wheel need dense per-vertex arrays in LDS (a row of A^2, neighbour
 // bitmaps, 16-bit counters): graphs of up to kTrace5MaxN vertices (above,
 // the five are counted directly)
-constexpr int32_t kTrace5MaxN = 16384;
+constexpr int32_t kTrace5MaxN = 32768;
 constexpr int kK5Class = 20;
 
 struct Back {
@@ -231,17 +231,21 @@ __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ of
                                                   const int32_t *__restrict__ adj, int32_t n,
                                                   int32_t nparts, unsigned long long *acc) {
     extern __shared__ uint32_t s_dyn[];
-    uint32_t *p2 = s_dyn;                               // n counters
-    int32_t *reach = reinterpret_cast<int32_t *>(s_dyn + n);   // the j with P2 > 0
-    uint32_t *nbm = s_dyn + 2 * (int64_t)n;             // bitmap of N(i)
+    // P2(i, j) < n <= 65536 and j < 65536: 16-bit counters packed two to a
+    // word, then the reached j as 16-bit entries, then the bitmaps
+    const int32_t hw = (n + 1) / 2;
+    uint32_t *p2w = s_dyn;                               // ceil(n / 2) words
+    uint16_t *reach = reinterpret_cast<uint16_t *>(s_dyn + hw);   // the j with P2 > 0
+    uint32_t *nbm = s_dyn + 2 * (int64_t)hw;             // bitmap of N(i)
     const int32_t nbw = (n + 31) / 32;
+    auto p2 = [&](int32_t j) -> uint32_t { return (p2w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu; };
     __shared__ uint32_t s_nreach;
     __shared__ int64_t s_task;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     const int grp = lane / kTriLanes, gl = lane % kTriLanes;
     constexpr int NW = NT / kWave;
     uint32_t *wbm = nbm + (int64_t)(1 + wid) * nbw;     // this wave's bitmap of N(a)
-    for (int32_t i = tid; i < n; i += NT) p2[i] = 0;
+    for (int32_t i = tid; i < hw; i += NT) p2w[i] = 0;
     for (int32_t i = tid; i < (1 + NW) * nbw; i += NT) nbm[i] = 0;
     if (tid == 0) s_nreach = 0;
     __syncthreads();
@@ -265,14 +269,16 @@ __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ of
             const int32_t x = adj[si + a], sx = off[x], dx = off[x + 1] - sx;
             for (int32_t b = lane; b < dx; b += kWave) {
                 const int32_t j = adj[sx + b];
-                if (atomicAdd(&p2[j], 1u) == 0u) reach[atomicAdd(&s_nreach, 1u)] = j;
+                const uint32_t sh = (uint32_t)(j & 1) * 16u;
+                if (((atomicAdd(&p2w[j >> 1], 1u << sh) >> sh) & 0xFFFFu) == 0u)
+                    reach[atomicAdd(&s_nreach, 1u)] = (uint16_t)j;
             }
         }
         __syncthreads();
         const int32_t nr = (int32_t)s_nreach;
         for (int32_t r = tid; r < nr && part == 0; r += NT) {
             const int32_t j = reach[r];
-            const uint64_t c = p2[j];
+            const uint64_t c = p2(j);
             if (j > i && c >= 3) k23 += (u128)(c * (c - 1) * (c - 2) / 6);
         }
         // sum over the reached j of P2(i, j) times the P2 of j's neighbours,
@@ -282,9 +288,9 @@ __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ of
         for (int32_t r = wid; r < nr && part == 0; r += NW) {
             const int32_t j = reach[r], sj = off[j], dj = off[j + 1] - sj;
             if (j != i && (dj > di || (dj == di && j > i))) continue;
-            const uint64_t pj = (uint64_t)p2[j] << (j != i);
+            const uint64_t pj = (uint64_t)p2(j) << (j != i);
             uint64_t sum = 0;
-            for (int32_t b = lane; b < dj; b += kWave) sum += p2[adj[sj + b]];
+            for (int32_t b = lane; b < dj; b += kWave) sum += p2(adj[sj + b]);
             tr += (u128)(pj * sum);
         }
         for (int32_t a = tid; a < di; a += NT) {
@@ -324,7 +330,7 @@ __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ of
                     for (int32_t k = gl; k < db; k += kTriLanes) {
                         const int32_t d = adj[sb + k];
                         if (d != i && ((wbm[d >> 5] >> (d & 31)) & 1u)) {
-                            twin += (u128)p2[d];
+                            twin += (u128)p2(d);
                             q += (nbm[d >> 5] >> (d & 31)) & 1u;
                         }
                     }
@@ -338,7 +344,8 @@ __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ of
             wave_sync();
         }
         __syncthreads();
-        for (int32_t r = tid; r < nr; r += NT) p2[reach[r]] = 0;
+        // a word's two counters belong to reached vertices or are zero
+        for (int32_t r = tid; r < nr; r += NT) p2w[reach[r] >> 1] = 0u;
         for (int32_t a = tid; a < di; a += NT) nbm[adj[si + a] >> 5] = 0u;
         if (tid == 0) s_nreach = 0;
         __syncthreads();
@@ -872,7 +879,7 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
         // wave's N(a): the widest workgroup (16, 8 or 4 waves, one vertex
         // each) whose LDS fits, so that a hub's triangles spread widest
         auto shmem_of = [&](int nt) {
-            return (size_t)n * 8 + (size_t)((n + 31) / 32) * 4 * (1 + nt / kWave);
+            return (size_t)((n + 1) / 2) * 8 + (size_t)((n + 31) / 32) * 4 * (1 + nt / kWave);
         };
         const int nt = shmem_of(1024) <= 160 * 1024 ? 1024 : shmem_of(512) <= 160 * 1024 ? 512 : 256;
         const size_t shmem = shmem_of(nt);
@@ -895,15 +902,17 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
     GPM_LAUNCH_CHECK("k_f5_trace5");
     if (trace5 && m > 0) {
         Span sp("k_f5_wheel", st);
-        // per wave: the counters c(x, .) and the bitmap of N(i)
-        const size_t shmem = (size_t)wheel_words_per_wave(n) * 4 * (kBlock / kWave);
+        // per wave: the counters c(x, .) and the bitmap of N(i); 4 waves
+        // per workgroup, fewer where their LDS does not fit
+        const size_t per_wave = (size_t)wheel_words_per_wave(n) * 4;
+        const int waves = per_wave * 4 <= 160 * 1024 ? 4 : per_wave * 2 <= 160 * 1024 ? 2 : 1;
+        const size_t shmem = per_wave * waves;
         const int per_cu =
             (int)std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / (int64_t)(shmem + 1024)));
         const int64_t arcs = 2 * m;
         hipLaunchKernelGGL(k_f5_wheel,
-                           dim3(grid_for((arcs + kWheelArcs - 1) / kWheelArcs, kBlock / kWave,
-                                         per_cu)),
-                           dim3(kBlock), shmem, st, g->off, g->adj, n, arcs, W.acc);
+                           dim3(grid_for((arcs + kWheelArcs - 1) / kWheelArcs, waves, per_cu)),
+                           dim3(waves * kWave), shmem, st, g->off, g->adj, n, arcs, W.acc);
     }
     GPM_LAUNCH_CHECK("k_f5_wheel");
     // 4-cycles (edge sets) and the sums over them
