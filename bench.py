@@ -649,6 +649,37 @@ def local_graph_leg(gpm, torch, scale, reps=3):
     return res
 
 
+def formula_scale_leg(gpm, torch, scales=(10, 11, 12, 13, 14, 15), reps=3):
+    """The 5-motif formula route alone on RMAT-10 .. RMAT-15 (RMAT-15: 32,768
+    vertices, the largest graph whose per-vertex arrays fit in LDS): call
+    time (one warm-up, `reps` timed calls) and the per-kernel spans."""
+    import graphgen
+
+    out = []
+    for sc in scales:
+        e = graphgen.rmat(sc, seed=sc)
+        g = gpm.Graph.build(e.n, torch.from_numpy(e.u).cuda(), torch.from_numpy(e.v).cuda())
+        ws = torch.empty(gpm.motif_formula_workspace_bytes(g, 5), dtype=torch.uint8,
+                         device="cuda")
+        c = gpm.motif_count_formula(g, 5, ws=ws)
+        torch.cuda.synchronize()
+        gpm.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            c = gpm.motif_count_formula(g, 5, ws=ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        gpm.timing_enable(False)
+        spans = {}
+        for name, t, _ in gpm.timing_read():
+            if name.startswith("k_f5"):
+                spans[name] = round(spans.get(name, 0.0) + t / reps, 3)
+        out.append({"graph": f"rmat{sc}", "n": g.n, "m": g.m, "ms": ms,
+                    "connected_5_subgraphs": sum(c),
+                    "subgraphs_per_sec": sum(c) / (ms * 1e-3), "spans_ms": spans})
+    return out
+
+
 def motif_enum_leg(gpm, torch, scale4=12, scale5=10, reps=3, enum5_large=False):
     """Pattern-oblivious motif counting (vertex extension of canonical
     embeddings, connectivity codes; no counting formulas): the 4-motifs of
@@ -828,6 +859,8 @@ def main():
     ap.add_argument("--enum5-large", action="store_true",
                     help="with --motif-enum-only: also time one 5-motif enumeration of "
                          "RMAT-12 (about 5 s) against the formula route")
+    ap.add_argument("--formula-only", action="store_true",
+                    help="time only the 5-motif formula route on RMAT-10 .. RMAT-15 and exit")
     ap.add_argument("--motif-only", action="store_true",
                     help="time only the RMAT-18 motif and listing leg (for kernel traces) and exit")
     ap.add_argument("--no-motif", action="store_true")
@@ -867,6 +900,9 @@ def main():
         return
     if args.lg_ablation_only:
         print(json.dumps({"local_graph_ablation": local_graph_leg(gpm, torch, 14)}))
+        return
+    if args.formula_only:
+        print(json.dumps({"formula_scaling": formula_scale_leg(gpm, torch)}))
         return
     if args.motif_enum_only:
         print(json.dumps({"motif_enumeration": motif_enum_leg(gpm, torch,
