@@ -366,19 +366,27 @@ __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ of
 // vertex opposite x: C(c(x, y), 2) over the y < x in N(i), c(x, y) = the
 // common neighbours p < x of x and y in N(i).  A wave per arc (i, x), the
 // arcs taken kWheelArcs at a time from a cursor (consecutive arcs share i,
-// whose neighbours stay marked in the wave's LDS bitmap); c(x, .) in 16-bit
-// counters packed two to an LDS word (c < n <= kTrace5MaxN), each increment
-// adding the count before it (0 + 1 + ... + (c - 1) = C(c, 2)), then
-// cleared whole.  Rows are sorted, so only their entries below x are read,
-// kWheelU chunks of 64 in flight per wave.
+// whose neighbours stay marked in the wave's LDS bitmap, with the number of
+// marks before each bitmap word); c(x, y) in 16-bit counters packed two to
+// an LDS word and indexed by y's position in N(i) (c < d(i) < 65536), so a
+// wave's counters take 2 bytes per vertex of the largest degree, not per
+// vertex of the graph; each increment adds the count before it (0 + 1 + ...
+// + (c - 1) = C(c, 2)), then the first d(i) counters are cleared.  Rows are
+// sorted, so only their entries below x are read, kWheelU chunks of 64 in
+// flight per wave.
 constexpr int kWheelArcs = 4;
 constexpr int kWheelU = 4;
 
-__host__ __device__ constexpr int32_t wheel_count_words(int32_t n) {
-    return ((n + 1) / 2 + 3) / 4 * 4;
+// LDS words per wave: counters (max degree), bitmap (n bits), 16-bit
+// prefix per bitmap word; each part a multiple of 4 words
+__host__ __device__ constexpr int32_t wheel_count_words(int32_t maxdeg) {
+    return ((maxdeg + 1) / 2 + 3) / 4 * 4;
 }
-__host__ __device__ constexpr int32_t wheel_words_per_wave(int32_t n) {
-    return wheel_count_words(n) + ((n + 31) / 32 + 3) / 4 * 4;
+__host__ __device__ constexpr int32_t wheel_bitmap_words(int32_t n) {
+    return ((n + 31) / 32 + 3) / 4 * 4;
+}
+__host__ __device__ constexpr int32_t wheel_words_per_wave(int32_t n, int32_t maxdeg) {
+    return wheel_count_words(maxdeg) + wheel_bitmap_words(n) + (wheel_bitmap_words(n) / 2 + 3) / 4 * 4;
 }
 
 __device__ __forceinline__ bool marked(const uint32_t *bm, int32_t v) {
@@ -387,13 +395,16 @@ __device__ __forceinline__ bool marked(const uint32_t *bm, int32_t v) {
 
 __global__ void __launch_bounds__(kBlock) k_f5_wheel(const int32_t *__restrict__ off,
                                                      const int32_t *__restrict__ adj, int32_t n,
-                                                     int64_t arcs, unsigned long long *acc) {
+                                                     int32_t maxdeg, int64_t arcs,
+                                                     unsigned long long *acc) {
     extern __shared__ uint4 s_wheel[];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
-    const int32_t cw = wheel_count_words(n), ww = wheel_words_per_wave(n);
+    const int32_t cw = wheel_count_words(maxdeg), ww = wheel_words_per_wave(n, maxdeg);
+    const int32_t nbw = (n + 31) / 32;
     uint32_t *cnt = reinterpret_cast<uint32_t *>(s_wheel) + (int64_t)wid * ww;
     uint4 *cnt4 = reinterpret_cast<uint4 *>(cnt);
     uint32_t *bm = cnt + cw;                    // N(i)
+    uint16_t *pf = reinterpret_cast<uint16_t *>(bm + wheel_bitmap_words(n));   // marks before
     for (int32_t k = lane; k < ww; k += kWave) cnt[k] = 0u;
     wave_sync();
     u128 sum = 0;
@@ -424,6 +435,14 @@ __global__ void __launch_bounds__(kBlock) k_f5_wheel(const int32_t *__restrict__
                     atomicOr(&bm[v >> 5], 1u << (v & 31));
                 }
                 wave_sync();
+                int32_t carry = 0;
+                for (int32_t w0 = 0; w0 < nbw; w0 += kWave) {
+                    const int32_t c = w0 + lane < nbw ? __popc(bm[w0 + lane]) : 0;
+                    const int32_t incl = wave_incl_scan(c);
+                    if (w0 + lane < nbw) pf[w0 + lane] = (uint16_t)(carry + incl - c);
+                    carry += __shfl(incl, kWave - 1, kWave);
+                }
+                wave_sync();
                 cur = i;
             }
             const int32_t x = adj[t], sx = off[x], dx = off[x + 1] - sx;
@@ -446,10 +465,15 @@ __global__ void __launch_bounds__(kBlock) k_f5_wheel(const int32_t *__restrict__
                         }
 #pragma unroll
                         for (int u = 0; u < kWheelU; u++) {
-                            if (y[u] < x && marked(bm, y[u])) {
-                                const uint32_t sh = (uint32_t)(y[u] & 1) * 16u;
-                                const uint32_t old = atomicAdd(&cnt[y[u] >> 1], 1u << sh);
-                                sum += (old >> sh) & 0xFFFFu;
+                            if (y[u] < x) {
+                                const uint32_t wv = bm[y[u] >> 5], b = (uint32_t)(y[u] & 31);
+                                if ((wv >> b) & 1u) {
+                                    // y's position in N(i)
+                                    const int32_t r = pf[y[u] >> 5] + __popc(wv & ((1u << b) - 1u));
+                                    const uint32_t sh = (uint32_t)(r & 1) * 16u;
+                                    const uint32_t old = atomicAdd(&cnt[r >> 1], 1u << sh);
+                                    sum += (old >> sh) & 0xFFFFu;
+                                }
                             }
                         }
                         if (__ballot(y[kWheelU - 1] >= x)) break;   // the rest are >= x
@@ -457,9 +481,10 @@ __global__ void __launch_bounds__(kBlock) k_f5_wheel(const int32_t *__restrict__
                 }
                 if (__ballot(p >= x)) break;
             }
-            if (touched) {
+            if (touched) {   // the first d(i) counters: ceil(d(i) / 8) uint4
+                const int32_t nclr = (off[i + 1] - off[i] + 7) / 8;
                 wave_sync();
-                for (int32_t k = lane; k < cw / 4; k += kWave) cnt4[k] = make_uint4(0u, 0u, 0u, 0u);
+                for (int32_t k = lane; k < nclr; k += kWave) cnt4[k] = make_uint4(0u, 0u, 0u, 0u);
                 wave_sync();
             }
         }
@@ -904,7 +929,7 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
         Span sp("k_f5_wheel", st);
         // per wave: the counters c(x, .) and the bitmap of N(i); 4 waves
         // per workgroup, fewer where their LDS does not fit
-        const size_t per_wave = (size_t)wheel_words_per_wave(n) * 4;
+        const size_t per_wave = (size_t)wheel_words_per_wave(n, g->max_degree) * 4;
         const int waves = per_wave * 4 <= 160 * 1024 ? 4 : per_wave * 2 <= 160 * 1024 ? 2 : 1;
         const size_t shmem = per_wave * waves;
         const int per_cu =
@@ -912,7 +937,8 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
         const int64_t arcs = 2 * m;
         hipLaunchKernelGGL(k_f5_wheel,
                            dim3(grid_for((arcs + kWheelArcs - 1) / kWheelArcs, waves, per_cu)),
-                           dim3(waves * kWave), shmem, st, g->off, g->adj, n, arcs, W.acc);
+                           dim3(waves * kWave), shmem, st, g->off, g->adj, n, g->max_degree,
+                           arcs, W.acc);
     }
     GPM_LAUNCH_CHECK("k_f5_wheel");
     // 4-cycles (edge sets) and the sums over them
