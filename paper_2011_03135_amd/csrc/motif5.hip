@@ -214,9 +214,9 @@ __global__ void __launch_bounds__(kBlock) k_f5_vertex(const int32_t *__restrict_
 // it, C(k4(t), 2) summed over the triangles, k4(t) = the common neighbours
 // of a and b also adjacent to c (each triangle is met at each of its three
 // vertices, so the sum is three times the count).  A
-// workgroup per task (i, part) builds P2(i, .) densely in LDS (n entries)
-// and lists the j it reaches; part 0 sums over the listed j and their
-// neighbours; each part marks N(i) in an LDS bitmap and walks the
+// workgroup per task (i, part) builds P2(i, .) densely in LDS (n 16-bit
+// counters, no list of the j it reaches: a ballot over the counter words
+// finds them); part 0 sums over the reached j and their neighbours; each part marks N(i) in an LDS bitmap and walks the
 // triangles at i whose end a of larger degree is among its kTracePart
 // neighbours of i (each wave with the bitmap of its a, two triangles at a
 // time, 32 lanes on each), then clears what it set.  The tasks come from a
@@ -230,24 +230,22 @@ template <int NT>
 __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ off,
                                                   const int32_t *__restrict__ adj, int32_t n,
                                                   int32_t nparts, unsigned long long *acc) {
-    extern __shared__ uint32_t s_dyn[];
-    // P2(i, j) < n <= 65536 and j < 65536: 16-bit counters packed two to a
-    // word, then the reached j as 16-bit entries, then the bitmaps
-    const int32_t hw = (n + 1) / 2;
-    uint32_t *p2w = s_dyn;                               // ceil(n / 2) words
-    uint16_t *reach = reinterpret_cast<uint16_t *>(s_dyn + hw);   // the j with P2 > 0
-    uint32_t *nbm = s_dyn + 2 * (int64_t)hw;             // bitmap of N(i)
+    extern __shared__ uint4 s_trace[];
+    // P2(i, j) < n <= 65536: 16-bit counters packed two to a word (hw4
+    // words, a multiple of 4), then the bitmaps; the reached j are the
+    // nonzero counters, found by scanning the words
+    const int32_t hw = (n + 1) / 2, hw4 = (hw + 3) / 4 * 4;
+    uint32_t *p2w = reinterpret_cast<uint32_t *>(s_trace);
+    uint32_t *nbm = p2w + hw4;                           // bitmap of N(i)
     const int32_t nbw = (n + 31) / 32;
     auto p2 = [&](int32_t j) -> uint32_t { return (p2w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu; };
-    __shared__ uint32_t s_nreach;
     __shared__ int64_t s_task;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     const int grp = lane / kTriLanes, gl = lane % kTriLanes;
     constexpr int NW = NT / kWave;
     uint32_t *wbm = nbm + (int64_t)(1 + wid) * nbw;     // this wave's bitmap of N(a)
-    for (int32_t i = tid; i < hw; i += NT) p2w[i] = 0;
+    for (int32_t i = tid; i < hw4; i += NT) p2w[i] = 0;
     for (int32_t i = tid; i < (1 + NW) * nbw; i += NT) nbm[i] = 0;
-    if (tid == 0) s_nreach = 0;
     __syncthreads();
     u128 tr = 0, k23 = 0, twin = 0, k5e = 0;
     // tasks (i, part) from a cursor, the parts from the last down, so that
@@ -269,29 +267,47 @@ __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ of
             const int32_t x = adj[si + a], sx = off[x], dx = off[x + 1] - sx;
             for (int32_t b = lane; b < dx; b += kWave) {
                 const int32_t j = adj[sx + b];
-                const uint32_t sh = (uint32_t)(j & 1) * 16u;
-                if (((atomicAdd(&p2w[j >> 1], 1u << sh) >> sh) & 0xFFFFu) == 0u)
-                    reach[atomicAdd(&s_nreach, 1u)] = (uint16_t)j;
+                atomicAdd(&p2w[j >> 1], 1u << ((uint32_t)(j & 1) * 16u));
             }
         }
         __syncthreads();
-        const int32_t nr = (int32_t)s_nreach;
-        for (int32_t r = tid; r < nr && part == 0; r += NT) {
-            const int32_t j = reach[r];
-            const uint64_t c = p2(j);
-            if (j > i && c >= 3) k23 += (u128)(c * (c - 1) * (c - 2) / 6);
-        }
-        // sum over the reached j of P2(i, j) times the P2 of j's neighbours,
-        // (A^3)_ij; the term is symmetric in i and j, so each pair j != i is
-        // taken once, doubled, at its end of larger (degree, id), walking
-        // the row of the other
-        for (int32_t r = wid; r < nr && part == 0; r += NW) {
-            const int32_t j = reach[r], sj = off[j], dj = off[j + 1] - sj;
-            if (j != i && (dj > di || (dj == di && j > i))) continue;
-            const uint64_t pj = (uint64_t)p2(j) << (j != i);
-            uint64_t sum = 0;
-            for (int32_t b = lane; b < dj; b += kWave) sum += p2(adj[sj + b]);
-            tr += (u128)(pj * sum);
+        if (part == 0) {
+            for (int32_t w = tid; w < hw; w += NT) {
+                const uint32_t v = p2w[w];
+                if (!v) continue;
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int32_t j = 2 * w + h;
+                    const uint64_t c = (v >> (16 * h)) & 0xFFFFu;
+                    if (j > i && c >= 3) k23 += (u128)(c * (c - 1) * (c - 2) / 6);
+                }
+            }
+            // sum over the reached j of P2(i, j) times the P2 of j's
+            // neighbours, (A^3)_ij; the term is symmetric in i and j, so each
+            // pair j != i is taken once, doubled, at its end of larger
+            // (degree, id), walking the row of the other; a wave per 64
+            // counter words, their nonzero ones by ballot
+            for (int32_t w0 = wid * kWave; w0 < hw; w0 += NW * kWave) {
+                const uint32_t v = w0 + lane < hw ? p2w[w0 + lane] : 0u;
+                uint64_t mask = __ballot(v != 0u);
+                while (mask) {
+                    const int src = __builtin_ctzll(mask);
+                    mask &= mask - 1ull;
+                    const uint32_t vv = __shfl(v, src, kWave);
+#pragma unroll
+                    for (int h = 0; h < 2; h++) {
+                        const uint64_t pv = (vv >> (16 * h)) & 0xFFFFu;
+                        const int32_t j = 2 * (w0 + src) + h;
+                        if (!pv) continue;
+                        const int32_t sj = off[j], dj = off[j + 1] - sj;
+                        if (j != i && (dj > di || (dj == di && j > i))) continue;
+                        const uint64_t pj = pv << (j != i);
+                        uint64_t sum = 0;
+                        for (int32_t b = lane; b < dj; b += kWave) sum += p2(adj[sj + b]);
+                        tr += (u128)(pj * sum);
+                    }
+                }
+            }
         }
         for (int32_t a = tid; a < di; a += NT) {
             const int32_t x = adj[si + a];
@@ -344,10 +360,9 @@ __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ of
             wave_sync();
         }
         __syncthreads();
-        // a word's two counters belong to reached vertices or are zero
-        for (int32_t r = tid; r < nr; r += NT) p2w[reach[r] >> 1] = 0u;
+        uint4 *p2w4 = reinterpret_cast<uint4 *>(p2w);
+        for (int32_t k = tid; k < hw4 / 4; k += NT) p2w4[k] = make_uint4(0u, 0u, 0u, 0u);
         for (int32_t a = tid; a < di; a += NT) nbm[adj[si + a] >> 5] = 0u;
-        if (tid == 0) s_nreach = 0;
         __syncthreads();
     }
     tr = wave_sum_u128(tr);
@@ -904,7 +919,8 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
         // wave's N(a): the widest workgroup (16, 8 or 4 waves, one vertex
         // each) whose LDS fits, so that a hub's triangles spread widest
         auto shmem_of = [&](int nt) {
-            return (size_t)((n + 1) / 2) * 8 + (size_t)((n + 31) / 32) * 4 * (1 + nt / kWave);
+            return (size_t)(((n + 1) / 2 + 3) / 4 * 4) * 4 +
+                   (size_t)((n + 31) / 32) * 4 * (1 + nt / kWave);
         };
         const int nt = shmem_of(1024) <= 160 * 1024 ? 1024 : shmem_of(512) <= 160 * 1024 ? 512 : 256;
         const size_t shmem = shmem_of(nt);
