@@ -106,7 +106,7 @@ constexpr int kFormulaClass[F_COUNT] = {0, 1, 2, 3, 4, 5, 6, 8, 9, 11, 12, 13, 1
 // wheel need dense per-vertex arrays in LDS (a row of A^2, neighbour
 // bitmaps, 16-bit counters): graphs of up to kTrace5MaxN vertices (above,
 // the five are counted directly)
-constexpr int32_t kTrace5MaxN = 32768;
+constexpr int32_t kTrace5MaxN = 65536;
 constexpr int kK5Class = 20;
 
 struct Back {
@@ -916,13 +916,16 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
     if (trace5 && m > 0) {
         Span sp("k_f5_trace5", st);
         // P2 counters, the reached list, the bitmaps of N(i) and of each
-        // wave's N(a): the widest workgroup (16, 8 or 4 waves, one vertex
+        // wave's N(a): the widest workgroup (16, 8, 4 or 2 waves, one vertex
         // each) whose LDS fits, so that a hub's triangles spread widest
         auto shmem_of = [&](int nt) {
             return (size_t)(((n + 1) / 2 + 3) / 4 * 4) * 4 +
                    (size_t)((n + 31) / 32) * 4 * (1 + nt / kWave);
         };
-        const int nt = shmem_of(1024) <= 160 * 1024 ? 1024 : shmem_of(512) <= 160 * 1024 ? 512 : 256;
+        const int nt = shmem_of(1024) <= 160 * 1024  ? 1024
+                       : shmem_of(512) <= 160 * 1024 ? 512
+                       : shmem_of(256) <= 160 * 1024 ? 256
+                                                     : 128;
         const size_t shmem = shmem_of(nt);
         const int per_cu =
             (int)std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / (int64_t)(shmem + 1024)));
@@ -936,8 +939,11 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
         else if (nt == 512)
             hipLaunchKernelGGL(k_f5_trace5<512>, grid, dim3(512), shmem, st, g->off, g->adj, n,
                                nparts, W.acc);
-        else
+        else if (nt == 256)
             hipLaunchKernelGGL(k_f5_trace5<256>, grid, dim3(256), shmem, st, g->off, g->adj, n,
+                               nparts, W.acc);
+        else
+            hipLaunchKernelGGL(k_f5_trace5<128>, grid, dim3(128), shmem, st, g->off, g->adj, n,
                                nparts, W.acc);
     }
     GPM_LAUNCH_CHECK("k_f5_trace5");
