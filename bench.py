@@ -649,10 +649,10 @@ def local_graph_leg(gpm, torch, scale, reps=3):
     return res
 
 
-def formula_scale_leg(gpm, torch, scales=(10, 11, 12, 13, 14, 15), reps=3):
-    """The 5-motif formula route alone on RMAT-10 .. RMAT-15 (RMAT-15: 32,768
-    vertices, the largest graph whose per-vertex arrays fit in LDS): call
-    time (one warm-up, `reps` timed calls) and the per-kernel spans."""
+def formula_scale_leg(gpm, torch, scales=(10, 11, 12, 13, 14, 15, 16), reps=3):
+    """The 5-motif formula route alone on RMAT-10 .. RMAT-16 (RMAT-16: 65,536
+    vertices, the largest graph whose rows of A^2 fit in LDS): call time (one
+    warm-up, `reps` timed calls) and the per-kernel spans."""
     import graphgen
 
     out = []
@@ -860,7 +860,7 @@ def main():
                     help="with --motif-enum-only: also time one 5-motif enumeration of "
                          "RMAT-12 (about 5 s) against the formula route")
     ap.add_argument("--formula-only", action="store_true",
-                    help="time only the 5-motif formula route on RMAT-10 .. RMAT-15 and exit")
+                    help="time only the 5-motif formula route on RMAT-10 .. RMAT-16 and exit")
     ap.add_argument("--motif-only", action="store_true",
                     help="time only the RMAT-18 motif and listing leg (for kernel traces) and exit")
     ap.add_argument("--no-motif", action="store_true")

@@ -383,7 +383,7 @@ gpm_status gpm_motif_count_enum(const gpm_graph *g, int32_t k, void *d_ws, uint6
  * closed forms in local counts: degrees, per-edge triangle counts
  * (Section 5), per-vertex triangle counts, neighbour-degree sums, sums
  * over the triangles, the 4-cycles and the 4-cliques, and the numbers of
- * 4-cycles and 4-cliques.  On graphs of up to 32,768 vertices five more
+ * 4-cycles and 4-cliques.  On graphs of up to 65,536 vertices five more
  * come from the rows of A^2, the triangles and the neighbourhoods: the
  * 5-cycle's from closed walks,
  * [tr(A^5) - 30 T - 10 sum_v (d_v - 2) t_v] / 10 (T triangles, t_v
