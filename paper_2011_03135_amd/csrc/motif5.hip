@@ -915,9 +915,9 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
     GPM_LAUNCH_CHECK("k_f5_local");
     if (trace5 && m > 0) {
         Span sp("k_f5_trace5", st);
-        // P2 counters, the reached list, the bitmaps of N(i) and of each
-        // wave's N(a): the widest workgroup (16, 8, 4 or 2 waves, one vertex
-        // each) whose LDS fits, so that a hub's triangles spread widest
+        // 16-bit P2 counters, the bitmaps of N(i) and of each wave's N(a):
+        // the widest workgroup (16, 8, 4 or 2 waves, one task each) whose
+        // LDS fits, so that a hub's triangles spread widest
         auto shmem_of = [&](int nt) {
             return (size_t)(((n + 1) / 2 + 3) / 4 * 4) * 4 +
                    (size_t)((n + 31) / 32) * 4 * (1 + nt / kWave);
