@@ -949,10 +949,10 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
     GPM_LAUNCH_CHECK("k_f5_trace5");
     if (trace5 && m > 0) {
         Span sp("k_f5_wheel", st);
-        // per wave: the counters c(x, .) and the bitmap of N(i); 4 waves
-        // per workgroup, fewer where their LDS does not fit
+        // per wave: the counters c(x, .) and the bitmap of N(i); up to 4
+        // waves per workgroup, as many as their LDS allows
         const size_t per_wave = (size_t)wheel_words_per_wave(n, g->max_degree) * 4;
-        const int waves = per_wave * 4 <= 160 * 1024 ? 4 : per_wave * 2 <= 160 * 1024 ? 2 : 1;
+        const int waves = (int)std::max<size_t>(1, std::min<size_t>(4, (160 * 1024) / per_wave));
         const size_t shmem = per_wave * waves;
         const int per_cu =
             (int)std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / (int64_t)(shmem + 1024)));
