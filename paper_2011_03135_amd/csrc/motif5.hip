@@ -226,7 +226,7 @@ constexpr int32_t kTracePart = 128;             // neighbours a per triangle-wal
 constexpr int kTriLanes = 32;                   // lanes per triangle walked
 constexpr int kTriGroups = kWave / kTriLanes;   // triangles per wave at a time
 
-template <int NT>
+template <int NT, bool SHARED>
 __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ off,
                                                   const int32_t *__restrict__ adj, int32_t n,
                                                   int32_t nparts, unsigned long long *acc) {
@@ -243,9 +243,10 @@ __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ of
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
     const int grp = lane / kTriLanes, gl = lane % kTriLanes;
     constexpr int NW = NT / kWave;
-    uint32_t *wbm = nbm + (int64_t)(1 + wid) * nbw;     // this wave's bitmap of N(a)
+    // this wave's bitmap of N(a) (SHARED: one for the workgroup, after N(i))
+    uint32_t *wbm = nbm + (int64_t)(1 + (SHARED ? 0 : wid)) * nbw;
     for (int32_t i = tid; i < hw4; i += NT) p2w[i] = 0;
-    for (int32_t i = tid; i < (1 + NW) * nbw; i += NT) nbm[i] = 0;
+    for (int32_t i = tid; i < (SHARED ? 2 : 1 + NW) * nbw; i += NT) nbm[i] = 0;
     __syncthreads();
     u128 tr = 0, k23 = 0, twin = 0, k5e = 0;
     // tasks (i, part) from a cursor, the parts from the last down, so that
@@ -318,46 +319,67 @@ __global__ void __launch_bounds__(NT) k_f5_trace5(const int32_t *__restrict__ of
         // bitmap; each triangle taken at its end of larger (degree, id), a,
         // walking the other end's row and testing N(a) (and N(i)) in LDS:
         // the common neighbours d != i of a and b add P2(i, d)
-        for (int32_t ai = a_lo + wid; ai < a_hi; ai += NW) {
-            const int32_t a = adj[si + ai], sa = off[a], da = off[a + 1] - sa;
-            for (int32_t k = lane; k < da; k += kWave) {
-                const int32_t x = adj[sa + k];
-                atomicOr(&wbm[x >> 5], 1u << (x & 31));
+        // the triangles of a whose lower ends are N(a)'s entries b0 .. b0+63
+        auto walk = [&](int32_t a, int32_t sa, int32_t da, int32_t b0, const uint32_t *abm) {
+            const int32_t b = b0 + lane < da ? adj[sa + b0 + lane] : -1;
+            bool tri = false;
+            if (b >= 0 && ((nbm[b >> 5] >> (b & 31)) & 1u)) {
+                const int32_t db = off[b + 1] - off[b];
+                tri = db < da || (db == da && b < a);
             }
-            wave_sync();
-            for (int32_t b0 = 0; b0 < da; b0 += kWave) {
-                const int32_t b = b0 + lane < da ? adj[sa + b0 + lane] : -1;
-                bool tri = false;
-                if (b >= 0 && ((nbm[b >> 5] >> (b & 31)) & 1u)) {
-                    const int32_t db = off[b + 1] - off[b];
-                    tri = db < da || (db == da && b < a);
-                }
-                // kTriGroups triangles at a time, kTriLanes lanes each
-                uint64_t mask = __ballot(tri);
-                while (mask) {
-                    uint64_t mm = mask;
-                    for (int g = 0; g < grp && mm; g++) mm &= mm - 1ull;
-                    const bool live = mm != 0ull;
-                    const int src = live ? __builtin_ctzll(mm) : 0;
-                    for (int g = 0; g < kTriGroups && mask; g++) mask &= mask - 1ull;
-                    const int32_t bb = __shfl(b, src, kWave);
-                    const int32_t sb = live ? off[bb] : 0, db = live ? off[bb + 1] - sb : 0;
-                    uint32_t q = 0;   // common neighbours of a, b adjacent to i
-                    for (int32_t k = gl; k < db; k += kTriLanes) {
-                        const int32_t d = adj[sb + k];
-                        if (d != i && ((wbm[d >> 5] >> (d & 31)) & 1u)) {
-                            twin += (u128)p2(d);
-                            q += (nbm[d >> 5] >> (d & 31)) & 1u;
-                        }
+            // kTriGroups triangles at a time, kTriLanes lanes each
+            uint64_t mask = __ballot(tri);
+            while (mask) {
+                uint64_t mm = mask;
+                for (int g = 0; g < grp && mm; g++) mm &= mm - 1ull;
+                const bool live = mm != 0ull;
+                const int src = live ? __builtin_ctzll(mm) : 0;
+                for (int g = 0; g < kTriGroups && mask; g++) mask &= mask - 1ull;
+                const int32_t bb = __shfl(b, src, kWave);
+                const int32_t sb = live ? off[bb] : 0, db = live ? off[bb + 1] - sb : 0;
+                uint32_t q = 0;   // common neighbours of a, b adjacent to i
+                for (int32_t k = gl; k < db; k += kTriLanes) {
+                    const int32_t d = adj[sb + k];
+                    if (d != i && ((abm[d >> 5] >> (d & 31)) & 1u)) {
+                        twin += (u128)p2(d);
+                        q += (nbm[d >> 5] >> (d & 31)) & 1u;
                     }
-#pragma unroll
-                    for (int o = kTriLanes / 2; o > 0; o >>= 1) q += __shfl_xor(q, o, kWave);
-                    if (gl == 0) k5e += (u128)q * (q - (q > 0)) / 2;
                 }
+#pragma unroll
+                for (int o = kTriLanes / 2; o > 0; o >>= 1) q += __shfl_xor(q, o, kWave);
+                if (gl == 0) k5e += (u128)q * (q - (q > 0)) / 2;
             }
-            wave_sync();
-            for (int32_t k = lane; k < da; k += kWave) wbm[adj[sa + k] >> 5] = 0u;
-            wave_sync();
+        };
+        if constexpr (!SHARED) {
+            // a wave per a, N(a) in the wave's own bitmap
+            for (int32_t ai = a_lo + wid; ai < a_hi; ai += NW) {
+                const int32_t a = adj[si + ai], sa = off[a], da = off[a + 1] - sa;
+                for (int32_t k = lane; k < da; k += kWave) {
+                    const int32_t x = adj[sa + k];
+                    atomicOr(&wbm[x >> 5], 1u << (x & 31));
+                }
+                wave_sync();
+                for (int32_t b0 = 0; b0 < da; b0 += kWave) walk(a, sa, da, b0, wbm);
+                wave_sync();
+                for (int32_t k = lane; k < da; k += kWave) wbm[adj[sa + k] >> 5] = 0u;
+                wave_sync();
+            }
+        } else {
+            // the workgroup on one a at a time, N(a) in one shared bitmap,
+            // the waves on its entries 64 at a time
+            uint32_t *abm = nbm + nbw;
+            for (int32_t ai = a_lo; ai < a_hi; ai++) {
+                const int32_t a = adj[si + ai], sa = off[a], da = off[a + 1] - sa;
+                for (int32_t k = tid; k < da; k += NT) {
+                    const int32_t x = adj[sa + k];
+                    atomicOr(&abm[x >> 5], 1u << (x & 31));
+                }
+                __syncthreads();
+                for (int32_t b0 = wid * kWave; b0 < da; b0 += NT) walk(a, sa, da, b0, abm);
+                __syncthreads();
+                for (int32_t k = tid; k < da; k += NT) abm[adj[sa + k] >> 5] = 0u;
+                __syncthreads();
+            }
         }
         __syncthreads();
         uint4 *p2w4 = reinterpret_cast<uint4 *>(p2w);
@@ -915,36 +937,26 @@ gpm_status motif_formula_count(const gpm_graph *g, int32_t k, void *ws, uint64_t
     GPM_LAUNCH_CHECK("k_f5_local");
     if (trace5 && m > 0) {
         Span sp("k_f5_trace5", st);
-        // 16-bit P2 counters, the bitmaps of N(i) and of each wave's N(a):
-        // the widest workgroup (16, 8, 4 or 2 waves, one task each) whose
-        // LDS fits, so that a hub's triangles spread widest
-        auto shmem_of = [&](int nt) {
-            return (size_t)(((n + 1) / 2 + 3) / 4 * 4) * 4 +
-                   (size_t)((n + 31) / 32) * 4 * (1 + nt / kWave);
-        };
-        const int nt = shmem_of(1024) <= 160 * 1024  ? 1024
-                       : shmem_of(512) <= 160 * 1024 ? 512
-                       : shmem_of(256) <= 160 * 1024 ? 256
-                                                     : 128;
-        const size_t shmem = shmem_of(nt);
+        // 16-bit P2 counters, the bitmaps of N(i) and of each wave's N(a)
+        // in 16-wave workgroups; where those bitmaps do not fit (above
+        // about 39,700 vertices), one N(a) bitmap that the workgroup's waves
+        // share, a at a time
+        const size_t p2_bytes = (size_t)(((n + 1) / 2 + 3) / 4 * 4) * 4;
+        const size_t bm_bytes = (size_t)((n + 31) / 32) * 4;
+        const bool shared = p2_bytes + bm_bytes * (1 + 1024 / kWave) > 160 * 1024;
+        const size_t shmem = p2_bytes + bm_bytes * (shared ? 2 : 1 + 1024 / kWave);
         const int per_cu =
             (int)std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / (int64_t)(shmem + 1024)));
         // a vertex's triangles split into parts of kTracePart neighbours
         // a, each part a task that builds the row of A^2 again
         const int32_t nparts = std::max<int32_t>(1, (g->max_degree + kTracePart - 1) / kTracePart);
         const dim3 grid(grid_for((int64_t)n * nparts, 1, per_cu));
-        if (nt == 1024)
-            hipLaunchKernelGGL(k_f5_trace5<1024>, grid, dim3(1024), shmem, st, g->off, g->adj, n,
-                               nparts, W.acc);
-        else if (nt == 512)
-            hipLaunchKernelGGL(k_f5_trace5<512>, grid, dim3(512), shmem, st, g->off, g->adj, n,
-                               nparts, W.acc);
-        else if (nt == 256)
-            hipLaunchKernelGGL(k_f5_trace5<256>, grid, dim3(256), shmem, st, g->off, g->adj, n,
-                               nparts, W.acc);
+        if (shared)
+            hipLaunchKernelGGL((k_f5_trace5<1024, true>), grid, dim3(1024), shmem, st, g->off,
+                               g->adj, n, nparts, W.acc);
         else
-            hipLaunchKernelGGL(k_f5_trace5<128>, grid, dim3(128), shmem, st, g->off, g->adj, n,
-                               nparts, W.acc);
+            hipLaunchKernelGGL((k_f5_trace5<1024, false>), grid, dim3(1024), shmem, st, g->off,
+                               g->adj, n, nparts, W.acc);
     }
     GPM_LAUNCH_CHECK("k_f5_trace5");
     if (trace5 && m > 0) {

@@ -139,12 +139,12 @@ def big_hub_counts(gpm):
 @pytest.mark.parametrize("n", [151, 32768, 40000, 60000, 65536, 65537])
 def test_formula_route_hub_and_lds_limit(gpm, big_hub_counts, n):
     """The hub graph alone, and padded with isolated vertices (which change
-    no count) to 32,768 vertices (the widest, 1024-thread form of the A^2-row
-    kernel), 40,000 and 60,000 (its 512- and 256-thread forms), 65,536, the
-    largest graph whose rows of A^2 fit in LDS (its 128-thread form,
-    152 KB), and 65,537, where the 5-cycle, K_{2,3}, class 16, K5 minus an
-    edge and the wheel are counted directly.  All equal the oracle's counts
-    of the hub graph."""
+    no count) to 32,768 vertices (the A^2-row kernel with a bitmap of N(a)
+    per wave), 40,000 and 60,000 (one N(a) bitmap shared by the workgroup's
+    waves), 65,536, the largest graph whose rows of A^2 fit in LDS (144 KB),
+    and 65,537, where the 5-cycle, K_{2,3}, class 16, K5 minus an edge and
+    the wheel are counted directly.  All equal the oracle's counts of the
+    hub graph."""
     e, want = big_hub_counts
     assert want[18] > 0 and want[19] > 0   # wheels and K5 minus an edge
     print(f"5-motif formula, hub graph on {n} vertices", flush=True)
